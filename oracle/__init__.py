@@ -1,0 +1,55 @@
+"""Plain FP64 CPU oracle for the operator-factorization discretization of the
+integral fractional Laplacian (Wu & Zhang, arXiv 2103.03658).
+
+TEST INFRASTRUCTURE ONLY.  This package is the independent reference that the
+GPU library is checked against.  Only the test suite, the smoke check and the
+CPU-baseline leg of the benchmark may import it.  The product path never calls
+it and shares no code with it (no kernels, headers, tables or helpers).
+
+Everything here is written for a reader to check against the paper by eye:
+dense, slow, FP64 (mpmath where FP64 cancels), following the paper's
+definitions in its own order and notation:
+
+  constants   c_{d,alpha} (Sec. 1, normalisation of the hypersingular form),
+              far-field integrals over Upsilon^c_+ (Sec. 2, eq. (L2)),
+  weights     weight integrals omega_k^p (Sec. 2.1 eq. (wi-1D), Appendix;
+              Sec. 2.2 eq. (2D-scheme0); Remark 2.2 for a kernel K(r)),
+  operator    origin rule, coefficients a_k, a_0, generator -c a_k, dense
+              Toeplitz / BTTB matrices and products (Sec. 2.1 eq. (1D-scheme),
+              Sec. 2.2 eq. (2D-scheme) and the matrices A^(1), A^(2)),
+              exterior-data term b (same equations), circulant embedding,
+  solve       Cholesky and plain CG on the dense/BTTB product,
+  exact       closed forms used as pins (eq. (fun0), Example 3.2.3, and
+              standard Fourier-transform identities).
+
+Readings taken where the paper is silent, garbled or self-contradictory are
+listed in each function's docstring (and collected in the design notes):
+  R1  Appendix p=2 weights: integrate the quadratic Lagrange basis exactly
+      (the printed xi_{N-3/4}, xi_{k-+1/2} are not what the integral gives).
+  R2  1D origin value for p=2: Phi(x,0) ~ (4 Phi(xi_1) - Phi(xi_2))/3.
+  R3  2D origin value: Phi(x,0) ~ (Phi(xi_10) + Phi(xi_01))/2, i.e. the
+      average over axes (so a_11 carries no omega_00 term).
+  R4  3D and 2D p=2: the same axis-average rule, with the p=2 Richardson
+      step of R2 on each axis.  Parity unpinned (no printed numbers).
+  R5  gamma = 2 throughout (the paper's recommended and tabulated choice).
+  R6  Tempered kernel: normalisation c-bar = c_{d,alpha}; K enters the weight
+      integrals and the far-field constant.  Parity unpinned beyond the
+      lambda -> 0 reduction.
+  R7  Embedding slots whose folded offset exceeds N-2 are zero.
+"""
+
+from .constants import c_dalpha, far_field_T, K_ball
+from .weights import weights
+from .operator import (origin_rule, coefficients, generator, dense_matrix,
+                       apply_dense, apply_bttb, apply, apply_rows,
+                       embed_generator, symbol,
+                       exterior_b_1d, exterior_b_2d, grid_points)
+from .solve import solve_cholesky, solve_cg
+from . import exact
+
+__all__ = [
+    "c_dalpha", "far_field_T", "K_ball", "weights", "origin_rule",
+    "coefficients", "generator", "dense_matrix", "apply_dense", "apply_bttb",
+    "apply", "apply_rows", "embed_generator", "symbol", "exterior_b_1d", "exterior_b_2d",
+    "grid_points", "solve_cholesky", "solve_cg", "exact",
+]

@@ -1,0 +1,281 @@
+"""Coefficients, generator, dense operator and exterior-data term
+(test infrastructure; see package header).
+
+Notation follows Sec. 2: lattice x_i = -1 + i h (Omega = (-1,1)^d, L = 2,
+h = L/N), interior indices i in {1..N-1}^d (n = N-1 unknowns per axis; nodes
+with a component 0 or N carry u = g, as in the sums for b in eq. (1D-scheme)
+and (2D-scheme)), offsets k in {0..N}^d, xi_k = h k.
+
+Scheme, written for general d (Sec. 2.1 eq. (L1h), (1D-scheme); Sec. 2.2
+eq. (2D-scheme); the 3D case is said to follow the 2D lines):
+
+  (-Delta)_h u_i = -c_{d,alpha} [ a_0 u_i + sum_{k != 0, |k_s| <= N} a_{|k|} u_{i+k} + (far field of g) ]
+
+  a_k = 2^{z(k)} W_k / |xi_k|^gamma          (k != 0, z(k) = # zero entries)
+  a_0 = - sum_{k != 0} 2^{d - z(k)} a_k - 2^d T_d
+
+W is omega with the origin value redistributed (origin_rule).  The factor
+2^{z(k)} counts the sign patterns m of (FL1) that land on the same lattice
+neighbour; 2^{d-z(k)} counts the distinct neighbours with offset pattern |k|,
+each of which subtracts u_i once per sign pattern.  For d = 1 this is the
+paper's a_1 = (zeta omega_0 + omega_1)/xi_1^gamma, a_j = omega_j/xi_j^gamma,
+a_0 = -2 (sum a_j + 1/(alpha L^alpha)); for d = 2 it is the case list under
+(2D-scheme) with reading R3 for the origin.
+
+The matrix on the interior unknowns is A = [G_{|i-j|}] with G = -c a
+(symmetric Toeplitz A^(1), BTTB A^(2), and the 3-level analogue).
+"""
+
+import math
+
+import numpy as np
+from scipy.linalg import toeplitz
+
+from .constants import c_dalpha, far_field_T
+from .weights import weights as _weights
+
+GAMMA = 2.0
+
+
+def grid_points(N, d=1):
+    """Interior coordinates x_i = -1 + i h, i = 1..N-1 (one axis)."""
+    h = 2.0 / N
+    return -1.0 + h * np.arange(1, N)
+
+
+def origin_rule(om, d, p):
+    """Redistribute omega_0 (the weight of Phi(x, 0), a limit) to the axis
+    offsets.  gamma = 2: Phi(x, 0) = u''-type limit, replaced by the average
+    over axes s of Phi(x, h e_s) (p <= 1; the paper's 1D rule
+    Phi(x, xi_0) ~ Phi(x, xi_1), reading R3 in 2D) or of the Richardson
+    combination (4 Phi(x, h e_s) - Phi(x, 2h e_s))/3 (p = 2, readings R2, R4).
+    """
+    W = np.array(om, dtype=np.float64, copy=True)
+    zero = (0,) * d
+    w0 = W[zero]
+    W[zero] = 0.0
+    c1, c2 = (1.0, 0.0) if p <= 1 else (4.0 / 3.0, -1.0 / 3.0)
+    for s in range(d):
+        e1 = tuple(1 if j == s else 0 for j in range(d))
+        e2 = tuple(2 if j == s else 0 for j in range(d))
+        W[e1] += w0 * c1 / d
+        if c2:
+            W[e2] += w0 * c2 / d
+    return W
+
+
+def _offset_tables(N, d):
+    k = np.indices((N + 1,) * d).reshape(d, -1).T          # all offsets
+    z = (k == 0).sum(axis=1)
+    norm = np.sqrt((k.astype(np.float64) ** 2).sum(axis=1))
+    return k, z, norm
+
+
+def coefficients(W, d, h, T):
+    """a_k for k in {0..N}^d from the origin-corrected weights W."""
+    N = W.shape[0] - 1
+    k, z, norm = _offset_tables(N, d)
+    Wf = W.reshape(-1)
+    a = np.zeros_like(Wf)
+    nz = norm > 0
+    a[nz] = (2.0 ** z[nz]) * Wf[nz] / (h * norm[nz]) ** GAMMA
+    # a_0: compensated sum over all neighbours, then the far field
+    terms = list((2.0 ** (d - z[nz])) * a[nz])
+    a[~nz] = -math.fsum(terms) - (2.0 ** d) * T
+    return a.reshape(W.shape)
+
+
+def generator(d, alpha, p, N, lam=0.0, return_parts=False):
+    """G_k = -c_{d,alpha} a_k on {0..N}^d (FP64).
+
+    lam > 0 selects the tempered kernel exp(-lam r) (Remark 2.2, reading R6:
+    same normalisation constant c_{d,alpha})."""
+    h = 2.0 / N
+    om = _weights(d, alpha, p, N, h=h, lam=lam)
+    W = origin_rule(om, d, p)
+    T = far_field_T(d, alpha, L=2.0, lam=lam)
+    a = coefficients(W, d, h, T)
+    G = -c_dalpha(d, alpha) * a
+    if return_parts:
+        return G, dict(omega=om, W=W, T=T, a=a)
+    return G
+
+
+# ---------------------------------------------------------------------------
+# dense operator
+# ---------------------------------------------------------------------------
+
+def dense_matrix(G):
+    """Materialise A_{ij} = G_{|i-j|} on the interior (n = N-1 per axis)."""
+    d = G.ndim
+    n = G.shape[0] - 2
+    idx = np.indices((n,) * d).reshape(d, -1)
+    diff = [np.abs(idx[s][:, None] - idx[s][None, :]) for s in range(d)]
+    return G[tuple(diff)]
+
+
+def apply_dense(G, u):
+    """y = A u with A materialised (small grids)."""
+    A = dense_matrix(G)
+    shp = u.shape
+    d = G.ndim
+    ub = u.reshape((-1,) + shp[d:]) if u.ndim > d else u.reshape(-1)
+    return (A @ ub).reshape(shp)
+
+
+def apply_bttb(G, u):
+    """y = A u without an FFT: y[i0] = sum_{j0} A_{|i0-j0|} u[j0], each
+    block applied as a dense (d-1)-level Toeplitz product.  O(n^{2d})."""
+    d = G.ndim
+    n = G.shape[0] - 2
+    if d == 1:
+        T = toeplitz(G[:n])
+        return T @ u
+    if d == 2:
+        # Toeplitz blocks T_m[i1, j1] = G[m, |i1 - j1|]
+        j = np.arange(n)
+        D = np.abs(j[:, None] - j[None, :])
+        Tm = G[:n][:, D]                                # (m, i1, j1)
+        V = Tm @ u.T                                    # (m, i1, j0)
+        y = np.zeros((n, n))
+        for i0 in range(n):
+            m = np.abs(i0 - j)                          # over j0
+            y[i0] = V[m, :, j].sum(axis=0)
+        return y
+    if d == 3:
+        y = np.zeros((n, n, n))
+        # V[m, j0] = A2(G[m]) u[j0]
+        A2 = [dense_matrix(G[m]) for m in range(n)]
+        U = u.reshape(n, n * n)
+        V = np.stack([U @ A2[m].T for m in range(n)])   # (m, j0, n^2)
+        for i0 in range(n):
+            m = np.abs(i0 - np.arange(n))
+            y[i0] = V[m, np.arange(n)].sum(axis=0).reshape(n, n)
+        return y
+    raise ValueError("d must be 1, 2 or 3")
+
+
+def apply(G, u):
+    """Dense product, materialised when small, block form otherwise."""
+    n = G.shape[0] - 2
+    if n ** G.ndim <= 4096:
+        return apply_dense(G, u)
+    return apply_bttb(G, u)
+
+
+def apply_rows(G, u, rows):
+    """Exact y_i = sum_j G_{|i-j|} u_j at selected interior multi-indices
+    `rows` (array (m, d)), each by a compensated sum.  For sampled parity at
+    sizes where the full product is out of reach."""
+    d = G.ndim
+    n = G.shape[0] - 2
+    idx = np.indices((n,) * d).reshape(d, -1)
+    uf = u.reshape(-1)
+    out = np.empty(len(rows))
+    for r, i in enumerate(rows):
+        coef = G[tuple(np.abs(idx[s] - i[s]) for s in range(d))]
+        out[r] = math.fsum(coef * uf)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# circulant embedding (what a fast product computes)
+# ---------------------------------------------------------------------------
+
+def embed_generator(G):
+    """c on {0..M-1}^d, M = 2N: c[j] = G[m(j)], m(j_s) = min(j_s, M - j_s),
+    zero wherever some m(j_s) > N - 2 (reading R7)."""
+    d = G.ndim
+    N = G.shape[0] - 1
+    M = 2 * N
+    j = np.arange(M)
+    m = np.minimum(j, M - j)
+    keep = m <= N - 2
+    c = G[np.ix_(*([m] * d))].copy()
+    mask = keep
+    for s in range(1, d):
+        mask = np.multiply.outer(mask, keep)
+    c[~mask] = 0.0
+    return c
+
+
+def symbol(G):
+    """lambda-hat = DFT_M(c) / M^d, real part (c is real and even)."""
+    c = embed_generator(G)
+    lam = np.fft.fftn(c)
+    return lam.real / c.size, float(np.abs(lam.imag).max() / c.size)
+
+
+# ---------------------------------------------------------------------------
+# exterior data g != 0 (the b term of the paper)
+# ---------------------------------------------------------------------------
+
+def exterior_b_1d(G, g, alpha, lam=0.0):
+    """bold-b_i = sum over exterior nodes j (j <= 0 or j >= N, |j-i| <= N) of
+    G_{|j-i|} g(x_j) - c_{1,alpha} int_L^inf [g(x_i - xi) + g(x_i + xi)]
+    K(xi) xi^{-1-alpha} dxi   (eq. (1D-scheme) and the definition of b_i)."""
+    from scipy.integrate import quad
+    N = G.shape[0] - 1
+    h = 2.0 / N
+    L = 2.0
+    c = c_dalpha(1, alpha)
+    out = np.zeros(N - 1)
+    for i in range(1, N):
+        s = 0.0
+        for j in list(range(i - N, 1)) + list(range(N, i + N + 1)):
+            s += G[abs(j - i)] * g(-1.0 + j * h)
+        xi = -1.0 + i * h
+        f = lambda t: (g(xi - t) + g(xi + t)) * t ** (-1.0 - alpha) * (
+            math.exp(-lam * t) if lam else 1.0)
+        tail = quad(f, L, np.inf, epsabs=1e-15, epsrel=1e-13, limit=400)[0]
+        out[i - 1] = s - c * tail
+    return out
+
+
+def exterior_b_2d(G, g, alpha, nq=160):
+    """2D analogue (eq. (2D-scheme), definition of b_ij): the lattice sum of
+    G_{|k|} g over exterior nodes within the offset box, minus c_{2,alpha}
+    times  sum_m int_{Upsilon^c_+} g(x + (-1)^m o xi) |xi|^{-2-alpha} dxi.
+
+    The far-field region is split into {xi1 > L, xi2 < L}, {xi1 > L, xi2 > L},
+    {xi1 < L, xi2 > L}; on each unbounded axis xi = L/t, t in (0,1], and
+    tensor Gauss-Legendre (nq points per axis) is applied.  g must accept
+    numpy arrays (x1, x2)."""
+    N = G.shape[0] - 1
+    h = 2.0 / N
+    L = 2.0
+    c = c_dalpha(2, alpha)
+    n = N - 1
+    xg, wg = np.polynomial.legendre.leggauss(nq)
+    # bounded axis [0, L]
+    sb = L * (xg + 1) / 2
+    wb = wg * L / 2
+    # unbounded axis xi = L/t, t in (0,1]: dxi = L/t^2 dt
+    t = (xg + 1) / 2
+    su = L / t
+    wu = (wg / 2) * L / t ** 2
+    pieces = [(su, wu, sb, wb), (su, wu, su, wu), (sb, wb, su, wu)]
+    x = -1.0 + h * np.arange(N + 1)
+    out = np.zeros((n, n))
+    for i in range(1, N):
+        for jj in range(1, N):
+            # exterior lattice part
+            s = 0.0
+            for k0 in range(-N, N + 1):
+                a0 = i + k0
+                for k1 in range(-N, N + 1):
+                    a1 = jj + k1
+                    if 1 <= a0 <= N - 1 and 1 <= a1 <= N - 1:
+                        continue
+                    s += G[abs(k0), abs(k1)] * g(np.float64(-1.0 + a0 * h),
+                                                 np.float64(-1.0 + a1 * h))
+            # far field
+            tail = 0.0
+            for (s1, w1, s2, w2) in pieces:
+                X1, X2 = s1[:, None], s2[None, :]
+                Wt = w1[:, None] * w2[None, :] * (X1 ** 2 + X2 ** 2) ** (-1.0 - alpha / 2)
+                for m1 in (1.0, -1.0):
+                    for m2 in (1.0, -1.0):
+                        tail += float((Wt * g(x[i] + m1 * X1, x[jj] + m2 * X2)).sum())
+            out[i - 1, jj - 1] = s - c * tail
+    return out

@@ -1,0 +1,259 @@
+"""Pins of the CPU oracle by mathematics rather than printed numbers (CPU).
+
+Independent checks: known constants, the far-field integral and the weight
+moments by a different integration (scipy quadrature in cone coordinates),
+a brute-force evaluation of the scheme straight from the sum over sign
+patterns, the paper's own 2D case list for a_kl, structure (symmetry,
+positive definiteness), the identity of the p=0 and p=1 matrices at
+alpha = 1 in 1D, and the circulant embedding.
+"""
+
+import itertools
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle
+from oracle.constants import c_dalpha, far_field_T
+from oracle.weights import weights
+
+
+def test_c_dalpha_cauchy_values():
+    # alpha = 1: c_{d,1} = Gamma((d+1)/2) / pi^{(d+1)/2}
+    assert math.isclose(c_dalpha(1, 1.0), 1 / math.pi, rel_tol=1e-15)
+    assert math.isclose(c_dalpha(2, 1.0), 1 / (2 * math.pi), rel_tol=1e-15)
+    assert math.isclose(c_dalpha(3, 1.0), 1 / math.pi ** 2, rel_tol=1e-15)
+
+
+@pytest.mark.parametrize("alpha", [0.3, 1.0, 1.7])
+@pytest.mark.parametrize("lam", [0.0, 2.0])
+def test_far_field_T_cartesian(alpha, lam):
+    L = 2.0
+    K = (lambda r: math.exp(-lam * r)) if lam else (lambda r: 1.0)
+    if lam == 0:
+        assert math.isclose(far_field_T(1, alpha), 1 / (alpha * L ** alpha), rel_tol=1e-14)
+    else:
+        ref = integrate.quad(lambda t: K(t) * t ** (-1 - alpha), L, np.inf,
+                             epsrel=1e-13, epsabs=0)[0]
+        assert math.isclose(far_field_T(1, alpha, lam=lam), ref, rel_tol=1e-10)
+    # 2D: R^2_+ minus [0,L]^2 = {xi1 > L} u {xi1 < L, xi2 > L}
+    f2 = lambda y, x: K(math.hypot(x, y)) * (x * x + y * y) ** (-1 - alpha / 2)
+    a = integrate.dblquad(f2, L, np.inf, 0, np.inf, epsabs=0, epsrel=1e-11)[0]
+    b = integrate.dblquad(f2, 0, L, L, np.inf, epsabs=0, epsrel=1e-11)[0]
+    assert math.isclose(far_field_T(2, alpha, lam=lam), a + b, rel_tol=1e-8)
+
+
+@pytest.mark.parametrize("alpha", [0.5, 1.0, 1.5])
+def test_far_field_T3_closed_form(alpha):
+    """K = 1, d = 3: integrating the radial tail (cos theta / L)^alpha / alpha
+    over the part of the octant where e_3 is largest (times 3 by symmetry)
+    leaves 6/(alpha (alpha+1) L^alpha) int_0^{pi/4} (1 - (cos p / sqrt(1 +
+    cos^2 p))^{alpha+1}) dp."""
+    L = 2.0
+    f = lambda p: 1.0 - (math.cos(p) / math.sqrt(1.0 + math.cos(p) ** 2)) ** (alpha + 1)
+    ref = 6.0 / (alpha * (alpha + 1) * L ** alpha) * integrate.quad(
+        f, 0, math.pi / 4, epsabs=0, epsrel=1e-13)[0]
+    assert math.isclose(far_field_T(3, alpha), ref, rel_tol=1e-12)
+
+
+def _moment_reference(d, alpha, js, L, lam):
+    """int_{[0,L]^d} prod xi_s^{j_s} K(|xi|) |xi|^{2-d-alpha} dxi in cone
+    coordinates: for the region where xi_t is the largest component,
+    xi = r (w, 1)/|(w, 1)| with w in [0,1]^{d-1}, r in [0, L |(w,1)|]."""
+    J = sum(js)
+    total = 0.0
+    for t in range(d):
+        others = [s for s in range(d) if s != t]
+
+        def integrand(*w):
+            rho = math.sqrt(1.0 + sum(x * x for x in w))
+            e = {t: 1.0 / rho}
+            for s, x in zip(others, w):
+                e[s] = x / rho
+            P = 1.0
+            for s in range(d):
+                P *= e[s] ** js[s]
+            R = L * rho
+            q = J + 2.0 - alpha            # r^{J} r^{2-d-alpha} r^{d-1}
+            if lam:
+                rad = integrate.quad(lambda r: r ** (q - 1) * math.exp(-lam * r), 0, R,
+                                     epsabs=0, epsrel=1e-13)[0]
+            else:
+                rad = R ** q / q
+            return P * rad * rho ** (-d)       # dOmega = dw / rho^d
+        if d == 2:
+            total += integrate.quad(integrand, 0, 1, epsabs=0, epsrel=1e-13)[0]
+        else:
+            total += integrate.dblquad(lambda y, x: integrand(x, y), 0, 1, 0, 1,
+                                       epsabs=0, epsrel=1e-11)[0]
+    return total
+
+
+@pytest.mark.parametrize("d,N", [(1, 16), (2, 8), (3, 4)])
+@pytest.mark.parametrize("p", [0, 1, 2])
+@pytest.mark.parametrize("alpha", [0.4, 1.3])
+@pytest.mark.parametrize("lam", [0.0, 1.5])
+def test_weight_moments(d, N, p, alpha, lam):
+    """sum_k omega_k prod_s xi_{k_s}^{j_s} equals the moment of the weight
+    function for every j_s <= p (the basis reproduces such polynomials):
+    partition of unity for all p, plus linear / quadratic reproduction."""
+    if d == 3 and lam:
+        pytest.skip("3D tempered moments: reference too slow; covered in 2D")
+    L, h = 2.0, 2.0 / N
+    om = weights(d, alpha, p, N, h=h, lam=lam)
+    xi = h * np.arange(N + 1)
+    for js in itertools.product(range(p + 1), repeat=d):
+        if d == 1:
+            q = js[0] + 2.0 - alpha
+            if lam:
+                ref = integrate.quad(lambda r: r ** (q - 1) * math.exp(-lam * r), 0, L,
+                                     epsabs=0, epsrel=1e-13)[0]
+            else:
+                ref = L ** q / q
+        else:
+            ref = _moment_reference(d, alpha, js, L, lam)
+        mono = np.ones_like(om)
+        for s in range(d):
+            shp = [1] * d
+            shp[s] = N + 1
+            mono = mono * (xi ** js[s]).reshape(shp)
+        got = math.fsum((om * mono).ravel())
+        assert math.isclose(got, ref, rel_tol=1e-10), (js, got, ref)
+
+
+def _brute_force_apply(d, W, T, alpha, u, N):
+    """(-Delta)_h u at every interior node, summing the sign patterns of the
+    reformulated integral one by one: -c [ sum_{k != 0} W_k/|xi_k|^2
+    sum_m (u(x_i + (-1)^m o xi_k) - u(x_i)) - 2^d T u_i ], u = 0 outside."""
+    h = 2.0 / N
+    n = N - 1
+    c = c_dalpha(d, alpha)
+    U = np.zeros((N + 1,) * d)
+    U[(slice(1, N),) * d] = u
+    out = np.zeros((n,) * d)
+    for i in itertools.product(range(1, N), repeat=d):
+        terms = []
+        for k in itertools.product(range(N + 1), repeat=d):
+            if not any(k):
+                continue
+            wk = W[k] / (h * h * sum(kk * kk for kk in k))
+            for m in itertools.product((1, -1), repeat=d):
+                j = tuple(ii + mm * kk for ii, mm, kk in zip(i, m, k))
+                inside = all(0 <= jj <= N for jj in j)
+                uj = U[j] if inside else 0.0
+                terms.append(wk * (uj - U[i]))
+        terms.append(-(2 ** d) * T * U[i])
+        out[tuple(ii - 1 for ii in i)] = -c * math.fsum(terms)
+    return out
+
+
+@pytest.mark.parametrize("d,N", [(1, 8), (2, 4), (2, 6), (3, 4)])
+@pytest.mark.parametrize("p", [1, 2])
+def test_brute_force_sign_pattern_sum(d, N, p):
+    alpha = 0.8
+    G, parts = oracle.generator(d, alpha, p, N, return_parts=True)
+    rng = np.random.default_rng(7)
+    u = rng.uniform(-1, 1, (N - 1,) * d)
+    ref = _brute_force_apply(d, parts["W"], parts["T"], alpha, u, N)
+    got = oracle.apply_dense(G, u)
+    scale = np.abs(oracle.dense_matrix(G)).sum(axis=1).max()
+    assert np.abs(got - ref).max() <= 1e-13 * scale
+
+
+def test_2d_case_list():
+    """The paper's a_kl case list for d = 2 (with reading R3: a_11 carries
+    no omega_00 term) against the general-d formula."""
+    alpha, p, N = 1.3, 1, 8
+    h = 2.0 / N
+    G, parts = oracle.generator(2, alpha, p, N, return_parts=True)
+    om, T = parts["omega"], parts["T"]
+    a = np.zeros_like(om)
+    for k in range(N + 1):
+        for l in range(N + 1):
+            if k == l == 0:
+                continue
+            r2 = h * h * (k * k + l * l)
+            if (k, l) in ((0, 1), (1, 0)):
+                a[k, l] = (2 * om[k, l] + om[0, 0]) / r2
+            elif k == 0 or l == 0:
+                a[k, l] = 2 * om[k, l] / r2
+            else:
+                a[k, l] = om[k, l] / r2
+    a[0, 0] = (-2 * (a[1:, 0].sum() + a[0, 1:].sum()) - 4 * a[1:, 1:].sum() - 4 * T)
+    np.testing.assert_allclose(parts["a"], a, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(G, -c_dalpha(2, alpha) * a, rtol=1e-13)
+
+
+@pytest.mark.parametrize("d,N", [(1, 32), (2, 12), (3, 6)])
+@pytest.mark.parametrize("p", [0, 1, 2])
+@pytest.mark.parametrize("alpha,lam", [(0.3, 0.0), (1.0, 0.0), (1.9, 0.0), (1.2, 3.0)])
+def test_symmetric_positive_definite(d, N, p, alpha, lam):
+    if d == 3 and lam and p != 1:
+        pytest.skip("3D tempered: one basis suffices (far-field constant is slow)")
+    G = oracle.generator(d, alpha, p, N, lam=lam)
+    A = oracle.dense_matrix(G)
+    assert np.array_equal(A, A.T)
+    assert np.linalg.eigvalsh(A).min() > 0
+
+
+@pytest.mark.parametrize("N", [16, 64, 256])
+def test_p0_equals_p1_at_alpha_one(N):
+    """Example 3.2.1: at alpha = 1 the constant and linear bases give the
+    same 1D differentiation matrix."""
+    G0 = oracle.generator(1, 1.0, 0, N)
+    G1 = oracle.generator(1, 1.0, 1, N)
+    np.testing.assert_allclose(G0, G1, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("d,N,p", [(1, 64, 1), (2, 16, 2), (2, 32, 1), (3, 8, 1)])
+def test_circulant_embedding_product(d, N, p):
+    G = oracle.generator(d, 0.9, p, N)
+    lam, imag = oracle.symbol(G)
+    assert imag < 1e-13 * np.abs(lam).max()
+    M = 2 * N
+    n = N - 1
+    rng = np.random.default_rng(1)
+    u = rng.uniform(-1, 1, (n,) * d)
+    z = np.zeros((M,) * d)
+    z[(slice(0, n),) * d] = u
+    y = np.fft.ifftn(lam * M ** d * np.fft.fftn(z)).real[(slice(0, n),) * d]
+    ref = oracle.apply(G, u)
+    assert np.abs(y - ref).max() <= 1e-13 * np.abs(oracle.dense_matrix(G)).sum(axis=1).max()
+
+
+def test_tempered_reduces_to_fractional():
+    for d, N in ((1, 32), (2, 8)):
+        G0 = oracle.generator(d, 1.1, 1, N)
+        Gt = oracle.generator(d, 1.1, 1, N, lam=1e-9)
+        np.testing.assert_allclose(Gt, G0, rtol=1e-7)
+
+
+def test_bttb_block_product_matches_dense():
+    rng = np.random.default_rng(3)
+    for d, N in ((2, 20), (3, 8)):
+        G = oracle.generator(d, 1.4, 1, N)
+        u = rng.uniform(-1, 1, (N - 1,) * d)
+        np.testing.assert_allclose(oracle.apply_bttb(G, u), oracle.apply_dense(G, u),
+                                   rtol=0, atol=1e-12 * np.abs(G).sum() * 4)
+
+
+def test_apply_rows_matches_dense():
+    rng = np.random.default_rng(4)
+    G = oracle.generator(2, 0.7, 2, 16)
+    u = rng.uniform(-1, 1, (15, 15))
+    y = oracle.apply_dense(G, u)
+    rows = np.array([[0, 0], [3, 7], [14, 14], [14, 0]])
+    got = oracle.apply_rows(G, u, rows)
+    np.testing.assert_allclose(got, y[tuple(rows.T)], rtol=1e-12)
+
+
+def test_cg_matches_cholesky():
+    rng = np.random.default_rng(5)
+    G = oracle.generator(2, 1.5, 1, 16)
+    f = rng.uniform(-1, 1, (15, 15))
+    u1 = oracle.solve_cholesky(G, f)
+    u2, it, rel = oracle.solve_cg(G, f, tol=1e-13)
+    assert rel <= 1e-13
+    assert np.abs(u1 - u2).max() <= 1e-10 * np.abs(u1).max()
