@@ -1,0 +1,159 @@
+/*
+ * fl.h -- C ABI of the MI355X (gfx950) library for the operator-factorization
+ * discretization of the integral fractional Laplacian (-Delta)^{alpha/2} and
+ * its tempered generalization (Wu & Zhang, arXiv 2103.03658).
+ *
+ * Problem (Sec. 1, eq. (Poisson) and (BC)):  (-Delta)^{alpha/2} u = f on
+ * Omega = (-1,1)^d, u = g on the complement, d = 1, 2, 3, alpha in (0,2).
+ * Discretization (Sec. 2, eq. (1D-scheme), (2D-scheme); Remark 2.2):
+ * (-Delta)^{alpha/2}_h u = A u + b, A the symmetric (multilevel) Toeplitz
+ * matrix with generator G_k = -c_{d,alpha} a_k, k in {0..N}^d, h = 2/N,
+ * splitting parameter gamma = 2, Lagrange basis of degree 0, 1 or 2 in xi.
+ * The product A u is computed by circulant embedding of size M = 2N per axis
+ * and FFT (Sec. 2.1: the Toeplitz structure admits FFT products).
+ *
+ * Conventions for every entry point:
+ *  - Vectors live in device memory owned by the caller, contiguous,
+ *    row-major over the n^d interior points (n = N-1, last index fastest),
+ *    right-hand sides stored one after another: element (r, i) at
+ *    r * n^d + i.  Interior point i_s corresponds to x = -1 + (i_s+1) h.
+ *  - `stream` is a hipStream_t passed as void* (NULL: the default stream).
+ *    Work is enqueued on it; fl_apply returns without waiting, fl_solve
+ *    waits for its result.
+ *  - No C++ exception crosses the boundary.  A non-FL_OK status leaves a
+ *    thread-local message readable with fl_last_error().  Argument checks
+ *    happen before any device work.
+ *  - An operator handle is immutable after creation apart from its
+ *    schedule and solver settings; it owns its device buffers.  One handle
+ *    must not be used by two host threads at once.
+ */
+#ifndef FL_H
+#define FL_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fl_op_s *fl_op;
+
+typedef enum {
+  FL_OK = 0,
+  FL_E_INVAL = 1,       /* invalid argument */
+  FL_E_UNSUPPORTED = 2, /* valid but outside what is built (e.g. M not a power of two) */
+  FL_E_NOMEM = 3,       /* device allocation failed */
+  FL_E_DEVICE = 4,      /* a HIP call failed */
+  FL_E_NOCONV = 5,      /* maxiter reached before the tolerance */
+  FL_E_BREAKDOWN = 6    /* non-finite values or p.Ap <= 0 in CG */
+} fl_status;
+
+enum { FL_KERNEL_FRACTIONAL = 0, FL_KERNEL_TEMPERED = 1 };
+
+/* Per right-hand-side result of fl_solve. */
+typedef struct {
+  int iters;          /* CG iterations (FP64 path) / inner FP32 iterations summed (mixed) */
+  int outer_iters;    /* refinement steps (mixed path), 0 otherwise */
+  int converged;      /* 1 if the stopping rule was met */
+  int status;         /* fl_status of this right-hand side */
+  double relres_rec;  /* recursive ||r||_2 / ||f||_2 at exit (mixed: the FP64 residual) */
+  double relres_true; /* ||f - A u||_2 / ||f||_2 recomputed with an FP64 product at exit */
+} fl_info;
+
+/*
+ * fl_weights -- build the operator (-Delta)^{alpha/2}_h (or the tempered
+ * operator with kernel K(r) = exp(-lambda r), Remark 2.2) on (-1,1)^d.
+ * Computes on the GPU in FP64: the weight integrals omega_k^p (Sec. 2.1
+ * eq. (wi-1D), Sec. 2.2 eq. (2D-scheme0)), the origin rule, the
+ * coefficients a_k, the diagonal a_0 (with the far-field integral of
+ * eq. (L2)), the generator G = -c a, and the symbol lambda-hat = DFT of the
+ * circulant embedding of G divided by M^d (FP64 and an FP32 copy).
+ *   d       1, 2 or 3
+ *   alpha   in (0, 2)
+ *   degree  Lagrange degree p in {0, 1, 2}; p = 2 needs N even
+ *   h       mesh size; N = 2/h must be an integer (to 1e-12 relative),
+ *           N >= 4, and M = 2N a power of two with 8 <= M <= 2048
+ *   kernel  FL_KERNEL_FRACTIONAL (lambda ignored) or FL_KERNEL_TEMPERED
+ *   lambda  tempering rate >= 0 (normalisation constant c_{d,alpha})
+ *   stream  HIP stream for the setup kernels
+ *   out     receives the handle; unchanged on error
+ * Errors: FL_E_INVAL (argument), FL_E_UNSUPPORTED (size), FL_E_NOMEM,
+ * FL_E_DEVICE.  Synchronous: the handle is ready on return.
+ */
+fl_status fl_weights(int d, double alpha, int degree, double h, int kernel, double lambda,
+                     void *stream, fl_op *out);
+
+/* Copy the FP64 generator G_k, k in {0..N}^d (row-major, (N+1)^d values),
+ * to host memory.  count must be >= (N+1)^d.  Test hook. */
+fl_status fl_generator(fl_op A, double *host_out, size_t count);
+
+/* Copy the folded FP64 symbol lambda-hat_k, k in {0..N}^d (the full
+ * symbol on {0..M-1}^d is even: lambda-hat_j = lambda-hat_{min(j, M-j)}). */
+fl_status fl_symbol(fl_op A, double *host_out, size_t count);
+
+/* Copy the circulant embedding c_j, j in {0..M-1}^d, of the generator as
+ * laid out on the device: c_j = G_{m(j)}, m(j_s) = min(j_s, M - j_s), zero
+ * where some m(j_s) > N-2.  count >= M^d.  Test hook for the index maps. */
+fl_status fl_embedding(fl_op A, double *host_out, size_t count);
+
+/* Geometry of A: dimension, intervals N, interior points per axis n = N-1,
+ * embedding length M = 2N.  Any pointer may be NULL. */
+fl_status fl_query(fl_op A, int *d, int *N, int *n, int *M);
+
+/*
+ * fl_apply -- y = A u for nrhs right-hand sides (the g = 0 operator; the
+ * exterior-data term b is not added).
+ *   u, y    device arrays of nrhs * n^d doubles (fp32 = 0) or floats
+ *           (fp32 = 1), distinct, caller-owned
+ *   nrhs    >= 1
+ *   fp32    0: FP64 transforms and FP64 symbol; 1: FP32 transforms and symbol
+ * Asynchronous on `stream`.  Errors: FL_E_INVAL, FL_E_NOMEM, FL_E_DEVICE.
+ */
+fl_status fl_apply(fl_op A, const void *u, void *y, int nrhs, int fp32, void *stream);
+
+/*
+ * fl_solve -- solve A u = f for nrhs right-hand sides by conjugate gradients
+ * (A is symmetric positive definite, Sec. 2.2).
+ *   f       device, nrhs * n^d doubles
+ *   g       exterior data; must be NULL (g = 0).  Non-NULL: FL_E_UNSUPPORTED
+ *   tol     stop when ||r||_2 <= tol ||f||_2 (per right-hand side), tol > 0
+ *   maxiter CG iteration cap (FP64 path) / inner iteration cap per
+ *           refinement step (mixed path), >= 1
+ *   mixed   0: FP64 CG, recursive residual.  1: FP32 CG inner solves with
+ *           FP64 residuals r = f - A u and FP64 updates u += delta
+ *           (iterative refinement) until the FP64 residual meets tol
+ *   u       device, nrhs * n^d doubles, output (x0 = 0)
+ *   info    host array of nrhs fl_info, or NULL
+ * Blocks until done.  Returns FL_OK if every right-hand side converged,
+ * otherwise the first failing status (FL_E_NOCONV, FL_E_BREAKDOWN); u then
+ * holds the last iterate.  A right-hand side f = 0 gives u = 0.
+ */
+fl_status fl_solve(fl_op A, const double *f, const double *g, double tol, int maxiter, int mixed,
+                   double *u, int nrhs, fl_info *info, void *stream);
+
+/* Mixed-precision settings: relative tolerance of each FP32 inner solve
+ * (0 < inner_tol < 1) and the refinement step cap (>= 1). */
+fl_status fl_set_refinement(fl_op A, double inner_tol, int max_outer);
+
+/*
+ * Launch schedule of the transform passes (elements per thread E and lines
+ * per block) for FP64 (fp32 = 0) or FP32 transforms.  E in {8, 16}, E <= M;
+ * lines per block >= 1 with (lines * M / E) <= 512 threads and at most
+ * 64 KiB of LDS.  Values <= 0 keep the current setting.  Used by the
+ * schedule tuner; results do not depend on the schedule beyond rounding.
+ */
+fl_status fl_set_schedule(fl_op A, int fp32, int e_first, int e_mid, int e_c2c, int w_first,
+                          int w_c2c, int lpb_mid);
+fl_status fl_get_schedule(fl_op A, int fp32, int *sched6);
+
+/* Release the handle and its device memory.  NULL is accepted. */
+void fl_destroy(fl_op A);
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char *fl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FL_H */

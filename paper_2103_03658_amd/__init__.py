@@ -1,0 +1,133 @@
+"""Fractional Laplacian on MI355X: operator-factorization discretization
+(Wu & Zhang, arXiv 2103.03658) applied by circulant-embedded FFT and solved
+by conjugate gradients in hand-written HIP kernels for gfx950.
+
+Thin Python layer over the C ABI (include/fl.h): it converts arguments and
+hands device pointers of torch tensors to the library.  torch provides device
+memory and streams only.
+"""
+
+import ctypes
+
+from ._lib import (FL_KERNEL_FRACTIONAL, FL_KERNEL_TEMPERED, FlError, FlInfo, check, lib)
+
+__all__ = ["Operator", "FlError", "FlInfo", "lib"]
+
+
+def _stream_ptr(stream):
+    """hipStream_t of `stream`, or torch's current stream, or NULL (the
+    default stream) when no device is visible (argument checks still run)."""
+    import torch
+    if stream is None:
+        if not torch.cuda.is_available():
+            return ctypes.c_void_p(None)
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Operator:
+    """The discrete operator A (g = 0 part of (-Delta)^{alpha/2}_h) on (-1,1)^d.
+
+    Built on the current CUDA/HIP device by fl_weights.  Vectors are torch
+    tensors on that device holding nrhs * n^d values (any shape with that
+    many elements, contiguous)."""
+
+    def __init__(self, d, alpha, degree, N=None, h=None, kernel="fractional", lam=0.0,
+                 stream=None):
+        if h is None:
+            if N is None:
+                raise ValueError("give N or h")
+            h = 2.0 / N
+        kind = {"fractional": FL_KERNEL_FRACTIONAL, "tempered": FL_KERNEL_TEMPERED}[kernel]
+        self._h = ctypes.c_void_p()
+        self._lib = lib()
+        check(self._lib.fl_weights(int(d), float(alpha), int(degree), float(h), kind,
+                                   float(lam), _stream_ptr(stream), ctypes.byref(self._h)))
+        q = [ctypes.c_int() for _ in range(4)]
+        check(self._lib.fl_query(self._h, *[ctypes.byref(x) for x in q]))
+        self.d, self.N, self.n, self.M = (x.value for x in q)
+        self.alpha, self.degree, self.kernel, self.lam = float(alpha), int(degree), kernel, lam
+        self.nd = self.n ** self.d
+
+    # -- host copies (test hooks) ------------------------------------------
+    def _host(self, fn, count):
+        import numpy as np
+        out = np.empty(count, dtype=np.float64)
+        check(fn(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), count))
+        return out
+
+    def generator(self):
+        return self._host(self._lib.fl_generator, (self.N + 1) ** self.d).reshape(
+            (self.N + 1,) * self.d)
+
+    def symbol(self):
+        return self._host(self._lib.fl_symbol, (self.N + 1) ** self.d).reshape(
+            (self.N + 1,) * self.d)
+
+    def embedding(self):
+        return self._host(self._lib.fl_embedding, self.M ** self.d).reshape((self.M,) * self.d)
+
+    # -- compute ----------------------------------------------------------------
+    def _nrhs(self, t):
+        if not t.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        if t.numel() % self.nd:
+            raise ValueError(f"size {t.numel()} is not a multiple of n^d = {self.nd}")
+        return t.numel() // self.nd
+
+    def apply(self, u, out=None, stream=None):
+        """y = A u; FP32 transforms when u is float32, FP64 when float64."""
+        import torch
+        if u.dtype not in (torch.float32, torch.float64):
+            raise TypeError("u must be float32 or float64")
+        nrhs = self._nrhs(u)
+        if out is None:
+            out = torch.empty_like(u)
+        if out.dtype != u.dtype or out.numel() != u.numel() or not out.is_contiguous():
+            raise ValueError("out must match u")
+        check(self._lib.fl_apply(self._h, ctypes.c_void_p(u.data_ptr()),
+                                 ctypes.c_void_p(out.data_ptr()), nrhs,
+                                 1 if u.dtype == torch.float32 else 0, _stream_ptr(stream)))
+        return out
+
+    def solve(self, f, tol=1e-10, maxiter=20000, mixed=False, out=None, stream=None,
+              raise_on_fail=True):
+        """u with A u = f (CG; mixed=True: FP32 inner CG + FP64 refinement).
+        Returns (u, list of per-RHS info dicts)."""
+        import torch
+        if f.dtype != torch.float64:
+            raise TypeError("f must be float64")
+        nrhs = self._nrhs(f)
+        if out is None:
+            out = torch.empty_like(f)
+        info = (FlInfo * nrhs)()
+        st = self._lib.fl_solve(self._h, ctypes.c_void_p(f.data_ptr()), None, float(tol),
+                                int(maxiter), 1 if mixed else 0, ctypes.c_void_p(out.data_ptr()),
+                                nrhs, info, _stream_ptr(stream))
+        infos = [i.as_dict() for i in info]
+        if raise_on_fail:
+            check(st)
+        return out, infos
+
+    def set_refinement(self, inner_tol, max_outer):
+        check(self._lib.fl_set_refinement(self._h, float(inner_tol), int(max_outer)))
+
+    def set_schedule(self, fp32, e_first=0, e_mid=0, e_c2c=0, w_first=0, w_c2c=0, lpb_mid=0):
+        check(self._lib.fl_set_schedule(self._h, int(bool(fp32)), e_first, e_mid, e_c2c,
+                                        w_first, w_c2c, lpb_mid))
+
+    def get_schedule(self, fp32):
+        s = (ctypes.c_int * 6)()
+        check(self._lib.fl_get_schedule(self._h, int(bool(fp32)), s))
+        return dict(zip(["e_first", "e_mid", "e_c2c", "w_first", "w_c2c", "lpb_mid"], list(s)))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.fl_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

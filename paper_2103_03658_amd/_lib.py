@@ -1,0 +1,85 @@
+"""ctypes binding of libfl.so (the C ABI declared in include/fl.h).
+
+Argument marshalling only: every step of the computation runs in the
+library's HIP kernels.  The library must be built in-tree
+(python -m paper_2103_03658_amd.build); there is no fallback.
+"""
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libfl.so")
+
+FL_OK = 0
+FL_E_INVAL = 1
+FL_E_UNSUPPORTED = 2
+FL_E_NOMEM = 3
+FL_E_DEVICE = 4
+FL_E_NOCONV = 5
+FL_E_BREAKDOWN = 6
+STATUS_NAMES = {0: "FL_OK", 1: "FL_E_INVAL", 2: "FL_E_UNSUPPORTED", 3: "FL_E_NOMEM",
+                4: "FL_E_DEVICE", 5: "FL_E_NOCONV", 6: "FL_E_BREAKDOWN"}
+
+FL_KERNEL_FRACTIONAL = 0
+FL_KERNEL_TEMPERED = 1
+
+
+class FlInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("outer_iters", ctypes.c_int),
+                ("converged", ctypes.c_int), ("status", ctypes.c_int),
+                ("relres_rec", ctypes.c_double), ("relres_true", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class FlError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+# name -> (restype, argtypes); mirrors include/fl.h
+_P = ctypes.c_void_p
+_SIGS = {
+    "fl_weights": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                  ctypes.c_int, ctypes.c_double, _P, ctypes.POINTER(_P)]),
+    "fl_generator": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t]),
+    "fl_symbol": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t]),
+    "fl_embedding": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t]),
+    "fl_query": (ctypes.c_int, [_P] + [ctypes.POINTER(ctypes.c_int)] * 4),
+    "fl_apply": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, _P]),
+    "fl_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_int, ctypes.c_int, _P,
+                                ctypes.c_int, ctypes.POINTER(FlInfo), _P]),
+    "fl_set_refinement": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int]),
+    "fl_set_schedule": (ctypes.c_int, [_P, ctypes.c_int] + [ctypes.c_int] * 6),
+    "fl_get_schedule": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+    "fl_destroy": (None, [_P]),
+    "fl_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libfl.so once; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError(f"{LIBPATH} is not built; run "
+                               "`python -m paper_2103_03658_amd.build` first")
+        handle = ctypes.CDLL(LIBPATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def check(status):
+    if status != FL_OK:
+        msg = lib().fl_last_error()
+        raise FlError(status, msg.decode() if msg else "")
+    return status

@@ -1,0 +1,547 @@
+// C ABI (include/fl.h): validation, operator handles, device buffers and
+// the host-side control of the solvers.  No exception crosses the boundary.
+#include "../../include/fl.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fl_internal.h"
+
+using fl::Error;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fl_status fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return (fl_status)code;
+}
+
+template <typename F>
+fl_status guarded(F&& f) {
+  try {
+    g_last_error.clear();
+    return f();
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(FL_E_NOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(FL_E_DEVICE, e.what());
+  }
+}
+
+void* dmalloc(size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 256;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error(FL_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  return p;
+}
+
+// Grow-only device buffer.
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  void* get(size_t need) {
+    if (need > bytes) {
+      if (p) hipFree(p);
+      p = nullptr;
+      bytes = 0;
+      p = dmalloc(need);
+      bytes = need;
+    }
+    return p;
+  }
+  void release() {
+    if (p) hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+};
+
+constexpr int kMaxBlocks = 4096;
+
+// Device-resident CG bookkeeping for up to `cap` right-hand sides.
+struct CgState {
+  DBuf mem;
+  int cap = 0;
+  fl::CgScalars s{};
+  void ensure(int nrhs, hipStream_t st) {
+    if (nrhs <= cap) return;
+    const size_t nd8 = (size_t)nrhs * sizeof(double);
+    const size_t ni4 = (size_t)nrhs * sizeof(int);
+    const size_t part = (size_t)nrhs * kMaxBlocks * sizeof(double);
+    const size_t total = 5 * nd8 + 3 * ni4 + 256 + 2 * part + 2 * ni4 + 64 * 16;
+    char* b = (char*)mem.get(total);
+    auto take = [&](size_t n) {
+      char* r = b;
+      b += (n + 255) / 256 * 256;
+      return r;
+    };
+    char* base = b;
+    s.rr = (double*)take(nd8);
+    s.alpha = (double*)take(nd8);
+    s.beta = (double*)take(nd8);
+    s.thresh2 = (double*)take(nd8);
+    s.rr0 = (double*)take(nd8);
+    s.active = (int*)take(ni4);
+    s.iters = (int*)take(ni4);
+    s.status = (int*)take(ni4);
+    s.n_active = (int*)take(sizeof(int));
+    s.part_a = (double*)take(part);
+    s.part_b = (double*)take(part);
+    s.cnt_a = (unsigned*)take(ni4);
+    s.cnt_b = (unsigned*)take(ni4);
+    s.max_blocks = kMaxBlocks;
+    fl::fill_zero_bytes(base, (size_t)(b - base), st);
+    cap = nrhs;
+  }
+};
+
+}  // namespace
+
+struct fl_op_s {
+  fl::Geometry g{};
+  int degree = 0, kernel = 0, device = 0;
+  double alpha = 0, h = 0, lambda = 0, c = 0;
+  double* G = nullptr;
+  double* lam64 = nullptr;
+  float* lam32 = nullptr;
+  const void* tw64 = nullptr;
+  const void* tw32 = nullptr;
+  fl::Schedule sc64{}, sc32{};
+  double inner_tol = 1e-4;
+  int max_outer = 40;
+  DBuf ws;                // FFT intermediates
+  DBuf vecs;              // solver vectors
+  CgState cg, cg_out;     // inner CG state; outer (refinement) bookkeeping
+  DBuf outer_flags;
+  hipEvent_t done = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool used = false;
+
+  // Order this call after the previous one if it ran on another stream
+  // (the workspace is shared).
+  void begin(hipStream_t st) {
+    if (used && st != last_stream) FL_HIP(hipStreamWaitEvent(st, done, 0));
+  }
+  void end(hipStream_t st) {
+    FL_HIP(hipEventRecord(done, st));
+    last_stream = st;
+    used = true;
+  }
+};
+
+namespace fl {
+
+Schedule default_schedule(const Geometry& g, bool fp32) {
+  const int M = g.M;
+  auto pickE = [&](int want) { return std::min(want, M); };
+  Schedule s{};
+  s.E_first = pickE(M >= 256 ? 16 : 8);
+  s.E_mid = pickE(M >= 256 ? 16 : 8);
+  s.E_c2c = pickE(M >= 256 ? 16 : 8);
+  const size_t tsz = fp32 ? 4 : 8;
+  auto fitW = [&](int E, int want) {
+    const int tpl = M / E;
+    const size_t lb = (size_t)2 * (M + M / E) * tsz;
+    int w = std::max(1, std::min(want, 256 / std::max(1, tpl)));
+    while (w > 1 && lb * w > 65536) w /= 2;
+    return w;
+  };
+  s.W_first = fitW(s.E_first, 16);
+  s.W_c2c = fitW(s.E_c2c, 16);
+  s.LPB_mid = fitW(s.E_mid, 64);
+  return s;
+}
+
+}  // namespace fl
+
+namespace {
+
+void set_device(fl_op A) { FL_HIP(hipSetDevice(A->device)); }
+
+void check_schedule(const fl::Geometry& g, const fl::Schedule& s, bool fp32) {
+  const size_t tsz = fp32 ? 4 : 8;
+  auto ok = [&](int E, int W) {
+    if (!(E == 8 || E == 16) || E > g.M) return false;
+    if (W < 1) return false;
+    const int tpl = g.M / E;
+    if ((long)W * tpl > 512) return false;
+    if ((size_t)2 * (g.M + g.M / E) * tsz * W > 65536) return false;
+    return true;
+  };
+  if (!ok(s.E_first, s.W_first) || !ok(s.E_mid, s.LPB_mid) || !ok(s.E_c2c, s.W_c2c))
+    throw Error(FL_E_INVAL, "schedule out of range");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fl_last_error(void) { return g_last_error.c_str(); }
+
+fl_status fl_weights(int d, double alpha, int degree, double h, int kernel, double lambda,
+                     void* stream, fl_op* out) {
+  return guarded([&]() -> fl_status {
+    if (!out) return fail(FL_E_INVAL, "out is NULL");
+    if (d < 1 || d > 3) return fail(FL_E_INVAL, "d must be 1, 2 or 3");
+    if (!(alpha > 0.0 && alpha < 2.0)) return fail(FL_E_INVAL, "alpha must lie in (0, 2)");
+    if (degree < 0 || degree > 2) return fail(FL_E_INVAL, "degree must be 0, 1 or 2");
+    if (!(h > 0.0) || !std::isfinite(h)) return fail(FL_E_INVAL, "h must be positive");
+    if (kernel != FL_KERNEL_FRACTIONAL && kernel != FL_KERNEL_TEMPERED)
+      return fail(FL_E_INVAL, "unknown kernel");
+    if (kernel == FL_KERNEL_TEMPERED && (!(lambda >= 0.0) || !std::isfinite(lambda)))
+      return fail(FL_E_INVAL, "lambda must be finite and >= 0");
+    const double Nf = 2.0 / h;
+    const double Nr = std::round(Nf);
+    if (!(Nr >= 1.0) || std::fabs(Nf - Nr) > 1e-12 * Nr)
+      return fail(FL_E_INVAL, "2/h must be an integer");
+    if (Nr > 1e6) return fail(FL_E_UNSUPPORTED, "N too large");
+    const int N = (int)Nr;
+    if (N < 4) return fail(FL_E_INVAL, "N = 2/h must be >= 4");
+    if (degree == 2 && N % 2) return fail(FL_E_INVAL, "degree 2 needs N even");
+    const int M = 2 * N;
+    if ((M & (M - 1)) || M < 8 || M > 2048)
+      return fail(FL_E_UNSUPPORTED, "M = 2N must be a power of two in [8, 2048]");
+    hipStream_t st = (hipStream_t)stream;
+    fl_op A = new fl_op_s();
+    try {
+      FL_HIP(hipGetDevice(&A->device));
+      A->g.d = d;
+      A->g.N = N;
+      A->g.n = N - 1;
+      A->g.M = M;
+      A->g.nd = 1;
+      for (int s = 0; s < d; ++s) A->g.nd *= (N - 1);
+      A->degree = degree;
+      A->kernel = kernel;
+      A->alpha = alpha;
+      A->h = 2.0 / N;
+      A->lambda = kernel == FL_KERNEL_TEMPERED ? lambda : 0.0;
+      // c_{d,alpha} = 2^{alpha-1} alpha Gamma((d+alpha)/2) / (pi^{d/2} Gamma(1-alpha/2))
+      A->c = std::pow(2.0, alpha - 1.0) * alpha * std::tgamma((d + alpha) / 2.0) /
+             (std::pow(M_PI, d / 2.0) * std::tgamma(1.0 - alpha / 2.0));
+      long nf = 1;
+      for (int s = 0; s < d; ++s) nf *= (N + 1);
+      A->G = (double*)dmalloc((size_t)nf * sizeof(double));
+      A->lam64 = (double*)dmalloc((size_t)nf * sizeof(double));
+      A->lam32 = (float*)dmalloc((size_t)nf * sizeof(float));
+      fl::GenParams gp{d, degree, N, kernel, alpha, A->h, A->lambda, A->c};
+      fl::build_generator(gp, A->G, st);
+      fl::build_symbol(A->g, A->G, A->lam64, A->lam32, st);
+      A->tw64 = fl::twiddles(M, false, st);
+      A->tw32 = fl::twiddles(M, true, st);
+      A->sc64 = fl::default_schedule(A->g, false);
+      A->sc32 = fl::default_schedule(A->g, true);
+      FL_HIP(hipEventCreateWithFlags(&A->done, hipEventDisableTiming));
+      FL_HIP(hipStreamSynchronize(st));
+    } catch (...) {
+      fl_destroy(A);
+      throw;
+    }
+    *out = A;
+    return FL_OK;
+  });
+}
+
+void fl_destroy(fl_op A) {
+  if (!A) return;
+  hipSetDevice(A->device);
+  hipDeviceSynchronize();
+  if (A->G) hipFree(A->G);
+  if (A->lam64) hipFree(A->lam64);
+  if (A->lam32) hipFree(A->lam32);
+  A->ws.release();
+  A->vecs.release();
+  A->cg.mem.release();
+  A->cg_out.mem.release();
+  A->outer_flags.release();
+  if (A->done) hipEventDestroy(A->done);
+  delete A;
+}
+
+fl_status fl_query(fl_op A, int* d, int* N, int* n, int* M) {
+  if (!A) return fail(FL_E_INVAL, "null handle");
+  if (d) *d = A->g.d;
+  if (N) *N = A->g.N;
+  if (n) *n = A->g.n;
+  if (M) *M = A->g.M;
+  return FL_OK;
+}
+
+static fl_status copy_out(fl_op A, const void* src, void* host, size_t count, size_t need,
+                          size_t esz) {
+  if (!A || !host) return fail(FL_E_INVAL, "null argument");
+  if (count < need) return fail(FL_E_INVAL, "output buffer too small");
+  set_device(A);
+  FL_HIP(hipDeviceSynchronize());
+  FL_HIP(hipMemcpy(host, src, need * esz, hipMemcpyDeviceToHost));
+  return FL_OK;
+}
+
+fl_status fl_generator(fl_op A, double* host_out, size_t count) {
+  return guarded([&]() -> fl_status {
+    if (!A) return fail(FL_E_INVAL, "null handle");
+    size_t nf = 1;
+    for (int s = 0; s < A->g.d; ++s) nf *= (size_t)(A->g.N + 1);
+    return copy_out(A, A->G, host_out, count, nf, sizeof(double));
+  });
+}
+
+fl_status fl_symbol(fl_op A, double* host_out, size_t count) {
+  return guarded([&]() -> fl_status {
+    if (!A) return fail(FL_E_INVAL, "null handle");
+    size_t nf = 1;
+    for (int s = 0; s < A->g.d; ++s) nf *= (size_t)(A->g.N + 1);
+    return copy_out(A, A->lam64, host_out, count, nf, sizeof(double));
+  });
+}
+
+fl_status fl_embedding(fl_op A, double* host_out, size_t count) {
+  return guarded([&]() -> fl_status {
+    if (!A || !host_out) return fail(FL_E_INVAL, "null argument");
+    size_t nm = 1;
+    for (int s = 0; s < A->g.d; ++s) nm *= (size_t)A->g.M;
+    if (count < nm) return fail(FL_E_INVAL, "output buffer too small");
+    set_device(A);
+    double* tmp = (double*)dmalloc(nm * sizeof(double));
+    fl::embed_generator(A->g, A->G, tmp, nullptr);
+    hipError_t e = hipMemcpy(host_out, tmp, nm * sizeof(double), hipMemcpyDeviceToHost);
+    hipFree(tmp);
+    if (e != hipSuccess) return fail(FL_E_DEVICE, hipGetErrorString(e));
+    return FL_OK;
+  });
+}
+
+fl_status fl_set_schedule(fl_op A, int fp32, int e_first, int e_mid, int e_c2c, int w_first,
+                          int w_c2c, int lpb_mid) {
+  return guarded([&]() -> fl_status {
+    if (!A) return fail(FL_E_INVAL, "null handle");
+    fl::Schedule s = fp32 ? A->sc32 : A->sc64;
+    if (e_first > 0) s.E_first = e_first;
+    if (e_mid > 0) s.E_mid = e_mid;
+    if (e_c2c > 0) s.E_c2c = e_c2c;
+    if (w_first > 0) s.W_first = w_first;
+    if (w_c2c > 0) s.W_c2c = w_c2c;
+    if (lpb_mid > 0) s.LPB_mid = lpb_mid;
+    check_schedule(A->g, s, fp32 != 0);
+    (fp32 ? A->sc32 : A->sc64) = s;
+    return FL_OK;
+  });
+}
+
+fl_status fl_get_schedule(fl_op A, int fp32, int* s6) {
+  if (!A || !s6) return fail(FL_E_INVAL, "null argument");
+  const fl::Schedule& s = fp32 ? A->sc32 : A->sc64;
+  s6[0] = s.E_first;
+  s6[1] = s.E_mid;
+  s6[2] = s.E_c2c;
+  s6[3] = s.W_first;
+  s6[4] = s.W_c2c;
+  s6[5] = s.LPB_mid;
+  return FL_OK;
+}
+
+fl_status fl_set_refinement(fl_op A, double inner_tol, int max_outer) {
+  if (!A) return fail(FL_E_INVAL, "null handle");
+  if (!(inner_tol > 0.0 && inner_tol < 1.0) || max_outer < 1)
+    return fail(FL_E_INVAL, "inner_tol in (0,1) and max_outer >= 1 required");
+  A->inner_tol = inner_tol;
+  A->max_outer = max_outer;
+  return FL_OK;
+}
+
+fl_status fl_apply(fl_op A, const void* u, void* y, int nrhs, int fp32, void* stream) {
+  return guarded([&]() -> fl_status {
+    if (!A) return fail(FL_E_INVAL, "null handle");
+    if (!u || !y) return fail(FL_E_INVAL, "null vector");
+    if (u == y) return fail(FL_E_INVAL, "u and y must be distinct");
+    if (nrhs < 1) return fail(FL_E_INVAL, "nrhs must be >= 1");
+    set_device(A);
+    hipStream_t st = (hipStream_t)stream;
+    A->begin(st);
+    void* ws = A->ws.get(fl::apply_workspace_bytes(A->g, nrhs, fp32 != 0));
+    if (fp32)
+      fl::apply_passes<float>(A->g, A->sc32, A->lam32, A->tw32, (const float*)u, (float*)y, nrhs,
+                              ws, st, fl::PM_PLAIN, nullptr, nullptr, nullptr, nullptr, nullptr);
+    else
+      fl::apply_passes<double>(A->g, A->sc64, A->lam64, A->tw64, (const double*)u, (double*)y,
+                               nrhs, ws, st, fl::PM_PLAIN, nullptr, nullptr, nullptr, nullptr,
+                               nullptr);
+    A->end(st);
+    return FL_OK;
+  });
+}
+
+}  // extern "C"
+
+namespace {
+
+// Run CG iterations until no right-hand side is active (checked every
+// `chunk` iterations with one 4-byte read) or the cap is reached.
+template <typename T>
+void cg_loop(fl_op A, const fl::Schedule& sc, const T* lam, const void* tw, T* x, T* r, T* p,
+             T* q, int nrhs, int maxiter, const fl::CgScalars& cg, void* ws, hipStream_t st) {
+  int done = 0;
+  int chunk = 4;
+  while (done < maxiter) {
+    const int k = std::min(chunk, maxiter - done);
+    for (int i = 0; i < k; ++i) {
+      fl::apply_passes<T>(A->g, sc, lam, tw, nullptr, q, nrhs, ws, st, fl::PM_CG, r, p, nullptr,
+                          &cg, cg.active);
+      fl::cg_update<T>(A->g, x, r, p, q, nrhs, maxiter, cg, st);
+    }
+    done += k;
+    int nact = 0;
+    FL_HIP(hipMemcpyAsync(&nact, cg.n_active, sizeof(int), hipMemcpyDeviceToHost, st));
+    FL_HIP(hipStreamSynchronize(st));
+    if (nact == 0) break;
+    chunk = std::min(chunk * 2, 64);
+  }
+}
+
+}  // namespace
+
+extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double tol, int maxiter,
+                              int mixed, double* u, int nrhs, fl_info* info, void* stream) {
+  return guarded([&]() -> fl_status {
+    if (!A) return fail(FL_E_INVAL, "null handle");
+    if (!f || !u) return fail(FL_E_INVAL, "null vector");
+    if (g) return fail(FL_E_UNSUPPORTED, "nonzero exterior data g is not supported");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(FL_E_INVAL, "tol must be positive");
+    if (maxiter < 1) return fail(FL_E_INVAL, "maxiter must be >= 1");
+    if (nrhs < 1) return fail(FL_E_INVAL, "nrhs must be >= 1");
+    if ((const void*)f == (const void*)u) return fail(FL_E_INVAL, "f and u must be distinct");
+    set_device(A);
+    hipStream_t st = (hipStream_t)stream;
+    A->begin(st);
+    const long nd = A->g.nd;
+    const size_t v8 = (size_t)nrhs * nd * sizeof(double);
+    const size_t v4 = (size_t)nrhs * nd * sizeof(float);
+    std::vector<int> iters(nrhs, 0), outer(nrhs, 0), status(nrhs, 0);
+    std::vector<double> rec(nrhs, 0.0), tru(nrhs, 0.0);
+    A->cg.ensure(nrhs, st);
+    A->cg_out.ensure(nrhs, st);
+    const fl::CgScalars& cg = A->cg.s;
+    const fl::CgScalars& co = A->cg_out.s;
+    if (!mixed) {
+      void* ws = A->ws.get(fl::apply_workspace_bytes(A->g, nrhs, false));
+      char* vb = (char*)A->vecs.get(3 * v8 + 3 * 256);
+      double* r = (double*)vb;
+      double* p = (double*)(vb + ((v8 + 255) / 256) * 256);
+      double* q = (double*)(vb + 2 * ((v8 + 255) / 256) * 256);
+      fl::fill_int(cg.n_active, 0, 1, st);
+      fl::cg_init<double>(A->g, f, u, r, p, nrhs, tol, cg, nullptr, st);
+      cg_loop<double>(A, A->sc64, A->lam64, A->tw64, u, r, p, q, nrhs, maxiter, cg, ws, st);
+      std::vector<double> rr(nrhs), rr0(nrhs);
+      FL_HIP(hipMemcpyAsync(iters.data(), cg.iters, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
+      FL_HIP(hipMemcpyAsync(status.data(), cg.status, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
+      FL_HIP(hipMemcpyAsync(rr.data(), cg.rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+      FL_HIP(hipMemcpyAsync(rr0.data(), cg.rr0, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+      // true residual with an FP64 product (into q)
+      fl::apply_passes<double>(A->g, A->sc64, A->lam64, A->tw64, u, q, nrhs, ws, st, fl::PM_RESID,
+                               nullptr, nullptr, f, &co, nullptr);
+      std::vector<double> rt(nrhs);
+      FL_HIP(hipMemcpyAsync(rt.data(), co.rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+      FL_HIP(hipStreamSynchronize(st));
+      for (int o = 0; o < nrhs; ++o) {
+        const double fn = std::sqrt(rr0[o]);
+        rec[o] = fn > 0 ? std::sqrt(rr[o]) / fn : 0.0;
+        tru[o] = fn > 0 ? std::sqrt(rt[o]) / fn : 0.0;
+        if (status[o] == 0 && !(rec[o] <= tol) && fn > 0) status[o] = FL_E_NOCONV;
+      }
+    } else {
+      // FP64 residual / iterate, FP32 inner CG on A delta = r / ||r||
+      void* ws = A->ws.get(fl::apply_workspace_bytes(A->g, nrhs, false));
+      const size_t a8 = ((v8 + 255) / 256) * 256, a4 = ((v4 + 255) / 256) * 256;
+      char* vb = (char*)A->vecs.get(a8 + 5 * a4 + 4 * 256);
+      double* r64 = (double*)vb;
+      float* rhs32 = (float*)(vb + a8);
+      float* d32 = (float*)(vb + a8 + a4);
+      float* r32 = (float*)(vb + a8 + 2 * a4);
+      float* p32 = (float*)(vb + a8 + 3 * a4);
+      float* q32 = (float*)(vb + a8 + 4 * a4);
+      int* oact = (int*)A->outer_flags.get((size_t)nrhs * sizeof(int) + 2 * nrhs * sizeof(double));
+      double* f2 = (double*)(oact + ((nrhs + 1) / 2) * 2);
+      double* scale = f2 + nrhs;
+      // u = 0, r = f, ||f||^2
+      fl::fill_zero_bytes(u, v8, st);
+      FL_HIP(hipMemcpyAsync(r64, f, v8, hipMemcpyDeviceToDevice, st));
+      fl::sum_squares(f, nd, nrhs, f2, co.part_a, co.cnt_a, co.max_blocks, st);
+      FL_HIP(hipMemcpyAsync(co.rr, f2, nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
+      std::vector<double> hf2(nrhs), hrr(nrhs);
+      std::vector<int> hact(nrhs), hit(nrhs), hst(nrhs);
+      FL_HIP(hipMemcpyAsync(hf2.data(), f2, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+      FL_HIP(hipStreamSynchronize(st));
+      hrr = hf2;
+      for (int step = 0;; ++step) {
+        int nact = 0;
+        for (int o = 0; o < nrhs; ++o) {
+          const double rel = hf2[o] > 0 ? std::sqrt(hrr[o] / hf2[o]) : 0.0;
+          const bool bad = !std::isfinite(rel);
+          hact[o] = (!bad && rel > tol && status[o] == 0) ? 1 : 0;
+          if (bad) status[o] = FL_E_BREAKDOWN;
+          nact += hact[o];
+        }
+        if (nact == 0) break;
+        if (step >= A->max_outer) {
+          for (int o = 0; o < nrhs; ++o)
+            if (hact[o]) status[o] = FL_E_NOCONV;
+          break;
+        }
+        FL_HIP(hipMemcpyAsync(oact, hact.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+        fl::refine_scale(r64, rhs32, co.rr, scale, nd, nrhs, oact, st);
+        fl::fill_int(cg.n_active, 0, 1, st);
+        fl::cg_init<float>(A->g, rhs32, d32, r32, p32, nrhs, A->inner_tol, cg, oact, st);
+        cg_loop<float>(A, A->sc32, A->lam32, A->tw32, d32, r32, p32, q32, nrhs, maxiter, cg, ws,
+                       st);
+        fl::refine_axpy(u, d32, scale, nd, nrhs, oact, st);
+        // r = f - A u in FP64 and ||r||^2 into co.rr
+        fl::apply_passes<double>(A->g, A->sc64, A->lam64, A->tw64, u, r64, nrhs, ws, st,
+                                 fl::PM_RESID, nullptr, nullptr, f, &co, oact);
+        FL_HIP(hipMemcpyAsync(hit.data(), cg.iters, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
+        FL_HIP(hipMemcpyAsync(hst.data(), cg.status, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
+        FL_HIP(hipMemcpyAsync(hrr.data(), co.rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+        FL_HIP(hipStreamSynchronize(st));
+        for (int o = 0; o < nrhs; ++o)
+          if (hact[o]) {
+            iters[o] += hit[o];
+            outer[o] += 1;
+            if (hst[o] == FL_E_BREAKDOWN && hit[o] == 0) status[o] = FL_E_BREAKDOWN;
+          }
+      }
+      for (int o = 0; o < nrhs; ++o) {
+        const double rel = hf2[o] > 0 ? std::sqrt(hrr[o] / hf2[o]) : 0.0;
+        rec[o] = rel;
+        tru[o] = rel;
+      }
+    }
+    A->end(st);
+    fl_status worst = FL_OK;
+    for (int o = 0; o < nrhs; ++o) {
+      if (info) {
+        info[o].iters = iters[o];
+        info[o].outer_iters = outer[o];
+        info[o].status = status[o];
+        info[o].converged = status[o] == 0;
+        info[o].relres_rec = rec[o];
+        info[o].relres_true = tru[o];
+      }
+      if (status[o] != 0 && worst == FL_OK) worst = (fl_status)status[o];
+    }
+    if (worst != FL_OK) g_last_error = "some right-hand sides did not converge";
+    return worst;
+  });
+}

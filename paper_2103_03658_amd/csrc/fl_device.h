@@ -1,0 +1,261 @@
+// Device-side building blocks shared by the library's kernels: complex
+// arithmetic, small in-register DFTs (radix 2/4/8/16) and the register+LDS
+// Stockham engine that transforms one line of length M held by M/E threads
+// (E elements per thread).  gfx950 (CDNA4, wave64) only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fl {
+
+template <typename T>
+struct cx {
+  T x, y;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
+  return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.x * s, a.y * s}; }
+
+// Multiply by DIR*i:  DIR = -1 gives -i (forward kernel e^{-2 pi i/4}), +1 gives +i.
+template <int DIR, typename T>
+__device__ __forceinline__ cx<T> mul_i(cx<T> a) {
+  if constexpr (DIR < 0) return {a.y, -a.x};
+  else return {-a.y, a.x};
+}
+
+// ---------------------------------------------------------------------------
+// In-register DFTs, natural order in and out.  X_k = sum_j v_j w^{jk},
+// w = exp(DIR * 2 pi i / R).  DIR = -1 forward, +1 inverse (unnormalised).
+// ---------------------------------------------------------------------------
+template <int DIR, typename T>
+__device__ __forceinline__ void dft2(cx<T>* v) {
+  cx<T> a = v[0];
+  v[0] = cadd(a, v[1]);
+  v[1] = csub(a, v[1]);
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft4(cx<T>* v) {
+  cx<T> a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+  cx<T> b0 = cadd(v[1], v[3]), b1 = mul_i<DIR>(csub(v[1], v[3]));
+  v[0] = cadd(a0, b0);
+  v[2] = csub(a0, b0);
+  v[1] = cadd(a1, b1);
+  v[3] = csub(a1, b1);
+}
+
+// w8^1 = (1 + DIR i)/sqrt2 ; w8^3 = (-1 + DIR i)/sqrt2
+template <int DIR, typename T>
+__device__ __forceinline__ cx<T> mul_w8_1(cx<T> a) {
+  const T s = (T)0.70710678118654752440084436210485;
+  if constexpr (DIR < 0) return {(a.x + a.y) * s, (a.y - a.x) * s};
+  else return {(a.x - a.y) * s, (a.y + a.x) * s};
+}
+template <int DIR, typename T>
+__device__ __forceinline__ cx<T> mul_w8_3(cx<T> a) {
+  const T s = (T)0.70710678118654752440084436210485;
+  if constexpr (DIR < 0) return {(a.y - a.x) * s, -(a.x + a.y) * s};
+  else return {-(a.x + a.y) * s, (a.x - a.y) * s};
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft8(cx<T>* v) {
+  cx<T> e[4] = {v[0], v[2], v[4], v[6]};
+  cx<T> o[4] = {v[1], v[3], v[5], v[7]};
+  dft4<DIR>(e);
+  dft4<DIR>(o);
+  o[1] = mul_w8_1<DIR>(o[1]);
+  o[2] = mul_i<DIR>(o[2]);
+  o[3] = mul_w8_3<DIR>(o[3]);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[k] = cadd(e[k], o[k]);
+    v[k + 4] = csub(e[k], o[k]);
+  }
+}
+
+// cos(2 pi j / 16), sin(2 pi j / 16) for j = 0..4
+template <typename T>
+__device__ __forceinline__ cx<T> w16(int jk) {
+  // returns exp(-2 pi i jk/16) for the forward sign; caller conjugates.
+  const T c1 = (T)0.92387953251128675612818318939679;
+  const T s1 = (T)0.38268343236508977172845998403040;
+  const T c2 = (T)0.70710678118654752440084436210485;
+  switch (jk & 15) {
+    case 0: return {(T)1, (T)0};
+    case 1: return {c1, -s1};
+    case 2: return {c2, -c2};
+    case 3: return {s1, -c1};
+    case 4: return {(T)0, (T)-1};
+    case 5: return {-s1, -c1};
+    case 6: return {-c2, -c2};
+    case 7: return {-c1, -s1};
+    case 8: return {(T)-1, (T)0};
+    case 9: return {-c1, s1};
+    case 10: return {-c2, c2};
+    case 11: return {-s1, c1};
+    case 12: return {(T)0, (T)1};
+    case 13: return {s1, c1};
+    case 14: return {c2, c2};
+    default: return {c1, s1};
+  }
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft16(cx<T>* v) {
+  // n = 4 n1 + n2, k = k1 + 4 k2
+  cx<T> a[4][4];
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+    for (int n1 = 0; n1 < 4; ++n1) a[n2][n1] = v[4 * n1 + n2];
+    dft4<DIR>(a[n2]);  // a[n2][k1]
+  }
+#pragma unroll
+  for (int n2 = 1; n2 < 4; ++n2) {
+#pragma unroll
+    for (int k1 = 1; k1 < 4; ++k1) {
+      cx<T> w = w16<T>(n2 * k1);
+      if constexpr (DIR > 0) w.y = -w.y;
+      a[n2][k1] = cmul(a[n2][k1], w);
+    }
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) {
+    cx<T> b[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+    dft4<DIR>(b);
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = b[k2];
+  }
+}
+
+template <int R, int DIR, typename T>
+__device__ __forceinline__ void dft(cx<T>* v) {
+  if constexpr (R == 1) {
+  } else if constexpr (R == 2) dft2<DIR>(v);
+  else if constexpr (R == 4) dft4<DIR>(v);
+  else if constexpr (R == 8) dft8<DIR>(v);
+  else if constexpr (R == 16) dft16<DIR>(v);
+  else static_assert(R == 2, "unsupported radix");
+}
+
+// ---------------------------------------------------------------------------
+// Stockham plan for a line of length M = E^(S-1) * R_last, E elements per
+// thread, TPL = M/E threads per line.  Stage s combines sub-transforms of
+// length Ls = E^s with radix R_s (E, ..., E, R_last).
+// ---------------------------------------------------------------------------
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
+constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
+template <int M, int E>
+struct Plan {
+  static_assert((M & (M - 1)) == 0 && (E & (E - 1)) == 0 && E <= M, "powers of two, E <= M");
+  static constexpr int TPL = M / E;
+  static constexpr int LOGE = ilog2(E);
+  static constexpr int S = (ilog2(M) + LOGE - 1) / LOGE;
+  static constexpr int RLAST = M / ipow(E, S - 1);
+  static constexpr int radix(int s) { return s < S - 1 ? E : RLAST; }
+  static constexpr int ls(int s) { return ipow(E, s); }
+  // register slot -> j such that the slot holds element t + TPL * j after
+  // the last stage (the first stage reads element t + TPL*j into slot j).
+  static constexpr int jslot(int slot) {
+    return (slot / RLAST) + (slot % RLAST) * (E / RLAST);
+  }
+  static constexpr int slot_of_j(int j) {
+    // inverse of jslot
+    return (j % (E / RLAST)) * RLAST + j / (E / RLAST);
+  }
+  // LDS words per line (padding one word per E elements breaks the stride-E
+  // bank pattern of the first exchange).
+  static constexpr int LDSN = M + M / E;
+  __device__ static __forceinline__ int pad(int i) { return i + (i >> LOGE); }
+};
+
+// One Stockham stage s >= 1: exchange the previous stage's outputs through
+// LDS, then twiddle and DFT.  lre/lim: this line's LDS planes.
+template <typename T, int M, int E, int DIR, int s>
+__device__ __forceinline__ void stockham_stage(cx<T> (&v)[E], T* lre, T* lim, int t,
+                                               const cx<T>* __restrict__ tw) {
+  using P = Plan<M, E>;
+  constexpr int TPL = P::TPL;
+  constexpr int Rp = P::radix(s - 1);
+  constexpr int Lp = P::ls(s - 1);
+  constexpr int R = P::radix(s);
+  constexpr int Ls = P::ls(s);
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < E / Rp; ++q) {
+    const int b = t + q * TPL;
+    const int k = b & (Lp - 1);
+#pragma unroll
+    for (int r = 0; r < Rp; ++r) {
+      const int o = P::pad((b - k) * Rp + k + r * Lp);
+      lre[o] = v[q * Rp + r].x;
+      lim[o] = v[q * Rp + r].y;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < E / R; ++q) {
+    const int b = t + q * TPL;
+    const int k = b & (Ls - 1);
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+      const int i = P::pad(b + j * (M / R));
+      v[q * R + j].x = lre[i];
+      v[q * R + j].y = lim[i];
+    }
+#pragma unroll
+    for (int j = 1; j < R; ++j) {
+      cx<T> w = tw[j * k * (M / (Ls * R))];
+      if constexpr (DIR > 0) w.y = -w.y;
+      v[q * R + j] = cmul(v[q * R + j], w);
+    }
+    dft<R, DIR>(&v[q * R]);
+  }
+}
+
+template <typename T, int M, int E, int DIR, int s>
+__device__ __forceinline__ void stockham_from(cx<T> (&v)[E], T* lre, T* lim, int t,
+                                              const cx<T>* __restrict__ tw) {
+  if constexpr (s < Plan<M, E>::S) {
+    stockham_stage<T, M, E, DIR, s>(v, lre, lim, t, tw);
+    stockham_from<T, M, E, DIR, s + 1>(v, lre, lim, t, tw);
+  }
+}
+
+// Full length-M transform of one line.  On entry slot j holds element
+// t + TPL*j; on exit slot `sl` holds output element t + TPL*Plan::jslot(sl).
+// Every thread of the block must call this (it contains barriers).
+template <typename T, int M, int E, int DIR>
+__device__ __forceinline__ void fft_line(cx<T> (&v)[E], T* lre, T* lim, int t,
+                                         const cx<T>* __restrict__ tw) {
+  dft<Plan<M, E>::radix(0), DIR>(v);
+  stockham_from<T, M, E, DIR, 1>(v, lre, lim, t, tw);
+}
+
+// Reorder slots so that slot j holds element t + TPL*j (compile-time permutation).
+template <typename T, int M, int E>
+__device__ __forceinline__ void to_natural(cx<T> (&v)[E]) {
+  cx<T> w[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) w[j] = v[Plan<M, E>::slot_of_j(j)];
+#pragma unroll
+  for (int j = 0; j < E; ++j) v[j] = w[j];
+}
+
+}  // namespace fl

@@ -1,0 +1,141 @@
+// Double-precision instantiation of the FFT passes, the twiddle tables and
+// the symbol construction (lambda-hat = DFT of the embedded generator / M^d).
+#include <map>
+#include <mutex>
+
+#include "passes_host.h"
+
+namespace fl {
+
+template <>
+void apply_passes<double>(const Geometry& g, const Schedule& sc, const double* lam,
+                          const void* tw, const double* u, double* y, int nrhs, void* ws,
+                          hipStream_t st, int mode, const double* rvec, double* pvec,
+                          const double* fvec, const CgScalars* cg, const int* active) {
+  apply_passes_t<double>(g, sc, lam, tw, u, y, nrhs, ws, st, mode, rvec, pvec, fvec, cg, active);
+}
+
+size_t apply_workspace_bytes(const Geometry& g, int nrhs, bool fp32) {
+  return fp32 ? ws_bytes_t<float>(g, nrhs) : ws_bytes_t<double>(g, nrhs);
+}
+
+const void* twiddles(int M, bool fp32, hipStream_t st) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, bool>, void*> cache;
+  int dev = 0;
+  FL_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto key = std::make_tuple(dev, M, fp32);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  void* p = nullptr;
+  const size_t bytes = (size_t)M * (fp32 ? sizeof(cx<float>) : sizeof(cx<double>));
+  FL_HIP(hipMalloc(&p, bytes));
+  const int thr = 256, blk = (M + thr - 1) / thr;
+  if (fp32)
+    hipLaunchKernelGGL(k_twiddle<float>, dim3(blk), dim3(thr), 0, st, (cx<float>*)p, M);
+  else
+    hipLaunchKernelGGL(k_twiddle<double>, dim3(blk), dim3(thr), 0, st, (cx<double>*)p, M);
+  check_launch("twiddles");
+  FL_HIP(hipStreamSynchronize(st));
+  cache[key] = p;
+  return p;
+}
+
+// c[j] = G[m(j)] with m(j_s) = min(j_s, M - j_s); zero where some m(j_s) > N-2.
+__device__ __forceinline__ double embed_value(const double* G, int d, int N, int M, long j) {
+  long rem = j;
+  long gi = 0;
+  bool keep = true;
+  int idx[3] = {0, 0, 0};
+  for (int s = d - 1; s >= 0; --s) {  // last index fastest
+    idx[s] = (int)(rem % M);
+    rem /= M;
+  }
+  for (int s = 0; s < d; ++s) {
+    const int m = idx[s] <= M - idx[s] ? idx[s] : M - idx[s];
+    keep = keep && (m <= N - 2);
+    gi = gi * (N + 1) + m;
+  }
+  return keep ? G[gi] : 0.0;
+}
+
+__global__ void k_embed(cx<double>* c, const double* G, int d, int N, int M, long total) {
+  const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < total) c[j] = {embed_value(G, d, N, M, j), 0.0};
+}
+
+__global__ void k_embed_real(double* c, const double* G, int d, int N, int M, long total) {
+  const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < total) c[j] = embed_value(G, d, N, M, j);
+}
+
+void embed_generator(const Geometry& g, const double* G, double* out, hipStream_t st) {
+  long total = 1;
+  for (int s = 0; s < g.d; ++s) total *= g.M;
+  hipLaunchKernelGGL(k_embed_real, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, out,
+                     G, g.d, g.N, g.M, total);
+  check_launch("embed");
+}
+
+// lambda-hat folded to k in [0, N]^d: Re(c_hat[k]) / M^d, plus an FP32 copy.
+__global__ void k_fold(const cx<double>* chat, double* l64, float* l32, int d, int N, int M,
+                       long total, double inv) {
+  const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= total) return;
+  long rem = k;
+  int idx[3] = {0, 0, 0};
+  for (int s = d - 1; s >= 0; --s) {
+    idx[s] = (int)(rem % (N + 1));
+    rem /= (N + 1);
+  }
+  long ci = 0;
+  for (int s = 0; s < d; ++s) ci = ci * M + idx[s];
+  const double v = chat[ci].x * inv;
+  l64[k] = v;
+  l32[k] = (float)v;
+}
+
+void build_symbol(const Geometry& g, const double* G, double* lam64, float* lam32,
+                  hipStream_t st) {
+  const int M = g.M, d = g.d;
+  long total = 1;
+  for (int s = 0; s < d; ++s) total *= M;
+  cx<double>* c = nullptr;
+  FL_HIP(hipMalloc(&c, (size_t)total * sizeof(cx<double>)));
+  const int thr = 256;
+  hipLaunchKernelGGL(k_embed, dim3((unsigned)((total + thr - 1) / thr)), dim3(thr), 0, st, c, G,
+                     d, g.N, M, total);
+  check_launch("embed");
+  const cx<double>* tw = reinterpret_cast<const cx<double>*>(twiddles(M, false, st));
+  const int E = M >= 16 ? 16 : 8;
+  const int TPL = M / E;
+  const size_t lb = line_lds_bytes<double>(M, E);
+  int W = 256 / TPL;
+  if (W < 1) W = 1;
+  while (W > 1 && lb * W > 65536) W /= 2;
+  long Md1 = total / M;  // lines per axis
+  if (d >= 2) {
+    // axis 0: columns = M^(d-1), row stride M^(d-1)
+    C2CArgs<double> a0{c, c, nullptr, Md1, 0, Md1, 0, Md1, 1, M, M, W, tw};
+    launch_c2c<double>(M, E, -1, a0, 1, st);
+  }
+  if (d == 3) {
+    // axis 1: slices k0 (stride M*M), rows stride M, columns M
+    C2CArgs<double> a1{c, c, nullptr, M, (long)M * M, M, (long)M * M, M, 1, M, M, W, tw};
+    launch_c2c<double>(M, E, -1, a1, M, st);
+  }
+  int LPB = 256 / TPL;
+  if (LPB < 1) LPB = 1;
+  while (LPB > 1 && lb * LPB > 65536) LPB /= 2;
+  launch_fwd_rows<double>(M, E, c, Md1, LPB, tw, st);
+  long nf = 1;
+  for (int s = 0; s < d; ++s) nf *= (g.N + 1);
+  hipLaunchKernelGGL(k_fold, dim3((unsigned)((nf + thr - 1) / thr)), dim3(thr), 0, st, c, lam64,
+                     lam32, d, g.N, M, nf, 1.0 / (double)total);
+  check_launch("fold");
+  FL_HIP(hipStreamSynchronize(st));
+  FL_HIP(hipFree(c));
+}
+
+}  // namespace fl

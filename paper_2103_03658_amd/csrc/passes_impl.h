@@ -1,0 +1,595 @@
+// FFT pass kernels of the circulant-embedded multilevel Toeplitz product
+//   y = Re IDFT_M( lambda-hat * DFT_M( zero-pad(u) ) ) restricted to [0,n)^d
+// (the fast product that the Toeplitz structure of A^(1), A^(2) allows,
+// Sec. 2.1 and 2.2).  Included by one translation unit per precision.
+//
+// Data layout (row-major, last index fastest, RHS-major):
+//   u, y          [nrhs][n]^d                 real
+//   T1 (2D, 3D)   [nrhs][M/2+1][n^(d-1)]      complex, after the axis-0 pass
+//   T2 (3D)       [nrhs][M/2+1][M][n]         complex, after the axis-1 pass
+// The axis-0 pass packs two real columns into one complex line and splits
+// the result by Hermitian symmetry, so only rows 0..M/2 of the axis-0
+// frequency exist (the product of a real input with the real, even symbol
+// keeps that symmetry, which the last pass uses to rebuild the other half).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fl_device.h"
+#include "fl_internal.h"
+
+namespace fl {
+
+// ---------------------------------------------------------------------------
+// reductions
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Deterministic block sum (fixed tree for a fixed blockDim); result in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  const int tid = threadIdx.x;
+  v = wave_sum(v);
+  __syncthreads();
+  if ((tid & 63) == 0) sh[tid >> 6] = v;
+  __syncthreads();
+  const int nw = (blockDim.x + 63) >> 6;
+  double s = 0.0;
+  if (tid < 64) {
+    s = tid < nw ? sh[tid] : 0.0;
+    s = wave_sum(s);
+  }
+  return s;
+}
+
+// Publish this block's partial; if it is the last of nb blocks, return true
+// in every thread of the block and the total (fixed order) in *total (thread 0).
+__device__ __forceinline__ bool last_block_total(double blk, double* part, unsigned* cnt, int nb,
+                                                 int bidx, double* sh, double* total) {
+  __shared__ int s_last;
+  if (threadIdx.x == 0) {
+    part[bidx] = blk;
+    __threadfence();
+    unsigned prev = atomicAdd(cnt, 1u);
+    s_last = (prev == (unsigned)(nb - 1));
+    if (s_last) __threadfence();
+  }
+  __syncthreads();
+  if (!s_last) return false;
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nb; i += blockDim.x)
+    v += __hip_atomic_load(&part[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  v = block_sum(v, sh);
+  if (threadIdx.x == 0) {
+    *total = v;
+    atomicExch(cnt, 0u);
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// first pass (axis 0, strided): real columns packed in pairs -> rows 0..M/2
+// ---------------------------------------------------------------------------
+template <typename T>
+struct FirstArgs {
+  const T* u;            // PM_PLAIN input
+  T* p;                  // PM_CG: p <- r + beta p (in place)
+  const T* r;
+  const double* beta;    // per RHS
+  const int* active;     // per RHS, may be null
+  cx<T>* out;
+  long C;                // real columns per RHS (n^(d-1))
+  long in_os;            // elements between RHS in u/p/r
+  long out_os;           // complex elements between RHS in out
+  int n_in;              // rows of input (n)
+  int W;                 // complex lines per block
+  int mode;
+  const cx<T>* tw;
+};
+
+template <typename T, int M, int E>
+__global__ void __launch_bounds__(512) k_first(FirstArgs<T> a) {
+  using P = Plan<M, E>;
+  constexpr int TPL = P::TPL;
+  extern __shared__ unsigned char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  const int o = blockIdx.y;
+  if (a.active && !a.active[o]) return;
+  const int W = a.W;
+  const int c = threadIdx.x % W, t = threadIdx.x / W;
+  T* lre = lds + (long)c * 2 * P::LDSN;
+  T* lim = lre + P::LDSN;
+  const long col = ((long)blockIdx.x * W + c) * 2;
+  const bool h0 = col < a.C, h1 = col + 1 < a.C;
+  const T bt = a.mode == PM_CG ? (T)a.beta[o] : (T)0;
+  cx<T> v[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int row = t + j * TPL;
+    T re = 0, im = 0;
+    if (row < a.n_in) {
+      const long i0 = (long)o * a.in_os + (long)row * a.C + col;
+      if (a.mode == PM_CG) {
+        if (h0) { re = a.r[i0] + bt * a.p[i0]; a.p[i0] = re; }
+        if (h1) { im = a.r[i0 + 1] + bt * a.p[i0 + 1]; a.p[i0 + 1] = im; }
+      } else {
+        if (h0) re = a.u[i0];
+        if (h1) im = a.u[i0 + 1];
+      }
+    }
+    v[j] = {re, im};
+  }
+  fft_line<T, M, E, -1>(v, lre, lim, t, a.tw);
+  __syncthreads();
+#pragma unroll
+  for (int sl = 0; sl < E; ++sl) {
+    const int i = P::pad(t + TPL * P::jslot(sl));
+    lre[i] = v[sl].x;
+    lim[i] = v[sl].y;
+  }
+  __syncthreads();
+  const T half = (T)0.5;
+#pragma unroll
+  for (int j = 0; j <= E / 2; ++j) {
+    const int k = t + TPL * j;
+    if (k <= M / 2) {
+      const int km = (M - k) & (M - 1);
+      const cx<T> z = {lre[P::pad(k)], lim[P::pad(k)]};
+      const cx<T> zm = {lre[P::pad(km)], lim[P::pad(km)]};
+      // X_a = (Z + conj Zm)/2 ; X_b = (Z - conj Zm)/(2i)
+      const cx<T> xa = {(z.x + zm.x) * half, (z.y - zm.y) * half};
+      const cx<T> xb = {(z.y + zm.y) * half, (zm.x - z.x) * half};
+      const long oi = (long)o * a.out_os + (long)k * a.C + col;
+      if (h0) a.out[oi] = xa;
+      if (h1) a.out[oi + 1] = xb;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// last pass (axis 0, strided): rows 0..M/2 (Hermitian half) -> real pairs
+// ---------------------------------------------------------------------------
+template <typename T>
+struct LastArgs {
+  const cx<T>* in;
+  T* y;
+  const T* p;            // PM_CG: dot partner
+  const double* f;       // PM_RESID: right-hand side (FP64)
+  const int* active;
+  CgScalars cg;
+  long C;                // real columns per RHS
+  long in_os;            // complex elements between RHS of in
+  long y_os;             // elements between RHS of y / p / f
+  int n_out;
+  int W;
+  int mode;
+  const cx<T>* tw;
+};
+
+template <typename T, int M, int E>
+__global__ void __launch_bounds__(512) k_last(LastArgs<T> a) {
+  using P = Plan<M, E>;
+  constexpr int TPL = P::TPL;
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ double red[16];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  const int o = blockIdx.y;
+  if (a.active && !a.active[o]) return;
+  const int W = a.W;
+  const int c = threadIdx.x % W, t = threadIdx.x / W;
+  T* lre = lds + (long)c * 2 * P::LDSN;
+  T* lim = lre + P::LDSN;
+  const long col = ((long)blockIdx.x * W + c) * 2;
+  const bool h0 = col < a.C, h1 = col + 1 < a.C;
+  cx<T> v[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int idx = t + j * TPL;
+    const bool up = idx > M / 2;
+    const int kk = up ? M - idx : idx;
+    const long ii = (long)o * a.in_os + (long)kk * a.C + col;
+    cx<T> ya = {0, 0}, yb = {0, 0};
+    if (h0) ya = a.in[ii];
+    if (h1) yb = a.in[ii + 1];
+    if (up) { ya.y = -ya.y; yb.y = -yb.y; }
+    v[j] = {ya.x - yb.y, ya.y + yb.x};  // Ya + i Yb
+  }
+  fft_line<T, M, E, +1>(v, lre, lim, t, a.tw);
+  double acc = 0.0;
+#pragma unroll
+  for (int sl = 0; sl < E; ++sl) {
+    const int row = t + TPL * P::jslot(sl);
+    if (row < a.n_out) {
+      const long i0 = (long)o * a.y_os + (long)row * a.C + col;
+      if (a.mode == PM_RESID) {
+        if (h0) { const double r0 = a.f[i0] - (double)v[sl].x; a.y[i0] = (T)r0; acc += r0 * r0; }
+        if (h1) { const double r1 = a.f[i0 + 1] - (double)v[sl].y; a.y[i0 + 1] = (T)r1; acc += r1 * r1; }
+      } else {
+        if (h0) a.y[i0] = v[sl].x;
+        if (h1) a.y[i0 + 1] = v[sl].y;
+        if (a.mode == PM_CG) {
+          if (h0) acc += (double)a.p[i0] * (double)v[sl].x;
+          if (h1) acc += (double)a.p[i0 + 1] * (double)v[sl].y;
+        }
+      }
+    }
+  }
+  if (a.mode == PM_PLAIN) return;
+  const double blk = block_sum(acc, red);
+  double tot = 0.0;
+  const int nb = gridDim.x;
+  if (last_block_total(blk, a.cg.part_a + (long)o * a.cg.max_blocks, a.cg.cnt_a + o, nb,
+                       blockIdx.x, red, &tot)) {
+    if (threadIdx.x == 0) {
+      if (a.mode == PM_CG) {
+        const double al = a.cg.rr[o] / tot;
+        if (!(tot > 0.0) || !isfinite(al)) {
+          a.cg.active[o] = 0;
+          a.cg.status[o] = 6;
+          atomicSub(a.cg.n_active, 1);
+          a.cg.alpha[o] = 0.0;
+        } else {
+          a.cg.alpha[o] = al;
+        }
+      } else {
+        a.cg.rr[o] = tot;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// strided complex-to-complex pass (3D axis 1; symbol construction)
+// ---------------------------------------------------------------------------
+template <typename T>
+struct C2CArgs {
+  const cx<T>* in;
+  cx<T>* out;
+  const int* active;     // per RHS (outer index / outer_per_rhs), may be null
+  long C;                // complex columns
+  long in_os, in_rs;     // per outer slice / per row (complex elements)
+  long out_os, out_rs;
+  int outer_per_rhs;
+  int n_in, n_out;
+  int W;
+  const cx<T>* tw;
+};
+
+template <typename T, int M, int E, int DIR>
+__global__ void __launch_bounds__(512) k_c2c(C2CArgs<T> a) {
+  using P = Plan<M, E>;
+  constexpr int TPL = P::TPL;
+  extern __shared__ unsigned char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  const int o = blockIdx.y;
+  if (a.active && !a.active[o / a.outer_per_rhs]) return;
+  const int W = a.W;
+  const int c = threadIdx.x % W, t = threadIdx.x / W;
+  T* lre = lds + (long)c * 2 * P::LDSN;
+  T* lim = lre + P::LDSN;
+  const long col = (long)blockIdx.x * W + c;
+  const bool h = col < a.C;
+  cx<T> v[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int row = t + j * TPL;
+    v[j] = (h && row < a.n_in) ? a.in[(long)o * a.in_os + (long)row * a.in_rs + col]
+                               : cx<T>{0, 0};
+  }
+  fft_line<T, M, E, DIR>(v, lre, lim, t, a.tw);
+#pragma unroll
+  for (int sl = 0; sl < E; ++sl) {
+    const int row = t + TPL * P::jslot(sl);
+    if (h && row < a.n_out) a.out[(long)o * a.out_os + (long)row * a.out_rs + col] = v[sl];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// middle pass (last axis, contiguous): forward, symbol multiply, inverse
+// ---------------------------------------------------------------------------
+template <typename T>
+struct MidArgs {
+  cx<T>* data;
+  const T* lam;          // folded symbol, (N+1)^d
+  const int* active;
+  long rows;             // lines per RHS
+  long o_stride;         // complex elements between RHS
+  long row_stride;       // complex elements between lines
+  int n_in, n_out;
+  int N1;                // N + 1
+  int d;
+  int LPB;
+  const cx<T>* tw;
+};
+
+template <typename T, int M, int E>
+__global__ void __launch_bounds__(512) k_mid(MidArgs<T> a) {
+  using P = Plan<M, E>;
+  constexpr int TPL = P::TPL;
+  extern __shared__ unsigned char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  const int o = blockIdx.y;
+  if (a.active && !a.active[o]) return;
+  const int l = threadIdx.x / TPL, t = threadIdx.x % TPL;
+  const long line = (long)blockIdx.x * a.LPB + l;
+  const bool h = line < a.rows;
+  T* lre = lds + (long)l * 2 * P::LDSN;
+  T* lim = lre + P::LDSN;
+  cx<T>* base = a.data + (long)o * a.o_stride + (h ? line : 0) * a.row_stride;
+  cx<T> v[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int i = t + j * TPL;
+    v[j] = (h && i < a.n_in) ? base[i] : cx<T>{0, 0};
+  }
+  fft_line<T, M, E, -1>(v, lre, lim, t, a.tw);
+  // symbol row of this line
+  long lrow;
+  if (a.d == 3) {
+    const long k0 = line / M, k1 = line % M;
+    lrow = (k0 * a.N1 + (k1 <= M / 2 ? k1 : M - k1)) * a.N1;
+  } else if (a.d == 2) {
+    lrow = line * a.N1;
+  } else {
+    lrow = 0;
+  }
+  const T* lr = a.lam + (h ? lrow : 0);
+#pragma unroll
+  for (int sl = 0; sl < E; ++sl) {
+    const int k = t + TPL * P::jslot(sl);
+    const T s = lr[k <= M / 2 ? k : M - k];
+    v[sl] = cscale(v[sl], s);
+  }
+  to_natural<T, M, E>(v);
+  fft_line<T, M, E, +1>(v, lre, lim, t, a.tw);
+#pragma unroll
+  for (int sl = 0; sl < E; ++sl) {
+    const int i = t + TPL * P::jslot(sl);
+    if (h && i < a.n_out) base[i] = v[sl];
+  }
+}
+
+// contiguous forward transform of full lines (symbol construction)
+template <typename T, int M, int E>
+__global__ void __launch_bounds__(512) k_fwd_rows(cx<T>* data, long rows, int LPB,
+                                                   const cx<T>* tw) {
+  using P = Plan<M, E>;
+  constexpr int TPL = P::TPL;
+  extern __shared__ unsigned char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  const int l = threadIdx.x / TPL, t = threadIdx.x % TPL;
+  const long line = (long)blockIdx.x * LPB + l;
+  const bool h = line < rows;
+  T* lre = lds + (long)l * 2 * P::LDSN;
+  T* lim = lre + P::LDSN;
+  cx<T>* base = data + (h ? line : 0) * (long)M;
+  cx<T> v[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) v[j] = h ? base[t + j * TPL] : cx<T>{0, 0};
+  fft_line<T, M, E, -1>(v, lre, lim, t, tw);
+#pragma unroll
+  for (int sl = 0; sl < E; ++sl)
+    if (h) base[t + TPL * P::jslot(sl)] = v[sl];
+}
+
+// ---------------------------------------------------------------------------
+// 1D: one right-hand side per line, whole product in one block
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Line1Args {
+  const T* u;
+  T* y;
+  T* p;
+  const T* r;
+  const double* f;
+  const double* beta;
+  const int* active;
+  CgScalars cg;
+  const T* lam;
+  int n;
+  int nrhs;
+  int mode;
+  const cx<T>* tw;
+};
+
+template <typename T, int M, int E>
+__global__ void __launch_bounds__(512) k_line1d(Line1Args<T> a) {
+  using P = Plan<M, E>;
+  constexpr int TPL = P::TPL;
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ double red[16];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  T* lre = lds;
+  T* lim = lds + P::LDSN;
+  const int t = threadIdx.x;
+  // one right-hand side per line (imaginary part zero): its bits do not
+  // depend on which other right-hand sides share the launch
+  const int ra = blockIdx.x, rb = ra;
+  const bool hb = false;
+  const bool acta = !a.active || a.active[ra];
+  const bool actb = hb && (!a.active || a.active[rb]);
+  if (!acta && !actb) return;
+  const long n = a.n;
+  const T ba = (a.mode == PM_CG && acta) ? (T)a.beta[ra] : (T)0;
+  const T bb = (a.mode == PM_CG && actb) ? (T)a.beta[rb] : (T)0;
+  cx<T> v[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int i = t + j * TPL;
+    T re = 0, im = 0;
+    if (i < n) {
+      if (a.mode == PM_CG) {
+        if (acta) { re = a.r[ra * n + i] + ba * a.p[ra * n + i]; a.p[ra * n + i] = re; }
+        if (actb) { im = a.r[rb * n + i] + bb * a.p[rb * n + i]; a.p[rb * n + i] = im; }
+      } else {
+        if (acta) re = a.u[ra * n + i];
+        if (actb) im = a.u[rb * n + i];
+      }
+    }
+    v[j] = {re, im};
+  }
+  fft_line<T, M, E, -1>(v, lre, lim, t, a.tw);
+#pragma unroll
+  for (int sl = 0; sl < E; ++sl) {
+    const int k = t + TPL * P::jslot(sl);
+    v[sl] = cscale(v[sl], a.lam[k <= M / 2 ? k : M - k]);
+  }
+  to_natural<T, M, E>(v);
+  fft_line<T, M, E, +1>(v, lre, lim, t, a.tw);
+  double sa = 0.0, sb = 0.0;
+#pragma unroll
+  for (int sl = 0; sl < E; ++sl) {
+    const int i = t + TPL * P::jslot(sl);
+    if (i < n) {
+      if (a.mode == PM_RESID) {
+        if (acta) { const double q = a.f[ra * n + i] - (double)v[sl].x; a.y[ra * n + i] = (T)q; sa += q * q; }
+        if (actb) { const double q = a.f[rb * n + i] - (double)v[sl].y; a.y[rb * n + i] = (T)q; sb += q * q; }
+      } else {
+        if (acta) a.y[ra * n + i] = v[sl].x;
+        if (actb) a.y[rb * n + i] = v[sl].y;
+        if (a.mode == PM_CG) {
+          if (acta) sa += (double)a.p[ra * n + i] * (double)v[sl].x;
+          if (actb) sb += (double)a.p[rb * n + i] * (double)v[sl].y;
+        }
+      }
+    }
+  }
+  if (a.mode == PM_PLAIN) return;
+  sa = block_sum(sa, red);
+  __syncthreads();
+  sb = block_sum(sb, red);
+  if (threadIdx.x == 0) {
+    for (int s = 0; s < 2; ++s) {
+      const int rr = s ? rb : ra;
+      const bool act = s ? actb : acta;
+      const double tot = s ? sb : sa;
+      if (!act) continue;
+      if (a.mode == PM_CG) {
+        const double al = a.cg.rr[rr] / tot;
+        if (!(tot > 0.0) || !isfinite(al)) {
+          a.cg.active[rr] = 0;
+          a.cg.status[rr] = 6;
+          atomicSub(a.cg.n_active, 1);
+          a.cg.alpha[rr] = 0.0;
+        } else {
+          a.cg.alpha[rr] = al;
+        }
+      } else {
+        a.cg.rr[rr] = tot;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+#define FL_CASE_ME(M_, E_, ...) \
+  case (M_ * 64 + E_): {        \
+    constexpr int M = M_;       \
+    constexpr int E = E_;       \
+    __VA_ARGS__;                \
+  } break;
+
+#define FL_DISPATCH(Mv, Ev, ...)                                                         \
+  switch ((Mv) * 64 + (Ev)) {                                                            \
+    FL_CASE_ME(8, 8, __VA_ARGS__)                                                        \
+    FL_CASE_ME(16, 8, __VA_ARGS__)                                                       \
+    FL_CASE_ME(16, 16, __VA_ARGS__)                                                      \
+    FL_CASE_ME(32, 8, __VA_ARGS__)                                                       \
+    FL_CASE_ME(32, 16, __VA_ARGS__)                                                      \
+    FL_CASE_ME(64, 8, __VA_ARGS__)                                                       \
+    FL_CASE_ME(64, 16, __VA_ARGS__)                                                      \
+    FL_CASE_ME(128, 8, __VA_ARGS__)                                                      \
+    FL_CASE_ME(128, 16, __VA_ARGS__)                                                     \
+    FL_CASE_ME(256, 8, __VA_ARGS__)                                                      \
+    FL_CASE_ME(256, 16, __VA_ARGS__)                                                     \
+    FL_CASE_ME(512, 8, __VA_ARGS__)                                                      \
+    FL_CASE_ME(512, 16, __VA_ARGS__)                                                     \
+    FL_CASE_ME(1024, 8, __VA_ARGS__)                                                     \
+    FL_CASE_ME(1024, 16, __VA_ARGS__)                                                    \
+    FL_CASE_ME(2048, 8, __VA_ARGS__)                                                     \
+    FL_CASE_ME(2048, 16, __VA_ARGS__)                                                    \
+    default:                                                                             \
+      throw Error(2, "unsupported transform length / radix (M=" + std::to_string(Mv) +   \
+                         ", E=" + std::to_string(Ev) + ")");                             \
+  }
+
+template <typename T>
+inline size_t line_lds_bytes(int M, int E) {
+  return (size_t)2 * (M + M / E) * sizeof(T);
+}
+
+inline void check_launch(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) throw Error(4, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <typename T>
+void launch_first(int M, int E, const FirstArgs<T>& a, int nrhs, hipStream_t st) {
+  const long pairs = (a.C + 1) / 2;
+  dim3 grid((unsigned)((pairs + a.W - 1) / a.W), (unsigned)nrhs);
+  const int threads = a.W * (M / E);
+  const size_t sh = line_lds_bytes<T>(M, E) * a.W;
+  FL_DISPATCH(M, E, hipLaunchKernelGGL((k_first<T, M, E>), grid, dim3(threads), sh, st, a));
+  check_launch("first pass");
+}
+
+template <typename T>
+void launch_last(int M, int E, const LastArgs<T>& a, int nrhs, hipStream_t st) {
+  const long pairs = (a.C + 1) / 2;
+  dim3 grid((unsigned)((pairs + a.W - 1) / a.W), (unsigned)nrhs);
+  if (a.mode != PM_PLAIN && (int)grid.x > a.cg.max_blocks)
+    throw Error(2, "too many blocks for the reduction buffers");
+  const int threads = a.W * (M / E);
+  const size_t sh = line_lds_bytes<T>(M, E) * a.W;
+  FL_DISPATCH(M, E, hipLaunchKernelGGL((k_last<T, M, E>), grid, dim3(threads), sh, st, a));
+  check_launch("last pass");
+}
+
+template <typename T>
+void launch_c2c(int M, int E, int dir, const C2CArgs<T>& a, long outer, hipStream_t st) {
+  dim3 grid((unsigned)((a.C + a.W - 1) / a.W), (unsigned)outer);
+  const int threads = a.W * (M / E);
+  const size_t sh = line_lds_bytes<T>(M, E) * a.W;
+  if (dir < 0) {
+    FL_DISPATCH(M, E, hipLaunchKernelGGL((k_c2c<T, M, E, -1>), grid, dim3(threads), sh, st, a));
+  } else {
+    FL_DISPATCH(M, E, hipLaunchKernelGGL((k_c2c<T, M, E, 1>), grid, dim3(threads), sh, st, a));
+  }
+  check_launch("c2c pass");
+}
+
+template <typename T>
+void launch_mid(int M, int E, const MidArgs<T>& a, int nrhs, hipStream_t st) {
+  dim3 grid((unsigned)((a.rows + a.LPB - 1) / a.LPB), (unsigned)nrhs);
+  const int threads = a.LPB * (M / E);
+  const size_t sh = line_lds_bytes<T>(M, E) * a.LPB;
+  FL_DISPATCH(M, E, hipLaunchKernelGGL((k_mid<T, M, E>), grid, dim3(threads), sh, st, a));
+  check_launch("middle pass");
+}
+
+template <typename T>
+void launch_fwd_rows(int M, int E, cx<T>* data, long rows, int LPB, const cx<T>* tw,
+                     hipStream_t st) {
+  dim3 grid((unsigned)((rows + LPB - 1) / LPB));
+  const int threads = LPB * (M / E);
+  const size_t sh = line_lds_bytes<T>(M, E) * LPB;
+  FL_DISPATCH(M, E, hipLaunchKernelGGL((k_fwd_rows<T, M, E>), grid, dim3(threads), sh, st,
+                                       data, rows, LPB, tw));
+  check_launch("row transform");
+}
+
+template <typename T>
+void launch_line1d(int M, int E, const Line1Args<T>& a, hipStream_t st) {
+  dim3 grid((unsigned)a.nrhs);
+  const int threads = M / E;
+  const size_t sh = line_lds_bytes<T>(M, E);
+  FL_DISPATCH(M, E, hipLaunchKernelGGL((k_line1d<T, M, E>), grid, dim3(threads), sh, st, a));
+  check_launch("1D line");
+}
+
+}  // namespace fl

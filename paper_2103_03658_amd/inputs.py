@@ -1,0 +1,64 @@
+"""Seeded synthetic inputs (right-hand sides, request streams).
+
+Holds none of the method's arithmetic: only random draws and grid shapes.
+Seeds follow one convention everywhere: numpy's PCG64 via
+numpy.random.default_rng, FP64 draws in row-major order over the n^d
+interior points; right-hand side j of a batch seeded s uses seed s + j.
+"""
+
+import numpy as np
+
+
+def grid_shape(d, N):
+    return (N - 1,) * d
+
+
+def uniform_rhs(d, N, nrhs=1, seed=0):
+    """nrhs arrays of i.i.d. U[-1, 1] values, shape (nrhs, n, ..., n)."""
+    shp = grid_shape(d, N)
+    return np.stack([np.random.default_rng(seed + j).uniform(-1.0, 1.0, shp)
+                     for j in range(nrhs)])
+
+
+def normal_rhs(d, N, nrhs=1, seed=0):
+    """nrhs arrays of i.i.d. N(0, 1) values, shape (nrhs, n, ..., n)."""
+    shp = grid_shape(d, N)
+    return np.stack([np.random.default_rng(seed + j).standard_normal(shp)
+                     for j in range(nrhs)])
+
+
+def interior_coords(d, N):
+    """Coordinates x_i = -1 + (i+1) h of the interior points, one array per axis."""
+    h = 2.0 / N
+    x = -1.0 + h * np.arange(1, N)
+    return np.meshgrid(*([x] * d), indexing="ij")
+
+
+def request_stream(n_requests=4096, rate=200.0, seed=0, alpha_round=0.01):
+    """Serving workload: Poisson arrivals, d = 2 problems of mixed size.
+
+    Each request: n in {63, 127, 255, 511} with probabilities 0.4/0.3/0.2/0.1
+    (N = n + 1), alpha ~ U(0.2, 1.9) rounded to `alpha_round` (so that
+    identical operators recur), degree in {0, 1, 2}, 1..8 right-hand sides
+    of U[-1, 1] values drawn from default_rng([seed, request id, j])."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, n_requests))
+    ns = rng.choice([63, 127, 255, 511], size=n_requests, p=[0.4, 0.3, 0.2, 0.1])
+    alphas = rng.uniform(0.2, 1.9, n_requests)
+    if alpha_round:
+        alphas = np.round(alphas / alpha_round) * alpha_round
+    degrees = rng.integers(0, 3, n_requests)
+    nrhs = rng.integers(1, 9, n_requests)
+    reqs = []
+    for i in range(n_requests):
+        reqs.append(dict(id=i, t_arrive=float(t[i]), d=2, N=int(ns[i]) + 1,
+                         alpha=float(alphas[i]), degree=int(degrees[i]),
+                         nrhs=int(nrhs[i]), seed=[seed, i]))
+    return reqs
+
+
+def request_rhs(req):
+    """Right-hand sides of one request, shape (nrhs, n, n)."""
+    n = req["N"] - 1
+    return np.stack([np.random.default_rng(list(req["seed"]) + [j]).uniform(-1.0, 1.0, (n, n))
+                     for j in range(req["nrhs"])])

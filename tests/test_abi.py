@@ -1,0 +1,78 @@
+"""The C ABI library loads, exports every symbol the header declares, and
+rejects invalid arguments before touching a device (CPU only)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2103_03658_amd as fl
+from paper_2103_03658_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for fn in os.listdir(inc):
+        if fn.endswith(".h"):
+            text = open(os.path.join(inc, fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(fl_[a-z_0-9]+)\s*\(", text))
+    return names
+
+
+def test_library_exports_header_symbols():
+    lib = _lib.lib()
+    names = declared_symbols()
+    assert {"fl_weights", "fl_apply", "fl_solve", "fl_destroy"} <= names
+    for name in names:
+        assert hasattr(lib, name), name
+    # the binding declares exactly the header's functions
+    assert set(_lib._SIGS) == names
+
+
+@pytest.mark.parametrize("args,code", [
+    ((0, 1.0, 1, 0.25), _lib.FL_E_INVAL),        # d
+    ((4, 1.0, 1, 0.25), _lib.FL_E_INVAL),
+    ((2, 0.0, 1, 0.25), _lib.FL_E_INVAL),        # alpha
+    ((2, 2.0, 1, 0.25), _lib.FL_E_INVAL),
+    ((2, float("nan"), 1, 0.25), _lib.FL_E_INVAL),
+    ((2, 1.0, 3, 0.25), _lib.FL_E_INVAL),        # degree
+    ((2, 1.0, 1, 0.3), _lib.FL_E_INVAL),         # 2/h not an integer
+    ((2, 1.0, 1, -0.25), _lib.FL_E_INVAL),
+    ((2, 1.0, 1, 1.0), _lib.FL_E_INVAL),         # N = 2 < 4
+    ((2, 1.0, 2, 2.0 / 9), _lib.FL_E_INVAL),     # p = 2, N odd
+    ((2, 1.0, 1, 2.0 / 12), _lib.FL_E_UNSUPPORTED),  # M = 24
+    ((1, 1.0, 1, 2.0 / 2048), _lib.FL_E_UNSUPPORTED),  # M = 4096
+])
+def test_fl_weights_validation(args, code):
+    lib = _lib.lib()
+    h = ctypes.c_void_p()
+    st = lib.fl_weights(*args, 0, 0.0, None, ctypes.byref(h))
+    assert st == code
+    assert lib.fl_last_error()
+    assert h.value is None
+
+
+def test_tempered_lambda_validation():
+    lib = _lib.lib()
+    h = ctypes.c_void_p()
+    assert lib.fl_weights(2, 1.0, 1, 0.25, 1, -1.0, None, ctypes.byref(h)) == _lib.FL_E_INVAL
+    assert lib.fl_weights(2, 1.0, 1, 0.25, 7, 0.0, None, ctypes.byref(h)) == _lib.FL_E_INVAL
+
+
+def test_null_handle_errors():
+    lib = _lib.lib()
+    assert lib.fl_apply(None, None, None, 1, 0, None) == _lib.FL_E_INVAL
+    assert lib.fl_solve(None, None, None, 1e-10, 10, 0, None, 1, None, None) == _lib.FL_E_INVAL
+    assert lib.fl_set_refinement(None, 1e-3, 3) == _lib.FL_E_INVAL
+    lib.fl_destroy(None)  # accepted
+
+
+def test_error_raises_in_binding():
+    with pytest.raises(fl.FlError) as ei:
+        fl.Operator(2, 1.0, 2, N=9)
+    assert ei.value.status == _lib.FL_E_INVAL
