@@ -1,0 +1,227 @@
+#!/usr/bin/env python3
+"""Benchmark of the fractional-Poisson hot path on one MI355X.
+
+Workload (the headline configuration): 2D, Omega = (-1,1)^2, N = 512
+(511^2 = 261,121 unknowns, embedding 1024^2), quadratic basis, alpha cycling
+over {0.5, 1.0, 1.5}; each step solves one batch of 17 right-hand sides
+(the manufactured right-hand side of u = (1-|x|^2)_+^{1+alpha/2} inside the
+unit disk plus 16 U[-1,1] fields, seeds 0..15) to a relative residual of
+1e-10 with the mixed path (FP32 inner CG, FP64 refinement) of fl_solve.
+Operators (weights, symbol) are built before the timed region; inputs are
+resident in HBM when it starts.
+
+Printed: one JSON line with solves/s (right-hand sides solved per second),
+p50/p99 latency of a batch, the FP64 one-at-a-time path for comparison,
+the roofline of the dominant FFT-matvec kernel (HIP events inside the
+library, on the stream the kernels run on), and the CPU oracle timed on a
+bounded sample as a baseline.
+"""
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+METRIC = ("CG solves/s + p50/p99 latency (2D 511², tol 1e-10); "
+          "FFT-matvec HBM GB/s")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=6)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--N", type=int, default=512)
+    ap.add_argument("--degree", type=int, default=2)
+    ap.add_argument("--nrand", type=int, default=16)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--path", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--fp64-single", type=int, default=2,
+                    help="right-hand sides per alpha solved one at a time in FP64 for comparison")
+    ap.add_argument("--cpu-budget", type=float, default=20.0,
+                    help="seconds of oracle work for the CPU baseline (0: skip)")
+    ap.add_argument("--profile-reps", type=int, default=20)
+    return ap.parse_args()
+
+
+def pass_bytes(d, N, nrhs, sr):
+    """Algorithmic HBM bytes of each kernel of one batched product y = A u
+    (2D: axis-0 forward, last-axis fused, axis-0 inverse).  Complex values
+    are 2*sr bytes; the axis-0 frequency keeps rows 0..M/2 (Hermitian half)."""
+    n, M = N - 1, 2 * N
+    h = M // 2 + 1
+    assert d == 2
+    vec = n * n * sr * nrhs
+    mid = h * n * 2 * sr * nrhs
+    sym = (N + 1) ** 2 * sr
+    return [vec + mid, 2 * mid + sym, mid + vec]
+
+
+def cpu_baseline(N, degree, alpha, iters, budget):
+    """Time the oracle (dense block-Toeplitz product, no FFT) on this host."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+    cores = len(os.sched_getaffinity(0))
+    cores = min(cores, 16)
+    ctx = threadpool_limits(limits=cores) if threadpool_limits else None
+    try:
+        t0 = time.perf_counter()
+        G = oracle.generator(2, alpha, degree, N)
+        t_gen = time.perf_counter() - t0
+        from paper_2103_03658_amd import inputs
+        u = inputs.uniform_rhs(2, N, 1, seed=0)[0]
+        nmv = 0
+        t0 = time.perf_counter()
+        while True:
+            oracle.apply_bttb(G, u)
+            nmv += 1
+            el = time.perf_counter() - t0
+            if el > budget or nmv >= 50:
+                break
+        t_mv = el / nmv
+    finally:
+        if ctx is not None:
+            ctx.__exit__(None, None, None)
+    return dict(value=1.0 / (t_mv * iters), unit="solves/s", cores=cores, kind="oracle",
+                sample=(f"oracle block-Toeplitz product (no FFT) at {N - 1}^2, p={degree}, "
+                        f"alpha={alpha}: {nmv} products in {el:.1f} s ({t_mv:.3f} s each); "
+                        f"solves/s = 1/(t_product * {iters} CG iterations, the FP64 "
+                        f"iteration count of this matrix at tol 1e-10); oracle generator "
+                        f"{t_gen:.1f} s not included"),
+                matvec_s=t_mv, generator_s=t_gen)
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; "
+                          f"--gpus {args.gpus} (WORLD_SIZE {world}) is not supported"}))
+        sys.exit(2)
+    import torch
+    import paper_2103_03658_amd as fl
+    from paper_2103_03658_amd import inputs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    N, p = args.N, args.degree
+    alphas = [0.5, 1.0, 1.5]
+    nrhs = 1 + args.nrand
+    t0 = time.perf_counter()
+    ops, rhs = {}, {}
+    setup_s = {}
+    for a in alphas:
+        ts = time.perf_counter()
+        ops[a] = fl.Operator(2, a, p, N=N)
+        torch.cuda.synchronize()
+        setup_s[a] = time.perf_counter() - ts
+        f = np.concatenate([inputs.manufactured_rhs_disk(N, a)[None],
+                            inputs.uniform_rhs(2, N, args.nrand, seed=0)])
+        rhs[a] = torch.from_numpy(f).to(dev)
+    out = torch.empty_like(rhs[alphas[0]])
+    mixed = args.path == "mixed"
+
+    def step(k):
+        a = alphas[k % len(alphas)]
+        _, info = ops[a].solve(rhs[a], tol=args.tol, mixed=mixed, out=out)
+        return info
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    lat, infos = [], []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        infos.append(step(k))
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t_start
+    solves = args.steps * nrhs
+    value = solves / total
+    max_relres = max(i["relres_true"] for inf in infos for i in inf)
+    iters = {alphas[k % 3]: [i["iters"] for i in infos[k]] for k in range(min(3, args.steps))}
+    outers = {alphas[k % 3]: [i["outer_iters"] for i in infos[k]]
+              for k in range(min(3, args.steps))}
+
+    # FP64, one right-hand side at a time (the plain path), same operators
+    fp64 = {}
+    if args.fp64_single > 0:
+        n1 = args.fp64_single
+        tsum, cnt, it64 = 0.0, 0, {}
+        for a in alphas:
+            for j in range(n1):
+                f1 = rhs[a][1 + j].contiguous()
+                ops[a].solve(f1, tol=args.tol, mixed=False)  # warm
+                torch.cuda.synchronize()
+                ts = time.perf_counter()
+                _, inf = ops[a].solve(f1, tol=args.tol, mixed=False)
+                tsum += time.perf_counter() - ts
+                cnt += 1
+                it64.setdefault(a, []).append(inf[0]["iters"])
+        fp64 = {"solves_per_s": cnt / tsum, "ms_per_solve": 1e3 * tsum / cnt,
+                "iters": it64}
+        # accuracy of the mixed path against the FP64 path (one RHS per alpha)
+        diffs = []
+        for a in alphas:
+            f1 = rhs[a][1].contiguous()
+            u64, _ = ops[a].solve(f1, tol=args.tol, mixed=False)
+            umx, _ = ops[a].solve(f1, tol=args.tol, mixed=True)
+            diffs.append(float((umx - u64).abs().max() / u64.abs().max()))
+        fp64["mixed_vs_fp64_rel_linf"] = max(diffs)
+
+    # roofline of the dominant FFT-matvec kernel (FP32, the inner-solve product)
+    a = 1.5
+    u32 = rhs[a].to(torch.float32).contiguous()
+    ms = ops[a].profile_apply(u32, reps=args.profile_reps)
+    by = pass_bytes(2, N, nrhs, 4)
+    names = ["axis0_fwd_r2c", "last_axis_fwd_symbol_inv", "axis0_inv_c2r"]
+    gbs = [b / (t * 1e-3) / 1e9 for b, t in zip(by, ms)]
+    dom = int(np.argmax(ms))
+    ms64 = ops[a].profile_apply(rhs[a], reps=args.profile_reps)
+    by64 = pass_bytes(2, N, nrhs, 8)
+    roof = {"bound": "hbm", "achieved": gbs[dom], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs[dom] / HBM_PEAK_GBS, "traffic": None,
+            "kernel": names[dom], "precision": "f32", "nrhs": nrhs,
+            "bytes_per_launch": by[dom], "ms_per_launch": ms[dom],
+            "per_kernel": [{"kernel": nm, "ms": t, "bytes": b, "GBs": g}
+                           for nm, t, b, g in zip(names, ms, by, gbs)],
+            "matvec_GBs_f32": sum(by) / (sum(ms) * 1e-3) / 1e9,
+            "matvec_GBs_f64": sum(by64) / (sum(ms64) * 1e-3) / 1e9,
+            "matvec_ms_f32": sum(ms), "matvec_ms_f64": sum(ms64)}
+
+    cpu = None
+    if args.cpu_budget > 0:
+        it_ref = int(np.median(fp64["iters"][1.0])) if fp64 else 150
+        cpu = cpu_baseline(N, p, 1.0, it_ref, args.cpu_budget)
+
+    lat_ms = np.array(lat) * 1e3
+    res = {
+        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * total / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if mixed else "f64", "data": "synthetic",
+        "config": {"workload": (f"2D fractional Poisson, {N - 1}^2 unknowns (N={N}, embedding "
+                                f"{2 * N}^2), degree {p}, alpha cycling 0.5/1.0/1.5, "
+                                f"{nrhs} RHS per batched solve, tol {args.tol:g}, "
+                                + ("FP32-inner CG + FP64 refinement" if mixed else "FP64 CG")),
+                   "global_batch": nrhs, "grid": f"{N - 1}x{N - 1}", "degree": p,
+                   "alphas": alphas, "tol": args.tol, "path": args.path},
+        "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+        "latency_unit": "ms per batched solve (all RHS of the batch complete)",
+        "max_relres_true": max_relres, "iters": iters, "outer_iters": outers,
+        "setup_s": setup_s, "fp64_single": fp64, "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -146,6 +146,22 @@ fl_status fl_set_schedule(fl_op A, int fp32, int e_first, int e_mid, int e_c2c, 
                           int w_c2c, int lpb_mid);
 fl_status fl_get_schedule(fl_op A, int fp32, int *sched6);
 
+/*
+ * fl_profile_apply -- measurement hook: run fl_apply's kernel sequence
+ * `reps` times on `stream` with a HIP event recorded between consecutive
+ * kernels, and return the mean duration of each kernel in milliseconds.
+ * The kernels are the transform passes in launch order: 1 for d = 1 (the
+ * whole product), 3 for d = 2 (axis 0 forward, last axis forward * symbol *
+ * inverse, axis 0 inverse), 5 for d = 3 (axis 0, axis 1, last axis, axis 1
+ * inverse, axis 0 inverse).  Same arguments as fl_apply plus
+ *   reps          >= 1
+ *   ms_per_pass   host array of at least max_passes doubles (output)
+ *   n_passes      host int (output): number of kernels per application
+ * Blocks until done.  Errors as fl_apply; FL_E_INVAL if max_passes is too small.
+ */
+fl_status fl_profile_apply(fl_op A, const void *u, void *y, int nrhs, int fp32, int reps,
+                           void *stream, double *ms_per_pass, int max_passes, int *n_passes);
+
 /* Release the handle and its device memory.  NULL is accepted. */
 void fl_destroy(fl_op A);
 

@@ -132,15 +132,14 @@ def apply_bttb(G, u):
         T = toeplitz(G[:n])
         return T @ u
     if d == 2:
-        # Toeplitz blocks T_m[i1, j1] = G[m, |i1 - j1|]
-        j = np.arange(n)
-        D = np.abs(j[:, None] - j[None, :])
-        Tm = G[:n][:, D]                                # (m, i1, j1)
-        V = Tm @ u.T                                    # (m, i1, j0)
+        # y[i0] = sum_m ( Z_m[i0 - m] + Z_m[i0 + m] ), Z_m[j0] = T_m u[j0],
+        # T_m[i1, j1] = G[m, |i1 - j1|] (symmetric Toeplitz block)
         y = np.zeros((n, n))
-        for i0 in range(n):
-            m = np.abs(i0 - j)                          # over j0
-            y[i0] = V[m, :, j].sum(axis=0)
+        for m in range(n):
+            Z = u @ toeplitz(G[m, :n])
+            y[m:] += Z[:n - m]
+            if m:
+                y[:n - m] += Z[m:]
         return y
     if d == 3:
         y = np.zeros((n, n, n))

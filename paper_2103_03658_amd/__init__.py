@@ -109,6 +109,21 @@ class Operator:
             check(st)
         return out, infos
 
+    def profile_apply(self, u, out=None, reps=20, stream=None):
+        """Mean milliseconds per kernel of y = A u (HIP events between the
+        kernels, on the stream the kernels run on)."""
+        import torch
+        nrhs = self._nrhs(u)
+        if out is None:
+            out = torch.empty_like(u)
+        ms = (ctypes.c_double * 8)()
+        npass = ctypes.c_int()
+        check(self._lib.fl_profile_apply(self._h, ctypes.c_void_p(u.data_ptr()),
+                                         ctypes.c_void_p(out.data_ptr()), nrhs,
+                                         1 if u.dtype == torch.float32 else 0, int(reps),
+                                         _stream_ptr(stream), ms, 8, ctypes.byref(npass)))
+        return [ms[i] for i in range(npass.value)]
+
     def set_refinement(self, inner_tol, max_outer):
         check(self._lib.fl_set_refinement(self._h, float(inner_tol), int(max_outer)))
 

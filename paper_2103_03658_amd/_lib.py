@@ -55,6 +55,9 @@ _SIGS = {
     "fl_set_refinement": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int]),
     "fl_set_schedule": (ctypes.c_int, [_P, ctypes.c_int] + [ctypes.c_int] * 6),
     "fl_get_schedule": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+    "fl_profile_apply": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        _P, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_int)]),
     "fl_destroy": (None, [_P]),
     "fl_last_error": (ctypes.c_char_p, []),
 }

@@ -385,6 +385,50 @@ fl_status fl_apply(fl_op A, const void* u, void* y, int nrhs, int fp32, void* st
   });
 }
 
+fl_status fl_profile_apply(fl_op A, const void* u, void* y, int nrhs, int fp32, int reps,
+                           void* stream, double* ms_per_pass, int max_passes, int* n_passes) {
+  return guarded([&]() -> fl_status {
+    if (!A) return fail(FL_E_INVAL, "null handle");
+    if (!u || !y || !ms_per_pass || !n_passes) return fail(FL_E_INVAL, "null argument");
+    if (u == y) return fail(FL_E_INVAL, "u and y must be distinct");
+    if (nrhs < 1 || reps < 1) return fail(FL_E_INVAL, "nrhs and reps must be >= 1");
+    const int np = fl::apply_npasses(A->g.d);
+    if (max_passes < np) return fail(FL_E_INVAL, "max_passes too small");
+    set_device(A);
+    hipStream_t st = (hipStream_t)stream;
+    A->begin(st);
+    void* ws = A->ws.get(fl::apply_workspace_bytes(A->g, nrhs, fp32 != 0));
+    std::vector<hipEvent_t> ev((size_t)(np + 1) * reps);
+    for (auto& e : ev) FL_HIP(hipEventCreate(&e));
+    for (int r = 0; r < reps; ++r) {
+      hipEvent_t* er = ev.data() + (size_t)r * (np + 1);
+      if (fp32)
+        fl::apply_passes<float>(A->g, A->sc32, A->lam32, A->tw32, (const float*)u, (float*)y,
+                                nrhs, ws, st, fl::PM_PLAIN, nullptr, nullptr, nullptr, nullptr,
+                                nullptr, er);
+      else
+        fl::apply_passes<double>(A->g, A->sc64, A->lam64, A->tw64, (const double*)u,
+                                 (double*)y, nrhs, ws, st, fl::PM_PLAIN, nullptr, nullptr,
+                                 nullptr, nullptr, nullptr, er);
+    }
+    FL_HIP(hipStreamSynchronize(st));
+    for (int k = 0; k < np; ++k) {
+      double tot = 0.0;
+      for (int r = 0; r < reps; ++r) {
+        float ms = 0.f;
+        FL_HIP(hipEventElapsedTime(&ms, ev[(size_t)r * (np + 1) + k],
+                                   ev[(size_t)r * (np + 1) + k + 1]));
+        tot += ms;
+      }
+      ms_per_pass[k] = tot / reps;
+    }
+    *n_passes = np;
+    for (auto& e : ev) hipEventDestroy(e);
+    A->end(st);
+    return FL_OK;
+  });
+}
+
 }  // extern "C"
 
 namespace {

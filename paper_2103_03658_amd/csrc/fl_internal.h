@@ -82,7 +82,10 @@ template <typename T>
 void apply_passes(const Geometry& g, const Schedule& sc, const T* lam, const void* tw,
                   const T* u, T* y, int nrhs, void* ws, hipStream_t st, int mode,
                   const T* rvec, T* pvec, const double* fvec, const CgScalars* cg,
-                  const int* active);
+                  const int* active, hipEvent_t* ev = nullptr);
+
+// Number of kernel launches (passes) of one application: 1, 3 or 5 for d = 1, 2, 3.
+inline int apply_npasses(int d) { return d == 1 ? 1 : (d == 2 ? 3 : 5); }
 
 // Twiddle table exp(-2 pi i j / M), j < M (cx<T> array), cached per device.
 const void* twiddles(int M, bool fp32, hipStream_t st);

@@ -11,8 +11,9 @@ template <>
 void apply_passes<double>(const Geometry& g, const Schedule& sc, const double* lam,
                           const void* tw, const double* u, double* y, int nrhs, void* ws,
                           hipStream_t st, int mode, const double* rvec, double* pvec,
-                          const double* fvec, const CgScalars* cg, const int* active) {
-  apply_passes_t<double>(g, sc, lam, tw, u, y, nrhs, ws, st, mode, rvec, pvec, fvec, cg, active);
+                          const double* fvec, const CgScalars* cg, const int* active,
+                          hipEvent_t* ev) {
+  apply_passes_t<double>(g, sc, lam, tw, u, y, nrhs, ws, st, mode, rvec, pvec, fvec, cg, active, ev);
 }
 
 size_t apply_workspace_bytes(const Geometry& g, int nrhs, bool fp32) {

@@ -62,3 +62,17 @@ def request_rhs(req):
     n = req["N"] - 1
     return np.stack([np.random.default_rng(list(req["seed"]) + [j]).uniform(-1.0, 1.0, (n, n))
                      for j in range(req["nrhs"])])
+
+
+def manufactured_rhs_disk(N, alpha):
+    """Right-hand side for u = (1-|x|^2)_+^{1+alpha/2} on the 2D grid, taken
+    inside the unit disk from the closed form
+    2^alpha Gamma(1+alpha/2) Gamma(2+alpha/2) (1 - (1+alpha/2)|x|^2)
+    and set to zero in the corners |x| >= 1 of the square (there the
+    continuous value needs a singular quadrature; for throughput runs any
+    right-hand side serves).  Shape (n, n)."""
+    import math
+    X0, X1 = interior_coords(2, N)
+    r2 = X0 * X0 + X1 * X1
+    c = 2.0 ** alpha * math.gamma(1.0 + alpha / 2.0) * math.gamma(2.0 + alpha / 2.0)
+    return np.where(r2 < 1.0, c * (1.0 - (1.0 + alpha / 2.0) * r2), 0.0)
