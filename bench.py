@@ -46,6 +46,9 @@ def parse():
     ap.add_argument("--cpu-budget", type=float, default=20.0,
                     help="seconds of oracle work for the CPU baseline (0: skip)")
     ap.add_argument("--profile-reps", type=int, default=20)
+    ap.add_argument("--no-tune", action="store_true", help="keep the default launch schedule")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only time the FFT-matvec kernels (for profiler runs)")
     return ap.parse_args()
 
 
@@ -128,6 +131,29 @@ def main():
         rhs[a] = torch.from_numpy(f).to(dev)
     out = torch.empty_like(rhs[alphas[0]])
     mixed = args.path == "mixed"
+
+    # launch schedules: tuned once per precision on one operator (same M for all)
+    from paper_2103_03658_amd import tune as _tune
+    sched = {"default_f32": ops[1.5].get_schedule(True), "default_f64": ops[1.5].get_schedule(False)}
+    if not args.no_tune:
+        t_tune = time.perf_counter()
+        for fp32 in (True, False):
+            best, _ = _tune.tune(ops[1.5], nrhs, fp32, use_cache=False)
+            for a in alphas:
+                ops[a].set_schedule(fp32, **best)
+        sched["tune_s"] = time.perf_counter() - t_tune
+    sched["f32"] = ops[1.5].get_schedule(True)
+    sched["f64"] = ops[1.5].get_schedule(False)
+
+    if args.roofline_only:
+        u32 = rhs[1.5].to(torch.float32).contiguous()
+        for _ in range(max(1, args.steps)):
+            ms = ops[1.5].profile_apply(u32, reps=args.profile_reps)
+        by = pass_bytes(2, N, nrhs, 4)
+        print(json.dumps({"roofline_only": True, "ms_per_kernel": ms,
+                          "GBs": [b / (t * 1e-3) / 1e9 for b, t in zip(by, ms)],
+                          "schedule": sched}))
+        return
 
     def step(k):
         a = alphas[k % len(alphas)]
@@ -218,7 +244,8 @@ def main():
         "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
         "latency_unit": "ms per batched solve (all RHS of the batch complete)",
         "max_relres_true": max_relres, "iters": iters, "outer_iters": outers,
-        "setup_s": setup_s, "fp64_single": fp64, "roofline": roof, "cpu_baseline": cpu,
+        "setup_s": setup_s, "schedule": sched, "fp64_single": fp64, "roofline": roof,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(res))
 

@@ -137,9 +137,10 @@ fl_status fl_set_refinement(fl_op A, double inner_tol, int max_outer);
 
 /*
  * Launch schedule of the transform passes (elements per thread E and lines
- * per block) for FP64 (fp32 = 0) or FP32 transforms.  E in {8, 16}, E <= M;
- * lines per block >= 1 with (lines * M / E) <= 512 threads and at most
- * 64 KiB of LDS.  Values <= 0 keep the current setting.  Used by the
+ * per block) for FP64 (fp32 = 0) or FP32 transforms.  E in {8, 16, 32},
+ * E <= M; lines per block >= 1 with (lines * M / E) <= 512 threads and
+ * lines * 2 (M + M/E) * sizeof(real) <= 160 KiB of LDS.  Values <= 0 keep
+ * the current setting; FL_E_INVAL leaves it unchanged.  Used by the
  * schedule tuner; results do not depend on the schedule beyond rounding.
  */
 fl_status fl_set_schedule(fl_op A, int fp32, int e_first, int e_mid, int e_c2c, int w_first,

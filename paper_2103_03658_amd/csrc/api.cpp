@@ -70,7 +70,7 @@ struct DBuf {
   }
 };
 
-constexpr int kMaxBlocks = 4096;
+constexpr int kMaxBlocks = 8192;
 
 // Device-resident CG bookkeeping for up to `cap` right-hand sides.
 struct CgState {
@@ -82,7 +82,7 @@ struct CgState {
     const size_t nd8 = (size_t)nrhs * sizeof(double);
     const size_t ni4 = (size_t)nrhs * sizeof(int);
     const size_t part = (size_t)nrhs * kMaxBlocks * sizeof(double);
-    const size_t total = 5 * nd8 + 3 * ni4 + 256 + 2 * part + 2 * ni4 + 64 * 16;
+    const size_t total = 4 * nd8 + 3 * ni4 + sizeof(int) + 2 * part + 10 * 256;
     char* b = (char*)mem.get(total);
     auto take = [&](size_t n) {
       char* r = b;
@@ -90,19 +90,16 @@ struct CgState {
       return r;
     };
     char* base = b;
-    s.rr = (double*)take(nd8);
-    s.alpha = (double*)take(nd8);
-    s.beta = (double*)take(nd8);
+    s.rr_cur = (double*)take(nd8);
+    s.rr_prev = (double*)take(nd8);
     s.thresh2 = (double*)take(nd8);
-    s.rr0 = (double*)take(nd8);
+    s.alpha = (double*)take(nd8);
     s.active = (int*)take(ni4);
     s.iters = (int*)take(ni4);
     s.status = (int*)take(ni4);
     s.n_active = (int*)take(sizeof(int));
     s.part_a = (double*)take(part);
     s.part_b = (double*)take(part);
-    s.cnt_a = (unsigned*)take(ni4);
-    s.cnt_b = (unsigned*)take(ni4);
     s.max_blocks = kMaxBlocks;
     fl::fill_zero_bytes(base, (size_t)(b - base), st);
     cap = nrhs;
@@ -125,8 +122,8 @@ struct fl_op_s {
   int max_outer = 40;
   DBuf ws;                // FFT intermediates
   DBuf vecs;              // solver vectors
-  CgState cg, cg_out;     // inner CG state; outer (refinement) bookkeeping
-  DBuf outer_flags;
+  CgState cg, cg_out;     // CG state; partial sums of residual norms
+  DBuf outer_flags;       // per-RHS flags and norms of the refinement loop
   hipEvent_t done = nullptr;
   hipStream_t last_stream = nullptr;
   bool used = false;
@@ -145,19 +142,37 @@ struct fl_op_s {
 
 namespace fl {
 
+static size_t line_bytes(int M, int E, bool fp32) {
+  return (size_t)2 * (M + M / E) * (fp32 ? 4 : 8);
+}
+
+bool schedule_ok(const Geometry& g, const Schedule& s, bool fp32) {
+  auto ok = [&](int E, int W) {
+    if (!(E == 8 || E == 16 || E == 32) || E > g.M) return false;
+    if (W < 1) return false;
+    if ((long)W * (g.M / E) > 512) return false;
+    if (line_bytes(g.M, E, fp32) * W > kMaxLds) return false;
+    return true;
+  };
+  return ok(s.E_first, s.W_first) && ok(s.E_mid, s.LPB_mid) && ok(s.E_c2c, s.W_c2c);
+}
+
+// Starting schedule before tuning: radix-16 register stages (radix 32 in the
+// strided FP32 passes for lines of 512 and more), blocks of up to 256 threads, up to 96 KiB of
+// LDS, and as many lines per block as that allows (wider column tiles in the
+// strided passes).
 Schedule default_schedule(const Geometry& g, bool fp32) {
   const int M = g.M;
   auto pickE = [&](int want) { return std::min(want, M); };
   Schedule s{};
-  s.E_first = pickE(M >= 256 ? 16 : 8);
-  s.E_mid = pickE(M >= 256 ? 16 : 8);
-  s.E_c2c = pickE(M >= 256 ? 16 : 8);
-  const size_t tsz = fp32 ? 4 : 8;
+  const int e = fp32 && M >= 512 ? 32 : (M >= 256 ? 16 : 8);
+  s.E_first = pickE(e);
+  s.E_mid = pickE(std::min(e, 16));
+  s.E_c2c = pickE(e);
   auto fitW = [&](int E, int want) {
     const int tpl = M / E;
-    const size_t lb = (size_t)2 * (M + M / E) * tsz;
     int w = std::max(1, std::min(want, 256 / std::max(1, tpl)));
-    while (w > 1 && lb * w > 65536) w /= 2;
+    while (w > 1 && line_bytes(M, E, fp32) * w > 96 * 1024) w /= 2;
     return w;
   };
   s.W_first = fitW(s.E_first, 16);
@@ -173,17 +188,7 @@ namespace {
 void set_device(fl_op A) { FL_HIP(hipSetDevice(A->device)); }
 
 void check_schedule(const fl::Geometry& g, const fl::Schedule& s, bool fp32) {
-  const size_t tsz = fp32 ? 4 : 8;
-  auto ok = [&](int E, int W) {
-    if (!(E == 8 || E == 16) || E > g.M) return false;
-    if (W < 1) return false;
-    const int tpl = g.M / E;
-    if ((long)W * tpl > 512) return false;
-    if ((size_t)2 * (g.M + g.M / E) * tsz * W > 65536) return false;
-    return true;
-  };
-  if (!ok(s.E_first, s.W_first) || !ok(s.E_mid, s.LPB_mid) || !ok(s.E_c2c, s.W_c2c))
-    throw Error(FL_E_INVAL, "schedule out of range");
+  if (!fl::schedule_ok(g, s, fp32)) throw Error(FL_E_INVAL, "schedule out of range");
 }
 
 }  // namespace
@@ -433,27 +438,62 @@ fl_status fl_profile_apply(fl_op A, const void* u, void* y, int nrhs, int fp32, 
 
 namespace {
 
-// Run CG iterations until no right-hand side is active (checked every
-// `chunk` iterations with one 4-byte read) or the cap is reached.
+// Per-call view of the CG state: block counts, iteration cap, tolerance.
+fl::CgScalars cg_view(const fl::CgScalars& base, const fl::Geometry& g, const fl::Schedule& sc,
+                      int nrhs, int maxiter, double tol) {
+  fl::CgScalars c = base;
+  c.nb_a = fl::last_pass_blocks(g, sc);
+  c.nb_b = fl::vec_blocks(g.nd, nrhs);
+  if (c.nb_a > c.max_blocks || c.nb_b > c.max_blocks)
+    throw Error(FL_E_UNSUPPORTED, "too many blocks for the reduction buffers");
+  c.maxiter = maxiter;
+  c.tol2 = tol * tol;
+  return c;
+}
+
+// CG from x0 = 0 on A x = rhs until no right-hand side is active.  The
+// number of active right-hand sides is read back every `chunk` iterations
+// (one 4-byte copy); masked launches past convergence cost only launch time.
 template <typename T>
-void cg_loop(fl_op A, const fl::Schedule& sc, const T* lam, const void* tw, T* x, T* r, T* p,
-             T* q, int nrhs, int maxiter, const fl::CgScalars& cg, void* ws, hipStream_t st) {
+void cg_run(fl_op A, const fl::Schedule& sc, const T* lam, const void* tw, const T* rhs, T* x,
+            T* r, T* p, T* q, int nrhs, const fl::CgScalars& cg, const int* outer_active,
+            void* ws, hipStream_t st) {
+  fl::fill_int(cg.n_active, 0, 1, st);
+  fl::cg_init<T>(A->g, rhs, x, r, p, nrhs, cg, outer_active, st);
   int done = 0;
-  int chunk = 4;
-  while (done < maxiter) {
-    const int k = std::min(chunk, maxiter - done);
+  int chunk = 8;
+  const int cap = cg.maxiter + 2;
+  while (done < cap) {
+    const int k = std::min(chunk, cap - done);
     for (int i = 0; i < k; ++i) {
       fl::apply_passes<T>(A->g, sc, lam, tw, nullptr, q, nrhs, ws, st, fl::PM_CG, r, p, nullptr,
                           &cg, cg.active);
-      fl::cg_update<T>(A->g, x, r, p, q, nrhs, maxiter, cg, st);
+      fl::cg_update<T>(A->g, x, r, p, q, nrhs, cg, st);
     }
     done += k;
     int nact = 0;
     FL_HIP(hipMemcpyAsync(&nact, cg.n_active, sizeof(int), hipMemcpyDeviceToHost, st));
     FL_HIP(hipStreamSynchronize(st));
     if (nact == 0) break;
-    chunk = std::min(chunk * 2, 64);
+    chunk = std::min(chunk * 2, 32);
   }
+}
+
+// ||f - A u||^2 per RHS (FP64 product) into out; r receives the residual.
+void fp64_residual(fl_op A, const double* f, const double* u, double* r, int nrhs,
+                   const fl::CgScalars& co, const int* active, double* out, void* ws,
+                   hipStream_t st) {
+  fl::apply_passes<double>(A->g, A->sc64, A->lam64, A->tw64, u, r, nrhs, ws, st, fl::PM_RESID,
+                           nullptr, nullptr, f, &co, active);
+  fl::reduce_parts(co.part_a, fl::last_pass_blocks(A->g, A->sc64), co.max_blocks, nrhs, out,
+                   active, st);
+}
+
+void sum_squares(fl_op A, const double* v, int nrhs, const fl::CgScalars& co, double* out,
+                 hipStream_t st) {
+  fl::sum_squares_parts(v, A->g.nd, nrhs, co.part_b, co.max_blocks, st);
+  fl::reduce_parts(co.part_b, fl::vec_blocks(A->g.nd, nrhs), co.max_blocks, nrhs, out, nullptr,
+                   st);
 }
 
 }  // namespace
@@ -474,58 +514,56 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
     const long nd = A->g.nd;
     const size_t v8 = (size_t)nrhs * nd * sizeof(double);
     const size_t v4 = (size_t)nrhs * nd * sizeof(float);
+    const size_t a8 = ((v8 + 255) / 256) * 256, a4 = ((v4 + 255) / 256) * 256;
     std::vector<int> iters(nrhs, 0), outer(nrhs, 0), status(nrhs, 0);
     std::vector<double> rec(nrhs, 0.0), tru(nrhs, 0.0);
     A->cg.ensure(nrhs, st);
     A->cg_out.ensure(nrhs, st);
-    const fl::CgScalars& cg = A->cg.s;
     const fl::CgScalars& co = A->cg_out.s;
+    // per-RHS host-visible norms and flags: f2, rr (outer), scale, flags
+    char* fb = (char*)A->outer_flags.get(3 * (size_t)nrhs * sizeof(double) + nrhs * sizeof(int) + 1024);
+    double* f2 = (double*)fb;
+    double* rro = f2 + nrhs;
+    double* scale = rro + nrhs;
+    int* oact = (int*)(scale + nrhs);
+    void* ws = A->ws.get(fl::apply_workspace_bytes(A->g, nrhs, false));
+    std::vector<double> hf2(nrhs), hrr(nrhs);
+    sum_squares(A, f, nrhs, co, f2, st);
     if (!mixed) {
-      void* ws = A->ws.get(fl::apply_workspace_bytes(A->g, nrhs, false));
-      char* vb = (char*)A->vecs.get(3 * v8 + 3 * 256);
+      const fl::CgScalars cg = cg_view(A->cg.s, A->g, A->sc64, nrhs, maxiter, tol);
+      char* vb = (char*)A->vecs.get(3 * a8);
       double* r = (double*)vb;
-      double* p = (double*)(vb + ((v8 + 255) / 256) * 256);
-      double* q = (double*)(vb + 2 * ((v8 + 255) / 256) * 256);
-      fl::fill_int(cg.n_active, 0, 1, st);
-      fl::cg_init<double>(A->g, f, u, r, p, nrhs, tol, cg, nullptr, st);
-      cg_loop<double>(A, A->sc64, A->lam64, A->tw64, u, r, p, q, nrhs, maxiter, cg, ws, st);
-      std::vector<double> rr(nrhs), rr0(nrhs);
+      double* p = (double*)(vb + a8);
+      double* q = (double*)(vb + 2 * a8);
+      cg_run<double>(A, A->sc64, A->lam64, A->tw64, f, u, r, p, q, nrhs, cg, nullptr, ws, st);
+      std::vector<double> rr(nrhs);
       FL_HIP(hipMemcpyAsync(iters.data(), cg.iters, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
       FL_HIP(hipMemcpyAsync(status.data(), cg.status, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
-      FL_HIP(hipMemcpyAsync(rr.data(), cg.rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
-      FL_HIP(hipMemcpyAsync(rr0.data(), cg.rr0, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+      FL_HIP(hipMemcpyAsync(rr.data(), cg.rr_cur, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
       // true residual with an FP64 product (into q)
-      fl::apply_passes<double>(A->g, A->sc64, A->lam64, A->tw64, u, q, nrhs, ws, st, fl::PM_RESID,
-                               nullptr, nullptr, f, &co, nullptr);
-      std::vector<double> rt(nrhs);
-      FL_HIP(hipMemcpyAsync(rt.data(), co.rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+      fp64_residual(A, f, u, q, nrhs, co, nullptr, rro, ws, st);
+      FL_HIP(hipMemcpyAsync(hrr.data(), rro, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+      FL_HIP(hipMemcpyAsync(hf2.data(), f2, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
       FL_HIP(hipStreamSynchronize(st));
       for (int o = 0; o < nrhs; ++o) {
-        const double fn = std::sqrt(rr0[o]);
+        const double fn = std::sqrt(hf2[o]);
         rec[o] = fn > 0 ? std::sqrt(rr[o]) / fn : 0.0;
-        tru[o] = fn > 0 ? std::sqrt(rt[o]) / fn : 0.0;
+        tru[o] = fn > 0 ? std::sqrt(hrr[o]) / fn : 0.0;
         if (status[o] == 0 && !(rec[o] <= tol) && fn > 0) status[o] = FL_E_NOCONV;
       }
     } else {
-      // FP64 residual / iterate, FP32 inner CG on A delta = r / ||r||
-      void* ws = A->ws.get(fl::apply_workspace_bytes(A->g, nrhs, false));
-      const size_t a8 = ((v8 + 255) / 256) * 256, a4 = ((v4 + 255) / 256) * 256;
-      char* vb = (char*)A->vecs.get(a8 + 5 * a4 + 4 * 256);
+      // FP64 residual and iterate; FP32 CG on A delta = r / ||r|| (inner_tol)
+      const fl::CgScalars cg = cg_view(A->cg.s, A->g, A->sc32, nrhs, maxiter, A->inner_tol);
+      char* vb = (char*)A->vecs.get(a8 + 5 * a4);
       double* r64 = (double*)vb;
       float* rhs32 = (float*)(vb + a8);
       float* d32 = (float*)(vb + a8 + a4);
       float* r32 = (float*)(vb + a8 + 2 * a4);
       float* p32 = (float*)(vb + a8 + 3 * a4);
       float* q32 = (float*)(vb + a8 + 4 * a4);
-      int* oact = (int*)A->outer_flags.get((size_t)nrhs * sizeof(int) + 2 * nrhs * sizeof(double));
-      double* f2 = (double*)(oact + ((nrhs + 1) / 2) * 2);
-      double* scale = f2 + nrhs;
-      // u = 0, r = f, ||f||^2
       fl::fill_zero_bytes(u, v8, st);
       FL_HIP(hipMemcpyAsync(r64, f, v8, hipMemcpyDeviceToDevice, st));
-      fl::sum_squares(f, nd, nrhs, f2, co.part_a, co.cnt_a, co.max_blocks, st);
-      FL_HIP(hipMemcpyAsync(co.rr, f2, nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
-      std::vector<double> hf2(nrhs), hrr(nrhs);
+      FL_HIP(hipMemcpyAsync(rro, f2, nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
       std::vector<int> hact(nrhs), hit(nrhs), hst(nrhs);
       FL_HIP(hipMemcpyAsync(hf2.data(), f2, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
       FL_HIP(hipStreamSynchronize(st));
@@ -546,18 +584,14 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
           break;
         }
         FL_HIP(hipMemcpyAsync(oact, hact.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
-        fl::refine_scale(r64, rhs32, co.rr, scale, nd, nrhs, oact, st);
-        fl::fill_int(cg.n_active, 0, 1, st);
-        fl::cg_init<float>(A->g, rhs32, d32, r32, p32, nrhs, A->inner_tol, cg, oact, st);
-        cg_loop<float>(A, A->sc32, A->lam32, A->tw32, d32, r32, p32, q32, nrhs, maxiter, cg, ws,
-                       st);
+        fl::refine_scale(r64, rhs32, rro, scale, nd, nrhs, oact, st);
+        cg_run<float>(A, A->sc32, A->lam32, A->tw32, rhs32, d32, r32, p32, q32, nrhs, cg, oact,
+                      ws, st);
         fl::refine_axpy(u, d32, scale, nd, nrhs, oact, st);
-        // r = f - A u in FP64 and ||r||^2 into co.rr
-        fl::apply_passes<double>(A->g, A->sc64, A->lam64, A->tw64, u, r64, nrhs, ws, st,
-                                 fl::PM_RESID, nullptr, nullptr, f, &co, oact);
+        fp64_residual(A, f, u, r64, nrhs, co, oact, rro, ws, st);
         FL_HIP(hipMemcpyAsync(hit.data(), cg.iters, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
         FL_HIP(hipMemcpyAsync(hst.data(), cg.status, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
-        FL_HIP(hipMemcpyAsync(hrr.data(), co.rr, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+        FL_HIP(hipMemcpyAsync(hrr.data(), rro, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
         FL_HIP(hipStreamSynchronize(st));
         for (int o = 0; o < nrhs; ++o)
           if (hact[o]) {

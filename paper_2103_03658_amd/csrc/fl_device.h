@@ -1,5 +1,5 @@
 // Device-side building blocks shared by the library's kernels: complex
-// arithmetic, small in-register DFTs (radix 2/4/8/16) and the register+LDS
+// arithmetic, small in-register DFTs (radix 2 to 32) and the register+LDS
 // Stockham engine that transforms one line of length M held by M/E threads
 // (E elements per thread).  gfx950 (CDNA4, wave64) only.
 #pragma once
@@ -143,6 +143,53 @@ __device__ __forceinline__ void dft16(cx<T>* v) {
   }
 }
 
+// cos(pi k/16), sin(pi k/16), k = 0..15: w32^k = (c, DIR s)
+__device__ __forceinline__ constexpr double c32(int k) {
+  constexpr double t[16] = {1.0,
+                            0.98078528040323044912618223613424,
+                            0.92387953251128675612818318939679,
+                            0.83146961230254523707878837761791,
+                            0.70710678118654752440084436210485,
+                            0.55557023301960222474283081394853,
+                            0.38268343236508977172845998403040,
+                            0.19509032201612826784828486847702,
+                            0.0,
+                            -0.19509032201612826784828486847702,
+                            -0.38268343236508977172845998403040,
+                            -0.55557023301960222474283081394853,
+                            -0.70710678118654752440084436210485,
+                            -0.83146961230254523707878837761791,
+                            -0.92387953251128675612818318939679,
+                            -0.98078528040323044912618223613424};
+  return t[k];
+}
+__device__ __forceinline__ constexpr double s32(int k) { return k <= 8 ? c32(8 - k) : c32(k - 8); }
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft32(cx<T>* v) {
+  cx<T> e[16], o[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    e[k] = v[2 * k];
+    o[k] = v[2 * k + 1];
+  }
+  dft16<DIR>(e);
+  dft16<DIR>(o);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    cx<T> t = o[k];
+    if (k == 8) {
+      t = mul_i<DIR>(t);
+    } else if (k != 0) {
+      const T c = (T)c32(k);
+      const T sn = (T)(DIR < 0 ? -s32(k) : s32(k));
+      t = cmul(t, cx<T>{c, sn});
+    }
+    v[k] = cadd(e[k], t);
+    v[k + 16] = csub(e[k], t);
+  }
+}
+
 template <int R, int DIR, typename T>
 __device__ __forceinline__ void dft(cx<T>* v) {
   if constexpr (R == 1) {
@@ -150,6 +197,7 @@ __device__ __forceinline__ void dft(cx<T>* v) {
   else if constexpr (R == 4) dft4<DIR>(v);
   else if constexpr (R == 8) dft8<DIR>(v);
   else if constexpr (R == 16) dft16<DIR>(v);
+  else if constexpr (R == 32) dft32<DIR>(v);
   else static_assert(R == 2, "unsupported radix");
 }
 

@@ -23,34 +23,43 @@ struct Error : std::runtime_error {
   } while (0)
 
 // ---------------------------------------------------------------------------
-// per-RHS CG bookkeeping (device pointers, all arrays of length nrhs unless
-// noted).  Shared by the pass epilogues and the update kernels.
+// Per-RHS CG state on the device (arrays of length nrhs unless noted).
+//
+// Reductions never use atomics or device-scope fences: each block of a kernel
+// writes its partial sum to part_a / part_b, and every block of the kernel
+// that consumes the sum re-adds the partials itself in a fixed order.  Each
+// scalar is written by block 0 of one kernel and read only by later kernels:
+//   first pass  reads part_b (r.r), rr_prev, iters, thresh2; writes rr_cur,
+//               thresh2 (first iteration), and on exit active/status/n_active
+//   last pass   writes part_a (p.q)
+//   update      reads part_a, rr_cur; writes part_b, rr_prev <- rr_cur,
+//               iters += 1, alpha
+// so no kernel reads a value that a concurrently running block may change.
 // ---------------------------------------------------------------------------
 struct CgScalars {
-  double* rr;        // current ||r||^2
-  double* alpha;     // rr / (p.Ap)
-  double* beta;      // rr_new / rr_old (0 on the first iteration)
-  double* thresh2;   // stop when rr <= thresh2
-  double* rr0;       // ||rhs||^2 at start
+  double* rr_cur;    // ||r_k||^2 of the current iteration
+  double* rr_prev;   // ||r_{k-1}||^2
+  double* thresh2;   // stop when ||r||^2 <= thresh2 (= tol^2 ||r_0||^2)
+  double* alpha;     // last step length (diagnostics)
   int* active;       // 1 while iterating
-  int* iters;        // iterations done
-  int* status;       // 0 running/converged, 5 no convergence, 6 breakdown
-  int* n_active;     // single int: number of active RHS
-  double* part_a;    // partial sums, nrhs * max_blocks
-  double* part_b;
-  unsigned* cnt_a;   // last-block counters, nrhs
-  unsigned* cnt_b;
+  int* iters;        // completed updates
+  int* status;       // 0 converged/running, 5 no convergence, 6 breakdown
+  int* n_active;     // single int: number of active RHS (host polls it)
+  double* part_a;    // p.q partials, nrhs * max_blocks
+  double* part_b;    // r.r partials, nrhs * max_blocks
+  int nb_a;          // valid partials per RHS in part_a (last-pass blocks)
+  int nb_b;          // valid partials per RHS in part_b (update / init blocks)
   int max_blocks;
+  int maxiter;
+  double tol2;
 };
 
 // Epilogue/prologue selection of the first and last FFT passes.
 enum PassMode {
   PM_PLAIN = 0,     // y = A u
-  PM_CG = 1,        // first pass: p = r + beta p ; last pass: q = A p, alpha = rr / p.q
-  PM_RESID = 2,     // last pass: y = f - A u and ||y||^2 per RHS (FP64 only)
+  PM_CG = 1,        // first pass: beta, convergence, p = r + beta p; last pass: q = A p, p.q partials
+  PM_RESID = 2,     // last pass: y = f - A u and partials of ||y||^2 (FP64 only)
 };
-
-struct ApplyPlan;  // defined in the passes unit
 
 // Geometry of one operator application.
 struct Geometry {
@@ -66,18 +75,26 @@ struct Schedule {
   int E_first;   // elements per thread, strided passes along axis 0
   int E_mid;     // elements per thread, contiguous middle pass
   int E_c2c;     // elements per thread, 3D axis-1 passes
-  int W_first;   // lines per block in strided passes
-  int W_c2c;
+  int W_first;   // lines per block in the axis-0 passes
+  int W_c2c;     // lines per block in the 3D axis-1 passes
   int LPB_mid;   // lines per block in the middle pass
 };
 
+constexpr size_t kMaxLds = 160 * 1024;   // LDS per workgroup on gfx950
+
 Schedule default_schedule(const Geometry& g, bool fp32);
+bool schedule_ok(const Geometry& g, const Schedule& s, bool fp32);
 
 // Workspace bytes for nrhs right-hand sides (FFT intermediates).
 size_t apply_workspace_bytes(const Geometry& g, int nrhs, bool fp32);
 
-// y = A u (mode PM_PLAIN), CG fused step (PM_CG: uses r, p in place of u,
-// writes q into y), or FP64 residual (PM_RESID: y = f - A u).
+// Number of blocks per RHS of the last pass (= partials it writes).
+int last_pass_blocks(const Geometry& g, const Schedule& sc);
+// Blocks per RHS of the vector kernels (update, init, sums).
+int vec_blocks(long nd, int nrhs);
+
+// y = A u (mode PM_PLAIN), CG step (PM_CG: p <- r + beta p from rvec/pvec,
+// q = A p into y), or FP64 residual (PM_RESID: y = f - A u).
 template <typename T>
 void apply_passes(const Geometry& g, const Schedule& sc, const T* lam, const void* tw,
                   const T* u, T* y, int nrhs, void* ws, hipStream_t st, int mode,
@@ -100,21 +117,25 @@ void build_symbol(const Geometry& g, const double* G, double* lam64, float* lam3
                   hipStream_t st);
 void embed_generator(const Geometry& g, const double* G, double* out, hipStream_t st);
 
-// CG kernels (cg unit).
+// CG kernels (cg unit).  cg.nb_b must equal vec_blocks(g.nd, nrhs).
 template <typename T>
-void cg_init(const Geometry& g, const T* rhs, T* x, T* r, T* p, int nrhs, double tol,
-             const CgScalars& cg, const int* outer_active, hipStream_t st);
+void cg_init(const Geometry& g, const T* rhs, T* x, T* r, T* p, int nrhs, const CgScalars& cg,
+             const int* outer_active, hipStream_t st);
 template <typename T>
-void cg_update(const Geometry& g, T* x, T* r, const T* p, const T* q, int nrhs, int maxiter,
+void cg_update(const Geometry& g, T* x, T* r, const T* p, const T* q, int nrhs,
                const CgScalars& cg, hipStream_t st);
 void fill_int(int* p, int v, int n, hipStream_t st);
 void fill_zero_bytes(void* p, size_t bytes, hipStream_t st);
+// out[o] = sum_{b < nb} part[o * max_blocks + b] (fixed order)
+void reduce_parts(const double* part, int nb, int max_blocks, int nrhs, double* out,
+                  const int* active, hipStream_t st);
 // refinement helpers
 void refine_scale(const double* r64, float* r32, const double* rr, double* scale, long nd,
                   int nrhs, const int* active, hipStream_t st);
 void refine_axpy(double* u, const float* d32, const double* scale, long nd, int nrhs,
                  const int* active, hipStream_t st);
-void sum_squares(const double* v, long nd, int nrhs, double* out, double* part, unsigned* cnt,
-                 int max_blocks, hipStream_t st);
+// partials of sum v^2 per RHS into part (vec_blocks per RHS)
+void sum_squares_parts(const double* v, long nd, int nrhs, double* part, int max_blocks,
+                       hipStream_t st);
 
 }  // namespace fl

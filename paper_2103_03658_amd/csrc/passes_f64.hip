@@ -20,6 +20,12 @@ size_t apply_workspace_bytes(const Geometry& g, int nrhs, bool fp32) {
   return fp32 ? ws_bytes_t<float>(g, nrhs) : ws_bytes_t<double>(g, nrhs);
 }
 
+int last_pass_blocks(const Geometry& g, const Schedule& sc) {
+  if (g.d == 1) return 1;
+  const long C0 = g.d == 2 ? (long)g.n : (long)g.n * g.n;
+  return (int)pair_tiles(C0, sc.W_first);
+}
+
 const void* twiddles(int M, bool fp32, hipStream_t st) {
   static std::mutex mu;
   static std::map<std::tuple<int, int, bool>, void*> cache;
@@ -118,12 +124,12 @@ void build_symbol(const Geometry& g, const double* G, double* lam64, float* lam3
   long Md1 = total / M;  // lines per axis
   if (d >= 2) {
     // axis 0: columns = M^(d-1), row stride M^(d-1)
-    C2CArgs<double> a0{c, c, nullptr, Md1, 0, Md1, 0, Md1, 1, M, M, W, tw};
+    C2CArgs<double> a0{c, c, nullptr, Md1, 0, Md1, 0, Md1, 0, 1, M, M, W, tw};
     launch_c2c<double>(M, E, -1, a0, 1, st);
   }
   if (d == 3) {
     // axis 1: slices k0 (stride M*M), rows stride M, columns M
-    C2CArgs<double> a1{c, c, nullptr, M, (long)M * M, M, (long)M * M, M, 1, M, M, W, tw};
+    C2CArgs<double> a1{c, c, nullptr, M, (long)M * M, M, (long)M * M, M, 0, 1, M, M, W, tw};
     launch_c2c<double>(M, E, -1, a1, M, st);
   }
   int LPB = 256 / TPL;

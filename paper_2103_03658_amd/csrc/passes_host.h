@@ -1,5 +1,5 @@
 // Host side of the operator application: pass sequence per dimension.
-// Included by one translation unit per precision (FL_REAL = float/double).
+// Included by one translation unit per precision.
 #pragma once
 
 #include "passes_impl.h"
@@ -32,8 +32,10 @@ void apply_passes_t(const Geometry& g, const Schedule& sc, const T* lam, const v
   const long h = M / 2 + 1;
   CgScalars nocg{};
   const CgScalars& c = cg ? *cg : nocg;
+  if ((mode == PM_CG || mode == PM_RESID) && !cg) throw Error(1, "missing reduction buffers");
   if (g.d == 1) {
-    Line1Args<T> a{u, y, pvec, rvec, fvec, c.beta, active, c, lam, n, nrhs, mode, tw};
+    Line1Args<T> a{u, y, pvec, rvec, fvec, active, c, c.part_a, c.max_blocks, lam, n, nrhs,
+                   mode, tw};
     mark();
     launch_line1d<T>(M, sc.E_mid, a, st);
     mark();
@@ -42,9 +44,9 @@ void apply_passes_t(const Geometry& g, const Schedule& sc, const T* lam, const v
   cx<T>* T1 = reinterpret_cast<cx<T>*>(ws);
   const long C0 = g.d == 2 ? (long)n : (long)n * n;   // columns of the axis-0 passes
   const long nd = g.nd;
-  // axis 0, forward (real pairs -> Hermitian half)
+  // axis 0, forward (real pairs -> Hermitian half); CG: iteration start
   {
-    FirstArgs<T> a{u, pvec, rvec, c.beta, active, T1, C0, nd, h * C0, n,
+    FirstArgs<T> a{u, pvec, rvec, active, c, T1, C0, nd, h * C0, 0, n,
                    sc.W_first, mode == PM_CG ? PM_CG : PM_PLAIN, tw};
     mark();
     launch_first<T>(M, sc.E_first, a, nrhs, st);
@@ -56,20 +58,21 @@ void apply_passes_t(const Geometry& g, const Schedule& sc, const T* lam, const v
   } else {
     cx<T>* T2 = T1 + (long)nrhs * h * n * n;
     // axis 1 forward: slices (rhs, k0), rows i1 < n -> k1 < M, columns i2
-    C2CArgs<T> f1{T1, T2, active, n, (long)n * n, n, (long)M * n, n, (int)h, n, M,
+    C2CArgs<T> f1{T1, T2, active, n, (long)n * n, n, (long)M * n, n, 0, (int)h, n, M,
                   sc.W_c2c, tw};
     mark();
     launch_c2c<T>(M, sc.E_c2c, -1, f1, (long)nrhs * h, st);
     MidArgs<T> m{T2, lam, active, h * M, h * M * n, n, n, n, N1, 3, sc.LPB_mid, tw};
     mark();
     launch_mid<T>(M, sc.E_mid, m, nrhs, st);
-    C2CArgs<T> i1{T2, T1, active, n, (long)M * n, n, (long)n * n, n, (int)h, M, n,
+    C2CArgs<T> i1{T2, T1, active, n, (long)M * n, n, (long)n * n, n, 0, (int)h, M, n,
                   sc.W_c2c, tw};
     mark();
     launch_c2c<T>(M, sc.E_c2c, +1, i1, (long)nrhs * h, st);
   }
   {
-    LastArgs<T> a{T1, y, pvec, fvec, active, c, C0, h * C0, nd, n, sc.W_first, mode, tw};
+    LastArgs<T> a{T1, y, pvec, fvec, active, c.part_a, c.max_blocks, C0, h * C0, nd, 0, n,
+                  sc.W_first, mode, tw};
     mark();
     launch_last<T>(M, sc.E_first, a, nrhs, st);
     mark();

@@ -11,6 +11,11 @@
 // the result by Hermitian symmetry, so only rows 0..M/2 of the axis-0
 // frequency exist (the product of a real input with the real, even symbol
 // keeps that symmetry, which the last pass uses to rebuild the other half).
+//
+// The strided (axis-0 and axis-1) passes run on a one-dimensional grid whose
+// block order is permuted so that each of the eight XCDs of the chip works
+// on a contiguous range of column tiles: neighbouring tiles share cache
+// lines, and this keeps them in one XCD's L2.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -21,7 +26,7 @@
 namespace fl {
 
 // ---------------------------------------------------------------------------
-// reductions
+// reductions (fixed order: results do not depend on timing)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -29,7 +34,7 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-// Deterministic block sum (fixed tree for a fixed blockDim); result in thread 0.
+// Block sum; result valid in thread 0.
 __device__ __forceinline__ double block_sum(double v, double* sh) {
   const int tid = threadIdx.x;
   v = wave_sum(v);
@@ -45,29 +50,66 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return s;
 }
 
-// Publish this block's partial; if it is the last of nb blocks, return true
-// in every thread of the block and the total (fixed order) in *total (thread 0).
-__device__ __forceinline__ bool last_block_total(double blk, double* part, unsigned* cnt, int nb,
-                                                 int bidx, double* sh, double* total) {
-  __shared__ int s_last;
-  if (threadIdx.x == 0) {
-    part[bidx] = blk;
-    __threadfence();
-    unsigned prev = atomicAdd(cnt, 1u);
-    s_last = (prev == (unsigned)(nb - 1));
-    if (s_last) __threadfence();
+// Sum of nb per-block partials written by an earlier kernel, in a fixed
+// order, returned to every thread of the block.
+__device__ __forceinline__ double sum_partials(const double* part, int nb, double* sh) {
+  if (threadIdx.x < 64) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < nb; i += 64) v += part[i];
+    v = wave_sum(v);
+    if (threadIdx.x == 0) sh[0] = v;
   }
   __syncthreads();
-  if (!s_last) return false;
-  double v = 0.0;
-  for (int i = threadIdx.x; i < nb; i += blockDim.x)
-    v += __hip_atomic_load(&part[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  v = block_sum(v, sh);
-  if (threadIdx.x == 0) {
-    *total = v;
-    atomicExch(cnt, 0u);
+  const double t = sh[0];
+  __syncthreads();
+  return t;
+}
+
+// Start of a CG iteration for RHS o (every block of the first pass runs it
+// and reaches the same decision).  Returns true if the RHS stops here;
+// `lead` is true for exactly one block of the RHS, which records the state.
+__device__ __forceinline__ bool cg_begin(const CgScalars& cg, int o, bool lead, double* sh,
+                                         double* beta) {
+  const double rr = sum_partials(cg.part_b + (long)o * cg.max_blocks, cg.nb_b, sh);
+  const int it = cg.iters[o];
+  bool stop = false;
+  int status = 0;
+  double b = 0.0;
+  if (!isfinite(rr)) {
+    stop = true;
+    status = 6;
+  } else if (it == 0) {
+    stop = rr == 0.0;
+  } else {
+    if (rr <= cg.thresh2[o]) {
+      stop = true;
+    } else if (it >= cg.maxiter) {
+      stop = true;
+      status = 5;
+    }
+    b = rr / cg.rr_prev[o];
   }
-  return true;
+  if (lead && threadIdx.x == 0) {
+    cg.rr_cur[o] = rr;
+    if (it == 0) cg.thresh2[o] = cg.tol2 * rr;
+    if (stop) {
+      cg.active[o] = 0;
+      cg.status[o] = status;
+      atomicSub(cg.n_active, 1);
+    }
+  }
+  *beta = b;
+  return stop;
+}
+
+// Logical (tile, outer) of this block: hardware places block b on XCD b % 8;
+// XCD x is given the contiguous logical range starting at x*q + min(x, r).
+__device__ __forceinline__ void xcd_tile(long ntiles, long& tile, long& outer) {
+  const long nb = gridDim.x, b = blockIdx.x;
+  const long x = b & 7, k = b >> 3, q = nb >> 3, r = nb & 7;
+  const long l = x * q + (x < r ? x : r) + k;
+  tile = l % ntiles;
+  outer = l / ntiles;
 }
 
 // ---------------------------------------------------------------------------
@@ -78,12 +120,13 @@ struct FirstArgs {
   const T* u;            // PM_PLAIN input
   T* p;                  // PM_CG: p <- r + beta p (in place)
   const T* r;
-  const double* beta;    // per RHS
   const int* active;     // per RHS, may be null
+  CgScalars cg;
   cx<T>* out;
   long C;                // real columns per RHS (n^(d-1))
   long in_os;            // elements between RHS in u/p/r
   long out_os;           // complex elements between RHS in out
+  long ntiles;           // column-pair tiles per RHS
   int n_in;              // rows of input (n)
   int W;                 // complex lines per block
   int mode;
@@ -95,16 +138,24 @@ __global__ void __launch_bounds__(512) k_first(FirstArgs<T> a) {
   using P = Plan<M, E>;
   constexpr int TPL = P::TPL;
   extern __shared__ unsigned char smem_raw[];
+  __shared__ double sh[16];
   T* lds = reinterpret_cast<T*>(smem_raw);
-  const int o = blockIdx.y;
+  long tile, ol;
+  xcd_tile(a.ntiles, tile, ol);
+  const int o = (int)ol;
   if (a.active && !a.active[o]) return;
+  T bt = 0;
+  if (a.mode == PM_CG) {
+    double beta;
+    if (cg_begin(a.cg, o, tile == 0, sh, &beta)) return;
+    bt = (T)beta;
+  }
   const int W = a.W;
   const int c = threadIdx.x % W, t = threadIdx.x / W;
   T* lre = lds + (long)c * 2 * P::LDSN;
   T* lim = lre + P::LDSN;
-  const long col = ((long)blockIdx.x * W + c) * 2;
+  const long col = (tile * W + c) * 2;
   const bool h0 = col < a.C, h1 = col + 1 < a.C;
-  const T bt = a.mode == PM_CG ? (T)a.beta[o] : (T)0;
   cx<T> v[E];
 #pragma unroll
   for (int j = 0; j < E; ++j) {
@@ -159,10 +210,12 @@ struct LastArgs {
   const T* p;            // PM_CG: dot partner
   const double* f;       // PM_RESID: right-hand side (FP64)
   const int* active;
-  CgScalars cg;
+  double* part;          // PM_CG / PM_RESID: per-block partials [nrhs][max_blocks]
+  int max_blocks;
   long C;                // real columns per RHS
   long in_os;            // complex elements between RHS of in
   long y_os;             // elements between RHS of y / p / f
+  long ntiles;
   int n_out;
   int W;
   int mode;
@@ -176,13 +229,15 @@ __global__ void __launch_bounds__(512) k_last(LastArgs<T> a) {
   extern __shared__ unsigned char smem_raw[];
   __shared__ double red[16];
   T* lds = reinterpret_cast<T*>(smem_raw);
-  const int o = blockIdx.y;
+  long tile, ol;
+  xcd_tile(a.ntiles, tile, ol);
+  const int o = (int)ol;
   if (a.active && !a.active[o]) return;
   const int W = a.W;
   const int c = threadIdx.x % W, t = threadIdx.x / W;
   T* lre = lds + (long)c * 2 * P::LDSN;
   T* lim = lre + P::LDSN;
-  const long col = ((long)blockIdx.x * W + c) * 2;
+  const long col = (tile * W + c) * 2;
   const bool h0 = col < a.C, h1 = col + 1 < a.C;
   cx<T> v[E];
 #pragma unroll
@@ -219,26 +274,7 @@ __global__ void __launch_bounds__(512) k_last(LastArgs<T> a) {
   }
   if (a.mode == PM_PLAIN) return;
   const double blk = block_sum(acc, red);
-  double tot = 0.0;
-  const int nb = gridDim.x;
-  if (last_block_total(blk, a.cg.part_a + (long)o * a.cg.max_blocks, a.cg.cnt_a + o, nb,
-                       blockIdx.x, red, &tot)) {
-    if (threadIdx.x == 0) {
-      if (a.mode == PM_CG) {
-        const double al = a.cg.rr[o] / tot;
-        if (!(tot > 0.0) || !isfinite(al)) {
-          a.cg.active[o] = 0;
-          a.cg.status[o] = 6;
-          atomicSub(a.cg.n_active, 1);
-          a.cg.alpha[o] = 0.0;
-        } else {
-          a.cg.alpha[o] = al;
-        }
-      } else {
-        a.cg.rr[o] = tot;
-      }
-    }
-  }
+  if (threadIdx.x == 0) a.part[(long)o * a.max_blocks + tile] = blk;
 }
 
 // ---------------------------------------------------------------------------
@@ -252,6 +288,7 @@ struct C2CArgs {
   long C;                // complex columns
   long in_os, in_rs;     // per outer slice / per row (complex elements)
   long out_os, out_rs;
+  long ntiles;
   int outer_per_rhs;
   int n_in, n_out;
   int W;
@@ -264,26 +301,26 @@ __global__ void __launch_bounds__(512) k_c2c(C2CArgs<T> a) {
   constexpr int TPL = P::TPL;
   extern __shared__ unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
-  const int o = blockIdx.y;
+  long tile, o;
+  xcd_tile(a.ntiles, tile, o);
   if (a.active && !a.active[o / a.outer_per_rhs]) return;
   const int W = a.W;
   const int c = threadIdx.x % W, t = threadIdx.x / W;
   T* lre = lds + (long)c * 2 * P::LDSN;
   T* lim = lre + P::LDSN;
-  const long col = (long)blockIdx.x * W + c;
+  const long col = tile * W + c;
   const bool h = col < a.C;
   cx<T> v[E];
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int row = t + j * TPL;
-    v[j] = (h && row < a.n_in) ? a.in[(long)o * a.in_os + (long)row * a.in_rs + col]
-                               : cx<T>{0, 0};
+    v[j] = (h && row < a.n_in) ? a.in[o * a.in_os + (long)row * a.in_rs + col] : cx<T>{0, 0};
   }
   fft_line<T, M, E, DIR>(v, lre, lim, t, a.tw);
 #pragma unroll
   for (int sl = 0; sl < E; ++sl) {
     const int row = t + TPL * P::jslot(sl);
-    if (h && row < a.n_out) a.out[(long)o * a.out_os + (long)row * a.out_rs + col] = v[sl];
+    if (h && row < a.n_out) a.out[o * a.out_os + (long)row * a.out_rs + col] = v[sl];
   }
 }
 
@@ -327,16 +364,16 @@ __global__ void __launch_bounds__(512) k_mid(MidArgs<T> a) {
   }
   fft_line<T, M, E, -1>(v, lre, lim, t, a.tw);
   // symbol row of this line
-  long lrow;
-  if (a.d == 3) {
-    const long k0 = line / M, k1 = line % M;
-    lrow = (k0 * a.N1 + (k1 <= M / 2 ? k1 : M - k1)) * a.N1;
-  } else if (a.d == 2) {
-    lrow = line * a.N1;
-  } else {
-    lrow = 0;
+  long lrow = 0;
+  if (h) {
+    if (a.d == 3) {
+      const long k0 = line / M, k1 = line % M;
+      lrow = (k0 * a.N1 + (k1 <= M / 2 ? k1 : M - k1)) * a.N1;
+    } else if (a.d == 2) {
+      lrow = line * a.N1;
+    }
   }
-  const T* lr = a.lam + (h ? lrow : 0);
+  const T* lr = a.lam + lrow;
 #pragma unroll
   for (int sl = 0; sl < E; ++sl) {
     const int k = t + TPL * P::jslot(sl);
@@ -355,7 +392,7 @@ __global__ void __launch_bounds__(512) k_mid(MidArgs<T> a) {
 // contiguous forward transform of full lines (symbol construction)
 template <typename T, int M, int E>
 __global__ void __launch_bounds__(512) k_fwd_rows(cx<T>* data, long rows, int LPB,
-                                                   const cx<T>* tw) {
+                                                  const cx<T>* tw) {
   using P = Plan<M, E>;
   constexpr int TPL = P::TPL;
   extern __shared__ unsigned char smem_raw[];
@@ -376,7 +413,9 @@ __global__ void __launch_bounds__(512) k_fwd_rows(cx<T>* data, long rows, int LP
 }
 
 // ---------------------------------------------------------------------------
-// 1D: one right-hand side per line, whole product in one block
+// 1D: one right-hand side per line (imaginary part zero, so its bits do not
+// depend on which other right-hand sides share the launch); the whole
+// product, and in CG mode the whole iteration start, in one block.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct Line1Args {
@@ -385,9 +424,10 @@ struct Line1Args {
   T* p;
   const T* r;
   const double* f;
-  const double* beta;
   const int* active;
   CgScalars cg;
+  double* part;          // PM_CG / PM_RESID partials, one per RHS
+  int max_blocks;
   const T* lam;
   int n;
   int nrhs;
@@ -405,31 +445,30 @@ __global__ void __launch_bounds__(512) k_line1d(Line1Args<T> a) {
   T* lre = lds;
   T* lim = lds + P::LDSN;
   const int t = threadIdx.x;
-  // one right-hand side per line (imaginary part zero): its bits do not
-  // depend on which other right-hand sides share the launch
-  const int ra = blockIdx.x, rb = ra;
-  const bool hb = false;
-  const bool acta = !a.active || a.active[ra];
-  const bool actb = hb && (!a.active || a.active[rb]);
-  if (!acta && !actb) return;
+  const int o = blockIdx.x;
+  if (a.active && !a.active[o]) return;
+  T bt = 0;
+  if (a.mode == PM_CG) {
+    double beta;
+    if (cg_begin(a.cg, o, true, red, &beta)) return;
+    bt = (T)beta;
+  }
   const long n = a.n;
-  const T ba = (a.mode == PM_CG && acta) ? (T)a.beta[ra] : (T)0;
-  const T bb = (a.mode == PM_CG && actb) ? (T)a.beta[rb] : (T)0;
+  const long base = (long)o * n;
   cx<T> v[E];
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int i = t + j * TPL;
-    T re = 0, im = 0;
+    T re = 0;
     if (i < n) {
       if (a.mode == PM_CG) {
-        if (acta) { re = a.r[ra * n + i] + ba * a.p[ra * n + i]; a.p[ra * n + i] = re; }
-        if (actb) { im = a.r[rb * n + i] + bb * a.p[rb * n + i]; a.p[rb * n + i] = im; }
+        re = a.r[base + i] + bt * a.p[base + i];
+        a.p[base + i] = re;
       } else {
-        if (acta) re = a.u[ra * n + i];
-        if (actb) im = a.u[rb * n + i];
+        re = a.u[base + i];
       }
     }
-    v[j] = {re, im};
+    v[j] = {re, (T)0};
   }
   fft_line<T, M, E, -1>(v, lre, lim, t, a.tw);
 #pragma unroll
@@ -439,49 +478,24 @@ __global__ void __launch_bounds__(512) k_line1d(Line1Args<T> a) {
   }
   to_natural<T, M, E>(v);
   fft_line<T, M, E, +1>(v, lre, lim, t, a.tw);
-  double sa = 0.0, sb = 0.0;
+  double acc = 0.0;
 #pragma unroll
   for (int sl = 0; sl < E; ++sl) {
     const int i = t + TPL * P::jslot(sl);
     if (i < n) {
       if (a.mode == PM_RESID) {
-        if (acta) { const double q = a.f[ra * n + i] - (double)v[sl].x; a.y[ra * n + i] = (T)q; sa += q * q; }
-        if (actb) { const double q = a.f[rb * n + i] - (double)v[sl].y; a.y[rb * n + i] = (T)q; sb += q * q; }
+        const double q = a.f[base + i] - (double)v[sl].x;
+        a.y[base + i] = (T)q;
+        acc += q * q;
       } else {
-        if (acta) a.y[ra * n + i] = v[sl].x;
-        if (actb) a.y[rb * n + i] = v[sl].y;
-        if (a.mode == PM_CG) {
-          if (acta) sa += (double)a.p[ra * n + i] * (double)v[sl].x;
-          if (actb) sb += (double)a.p[rb * n + i] * (double)v[sl].y;
-        }
+        a.y[base + i] = v[sl].x;
+        if (a.mode == PM_CG) acc += (double)a.p[base + i] * (double)v[sl].x;
       }
     }
   }
   if (a.mode == PM_PLAIN) return;
-  sa = block_sum(sa, red);
-  __syncthreads();
-  sb = block_sum(sb, red);
-  if (threadIdx.x == 0) {
-    for (int s = 0; s < 2; ++s) {
-      const int rr = s ? rb : ra;
-      const bool act = s ? actb : acta;
-      const double tot = s ? sb : sa;
-      if (!act) continue;
-      if (a.mode == PM_CG) {
-        const double al = a.cg.rr[rr] / tot;
-        if (!(tot > 0.0) || !isfinite(al)) {
-          a.cg.active[rr] = 0;
-          a.cg.status[rr] = 6;
-          atomicSub(a.cg.n_active, 1);
-          a.cg.alpha[rr] = 0.0;
-        } else {
-          a.cg.alpha[rr] = al;
-        }
-      } else {
-        a.cg.rr[rr] = tot;
-      }
-    }
-  }
+  const double tot = block_sum(acc, red);
+  if (threadIdx.x == 0) a.part[(long)o * a.max_blocks] = tot;
 }
 
 // ---------------------------------------------------------------------------
@@ -494,25 +508,23 @@ __global__ void __launch_bounds__(512) k_line1d(Line1Args<T> a) {
     __VA_ARGS__;                \
   } break;
 
+#define FL_CASES_M(M_, ...)            \
+  FL_CASE_ME(M_, 8, __VA_ARGS__)       \
+  FL_CASE_ME(M_, 16, __VA_ARGS__)      \
+  FL_CASE_ME(M_, 32, __VA_ARGS__)
+
 #define FL_DISPATCH(Mv, Ev, ...)                                                         \
   switch ((Mv) * 64 + (Ev)) {                                                            \
     FL_CASE_ME(8, 8, __VA_ARGS__)                                                        \
     FL_CASE_ME(16, 8, __VA_ARGS__)                                                       \
     FL_CASE_ME(16, 16, __VA_ARGS__)                                                      \
-    FL_CASE_ME(32, 8, __VA_ARGS__)                                                       \
-    FL_CASE_ME(32, 16, __VA_ARGS__)                                                      \
-    FL_CASE_ME(64, 8, __VA_ARGS__)                                                       \
-    FL_CASE_ME(64, 16, __VA_ARGS__)                                                      \
-    FL_CASE_ME(128, 8, __VA_ARGS__)                                                      \
-    FL_CASE_ME(128, 16, __VA_ARGS__)                                                     \
-    FL_CASE_ME(256, 8, __VA_ARGS__)                                                      \
-    FL_CASE_ME(256, 16, __VA_ARGS__)                                                     \
-    FL_CASE_ME(512, 8, __VA_ARGS__)                                                      \
-    FL_CASE_ME(512, 16, __VA_ARGS__)                                                     \
-    FL_CASE_ME(1024, 8, __VA_ARGS__)                                                     \
-    FL_CASE_ME(1024, 16, __VA_ARGS__)                                                    \
-    FL_CASE_ME(2048, 8, __VA_ARGS__)                                                     \
-    FL_CASE_ME(2048, 16, __VA_ARGS__)                                                    \
+    FL_CASES_M(32, __VA_ARGS__)                                                          \
+    FL_CASES_M(64, __VA_ARGS__)                                                          \
+    FL_CASES_M(128, __VA_ARGS__)                                                         \
+    FL_CASES_M(256, __VA_ARGS__)                                                         \
+    FL_CASES_M(512, __VA_ARGS__)                                                         \
+    FL_CASES_M(1024, __VA_ARGS__)                                                        \
+    FL_CASES_M(2048, __VA_ARGS__)                                                        \
     default:                                                                             \
       throw Error(2, "unsupported transform length / radix (M=" + std::to_string(Mv) +   \
                          ", E=" + std::to_string(Ev) + ")");                             \
@@ -528,37 +540,55 @@ inline void check_launch(const char* what) {
   if (e != hipSuccess) throw Error(4, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Allow more than 64 KiB of dynamic LDS (gfx950 has 160 KiB per workgroup).
+template <typename K>
+inline void lds_attr(K kernel, size_t bytes) {
+  if (bytes > 65536)
+    FL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+}
+
+#define FL_LAUNCH(KERNEL, GRID, BLOCK, SH, ST, ...) \
+  do {                                              \
+    auto kfn_ = KERNEL;                             \
+    lds_attr(kfn_, SH);                             \
+    hipLaunchKernelGGL(kfn_, GRID, BLOCK, SH, ST, __VA_ARGS__); \
+  } while (0)
+
+inline long pair_tiles(long C, int W) { return ((C + 1) / 2 + W - 1) / W; }
+
 template <typename T>
-void launch_first(int M, int E, const FirstArgs<T>& a, int nrhs, hipStream_t st) {
-  const long pairs = (a.C + 1) / 2;
-  dim3 grid((unsigned)((pairs + a.W - 1) / a.W), (unsigned)nrhs);
+void launch_first(int M, int E, FirstArgs<T> a, int nrhs, hipStream_t st) {
+  a.ntiles = pair_tiles(a.C, a.W);
+  dim3 grid((unsigned)(a.ntiles * nrhs));
   const int threads = a.W * (M / E);
   const size_t sh = line_lds_bytes<T>(M, E) * a.W;
-  FL_DISPATCH(M, E, hipLaunchKernelGGL((k_first<T, M, E>), grid, dim3(threads), sh, st, a));
+  FL_DISPATCH(M, E, FL_LAUNCH((k_first<T, M, E>), grid, dim3(threads), sh, st, a));
   check_launch("first pass");
 }
 
 template <typename T>
-void launch_last(int M, int E, const LastArgs<T>& a, int nrhs, hipStream_t st) {
-  const long pairs = (a.C + 1) / 2;
-  dim3 grid((unsigned)((pairs + a.W - 1) / a.W), (unsigned)nrhs);
-  if (a.mode != PM_PLAIN && (int)grid.x > a.cg.max_blocks)
+void launch_last(int M, int E, LastArgs<T> a, int nrhs, hipStream_t st) {
+  a.ntiles = pair_tiles(a.C, a.W);
+  if (a.mode != PM_PLAIN && a.ntiles > a.max_blocks)
     throw Error(2, "too many blocks for the reduction buffers");
+  dim3 grid((unsigned)(a.ntiles * nrhs));
   const int threads = a.W * (M / E);
   const size_t sh = line_lds_bytes<T>(M, E) * a.W;
-  FL_DISPATCH(M, E, hipLaunchKernelGGL((k_last<T, M, E>), grid, dim3(threads), sh, st, a));
+  FL_DISPATCH(M, E, FL_LAUNCH((k_last<T, M, E>), grid, dim3(threads), sh, st, a));
   check_launch("last pass");
 }
 
 template <typename T>
-void launch_c2c(int M, int E, int dir, const C2CArgs<T>& a, long outer, hipStream_t st) {
-  dim3 grid((unsigned)((a.C + a.W - 1) / a.W), (unsigned)outer);
+void launch_c2c(int M, int E, int dir, C2CArgs<T> a, long outer, hipStream_t st) {
+  a.ntiles = (a.C + a.W - 1) / a.W;
+  dim3 grid((unsigned)(a.ntiles * outer));
   const int threads = a.W * (M / E);
   const size_t sh = line_lds_bytes<T>(M, E) * a.W;
   if (dir < 0) {
-    FL_DISPATCH(M, E, hipLaunchKernelGGL((k_c2c<T, M, E, -1>), grid, dim3(threads), sh, st, a));
+    FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, -1>), grid, dim3(threads), sh, st, a));
   } else {
-    FL_DISPATCH(M, E, hipLaunchKernelGGL((k_c2c<T, M, E, 1>), grid, dim3(threads), sh, st, a));
+    FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, 1>), grid, dim3(threads), sh, st, a));
   }
   check_launch("c2c pass");
 }
@@ -568,7 +598,7 @@ void launch_mid(int M, int E, const MidArgs<T>& a, int nrhs, hipStream_t st) {
   dim3 grid((unsigned)((a.rows + a.LPB - 1) / a.LPB), (unsigned)nrhs);
   const int threads = a.LPB * (M / E);
   const size_t sh = line_lds_bytes<T>(M, E) * a.LPB;
-  FL_DISPATCH(M, E, hipLaunchKernelGGL((k_mid<T, M, E>), grid, dim3(threads), sh, st, a));
+  FL_DISPATCH(M, E, FL_LAUNCH((k_mid<T, M, E>), grid, dim3(threads), sh, st, a));
   check_launch("middle pass");
 }
 
@@ -578,8 +608,8 @@ void launch_fwd_rows(int M, int E, cx<T>* data, long rows, int LPB, const cx<T>*
   dim3 grid((unsigned)((rows + LPB - 1) / LPB));
   const int threads = LPB * (M / E);
   const size_t sh = line_lds_bytes<T>(M, E) * LPB;
-  FL_DISPATCH(M, E, hipLaunchKernelGGL((k_fwd_rows<T, M, E>), grid, dim3(threads), sh, st,
-                                       data, rows, LPB, tw));
+  FL_DISPATCH(M, E, FL_LAUNCH((k_fwd_rows<T, M, E>), grid, dim3(threads), sh, st, data, rows,
+                              LPB, tw));
   check_launch("row transform");
 }
 
@@ -588,7 +618,7 @@ void launch_line1d(int M, int E, const Line1Args<T>& a, hipStream_t st) {
   dim3 grid((unsigned)a.nrhs);
   const int threads = M / E;
   const size_t sh = line_lds_bytes<T>(M, E);
-  FL_DISPATCH(M, E, hipLaunchKernelGGL((k_line1d<T, M, E>), grid, dim3(threads), sh, st, a));
+  FL_DISPATCH(M, E, FL_LAUNCH((k_line1d<T, M, E>), grid, dim3(threads), sh, st, a));
   check_launch("1D line");
 }
 

@@ -219,3 +219,35 @@ def test_solve_zero_rhs_and_maxiter():
     assert info[1]["status"] == fl._lib.FL_E_NOCONV and info[1]["iters"] == 3
     with pytest.raises(fl.FlError):
         op.solve(f, tol=1e-12, maxiter=3)
+
+
+@pytest.mark.parametrize("d,N,fp32", [(2, 64, False), (2, 64, True), (3, 16, False),
+                                      (3, 16, True), (1, 256, True)])
+def test_schedules_give_same_product(d, N, fp32):
+    """Every launch schedule the tuner may pick computes the same product
+    (radix 8/16/32 register stages, 1..16 lines per block)."""
+    from paper_2103_03658_amd import tune
+    op = make_op(d, 1.1, 1, N)
+    u = inputs.uniform_rhs(d, N, 3, seed=21)
+    ut = torch.from_numpy(u.astype(np.float32) if fp32 else u).cuda()
+    G = orc_gen(d, 1.1, 1, N)
+    scales = [abs_scale(G, u[r]) for r in range(3)]
+    refs = [oracle.apply(G, ut[r].double().cpu().numpy()) for r in range(3)]
+    tol = 5e-6 if fp32 else 1e-12
+    base = op.get_schedule(fp32)
+    tried = 0
+    for E, W in tune.candidates(op.M, fp32):
+        for ek, wk in (("e_first", "w_first"), ("e_mid", "lpb_mid"), ("e_c2c", "w_c2c")):
+            if d == 1 and ek != "e_mid":
+                continue
+            s = dict(base)
+            s[ek], s[wk] = E, W
+            try:
+                op.set_schedule(fp32, **s)
+            except Exception:
+                continue
+            y = op.apply(ut).double().cpu().numpy()
+            for r in range(3):
+                assert np.abs(y[r] - refs[r]).max() <= tol * scales[r], (ek, E, wk, W)
+            tried += 1
+    assert tried >= 5
