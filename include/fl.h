@@ -52,8 +52,9 @@ enum { FL_KERNEL_FRACTIONAL = 0, FL_KERNEL_TEMPERED = 1 };
 
 /* Per right-hand-side result of fl_solve. */
 typedef struct {
-  int iters;          /* CG iterations (FP64 path) / inner FP32 iterations summed (mixed) */
-  int outer_iters;    /* refinement steps (mixed path), 0 otherwise */
+  int iters;          /* CG iterations (FP32 iterations for the mixed paths, summed) */
+  int outer_iters;    /* FP64 residual replacements (mixed = 1) or refinement steps
+                         (mixed = 2); 0 for mixed = 0 */
   int converged;      /* 1 if the stopping rule was met */
   int status;         /* fl_status of this right-hand side */
   double relres_rec;  /* recursive ||r||_2 / ||f||_2 at exit (mixed: the FP64 residual) */
@@ -117,11 +118,18 @@ fl_status fl_apply(fl_op A, const void *u, void *y, int nrhs, int fp32, void *st
  *   f       device, nrhs * n^d doubles
  *   g       exterior data; must be NULL (g = 0).  Non-NULL: FL_E_UNSUPPORTED
  *   tol     stop when ||r||_2 <= tol ||f||_2 (per right-hand side), tol > 0
- *   maxiter CG iteration cap (FP64 path) / inner iteration cap per
- *           refinement step (mixed path), >= 1
- *   mixed   0: FP64 CG, recursive residual.  1: FP32 CG inner solves with
- *           FP64 residuals r = f - A u and FP64 updates u += delta
- *           (iterative refinement) until the FP64 residual meets tol
+ *   maxiter CG iteration cap (mixed = 0, 1) / inner iteration cap per
+ *           refinement step (mixed = 2), >= 1
+ *   mixed   0: FP64 CG; stops on the recursive residual.
+ *           1: FP32 CG with FP64 reliable updates: the FP32 recursion runs on
+ *           a correction; whenever its residual norm has dropped by the factor
+ *           delta (fl_set_refinement) since the last update, the
+ *           correction is added to the FP64 iterate and the residual is
+ *           recomputed as r = f - A u with an FP64 product; stops when that
+ *           FP64 residual meets tol.
+ *           2: iterative refinement with restarts: FP32 CG solves A d = r to
+ *           the relative tolerance inner_tol, u += d in FP64, r = f - A u in
+ *           FP64, until the FP64 residual meets tol.
  *   u       device, nrhs * n^d doubles, output (x0 = 0)
  *   info    host array of nrhs fl_info, or NULL
  * Blocks until done.  Returns FL_OK if every right-hand side converged,
@@ -131,9 +139,13 @@ fl_status fl_apply(fl_op A, const void *u, void *y, int nrhs, int fp32, void *st
 fl_status fl_solve(fl_op A, const double *f, const double *g, double tol, int maxiter, int mixed,
                    double *u, int nrhs, fl_info *info, void *stream);
 
-/* Mixed-precision settings: relative tolerance of each FP32 inner solve
- * (0 < inner_tol < 1) and the refinement step cap (>= 1). */
-fl_status fl_set_refinement(fl_op A, double inner_tol, int max_outer);
+/* Mixed-precision settings.  delta (default 0.1): a reliable update
+ * (mixed = 1) happens once the FP32 residual norm has dropped below delta
+ * times its value at the previous update.  inner_tol (default 1e-4):
+ * relative tolerance of each FP32 inner solve of mixed = 2.  max_outer
+ * (default 40): refinement step cap of mixed = 2.  delta, inner_tol in
+ * (0, 1), max_outer >= 1, else FL_E_INVAL and nothing changes. */
+fl_status fl_set_refinement(fl_op A, double delta, double inner_tol, int max_outer);
 
 /*
  * Launch schedule of the transform passes (elements per thread E and lines

@@ -92,7 +92,8 @@ class Operator:
 
     def solve(self, f, tol=1e-10, maxiter=20000, mixed=False, out=None, stream=None,
               raise_on_fail=True):
-        """u with A u = f (CG; mixed=True: FP32 inner CG + FP64 refinement).
+        """u with A u = f by CG.  mixed: False/0 FP64; True/1 FP32 CG with FP64
+        reliable updates; 2 FP32 inner solves with FP64 iterative refinement.
         Returns (u, list of per-RHS info dicts)."""
         import torch
         if f.dtype != torch.float64:
@@ -102,7 +103,7 @@ class Operator:
             out = torch.empty_like(f)
         info = (FlInfo * nrhs)()
         st = self._lib.fl_solve(self._h, ctypes.c_void_p(f.data_ptr()), None, float(tol),
-                                int(maxiter), 1 if mixed else 0, ctypes.c_void_p(out.data_ptr()),
+                                int(maxiter), int(mixed), ctypes.c_void_p(out.data_ptr()),
                                 nrhs, info, _stream_ptr(stream))
         infos = [i.as_dict() for i in info]
         if raise_on_fail:
@@ -124,8 +125,9 @@ class Operator:
                                          _stream_ptr(stream), ms, 8, ctypes.byref(npass)))
         return [ms[i] for i in range(npass.value)]
 
-    def set_refinement(self, inner_tol, max_outer):
-        check(self._lib.fl_set_refinement(self._h, float(inner_tol), int(max_outer)))
+    def set_refinement(self, delta=0.1, inner_tol=1e-4, max_outer=40):
+        check(self._lib.fl_set_refinement(self._h, float(delta), float(inner_tol),
+                                          int(max_outer)))
 
     def set_schedule(self, fp32, e_first=0, e_mid=0, e_c2c=0, w_first=0, w_c2c=0, lpb_mid=0):
         check(self._lib.fl_set_schedule(self._h, int(bool(fp32)), e_first, e_mid, e_c2c,

@@ -52,7 +52,7 @@ _SIGS = {
     "fl_apply": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, _P]),
     "fl_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_int, ctypes.c_int, _P,
                                 ctypes.c_int, ctypes.POINTER(FlInfo), _P]),
-    "fl_set_refinement": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_int]),
+    "fl_set_refinement": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double, ctypes.c_int]),
     "fl_set_schedule": (ctypes.c_int, [_P, ctypes.c_int] + [ctypes.c_int] * 6),
     "fl_get_schedule": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "fl_profile_apply": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int,

@@ -118,7 +118,8 @@ struct fl_op_s {
   const void* tw64 = nullptr;
   const void* tw32 = nullptr;
   fl::Schedule sc64{}, sc32{};
-  double inner_tol = 1e-4;
+  double delta = 0.1;       // reliable-update trigger (mixed = 1)
+  double inner_tol = 1e-4;  // inner solve tolerance (mixed = 2)
   int max_outer = 40;
   DBuf ws;                // FFT intermediates
   DBuf vecs;              // solver vectors
@@ -359,10 +360,11 @@ fl_status fl_get_schedule(fl_op A, int fp32, int* s6) {
   return FL_OK;
 }
 
-fl_status fl_set_refinement(fl_op A, double inner_tol, int max_outer) {
+fl_status fl_set_refinement(fl_op A, double delta, double inner_tol, int max_outer) {
   if (!A) return fail(FL_E_INVAL, "null handle");
-  if (!(inner_tol > 0.0 && inner_tol < 1.0) || max_outer < 1)
-    return fail(FL_E_INVAL, "inner_tol in (0,1) and max_outer >= 1 required");
+  if (!(delta > 0.0 && delta < 1.0) || !(inner_tol > 0.0 && inner_tol < 1.0) || max_outer < 1)
+    return fail(FL_E_INVAL, "delta and inner_tol in (0,1) and max_outer >= 1 required");
+  A->delta = delta;
   A->inner_tol = inner_tol;
   A->max_outer = max_outer;
   return FL_OK;
@@ -507,6 +509,7 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
     if (!(tol > 0.0) || !std::isfinite(tol)) return fail(FL_E_INVAL, "tol must be positive");
     if (maxiter < 1) return fail(FL_E_INVAL, "maxiter must be >= 1");
     if (nrhs < 1) return fail(FL_E_INVAL, "nrhs must be >= 1");
+    if (mixed < 0 || mixed > 2) return fail(FL_E_INVAL, "mixed must be 0, 1 or 2");
     if ((const void*)f == (const void*)u) return fail(FL_E_INVAL, "f and u must be distinct");
     set_device(A);
     hipStream_t st = (hipStream_t)stream;
@@ -521,11 +524,15 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
     A->cg_out.ensure(nrhs, st);
     const fl::CgScalars& co = A->cg_out.s;
     // per-RHS host-visible norms and flags: f2, rr (outer), scale, flags
-    char* fb = (char*)A->outer_flags.get(3 * (size_t)nrhs * sizeof(double) + nrhs * sizeof(int) + 1024);
+    char* fb = (char*)A->outer_flags.get(4 * (size_t)nrhs * sizeof(double) +
+                                         3 * (size_t)nrhs * sizeof(int) + 1024);
     double* f2 = (double*)fb;
     double* rro = f2 + nrhs;
     double* scale = rro + nrhs;
-    int* oact = (int*)(scale + nrhs);
+    double* rr_last = scale + nrhs;
+    int* oact = (int*)(rr_last + nrhs);
+    int* trig = oact + nrhs;
+    int* nupd = trig + nrhs;
     void* ws = A->ws.get(fl::apply_workspace_bytes(A->g, nrhs, false));
     std::vector<double> hf2(nrhs), hrr(nrhs);
     sum_squares(A, f, nrhs, co, f2, st);
@@ -550,6 +557,63 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
         rec[o] = fn > 0 ? std::sqrt(rr[o]) / fn : 0.0;
         tru[o] = fn > 0 ? std::sqrt(hrr[o]) / fn : 0.0;
         if (status[o] == 0 && !(rec[o] <= tol) && fn > 0) status[o] = FL_E_NOCONV;
+      }
+    } else if (mixed == 1) {
+      // FP32 CG with FP64 reliable updates: the FP32 recursion runs on a
+      // correction xlo; every `chunk` iterations each RHS whose FP32 residual
+      // fell below delta^2 of its value at the last update (or below the
+      // tolerance) folds xlo into the FP64 iterate u, recomputes r = f - A u
+      // in FP64, stops if ||r|| <= tol ||f||, and otherwise continues from
+      // r (rounded to FP32) with the same search direction.
+      fl::CgScalars cg = cg_view(A->cg.s, A->g, A->sc32, nrhs, maxiter, tol);
+      cg.tol2 = 0.0;  // the FP32 recursion never stops on its own residual
+      const double delta2 = A->delta * A->delta;
+      const int nb64 = fl::last_pass_blocks(A->g, A->sc64);
+      char* vb = (char*)A->vecs.get(a8 + 5 * a4);
+      double* r64 = (double*)vb;
+      float* rhs32 = (float*)(vb + a8);
+      float* xlo = (float*)(vb + a8 + a4);
+      float* r32 = (float*)(vb + a8 + 2 * a4);
+      float* p32 = (float*)(vb + a8 + 3 * a4);
+      float* q32 = (float*)(vb + a8 + 4 * a4);
+      fl::fill_zero_bytes(u, v8, st);
+      fl::to_float(f, rhs32, (long)nrhs * nd, st);
+      FL_HIP(hipMemcpyAsync(rr_last, f2, nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
+      fl::fill_int(nupd, 0, nrhs, st);
+      fl::fill_int(cg.n_active, 0, 1, st);
+      fl::cg_init<float>(A->g, rhs32, xlo, r32, p32, nrhs, cg, nullptr, st);
+      const int chunk = 8;
+      for (int done = 0; done < maxiter + chunk; done += chunk) {
+        for (int i = 0; i < chunk; ++i) {
+          fl::apply_passes<float>(A->g, A->sc32, A->lam32, A->tw32, nullptr, q32, nrhs, ws, st,
+                                  fl::PM_CG, r32, p32, nullptr, &cg, cg.active);
+          fl::cg_update<float>(A->g, xlo, r32, p32, q32, nrhs, cg, st);
+        }
+        fl::reliable_accum(A->g, u, xlo, nrhs, cg, rr_last, f2, delta2, tol * tol, trig, false,
+                           st);
+        fl::apply_passes<double>(A->g, A->sc64, A->lam64, A->tw64, u, r64, nrhs, ws, st,
+                                 fl::PM_RESID, nullptr, nullptr, f, &co, trig);
+        fl::reliable_replace(A->g, r64, r32, nrhs, cg, co.part_a, nb64, co.max_blocks, rr_last,
+                             f2, tol * tol, trig, nupd, st);
+        int nact = 0;
+        FL_HIP(hipMemcpyAsync(&nact, cg.n_active, sizeof(int), hipMemcpyDeviceToHost, st));
+        FL_HIP(hipStreamSynchronize(st));
+        if (nact == 0) break;
+      }
+      // fold what is left (RHS stopped by maxiter) and report true residuals
+      fl::reliable_accum(A->g, u, xlo, nrhs, cg, rr_last, f2, delta2, tol * tol, trig, true, st);
+      fp64_residual(A, f, u, r64, nrhs, co, nullptr, rro, ws, st);
+      FL_HIP(hipMemcpyAsync(iters.data(), cg.iters, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
+      FL_HIP(hipMemcpyAsync(status.data(), cg.status, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
+      FL_HIP(hipMemcpyAsync(outer.data(), nupd, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
+      FL_HIP(hipMemcpyAsync(hrr.data(), rro, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+      FL_HIP(hipMemcpyAsync(hf2.data(), f2, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+      FL_HIP(hipStreamSynchronize(st));
+      for (int o = 0; o < nrhs; ++o) {
+        const double rel = hf2[o] > 0 ? std::sqrt(hrr[o] / hf2[o]) : 0.0;
+        rec[o] = rel;
+        tru[o] = rel;
+        if (status[o] == 0 && !(rel <= tol) && hf2[o] > 0) status[o] = FL_E_NOCONV;
       }
     } else {
       // FP64 residual and iterate; FP32 CG on A delta = r / ||r|| (inner_tol)

@@ -147,7 +147,104 @@ __global__ void __launch_bounds__(VT) k_sumsq_parts(const double* v, long nd, do
   if (threadIdx.x == 0) part[(long)o * max_blocks + blockIdx.x] = blk;
 }
 
+__global__ void __launch_bounds__(VT) k_to_float(const double* src, float* dst, long n) {
+  for (long i = (long)blockIdx.x * VT + threadIdx.x; i < n; i += (long)gridDim.x * VT)
+    dst[i] = (float)src[i];
+}
+
+// Reliable update, step 1: decide per RHS whether to replace the FP32
+// recursive residual by the true FP64 one (it fell below delta^2 times its
+// value at the last replacement, or below the final tolerance), and if so
+// fold the FP32 correction into the FP64 iterate: xhi += xlo, xlo = 0.
+// force: fold for every RHS (end of the solve).
+__global__ void __launch_bounds__(VT) k_reliable_accum(double* xhi, float* xlo, long nd,
+                                                       CgScalars cg, const double* rr_last,
+                                                       const double* f2, double delta2,
+                                                       double tol2, int* trig, int force) {
+  __shared__ double red[16];
+  const int o = blockIdx.y;
+  bool t = true;
+  if (!force) {
+    if (!cg.active[o]) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) trig[o] = 0;
+      return;
+    }
+    const double rr = sum_partials(cg.part_b + (long)o * cg.max_blocks, cg.nb_b, red);
+    t = !(rr >= delta2 * rr_last[o]) || rr <= tol2 * f2[o];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) trig[o] = t ? 1 : 0;
+  if (!t) return;
+  const long base = (long)o * nd;
+  for (long i = (long)blockIdx.x * VT + threadIdx.x; i < nd; i += (long)gridDim.x * VT) {
+    xhi[base + i] += (double)xlo[base + i];
+    xlo[base + i] = 0.0f;
+  }
+}
+
+// Reliable update, step 2 (after r64 = f - A xhi in FP64 for the flagged
+// RHS): stop if ||r64|| meets the tolerance, else r32 = r64 and fresh
+// partials of r32.r32 for the next iteration's beta.
+__global__ void __launch_bounds__(VT) k_reliable_replace(const double* r64, float* r32, long nd,
+                                                         CgScalars cg, const double* part64,
+                                                         int nb64, int mb64, double* rr_last,
+                                                         const double* f2, double tol2,
+                                                         const int* trig, int* nupd) {
+  __shared__ double red[16];
+  const int o = blockIdx.y;
+  if (!trig[o]) return;
+  const double rr64 = sum_partials(part64 + (long)o * mb64, nb64, red);
+  const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+  if (lead) {
+    rr_last[o] = rr64;
+    nupd[o] = nupd[o] + 1;
+  }
+  if (rr64 <= tol2 * f2[o] || !isfinite(rr64)) {
+    if (lead) {
+      cg.active[o] = 0;
+      cg.status[o] = isfinite(rr64) ? 0 : 6;
+      atomicSub(cg.n_active, 1);
+    }
+    return;
+  }
+  const long base = (long)o * nd;
+  double acc = 0.0;
+  for (long i = (long)blockIdx.x * VT + threadIdx.x; i < nd; i += (long)gridDim.x * VT) {
+    const float v = (float)r64[base + i];
+    r32[base + i] = v;
+    acc += (double)v * (double)v;
+  }
+  const double blk = block_sum(acc, red);
+  if (threadIdx.x == 0) cg.part_b[(long)o * cg.max_blocks + blockIdx.x] = blk;
+}
+
 }  // namespace
+
+void to_float(const double* src, float* dst, long n, hipStream_t st) {
+  long b = (n + VT * 4 - 1) / (VT * 4);
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  hipLaunchKernelGGL(k_to_float, dim3((unsigned)b), dim3(VT), 0, st, src, dst, n);
+  check_launch("to float");
+}
+
+void reliable_accum(const Geometry& g, double* xhi, float* xlo, int nrhs, const CgScalars& cg,
+                    const double* rr_last, const double* f2, double delta2, double tol2,
+                    int* trig, bool force, hipStream_t st) {
+  dim3 grid(cg.nb_b, nrhs);
+  hipLaunchKernelGGL(k_reliable_accum, grid, dim3(VT), 0, st, xhi, xlo, g.nd, cg, rr_last, f2,
+                     delta2, tol2, trig, force ? 1 : 0);
+  check_launch("reliable accumulate");
+}
+
+void reliable_replace(const Geometry& g, const double* r64, float* r32, int nrhs,
+                      const CgScalars& cg, const double* part64, int nb64, int mb64,
+                      double* rr_last, const double* f2, double tol2, const int* trig,
+                      int* nupd, hipStream_t st) {
+  dim3 grid(cg.nb_b, nrhs);
+  hipLaunchKernelGGL(k_reliable_replace, grid, dim3(VT), 0, st, r64, r32, g.nd, cg, part64, nb64,
+                     mb64, rr_last, f2, tol2, trig, nupd);
+  check_launch("reliable replace");
+}
 
 int vec_blocks(long nd, int nrhs) {
   // about 2048 blocks in total (8 per CU), at least 1024 elements per block

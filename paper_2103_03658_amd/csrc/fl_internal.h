@@ -134,6 +134,15 @@ void refine_scale(const double* r64, float* r32, const double* rr, double* scale
                   int nrhs, const int* active, hipStream_t st);
 void refine_axpy(double* u, const float* d32, const double* scale, long nd, int nrhs,
                  const int* active, hipStream_t st);
+// FP32 CG with FP64 reliable updates (see cg unit)
+void to_float(const double* src, float* dst, long n, hipStream_t st);
+void reliable_accum(const Geometry& g, double* xhi, float* xlo, int nrhs, const CgScalars& cg,
+                    const double* rr_last, const double* f2, double delta2, double tol2,
+                    int* trig, bool force, hipStream_t st);
+void reliable_replace(const Geometry& g, const double* r64, float* r32, int nrhs,
+                      const CgScalars& cg, const double* part64, int nb64, int mb64,
+                      double* rr_last, const double* f2, double tol2, const int* trig,
+                      int* nupd, hipStream_t st);
 // partials of sum v^2 per RHS into part (vec_blocks per RHS)
 void sum_squares_parts(const double* v, long nd, int nrhs, double* part, int max_blocks,
                        hipStream_t st);

@@ -68,7 +68,7 @@ def test_null_handle_errors():
     lib = _lib.lib()
     assert lib.fl_apply(None, None, None, 1, 0, None) == _lib.FL_E_INVAL
     assert lib.fl_solve(None, None, None, 1e-10, 10, 0, None, 1, None, None) == _lib.FL_E_INVAL
-    assert lib.fl_set_refinement(None, 1e-3, 3) == _lib.FL_E_INVAL
+    assert lib.fl_set_refinement(None, 0.1, 1e-3, 3) == _lib.FL_E_INVAL
     lib.fl_destroy(None)  # accepted
 
 

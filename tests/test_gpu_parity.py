@@ -159,9 +159,10 @@ def test_apply_ragged_and_edge_sizes():
 
 
 @pytest.mark.parametrize("d,alpha,p,N,mixed", [
-    (1, 1.5, 1, 256, False), (2, 1.5, 1, 16, False), (2, 0.5, 2, 32, False),
-    (3, 1.0, 1, 8, False), (2, 1.5, 1, 16, True), (2, 1.0, 2, 32, True), (3, 1.0, 1, 8, True),
-    (1, 1.5, 1, 256, True),
+    (1, 1.5, 1, 256, 0), (2, 1.5, 1, 16, 0), (2, 0.5, 2, 32, 0), (3, 1.0, 1, 8, 0),
+    (2, 1.5, 1, 16, 1), (2, 1.0, 2, 32, 1), (3, 1.0, 1, 8, 1), (1, 1.5, 1, 256, 1),
+    (2, 1.9, 2, 64, 1), (2, 1.5, 1, 16, 2), (2, 1.0, 2, 32, 2), (3, 1.0, 1, 8, 2),
+    (1, 1.5, 1, 256, 2),
 ])
 def test_solve_parity(d, alpha, p, N, mixed):
     print(f"[solve] d={d} alpha={alpha} p={p} N={N} mixed={mixed}", flush=True)
@@ -251,3 +252,29 @@ def test_schedules_give_same_product(d, N, fp32):
                 assert np.abs(y[r] - refs[r]).max() <= tol * scales[r], (ek, E, wk, W)
             tried += 1
     assert tried >= 5
+
+
+def test_mixed_solve_batch_invariance_bitwise():
+    """Mixed-precision solve: a right-hand side gives the same bits alone and
+    inside a batch (reliable updates are decided per right-hand side)."""
+    op = make_op(2, 1.5, 2, 32)
+    f = torch.from_numpy(inputs.uniform_rhs(2, 32, 3, seed=19)).cuda()
+    ub, ib = op.solve(f, tol=1e-10, mixed=1)
+    for r in range(3):
+        ua, ia = op.solve(f[r].contiguous(), tol=1e-10, mixed=1)
+        assert torch.equal(ua, ub[r])
+        assert ia[0]["iters"] == ib[r]["iters"]
+
+
+def test_mixed_maxiter_reports_noconv():
+    fl = _fl()
+    op = make_op(2, 1.5, 1, 32)
+    f = torch.from_numpy(inputs.uniform_rhs(2, 32, 1, seed=2)).cuda()
+    u, info = op.solve(f, tol=1e-12, maxiter=5, mixed=1, raise_on_fail=False)
+    assert info[0]["status"] == fl._lib.FL_E_NOCONV
+    assert info[0]["iters"] == 5
+    # the reported residual is the FP64 residual of the returned iterate
+    G = orc_gen(2, 1.5, 1, 32)
+    fn = f.cpu().numpy()[0]
+    rel = np.linalg.norm(fn - oracle.apply(G, u.cpu().numpy()[0])) / np.linalg.norm(fn)
+    assert abs(rel - info[0]["relres_true"]) <= 1e-6 * rel
