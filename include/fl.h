@@ -175,6 +175,13 @@ fl_status fl_get_schedule(fl_op A, int fp32, int *sched6);
 fl_status fl_profile_apply(fl_op A, const void *u, void *y, int nrhs, int fp32, int reps,
                            void *stream, double *ms_per_pass, int max_passes, int *n_passes);
 
+/* Replay CG iteration chunks from captured HIP graphs (enable = 1, the
+ * default) or launch every kernel directly (enable = 0).  Results are the
+ * same either way; graphs cut host launch cost.  fl_solve runs its work on
+ * a stream owned by the handle, ordered after `stream` and before later work
+ * on `stream` by events. */
+fl_status fl_set_graphs(fl_op A, int enable);
+
 /* Release the handle and its device memory.  NULL is accepted. */
 void fl_destroy(fl_op A);
 

@@ -133,6 +133,9 @@ class Operator:
         check(self._lib.fl_set_schedule(self._h, int(bool(fp32)), e_first, e_mid, e_c2c,
                                         w_first, w_c2c, lpb_mid))
 
+    def set_graphs(self, enable):
+        check(self._lib.fl_set_graphs(self._h, int(bool(enable))))
+
     def get_schedule(self, fp32):
         s = (ctypes.c_int * 6)()
         check(self._lib.fl_get_schedule(self._h, int(bool(fp32)), s))

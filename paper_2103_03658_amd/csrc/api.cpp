@@ -106,6 +106,19 @@ struct CgState {
   }
 };
 
+// A chunk of CG iterations captured once into a HIP graph and replayed.
+// The key lists every value baked into the captured launches (buffers,
+// schedule, sizes, tolerances); any change recaptures.
+struct ChunkGraph {
+  hipGraphExec_t exec = nullptr;
+  std::vector<double> key;
+  void reset() {
+    if (exec) hipGraphExecDestroy(exec);
+    exec = nullptr;
+    key.clear();
+  }
+};
+
 }  // namespace
 
 struct fl_op_s {
@@ -128,6 +141,13 @@ struct fl_op_s {
   hipEvent_t done = nullptr;
   hipStream_t last_stream = nullptr;
   bool used = false;
+  // solver stream (default priority), events and pinned flags for polling
+  hipStream_t solve_stream = nullptr;
+  hipEvent_t ev_in = nullptr;
+  hipEvent_t ev_poll[2] = {nullptr, nullptr};
+  int* pinned = nullptr;
+  ChunkGraph graph[2];    // captured CG chunks: FP64 (0), FP32 reliable (1)
+  bool use_graphs = true;
 
   // Order this call after the previous one if it ran on another stream
   // (the workspace is shared).
@@ -152,7 +172,7 @@ bool schedule_ok(const Geometry& g, const Schedule& s, bool fp32) {
     if (!(E == 8 || E == 16 || E == 32) || E > g.M) return false;
     if (W < 1) return false;
     if ((long)W * (g.M / E) > 512) return false;
-    if (line_bytes(g.M, E, fp32) * W > kMaxLds) return false;
+    if (line_bytes(g.M, E, fp32) * W > kMaxLds - 1024) return false;  // room for static LDS
     return true;
   };
   return ok(s.E_first, s.W_first) && ok(s.E_mid, s.LPB_mid) && ok(s.E_c2c, s.W_c2c);
@@ -275,6 +295,12 @@ void fl_destroy(fl_op A) {
   A->cg_out.mem.release();
   A->outer_flags.release();
   if (A->done) hipEventDestroy(A->done);
+  for (auto& gph : A->graph) gph.reset();
+  if (A->ev_in) hipEventDestroy(A->ev_in);
+  for (auto& e : A->ev_poll)
+    if (e) hipEventDestroy(e);
+  if (A->pinned) hipHostFree(A->pinned);
+  if (A->solve_stream) hipStreamDestroy(A->solve_stream);
   delete A;
 }
 
@@ -346,6 +372,12 @@ fl_status fl_set_schedule(fl_op A, int fp32, int e_first, int e_mid, int e_c2c, 
     (fp32 ? A->sc32 : A->sc64) = s;
     return FL_OK;
   });
+}
+
+fl_status fl_set_graphs(fl_op A, int enable) {
+  if (!A) return fail(FL_E_INVAL, "null handle");
+  A->use_graphs = enable != 0;
+  return FL_OK;
 }
 
 fl_status fl_get_schedule(fl_op A, int fp32, int* s6) {
@@ -453,6 +485,79 @@ fl::CgScalars cg_view(const fl::CgScalars& base, const fl::Geometry& g, const fl
   return c;
 }
 
+void ensure_solver_stream(fl_op A) {
+  if (A->solve_stream) return;
+  FL_HIP(hipStreamCreateWithFlags(&A->solve_stream, hipStreamNonBlocking));
+  FL_HIP(hipEventCreateWithFlags(&A->ev_in, hipEventDisableTiming));
+  for (auto& e : A->ev_poll) FL_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  FL_HIP(hipHostMalloc((void**)&A->pinned, 2 * sizeof(int), hipHostMallocDefault));
+}
+
+// Replay the captured chunk if `key` matches; otherwise run `enqueue` once
+// directly and capture it into a new graph for the next calls.
+template <typename F>
+void launch_chunk(ChunkGraph& g, const std::vector<double>& key, hipStream_t st, bool graphs,
+                  F&& enqueue) {
+  if (!graphs) {
+    enqueue();
+    return;
+  }
+  if (g.exec && g.key == key) {
+    FL_HIP(hipGraphLaunch(g.exec, st));
+    return;
+  }
+  g.reset();
+  enqueue();
+  hipGraph_t graph = nullptr;
+  FL_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  try {
+    enqueue();
+  } catch (...) {
+    (void)hipStreamEndCapture(st, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
+    throw;
+  }
+  FL_HIP(hipStreamEndCapture(st, &graph));
+  const hipError_t e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    g.exec = nullptr;
+    throw Error(FL_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  g.key = key;
+}
+
+// Run chunks until no right-hand side is active.  The active count of each
+// chunk is copied to pinned host memory and checked one chunk later, so the
+// GPU never waits for the host; the one extra chunk is fully masked.
+template <typename F>
+void chunk_loop(fl_op A, ChunkGraph& g, const std::vector<double>& key, int max_chunks,
+                const fl::CgScalars& cg, hipStream_t st, F&& enqueue) {
+  for (int c = 0; c < max_chunks; ++c) {
+    const int slot = c & 1;
+    launch_chunk(g, key, st, A->use_graphs, enqueue);
+    FL_HIP(hipMemcpyAsync(&A->pinned[slot], cg.n_active, sizeof(int), hipMemcpyDeviceToHost, st));
+    FL_HIP(hipEventRecord(A->ev_poll[slot], st));
+    if (c >= 1) {
+      FL_HIP(hipEventSynchronize(A->ev_poll[1 - slot]));
+      if (A->pinned[1 - slot] == 0) break;
+    }
+  }
+  FL_HIP(hipStreamSynchronize(st));
+}
+
+template <typename... P>
+std::vector<double> make_key(P... v) {
+  return {static_cast<double>(v)...};
+}
+
+inline double pkey(const void* p) { return (double)(uintptr_t)p; }
+
+inline std::vector<double> sched_key(const fl::Schedule& s) {
+  return {(double)s.E_first, (double)s.E_mid, (double)s.E_c2c, (double)s.W_first,
+          (double)s.W_c2c, (double)s.LPB_mid};
+}
+
 // CG from x0 = 0 on A x = rhs until no right-hand side is active.  The
 // number of active right-hand sides is read back every `chunk` iterations
 // (one 4-byte copy); masked launches past convergence cost only launch time.
@@ -512,7 +617,12 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
     if (mixed < 0 || mixed > 2) return fail(FL_E_INVAL, "mixed must be 0, 1 or 2");
     if ((const void*)f == (const void*)u) return fail(FL_E_INVAL, "f and u must be distinct");
     set_device(A);
-    hipStream_t st = (hipStream_t)stream;
+    // work runs on the operator's own stream, ordered after `stream`
+    hipStream_t user = (hipStream_t)stream;
+    ensure_solver_stream(A);
+    hipStream_t st = A->solve_stream;
+    FL_HIP(hipEventRecord(A->ev_in, user));
+    FL_HIP(hipStreamWaitEvent(st, A->ev_in, 0));
     A->begin(st);
     const long nd = A->g.nd;
     const size_t v8 = (size_t)nrhs * nd * sizeof(double);
@@ -538,11 +648,25 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
     sum_squares(A, f, nrhs, co, f2, st);
     if (!mixed) {
       const fl::CgScalars cg = cg_view(A->cg.s, A->g, A->sc64, nrhs, maxiter, tol);
-      char* vb = (char*)A->vecs.get(3 * a8);
+      char* vb = (char*)A->vecs.get(4 * a8);
       double* r = (double*)vb;
       double* p = (double*)(vb + a8);
       double* q = (double*)(vb + 2 * a8);
-      cg_run<double>(A, A->sc64, A->lam64, A->tw64, f, u, r, p, q, nrhs, cg, nullptr, ws, st);
+      double* x = (double*)(vb + 3 * a8);
+      fl::fill_int(cg.n_active, 0, 1, st);
+      fl::cg_init<double>(A->g, f, x, r, p, nrhs, cg, nullptr, st);
+      const int chunk = 8;
+      std::vector<double> key = make_key(0, nrhs, chunk, maxiter, tol);
+      for (double v : {pkey(ws), pkey(vb), pkey(A->cg.mem.p), pkey(A->lam64)}) key.push_back(v);
+      for (double v : sched_key(A->sc64)) key.push_back(v);
+      chunk_loop(A, A->graph[0], key, (maxiter + 2) / chunk + 2, cg, st, [&]() {
+        for (int i = 0; i < chunk; ++i) {
+          fl::apply_passes<double>(A->g, A->sc64, A->lam64, A->tw64, nullptr, q, nrhs, ws, st,
+                                   fl::PM_CG, r, p, nullptr, &cg, cg.active);
+          fl::cg_update<double>(A->g, x, r, p, q, nrhs, cg, st);
+        }
+      });
+      FL_HIP(hipMemcpyAsync(u, x, v8, hipMemcpyDeviceToDevice, st));
       std::vector<double> rr(nrhs);
       FL_HIP(hipMemcpyAsync(iters.data(), cg.iters, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
       FL_HIP(hipMemcpyAsync(status.data(), cg.status, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -569,39 +693,45 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
       cg.tol2 = 0.0;  // the FP32 recursion never stops on its own residual
       const double delta2 = A->delta * A->delta;
       const int nb64 = fl::last_pass_blocks(A->g, A->sc64);
-      char* vb = (char*)A->vecs.get(a8 + 5 * a4);
+      char* vb = (char*)A->vecs.get(3 * a8 + 5 * a4);
       double* r64 = (double*)vb;
-      float* rhs32 = (float*)(vb + a8);
-      float* xlo = (float*)(vb + a8 + a4);
-      float* r32 = (float*)(vb + a8 + 2 * a4);
-      float* p32 = (float*)(vb + a8 + 3 * a4);
-      float* q32 = (float*)(vb + a8 + 4 * a4);
-      fl::fill_zero_bytes(u, v8, st);
+      double* xhi = (double*)(vb + a8);
+      double* fc = (double*)(vb + 2 * a8);
+      float* rhs32 = (float*)(vb + 3 * a8);
+      float* xlo = (float*)(vb + 3 * a8 + a4);
+      float* r32 = (float*)(vb + 3 * a8 + 2 * a4);
+      float* p32 = (float*)(vb + 3 * a8 + 3 * a4);
+      float* q32 = (float*)(vb + 3 * a8 + 4 * a4);
+      fl::fill_zero_bytes(xhi, v8, st);
+      FL_HIP(hipMemcpyAsync(fc, f, v8, hipMemcpyDeviceToDevice, st));
       fl::to_float(f, rhs32, (long)nrhs * nd, st);
       FL_HIP(hipMemcpyAsync(rr_last, f2, nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
       fl::fill_int(nupd, 0, nrhs, st);
       fl::fill_int(cg.n_active, 0, 1, st);
       fl::cg_init<float>(A->g, rhs32, xlo, r32, p32, nrhs, cg, nullptr, st);
       const int chunk = 8;
-      for (int done = 0; done < maxiter + chunk; done += chunk) {
+      std::vector<double> key = make_key(1, nrhs, chunk, maxiter, tol, A->delta);
+      for (double v : {pkey(ws), pkey(vb), pkey(A->cg.mem.p), pkey(A->cg_out.mem.p),
+                       pkey(A->outer_flags.p), pkey(A->lam32)})
+        key.push_back(v);
+      for (double v : sched_key(A->sc32)) key.push_back(v);
+      for (double v : sched_key(A->sc64)) key.push_back(v);
+      chunk_loop(A, A->graph[1], key, (maxiter + 2) / chunk + 2, cg, st, [&]() {
         for (int i = 0; i < chunk; ++i) {
           fl::apply_passes<float>(A->g, A->sc32, A->lam32, A->tw32, nullptr, q32, nrhs, ws, st,
                                   fl::PM_CG, r32, p32, nullptr, &cg, cg.active);
           fl::cg_update<float>(A->g, xlo, r32, p32, q32, nrhs, cg, st);
         }
-        fl::reliable_accum(A->g, u, xlo, nrhs, cg, rr_last, f2, delta2, tol * tol, trig, false,
+        fl::reliable_accum(A->g, xhi, xlo, nrhs, cg, rr_last, f2, delta2, tol * tol, trig, false,
                            st);
-        fl::apply_passes<double>(A->g, A->sc64, A->lam64, A->tw64, u, r64, nrhs, ws, st,
-                                 fl::PM_RESID, nullptr, nullptr, f, &co, trig);
+        fl::apply_passes<double>(A->g, A->sc64, A->lam64, A->tw64, xhi, r64, nrhs, ws, st,
+                                 fl::PM_RESID, nullptr, nullptr, fc, &co, trig);
         fl::reliable_replace(A->g, r64, r32, nrhs, cg, co.part_a, nb64, co.max_blocks, rr_last,
                              f2, tol * tol, trig, nupd, st);
-        int nact = 0;
-        FL_HIP(hipMemcpyAsync(&nact, cg.n_active, sizeof(int), hipMemcpyDeviceToHost, st));
-        FL_HIP(hipStreamSynchronize(st));
-        if (nact == 0) break;
-      }
+      });
       // fold what is left (RHS stopped by maxiter) and report true residuals
-      fl::reliable_accum(A->g, u, xlo, nrhs, cg, rr_last, f2, delta2, tol * tol, trig, true, st);
+      fl::reliable_accum(A->g, xhi, xlo, nrhs, cg, rr_last, f2, delta2, tol * tol, trig, true, st);
+      FL_HIP(hipMemcpyAsync(u, xhi, v8, hipMemcpyDeviceToDevice, st));
       fp64_residual(A, f, u, r64, nrhs, co, nullptr, rro, ws, st);
       FL_HIP(hipMemcpyAsync(iters.data(), cg.iters, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
       FL_HIP(hipMemcpyAsync(status.data(), cg.status, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -671,6 +801,7 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
       }
     }
     A->end(st);
+    FL_HIP(hipStreamWaitEvent(user, A->done, 0));
     fl_status worst = FL_OK;
     for (int o = 0; o < nrhs; ++o) {
       if (info) {

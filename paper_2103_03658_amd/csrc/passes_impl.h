@@ -20,6 +20,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <unordered_set>
+
 #include "fl_device.h"
 #include "fl_internal.h"
 
@@ -540,12 +543,22 @@ inline void check_launch(const char* what) {
   if (e != hipSuccess) throw Error(4, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-// Allow more than 64 KiB of dynamic LDS (gfx950 has 160 KiB per workgroup).
+// Allow up to the full 160 KiB of dynamic LDS of a gfx950 workgroup; set
+// once per kernel (so never inside a stream capture after the first run).
 template <typename K>
 inline void lds_attr(K kernel, size_t bytes) {
-  if (bytes > 65536)
-    FL_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  if (bytes <= 65536) return;
+  static std::mutex mu;
+  static std::unordered_set<const void*> done;
+  const void* key = reinterpret_cast<const void*>(kernel);
+  std::lock_guard<std::mutex> lk(mu);
+  if (done.count(key)) return;
+  hipFuncAttributes fa{};
+  FL_HIP(hipFuncGetAttributes(&fa, key));
+  const int avail = (int)kMaxLds - (int)fa.sharedSizeBytes;  // minus static LDS
+  if ((int)bytes > avail) throw Error(2, "LDS request exceeds the workgroup limit");
+  FL_HIP(hipFuncSetAttribute(key, hipFuncAttributeMaxDynamicSharedMemorySize, avail));
+  done.insert(key);
 }
 
 #define FL_LAUNCH(KERNEL, GRID, BLOCK, SH, ST, ...) \

@@ -45,7 +45,7 @@ def key(op, nrhs, fp32):
 
 
 def _lds_ok(M, E, W, fp32):
-    return W * (M // E) <= 512 and W * 2 * (M + M // E) * (4 if fp32 else 8) <= 160 * 1024
+    return W * (M // E) <= 512 and W * 2 * (M + M // E) * (4 if fp32 else 8) <= 159 * 1024
 
 
 def candidates(M, fp32):

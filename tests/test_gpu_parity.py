@@ -278,3 +278,23 @@ def test_mixed_maxiter_reports_noconv():
     fn = f.cpu().numpy()[0]
     rel = np.linalg.norm(fn - oracle.apply(G, u.cpu().numpy()[0])) / np.linalg.norm(fn)
     assert abs(rel - info[0]["relres_true"]) <= 1e-6 * rel
+
+
+@pytest.mark.parametrize("mixed", [0, 1])
+def test_graph_replays_match_eager(mixed):
+    """Captured CG chunks replayed several times, with eager solves in
+    between, give the same bits as launching every kernel directly."""
+    op = make_op(2, 1.3, 2, 32)
+    f = torch.from_numpy(inputs.uniform_rhs(2, 32, 2, seed=31)).cuda()
+    op.set_graphs(False)
+    ue, ie = op.solve(f, tol=1e-10, mixed=mixed)
+    op.set_graphs(True)
+    for rep in range(3):
+        ug, ig = op.solve(f, tol=1e-10, mixed=mixed)      # capture, then replays
+        torch.cuda.synchronize()
+        assert torch.equal(ug, ue), rep
+        assert [i["iters"] for i in ig] == [i["iters"] for i in ie]
+        op.set_graphs(False)
+        ux, _ = op.solve(f, tol=1e-10, mixed=mixed)        # eager work in between
+        assert torch.equal(ux, ue)
+        op.set_graphs(True)
