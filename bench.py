@@ -51,7 +51,33 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch schedule")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only time the FFT-matvec kernels (for profiler runs)")
+    ap.add_argument("--serve-requests", type=int, default=512,
+                    help="requests of the serving stream (Poisson arrivals at 200/s; the full "
+                         "stream is 4096; 0: skip)")
+    ap.add_argument("--serve-workers", type=int, default=4)
+    ap.add_argument("--serve-only", action="store_true")
     return ap.parse_args()
+
+
+def run_serving(n_requests, workers, tol):
+    """Serving stream: d = 2, n in {63,127,255,511}, alpha ~ U(0.2, 1.9)
+    rounded to 0.01, degree in {0,1,2}, 1-8 U[-1,1] right-hand sides,
+    Poisson arrivals at 200 requests/s, mixed-precision solves to tol."""
+    import torch
+    from paper_2103_03658_amd import inputs
+    from paper_2103_03658_amd.serve import Request, Server
+    spec = inputs.request_stream(n_requests, rate=200.0, seed=0)
+    reqs = [Request(r["id"], 2, r["N"], r["alpha"], r["degree"],
+                    torch.from_numpy(inputs.request_rhs(r)).cuda(), t_arrive=r["t_arrive"])
+            for r in spec]
+    torch.cuda.synchronize()
+    srv = Server(workers=workers, tol=tol, mixed=1)
+    st = srv.run(reqs, realtime=True)
+    st["stream"] = (f"{n_requests} requests, Poisson arrivals at 200/s, d=2, "
+                    "n in {63,127,255,511} (p=.4/.3/.2/.1), alpha~U(0.2,1.9) rounded to 0.01, "
+                    "degree in {0,1,2}, 1-8 U[-1,1] RHS each, FP32 CG + FP64 reliable updates "
+                    f"to {tol:g}, {workers} worker streams")
+    return st
 
 
 def pass_bytes(d, N, nrhs, sr):
@@ -117,6 +143,10 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.serve_only:
+        print(json.dumps({"serving": run_serving(args.serve_requests, args.serve_workers,
+                                                 args.tol)}))
+        return
     N, p = args.N, args.degree
     alphas = [0.5, 1.0, 1.5]
     nrhs = 1 + args.nrand
@@ -226,6 +256,10 @@ def main():
             "matvec_GBs_f64": sum(by64) / (sum(ms64) * 1e-3) / 1e9,
             "matvec_ms_f32": sum(ms), "matvec_ms_f64": sum(ms64)}
 
+    serving = None
+    if args.serve_requests > 0:
+        serving = run_serving(args.serve_requests, args.serve_workers, args.tol)
+
     cpu = None
     if args.cpu_budget > 0:
         it_ref = int(np.median(fp64["iters"][1.0])) if fp64 else 150
@@ -247,8 +281,8 @@ def main():
         "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
         "latency_unit": "ms per batched solve (all RHS of the batch complete)",
         "max_relres_true": max_relres, "iters": iters, "outer_iters": outers,
-        "setup_s": setup_s, "schedule": sched, "fp64_single": fp64, "roofline": roof,
-        "cpu_baseline": cpu,
+        "setup_s": setup_s, "schedule": sched, "fp64_single": fp64, "serving": serving,
+        "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(res))
 

@@ -285,7 +285,9 @@ fl_status fl_weights(int d, double alpha, int degree, double h, int kernel, doub
 void fl_destroy(fl_op A) {
   if (!A) return;
   hipSetDevice(A->device);
-  hipDeviceSynchronize();
+  // wait for this handle's own work only (other streams keep running)
+  if (A->solve_stream) hipStreamSynchronize(A->solve_stream);
+  if (A->used && A->done) hipEventSynchronize(A->done);
   if (A->G) hipFree(A->G);
   if (A->lam64) hipFree(A->lam64);
   if (A->lam32) hipFree(A->lam32);

@@ -2,6 +2,8 @@
 rejects invalid arguments before touching a device (CPU only)."""
 
 import ctypes
+
+import numpy as np
 import os
 import re
 
@@ -76,3 +78,35 @@ def test_error_raises_in_binding():
     with pytest.raises(fl.FlError) as ei:
         fl.Operator(2, 1.0, 2, N=9)
     assert ei.value.status == _lib.FL_E_INVAL
+
+
+def test_request_stream_is_seeded_and_shaped():
+    from paper_2103_03658_amd import inputs
+    a = inputs.request_stream(256, seed=0)
+    b = inputs.request_stream(256, seed=0)
+    assert a == b
+    ns = [r["N"] - 1 for r in a]
+    assert set(ns) <= {63, 127, 255, 511}
+    assert all(0.2 - 1e-12 <= r["alpha"] <= 1.9 + 1e-12 and r["degree"] in (0, 1, 2) and 1 <= r["nrhs"] <= 8
+               for r in a)
+    t = [r["t_arrive"] for r in a]
+    assert all(x < y for x, y in zip(t, t[1:]))
+    rate = len(t) / t[-1]
+    assert 150 < rate < 260                         # Poisson arrivals at 200 / s
+    f = inputs.request_rhs(a[0])
+    assert f.shape == (a[0]["nrhs"], ns[0], ns[0]) and np.abs(f).max() <= 1
+
+
+def test_manufactured_rhs_matches_closed_form():
+    """The 2D benchmark right-hand side inside the unit disk is the closed
+    form of (-Delta)^{alpha/2} (1-|x|^2)_+^{1+alpha/2}."""
+    import oracle.exact as ex
+    from paper_2103_03658_amd import inputs
+    for alpha in (0.5, 1.0, 1.5):
+        f = inputs.manufactured_rhs_disk(32, alpha)
+        X0, X1 = inputs.interior_coords(2, 32)
+        r2 = X0 ** 2 + X1 ** 2
+        inside = r2 < 1
+        ref = ex.frac_lap_ball_power(r2[inside], 1 + alpha / 2, alpha, 2)
+        np.testing.assert_allclose(f[inside], ref, rtol=1e-13)
+        assert (f[~inside] == 0).all()
