@@ -114,7 +114,8 @@ fl_status fl_apply(fl_op A, const void *u, void *y, int nrhs, int fp32, void *st
 
 /*
  * fl_solve -- solve A u = f for nrhs right-hand sides by conjugate gradients
- * (A is symmetric positive definite, Sec. 2.2).
+ * (A is symmetric positive definite, Sec. 2.2), circulant-preconditioned by
+ * default (fl_set_preconditioner).
  *   f       device, nrhs * n^d doubles
  *   g       exterior data; must be NULL (g = 0).  Non-NULL: FL_E_UNSUPPORTED
  *   tol     stop when ||r||_2 <= tol ||f||_2 (per right-hand side), tol > 0
@@ -174,6 +175,19 @@ fl_status fl_get_schedule(fl_op A, int fp32, int *sched6);
  */
 fl_status fl_profile_apply(fl_op A, const void *u, void *y, int nrhs, int fp32, int reps,
                            void *stream, double *ms_per_pass, int max_passes, int *n_passes);
+
+/*
+ * Preconditioning of fl_solve: kind 1 (default) uses P = R C^{-1} R^T, the
+ * restriction to the n^d interior of the inverse of the embedding circulant
+ * C (symbol 1 / max(lambda-hat, 1e-12 max lambda-hat), so P is symmetric
+ * positive definite); kind 0 is plain CG.  Either way the stopping rule is
+ * the relative residual ||r||_2 <= tol ||f||_2.  FL_E_INVAL for other kinds.
+ */
+fl_status fl_set_preconditioner(fl_op A, int kind);
+
+/* y = P u for nrhs right-hand sides (same layout, precision and stream
+ * rules as fl_apply).  Test hook for the preconditioner. */
+fl_status fl_apply_precond(fl_op A, const void *u, void *y, int nrhs, int fp32, void *stream);
 
 /* Replay CG iteration chunks from captured HIP graphs (enable = 1, the
  * default) or launch every kernel directly (enable = 0).  Results are the

@@ -42,7 +42,7 @@ from .constants import c_dalpha, far_field_T, K_ball
 from .weights import weights
 from .operator import (origin_rule, coefficients, generator, dense_matrix,
                        apply_dense, apply_bttb, apply, apply_rows,
-                       embed_generator, symbol,
+                       embed_generator, symbol, precond_apply,
                        exterior_b_1d, exterior_b_2d, grid_points)
 from .solve import solve_cholesky, solve_cg
 from . import exact
@@ -50,6 +50,6 @@ from . import exact
 __all__ = [
     "c_dalpha", "far_field_T", "K_ball", "weights", "origin_rule",
     "coefficients", "generator", "dense_matrix", "apply_dense", "apply_bttb",
-    "apply", "apply_rows", "embed_generator", "symbol", "exterior_b_1d", "exterior_b_2d",
+    "apply", "apply_rows", "embed_generator", "symbol", "precond_apply", "exterior_b_1d", "exterior_b_2d",
     "grid_points", "solve_cholesky", "solve_cg", "exact",
 ]

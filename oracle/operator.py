@@ -205,6 +205,22 @@ def symbol(G):
     return lam.real / c.size, float(np.abs(lam.imag).max() / c.size)
 
 
+def precond_apply(G, v, floor_rel=1e-12):
+    """y = R C^{-1} R^T v: the preconditioner the solver uses (not part of
+    the paper, whose solver is unspecified).  C is the circulant embedding of
+    A (symbol lambda-hat), floored at floor_rel * max lambda-hat so that it
+    is positive definite; R restricts to the n^d interior."""
+    d = G.ndim
+    n = G.shape[0] - 2
+    M = 2 * (G.shape[0] - 1)
+    lam, _ = symbol(G)
+    lam = np.maximum(lam, floor_rel * lam.max())
+    z = np.zeros((M,) * d)
+    z[(slice(0, n),) * d] = v
+    y = np.fft.ifftn(np.fft.fftn(z) / (lam * M ** d)).real
+    return y[(slice(0, n),) * d]
+
+
 # ---------------------------------------------------------------------------
 # exterior data g != 0 (the b term of the paper)
 # ---------------------------------------------------------------------------

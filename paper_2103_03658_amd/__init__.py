@@ -133,6 +133,22 @@ class Operator:
         check(self._lib.fl_set_schedule(self._h, int(bool(fp32)), e_first, e_mid, e_c2c,
                                         w_first, w_c2c, lpb_mid))
 
+    def set_preconditioner(self, kind):
+        """1: circulant preconditioner (default), 0: plain CG."""
+        check(self._lib.fl_set_preconditioner(self._h, int(kind)))
+
+    def apply_precond(self, u, out=None, stream=None):
+        """y = P u (restricted inverse of the embedding circulant)."""
+        import torch
+        nrhs = self._nrhs(u)
+        if out is None:
+            out = torch.empty_like(u)
+        check(self._lib.fl_apply_precond(self._h, ctypes.c_void_p(u.data_ptr()),
+                                         ctypes.c_void_p(out.data_ptr()), nrhs,
+                                         1 if u.dtype == torch.float32 else 0,
+                                         _stream_ptr(stream)))
+        return out
+
     def set_graphs(self, enable):
         check(self._lib.fl_set_graphs(self._h, int(bool(enable))))
 

@@ -82,7 +82,7 @@ struct CgState {
     const size_t nd8 = (size_t)nrhs * sizeof(double);
     const size_t ni4 = (size_t)nrhs * sizeof(int);
     const size_t part = (size_t)nrhs * kMaxBlocks * sizeof(double);
-    const size_t total = 4 * nd8 + 3 * ni4 + sizeof(int) + 2 * part + 10 * 256;
+    const size_t total = 5 * nd8 + 3 * ni4 + sizeof(int) + 3 * part + 12 * 256;
     char* b = (char*)mem.get(total);
     auto take = [&](size_t n) {
       char* r = b;
@@ -94,12 +94,14 @@ struct CgState {
     s.rr_prev = (double*)take(nd8);
     s.thresh2 = (double*)take(nd8);
     s.alpha = (double*)take(nd8);
+    s.res2 = (double*)take(nd8);
     s.active = (int*)take(ni4);
     s.iters = (int*)take(ni4);
     s.status = (int*)take(ni4);
     s.n_active = (int*)take(sizeof(int));
     s.part_a = (double*)take(part);
     s.part_b = (double*)take(part);
+    s.part_c = (double*)take(part);
     s.max_blocks = kMaxBlocks;
     fl::fill_zero_bytes(base, (size_t)(b - base), st);
     cap = nrhs;
@@ -128,6 +130,9 @@ struct fl_op_s {
   double* G = nullptr;
   double* lam64 = nullptr;
   float* lam32 = nullptr;
+  double* linv64 = nullptr;   // preconditioner symbol 1/lambda-hat (floored)
+  float* linv32 = nullptr;
+  int precond = 1;            // 1: circulant-preconditioned CG
   const void* tw64 = nullptr;
   const void* tw32 = nullptr;
   fl::Schedule sc64{}, sc32{};
@@ -264,9 +269,17 @@ fl_status fl_weights(int d, double alpha, int degree, double h, int kernel, doub
       A->G = (double*)dmalloc((size_t)nf * sizeof(double));
       A->lam64 = (double*)dmalloc((size_t)nf * sizeof(double));
       A->lam32 = (float*)dmalloc((size_t)nf * sizeof(float));
+      A->linv64 = (double*)dmalloc((size_t)nf * sizeof(double));
+      A->linv32 = (float*)dmalloc((size_t)nf * sizeof(float));
       fl::GenParams gp{d, degree, N, kernel, alpha, A->h, A->lambda, A->c};
       fl::build_generator(gp, A->G, st);
       fl::build_symbol(A->g, A->G, A->lam64, A->lam32, st);
+      {
+        double* scr = (double*)dmalloc(256);
+        fl::build_inverse_symbol(A->g, A->lam64, nf, A->linv64, A->linv32, scr, st);
+        FL_HIP(hipStreamSynchronize(st));
+        hipFree(scr);
+      }
       A->tw64 = fl::twiddles(M, false, st);
       A->tw32 = fl::twiddles(M, true, st);
       A->sc64 = fl::default_schedule(A->g, false);
@@ -291,6 +304,8 @@ void fl_destroy(fl_op A) {
   if (A->G) hipFree(A->G);
   if (A->lam64) hipFree(A->lam64);
   if (A->lam32) hipFree(A->lam32);
+  if (A->linv64) hipFree(A->linv64);
+  if (A->linv32) hipFree(A->linv32);
   A->ws.release();
   A->vecs.release();
   A->cg.mem.release();
@@ -372,6 +387,36 @@ fl_status fl_set_schedule(fl_op A, int fp32, int e_first, int e_mid, int e_c2c, 
     if (lpb_mid > 0) s.LPB_mid = lpb_mid;
     check_schedule(A->g, s, fp32 != 0);
     (fp32 ? A->sc32 : A->sc64) = s;
+    return FL_OK;
+  });
+}
+
+fl_status fl_set_preconditioner(fl_op A, int kind) {
+  if (!A) return fail(FL_E_INVAL, "null handle");
+  if (kind != 0 && kind != 1) return fail(FL_E_INVAL, "kind must be 0 or 1");
+  A->precond = kind;
+  return FL_OK;
+}
+
+fl_status fl_apply_precond(fl_op A, const void* u, void* y, int nrhs, int fp32, void* stream) {
+  return guarded([&]() -> fl_status {
+    if (!A) return fail(FL_E_INVAL, "null handle");
+    if (!u || !y) return fail(FL_E_INVAL, "null vector");
+    if (u == y) return fail(FL_E_INVAL, "u and y must be distinct");
+    if (nrhs < 1) return fail(FL_E_INVAL, "nrhs must be >= 1");
+    set_device(A);
+    hipStream_t st = (hipStream_t)stream;
+    A->begin(st);
+    void* ws = A->ws.get(fl::apply_workspace_bytes(A->g, nrhs, fp32 != 0));
+    if (fp32)
+      fl::apply_passes<float>(A->g, A->sc32, A->linv32, A->tw32, (const float*)u, (float*)y,
+                              nrhs, ws, st, fl::PM_PLAIN, nullptr, nullptr, nullptr, nullptr,
+                              nullptr);
+    else
+      fl::apply_passes<double>(A->g, A->sc64, A->linv64, A->tw64, (const double*)u, (double*)y,
+                               nrhs, ws, st, fl::PM_PLAIN, nullptr, nullptr, nullptr, nullptr,
+                               nullptr);
+    A->end(st);
     return FL_OK;
   });
 }
@@ -476,13 +521,15 @@ namespace {
 
 // Per-call view of the CG state: block counts, iteration cap, tolerance.
 fl::CgScalars cg_view(const fl::CgScalars& base, const fl::Geometry& g, const fl::Schedule& sc,
-                      int nrhs, int maxiter, double tol) {
+                      int nrhs, int maxiter, double tol, int precond) {
   fl::CgScalars c = base;
   c.nb_a = fl::last_pass_blocks(g, sc);
-  c.nb_b = fl::vec_blocks(g.nd, nrhs);
-  if (c.nb_a > c.max_blocks || c.nb_b > c.max_blocks)
+  c.nb_c = fl::vec_blocks(g.nd, nrhs);
+  c.nb_b = precond ? c.nb_a : c.nb_c;   // r.z from the preconditioner's last pass
+  if (c.nb_a > c.max_blocks || c.nb_c > c.max_blocks)
     throw Error(FL_E_UNSUPPORTED, "too many blocks for the reduction buffers");
   c.maxiter = maxiter;
+  c.precond = precond;
   c.tol2 = tol * tol;
   return c;
 }
@@ -560,25 +607,51 @@ inline std::vector<double> sched_key(const fl::Schedule& s) {
           (double)s.W_c2c, (double)s.LPB_mid};
 }
 
+// z = P r (restricted inverse of the embedding circulant) and partials of r.z.
+template <typename T>
+void precond_apply(fl_op A, const fl::Schedule& sc, const T* linv, const void* tw, const T* r,
+                   T* z, int nrhs, void* ws, const fl::CgScalars& cg, const int* active,
+                   hipStream_t st) {
+  fl::apply_passes<T>(A->g, sc, linv, tw, r, z, nrhs, ws, st, fl::PM_DOT, nullptr, nullptr,
+                      nullptr, &cg, active);
+}
+
+// CG start: x = 0, r = rhs, p = 0; preconditioned: z = P r.
+template <typename T>
+void cg_start(fl_op A, const fl::Schedule& sc, const T* linv, const void* tw, const T* rhs,
+              T* x, T* r, T* p, T* z, int nrhs, const fl::CgScalars& cg,
+              const int* outer_active, void* ws, hipStream_t st) {
+  fl::fill_int(cg.n_active, 0, 1, st);
+  fl::cg_init<T>(A->g, rhs, x, r, p, nrhs, cg, outer_active, st);
+  if (cg.precond) precond_apply<T>(A, sc, linv, tw, r, z, nrhs, ws, cg, cg.active, st);
+}
+
+// One CG (or preconditioned CG) iteration for all active right-hand sides.
+template <typename T>
+void cg_iteration(fl_op A, const fl::Schedule& sc, const T* lam, const T* linv, const void* tw,
+                  T* x, T* r, T* p, T* q, T* z, int nrhs, const fl::CgScalars& cg, void* ws,
+                  hipStream_t st) {
+  fl::apply_passes<T>(A->g, sc, lam, tw, nullptr, q, nrhs, ws, st, fl::PM_CG,
+                      cg.precond ? z : r, p, nullptr, &cg, cg.active);
+  fl::cg_update<T>(A->g, x, r, p, q, nrhs, cg, st);
+  if (cg.precond) precond_apply<T>(A, sc, linv, tw, r, z, nrhs, ws, cg, cg.active, st);
+}
+
 // CG from x0 = 0 on A x = rhs until no right-hand side is active.  The
 // number of active right-hand sides is read back every `chunk` iterations
 // (one 4-byte copy); masked launches past convergence cost only launch time.
 template <typename T>
-void cg_run(fl_op A, const fl::Schedule& sc, const T* lam, const void* tw, const T* rhs, T* x,
-            T* r, T* p, T* q, int nrhs, const fl::CgScalars& cg, const int* outer_active,
-            void* ws, hipStream_t st) {
-  fl::fill_int(cg.n_active, 0, 1, st);
-  fl::cg_init<T>(A->g, rhs, x, r, p, nrhs, cg, outer_active, st);
+void cg_run(fl_op A, const fl::Schedule& sc, const T* lam, const T* linv, const void* tw,
+            const T* rhs, T* x, T* r, T* p, T* q, T* z, int nrhs, const fl::CgScalars& cg,
+            const int* outer_active, void* ws, hipStream_t st) {
+  cg_start<T>(A, sc, linv, tw, rhs, x, r, p, z, nrhs, cg, outer_active, ws, st);
   int done = 0;
   int chunk = 8;
   const int cap = cg.maxiter + 2;
   while (done < cap) {
     const int k = std::min(chunk, cap - done);
-    for (int i = 0; i < k; ++i) {
-      fl::apply_passes<T>(A->g, sc, lam, tw, nullptr, q, nrhs, ws, st, fl::PM_CG, r, p, nullptr,
-                          &cg, cg.active);
-      fl::cg_update<T>(A->g, x, r, p, q, nrhs, cg, st);
-    }
+    for (int i = 0; i < k; ++i)
+      cg_iteration<T>(A, sc, lam, linv, tw, x, r, p, q, z, nrhs, cg, ws, st);
     done += k;
     int nact = 0;
     FL_HIP(hipMemcpyAsync(&nact, cg.n_active, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -648,31 +721,30 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
     void* ws = A->ws.get(fl::apply_workspace_bytes(A->g, nrhs, false));
     std::vector<double> hf2(nrhs), hrr(nrhs);
     sum_squares(A, f, nrhs, co, f2, st);
+    const int pc = A->precond;
     if (!mixed) {
-      const fl::CgScalars cg = cg_view(A->cg.s, A->g, A->sc64, nrhs, maxiter, tol);
-      char* vb = (char*)A->vecs.get(4 * a8);
+      const fl::CgScalars cg = cg_view(A->cg.s, A->g, A->sc64, nrhs, maxiter, tol, pc);
+      char* vb = (char*)A->vecs.get(5 * a8);
       double* r = (double*)vb;
       double* p = (double*)(vb + a8);
       double* q = (double*)(vb + 2 * a8);
       double* x = (double*)(vb + 3 * a8);
-      fl::fill_int(cg.n_active, 0, 1, st);
-      fl::cg_init<double>(A->g, f, x, r, p, nrhs, cg, nullptr, st);
+      double* z = (double*)(vb + 4 * a8);
+      cg_start<double>(A, A->sc64, A->linv64, A->tw64, f, x, r, p, z, nrhs, cg, nullptr, ws, st);
       const int chunk = 8;
-      std::vector<double> key = make_key(0, nrhs, chunk, maxiter, tol);
+      std::vector<double> key = make_key(0, nrhs, chunk, maxiter, tol, pc);
       for (double v : {pkey(ws), pkey(vb), pkey(A->cg.mem.p), pkey(A->lam64)}) key.push_back(v);
       for (double v : sched_key(A->sc64)) key.push_back(v);
       chunk_loop(A, A->graph[0], key, (maxiter + 2) / chunk + 2, cg, st, [&]() {
-        for (int i = 0; i < chunk; ++i) {
-          fl::apply_passes<double>(A->g, A->sc64, A->lam64, A->tw64, nullptr, q, nrhs, ws, st,
-                                   fl::PM_CG, r, p, nullptr, &cg, cg.active);
-          fl::cg_update<double>(A->g, x, r, p, q, nrhs, cg, st);
-        }
+        for (int i = 0; i < chunk; ++i)
+          cg_iteration<double>(A, A->sc64, A->lam64, A->linv64, A->tw64, x, r, p, q, z, nrhs, cg,
+                               ws, st);
       });
       FL_HIP(hipMemcpyAsync(u, x, v8, hipMemcpyDeviceToDevice, st));
       std::vector<double> rr(nrhs);
       FL_HIP(hipMemcpyAsync(iters.data(), cg.iters, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
       FL_HIP(hipMemcpyAsync(status.data(), cg.status, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
-      FL_HIP(hipMemcpyAsync(rr.data(), cg.rr_cur, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+      FL_HIP(hipMemcpyAsync(rr.data(), cg.res2, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
       // true residual with an FP64 product (into q)
       fp64_residual(A, f, u, q, nrhs, co, nullptr, rro, ws, st);
       FL_HIP(hipMemcpyAsync(hrr.data(), rro, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -688,14 +760,14 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
       // FP32 CG with FP64 reliable updates: the FP32 recursion runs on a
       // correction xlo; every `chunk` iterations each RHS whose FP32 residual
       // fell below delta^2 of its value at the last update (or below the
-      // tolerance) folds xlo into the FP64 iterate u, recomputes r = f - A u
+      // tolerance) folds xlo into the FP64 iterate, recomputes r = f - A u
       // in FP64, stops if ||r|| <= tol ||f||, and otherwise continues from
       // r (rounded to FP32) with the same search direction.
-      fl::CgScalars cg = cg_view(A->cg.s, A->g, A->sc32, nrhs, maxiter, tol);
+      fl::CgScalars cg = cg_view(A->cg.s, A->g, A->sc32, nrhs, maxiter, tol, pc);
       cg.tol2 = 0.0;  // the FP32 recursion never stops on its own residual
       const double delta2 = A->delta * A->delta;
       const int nb64 = fl::last_pass_blocks(A->g, A->sc64);
-      char* vb = (char*)A->vecs.get(3 * a8 + 5 * a4);
+      char* vb = (char*)A->vecs.get(3 * a8 + 6 * a4);
       double* r64 = (double*)vb;
       double* xhi = (double*)(vb + a8);
       double* fc = (double*)(vb + 2 * a8);
@@ -704,32 +776,33 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
       float* r32 = (float*)(vb + 3 * a8 + 2 * a4);
       float* p32 = (float*)(vb + 3 * a8 + 3 * a4);
       float* q32 = (float*)(vb + 3 * a8 + 4 * a4);
+      float* z32 = (float*)(vb + 3 * a8 + 5 * a4);
       fl::fill_zero_bytes(xhi, v8, st);
       FL_HIP(hipMemcpyAsync(fc, f, v8, hipMemcpyDeviceToDevice, st));
       fl::to_float(f, rhs32, (long)nrhs * nd, st);
       FL_HIP(hipMemcpyAsync(rr_last, f2, nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
       fl::fill_int(nupd, 0, nrhs, st);
-      fl::fill_int(cg.n_active, 0, 1, st);
-      fl::cg_init<float>(A->g, rhs32, xlo, r32, p32, nrhs, cg, nullptr, st);
+      cg_start<float>(A, A->sc32, A->linv32, A->tw32, rhs32, xlo, r32, p32, z32, nrhs, cg,
+                      nullptr, ws, st);
       const int chunk = 8;
-      std::vector<double> key = make_key(1, nrhs, chunk, maxiter, tol, A->delta);
+      std::vector<double> key = make_key(1, nrhs, chunk, maxiter, tol, A->delta, pc);
       for (double v : {pkey(ws), pkey(vb), pkey(A->cg.mem.p), pkey(A->cg_out.mem.p),
                        pkey(A->outer_flags.p), pkey(A->lam32)})
         key.push_back(v);
       for (double v : sched_key(A->sc32)) key.push_back(v);
       for (double v : sched_key(A->sc64)) key.push_back(v);
       chunk_loop(A, A->graph[1], key, (maxiter + 2) / chunk + 2, cg, st, [&]() {
-        for (int i = 0; i < chunk; ++i) {
-          fl::apply_passes<float>(A->g, A->sc32, A->lam32, A->tw32, nullptr, q32, nrhs, ws, st,
-                                  fl::PM_CG, r32, p32, nullptr, &cg, cg.active);
-          fl::cg_update<float>(A->g, xlo, r32, p32, q32, nrhs, cg, st);
-        }
+        for (int i = 0; i < chunk; ++i)
+          cg_iteration<float>(A, A->sc32, A->lam32, A->linv32, A->tw32, xlo, r32, p32, q32, z32,
+                              nrhs, cg, ws, st);
         fl::reliable_accum(A->g, xhi, xlo, nrhs, cg, rr_last, f2, delta2, tol * tol, trig, false,
                            st);
         fl::apply_passes<double>(A->g, A->sc64, A->lam64, A->tw64, xhi, r64, nrhs, ws, st,
                                  fl::PM_RESID, nullptr, nullptr, fc, &co, trig);
         fl::reliable_replace(A->g, r64, r32, nrhs, cg, co.part_a, nb64, co.max_blocks, rr_last,
                              f2, tol * tol, trig, nupd, st);
+        if (pc) precond_apply<float>(A, A->sc32, A->linv32, A->tw32, r32, z32, nrhs, ws, cg, trig,
+                                     st);
       });
       // fold what is left (RHS stopped by maxiter) and report true residuals
       fl::reliable_accum(A->g, xhi, xlo, nrhs, cg, rr_last, f2, delta2, tol * tol, trig, true, st);
@@ -749,14 +822,15 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
       }
     } else {
       // FP64 residual and iterate; FP32 CG on A delta = r / ||r|| (inner_tol)
-      const fl::CgScalars cg = cg_view(A->cg.s, A->g, A->sc32, nrhs, maxiter, A->inner_tol);
-      char* vb = (char*)A->vecs.get(a8 + 5 * a4);
+      const fl::CgScalars cg = cg_view(A->cg.s, A->g, A->sc32, nrhs, maxiter, A->inner_tol, pc);
+      char* vb = (char*)A->vecs.get(a8 + 6 * a4);
       double* r64 = (double*)vb;
       float* rhs32 = (float*)(vb + a8);
       float* d32 = (float*)(vb + a8 + a4);
       float* r32 = (float*)(vb + a8 + 2 * a4);
       float* p32 = (float*)(vb + a8 + 3 * a4);
       float* q32 = (float*)(vb + a8 + 4 * a4);
+      float* z32 = (float*)(vb + a8 + 5 * a4);
       fl::fill_zero_bytes(u, v8, st);
       FL_HIP(hipMemcpyAsync(r64, f, v8, hipMemcpyDeviceToDevice, st));
       FL_HIP(hipMemcpyAsync(rro, f2, nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -781,8 +855,8 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
         }
         FL_HIP(hipMemcpyAsync(oact, hact.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
         fl::refine_scale(r64, rhs32, rro, scale, nd, nrhs, oact, st);
-        cg_run<float>(A, A->sc32, A->lam32, A->tw32, rhs32, d32, r32, p32, q32, nrhs, cg, oact,
-                      ws, st);
+        cg_run<float>(A, A->sc32, A->lam32, A->linv32, A->tw32, rhs32, d32, r32, p32, q32, z32,
+                      nrhs, cg, oact, ws, st);
         fl::refine_axpy(u, d32, scale, nd, nrhs, oact, st);
         fp64_residual(A, f, u, r64, nrhs, co, oact, rro, ws, st);
         FL_HIP(hipMemcpyAsync(hit.data(), cg.iters, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));

@@ -43,7 +43,7 @@ __global__ void __launch_bounds__(VT) k_cg_init(const T* rhs, T* x, T* r, T* p, 
   }
   const double blk = block_sum(acc, red);
   if (threadIdx.x == 0) {
-    cg.part_b[(long)o * cg.max_blocks + blockIdx.x] = blk;
+    (cg.precond ? cg.part_c : cg.part_b)[(long)o * cg.max_blocks + blockIdx.x] = blk;
     if (blockIdx.x == 0) {
       cg.iters[o] = 0;
       cg.status[o] = 0;
@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(VT) k_cg_update(T* x, T* r, const T* p, const 
   }
   const double blk = block_sum(acc, red);
   if (threadIdx.x == 0) {
-    cg.part_b[(long)o * cg.max_blocks + blockIdx.x] = blk;
+    (cg.precond ? cg.part_c : cg.part_b)[(long)o * cg.max_blocks + blockIdx.x] = blk;
     if (blockIdx.x == 0) {
       cg.rr_prev[o] = rr;
       cg.iters[o] = cg.iters[o] + 1;
@@ -169,7 +169,8 @@ __global__ void __launch_bounds__(VT) k_reliable_accum(double* xhi, float* xlo, 
       if (blockIdx.x == 0 && threadIdx.x == 0) trig[o] = 0;
       return;
     }
-    const double rr = sum_partials(cg.part_b + (long)o * cg.max_blocks, cg.nb_b, red);
+    const double rr = sum_partials((cg.precond ? cg.part_c : cg.part_b) + (long)o * cg.max_blocks,
+                                   cg.nb_c, red);
     t = !(rr >= delta2 * rr_last[o]) || rr <= tol2 * f2[o];
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) trig[o] = t ? 1 : 0;
@@ -206,6 +207,10 @@ __global__ void __launch_bounds__(VT) k_reliable_replace(const double* r64, floa
     }
     return;
   }
+  // Preconditioned: within one check interval the FP32 recursion reaches
+  // FP32 accuracy, so the old search direction no longer matches the
+  // replaced residual; restart it (the next beta is rho / inf = 0).
+  if (lead && cg.precond) cg.rr_prev[o] = INFINITY;
   const long base = (long)o * nd;
   double acc = 0.0;
   for (long i = (long)blockIdx.x * VT + threadIdx.x; i < nd; i += (long)gridDim.x * VT) {
@@ -214,7 +219,8 @@ __global__ void __launch_bounds__(VT) k_reliable_replace(const double* r64, floa
     acc += (double)v * (double)v;
   }
   const double blk = block_sum(acc, red);
-  if (threadIdx.x == 0) cg.part_b[(long)o * cg.max_blocks + blockIdx.x] = blk;
+  if (threadIdx.x == 0)
+    (cg.precond ? cg.part_c : cg.part_b)[(long)o * cg.max_blocks + blockIdx.x] = blk;
 }
 
 }  // namespace
@@ -230,7 +236,7 @@ void to_float(const double* src, float* dst, long n, hipStream_t st) {
 void reliable_accum(const Geometry& g, double* xhi, float* xlo, int nrhs, const CgScalars& cg,
                     const double* rr_last, const double* f2, double delta2, double tol2,
                     int* trig, bool force, hipStream_t st) {
-  dim3 grid(cg.nb_b, nrhs);
+  dim3 grid(cg.nb_c, nrhs);
   hipLaunchKernelGGL(k_reliable_accum, grid, dim3(VT), 0, st, xhi, xlo, g.nd, cg, rr_last, f2,
                      delta2, tol2, trig, force ? 1 : 0);
   check_launch("reliable accumulate");
@@ -240,7 +246,7 @@ void reliable_replace(const Geometry& g, const double* r64, float* r32, int nrhs
                       const CgScalars& cg, const double* part64, int nb64, int mb64,
                       double* rr_last, const double* f2, double tol2, const int* trig,
                       int* nupd, hipStream_t st) {
-  dim3 grid(cg.nb_b, nrhs);
+  dim3 grid(cg.nb_c, nrhs);
   hipLaunchKernelGGL(k_reliable_replace, grid, dim3(VT), 0, st, r64, r32, g.nd, cg, part64, nb64,
                      mb64, rr_last, f2, tol2, trig, nupd);
   check_launch("reliable replace");
@@ -259,7 +265,7 @@ int vec_blocks(long nd, int nrhs) {
 template <typename T>
 void cg_init(const Geometry& g, const T* rhs, T* x, T* r, T* p, int nrhs, const CgScalars& cg,
              const int* outer_active, hipStream_t st) {
-  dim3 grid(cg.nb_b, nrhs);
+  dim3 grid(cg.nb_c, nrhs);
   hipLaunchKernelGGL((k_cg_init<T>), grid, dim3(VT), 0, st, rhs, x, r, p, g.nd, cg,
                      outer_active);
   check_launch("cg init");
@@ -268,7 +274,7 @@ void cg_init(const Geometry& g, const T* rhs, T* x, T* r, T* p, int nrhs, const 
 template <typename T>
 void cg_update(const Geometry& g, T* x, T* r, const T* p, const T* q, int nrhs,
                const CgScalars& cg, hipStream_t st) {
-  dim3 grid(cg.nb_b, nrhs);
+  dim3 grid(cg.nb_c, nrhs);
   hipLaunchKernelGGL((k_cg_update<T>), grid, dim3(VT), 0, st, x, r, p, q, g.nd, cg);
   check_launch("cg update");
 }

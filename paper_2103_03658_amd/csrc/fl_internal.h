@@ -29,11 +29,13 @@ struct Error : std::runtime_error {
 // writes its partial sum to part_a / part_b, and every block of the kernel
 // that consumes the sum re-adds the partials itself in a fixed order.  Each
 // scalar is written by block 0 of one kernel and read only by later kernels:
-//   first pass  reads part_b (r.r), rr_prev, iters, thresh2; writes rr_cur,
-//               thresh2 (first iteration), and on exit active/status/n_active
+//   first pass  reads part_b (rho), part_c (r.r, preconditioned), rr_prev,
+//               iters, thresh2; writes rr_cur (rho), res2, thresh2 (first
+//               iteration), and on exit active/status/n_active
 //   last pass   writes part_a (p.q)
-//   update      reads part_a, rr_cur; writes part_b, rr_prev <- rr_cur,
-//               iters += 1, alpha
+//   update      reads part_a, rr_cur; writes the r.r partials (part_b, or
+//               part_c when preconditioned), rr_prev <- rr_cur, iters += 1
+//   precond.    z = P r: its last pass writes part_b (r.z)
 // so no kernel reads a value that a concurrently running block may change.
 // ---------------------------------------------------------------------------
 struct CgScalars {
@@ -46,11 +48,15 @@ struct CgScalars {
   int* status;       // 0 converged/running, 5 no convergence, 6 breakdown
   int* n_active;     // single int: number of active RHS (host polls it)
   double* part_a;    // p.q partials, nrhs * max_blocks
-  double* part_b;    // r.r partials, nrhs * max_blocks
+  double* part_b;    // rho partials: r.r (CG) or r.z (preconditioned), nrhs * max_blocks
+  double* part_c;    // r.r partials when preconditioned, nrhs * max_blocks
+  double* res2;      // ||r_k||^2 of the current iteration (stopping test, reports)
   int nb_a;          // valid partials per RHS in part_a (last-pass blocks)
-  int nb_b;          // valid partials per RHS in part_b (update / init blocks)
+  int nb_b;          // valid partials per RHS in part_b
+  int nb_c;          // valid partials per RHS in part_c (update / init blocks)
   int max_blocks;
   int maxiter;
+  int precond;       // 1: z = P r (preconditioned CG), rho = r.z
   double tol2;
 };
 
@@ -59,6 +65,7 @@ enum PassMode {
   PM_PLAIN = 0,     // y = A u
   PM_CG = 1,        // first pass: beta, convergence, p = r + beta p; last pass: q = A p, p.q partials
   PM_RESID = 2,     // last pass: y = f - A u and partials of ||y||^2 (FP64 only)
+  PM_DOT = 3,       // y = A u and partials of u.y into `part` (preconditioner r.z)
 };
 
 // Geometry of one operator application.
@@ -95,6 +102,7 @@ int vec_blocks(long nd, int nrhs);
 
 // y = A u (mode PM_PLAIN), CG step (PM_CG: p <- r + beta p from rvec/pvec,
 // q = A p into y), or FP64 residual (PM_RESID: y = f - A u).
+// PM_DOT writes its partials to cg->part_b.
 template <typename T>
 void apply_passes(const Geometry& g, const Schedule& sc, const T* lam, const void* tw,
                   const T* u, T* y, int nrhs, void* ws, hipStream_t st, int mode,
@@ -116,8 +124,11 @@ void build_generator(const GenParams& gp, double* G, hipStream_t st);
 void build_symbol(const Geometry& g, const double* G, double* lam64, float* lam32,
                   hipStream_t st);
 void embed_generator(const Geometry& g, const double* G, double* out, hipStream_t st);
+void build_inverse_symbol(const Geometry& g, const double* lam64, long nf, double* inv64,
+                          float* inv32, double* scratch, hipStream_t st);
 
-// CG kernels (cg unit).  cg.nb_b must equal vec_blocks(g.nd, nrhs).
+// CG kernels (cg unit).  The vector kernels run cg.nb_c = vec_blocks(g.nd, nrhs)
+// blocks per RHS and write that many r.r partials.
 template <typename T>
 void cg_init(const Geometry& g, const T* rhs, T* x, T* r, T* p, int nrhs, const CgScalars& cg,
              const int* outer_active, hipStream_t st);

@@ -103,6 +103,46 @@ __global__ void k_fold(const cx<double>* chat, double* l64, float* l32, int d, i
   l32[k] = (float)v;
 }
 
+// Preconditioner multiplier s / max(lambda-hat, 1e-12 max lambda-hat): the
+// restricted inverse R C^{-1} R^T of the embedding circulant C (floored so
+// that it stays positive definite even if some lambda-hat is not).  The
+// transforms are unnormalised and lambda-hat already carries one 1/M^d, so
+// s = 1/M^(2d).
+__global__ void __launch_bounds__(1024) k_symbol_max(const double* l, long n, double* out) {
+  __shared__ double sh[16];
+  double m = 0.0;
+  for (long i = threadIdx.x; i < n; i += blockDim.x) m = fmax(m, l[i]);
+  for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_down(m, off, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) t = fmax(t, sh[w]);
+    *out = t;
+  }
+}
+
+__global__ void k_symbol_inv(const double* l, long n, const double* lmax, double s,
+                             double* i64, float* i32) {
+  const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const double fl = 1e-12 * lmax[0];
+  const double v = s / fmax(l[k], fl);
+  i64[k] = v;
+  i32[k] = (float)v;
+}
+
+void build_inverse_symbol(const Geometry& g, const double* lam64, long nf, double* inv64,
+                          float* inv32, double* scratch, hipStream_t st) {
+  double s = 1.0;
+  for (int k = 0; k < 2 * g.d; ++k) s /= (double)g.M;
+  hipLaunchKernelGGL(k_symbol_max, dim3(1), dim3(1024), 0, st, lam64, nf, scratch);
+  check_launch("symbol max");
+  hipLaunchKernelGGL(k_symbol_inv, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, st, lam64,
+                     nf, scratch, s, inv64, inv32);
+  check_launch("symbol inverse");
+}
+
 void build_symbol(const Geometry& g, const double* G, double* lam64, float* lam32,
                   hipStream_t st) {
   const int M = g.M, d = g.d;

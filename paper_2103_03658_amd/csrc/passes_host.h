@@ -32,9 +32,10 @@ void apply_passes_t(const Geometry& g, const Schedule& sc, const T* lam, const v
   const long h = M / 2 + 1;
   CgScalars nocg{};
   const CgScalars& c = cg ? *cg : nocg;
-  if ((mode == PM_CG || mode == PM_RESID) && !cg) throw Error(1, "missing reduction buffers");
+  if (mode != PM_PLAIN && !cg) throw Error(1, "missing reduction buffers");
+  double* part = mode == PM_DOT ? c.part_b : c.part_a;
   if (g.d == 1) {
-    Line1Args<T> a{u, y, pvec, rvec, fvec, active, c, c.part_a, c.max_blocks, lam, n, nrhs,
+    Line1Args<T> a{u, y, pvec, rvec, fvec, active, c, part, c.max_blocks, lam, n, nrhs,
                    mode, tw};
     mark();
     launch_line1d<T>(M, sc.E_mid, a, st);
@@ -71,8 +72,8 @@ void apply_passes_t(const Geometry& g, const Schedule& sc, const T* lam, const v
     launch_c2c<T>(M, sc.E_c2c, +1, i1, (long)nrhs * h, st);
   }
   {
-    LastArgs<T> a{T1, y, pvec, fvec, active, c.part_a, c.max_blocks, C0, h * C0, nd, 0, n,
-                  sc.W_first, mode, tw};
+    LastArgs<T> a{T1, y, mode == PM_DOT ? u : pvec, fvec, active, part, c.max_blocks, C0,
+                  h * C0, nd, 0, n, sc.W_first, mode, tw};
     mark();
     launch_last<T>(M, sc.E_first, a, nrhs, st);
     mark();

@@ -73,27 +73,32 @@ __device__ __forceinline__ double sum_partials(const double* part, int nb, doubl
 // `lead` is true for exactly one block of the RHS, which records the state.
 __device__ __forceinline__ bool cg_begin(const CgScalars& cg, int o, bool lead, double* sh,
                                          double* beta) {
-  const double rr = sum_partials(cg.part_b + (long)o * cg.max_blocks, cg.nb_b, sh);
+  const double rho = sum_partials(cg.part_b + (long)o * cg.max_blocks, cg.nb_b, sh);
+  const double rr =
+      cg.precond ? sum_partials(cg.part_c + (long)o * cg.max_blocks, cg.nb_c, sh) : rho;
   const int it = cg.iters[o];
   bool stop = false;
   int status = 0;
   double b = 0.0;
-  if (!isfinite(rr)) {
+  if (!isfinite(rr) || !isfinite(rho)) {
     stop = true;
     status = 6;
   } else if (it == 0) {
     stop = rr == 0.0;
+  } else if (rr <= cg.thresh2[o]) {
+    stop = true;
+  } else if (it >= cg.maxiter) {
+    stop = true;
+    status = 5;
+  } else if (!(rho > 0.0)) {
+    stop = true;   // r.z <= 0: the preconditioned iteration broke down
+    status = 6;
   } else {
-    if (rr <= cg.thresh2[o]) {
-      stop = true;
-    } else if (it >= cg.maxiter) {
-      stop = true;
-      status = 5;
-    }
-    b = rr / cg.rr_prev[o];
+    b = rho / cg.rr_prev[o];
   }
   if (lead && threadIdx.x == 0) {
-    cg.rr_cur[o] = rr;
+    cg.rr_cur[o] = rho;
+    cg.res2[o] = rr;
     if (it == 0) cg.thresh2[o] = cg.tol2 * rr;
     if (stop) {
       cg.active[o] = 0;
@@ -210,10 +215,10 @@ template <typename T>
 struct LastArgs {
   const cx<T>* in;
   T* y;
-  const T* p;            // PM_CG: dot partner
+  const T* p;            // PM_CG / PM_DOT: dot partner
   const double* f;       // PM_RESID: right-hand side (FP64)
   const int* active;
-  double* part;          // PM_CG / PM_RESID: per-block partials [nrhs][max_blocks]
+  double* part;          // PM_CG / PM_DOT / PM_RESID: per-block partials [nrhs][max_blocks]
   int max_blocks;
   long C;                // real columns per RHS
   long in_os;            // complex elements between RHS of in
@@ -268,7 +273,7 @@ __global__ void __launch_bounds__(512) k_last(LastArgs<T> a) {
       } else {
         if (h0) a.y[i0] = v[sl].x;
         if (h1) a.y[i0 + 1] = v[sl].y;
-        if (a.mode == PM_CG) {
+        if (a.mode == PM_CG || a.mode == PM_DOT) {
           if (h0) acc += (double)a.p[i0] * (double)v[sl].x;
           if (h1) acc += (double)a.p[i0 + 1] * (double)v[sl].y;
         }
@@ -429,7 +434,7 @@ struct Line1Args {
   const double* f;
   const int* active;
   CgScalars cg;
-  double* part;          // PM_CG / PM_RESID partials, one per RHS
+  double* part;          // PM_CG / PM_DOT / PM_RESID partials, one per RHS
   int max_blocks;
   const T* lam;
   int n;
@@ -493,6 +498,7 @@ __global__ void __launch_bounds__(512) k_line1d(Line1Args<T> a) {
       } else {
         a.y[base + i] = v[sl].x;
         if (a.mode == PM_CG) acc += (double)a.p[base + i] * (double)v[sl].x;
+        if (a.mode == PM_DOT) acc += (double)a.u[base + i] * (double)v[sl].x;
       }
     }
   }

@@ -158,15 +158,17 @@ def test_apply_ragged_and_edge_sizes():
         assert np.abs(y[0] - oracle.apply(G, u[0])).max() <= 1e-12 * abs_scale(G, u[0])
 
 
+@pytest.mark.parametrize("pc", [1, 0])
 @pytest.mark.parametrize("d,alpha,p,N,mixed", [
     (1, 1.5, 1, 256, 0), (2, 1.5, 1, 16, 0), (2, 0.5, 2, 32, 0), (3, 1.0, 1, 8, 0),
     (2, 1.5, 1, 16, 1), (2, 1.0, 2, 32, 1), (3, 1.0, 1, 8, 1), (1, 1.5, 1, 256, 1),
     (2, 1.9, 2, 64, 1), (2, 1.5, 1, 16, 2), (2, 1.0, 2, 32, 2), (3, 1.0, 1, 8, 2),
     (1, 1.5, 1, 256, 2),
 ])
-def test_solve_parity(d, alpha, p, N, mixed):
-    print(f"[solve] d={d} alpha={alpha} p={p} N={N} mixed={mixed}", flush=True)
+def test_solve_parity(d, alpha, p, N, mixed, pc):
+    print(f"[solve] d={d} alpha={alpha} p={p} N={N} mixed={mixed} pc={pc}", flush=True)
     op = make_op(d, alpha, p, N)
+    op.set_preconditioner(pc)
     f = inputs.uniform_rhs(d, N, 2, seed=0)
     tol = 1e-10
     u, info = op.solve(torch.from_numpy(f).cuda(), tol=tol, mixed=mixed)
@@ -298,3 +300,27 @@ def test_graph_replays_match_eager(mixed):
         ux, _ = op.solve(f, tol=1e-10, mixed=mixed)        # eager work in between
         assert torch.equal(ux, ue)
         op.set_graphs(True)
+
+
+@pytest.mark.parametrize("d,N,fp32", [(1, 64, False), (2, 32, False), (2, 32, True),
+                                      (3, 8, False)])
+def test_precond_apply_parity(d, N, fp32):
+    op = make_op(d, 1.5, 2 if N % 2 == 0 else 1, N)
+    u = inputs.uniform_rhs(d, N, 2, seed=41)
+    ut = torch.from_numpy(u.astype(np.float32) if fp32 else u).cuda()
+    y = op.apply_precond(ut).double().cpu().numpy()
+    G = orc_gen(d, 1.5, 2 if N % 2 == 0 else 1, N)
+    for r in range(2):
+        ref = oracle.precond_apply(G, ut[r].double().cpu().numpy())
+        tol = 1e-5 if fp32 else 1e-12
+        assert np.abs(y[r] - ref).max() <= tol * np.abs(ref).max()
+
+
+def test_precond_cuts_iterations():
+    op = make_op(2, 1.5, 1, 64)
+    f = torch.from_numpy(inputs.uniform_rhs(2, 64, 1, seed=4)).cuda()
+    op.set_preconditioner(0)
+    _, i0 = op.solve(f, tol=1e-10)
+    op.set_preconditioner(1)
+    _, i1 = op.solve(f, tol=1e-10)
+    assert i1[0]["iters"] * 3 < i0[0]["iters"], (i0, i1)

@@ -257,3 +257,25 @@ def test_cg_matches_cholesky():
     u2, it, rel = oracle.solve_cg(G, f, tol=1e-13)
     assert rel <= 1e-13
     assert np.abs(u1 - u2).max() <= 1e-10 * np.abs(u1).max()
+
+
+@pytest.mark.parametrize("d,N", [(1, 16), (2, 8), (3, 4)])
+def test_precond_fft_matches_dense_circulant_inverse(d, N):
+    """The FFT form of R C^{-1} R^T against a dense inverse of the dense
+    embedding circulant (C_{jk} = c_{(j-k) mod M})."""
+    G = oracle.generator(d, 1.3, 1, N)
+    c = oracle.embed_generator(G)
+    lam, _ = oracle.symbol(G)
+    assert lam.min() > 1e-12 * lam.max()     # no flooring in these cases
+    M = 2 * N
+    n = N - 1
+    idx = np.indices((M,) * d).reshape(d, -1)
+    diff = tuple((idx[s][:, None] - idx[s][None, :]) % M for s in range(d))
+    C = c[diff]
+    rng = np.random.default_rng(8)
+    v = rng.uniform(-1, 1, (n,) * d)
+    z = np.zeros((M,) * d)
+    z[(slice(0, n),) * d] = v
+    y = np.linalg.solve(C, z.reshape(-1)).reshape((M,) * d)[(slice(0, n),) * d]
+    np.testing.assert_allclose(oracle.precond_apply(G, v), y, rtol=1e-10,
+                               atol=1e-12 * np.abs(y).max())
