@@ -43,12 +43,22 @@ def parse():
     ap.add_argument("--path", choices=["reliable", "refine", "fp64"], default="reliable",
                     help="reliable: FP32 CG with FP64 reliable updates; refine: restarted FP32 "
                          "inner solves with FP64 refinement; fp64: FP64 CG")
+    ap.add_argument("--delta", type=float, default=None,
+                    help="reliable path: residual reduction that triggers an FP64 update")
+    ap.add_argument("--inner-tol", type=float, default=None,
+                    help="refine path: relative tolerance of each FP32 inner solve")
     ap.add_argument("--fp64-single", type=int, default=2,
                     help="right-hand sides per alpha solved one at a time in FP64 for comparison")
     ap.add_argument("--cpu-budget", type=float, default=20.0,
                     help="seconds of oracle work for the CPU baseline (0: skip)")
     ap.add_argument("--profile-reps", type=int, default=20)
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch schedule")
+    ap.add_argument("--tune-cache", action="store_true",
+                    help="reuse / store tuned schedules in the tuner's JSON cache "
+                         "(FL_SCHEDULE_CACHE), so a profiler run can skip the tuning launches")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="roofline-only: also run a device copy of this many MiB, three times "
+                         "(the known-size kernel that scales the HBM byte counters)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only time the FFT-matvec kernels (for profiler runs)")
     ap.add_argument("--serve-requests", type=int, default=512,
@@ -93,8 +103,10 @@ def pass_bytes(d, N, nrhs, sr):
     return [vec + mid, 2 * mid + sym, mid + vec]
 
 
-def cpu_baseline(N, degree, alpha, iters, budget):
-    """Time the oracle (dense block-Toeplitz product, no FFT) on this host."""
+def cpu_baseline(N, degree, alpha, tol, budget):
+    """Time the oracle on this host: whole solves of one right-hand side by
+    its preconditioned CG (dense block-Toeplitz product, no FFT, for A; the
+    FFT form of the circulant inverse for P), repeated while the budget lasts."""
     import oracle
     try:
         from threadpoolctl import threadpool_limits
@@ -108,26 +120,28 @@ def cpu_baseline(N, degree, alpha, iters, budget):
         G = oracle.generator(2, alpha, degree, N)
         t_gen = time.perf_counter() - t0
         from paper_2103_03658_amd import inputs
-        u = inputs.uniform_rhs(2, N, 1, seed=0)[0]
-        nmv = 0
+        f = inputs.uniform_rhs(2, N, 1, seed=0)[0]
+        pc = lambda v: oracle.precond_apply(G, v)
+        ns, its = 0, []
         t0 = time.perf_counter()
         while True:
-            oracle.apply_bttb(G, u)
-            nmv += 1
+            _, it, rel = oracle.solve_cg(G, f, tol=tol, precond=pc)
+            its.append(it)
+            ns += 1
             el = time.perf_counter() - t0
-            if el > budget or nmv >= 50:
+            if el > budget or ns >= 20:
                 break
-        t_mv = el / nmv
     finally:
         if ctx is not None:
             ctx.__exit__(None, None, None)
-    return dict(value=1.0 / (t_mv * iters), unit="solves/s", cores=cores, kind="oracle",
-                sample=(f"oracle block-Toeplitz product (no FFT) at {N - 1}^2, p={degree}, "
-                        f"alpha={alpha}: {nmv} products in {el:.1f} s ({t_mv:.3f} s each); "
-                        f"solves/s = 1/(t_product * {iters} CG iterations, the FP64 "
-                        f"iteration count of this matrix at tol 1e-10); oracle generator "
-                        f"{t_gen:.1f} s not included"),
-                matvec_s=t_mv, generator_s=t_gen)
+    t_s = el / ns
+    return dict(value=1.0 / t_s, unit="solves/s", cores=cores, kind="oracle",
+                sample=(f"{ns} oracle solves of one uniform RHS at {N - 1}^2, p={degree}, "
+                        f"alpha={alpha}, tol {tol:g}: preconditioned CG on the dense "
+                        f"block-Toeplitz product, {its[0]} iterations, {t_s:.2f} s per solve "
+                        f"(final rel. residual {rel:.1e}); oracle generator {t_gen:.1f} s "
+                        f"not included"),
+                solve_s=t_s, iterations=its[0], generator_s=t_gen)
 
 
 def main():
@@ -163,6 +177,10 @@ def main():
         rhs[a] = torch.from_numpy(f).to(dev)
     out = torch.empty_like(rhs[alphas[0]])
     mixed = {"fp64": 0, "reliable": 1, "refine": 2}[args.path]
+    if args.delta is not None or args.inner_tol is not None:
+        for a in alphas:
+            ops[a].set_refinement(delta=args.delta if args.delta is not None else 0.1,
+                                  inner_tol=args.inner_tol if args.inner_tol is not None else 1e-4)
 
     # launch schedules: tuned once per precision on one operator (same M for all)
     from paper_2103_03658_amd import tune as _tune
@@ -170,7 +188,7 @@ def main():
     if not args.no_tune:
         t_tune = time.perf_counter()
         for fp32 in (True, False):
-            best, _ = _tune.tune(ops[1.5], nrhs, fp32, use_cache=False)
+            best, _ = _tune.tune(ops[1.5], nrhs, fp32, use_cache=args.tune_cache)
             for a in alphas:
                 ops[a].set_schedule(fp32, **best)
         sched["tune_s"] = time.perf_counter() - t_tune
@@ -178,9 +196,20 @@ def main():
     sched["f64"] = ops[1.5].get_schedule(False)
 
     if args.roofline_only:
+        if args.calib_copy_mib > 0:
+            nb = args.calib_copy_mib << 20
+            src = torch.ones(nb // 4, dtype=torch.float32, device=dev)
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            del src, dst
         u32 = rhs[1.5].to(torch.float32).contiguous()
+        acc = None
         for _ in range(max(1, args.steps)):
-            ms = ops[1.5].profile_apply(u32, reps=args.profile_reps)
+            m = ops[1.5].profile_apply(u32, reps=args.profile_reps)
+            acc = m if acc is None else [x + y for x, y in zip(acc, m)]
+        ms = [x / max(1, args.steps) for x in acc]
         by = pass_bytes(2, N, nrhs, 4)
         print(json.dumps({"roofline_only": True, "ms_per_kernel": ms,
                           "GBs": [b / (t * 1e-3) / 1e9 for b, t in zip(by, ms)],
@@ -262,8 +291,7 @@ def main():
 
     cpu = None
     if args.cpu_budget > 0:
-        it_ref = int(np.median(fp64["iters"][1.0])) if fp64 else 150
-        cpu = cpu_baseline(N, p, 1.0, it_ref, args.cpu_budget)
+        cpu = cpu_baseline(N, p, 1.0, args.tol, args.cpu_budget)
 
     lat_ms = np.array(lat) * 1e3
     res = {

@@ -161,9 +161,11 @@ fl_status fl_set_schedule(fl_op A, int fp32, int e_first, int e_mid, int e_c2c, 
 fl_status fl_get_schedule(fl_op A, int fp32, int *sched6);
 
 /*
- * fl_profile_apply -- measurement hook: run fl_apply's kernel sequence
- * `reps` times on `stream` with a HIP event recorded between consecutive
- * kernels, and return the mean duration of each kernel in milliseconds.
+ * fl_profile_apply -- measurement hook: run fl_apply's kernel sequence once
+ * on `stream` (so every kernel's input is in place), then each kernel alone
+ * `reps` times back to back between two HIP events, and return the mean
+ * duration per launch of each kernel in milliseconds; a last whole sequence
+ * leaves y = A u.
  * The kernels are the transform passes in launch order: 1 for d = 1 (the
  * whole product), 3 for d = 2 (axis 0 forward, last axis forward * symbol *
  * inverse, axis 0 inverse), 5 for d = 3 (axis 0, axis 1, last axis, axis 1

@@ -3,8 +3,9 @@
 The paper only says the SPD multilevel-Toeplitz system can be solved with
 fast FFT-based algorithms (Example 3.2.3); it names no solver.  A is
 symmetric positive definite (Sec. 2.2), so the oracle uses a Cholesky
-factorisation where A fits in memory and plain conjugate gradients on the
-block product otherwise.
+factorisation where A fits in memory and conjugate gradients on the block
+product otherwise, optionally preconditioned by the restricted inverse of
+the embedding circulant (operator.precond_apply).
 """
 
 import numpy as np
@@ -24,22 +25,29 @@ def solve_cholesky(G, f):
     return u.reshape(shp)
 
 
-def solve_cg(G, f, tol=1e-13, maxiter=100000, x0=None):
+def solve_cg(G, f, tol=1e-13, maxiter=100000, x0=None, precond=None):
     """Textbook CG (x0 = 0), stopping when ||r_k||_2 <= tol ||f||_2 on the
-    recursively updated residual.  Returns (u, iterations, rel. residual)."""
+    recursively updated residual.  With `precond` (a callable z = P r for an
+    SPD P) it is textbook preconditioned CG: rho = r.z drives alpha and beta,
+    the stopping rule stays on ||r||_2.  Returns (u, iterations, rel. residual)."""
+    P = precond if precond is not None else (lambda v: v)
     x = np.zeros_like(f) if x0 is None else x0.copy()
     r = f - apply(G, x) if x0 is not None else f.copy()
-    p = r.copy()
+    z = P(r)
+    p = z.copy()
+    rho = float(np.vdot(r, z))
     rr = float(np.vdot(r, r))
     fn = float(np.sqrt(np.vdot(f, f)))
     it = 0
     while np.sqrt(rr) > tol * fn and it < maxiter:
         q = apply(G, p)
-        a = rr / float(np.vdot(p, q))
+        a = rho / float(np.vdot(p, q))
         x += a * p
         r -= a * q
-        rr_new = float(np.vdot(r, r))
-        p = r + (rr_new / rr) * p
-        rr = rr_new
+        z = P(r)
+        rho_new = float(np.vdot(r, z))
+        p = z + (rho_new / rho) * p
+        rho = rho_new
+        rr = float(np.vdot(r, r))
         it += 1
     return x, it, np.sqrt(rr) / fn

@@ -152,6 +152,10 @@ struct fl_op_s {
   hipEvent_t ev_poll[2] = {nullptr, nullptr};
   int* pinned = nullptr;
   ChunkGraph graph[2];    // captured CG chunks: FP64 (0), FP32 reliable (1)
+  ChunkGraph glen[5];     // FP64 CG chunks of 1, 2, 4, 8, 16 iterations
+  DBuf poll_dev;          // packed CG state for the host (device side)
+  double* poll_host = nullptr;   // pinned copy
+  size_t poll_cap = 0;
   bool use_graphs = true;
 
   // Order this call after the previous one if it ran on another stream
@@ -173,14 +177,16 @@ static size_t line_bytes(int M, int E, bool fp32) {
 }
 
 bool schedule_ok(const Geometry& g, const Schedule& s, bool fp32) {
-  auto ok = [&](int E, int W) {
+  auto ok = [&](int E, int W, bool tiled) {
     if (!(E == 8 || E == 16 || E == 32) || E > g.M) return false;
-    if (W < 1) return false;
+    if (W < 1 || (tiled && !pow2(W))) return false;
     if ((long)W * (g.M / E) > 512) return false;
-    if (line_bytes(g.M, E, fp32) * W > kMaxLds - 1024) return false;  // room for static LDS
+    const size_t b = tiled ? tile_lds(g.M, E, W, fp32 ? 4 : 8).bytes : line_bytes(g.M, E, fp32) * W;
+    if (b > kMaxLds - 1024) return false;  // room for static LDS
     return true;
   };
-  return ok(s.E_first, s.W_first) && ok(s.E_mid, s.LPB_mid) && ok(s.E_c2c, s.W_c2c);
+  return ok(s.E_first, s.W_first, true) && ok(s.E_mid, s.LPB_mid, false) &&
+         ok(s.E_c2c, s.W_c2c, true);
 }
 
 // Starting schedule before tuning: radix-16 register stages (radix 32 in the
@@ -198,7 +204,8 @@ Schedule default_schedule(const Geometry& g, bool fp32) {
   auto fitW = [&](int E, int want) {
     const int tpl = M / E;
     int w = std::max(1, std::min(want, 256 / std::max(1, tpl)));
-    while (w > 1 && line_bytes(M, E, fp32) * w > 96 * 1024) w /= 2;
+    w = 1 << ilog2i(w + 1) >> 1;   // largest power of two <= w
+    while (w > 1 && tile_lds(M, E, w, fp32 ? 4 : 8).bytes > 96 * 1024) w /= 2;
     return w;
   };
   s.W_first = fitW(s.E_first, 16);
@@ -313,6 +320,9 @@ void fl_destroy(fl_op A) {
   A->outer_flags.release();
   if (A->done) hipEventDestroy(A->done);
   for (auto& gph : A->graph) gph.reset();
+  for (auto& gph : A->glen) gph.reset();
+  A->poll_dev.release();
+  if (A->poll_host) hipHostFree(A->poll_host);
   if (A->ev_in) hipEventDestroy(A->ev_in);
   for (auto& e : A->ev_poll)
     if (e) hipEventDestroy(e);
@@ -484,32 +494,37 @@ fl_status fl_profile_apply(fl_op A, const void* u, void* y, int nrhs, int fp32, 
     hipStream_t st = (hipStream_t)stream;
     A->begin(st);
     void* ws = A->ws.get(fl::apply_workspace_bytes(A->g, nrhs, fp32 != 0));
-    std::vector<hipEvent_t> ev((size_t)(np + 1) * reps);
-    for (auto& e : ev) FL_HIP(hipEventCreate(&e));
-    for (int r = 0; r < reps; ++r) {
-      hipEvent_t* er = ev.data() + (size_t)r * (np + 1);
+    auto run = [&](int only) {
       if (fp32)
         fl::apply_passes<float>(A->g, A->sc32, A->lam32, A->tw32, (const float*)u, (float*)y,
                                 nrhs, ws, st, fl::PM_PLAIN, nullptr, nullptr, nullptr, nullptr,
-                                nullptr, er);
+                                nullptr, nullptr, only);
       else
         fl::apply_passes<double>(A->g, A->sc64, A->lam64, A->tw64, (const double*)u,
                                  (double*)y, nrhs, ws, st, fl::PM_PLAIN, nullptr, nullptr,
-                                 nullptr, nullptr, nullptr, er);
-    }
-    FL_HIP(hipStreamSynchronize(st));
+                                 nullptr, nullptr, nullptr, nullptr, only);
+    };
+    // one whole product puts every pass's input in place; then each pass runs
+    // reps times back to back between two events; a last whole product
+    // leaves y = A u
+    hipEvent_t ev[2];
+    FL_HIP(hipEventCreate(&ev[0]));
+    FL_HIP(hipEventCreate(&ev[1]));
+    run(-1);
     for (int k = 0; k < np; ++k) {
-      double tot = 0.0;
-      for (int r = 0; r < reps; ++r) {
-        float ms = 0.f;
-        FL_HIP(hipEventElapsedTime(&ms, ev[(size_t)r * (np + 1) + k],
-                                   ev[(size_t)r * (np + 1) + k + 1]));
-        tot += ms;
-      }
-      ms_per_pass[k] = tot / reps;
+      FL_HIP(hipEventRecord(ev[0], st));
+      for (int r = 0; r < reps; ++r) run(k);
+      FL_HIP(hipEventRecord(ev[1], st));
+      FL_HIP(hipEventSynchronize(ev[1]));
+      float ms = 0.f;
+      FL_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+      ms_per_pass[k] = (double)ms / reps;
     }
+    run(-1);
+    FL_HIP(hipStreamSynchronize(st));
     *n_passes = np;
-    for (auto& e : ev) hipEventDestroy(e);
+    hipEventDestroy(ev[0]);
+    hipEventDestroy(ev[1]);
     A->end(st);
     return FL_OK;
   });
@@ -591,6 +606,67 @@ void chunk_loop(fl_op A, ChunkGraph& g, const std::vector<double>& key, int max_
       FL_HIP(hipEventSynchronize(A->ev_poll[1 - slot]));
       if (A->pinned[1 - slot] == 0) break;
     }
+  }
+  FL_HIP(hipStreamSynchronize(st));
+}
+
+// Run CG iterations in chunks whose length is predicted from each active
+// right-hand side's observed contraction of r.r (iterations to reach its
+// threshold at the rate of the previous chunk, at most 16); the host reads
+// the state after every chunk, so no work is queued past convergence.
+// Chunks are composed of captured graphs of 16, 8, 4, 2 and 1 iterations.
+template <typename F>
+void predictive_loop(fl_op A, const std::vector<double>& key, int cap, const fl::CgScalars& cg,
+                     int nrhs, hipStream_t st, F&& enqueue_one) {
+  const size_t pb = (1 + 4 * (size_t)nrhs) * sizeof(double);
+  double* dpoll = (double*)A->poll_dev.get(pb);
+  if (A->poll_cap < pb) {
+    if (A->poll_host) FL_HIP(hipHostFree(A->poll_host));
+    A->poll_host = nullptr;
+    A->poll_cap = 0;
+    FL_HIP(hipHostMalloc((void**)&A->poll_host, pb, hipHostMallocDefault));
+    A->poll_cap = pb;
+  }
+  static const int lens[5] = {1, 2, 4, 8, 16};
+  std::vector<double> rr_prev(nrhs, 0.0);
+  std::vector<int> it_prev(nrhs, 0);
+  int done = 0, next = 8;
+  while (done < cap) {
+    int k = std::min(next, cap - done);
+    for (int b = 4; b >= 0; --b) {
+      while (k >= lens[b]) {
+        std::vector<double> kb = key;
+        kb.push_back(lens[b]);
+        launch_chunk(A->glen[b], kb, st, A->use_graphs, [&]() {
+          for (int i = 0; i < lens[b]; ++i) enqueue_one();
+        });
+        k -= lens[b];
+        done += lens[b];
+      }
+    }
+    fl::pack_poll(cg, nrhs, dpoll, st);
+    FL_HIP(hipMemcpyAsync(A->poll_host, dpoll, pb, hipMemcpyDeviceToHost, st));
+    FL_HIP(hipStreamSynchronize(st));
+    const double* h = A->poll_host;
+    if (h[0] == 0.0) break;
+    int need = 1;
+    for (int o = 0; o < nrhs; ++o) {
+      const double* q = h + 1 + 4 * o;
+      if (q[2] == 0.0) continue;
+      const double rr = q[0], th = q[1];
+      const int it = (int)q[3];
+      int guess = 8;
+      if (rr <= th) {
+        guess = 1;
+      } else if (rr_prev[o] > 0.0 && it > it_prev[o] && rr > 0.0 && th > 0.0) {
+        const double rate = std::pow(rr / rr_prev[o], 1.0 / (it - it_prev[o]));
+        if (rate < 0.95) guess = (int)std::ceil(std::log(th / rr) / std::log(rate));
+      }
+      need = std::max(need, guess);
+      rr_prev[o] = rr;
+      it_prev[o] = it;
+    }
+    next = std::min(std::max(need, 1), 16);
   }
   FL_HIP(hipStreamSynchronize(st));
 }
@@ -735,10 +811,9 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
       std::vector<double> key = make_key(0, nrhs, chunk, maxiter, tol, pc);
       for (double v : {pkey(ws), pkey(vb), pkey(A->cg.mem.p), pkey(A->lam64)}) key.push_back(v);
       for (double v : sched_key(A->sc64)) key.push_back(v);
-      chunk_loop(A, A->graph[0], key, (maxiter + 2) / chunk + 2, cg, st, [&]() {
-        for (int i = 0; i < chunk; ++i)
-          cg_iteration<double>(A, A->sc64, A->lam64, A->linv64, A->tw64, x, r, p, q, z, nrhs, cg,
-                               ws, st);
+      predictive_loop(A, key, maxiter + 2, cg, nrhs, st, [&]() {
+        cg_iteration<double>(A, A->sc64, A->lam64, A->linv64, A->tw64, x, r, p, q, z, nrhs, cg,
+                             ws, st);
       });
       FL_HIP(hipMemcpyAsync(u, x, v8, hipMemcpyDeviceToDevice, st));
       std::vector<double> rr(nrhs);

@@ -97,6 +97,20 @@ __global__ void k_fill_int(int* p, int v, int n) {
   if (i < n) p[i] = v;
 }
 
+// Per-RHS CG state gathered for the host: [n_active, then per RHS
+// (r.r at the last iteration start, stopping threshold, active, iterations)].
+__global__ void k_pack_poll(CgScalars cg, int nrhs, double* out) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o == 0) out[0] = (double)cg.n_active[0];
+  if (o < nrhs) {
+    double* q = out + 1 + 4 * (long)o;
+    q[0] = cg.res2[o];
+    q[1] = cg.thresh2[o];
+    q[2] = (double)cg.active[o];
+    q[3] = (double)cg.iters[o];
+  }
+}
+
 __global__ void k_fill_zero(unsigned* p, size_t nwords) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nwords) p[i] = 0u;
@@ -291,6 +305,11 @@ template void cg_update<float>(const Geometry&, float*, float*, const float*, co
 void fill_int(int* p, int v, int n, hipStream_t st) {
   hipLaunchKernelGGL(k_fill_int, dim3((n + 255) / 256), dim3(256), 0, st, p, v, n);
   check_launch("fill");
+}
+
+void pack_poll(const CgScalars& cg, int nrhs, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_pack_poll, dim3((nrhs + 63) / 64), dim3(64), 0, st, cg, nrhs, out);
+  check_launch("poll pack");
 }
 
 void fill_zero_bytes(void* p, size_t bytes, hipStream_t st) {

@@ -89,6 +89,33 @@ struct Schedule {
 
 constexpr size_t kMaxLds = 160 * 1024;   // LDS per workgroup on gfx950
 
+// LDS layout of a strided-pass block of W lines (W a power of two): line l
+// owns [l*LS, (l+1)*LS) elements of the element type, its real plane at 0
+// and its imaginary plane at PO, each M + M/E long (padded index).  In the
+// cooperative row-segment phases a half wave touches 32/(2W) rows of the
+// 2W planes of the tile; with PO = R and LS = 2R (mod the bank count, in
+// elements), R = banks/(2W), those accesses land in distinct banks.
+struct TileLds {
+  int PO, LS;
+  size_t bytes;
+};
+inline TileLds tile_lds(int M, int E, int W, size_t elem) {
+  const int ldsn = M + M / E;
+  const int banks = elem == 8 ? 16 : 32;   // 4-byte banks, in elements
+  int R = banks / (2 * W);
+  if (R < 1) R = 1;
+  auto up = [&](int x, int res) { return x + (((res - x) % banks) + banks) % banks; };
+  const int PO = up(ldsn, R % banks);
+  const int LS = up(PO + ldsn, (2 * R) % banks);
+  return {PO, LS, (size_t)W * LS * elem};
+}
+inline bool pow2(int w) { return w >= 1 && (w & (w - 1)) == 0; }
+inline int ilog2i(int w) {
+  int l = 0;
+  while ((1 << l) < w) ++l;
+  return l;
+}
+
 Schedule default_schedule(const Geometry& g, bool fp32);
 bool schedule_ok(const Geometry& g, const Schedule& s, bool fp32);
 
@@ -102,12 +129,13 @@ int vec_blocks(long nd, int nrhs);
 
 // y = A u (mode PM_PLAIN), CG step (PM_CG: p <- r + beta p from rvec/pvec,
 // q = A p into y), or FP64 residual (PM_RESID: y = f - A u).
-// PM_DOT writes its partials to cg->part_b.
+// PM_DOT writes its partials to cg->part_b.  ev (optional): npasses + 1
+// events recorded around the passes; only >= 0 launches that pass alone.
 template <typename T>
 void apply_passes(const Geometry& g, const Schedule& sc, const T* lam, const void* tw,
                   const T* u, T* y, int nrhs, void* ws, hipStream_t st, int mode,
                   const T* rvec, T* pvec, const double* fvec, const CgScalars* cg,
-                  const int* active, hipEvent_t* ev = nullptr);
+                  const int* active, hipEvent_t* ev = nullptr, int only = -1);
 
 // Number of kernel launches (passes) of one application: 1, 3 or 5 for d = 1, 2, 3.
 inline int apply_npasses(int d) { return d == 1 ? 1 : (d == 2 ? 3 : 5); }
@@ -136,6 +164,8 @@ template <typename T>
 void cg_update(const Geometry& g, T* x, T* r, const T* p, const T* q, int nrhs,
                const CgScalars& cg, hipStream_t st);
 void fill_int(int* p, int v, int n, hipStream_t st);
+// out[0] = n_active; out[1 + 4 o ..] = res2, thresh2, active, iters of RHS o.
+void pack_poll(const CgScalars& cg, int nrhs, double* out, hipStream_t st);
 void fill_zero_bytes(void* p, size_t bytes, hipStream_t st);
 // out[o] = sum_{b < nb} part[o * max_blocks + b] (fixed order)
 void reduce_parts(const double* part, int nb, int max_blocks, int nrhs, double* out,

@@ -12,8 +12,8 @@ void apply_passes<double>(const Geometry& g, const Schedule& sc, const double* l
                           const void* tw, const double* u, double* y, int nrhs, void* ws,
                           hipStream_t st, int mode, const double* rvec, double* pvec,
                           const double* fvec, const CgScalars* cg, const int* active,
-                          hipEvent_t* ev) {
-  apply_passes_t<double>(g, sc, lam, tw, u, y, nrhs, ws, st, mode, rvec, pvec, fvec, cg, active, ev);
+                          hipEvent_t* ev, int only) {
+  apply_passes_t<double>(g, sc, lam, tw, u, y, nrhs, ws, st, mode, rvec, pvec, fvec, cg, active, ev, only);
 }
 
 size_t apply_workspace_bytes(const Geometry& g, int nrhs, bool fp32) {
@@ -160,16 +160,16 @@ void build_symbol(const Geometry& g, const double* G, double* lam64, float* lam3
   const size_t lb = line_lds_bytes<double>(M, E);
   int W = 256 / TPL;
   if (W < 1) W = 1;
-  while (W > 1 && lb * W > 65536) W /= 2;
+  while (W > 1 && tile_lds(M, E, W, sizeof(double)).bytes > 65536) W /= 2;
   long Md1 = total / M;  // lines per axis
   if (d >= 2) {
     // axis 0: columns = M^(d-1), row stride M^(d-1)
-    C2CArgs<double> a0{c, c, nullptr, Md1, 0, Md1, 0, Md1, 0, 1, M, M, W, tw};
+    C2CArgs<double> a0{c, c, nullptr, Md1, 0, Md1, 0, Md1, 0, 1, M, M, W, 0, 0, 0, tw};
     launch_c2c<double>(M, E, -1, a0, 1, st);
   }
   if (d == 3) {
     // axis 1: slices k0 (stride M*M), rows stride M, columns M
-    C2CArgs<double> a1{c, c, nullptr, M, (long)M * M, M, (long)M * M, M, 0, 1, M, M, W, tw};
+    C2CArgs<double> a1{c, c, nullptr, M, (long)M * M, M, (long)M * M, M, 0, 1, M, M, W, 0, 0, 0, tw};
     launch_c2c<double>(M, E, -1, a1, M, st);
   }
   int LPB = 256 / TPL;

@@ -121,7 +121,15 @@ __device__ __forceinline__ void xcd_tile(long ntiles, long& tile, long& outer) {
 }
 
 // ---------------------------------------------------------------------------
-// first pass (axis 0, strided): real columns packed in pairs -> rows 0..M/2
+// Strided passes (axis 0; 3D axis 1).  A block owns a tile of W lines (W
+// column pairs in the real passes, W complex columns in the complex pass).
+// Global memory is read and written cooperatively in row segments of the
+// tile (consecutive threads on consecutive columns), staged through the
+// lines' LDS planes; the transforms themselves run line-major (TPL
+// consecutive threads per line), so that a wave's LDS traffic stays inside
+// one line.  Inputs are zero at index >= M/2 and only outputs below M/2 are
+// kept (the embedded data occupies n <= M/2 - 1 rows): those register slots
+// are compile-time zeros / never computed.
 // ---------------------------------------------------------------------------
 template <typename T>
 struct FirstArgs {
@@ -135,11 +143,41 @@ struct FirstArgs {
   long in_os;            // elements between RHS in u/p/r
   long out_os;           // complex elements between RHS in out
   long ntiles;           // column-pair tiles per RHS
-  int n_in;              // rows of input (n)
-  int W;                 // complex lines per block
+  int n_in;              // rows of input (n <= M/2)
+  int W, lw;             // lines per block, log2(W)
+  int PO, LS;            // LDS plane offset and line stride (elements)
   int mode;
   const cx<T>* tw;
 };
+
+// Transform of one line held in LDS planes (natural order, inputs >= M/2
+// zero) and write-back in natural order of the outputs below M/2 (all
+// outputs if keep_all).
+template <typename T, int M, int E, int DIR, bool PRUNE_IN, bool PRUNE_OUT>
+__device__ __forceinline__ void line_in_lds(T* lre, T* lim, int t, const cx<T>* tw) {
+  using P = Plan<M, E>;
+  constexpr int TPL = P::TPL;
+  cx<T> v[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    if (!PRUNE_IN || j < E / 2) {
+      const int i = P::pad(t + j * TPL);
+      v[j] = {lre[i], lim[i]};
+    } else {
+      v[j] = {0, 0};
+    }
+  }
+  fft_line<T, M, E, DIR>(v, lre, lim, t, tw);
+  __syncthreads();
+#pragma unroll
+  for (int sl = 0; sl < E; ++sl) {
+    if (!PRUNE_OUT || P::jslot(sl) < E / 2) {
+      const int i = P::pad(t + TPL * P::jslot(sl));
+      lre[i] = v[sl].x;
+      lim[i] = v[sl].y;
+    }
+  }
+}
 
 template <typename T, int M, int E>
 __global__ void __launch_bounds__(512) k_first(FirstArgs<T> a) {
@@ -158,53 +196,63 @@ __global__ void __launch_bounds__(512) k_first(FirstArgs<T> a) {
     if (cg_begin(a.cg, o, tile == 0, sh, &beta)) return;
     bt = (T)beta;
   }
-  const int W = a.W;
-  const int c = threadIdx.x % W, t = threadIdx.x / W;
-  T* lre = lds + (long)c * 2 * P::LDSN;
-  T* lim = lre + P::LDSN;
-  const long col = (tile * W + c) * 2;
-  const bool h0 = col < a.C, h1 = col + 1 < a.C;
-  cx<T> v[E];
+  const int lw1 = a.lw + 1, W2 = 2 * a.W;
+  const int nthr = a.W * TPL;
+  const long col0 = tile * W2;
+  const long cl = a.C - col0;
+  const int ncol = cl < W2 ? (int)cl : W2;
+  // rows [0, M/2) of the tile into the planes (rows >= n_in are zero):
+  // (M/2) * 2W elements, exactly E per thread, all loads issued first
+  {
+    const long ib = (long)o * a.in_os + col0;
+    T x[E];
 #pragma unroll
-  for (int j = 0; j < E; ++j) {
-    const int row = t + j * TPL;
-    T re = 0, im = 0;
-    if (row < a.n_in) {
-      const long i0 = (long)o * a.in_os + (long)row * a.C + col;
-      if (a.mode == PM_CG) {
-        if (h0) { re = a.r[i0] + bt * a.p[i0]; a.p[i0] = re; }
-        if (h1) { im = a.r[i0 + 1] + bt * a.p[i0 + 1]; a.p[i0 + 1] = im; }
-      } else {
-        if (h0) re = a.u[i0];
-        if (h1) im = a.u[i0 + 1];
+    for (int j = 0; j < E; ++j) {
+      const int e = threadIdx.x + j * nthr;
+      const int row = e >> lw1, cc = e & (W2 - 1);
+      x[j] = 0;
+      if (row < a.n_in && cc < ncol) {
+        const long i = ib + (long)row * a.C + cc;
+        if (a.mode == PM_CG) {
+          x[j] = a.r[i] + bt * a.p[i];
+          a.p[i] = x[j];
+        } else {
+          x[j] = a.u[i];
+        }
       }
     }
-    v[j] = {re, im};
-  }
-  fft_line<T, M, E, -1>(v, lre, lim, t, a.tw);
-  __syncthreads();
 #pragma unroll
-  for (int sl = 0; sl < E; ++sl) {
-    const int i = P::pad(t + TPL * P::jslot(sl));
-    lre[i] = v[sl].x;
-    lim[i] = v[sl].y;
+    for (int j = 0; j < E; ++j) {
+      const int e = threadIdx.x + j * nthr;
+      const int row = e >> lw1, cc = e & (W2 - 1);
+      lds[(cc >> 1) * a.LS + (cc & 1) * a.PO + P::pad(row)] = x[j];
+    }
   }
   __syncthreads();
+  {
+    const int l = threadIdx.x / TPL, t = threadIdx.x % TPL;
+    T* lre = lds + l * a.LS;
+    line_in_lds<T, M, E, -1, true, false>(lre, lre + a.PO, t, a.tw);
+  }
+  __syncthreads();
+  // Hermitian split of each packed pair, rows k = 0..M/2, row segments of
+  // 2W complex values: X_a = (Z_k + conj Z_{M-k})/2, X_b = (Z_k - conj Z_{M-k})/(2i)
+  const long ob = (long)o * a.out_os + col0;
   const T half = (T)0.5;
+  const int tot3 = (M / 2 + 1) * a.W;   // E/2 full rounds and a partial one
 #pragma unroll
   for (int j = 0; j <= E / 2; ++j) {
-    const int k = t + TPL * j;
-    if (k <= M / 2) {
-      const int km = (M - k) & (M - 1);
-      const cx<T> z = {lre[P::pad(k)], lim[P::pad(k)]};
-      const cx<T> zm = {lre[P::pad(km)], lim[P::pad(km)]};
-      // X_a = (Z + conj Zm)/2 ; X_b = (Z - conj Zm)/(2i)
-      const cx<T> xa = {(z.x + zm.x) * half, (z.y - zm.y) * half};
-      const cx<T> xb = {(z.y + zm.y) * half, (zm.x - z.x) * half};
-      const long oi = (long)o * a.out_os + (long)k * a.C + col;
-      if (h0) a.out[oi] = xa;
-      if (h1) a.out[oi + 1] = xb;
-    }
+    const int e = threadIdx.x + j * nthr;
+    const int k = e >> a.lw, l = e & (a.W - 1);
+    if (e >= tot3 || 2 * l >= ncol) continue;
+    const T* re = lds + l * a.LS;
+    const T* im = re + a.PO;
+    const int km = (M - k) & (M - 1);
+    const cx<T> z = {re[P::pad(k)], im[P::pad(k)]};
+    const cx<T> zm = {re[P::pad(km)], im[P::pad(km)]};
+    const long oi = ob + (long)k * a.C + 2 * l;
+    a.out[oi] = {(z.x + zm.x) * half, (z.y - zm.y) * half};
+    if (2 * l + 1 < ncol) a.out[oi + 1] = {(z.y + zm.y) * half, (zm.x - z.x) * half};
   }
 }
 
@@ -224,8 +272,9 @@ struct LastArgs {
   long in_os;            // complex elements between RHS of in
   long y_os;             // elements between RHS of y / p / f
   long ntiles;
-  int n_out;
-  int W;
+  int n_out;             // rows of output (n <= M/2)
+  int W, lw;
+  int PO, LS;
   int mode;
   const cx<T>* tw;
 };
@@ -241,43 +290,67 @@ __global__ void __launch_bounds__(512) k_last(LastArgs<T> a) {
   xcd_tile(a.ntiles, tile, ol);
   const int o = (int)ol;
   if (a.active && !a.active[o]) return;
-  const int W = a.W;
-  const int c = threadIdx.x % W, t = threadIdx.x / W;
-  T* lre = lds + (long)c * 2 * P::LDSN;
-  T* lim = lre + P::LDSN;
-  const long col = (tile * W + c) * 2;
-  const bool h0 = col < a.C, h1 = col + 1 < a.C;
-  cx<T> v[E];
+  const int lw1 = a.lw + 1, W2 = 2 * a.W;
+  const int nthr = a.W * TPL;
+  const long col0 = tile * W2;
+  const long cl = a.C - col0;
+  const int ncol = cl < W2 ? (int)cl : W2;
+  // rows k = 0..M/2 of both halves of each pair: line input Y_a + i Y_b at
+  // k, and its Hermitian image conj(Y_a) + i conj(Y_b) at M - k
+  {
+    const long ib = (long)o * a.in_os + col0;
+    const int tot1 = (M / 2 + 1) * a.W;   // E/2 full rounds and a partial one
+    cx<T> ya_[E / 2 + 1], yb_[E / 2 + 1];
+#pragma unroll
+    for (int j = 0; j <= E / 2; ++j) {
+      const int e = threadIdx.x + j * nthr;
+      const int k = e >> a.lw, l = e & (a.W - 1);
+      ya_[j] = {0, 0};
+      yb_[j] = {0, 0};
+      const long ii = ib + (long)k * a.C + 2 * l;
+      if (e < tot1 && 2 * l < ncol) ya_[j] = a.in[ii];
+      if (e < tot1 && 2 * l + 1 < ncol) yb_[j] = a.in[ii + 1];
+    }
+#pragma unroll
+    for (int j = 0; j <= E / 2; ++j) {
+      const int e = threadIdx.x + j * nthr;
+      if (e >= tot1) continue;
+      const int k = e >> a.lw, l = e & (a.W - 1);
+      const cx<T> ya = ya_[j], yb = yb_[j];
+      T* re = lds + l * a.LS;
+      T* im = re + a.PO;
+      re[P::pad(k)] = ya.x - yb.y;
+      im[P::pad(k)] = ya.y + yb.x;
+      if (k > 0 && k < M / 2) {
+        re[P::pad(M - k)] = ya.x + yb.y;
+        im[P::pad(M - k)] = yb.x - ya.y;
+      }
+    }
+  }
+  __syncthreads();
+  {
+    const int l = threadIdx.x / TPL, t = threadIdx.x % TPL;
+    T* lre = lds + l * a.LS;
+    line_in_lds<T, M, E, +1, false, true>(lre, lre + a.PO, t, a.tw);
+  }
+  __syncthreads();
+  double acc = 0.0;
+  const long yb0 = (long)o * a.y_os + col0;
+  const int tot3 = a.n_out * W2;   // at most (M/2) * 2W: E rounds
 #pragma unroll
   for (int j = 0; j < E; ++j) {
-    const int idx = t + j * TPL;
-    const bool up = idx > M / 2;
-    const int kk = up ? M - idx : idx;
-    const long ii = (long)o * a.in_os + (long)kk * a.C + col;
-    cx<T> ya = {0, 0}, yb = {0, 0};
-    if (h0) ya = a.in[ii];
-    if (h1) yb = a.in[ii + 1];
-    if (up) { ya.y = -ya.y; yb.y = -yb.y; }
-    v[j] = {ya.x - yb.y, ya.y + yb.x};  // Ya + i Yb
-  }
-  fft_line<T, M, E, +1>(v, lre, lim, t, a.tw);
-  double acc = 0.0;
-#pragma unroll
-  for (int sl = 0; sl < E; ++sl) {
-    const int row = t + TPL * P::jslot(sl);
-    if (row < a.n_out) {
-      const long i0 = (long)o * a.y_os + (long)row * a.C + col;
-      if (a.mode == PM_RESID) {
-        if (h0) { const double r0 = a.f[i0] - (double)v[sl].x; a.y[i0] = (T)r0; acc += r0 * r0; }
-        if (h1) { const double r1 = a.f[i0 + 1] - (double)v[sl].y; a.y[i0 + 1] = (T)r1; acc += r1 * r1; }
-      } else {
-        if (h0) a.y[i0] = v[sl].x;
-        if (h1) a.y[i0 + 1] = v[sl].y;
-        if (a.mode == PM_CG || a.mode == PM_DOT) {
-          if (h0) acc += (double)a.p[i0] * (double)v[sl].x;
-          if (h1) acc += (double)a.p[i0 + 1] * (double)v[sl].y;
-        }
-      }
+    const int e = threadIdx.x + j * nthr;
+    const int row = e >> lw1, cc = e & (W2 - 1);
+    if (e >= tot3 || cc >= ncol) continue;
+    const T v = lds[(cc >> 1) * a.LS + (cc & 1) * a.PO + P::pad(row)];
+    const long i = yb0 + (long)row * a.C + cc;
+    if (a.mode == PM_RESID) {
+      const double r = a.f[i] - (double)v;
+      a.y[i] = (T)r;
+      acc += r * r;
+    } else {
+      a.y[i] = v;
+      if (a.mode == PM_CG || a.mode == PM_DOT) acc += (double)a.p[i] * (double)v;
     }
   }
   if (a.mode == PM_PLAIN) return;
@@ -299,36 +372,65 @@ struct C2CArgs {
   long ntiles;
   int outer_per_rhs;
   int n_in, n_out;
-  int W;
+  int W, lw;
+  int PO, LS;
   const cx<T>* tw;
 };
 
-template <typename T, int M, int E, int DIR>
+// PR: 0 full transform, 1 inputs >= M/2 zero (n_in <= M/2), 2 outputs below
+// M/2 only (n_out <= M/2).
+template <typename T, int M, int E, int DIR, int PR>
 __global__ void __launch_bounds__(512) k_c2c(C2CArgs<T> a) {
   using P = Plan<M, E>;
   constexpr int TPL = P::TPL;
+  constexpr int ROWS_IN = PR == 1 ? M / 2 : M;
   extern __shared__ unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
   long tile, o;
   xcd_tile(a.ntiles, tile, o);
   if (a.active && !a.active[o / a.outer_per_rhs]) return;
-  const int W = a.W;
-  const int c = threadIdx.x % W, t = threadIdx.x / W;
-  T* lre = lds + (long)c * 2 * P::LDSN;
-  T* lim = lre + P::LDSN;
-  const long col = tile * W + c;
-  const bool h = col < a.C;
-  cx<T> v[E];
+  const int nthr = a.W * TPL;
+  const long col0 = tile * a.W;
+  const long cl = a.C - col0;
+  const int ncol = cl < a.W ? (int)cl : a.W;
+  {
+    // ROWS_IN * W elements: exactly ROWS_IN / TPL per thread
+    constexpr int J = ROWS_IN / TPL;
+    const long ib = o * a.in_os + col0;
+    cx<T> x[J];
 #pragma unroll
-  for (int j = 0; j < E; ++j) {
-    const int row = t + j * TPL;
-    v[j] = (h && row < a.n_in) ? a.in[o * a.in_os + (long)row * a.in_rs + col] : cx<T>{0, 0};
+    for (int j = 0; j < J; ++j) {
+      const int e = threadIdx.x + j * nthr;
+      const int row = e >> a.lw, l = e & (a.W - 1);
+      x[j] = {0, 0};
+      if (row < a.n_in && l < ncol) x[j] = a.in[ib + (long)row * a.in_rs + l];
+    }
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int e = threadIdx.x + j * nthr;
+      const int row = e >> a.lw, l = e & (a.W - 1);
+      T* re = lds + l * a.LS;
+      re[P::pad(row)] = x[j].x;
+      re[a.PO + P::pad(row)] = x[j].y;
+    }
   }
-  fft_line<T, M, E, DIR>(v, lre, lim, t, a.tw);
+  __syncthreads();
+  {
+    const int l = threadIdx.x / TPL, t = threadIdx.x % TPL;
+    T* lre = lds + l * a.LS;
+    line_in_lds<T, M, E, DIR, PR == 1, PR == 2>(lre, lre + a.PO, t, a.tw);
+  }
+  __syncthreads();
+  const long obase = o * a.out_os + col0;
+  const int tot3 = a.n_out * a.W;   // at most ROWS_OUT * W
+  constexpr int ROWS_OUT = PR == 2 ? M / 2 : M;
 #pragma unroll
-  for (int sl = 0; sl < E; ++sl) {
-    const int row = t + TPL * P::jslot(sl);
-    if (h && row < a.n_out) a.out[o * a.out_os + (long)row * a.out_rs + col] = v[sl];
+  for (int j = 0; j < ROWS_OUT / TPL; ++j) {
+    const int e = threadIdx.x + j * nthr;
+    const int row = e >> a.lw, l = e & (a.W - 1);
+    if (e >= tot3 || l >= ncol) continue;
+    const T* re = lds + l * a.LS;
+    a.out[obase + (long)row * a.out_rs + l] = {re[P::pad(row)], re[a.PO + P::pad(row)]};
   }
 }
 
@@ -367,8 +469,8 @@ __global__ void __launch_bounds__(512) k_mid(MidArgs<T> a) {
   cx<T> v[E];
 #pragma unroll
   for (int j = 0; j < E; ++j) {
-    const int i = t + j * TPL;
-    v[j] = (h && i < a.n_in) ? base[i] : cx<T>{0, 0};
+    const int i = t + j * TPL;   // n_in <= M/2: slots j >= E/2 are zero
+    v[j] = (j < E / 2 && h && i < a.n_in) ? base[i] : cx<T>{0, 0};
   }
   fft_line<T, M, E, -1>(v, lre, lim, t, a.tw);
   // symbol row of this line
@@ -392,8 +494,8 @@ __global__ void __launch_bounds__(512) k_mid(MidArgs<T> a) {
   fft_line<T, M, E, +1>(v, lre, lim, t, a.tw);
 #pragma unroll
   for (int sl = 0; sl < E; ++sl) {
-    const int i = t + TPL * P::jslot(sl);
-    if (h && i < a.n_out) base[i] = v[sl];
+    const int i = t + TPL * P::jslot(sl);   // n_out <= M/2
+    if (P::jslot(sl) < E / 2 && h && i < a.n_out) base[i] = v[sl];
   }
 }
 
@@ -466,9 +568,9 @@ __global__ void __launch_bounds__(512) k_line1d(Line1Args<T> a) {
   cx<T> v[E];
 #pragma unroll
   for (int j = 0; j < E; ++j) {
-    const int i = t + j * TPL;
+    const int i = t + j * TPL;   // n <= M/2: slots j >= E/2 are zero
     T re = 0;
-    if (i < n) {
+    if (j < E / 2 && i < n) {
       if (a.mode == PM_CG) {
         re = a.r[base + i] + bt * a.p[base + i];
         a.p[base + i] = re;
@@ -490,7 +592,7 @@ __global__ void __launch_bounds__(512) k_line1d(Line1Args<T> a) {
 #pragma unroll
   for (int sl = 0; sl < E; ++sl) {
     const int i = t + TPL * P::jslot(sl);
-    if (i < n) {
+    if (P::jslot(sl) < E / 2 && i < n) {
       if (a.mode == PM_RESID) {
         const double q = a.f[base + i] - (double)v[sl].x;
         a.y[base + i] = (T)q;
@@ -578,42 +680,60 @@ inline long pair_tiles(long C, int W) { return ((C + 1) / 2 + W - 1) / W; }
 
 template <typename T>
 void launch_first(int M, int E, FirstArgs<T> a, int nrhs, hipStream_t st) {
+  if (!pow2(a.W) || a.n_in > M / 2) throw Error(2, "first pass: bad tile width or rows");
   a.ntiles = pair_tiles(a.C, a.W);
+  a.lw = ilog2i(a.W);
+  const TileLds tl = tile_lds(M, E, a.W, sizeof(T));
+  a.PO = tl.PO;
+  a.LS = tl.LS;
   dim3 grid((unsigned)(a.ntiles * nrhs));
   const int threads = a.W * (M / E);
-  const size_t sh = line_lds_bytes<T>(M, E) * a.W;
-  FL_DISPATCH(M, E, FL_LAUNCH((k_first<T, M, E>), grid, dim3(threads), sh, st, a));
+  FL_DISPATCH(M, E, FL_LAUNCH((k_first<T, M, E>), grid, dim3(threads), tl.bytes, st, a));
   check_launch("first pass");
 }
 
 template <typename T>
 void launch_last(int M, int E, LastArgs<T> a, int nrhs, hipStream_t st) {
+  if (!pow2(a.W) || a.n_out > M / 2) throw Error(2, "last pass: bad tile width or rows");
   a.ntiles = pair_tiles(a.C, a.W);
   if (a.mode != PM_PLAIN && a.ntiles > a.max_blocks)
     throw Error(2, "too many blocks for the reduction buffers");
+  a.lw = ilog2i(a.W);
+  const TileLds tl = tile_lds(M, E, a.W, sizeof(T));
+  a.PO = tl.PO;
+  a.LS = tl.LS;
   dim3 grid((unsigned)(a.ntiles * nrhs));
   const int threads = a.W * (M / E);
-  const size_t sh = line_lds_bytes<T>(M, E) * a.W;
-  FL_DISPATCH(M, E, FL_LAUNCH((k_last<T, M, E>), grid, dim3(threads), sh, st, a));
+  FL_DISPATCH(M, E, FL_LAUNCH((k_last<T, M, E>), grid, dim3(threads), tl.bytes, st, a));
   check_launch("last pass");
 }
 
 template <typename T>
 void launch_c2c(int M, int E, int dir, C2CArgs<T> a, long outer, hipStream_t st) {
+  if (!pow2(a.W)) throw Error(2, "c2c pass: bad tile width");
   a.ntiles = (a.C + a.W - 1) / a.W;
+  a.lw = ilog2i(a.W);
+  const TileLds tl = tile_lds(M, E, a.W, sizeof(T));
+  a.PO = tl.PO;
+  a.LS = tl.LS;
   dim3 grid((unsigned)(a.ntiles * outer));
   const int threads = a.W * (M / E);
-  const size_t sh = line_lds_bytes<T>(M, E) * a.W;
-  if (dir < 0) {
-    FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, -1>), grid, dim3(threads), sh, st, a));
+  const size_t sh = tl.bytes;
+  if (dir < 0 && a.n_in <= M / 2 && a.n_out == M) {
+    FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, -1, 1>), grid, dim3(threads), sh, st, a));
+  } else if (dir > 0 && a.n_in == M && a.n_out <= M / 2) {
+    FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, 1, 2>), grid, dim3(threads), sh, st, a));
+  } else if (dir < 0 && a.n_in == M && a.n_out == M) {
+    FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, -1, 0>), grid, dim3(threads), sh, st, a));
   } else {
-    FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, 1>), grid, dim3(threads), sh, st, a));
+    throw Error(2, "c2c pass: unsupported row ranges");
   }
   check_launch("c2c pass");
 }
 
 template <typename T>
 void launch_mid(int M, int E, const MidArgs<T>& a, int nrhs, hipStream_t st) {
+  if (a.n_in > M / 2 || a.n_out > M / 2) throw Error(2, "middle pass: rows beyond M/2");
   dim3 grid((unsigned)((a.rows + a.LPB - 1) / a.LPB), (unsigned)nrhs);
   const int threads = a.LPB * (M / E);
   const size_t sh = line_lds_bytes<T>(M, E) * a.LPB;
@@ -634,6 +754,7 @@ void launch_fwd_rows(int M, int E, cx<T>* data, long rows, int LPB, const cx<T>*
 
 template <typename T>
 void launch_line1d(int M, int E, const Line1Args<T>& a, hipStream_t st) {
+  if (a.n > M / 2) throw Error(2, "1D line: rows beyond M/2");
   dim3 grid((unsigned)a.nrhs);
   const int threads = M / E;
   const size_t sh = line_lds_bytes<T>(M, E);

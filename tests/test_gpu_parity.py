@@ -324,3 +324,20 @@ def test_precond_cuts_iterations():
     op.set_preconditioner(1)
     _, i1 = op.solve(f, tol=1e-10)
     assert i1[0]["iters"] * 3 < i0[0]["iters"], (i0, i1)
+
+
+@pytest.mark.parametrize("d,alpha,p,N", [(1, 1.5, 1, 256), (2, 1.0, 2, 64), (2, 1.9, 1, 32),
+                                         (3, 0.7, 1, 16)])
+def test_fp64_pcg_follows_oracle_pcg(d, alpha, p, N):
+    """FP64 preconditioned CG on the GPU takes the oracle's PCG steps: same
+    iteration count (within one, for rounding at the threshold) and the same
+    iterate to round-off growth."""
+    op = make_op(d, alpha, p, N)
+    f = inputs.uniform_rhs(d, N, 1, seed=12)
+    u, info = op.solve(torch.from_numpy(f).cuda(), tol=1e-10, mixed=0)
+    G = orc_gen(d, alpha, p, N)
+    ur, it, rel = oracle.solve_cg(G, f[0], tol=1e-10,
+                                  precond=lambda v: oracle.precond_apply(G, v))
+    print(f"  gpu iters {info[0]['iters']}, oracle iters {it}")
+    assert abs(info[0]["iters"] - it) <= 1
+    assert np.abs(u[0].cpu().numpy() - ur).max() <= 1e-8 * np.abs(ur).max()

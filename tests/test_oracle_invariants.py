@@ -259,6 +259,33 @@ def test_cg_matches_cholesky():
     assert np.abs(u1 - u2).max() <= 1e-10 * np.abs(u1).max()
 
 
+@pytest.mark.parametrize("d,N,alpha", [(1, 64, 1.5), (2, 16, 1.5), (2, 16, 0.5), (3, 6, 1.0)])
+def test_pcg_matches_cholesky_in_fewer_iterations(d, N, alpha):
+    """Preconditioned CG reaches the Cholesky solution, and the circulant
+    preconditioner cuts the iteration count of plain CG."""
+    rng = np.random.default_rng(6)
+    G = oracle.generator(d, alpha, 1, N)
+    f = rng.uniform(-1, 1, (N - 1,) * d)
+    u1 = oracle.solve_cholesky(G, f)
+    u0, it0, _ = oracle.solve_cg(G, f, tol=1e-12)
+    u2, it2, rel = oracle.solve_cg(G, f, tol=1e-12,
+                                   precond=lambda v: oracle.precond_apply(G, v))
+    assert rel <= 1e-12
+    assert np.abs(u1 - u2).max() <= 1e-9 * np.abs(u1).max()
+    assert it2 < it0
+
+
+def test_pcg_identity_preconditioner_is_cg():
+    """P = I reproduces plain CG step for step."""
+    rng = np.random.default_rng(7)
+    G = oracle.generator(2, 1.2, 1, 12)
+    f = rng.uniform(-1, 1, (11, 11))
+    a = oracle.solve_cg(G, f, tol=1e-12)
+    b = oracle.solve_cg(G, f, tol=1e-12, precond=lambda v: v.copy())
+    assert a[1] == b[1]
+    assert np.array_equal(a[0], b[0])
+
+
 @pytest.mark.parametrize("d,N", [(1, 16), (2, 8), (3, 4)])
 def test_precond_fft_matches_dense_circulant_inverse(d, N):
     """The FFT form of R C^{-1} R^T against a dense inverse of the dense
