@@ -27,6 +27,34 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0
+# Vector ALU peak without packed FP32 math (which this build does not emit):
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz; FP64 vector is the same.
+VALU_PEAK_TFLOPS = 78.6
+
+# HBM bytes per launch of the roofline kernels from rocprofv3 --pmc FETCH_SIZE
+# and WRITE_SIZE runs of `bench.py --roofline-only`, each scaled by what the
+# same counter reads for a device copy of known size in that run.  Keyed by
+# (kernel, precision, nrhs); valid only for the kernel sources they were
+# measured on (SHA-256 prefix of the transform-pass sources).
+TRAFFIC = {}
+TRAFFIC_SRC = None
+
+
+def pass_sources_hash():
+    import hashlib
+    root = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2103_03658_amd", "csrc")
+    h = hashlib.sha256()
+    for fn in ("fl_device.h", "passes_impl.h", "passes_host.h"):
+        with open(os.path.join(root, fn), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel, fp32, nrhs=17):
+    key = (kernel, "f32" if fp32 else "f64", nrhs)
+    if key not in TRAFFIC or TRAFFIC_SRC != pass_sources_hash():
+        return None
+    return TRAFFIC[key]
 METRIC = ("CG solves/s + p50/p99 latency (2D 511², tol 1e-10); "
           "FFT-matvec HBM GB/s")
 
@@ -40,9 +68,12 @@ def parse():
     ap.add_argument("--degree", type=int, default=2)
     ap.add_argument("--nrand", type=int, default=16)
     ap.add_argument("--tol", type=float, default=1e-10)
-    ap.add_argument("--path", choices=["reliable", "refine", "fp64"], default="reliable",
+    ap.add_argument("--path", choices=["reliable", "refine", "fp64"], default="fp64",
                     help="reliable: FP32 CG with FP64 reliable updates; refine: restarted FP32 "
                          "inner solves with FP64 refinement; fp64: FP64 CG")
+    ap.add_argument("--mixed-steps", type=int, default=3,
+                    help="timed batched solves of the mixed-precision path reported beside the "
+                         "headline path (0: skip)")
     ap.add_argument("--delta", type=float, default=None,
                     help="reliable path: residual reduction that triggers an FP64 update")
     ap.add_argument("--inner-tol", type=float, default=None,
@@ -101,6 +132,20 @@ def pass_bytes(d, N, nrhs, sr):
     mid = h * n * 2 * sr * nrhs
     sym = (N + 1) ** 2 * sr
     return [vec + mid, 2 * mid + sym, mid + vec]
+
+
+def pass_flops(d, N, nrhs):
+    """Nominal flops of each kernel of one batched 2D product: 5 M log2 M per
+    length-M complex transform, 2 per complex element for the symbol
+    multiply, 6 per output pair for the Hermitian split / merge."""
+    n, M = N - 1, 2 * N
+    h = M // 2 + 1
+    assert d == 2
+    fft = 5.0 * M * math.log2(M)
+    pairs = (n + 1) // 2
+    col = pairs * (fft + 6.0 * h)
+    mid = h * (2.0 * fft + 2.0 * M)
+    return [col * nrhs, mid * nrhs, col * nrhs]
 
 
 def cpu_baseline(N, degree, alpha, tol, budget):
@@ -179,7 +224,7 @@ def main():
     mixed = {"fp64": 0, "reliable": 1, "refine": 2}[args.path]
     if args.delta is not None or args.inner_tol is not None:
         for a in alphas:
-            ops[a].set_refinement(delta=args.delta if args.delta is not None else 0.1,
+            ops[a].set_refinement(delta=args.delta if args.delta is not None else 1e-3,
                                   inner_tol=args.inner_tol if args.inner_tol is not None else 1e-4)
 
     # launch schedules: tuned once per precision on one operator (same M for all)
@@ -204,14 +249,17 @@ def main():
                 dst.copy_(src)
             torch.cuda.synchronize()
             del src, dst
-        u32 = rhs[1.5].to(torch.float32).contiguous()
+        # the timed path's precision: FP64 unless a mixed path is selected
+        fp32 = mixed != 0
+        u_ = rhs[1.5].to(torch.float32).contiguous() if fp32 else rhs[1.5]
         acc = None
         for _ in range(max(1, args.steps)):
-            m = ops[1.5].profile_apply(u32, reps=args.profile_reps)
+            m = ops[1.5].profile_apply(u_, reps=args.profile_reps)
             acc = m if acc is None else [x + y for x, y in zip(acc, m)]
         ms = [x / max(1, args.steps) for x in acc]
-        by = pass_bytes(2, N, nrhs, 4)
-        print(json.dumps({"roofline_only": True, "ms_per_kernel": ms,
+        by = pass_bytes(2, N, nrhs, 4 if fp32 else 8)
+        print(json.dumps({"roofline_only": True, "precision": "f32" if fp32 else "f64",
+                          "ms_per_kernel": ms, "bytes_per_kernel": by,
                           "GBs": [b / (t * 1e-3) / 1e9 for b, t in zip(by, ms)],
                           "schedule": sched}))
         return
@@ -265,25 +313,57 @@ def main():
             diffs.append(float((umx - u64).abs().max() / u64.abs().max()))
         fp64["mixed_vs_fp64_rel_linf"] = max(diffs)
 
-    # roofline of the dominant FFT-matvec kernel (FP32, the inner-solve product)
+    # the mixed-precision path (FP32 CG, FP64 reliable updates) on the same batches
+    mixed_res = None
+    if args.mixed_steps > 0 and mixed != 1:
+        def mstep(k):
+            a = alphas[k % len(alphas)]
+            return ops[a].solve(rhs[a], tol=args.tol, mixed=1, out=out)[1]
+        mstep(0)
+        torch.cuda.synchronize()
+        mlat, minf = [], []
+        t0m = time.perf_counter()
+        for k in range(args.mixed_steps):
+            ts = time.perf_counter()
+            minf.append(mstep(k))
+            mlat.append(time.perf_counter() - ts)
+        torch.cuda.synchronize()
+        tm = time.perf_counter() - t0m
+        mixed_res = {"solves_per_s": args.mixed_steps * nrhs / tm,
+                     "p50_ms": float(np.percentile(np.array(mlat) * 1e3, 50)),
+                     "max_relres_true": max(i["relres_true"] for inf in minf for i in inf),
+                     "iters": {alphas[k % 3]: max(i["iters"] for i in minf[k])
+                               for k in range(min(3, args.mixed_steps))},
+                     "path": "FP32 CG with FP64 reliable updates"}
+
+    # roofline of the dominant kernel of the timed path: per-pass durations
+    # (HIP events on the operator's stream, each pass back to back) of the
+    # batched product in the timed precision, same operator and schedule
     a = 1.5
-    u32 = rhs[a].to(torch.float32).contiguous()
-    ms = ops[a].profile_apply(u32, reps=args.profile_reps)
-    by = pass_bytes(2, N, nrhs, 4)
     names = ["axis0_fwd_r2c", "last_axis_fwd_symbol_inv", "axis0_inv_c2r"]
-    gbs = [b / (t * 1e-3) / 1e9 for b, t in zip(by, ms)]
-    dom = int(np.argmax(ms))
-    ms64 = ops[a].profile_apply(rhs[a], reps=args.profile_reps)
-    by64 = pass_bytes(2, N, nrhs, 8)
-    roof = {"bound": "hbm", "achieved": gbs[dom], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": gbs[dom] / HBM_PEAK_GBS, "traffic": None,
-            "kernel": names[dom], "precision": "f32", "nrhs": nrhs,
-            "bytes_per_launch": by[dom], "ms_per_launch": ms[dom],
-            "per_kernel": [{"kernel": nm, "ms": t, "bytes": b, "GBs": g}
-                           for nm, t, b, g in zip(names, ms, by, gbs)],
-            "matvec_GBs_f32": sum(by) / (sum(ms) * 1e-3) / 1e9,
-            "matvec_GBs_f64": sum(by64) / (sum(ms64) * 1e-3) / 1e9,
-            "matvec_ms_f32": sum(ms), "matvec_ms_f64": sum(ms64)}
+
+    def passes(fp32):
+        u_ = rhs[a].to(torch.float32).contiguous() if fp32 else rhs[a]
+        ms_ = ops[a].profile_apply(u_, reps=args.profile_reps)
+        by_ = pass_bytes(2, N, nrhs, 4 if fp32 else 8)
+        fl_ = pass_flops(2, N, nrhs)
+        return [{"kernel": nm, "ms": t, "bytes": b, "GBs": b / (t * 1e-3) / 1e9,
+                 "flops": f, "TFLOPs": f / (t * 1e-3) / 1e12}
+                for nm, t, b, f in zip(names, ms_, by_, fl_)]
+
+    pk64, pk32 = passes(False), passes(True)
+    pk = pk32 if mixed else pk64
+    dom = max(range(3), key=lambda i: pk[i]["ms"])
+    kd = pk[dom]
+    roof = {"bound": "hbm", "achieved": kd["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": kd["GBs"] / HBM_PEAK_GBS, "traffic": traffic_for(kd["kernel"], bool(mixed), nrhs),
+            "kernel": kd["kernel"], "precision": "f32" if mixed else "f64", "nrhs": nrhs,
+            "bytes_per_launch": kd["bytes"], "ms_per_launch": kd["ms"],
+            "alu_TFLOPs": kd["TFLOPs"], "alu_peak_TFLOPs": VALU_PEAK_TFLOPS,
+            "alu_frac": kd["TFLOPs"] / VALU_PEAK_TFLOPS,
+            "per_kernel_f64": pk64, "per_kernel_f32": pk32,
+            "matvec_ms_f64": sum(k["ms"] for k in pk64),
+            "matvec_ms_f32": sum(k["ms"] for k in pk32)}
 
     serving = None
     if args.serve_requests > 0:
@@ -309,7 +389,8 @@ def main():
         "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
         "latency_unit": "ms per batched solve (all RHS of the batch complete)",
         "max_relres_true": max_relres, "iters": iters, "outer_iters": outers,
-        "setup_s": setup_s, "schedule": sched, "fp64_single": fp64, "serving": serving,
+        "setup_s": setup_s, "schedule": sched, "fp64_single": fp64, "mixed": mixed_res,
+        "serving": serving,
         "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(res))

@@ -127,7 +127,9 @@ fl_status fl_apply(fl_op A, const void *u, void *y, int nrhs, int fp32, void *st
  *           delta (fl_set_refinement) since the last update, the
  *           correction is added to the FP64 iterate and the residual is
  *           recomputed as r = f - A u with an FP64 product; stops when that
- *           FP64 residual meets tol.
+ *           FP64 residual meets tol.  The test runs every 8 iterations.
+ *           Preconditioned, the search direction restarts from the new
+ *           residual at each update.
  *           2: iterative refinement with restarts: FP32 CG solves A d = r to
  *           the relative tolerance inner_tol, u += d in FP64, r = f - A u in
  *           FP64, until the FP64 residual meets tol.
@@ -140,7 +142,7 @@ fl_status fl_apply(fl_op A, const void *u, void *y, int nrhs, int fp32, void *st
 fl_status fl_solve(fl_op A, const double *f, const double *g, double tol, int maxiter, int mixed,
                    double *u, int nrhs, fl_info *info, void *stream);
 
-/* Mixed-precision settings.  delta (default 0.1): a reliable update
+/* Mixed-precision settings.  delta (default 1e-3): a reliable update
  * (mixed = 1) happens once the FP32 residual norm has dropped below delta
  * times its value at the previous update.  inner_tol (default 1e-4):
  * relative tolerance of each FP32 inner solve of mixed = 2.  max_outer

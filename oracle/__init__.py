@@ -39,8 +39,8 @@ listed in each function's docstring (and collected in the design notes):
 """
 
 from .constants import c_dalpha, far_field_T, K_ball
-from .weights import weights
-from .operator import (origin_rule, coefficients, generator, dense_matrix,
+from .weights import weights, weights_at
+from .operator import (origin_rule, coefficients, generator, generator_at, dense_matrix,
                        apply_dense, apply_bttb, apply, apply_rows,
                        embed_generator, symbol, precond_apply,
                        exterior_b_1d, exterior_b_2d, grid_points)
@@ -48,8 +48,8 @@ from .solve import solve_cholesky, solve_cg
 from . import exact
 
 __all__ = [
-    "c_dalpha", "far_field_T", "K_ball", "weights", "origin_rule",
-    "coefficients", "generator", "dense_matrix", "apply_dense", "apply_bttb",
+    "c_dalpha", "far_field_T", "K_ball", "weights", "weights_at", "origin_rule",
+    "coefficients", "generator", "generator_at", "dense_matrix", "apply_dense", "apply_bttb",
     "apply", "apply_rows", "embed_generator", "symbol", "precond_apply", "exterior_b_1d", "exterior_b_2d",
     "grid_points", "solve_cholesky", "solve_cg", "exact",
 ]

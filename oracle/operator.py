@@ -101,6 +101,21 @@ def generator(d, alpha, p, N, lam=0.0, return_parts=False):
     return G
 
 
+def generator_at(d, alpha, p, N, nodes, lam=0.0):
+    """G_k = -c_{d,alpha} 2^{z(k)} omega_k / |xi_k|^2 at selected offsets
+    away from the origin correction (every node with |k|_1 > 2), d = 2, 3;
+    the same definitions as generator(), for sampled checks at large N."""
+    from .weights import weights_at
+    nodes = np.asarray(nodes, dtype=np.int64)
+    if (np.abs(nodes).sum(axis=1) <= 2).any():
+        raise ValueError("generator_at: offsets with |k|_1 <= 2 carry origin corrections")
+    h = 2.0 / N
+    om = weights_at(d, alpha, p, N, nodes, h=h, lam=lam)
+    z = (nodes == 0).sum(axis=1)
+    norm2 = (h * h) * (nodes.astype(np.float64) ** 2).sum(axis=1)
+    return -c_dalpha(d, alpha) * (2.0 ** z) * om / norm2 ** (GAMMA / 2.0)
+
+
 # ---------------------------------------------------------------------------
 # dense operator
 # ---------------------------------------------------------------------------

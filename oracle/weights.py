@@ -26,6 +26,7 @@ d pyramids xi = r (.., 1, ..) with Gauss-Jacobi in r for the weight r^{1-alpha}
 cone coordinates.
 """
 
+import itertools
 import math
 
 import mpmath
@@ -215,6 +216,47 @@ def _weights_nd(d, alpha, p, N, h, lam, Q=None):
     for idx in np.ndindex(*(nb,) * d):
         om[tuple(first[0] + i for i in idx)] += I0[idx]
     return om * h ** (2.0 - alpha)
+
+
+def weights_at(d, alpha, p, N, nodes, h=None, lam=0.0, Q=None):
+    """omega^p_k at selected multi-indices `nodes` (integer array (m, d)),
+    d = 2 or 3, by the same element quadrature as weights(): the sum over
+    the elements touching node k of int phi_k g.  For sampled checks at
+    sizes where the whole lattice is out of reach."""
+    if h is None:
+        h = 2.0 / N
+    if Q is None:
+        Q = 20 if d == 2 else 14
+    X, WB, first, els = _dim_tables(p, N, Q)
+    E, nb = WB.shape[0], WB.shape[1]
+    ex = 2.0 - d - alpha
+    I0 = _origin_element(d, alpha, p, h, lam, els)
+    X2 = X ** 2
+    out = np.zeros(len(nodes))
+    for m, k in enumerate(np.asarray(nodes, dtype=np.int64)):
+        # per axis: the (element, local basis index) pairs whose node is k_s
+        per = [[(e, a) for e in range(E) for a in range(nb) if first[e] + a == k[s]]
+               for s in range(d)]
+        total = 0.0
+        for combo in itertools.product(*per):
+            es = [e for e, _ in combo]
+            if all(e == 0 for e in es):
+                total += I0[tuple(a for _, a in combo)]
+                continue
+            r2 = X2[es[0]][:, None] + X2[es[1]][None, :]
+            if d == 3:
+                r2 = r2[:, :, None] + X2[es[2]][None, None, :]
+            r = np.sqrt(r2)
+            g = r ** ex
+            if lam:
+                g = g * np.exp(-lam * h * r)
+            wb = [WB[e, a] for e, a in combo]
+            if d == 2:
+                total += np.einsum("qr,q,r->", g, wb[0], wb[1])
+            else:
+                total += np.einsum("qrs,q,r,s->", g, wb[0], wb[1], wb[2])
+        out[m] = total
+    return out * h ** (2.0 - alpha)
 
 
 def weights(d, alpha, p, N, h=None, lam=0.0, Q=None):

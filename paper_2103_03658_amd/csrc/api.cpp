@@ -136,7 +136,7 @@ struct fl_op_s {
   const void* tw64 = nullptr;
   const void* tw32 = nullptr;
   fl::Schedule sc64{}, sc32{};
-  double delta = 0.1;       // reliable-update trigger (mixed = 1)
+  double delta = 1e-3;      // reliable-update trigger (mixed = 1)
   double inner_tol = 1e-4;  // inner solve tolerance (mixed = 2)
   int max_outer = 40;
   DBuf ws;                // FFT intermediates

@@ -55,7 +55,7 @@ void apply_passes_t(const Geometry& g, const Schedule& sc, const T* lam, const v
     if (go()) launch_first<T>(M, sc.E_first, a, nrhs, st);
   }
   if (g.d == 2) {
-    MidArgs<T> m{T1, lam, active, h, h * n, n, n, n, N1, 2, sc.LPB_mid, tw};
+    MidArgs<T> m{T1, lam, active, h, h * n, n, n, n, N1, 2, sc.LPB_mid, nrhs, tw};
     if (go()) launch_mid<T>(M, sc.E_mid, m, nrhs, st);
   } else {
     cx<T>* T2 = T1 + (long)nrhs * h * n * n;
@@ -63,7 +63,7 @@ void apply_passes_t(const Geometry& g, const Schedule& sc, const T* lam, const v
     C2CArgs<T> f1{T1, T2, active, n, (long)n * n, n, (long)M * n, n, 0, (int)h, n, M,
                   sc.W_c2c, 0, 0, 0, tw};
     if (go()) launch_c2c<T>(M, sc.E_c2c, -1, f1, (long)nrhs * h, st);
-    MidArgs<T> m{T2, lam, active, h * M, h * M * n, n, n, n, N1, 3, sc.LPB_mid, tw};
+    MidArgs<T> m{T2, lam, active, h * M, h * M * n, n, n, n, N1, 3, sc.LPB_mid, nrhs, tw};
     if (go()) launch_mid<T>(M, sc.E_mid, m, nrhs, st);
     C2CArgs<T> i1{T2, T1, active, n, (long)M * n, n, (long)n * n, n, 0, (int)h, M, n,
                   sc.W_c2c, 0, 0, 0, tw};

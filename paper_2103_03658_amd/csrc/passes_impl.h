@@ -449,6 +449,7 @@ struct MidArgs {
   int N1;                // N + 1
   int d;
   int LPB;
+  int nrhs;
   const cx<T>* tw;
 };
 
@@ -458,10 +459,15 @@ __global__ void __launch_bounds__(512) k_mid(MidArgs<T> a) {
   constexpr int TPL = P::TPL;
   extern __shared__ unsigned char smem_raw[];
   T* lds = reinterpret_cast<T*>(smem_raw);
-  const int o = blockIdx.y;
+  // right-hand side fastest within each XCD's contiguous range of blocks:
+  // all RHS of a row block run close together and share its symbol rows in
+  // that XCD's L2
+  long ol, rb;
+  xcd_tile(a.nrhs, ol, rb);
+  const int o = (int)ol;
   if (a.active && !a.active[o]) return;
   const int l = threadIdx.x / TPL, t = threadIdx.x % TPL;
-  const long line = (long)blockIdx.x * a.LPB + l;
+  const long line = rb * a.LPB + l;
   const bool h = line < a.rows;
   T* lre = lds + (long)l * 2 * P::LDSN;
   T* lim = lre + P::LDSN;
@@ -734,10 +740,12 @@ void launch_c2c(int M, int E, int dir, C2CArgs<T> a, long outer, hipStream_t st)
 template <typename T>
 void launch_mid(int M, int E, const MidArgs<T>& a, int nrhs, hipStream_t st) {
   if (a.n_in > M / 2 || a.n_out > M / 2) throw Error(2, "middle pass: rows beyond M/2");
-  dim3 grid((unsigned)((a.rows + a.LPB - 1) / a.LPB), (unsigned)nrhs);
+  MidArgs<T> b = a;
+  b.nrhs = nrhs;
+  dim3 grid((unsigned)(((a.rows + a.LPB - 1) / a.LPB) * nrhs));
   const int threads = a.LPB * (M / E);
   const size_t sh = line_lds_bytes<T>(M, E) * a.LPB;
-  FL_DISPATCH(M, E, FL_LAUNCH((k_mid<T, M, E>), grid, dim3(threads), sh, st, a));
+  FL_DISPATCH(M, E, FL_LAUNCH((k_mid<T, M, E>), grid, dim3(threads), sh, st, b));
   check_launch("middle pass");
 }
 

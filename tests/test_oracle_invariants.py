@@ -306,3 +306,41 @@ def test_precond_fft_matches_dense_circulant_inverse(d, N):
     y = np.linalg.solve(C, z.reshape(-1)).reshape((M,) * d)[(slice(0, n),) * d]
     np.testing.assert_allclose(oracle.precond_apply(G, v), y, rtol=1e-10,
                                atol=1e-12 * np.abs(y).max())
+
+
+@pytest.mark.parametrize("d,N", [(2, 8), (2, 12), (3, 4), (3, 6)])
+@pytest.mark.parametrize("p", [0, 1, 2])
+@pytest.mark.parametrize("lam", [0.0, 1.5])
+def test_weights_at_matches_full_lattice(d, N, p, lam):
+    """Per-node weights (for sampled checks at large N) equal the whole-lattice
+    computation at every node, origin element included."""
+    om = weights(d, 0.9, p, N, lam=lam)
+    nodes = np.indices((N + 1,) * d).reshape(d, -1).T
+    got = oracle.weights_at(d, 0.9, p, N, nodes, lam=lam)
+    np.testing.assert_allclose(got, om.reshape(-1), rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("d,N,p", [(2, 16, 2), (3, 6, 1)])
+def test_generator_at_matches_generator(d, N, p):
+    G = oracle.generator(d, 1.3, p, N, lam=0.7)
+    nodes = np.array([k for k in np.indices((N + 1,) * d).reshape(d, -1).T if k.sum() > 2])
+    got = oracle.generator_at(d, 1.3, p, N, nodes, lam=0.7)
+    np.testing.assert_allclose(got, G[tuple(nodes.T)], rtol=1e-13, atol=0)
+    with pytest.raises(ValueError):
+        oracle.generator_at(d, 1.3, p, N, np.array([[1] + [0] * (d - 1)]))
+
+
+@pytest.mark.parametrize("d,N,p,lam", [(1, 64, 1, 0.0), (2, 16, 2, 0.0), (2, 16, 1, 2.0),
+                                       (3, 6, 1, 0.0)])
+def test_full_stencil_sum_is_far_field(d, N, p, lam):
+    """Summing G over the whole symmetric stencil [-N, N]^d leaves only the
+    far-field term: c_{d,alpha} 2^d T_d (the scheme annihilates constants
+    except for the part of the kernel outside the truncation box)."""
+    alpha = 1.1
+    G = oracle.generator(d, alpha, p, N, lam=lam)
+    k = np.indices((N + 1,) * d).reshape(d, -1).T
+    mult = 2.0 ** (d - (k == 0).sum(axis=1))
+    total = math.fsum(mult * G.reshape(-1))
+    ref = c_dalpha(d, alpha) * 2 ** d * far_field_T(d, alpha, L=2.0, lam=lam)
+    scale = np.abs(G).max()
+    assert abs(total - ref) <= 1e-12 * scale * len(mult) ** 0.5
