@@ -36,8 +36,12 @@ VALU_PEAK_TFLOPS = 78.6
 # same counter reads for a device copy of known size in that run.  Keyed by
 # (kernel, precision, nrhs); valid only for the kernel sources they were
 # measured on (SHA-256 prefix of the transform-pass sources).
-TRAFFIC = {}
-TRAFFIC_SRC = None
+TRAFFIC = {
+    ("axis0_fwd_r2c", "f64", 17): 109881266,
+    ("last_axis_fwd_symbol_inv", "f64", 17): 145091015,
+    ("axis0_inv_c2r", "f64", 17): 109543374,
+}
+TRAFFIC_SRC = "5c1f27fc93c883a5"
 
 
 def pass_sources_hash():
@@ -352,6 +356,20 @@ def main():
                 for nm, t, b, f in zip(names, ms_, by_, fl_)]
 
     pk64, pk32 = passes(False), passes(True)
+
+    # a plain device copy of 1 GiB (read + write), HIP events on torch's stream
+    src = torch.ones((1 << 30) // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    copy_gbs = 5 * 2 * (1 << 30) / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+
     pk = pk32 if mixed else pk64
     dom = max(range(3), key=lambda i: pk[i]["ms"])
     kd = pk[dom]
@@ -361,6 +379,7 @@ def main():
             "bytes_per_launch": kd["bytes"], "ms_per_launch": kd["ms"],
             "alu_TFLOPs": kd["TFLOPs"], "alu_peak_TFLOPs": VALU_PEAK_TFLOPS,
             "alu_frac": kd["TFLOPs"] / VALU_PEAK_TFLOPS,
+            "copy_GBs": copy_gbs, "frac_of_copy": kd["GBs"] / copy_gbs,
             "per_kernel_f64": pk64, "per_kernel_f32": pk32,
             "matvec_ms_f64": sum(k["ms"] for k in pk64),
             "matvec_ms_f32": sum(k["ms"] for k in pk32)}

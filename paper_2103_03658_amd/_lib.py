@@ -75,6 +75,9 @@ def lib():
         if not os.path.exists(LIBPATH):
             raise RuntimeError(f"{LIBPATH} is not built; run "
                                "`python -m paper_2103_03658_amd.build` first")
+        # PyTorch provides the device memory and streams the library works
+        # on; load its HIP runtime first so that both share one runtime.
+        import torch  # noqa: F401
         handle = ctypes.CDLL(LIBPATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(handle, name)
