@@ -117,7 +117,9 @@ fl_status fl_apply(fl_op A, const void *u, void *y, int nrhs, int fp32, void *st
  * (A is symmetric positive definite, Sec. 2.2), circulant-preconditioned by
  * default (fl_set_preconditioner).
  *   f       device, nrhs * n^d doubles
- *   g       exterior data; must be NULL (g = 0).  Non-NULL: FL_E_UNSUPPORTED
+ *   g       device, nrhs * n^d doubles: the exterior-data term b of the scheme
+ *           (fl_exterior); the solve is then A u = f - b.  NULL: g = 0
+ *           outside Omega (b = 0).  Must not alias u.
  *   tol     stop when ||r||_2 <= tol ||f||_2 (per right-hand side), tol > 0
  *   maxiter CG iteration cap (mixed = 0, 1) / inner iteration cap per
  *           refinement step (mixed = 2), >= 1
@@ -141,6 +143,32 @@ fl_status fl_apply(fl_op A, const void *u, void *y, int nrhs, int fp32, void *st
  */
 fl_status fl_solve(fl_op A, const double *f, const double *g, double tol, int maxiter, int mixed,
                    double *u, int nrhs, fl_info *info, void *stream);
+
+/*
+ * fl_exterior -- the exterior-data term b of the scheme with nonhomogeneous
+ * data u = g outside Omega (Sec. 2.1 eq. (1D-scheme) and Sec. 2.2
+ * eq. (2D-scheme), the terms of the discrete operator that involve values of
+ * g; with them the discrete equation reads A u + b = f):
+ *   b_i = sum over lattice nodes j outside the interior with |j - i|_inf <= N
+ *           of G_{|j - i|} g(x_j)  -  c_{d,alpha} tail_i,
+ *   tail_i = sum over the 2^d sign patterns m of the integral over the far
+ *            field (xi >= 0 outside the box [0, L]^d, L = 2) of
+ *            g(x_i + (-1)^m o xi) K(|xi|) |xi|^{-d-alpha} d xi.
+ * The lattice sum runs on the GPU (a multilevel Toeplitz product of G with g
+ * on the node lattice, by circulant embedding in 4N points per axis for
+ * d = 2, directly for d = 1).  The far-field integrals need g beyond the
+ * lattice, which the library cannot evaluate: the caller supplies them.
+ *   g_lat  device, nrhs * (3N+1)^d doubles: g(x_j), x_j = -1 + j h for
+ *          j in [-N, 2N]^d, row-major, last index fastest (entries at
+ *          interior nodes are ignored)
+ *   tail   device, nrhs * n^d doubles (interior layout), or NULL (tail = 0)
+ *   b      device, nrhs * n^d doubles, output
+ * FL_E_UNSUPPORTED unless d = 1, or d = 2 with M = 2N <= 1024.  Same stream
+ * rules as fl_apply; allocates its transform buffers (2 (4N)^2 complex
+ * doubles for d = 2) on first use and keeps them with the operator.
+ */
+fl_status fl_exterior(fl_op A, const double *g_lat, const double *tail, double *b, int nrhs,
+                      void *stream);
 
 /* Mixed-precision settings.  delta (default 1e-3): a reliable update
  * (mixed = 1) happens once the FP32 residual norm has dropped below delta

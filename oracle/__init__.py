@@ -43,7 +43,9 @@ from .weights import weights, weights_at
 from .operator import (origin_rule, coefficients, generator, generator_at, dense_matrix,
                        apply_dense, apply_bttb, apply, apply_rows,
                        embed_generator, symbol, precond_apply,
-                       exterior_b_1d, exterior_b_2d, grid_points)
+                       exterior_b_1d, exterior_b_2d, exterior_lattice_1d,
+                       exterior_lattice_2d, far_field_tail_1d, far_field_tail_2d,
+                       grid_points)
 from .solve import solve_cholesky, solve_cg
 from . import exact
 
@@ -51,5 +53,6 @@ __all__ = [
     "c_dalpha", "far_field_T", "K_ball", "weights", "weights_at", "origin_rule",
     "coefficients", "generator", "generator_at", "dense_matrix", "apply_dense", "apply_bttb",
     "apply", "apply_rows", "embed_generator", "symbol", "precond_apply", "exterior_b_1d", "exterior_b_2d",
+    "exterior_lattice_1d", "exterior_lattice_2d", "far_field_tail_1d", "far_field_tail_2d",
     "grid_points", "solve_cholesky", "solve_cg", "exact",
 ]

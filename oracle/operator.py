@@ -240,48 +240,75 @@ def precond_apply(G, v, floor_rel=1e-12):
 # exterior data g != 0 (the b term of the paper)
 # ---------------------------------------------------------------------------
 
-def exterior_b_1d(G, g, alpha, lam=0.0):
-    """bold-b_i = sum over exterior nodes j (j <= 0 or j >= N, |j-i| <= N) of
-    G_{|j-i|} g(x_j) - c_{1,alpha} int_L^inf [g(x_i - xi) + g(x_i + xi)]
-    K(xi) xi^{-1-alpha} dxi   (eq. (1D-scheme) and the definition of b_i)."""
-    from scipy.integrate import quad
+def exterior_lattice_1d(G, g):
+    """Lattice part of bold-b_i: sum over exterior nodes j (j <= 0 or j >= N,
+    |j - i| <= N) of G_{|j-i|} g(x_j), x_j = -1 + j h (eq. (1D-scheme))."""
     N = G.shape[0] - 1
     h = 2.0 / N
-    L = 2.0
-    c = c_dalpha(1, alpha)
     out = np.zeros(N - 1)
     for i in range(1, N):
         s = 0.0
         for j in list(range(i - N, 1)) + list(range(N, i + N + 1)):
             s += G[abs(j - i)] * g(-1.0 + j * h)
-        xi = -1.0 + i * h
-        f = lambda t: (g(xi - t) + g(xi + t)) * t ** (-1.0 - alpha) * (
-            math.exp(-lam * t) if lam else 1.0)
-        tail = quad(f, L, np.inf, epsabs=1e-15, epsrel=1e-13, limit=400)[0]
-        out[i - 1] = s - c * tail
+        out[i - 1] = s
     return out
 
 
-def exterior_b_2d(G, g, alpha, nq=160):
-    """2D analogue (eq. (2D-scheme), definition of b_ij): the lattice sum of
-    G_{|k|} g over exterior nodes within the offset box, minus c_{2,alpha}
-    times  sum_m int_{Upsilon^c_+} g(x + (-1)^m o xi) |xi|^{-2-alpha} dxi.
-
-    The far-field region is split into {xi1 > L, xi2 < L}, {xi1 > L, xi2 > L},
-    {xi1 < L, xi2 > L}; on each unbounded axis xi = L/t, t in (0,1], and
-    tensor Gauss-Legendre (nq points per axis) is applied.  g must accept
-    numpy arrays (x1, x2)."""
-    N = G.shape[0] - 1
+def far_field_tail_1d(N, g, alpha, lam=0.0):
+    """tail_i = int_L^inf [g(x_i - xi) + g(x_i + xi)] K(xi) xi^{-1-alpha} dxi,
+    L = 2: the far-field integrals of bold-b_i (eq. (L2h))."""
+    from scipy.integrate import quad
     h = 2.0 / N
     L = 2.0
-    c = c_dalpha(2, alpha)
+    out = np.zeros(N - 1)
+    for i in range(1, N):
+        xi = -1.0 + i * h
+        f = lambda t: (g(xi - t) + g(xi + t)) * t ** (-1.0 - alpha) * (
+            math.exp(-lam * t) if lam else 1.0)
+        out[i - 1] = quad(f, L, np.inf, epsabs=1e-15, epsrel=1e-13, limit=400)[0]
+    return out
+
+
+def exterior_b_1d(G, g, alpha, lam=0.0):
+    """bold-b_i = lattice sum - c_{1,alpha} tail_i (eq. (1D-scheme) and the
+    definition of b_i)."""
+    N = G.shape[0] - 1
+    return exterior_lattice_1d(G, g) - c_dalpha(1, alpha) * far_field_tail_1d(N, g, alpha, lam)
+
+
+def exterior_lattice_2d(G, g):
+    """Lattice part of bold-b_ij (eq. (2D-scheme)): for every interior node,
+    the sum of G_{|k|} g(x_{i+k}) over the offsets k in [-N, N]^2 whose node
+    i + k is outside the interior.  g must accept numpy arrays (x1, x2)."""
+    N = G.shape[0] - 1
+    h = 2.0 / N
+    n = N - 1
+    k = np.arange(-N, N + 1)
+    Gs = G[np.abs(k)[:, None], np.abs(k)[None, :]]        # symmetric stencil
+    out = np.zeros((n, n))
+    for i in range(1, N):
+        a0 = i + k
+        for jj in range(1, N):
+            a1 = jj + k
+            inside = ((a0 >= 1) & (a0 <= N - 1))[:, None] & ((a1 >= 1) & (a1 <= N - 1))[None, :]
+            vals = g((-1.0 + a0 * h)[:, None], (-1.0 + a1 * h)[None, :])
+            out[i - 1, jj - 1] = math.fsum((Gs * vals)[~inside].ravel())
+    return out
+
+
+def far_field_tail_2d(N, g, alpha, nq=160):
+    """tail_ij = sum_m int_{Upsilon^c_+} g(x + (-1)^m o xi) |xi|^{-2-alpha} dxi
+    (the far-field integrals of bold-b_ij).  The region is split into
+    {xi1 > L, xi2 < L}, {xi1 > L, xi2 > L}, {xi1 < L, xi2 > L}; on each
+    unbounded axis xi = L/t, t in (0,1], and tensor Gauss-Legendre (nq points
+    per axis) is applied."""
+    h = 2.0 / N
+    L = 2.0
     n = N - 1
     xg, wg = np.polynomial.legendre.leggauss(nq)
-    # bounded axis [0, L]
-    sb = L * (xg + 1) / 2
+    sb = L * (xg + 1) / 2            # bounded axis [0, L]
     wb = wg * L / 2
-    # unbounded axis xi = L/t, t in (0,1]: dxi = L/t^2 dt
-    t = (xg + 1) / 2
+    t = (xg + 1) / 2                 # unbounded axis xi = L/t: dxi = L/t^2 dt
     su = L / t
     wu = (wg / 2) * L / t ** 2
     pieces = [(su, wu, sb, wb), (su, wu, su, wu), (sb, wb, su, wu)]
@@ -289,17 +316,6 @@ def exterior_b_2d(G, g, alpha, nq=160):
     out = np.zeros((n, n))
     for i in range(1, N):
         for jj in range(1, N):
-            # exterior lattice part
-            s = 0.0
-            for k0 in range(-N, N + 1):
-                a0 = i + k0
-                for k1 in range(-N, N + 1):
-                    a1 = jj + k1
-                    if 1 <= a0 <= N - 1 and 1 <= a1 <= N - 1:
-                        continue
-                    s += G[abs(k0), abs(k1)] * g(np.float64(-1.0 + a0 * h),
-                                                 np.float64(-1.0 + a1 * h))
-            # far field
             tail = 0.0
             for (s1, w1, s2, w2) in pieces:
                 X1, X2 = s1[:, None], s2[None, :]
@@ -307,5 +323,12 @@ def exterior_b_2d(G, g, alpha, nq=160):
                 for m1 in (1.0, -1.0):
                     for m2 in (1.0, -1.0):
                         tail += float((Wt * g(x[i] + m1 * X1, x[jj] + m2 * X2)).sum())
-            out[i - 1, jj - 1] = s - c * tail
+            out[i - 1, jj - 1] = tail
     return out
+
+
+def exterior_b_2d(G, g, alpha, nq=160):
+    """2D analogue (eq. (2D-scheme), definition of b_ij): lattice sum minus
+    c_{2,alpha} times the far-field integrals."""
+    N = G.shape[0] - 1
+    return exterior_lattice_2d(G, g) - c_dalpha(2, alpha) * far_field_tail_2d(N, g, alpha, nq)

@@ -90,19 +90,48 @@ class Operator:
                                  1 if u.dtype == torch.float32 else 0, _stream_ptr(stream)))
         return out
 
+    def exterior(self, g_lat, tail=None, out=None, stream=None):
+        """Exterior-data term b (fl_exterior): g_lat holds g on the node
+        lattice [-N, 2N]^d, shape (nrhs, 3N+1, ...); tail the far-field
+        integrals per interior point (nrhs, n, ...) or None."""
+        import torch
+        if g_lat.dtype != torch.float64 or not g_lat.is_contiguous():
+            raise TypeError("g_lat must be a contiguous float64 tensor")
+        L = 3 * self.N + 1
+        if g_lat.numel() % (L ** self.d):
+            raise ValueError(f"g_lat must hold nrhs * {L}^{self.d} values")
+        nrhs = g_lat.numel() // L ** self.d
+        if tail is not None and (tail.dtype != torch.float64 or tail.numel() != nrhs * self.nd
+                                 or not tail.is_contiguous()):
+            raise ValueError("tail must be a contiguous float64 tensor of nrhs * n^d values")
+        if out is None:
+            out = torch.empty((nrhs,) + (self.N - 1,) * self.d, dtype=torch.float64,
+                              device=g_lat.device)
+        check(self._lib.fl_exterior(self._h, ctypes.c_void_p(g_lat.data_ptr()),
+                                    ctypes.c_void_p(tail.data_ptr()) if tail is not None
+                                    else None, ctypes.c_void_p(out.data_ptr()), nrhs,
+                                    _stream_ptr(stream)))
+        return out
+
     def solve(self, f, tol=1e-10, maxiter=20000, mixed=False, out=None, stream=None,
-              raise_on_fail=True):
-        """u with A u = f by CG.  mixed: False/0 FP64; True/1 FP32 CG with FP64
+              raise_on_fail=True, b=None):
+        """u with A u = f - b by CG (b: the exterior-data term from exterior(),
+        or None for g = 0).  mixed: False/0 FP64; True/1 FP32 CG with FP64
         reliable updates; 2 FP32 inner solves with FP64 iterative refinement.
         Returns (u, list of per-RHS info dicts)."""
         import torch
         if f.dtype != torch.float64:
             raise TypeError("f must be float64")
         nrhs = self._nrhs(f)
+        if b is not None and (b.dtype != torch.float64 or b.shape != f.shape
+                              or not b.is_contiguous()):
+            raise ValueError("b must be a contiguous float64 tensor shaped like f")
         if out is None:
             out = torch.empty_like(f)
         info = (FlInfo * nrhs)()
-        st = self._lib.fl_solve(self._h, ctypes.c_void_p(f.data_ptr()), None, float(tol),
+        st = self._lib.fl_solve(self._h, ctypes.c_void_p(f.data_ptr()),
+                                ctypes.c_void_p(b.data_ptr()) if b is not None else None,
+                                float(tol),
                                 int(maxiter), int(mixed), ctypes.c_void_p(out.data_ptr()),
                                 nrhs, info, _stream_ptr(stream))
         infos = [i.as_dict() for i in info]

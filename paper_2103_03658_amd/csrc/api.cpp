@@ -153,6 +153,10 @@ struct fl_op_s {
   int* pinned = nullptr;
   ChunkGraph graph[2];    // captured CG chunks: FP64 (0), FP32 reliable (1)
   ChunkGraph glen[5];     // FP64 CG chunks of 1, 2, 4, 8, 16 iterations
+  DBuf ext_khat;          // transformed wrapped generator of the exterior term
+  DBuf ext_work;          // exterior-term transform workspace
+  bool ext_ready = false;
+  DBuf ext_rhs;           // f - b for solves with exterior data
   DBuf poll_dev;          // packed CG state for the host (device side)
   double* poll_host = nullptr;   // pinned copy
   size_t poll_cap = 0;
@@ -322,6 +326,9 @@ void fl_destroy(fl_op A) {
   for (auto& gph : A->graph) gph.reset();
   for (auto& gph : A->glen) gph.reset();
   A->poll_dev.release();
+  A->ext_khat.release();
+  A->ext_work.release();
+  A->ext_rhs.release();
   if (A->poll_host) hipHostFree(A->poll_host);
   if (A->ev_in) hipEventDestroy(A->ev_in);
   for (auto& e : A->ev_poll)
@@ -756,17 +763,38 @@ void sum_squares(fl_op A, const double* v, int nrhs, const fl::CgScalars& co, do
 
 }  // namespace
 
+extern "C" fl_status fl_exterior(fl_op A, const double* g_lat, const double* tail, double* b,
+                                 int nrhs, void* stream) {
+  return guarded([&]() -> fl_status {
+    if (!A) return fail(FL_E_INVAL, "null handle");
+    if (!g_lat || !b) return fail(FL_E_INVAL, "null argument");
+    if (nrhs < 1) return fail(FL_E_INVAL, "nrhs must be >= 1");
+    if (!fl::exterior_supported(A->g))
+      return fail(FL_E_UNSUPPORTED, "exterior data: supported for d = 1 and d = 2 with M <= 1024");
+    set_device(A);
+    hipStream_t st = (hipStream_t)stream;
+    A->begin(st);
+    const size_t kb = fl::exterior_khat_bytes(A->g);
+    void* kh = kb ? A->ext_khat.get(kb) : nullptr;
+    void* wk = kb ? A->ext_work.get(kb) : nullptr;
+    fl::exterior_term(A->g, A->G, A->c, g_lat, tail, b, nrhs, kh, A->ext_ready, wk, st);
+    A->ext_ready = kb != 0;
+    A->end(st);
+    return FL_OK;
+  });
+}
+
 extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double tol, int maxiter,
                               int mixed, double* u, int nrhs, fl_info* info, void* stream) {
   return guarded([&]() -> fl_status {
     if (!A) return fail(FL_E_INVAL, "null handle");
     if (!f || !u) return fail(FL_E_INVAL, "null vector");
-    if (g) return fail(FL_E_UNSUPPORTED, "nonzero exterior data g is not supported");
     if (!(tol > 0.0) || !std::isfinite(tol)) return fail(FL_E_INVAL, "tol must be positive");
     if (maxiter < 1) return fail(FL_E_INVAL, "maxiter must be >= 1");
     if (nrhs < 1) return fail(FL_E_INVAL, "nrhs must be >= 1");
     if (mixed < 0 || mixed > 2) return fail(FL_E_INVAL, "mixed must be 0, 1 or 2");
     if ((const void*)f == (const void*)u) return fail(FL_E_INVAL, "f and u must be distinct");
+    if (g && (const void*)g == (const void*)u) return fail(FL_E_INVAL, "g and u must be distinct");
     set_device(A);
     // work runs on the operator's own stream, ordered after `stream`
     hipStream_t user = (hipStream_t)stream;
@@ -777,6 +805,12 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
     A->begin(st);
     const long nd = A->g.nd;
     const size_t v8 = (size_t)nrhs * nd * sizeof(double);
+    if (g) {
+      // exterior term b: solve A u = f - b
+      double* fb = (double*)A->ext_rhs.get(v8);
+      fl::difference(f, g, fb, (long)nrhs * nd, st);
+      f = fb;
+    }
     const size_t v4 = (size_t)nrhs * nd * sizeof(float);
     const size_t a8 = ((v8 + 255) / 256) * 256, a4 = ((v4 + 255) / 256) * 256;
     std::vector<int> iters(nrhs, 0), outer(nrhs, 0), status(nrhs, 0);

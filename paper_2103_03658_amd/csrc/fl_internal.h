@@ -152,6 +152,20 @@ void build_generator(const GenParams& gp, double* G, hipStream_t st);
 void build_symbol(const Geometry& g, const double* G, double* lam64, float* lam32,
                   hipStream_t st);
 void embed_generator(const Geometry& g, const double* G, double* out, hipStream_t st);
+// Exterior-data term (exterior unit): b = lattice sum of G with g on
+// [-N, 2N]^d minus c * tail (tail may be null).  khat: the transformed
+// wrapped generator (exterior_khat_bytes), filled when !khat_ready; work:
+// the same size.  Supported for d = 1 and d = 2 with 2M <= 2048.
+bool exterior_supported(const Geometry& g);
+void difference(const double* a, const double* b, double* out, long n, hipStream_t st);
+size_t exterior_khat_bytes(const Geometry& g);
+void exterior_term(const Geometry& g, const double* G, double c, const double* g_lat,
+                   const double* tail, double* b, int nrhs, void* khat, bool khat_ready,
+                   void* work, hipStream_t st);
+
+// In-place unnormalised DFT (dir -1) or inverse (dir +1) of a P^d complex FP64
+// array (interleaved re, im), P a supported power of two.
+void fft_full(int P, int d, void* c, int dir, hipStream_t st);
 void build_inverse_symbol(const Geometry& g, const double* lam64, long nf, double* inv64,
                           float* inv32, double* scratch, hipStream_t st);
 

@@ -143,6 +143,35 @@ void build_inverse_symbol(const Geometry& g, const double* lam64, long nf, doubl
   check_launch("symbol inverse");
 }
 
+void fft_full(int P, int d, void* cv, int dir, hipStream_t st) {
+  cx<double>* c = reinterpret_cast<cx<double>*>(cv);
+  const cx<double>* tw = reinterpret_cast<const cx<double>*>(twiddles(P, false, st));
+  long total = 1;
+  for (int s = 0; s < d; ++s) total *= P;
+  const int E = P >= 16 ? 16 : 8;
+  const int TPL = P / E;
+  const size_t lb = line_lds_bytes<double>(P, E);
+  int W = 256 / TPL;
+  if (W < 1) W = 1;
+  while (W > 1 && tile_lds(P, E, W, sizeof(double)).bytes > 65536) W /= 2;
+  const long Pd1 = total / P;  // lines per axis
+  if (d >= 2) {
+    // axis 0: columns = P^(d-1), row stride P^(d-1)
+    C2CArgs<double> a0{c, c, nullptr, Pd1, 0, Pd1, 0, Pd1, 0, 1, P, P, W, 0, 0, 0, tw};
+    launch_c2c<double>(P, E, dir, a0, 1, st);
+  }
+  if (d == 3) {
+    // axis 1: slices k0 (stride P*P), rows stride P, columns P
+    C2CArgs<double> a1{c, c, nullptr, P, (long)P * P, P, (long)P * P, P, 0, 1, P, P, W, 0, 0, 0,
+                       tw};
+    launch_c2c<double>(P, E, dir, a1, P, st);
+  }
+  int LPB = 256 / TPL;
+  if (LPB < 1) LPB = 1;
+  while (LPB > 1 && lb * LPB > 65536) LPB /= 2;
+  launch_rows<double>(P, E, dir, c, Pd1, LPB, tw, st);
+}
+
 void build_symbol(const Geometry& g, const double* G, double* lam64, float* lam32,
                   hipStream_t st) {
   const int M = g.M, d = g.d;
@@ -154,28 +183,7 @@ void build_symbol(const Geometry& g, const double* G, double* lam64, float* lam3
   hipLaunchKernelGGL(k_embed, dim3((unsigned)((total + thr - 1) / thr)), dim3(thr), 0, st, c, G,
                      d, g.N, M, total);
   check_launch("embed");
-  const cx<double>* tw = reinterpret_cast<const cx<double>*>(twiddles(M, false, st));
-  const int E = M >= 16 ? 16 : 8;
-  const int TPL = M / E;
-  const size_t lb = line_lds_bytes<double>(M, E);
-  int W = 256 / TPL;
-  if (W < 1) W = 1;
-  while (W > 1 && tile_lds(M, E, W, sizeof(double)).bytes > 65536) W /= 2;
-  long Md1 = total / M;  // lines per axis
-  if (d >= 2) {
-    // axis 0: columns = M^(d-1), row stride M^(d-1)
-    C2CArgs<double> a0{c, c, nullptr, Md1, 0, Md1, 0, Md1, 0, 1, M, M, W, 0, 0, 0, tw};
-    launch_c2c<double>(M, E, -1, a0, 1, st);
-  }
-  if (d == 3) {
-    // axis 1: slices k0 (stride M*M), rows stride M, columns M
-    C2CArgs<double> a1{c, c, nullptr, M, (long)M * M, M, (long)M * M, M, 0, 1, M, M, W, 0, 0, 0, tw};
-    launch_c2c<double>(M, E, -1, a1, M, st);
-  }
-  int LPB = 256 / TPL;
-  if (LPB < 1) LPB = 1;
-  while (LPB > 1 && lb * LPB > 65536) LPB /= 2;
-  launch_fwd_rows<double>(M, E, c, Md1, LPB, tw, st);
+  fft_full(M, d, c, -1, st);
   long nf = 1;
   for (int s = 0; s < d; ++s) nf *= (g.N + 1);
   hipLaunchKernelGGL(k_fold, dim3((unsigned)((nf + thr - 1) / thr)), dim3(thr), 0, st, c, lam64,

@@ -505,10 +505,11 @@ __global__ void __launch_bounds__(512) k_mid(MidArgs<T> a) {
   }
 }
 
-// contiguous forward transform of full lines (symbol construction)
-template <typename T, int M, int E>
-__global__ void __launch_bounds__(512) k_fwd_rows(cx<T>* data, long rows, int LPB,
-                                                  const cx<T>* tw) {
+// contiguous transform of full lines in place (symbol construction, exterior
+// term); DIR -1 forward, +1 inverse (unnormalised)
+template <typename T, int M, int E, int DIR>
+__global__ void __launch_bounds__(512) k_rows(cx<T>* data, long rows, int LPB,
+                                              const cx<T>* tw) {
   using P = Plan<M, E>;
   constexpr int TPL = P::TPL;
   extern __shared__ unsigned char smem_raw[];
@@ -522,7 +523,7 @@ __global__ void __launch_bounds__(512) k_fwd_rows(cx<T>* data, long rows, int LP
   cx<T> v[E];
 #pragma unroll
   for (int j = 0; j < E; ++j) v[j] = h ? base[t + j * TPL] : cx<T>{0, 0};
-  fft_line<T, M, E, -1>(v, lre, lim, t, tw);
+  fft_line<T, M, E, DIR>(v, lre, lim, t, tw);
 #pragma unroll
   for (int sl = 0; sl < E; ++sl)
     if (h) base[t + TPL * P::jslot(sl)] = v[sl];
@@ -731,6 +732,8 @@ void launch_c2c(int M, int E, int dir, C2CArgs<T> a, long outer, hipStream_t st)
     FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, 1, 2>), grid, dim3(threads), sh, st, a));
   } else if (dir < 0 && a.n_in == M && a.n_out == M) {
     FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, -1, 0>), grid, dim3(threads), sh, st, a));
+  } else if (dir > 0 && a.n_in == M && a.n_out == M) {
+    FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, 1, 0>), grid, dim3(threads), sh, st, a));
   } else {
     throw Error(2, "c2c pass: unsupported row ranges");
   }
@@ -750,13 +753,18 @@ void launch_mid(int M, int E, const MidArgs<T>& a, int nrhs, hipStream_t st) {
 }
 
 template <typename T>
-void launch_fwd_rows(int M, int E, cx<T>* data, long rows, int LPB, const cx<T>* tw,
-                     hipStream_t st) {
+void launch_rows(int M, int E, int dir, cx<T>* data, long rows, int LPB, const cx<T>* tw,
+                 hipStream_t st) {
   dim3 grid((unsigned)((rows + LPB - 1) / LPB));
   const int threads = LPB * (M / E);
   const size_t sh = line_lds_bytes<T>(M, E) * LPB;
-  FL_DISPATCH(M, E, FL_LAUNCH((k_fwd_rows<T, M, E>), grid, dim3(threads), sh, st, data, rows,
-                              LPB, tw));
+  if (dir < 0) {
+    FL_DISPATCH(M, E, FL_LAUNCH((k_rows<T, M, E, -1>), grid, dim3(threads), sh, st, data, rows,
+                                LPB, tw));
+  } else {
+    FL_DISPATCH(M, E, FL_LAUNCH((k_rows<T, M, E, 1>), grid, dim3(threads), sh, st, data, rows,
+                                LPB, tw));
+  }
   check_launch("row transform");
 }
 

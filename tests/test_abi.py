@@ -110,3 +110,8 @@ def test_manufactured_rhs_matches_closed_form():
         ref = ex.frac_lap_ball_power(r2[inside], 1 + alpha / 2, alpha, 2)
         np.testing.assert_allclose(f[inside], ref, rtol=1e-13)
         assert (f[~inside] == 0).all()
+
+
+def test_exterior_null_and_unsupported():
+    lib = _lib.lib()
+    assert lib.fl_exterior(None, None, None, None, 1, None) == _lib.FL_E_INVAL
