@@ -100,6 +100,9 @@ def parse():
                     help="requests of the serving stream (Poisson arrivals at 200/s; the full "
                          "stream is 4096; 0: skip)")
     ap.add_argument("--serve-workers", type=int, default=4)
+    ap.add_argument("--configs", type=int, default=1,
+                    help="1: also measure the 1D, 2D 255^2, 3D 127^3 and tempered 1023^2 "
+                         "workloads (a few seconds); 0: skip")
     ap.add_argument("--serve-only", action="store_true")
     return ap.parse_args()
 
@@ -150,6 +153,92 @@ def pass_flops(d, N, nrhs):
     col = pairs * (fft + 6.0 * h)
     mid = h * (2.0 * fft + 2.0 * M)
     return [col * nrhs, mid * nrhs, col * nrhs]
+
+
+def run_configs(dev, tol, quick=False):
+    """The other workloads of the method at their full sizes (not the headline
+    metric): per config, solves/s or latency, iterations, true residuals; and
+    FFT-matvec rates on the large-working-set shapes (tempered 1023^2 x 64
+    RHS FP32, 3D 127^3 x 8 RHS FP32)."""
+    import torch
+    import paper_2103_03658_amd as fl
+    from paper_2103_03658_amd import inputs, tune
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, r
+
+    out = {}
+    # C1: 1D, N = 1024 (h = 1/512), alpha = 1.5, p = 1, FP64, tol 1e-12
+    op = fl.Operator(1, 1.5, 1, N=1024)
+    f = torch.from_numpy(np.stack([np.full(1023, math.gamma(2.5)),
+                                   inputs.uniform_rhs(1, 1024, 1, seed=0)[0]])).to(dev)
+    t, (u, inf) = timed(lambda: op.solve(f, tol=1e-12), 5)
+    out["C1_1d_N1024"] = {"ms_per_batched_solve": 1e3 * t, "nrhs": 2,
+                          "iters": [i["iters"] for i in inf],
+                          "relres_true": [i["relres_true"] for i in inf]}
+    op.close()
+    # C2: 2D 255^2, p = 2, 17 RHS, FP64 PCG, tol 1e-10
+    c2 = {}
+    for a in (0.5, 1.0, 1.5):
+        op = fl.Operator(2, a, 2, N=256)
+        tune.tune(op, 17, False, use_cache=False)
+        f = torch.from_numpy(np.concatenate([inputs.manufactured_rhs_disk(256, a)[None],
+                                             inputs.uniform_rhs(2, 256, 16, seed=0)])).to(dev)
+        t, (u, inf) = timed(lambda: op.solve(f, tol=tol), 3)
+        c2[str(a)] = {"solves_per_s": 17 / t, "iters": max(i["iters"] for i in inf),
+                      "max_relres_true": max(i["relres_true"] for i in inf)}
+        op.close()
+    out["C2_2d_255_fp64_17rhs"] = c2
+    # C3: 3D 127^3, alpha = 1, p = 1, N(0,1) seed 3, mixed precision; FP64 as reference
+    op = fl.Operator(3, 1.0, 1, N=128)
+    for fp32 in (True, False):
+        tune.tune(op, 1, fp32, use_cache=False)
+    f = torch.from_numpy(inputs.normal_rhs(3, 128, 1, seed=3)).to(dev)
+    tm, (um, im) = timed(lambda: op.solve(f, tol=tol, mixed=1), 3)
+    t6, (u6, i6) = timed(lambda: op.solve(f, tol=tol, mixed=0), 3)
+    u8 = torch.from_numpy(inputs.normal_rhs(3, 128, 8, seed=3).astype(np.float32)).to(dev)
+    ms3 = op.profile_apply(u8, reps=10)
+    # per RHS: n^3 real in and out, and h n^2 (axis 0) and h M n (axis 1) complex
+    # lines each written and read twice; the folded symbol once per product
+    n3, M3 = 127, 256
+    h3 = M3 // 2 + 1
+    by3 = 8 * 4 * (2 * n3 ** 3 + 8 * (h3 * n3 * n3 + h3 * M3 * n3)) + 129 ** 3 * 4
+    out["C3_3d_127"] = {"mixed_s_per_solve": tm, "fp64_s_per_solve": t6,
+                        "mixed_iters": im[0]["iters"], "mixed_updates": im[0]["outer_iters"],
+                        "fp64_iters": i6[0]["iters"], "relres_true_mixed": im[0]["relres_true"],
+                        "mixed_vs_fp64_rel_linf": float((um - u6).abs().max() / u6.abs().max()),
+                        "matvec_fp32_8rhs_ms": sum(ms3),
+                        "matvec_fp32_8rhs_GBs": by3 / (sum(ms3) * 1e-3) / 1e9,
+                        "matvec_ms_per_pass": ms3}
+    op.close()
+    # C5: tempered 2D 1023^2, alpha = 1.2, p = 1, 64 N(0,1) RHS per lambda, mixed to tol
+    c5 = {}
+    f = torch.from_numpy(inputs.normal_rhs(2, 1024, 64, seed=0)).to(dev)
+    for lam in ((1.0,) if quick else (0.5, 1.0, 5.0)):
+        op = fl.Operator(2, 1.2, 1, N=1024, kernel="tempered", lam=lam)
+        best32, _ = tune.tune(op, 64, True, use_cache=False)
+        tune.tune(op, 64, False, use_cache=False)
+        t, (u, inf) = timed(lambda: op.solve(f, tol=tol, mixed=1), 1)
+        t64, (u64, inf64) = timed(lambda: op.solve(f, tol=tol, mixed=0), 1)
+        ms5 = op.profile_apply(f.to(torch.float32), reps=10)
+        by5 = pass_bytes(2, 1024, 64, 4)
+        c5[str(lam)] = {"mixed_solves_per_s": 64 / t, "fp64_solves_per_s": 64 / t64,
+                        "mixed_iters": max(i["iters"] for i in inf),
+                        "fp64_iters": max(i["iters"] for i in inf64),
+                        "max_relres_true_mixed": max(i["relres_true"] for i in inf),
+                        "schedule_f32": best32,
+                        "matvec_fp32_64rhs_ms": sum(ms5),
+                        "matvec_fp32_64rhs_GBs": sum(by5) / (sum(ms5) * 1e-3) / 1e9,
+                        "per_pass_GBs": [b / (m * 1e-3) / 1e9 for b, m in zip(by5, ms5)]}
+        op.close()
+    out["C5_tempered_1023_64rhs"] = c5
+    return out
 
 
 def cpu_baseline(N, degree, alpha, tol, budget):
@@ -384,6 +473,8 @@ def main():
             "matvec_ms_f64": sum(k["ms"] for k in pk64),
             "matvec_ms_f32": sum(k["ms"] for k in pk32)}
 
+    configs = run_configs(dev, args.tol) if args.configs else None
+
     serving = None
     if args.serve_requests > 0:
         serving = run_serving(args.serve_requests, args.serve_workers, args.tol)
@@ -409,7 +500,7 @@ def main():
         "latency_unit": "ms per batched solve (all RHS of the batch complete)",
         "max_relres_true": max_relres, "iters": iters, "outer_iters": outers,
         "setup_s": setup_s, "schedule": sched, "fp64_single": fp64, "mixed": mixed_res,
-        "serving": serving,
+        "serving": serving, "configs": configs,
         "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(res))

@@ -42,7 +42,8 @@ from .constants import c_dalpha, far_field_T, K_ball
 from .weights import weights, weights_at
 from .operator import (origin_rule, coefficients, generator, generator_at, dense_matrix,
                        apply_dense, apply_bttb, apply, apply_rows,
-                       embed_generator, symbol, precond_apply,
+                       embed_generator, symbol, precond_apply, tau_symbol,
+                       tau_precond_apply,
                        exterior_b_1d, exterior_b_2d, exterior_lattice_1d,
                        exterior_lattice_2d, far_field_tail_1d, far_field_tail_2d,
                        grid_points)
@@ -52,7 +53,7 @@ from . import exact
 __all__ = [
     "c_dalpha", "far_field_T", "K_ball", "weights", "weights_at", "origin_rule",
     "coefficients", "generator", "generator_at", "dense_matrix", "apply_dense", "apply_bttb",
-    "apply", "apply_rows", "embed_generator", "symbol", "precond_apply", "exterior_b_1d", "exterior_b_2d",
+    "apply", "apply_rows", "embed_generator", "symbol", "precond_apply", "tau_symbol", "tau_precond_apply", "exterior_b_1d", "exterior_b_2d",
     "exterior_lattice_1d", "exterior_lattice_2d", "far_field_tail_1d", "far_field_tail_2d",
     "grid_points", "solve_cholesky", "solve_cg", "exact",
 ]

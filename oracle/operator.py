@@ -240,6 +240,57 @@ def precond_apply(G, v, floor_rel=1e-12):
 # exterior data g != 0 (the b term of the paper)
 # ---------------------------------------------------------------------------
 
+def tau_symbol(G):
+    """Eigenvalues of the natural tau approximation of the multilevel Toeplitz
+    matrix A (entries G_{|i-j|}): tau(T) = T - H(T) on every level, H(T) the
+    Hankel matrix with first row (t_2, ..., t_{n-1}, 0, 0) and last row its
+    reverse.  tau(T) is diagonalised by the sine transform S_{jk} =
+    sin(pi j k / (n+1)), j, k = 1..n, on each axis; its first column is
+    c = t - (t shifted by two) on each level, so lam = (S..S c) / prod_s
+    sin(pi k_s / (n+1)).  Dense sine matrices, shape (n,)*d."""
+    d = G.ndim
+    n = G.shape[0] - 2
+    c = np.array(G[(slice(0, n),) * d], dtype=np.float64)
+    for ax in range(d):
+        a = [slice(None)] * d
+        b = [slice(None)] * d
+        a[ax] = slice(0, n - 2)
+        b[ax] = slice(2, n)
+        c2 = c.copy()
+        c2[tuple(a)] -= c[tuple(b)]
+        c = c2
+    k = np.arange(1, n + 1)
+    S = np.sin(np.pi * np.outer(k, k) / (n + 1))
+    y = c
+    for ax in range(d):
+        y = np.moveaxis(np.tensordot(S, y, axes=([1], [ax])), 0, ax)
+    s1 = S[:, 0]
+    den = np.ones((n,) * d)
+    for ax in range(d):
+        shp = [1] * d
+        shp[ax] = n
+        den = den * s1.reshape(shp)
+    return y / den
+
+
+def tau_precond_apply(G, v, floor_rel=1e-12):
+    """tau(T)^{-1} v = (2/(n+1))^d S..S diag(1/lam) S..S v with the dense sine
+    matrices (S^2 = (n+1)/2 I); lam floored at floor_rel * max lam."""
+    d = G.ndim
+    n = G.shape[0] - 2
+    lam = tau_symbol(G)
+    lam = np.maximum(lam, floor_rel * lam.max())
+    k = np.arange(1, n + 1)
+    S = np.sin(np.pi * np.outer(k, k) / (n + 1))
+    y = np.array(v, dtype=np.float64)
+    for ax in range(d):
+        y = np.moveaxis(np.tensordot(S, y, axes=([1], [ax])), 0, ax)
+    y = y / lam
+    for ax in range(d):
+        y = np.moveaxis(np.tensordot(S, y, axes=([1], [ax])), 0, ax)
+    return y * (2.0 / (n + 1)) ** d
+
+
 def exterior_lattice_1d(G, g):
     """Lattice part of bold-b_i: sum over exterior nodes j (j <= 0 or j >= N,
     |j - i| <= N) of G_{|j-i|} g(x_j), x_j = -1 + j h (eq. (1D-scheme))."""

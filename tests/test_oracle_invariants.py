@@ -344,3 +344,89 @@ def test_full_stencil_sum_is_far_field(d, N, p, lam):
     ref = c_dalpha(d, alpha) * 2 ** d * far_field_T(d, alpha, L=2.0, lam=lam)
     scale = np.abs(G).max()
     assert abs(total - ref) <= 1e-12 * scale * len(mult) ** 0.5
+
+
+def _hankel_tau_1d(t):
+    """tau(T) = T - H from the definition: H_{ij} = t_{i+j+2} (first row
+    t_2 .. t_{n-1}, 0, 0) plus its persymmetric image t_{2n-i-j} (last row
+    0, 0, t_{n-1} .. t_2), 0-based indices, t_k = 0 for k > n - 1."""
+    n = len(t)
+    T = np.array([[t[abs(i - j)] for j in range(n)] for i in range(n)])
+    H = np.zeros((n, n))
+    for i in range(n):
+        for j in range(n):
+            if i + j + 2 <= n - 1:
+                H[i, j] += t[i + j + 2]
+            if 2 * n - i - j <= n - 1:
+                H[i, j] += t[2 * n - i - j]
+    return T - H
+
+
+@pytest.mark.parametrize("alpha,p", [(0.5, 1), (1.5, 2), (1.9, 0)])
+def test_tau_symbol_1d_is_spectrum_of_t_minus_hankel(alpha, p):
+    N = 16
+    G = oracle.generator(1, alpha, p, N)
+    n = N - 1
+    tau = _hankel_tau_1d(G[:n])
+    lam = oracle.tau_symbol(G)
+    k = np.arange(1, n + 1)
+    S = np.sin(np.pi * np.outer(k, k) / N) * np.sqrt(2.0 / N)   # orthogonal
+    np.testing.assert_allclose(S @ np.diag(lam) @ S, tau, atol=1e-12 * np.abs(tau).max())
+    np.testing.assert_allclose(np.sort(np.linalg.eigvalsh(tau)), np.sort(lam),
+                               rtol=1e-11, atol=1e-12 * lam.max())
+
+
+def test_tau_symbol_2d_is_spectrum_of_tensor_tau():
+    """2-level: tau(T) = sum_ab t_ab tau(B_a) (x) tau(B_b), B_a the Toeplitz
+    basis matrix of offset a, built densely; its eigen-decomposition in the
+    2D sine basis has the oracle's eigenvalues."""
+    N, alpha = 8, 1.2
+    G = oracle.generator(2, alpha, 1, N)
+    n = N - 1
+    taus = []
+    for a in range(n):
+        e = np.zeros(n)
+        e[a] = 1.0
+        taus.append(_hankel_tau_1d(e))
+    tau = sum(G[a, b] * np.kron(taus[a], taus[b]) for a in range(n) for b in range(n))
+    k = np.arange(1, n + 1)
+    S = np.sin(np.pi * np.outer(k, k) / N) * np.sqrt(2.0 / N)
+    S2 = np.kron(S, S)
+    lam = oracle.tau_symbol(G).reshape(-1)
+    np.testing.assert_allclose(S2 @ np.diag(lam) @ S2, tau, atol=1e-12 * np.abs(tau).max())
+
+
+@pytest.mark.parametrize("d,N", [(1, 32), (2, 16), (3, 8)])
+def test_tau_precond_inverts_tau(d, N):
+    G = oracle.generator(d, 1.3, 1, N)
+    n = N - 1
+    rng = np.random.default_rng(2)
+    v = rng.uniform(-1, 1, (n,) * d)
+    z = oracle.tau_precond_apply(G, v)
+    # apply tau(T) to z through its spectrum with an independent FFT-free path:
+    # tau(T) z = (2/N)^d S (lam * S z)
+    lam = oracle.tau_symbol(G)
+    k = np.arange(1, n + 1)
+    S = np.sin(np.pi * np.outer(k, k) / N)
+    y = z
+    for ax in range(d):
+        y = np.moveaxis(np.tensordot(S, y, axes=([1], [ax])), 0, ax)
+    y = y * lam
+    for ax in range(d):
+        y = np.moveaxis(np.tensordot(S, y, axes=([1], [ax])), 0, ax)
+    np.testing.assert_allclose(y * (2.0 / N) ** d, v, atol=1e-10)
+
+
+@pytest.mark.parametrize("d,N,alpha", [(1, 64, 1.5), (2, 16, 1.9), (2, 32, 1.0), (3, 8, 1.5)])
+def test_tau_pcg_matches_cholesky(d, N, alpha):
+    rng = np.random.default_rng(9)
+    G = oracle.generator(d, alpha, 1, N)
+    f = rng.uniform(-1, 1, (N - 1,) * d)
+    u1 = oracle.solve_cholesky(G, f)
+    u2, it, rel = oracle.solve_cg(G, f, tol=1e-12,
+                                  precond=lambda v: oracle.tau_precond_apply(G, v))
+    assert rel <= 1e-12
+    assert np.abs(u1 - u2).max() <= 1e-9 * np.abs(u1).max()
+    _, it_emb, _ = oracle.solve_cg(G, f, tol=1e-12,
+                                   precond=lambda v: oracle.precond_apply(G, v))
+    assert it <= it_emb + 1
