@@ -209,16 +209,24 @@ fl_status fl_profile_apply(fl_op A, const void *u, void *y, int nrhs, int fp32, 
                            void *stream, double *ms_per_pass, int max_passes, int *n_passes);
 
 /*
- * Preconditioning of fl_solve: kind 1 (default) uses P = R C^{-1} R^T, the
- * restriction to the n^d interior of the inverse of the embedding circulant
- * C (symbol 1 / max(lambda-hat, 1e-12 max lambda-hat), so P is symmetric
- * positive definite); kind 0 is plain CG.  Either way the stopping rule is
- * the relative residual ||r||_2 <= tol ||f||_2.  FL_E_INVAL for other kinds.
+ * Preconditioning of fl_solve (the paper names no solver; A is SPD, Sec. 2.2):
+ *   kind 2 (default): P = tau(A)^{-1}, the inverse of the natural tau
+ *     approximation of the multilevel Toeplitz matrix (A minus its Hankel
+ *     part on every level), diagonalised by the sine transform of each axis
+ *     and applied with the same transform passes on odd-extended lines;
+ *   kind 1: P = R C^{-1} R^T, the restriction to the n^d interior of the
+ *     inverse of the embedding circulant C (symbol 1 / max(lambda-hat,
+ *     1e-12 max lambda-hat));
+ *   kind 0: plain CG.
+ * Both preconditioners are symmetric positive definite (eigenvalues floored
+ * at 1e-12 of the largest).  The stopping rule is the relative residual
+ * ||r||_2 <= tol ||f||_2 either way.  FL_E_INVAL for other kinds.
  */
 fl_status fl_set_preconditioner(fl_op A, int kind);
 
-/* y = P u for nrhs right-hand sides (same layout, precision and stream
- * rules as fl_apply).  Test hook for the preconditioner. */
+/* y = P u for nrhs right-hand sides with the selected preconditioner (same
+ * layout, precision and stream rules as fl_apply).  FL_E_INVAL with kind 0.
+ * Test hook for the preconditioners. */
 fl_status fl_apply_precond(fl_op A, const void *u, void *y, int nrhs, int fp32, void *stream);
 
 /* Replay CG iteration chunks from captured HIP graphs (enable = 1, the

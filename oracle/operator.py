@@ -245,32 +245,25 @@ def tau_symbol(G):
     matrix A (entries G_{|i-j|}): tau(T) = T - H(T) on every level, H(T) the
     Hankel matrix with first row (t_2, ..., t_{n-1}, 0, 0) and last row its
     reverse.  tau(T) is diagonalised by the sine transform S_{jk} =
-    sin(pi j k / (n+1)), j, k = 1..n, on each axis; its first column is
-    c = t - (t shifted by two) on each level, so lam = (S..S c) / prod_s
-    sin(pi k_s / (n+1)).  Dense sine matrices, shape (n,)*d."""
+    sin(pi j k / (n+1)), j, k = 1..n, on each axis; with its first column
+    c = t - (t shifted by two) on each level the eigenvalues are
+    (S..S c)(k) / prod_s sin(theta_{k_s}), theta_k = pi k / (n+1), which
+    telescopes (U_j - U_{j-2} = 2 cos(j theta) for the Chebyshev quotients
+    U_j = sin((j+1) theta) / sin(theta)) into the truncated cosine series
+        lam(k) = sum_{j in [0, n-1]^d} t_j prod_s w(j_s) cos(j_s theta_{k_s}),
+    w(0) = 1, w(j) = 2; summed in this form (dense cosine matrices), which
+    keeps its accuracy near theta = 0 and pi where the sine quotient loses
+    digits.  Shape (n,)*d."""
     d = G.ndim
     n = G.shape[0] - 2
-    c = np.array(G[(slice(0, n),) * d], dtype=np.float64)
-    for ax in range(d):
-        a = [slice(None)] * d
-        b = [slice(None)] * d
-        a[ax] = slice(0, n - 2)
-        b[ax] = slice(2, n)
-        c2 = c.copy()
-        c2[tuple(a)] -= c[tuple(b)]
-        c = c2
+    t = np.array(G[(slice(0, n),) * d], dtype=np.float64)
     k = np.arange(1, n + 1)
-    S = np.sin(np.pi * np.outer(k, k) / (n + 1))
-    y = c
+    j = np.arange(n)
+    C = np.cos(np.pi * np.outer(k, j) / (n + 1)) * np.where(j == 0, 1.0, 2.0)[None, :]
+    y = t
     for ax in range(d):
-        y = np.moveaxis(np.tensordot(S, y, axes=([1], [ax])), 0, ax)
-    s1 = S[:, 0]
-    den = np.ones((n,) * d)
-    for ax in range(d):
-        shp = [1] * d
-        shp[ax] = n
-        den = den * s1.reshape(shp)
-    return y / den
+        y = np.moveaxis(np.tensordot(C, y, axes=([1], [ax])), 0, ax)
+    return y
 
 
 def tau_precond_apply(G, v, floor_rel=1e-12):

@@ -163,7 +163,8 @@ class Operator:
                                         w_first, w_c2c, lpb_mid))
 
     def set_preconditioner(self, kind):
-        """1: circulant preconditioner (default), 0: plain CG."""
+        """2: tau preconditioner (default), 1: restricted inverse of the
+        embedding circulant, 0: plain CG."""
         check(self._lib.fl_set_preconditioner(self._h, int(kind)))
 
     def apply_precond(self, u, out=None, stream=None):

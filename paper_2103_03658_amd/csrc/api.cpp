@@ -130,9 +130,9 @@ struct fl_op_s {
   double* G = nullptr;
   double* lam64 = nullptr;
   float* lam32 = nullptr;
-  double* linv64 = nullptr;   // preconditioner symbol 1/lambda-hat (floored)
+  double* linv64 = nullptr;   // preconditioner multiplier 1/lambda-hat (floored)
   float* linv32 = nullptr;
-  int precond = 1;            // 1: circulant-preconditioned CG
+  int precond = 2;            // 0 plain CG, 1 circulant, 2 tau preconditioner
   const void* tw64 = nullptr;
   const void* tw32 = nullptr;
   fl::Schedule sc64{}, sc32{};
@@ -223,6 +223,19 @@ Schedule default_schedule(const Geometry& g, bool fp32) {
 namespace {
 
 void set_device(fl_op A) { FL_HIP(hipSetDevice(A->device)); }
+
+// multiplier of the preconditioners (kind 1 zero-padded, kind 2 odd-extended
+// passes share it)
+template <typename T>
+const T* pc_symbol(fl_op A);
+template <>
+const double* pc_symbol<double>(fl_op A) {
+  return A->linv64;
+}
+template <>
+const float* pc_symbol<float>(fl_op A) {
+  return A->linv32;
+}
 
 void check_schedule(const fl::Geometry& g, const fl::Schedule& s, bool fp32) {
   if (!fl::schedule_ok(g, s, fp32)) throw Error(FL_E_INVAL, "schedule out of range");
@@ -410,7 +423,7 @@ fl_status fl_set_schedule(fl_op A, int fp32, int e_first, int e_mid, int e_c2c, 
 
 fl_status fl_set_preconditioner(fl_op A, int kind) {
   if (!A) return fail(FL_E_INVAL, "null handle");
-  if (kind != 0 && kind != 1) return fail(FL_E_INVAL, "kind must be 0 or 1");
+  if (kind < 0 || kind > 2) return fail(FL_E_INVAL, "kind must be 0, 1 or 2");
   A->precond = kind;
   return FL_OK;
 }
@@ -421,18 +434,20 @@ fl_status fl_apply_precond(fl_op A, const void* u, void* y, int nrhs, int fp32, 
     if (!u || !y) return fail(FL_E_INVAL, "null vector");
     if (u == y) return fail(FL_E_INVAL, "u and y must be distinct");
     if (nrhs < 1) return fail(FL_E_INVAL, "nrhs must be >= 1");
+    if (A->precond == 0) return fail(FL_E_INVAL, "no preconditioner selected");
     set_device(A);
     hipStream_t st = (hipStream_t)stream;
     A->begin(st);
     void* ws = A->ws.get(fl::apply_workspace_bytes(A->g, nrhs, fp32 != 0));
+    const bool odd = A->precond == 2;
     if (fp32)
-      fl::apply_passes<float>(A->g, A->sc32, A->linv32, A->tw32, (const float*)u, (float*)y,
-                              nrhs, ws, st, fl::PM_PLAIN, nullptr, nullptr, nullptr, nullptr,
-                              nullptr);
+      fl::apply_passes<float>(A->g, A->sc32, pc_symbol<float>(A), A->tw32, (const float*)u,
+                              (float*)y, nrhs, ws, st, fl::PM_PLAIN, nullptr, nullptr, nullptr,
+                              nullptr, nullptr, nullptr, -1, odd);
     else
-      fl::apply_passes<double>(A->g, A->sc64, A->linv64, A->tw64, (const double*)u, (double*)y,
-                               nrhs, ws, st, fl::PM_PLAIN, nullptr, nullptr, nullptr, nullptr,
-                               nullptr);
+      fl::apply_passes<double>(A->g, A->sc64, pc_symbol<double>(A), A->tw64, (const double*)u,
+                               (double*)y, nrhs, ws, st, fl::PM_PLAIN, nullptr, nullptr, nullptr,
+                               nullptr, nullptr, nullptr, -1, odd);
     A->end(st);
     return FL_OK;
   });
@@ -690,13 +705,15 @@ inline std::vector<double> sched_key(const fl::Schedule& s) {
           (double)s.W_c2c, (double)s.LPB_mid};
 }
 
-// z = P r (restricted inverse of the embedding circulant) and partials of r.z.
+// z = P r and partials of r.z: P the restricted inverse of the embedding
+// circulant (kind 1, zero-padded passes) or the inverse of the tau
+// approximation (kind 2, odd-extended passes); `linv` is its multiplier.
 template <typename T>
 void precond_apply(fl_op A, const fl::Schedule& sc, const T* linv, const void* tw, const T* r,
                    T* z, int nrhs, void* ws, const fl::CgScalars& cg, const int* active,
                    hipStream_t st) {
   fl::apply_passes<T>(A->g, sc, linv, tw, r, z, nrhs, ws, st, fl::PM_DOT, nullptr, nullptr,
-                      nullptr, &cg, active);
+                      nullptr, &cg, active, nullptr, -1, A->precond == 2);
 }
 
 // CG start: x = 0, r = rhs, p = 0; preconditioned: z = P r.
@@ -840,13 +857,13 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
       double* q = (double*)(vb + 2 * a8);
       double* x = (double*)(vb + 3 * a8);
       double* z = (double*)(vb + 4 * a8);
-      cg_start<double>(A, A->sc64, A->linv64, A->tw64, f, x, r, p, z, nrhs, cg, nullptr, ws, st);
+      cg_start<double>(A, A->sc64, pc_symbol<double>(A), A->tw64, f, x, r, p, z, nrhs, cg, nullptr, ws, st);
       const int chunk = 8;
       std::vector<double> key = make_key(0, nrhs, chunk, maxiter, tol, pc);
       for (double v : {pkey(ws), pkey(vb), pkey(A->cg.mem.p), pkey(A->lam64)}) key.push_back(v);
       for (double v : sched_key(A->sc64)) key.push_back(v);
       predictive_loop(A, key, maxiter + 2, cg, nrhs, st, [&]() {
-        cg_iteration<double>(A, A->sc64, A->lam64, A->linv64, A->tw64, x, r, p, q, z, nrhs, cg,
+        cg_iteration<double>(A, A->sc64, A->lam64, pc_symbol<double>(A), A->tw64, x, r, p, q, z, nrhs, cg,
                              ws, st);
       });
       FL_HIP(hipMemcpyAsync(u, x, v8, hipMemcpyDeviceToDevice, st));
@@ -891,7 +908,7 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
       fl::to_float(f, rhs32, (long)nrhs * nd, st);
       FL_HIP(hipMemcpyAsync(rr_last, f2, nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
       fl::fill_int(nupd, 0, nrhs, st);
-      cg_start<float>(A, A->sc32, A->linv32, A->tw32, rhs32, xlo, r32, p32, z32, nrhs, cg,
+      cg_start<float>(A, A->sc32, pc_symbol<float>(A), A->tw32, rhs32, xlo, r32, p32, z32, nrhs, cg,
                       nullptr, ws, st);
       const int chunk = 8;
       std::vector<double> key = make_key(1, nrhs, chunk, maxiter, tol, A->delta, pc);
@@ -902,7 +919,7 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
       for (double v : sched_key(A->sc64)) key.push_back(v);
       chunk_loop(A, A->graph[1], key, (maxiter + 2) / chunk + 2, cg, st, [&]() {
         for (int i = 0; i < chunk; ++i)
-          cg_iteration<float>(A, A->sc32, A->lam32, A->linv32, A->tw32, xlo, r32, p32, q32, z32,
+          cg_iteration<float>(A, A->sc32, A->lam32, pc_symbol<float>(A), A->tw32, xlo, r32, p32, q32, z32,
                               nrhs, cg, ws, st);
         fl::reliable_accum(A->g, xhi, xlo, nrhs, cg, rr_last, f2, delta2, tol * tol, trig, false,
                            st);
@@ -910,7 +927,7 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
                                  fl::PM_RESID, nullptr, nullptr, fc, &co, trig);
         fl::reliable_replace(A->g, r64, r32, nrhs, cg, co.part_a, nb64, co.max_blocks, rr_last,
                              f2, tol * tol, trig, nupd, st);
-        if (pc) precond_apply<float>(A, A->sc32, A->linv32, A->tw32, r32, z32, nrhs, ws, cg, trig,
+        if (pc) precond_apply<float>(A, A->sc32, pc_symbol<float>(A), A->tw32, r32, z32, nrhs, ws, cg, trig,
                                      st);
       });
       // fold what is left (RHS stopped by maxiter) and report true residuals
@@ -964,7 +981,7 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
         }
         FL_HIP(hipMemcpyAsync(oact, hact.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
         fl::refine_scale(r64, rhs32, rro, scale, nd, nrhs, oact, st);
-        cg_run<float>(A, A->sc32, A->lam32, A->linv32, A->tw32, rhs32, d32, r32, p32, q32, z32,
+        cg_run<float>(A, A->sc32, A->lam32, pc_symbol<float>(A), A->tw32, rhs32, d32, r32, p32, q32, z32,
                       nrhs, cg, oact, ws, st);
         fl::refine_axpy(u, d32, scale, nd, nrhs, oact, st);
         fp64_residual(A, f, u, r64, nrhs, co, oact, rro, ws, st);

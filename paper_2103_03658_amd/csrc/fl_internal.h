@@ -131,11 +131,15 @@ int vec_blocks(long nd, int nrhs);
 // q = A p into y), or FP64 residual (PM_RESID: y = f - A u).
 // PM_DOT writes its partials to cg->part_b.  ev (optional): npasses + 1
 // events recorded around the passes; only >= 0 launches that pass alone.
+// odd: every axis is odd-extended instead of zero-padded (positions 1..n and
+// their negated reflections), which with a real even symbol applies
+// S diag(.) S with S the sine transform of each axis (not with PM_CG).
 template <typename T>
 void apply_passes(const Geometry& g, const Schedule& sc, const T* lam, const void* tw,
                   const T* u, T* y, int nrhs, void* ws, hipStream_t st, int mode,
                   const T* rvec, T* pvec, const double* fvec, const CgScalars* cg,
-                  const int* active, hipEvent_t* ev = nullptr, int only = -1);
+                  const int* active, hipEvent_t* ev = nullptr, int only = -1,
+                  bool odd = false);
 
 // Number of kernel launches (passes) of one application: 1, 3 or 5 for d = 1, 2, 3.
 inline int apply_npasses(int d) { return d == 1 ? 1 : (d == 2 ? 3 : 5); }

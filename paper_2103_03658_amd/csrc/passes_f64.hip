@@ -12,8 +12,8 @@ void apply_passes<double>(const Geometry& g, const Schedule& sc, const double* l
                           const void* tw, const double* u, double* y, int nrhs, void* ws,
                           hipStream_t st, int mode, const double* rvec, double* pvec,
                           const double* fvec, const CgScalars* cg, const int* active,
-                          hipEvent_t* ev, int only) {
-  apply_passes_t<double>(g, sc, lam, tw, u, y, nrhs, ws, st, mode, rvec, pvec, fvec, cg, active, ev, only);
+                          hipEvent_t* ev, int only, bool odd) {
+  apply_passes_t<double>(g, sc, lam, tw, u, y, nrhs, ws, st, mode, rvec, pvec, fvec, cg, active, ev, only, odd);
 }
 
 size_t apply_workspace_bytes(const Geometry& g, int nrhs, bool fp32) {
@@ -103,11 +103,15 @@ __global__ void k_fold(const cx<double>* chat, double* l64, float* l32, int d, i
   l32[k] = (float)v;
 }
 
-// Preconditioner multiplier s / max(lambda-hat, 1e-12 max lambda-hat): the
-// restricted inverse R C^{-1} R^T of the embedding circulant C (floored so
-// that it stays positive definite even if some lambda-hat is not).  The
-// transforms are unnormalised and lambda-hat already carries one 1/M^d, so
-// s = 1/M^(2d).
+// Preconditioner multiplier s / max(lambda-hat, 1e-12 max lambda-hat): with
+// zero-padded passes the restricted inverse R C^{-1} R^T of the embedding
+// circulant C; with odd-extended passes the inverse of the natural tau
+// approximation of A (T minus its Hankel part on every level), whose
+// eigenvalues t_0 + 2 sum_j t_j cos(j pi k / N) per axis are M^d lambda-hat(k)
+// at the interior frequencies k in [1, n]^d (the embedding keeps offsets up
+// to N - 2, the tau first column's range).  Floored so that both stay
+// positive definite even if some lambda-hat is not.  The transforms are
+// unnormalised and lambda-hat carries one 1/M^d, so s = 1/M^(2d).
 __global__ void __launch_bounds__(1024) k_symbol_max(const double* l, long n, double* out) {
   __shared__ double sh[16];
   double m = 0.0;

@@ -20,7 +20,7 @@ template <typename T>
 void apply_passes_t(const Geometry& g, const Schedule& sc, const T* lam, const void* twv,
                     const T* u, T* y, int nrhs, void* ws, hipStream_t st, int mode,
                     const T* rvec, T* pvec, const double* fvec, const CgScalars* cg,
-                    const int* active, hipEvent_t* ev, int only) {
+                    const int* active, hipEvent_t* ev, int only, bool odd) {
   // optional timing: ev[k] recorded before pass k, ev[npasses] after the last;
   // only >= 0 launches that pass alone (its input must already be in place)
   int pass = 0;
@@ -41,7 +41,7 @@ void apply_passes_t(const Geometry& g, const Schedule& sc, const T* lam, const v
   if (g.d == 1) {
     Line1Args<T> a{u, y, pvec, rvec, fvec, active, c, part, c.max_blocks, lam, n, nrhs,
                    mode, tw};
-    if (go()) launch_line1d<T>(M, sc.E_mid, a, st);
+    if (go()) launch_line1d<T>(M, sc.E_mid, a, st, odd);
     done();
     return;
   }
@@ -52,27 +52,27 @@ void apply_passes_t(const Geometry& g, const Schedule& sc, const T* lam, const v
   {
     FirstArgs<T> a{u, pvec, rvec, active, c, T1, C0, nd, h * C0, 0, n,
                    sc.W_first, 0, 0, 0, mode == PM_CG ? PM_CG : PM_PLAIN, tw};
-    if (go()) launch_first<T>(M, sc.E_first, a, nrhs, st);
+    if (go()) launch_first<T>(M, sc.E_first, a, nrhs, st, odd);
   }
   if (g.d == 2) {
     MidArgs<T> m{T1, lam, active, h, h * n, n, n, n, N1, 2, sc.LPB_mid, nrhs, tw};
-    if (go()) launch_mid<T>(M, sc.E_mid, m, nrhs, st);
+    if (go()) launch_mid<T>(M, sc.E_mid, m, nrhs, st, odd);
   } else {
     cx<T>* T2 = T1 + (long)nrhs * h * n * n;
     // axis 1 forward: slices (rhs, k0), rows i1 < n -> k1 < M, columns i2
     C2CArgs<T> f1{T1, T2, active, n, (long)n * n, n, (long)M * n, n, 0, (int)h, n, M,
                   sc.W_c2c, 0, 0, 0, tw};
-    if (go()) launch_c2c<T>(M, sc.E_c2c, -1, f1, (long)nrhs * h, st);
+    if (go()) launch_c2c<T>(M, sc.E_c2c, -1, f1, (long)nrhs * h, st, odd);
     MidArgs<T> m{T2, lam, active, h * M, h * M * n, n, n, n, N1, 3, sc.LPB_mid, nrhs, tw};
-    if (go()) launch_mid<T>(M, sc.E_mid, m, nrhs, st);
+    if (go()) launch_mid<T>(M, sc.E_mid, m, nrhs, st, odd);
     C2CArgs<T> i1{T2, T1, active, n, (long)M * n, n, (long)n * n, n, 0, (int)h, M, n,
                   sc.W_c2c, 0, 0, 0, tw};
-    if (go()) launch_c2c<T>(M, sc.E_c2c, +1, i1, (long)nrhs * h, st);
+    if (go()) launch_c2c<T>(M, sc.E_c2c, +1, i1, (long)nrhs * h, st, odd);
   }
   {
     LastArgs<T> a{T1, y, mode == PM_DOT ? u : pvec, fvec, active, part, c.max_blocks, C0,
                   h * C0, nd, 0, n, sc.W_first, 0, 0, 0, mode, tw};
-    if (go()) launch_last<T>(M, sc.E_first, a, nrhs, st);
+    if (go()) launch_last<T>(M, sc.E_first, a, nrhs, st, odd);
     done();
   }
 }

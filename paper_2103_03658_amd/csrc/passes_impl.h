@@ -150,21 +150,27 @@ struct FirstArgs {
   const cx<T>* tw;
 };
 
-// Transform of one line held in LDS planes (natural order, inputs >= M/2
-// zero) and write-back in natural order of the outputs below M/2 (all
-// outputs if keep_all).
-template <typename T, int M, int E, int DIR, bool PRUNE_IN, bool PRUNE_OUT>
+// Transform of one line held in LDS planes (natural order) and write-back in
+// natural order of the outputs (only those below M/2 if PRUNE_OUT).  IN: 0
+// every input is read; 1 inputs at index >= M/2 are zero; 2 the line is the
+// odd extension of its lower half (input at e >= M/2 is -input[M - e], zero
+// at M/2), of which only the lower half is in LDS.
+template <typename T, int M, int E, int DIR, int IN, bool PRUNE_OUT>
 __device__ __forceinline__ void line_in_lds(T* lre, T* lim, int t, const cx<T>* tw) {
   using P = Plan<M, E>;
   constexpr int TPL = P::TPL;
   cx<T> v[E];
 #pragma unroll
   for (int j = 0; j < E; ++j) {
-    if (!PRUNE_IN || j < E / 2) {
-      const int i = P::pad(t + j * TPL);
+    const int e = t + j * TPL;
+    if (IN == 0 || j < E / 2) {
+      const int i = P::pad(e);
       v[j] = {lre[i], lim[i]};
-    } else {
+    } else if (IN == 1) {
       v[j] = {0, 0};
+    } else {
+      const int i = P::pad(M - e);
+      v[j] = e == M / 2 ? cx<T>{0, 0} : cx<T>{-lre[i], -lim[i]};
     }
   }
   fft_line<T, M, E, DIR>(v, lre, lim, t, tw);
@@ -179,7 +185,10 @@ __device__ __forceinline__ void line_in_lds(T* lre, T* lim, int t, const cx<T>* 
   }
 }
 
-template <typename T, int M, int E>
+// ODD: the columns are odd-extended (row e holds input row e - 1 for
+// 1 <= e <= n, and -input row M - e - 1 above M/2), the embedding of the
+// sine transform used by the tau preconditioner.
+template <typename T, int M, int E, bool ODD>
 __global__ void __launch_bounds__(512) k_first(FirstArgs<T> a) {
   using P = Plan<M, E>;
   constexpr int TPL = P::TPL;
@@ -210,9 +219,10 @@ __global__ void __launch_bounds__(512) k_first(FirstArgs<T> a) {
     for (int j = 0; j < E; ++j) {
       const int e = threadIdx.x + j * nthr;
       const int row = e >> lw1, cc = e & (W2 - 1);
+      const int src = ODD ? row - 1 : row;
       x[j] = 0;
-      if (row < a.n_in && cc < ncol) {
-        const long i = ib + (long)row * a.C + cc;
+      if (src >= 0 && src < a.n_in && cc < ncol) {
+        const long i = ib + (long)src * a.C + cc;
         if (a.mode == PM_CG) {
           x[j] = a.r[i] + bt * a.p[i];
           a.p[i] = x[j];
@@ -232,7 +242,7 @@ __global__ void __launch_bounds__(512) k_first(FirstArgs<T> a) {
   {
     const int l = threadIdx.x / TPL, t = threadIdx.x % TPL;
     T* lre = lds + l * a.LS;
-    line_in_lds<T, M, E, -1, true, false>(lre, lre + a.PO, t, a.tw);
+    line_in_lds<T, M, E, -1, ODD ? 2 : 1, false>(lre, lre + a.PO, t, a.tw);
   }
   __syncthreads();
   // Hermitian split of each packed pair, rows k = 0..M/2, row segments of
@@ -279,7 +289,8 @@ struct LastArgs {
   const cx<T>* tw;
 };
 
-template <typename T, int M, int E>
+// ODD: output rows are rows 1..n of the (odd) line.
+template <typename T, int M, int E, bool ODD>
 __global__ void __launch_bounds__(512) k_last(LastArgs<T> a) {
   using P = Plan<M, E>;
   constexpr int TPL = P::TPL;
@@ -331,7 +342,7 @@ __global__ void __launch_bounds__(512) k_last(LastArgs<T> a) {
   {
     const int l = threadIdx.x / TPL, t = threadIdx.x % TPL;
     T* lre = lds + l * a.LS;
-    line_in_lds<T, M, E, +1, false, true>(lre, lre + a.PO, t, a.tw);
+    line_in_lds<T, M, E, +1, 0, true>(lre, lre + a.PO, t, a.tw);
   }
   __syncthreads();
   double acc = 0.0;
@@ -342,7 +353,7 @@ __global__ void __launch_bounds__(512) k_last(LastArgs<T> a) {
     const int e = threadIdx.x + j * nthr;
     const int row = e >> lw1, cc = e & (W2 - 1);
     if (e >= tot3 || cc >= ncol) continue;
-    const T v = lds[(cc >> 1) * a.LS + (cc & 1) * a.PO + P::pad(row)];
+    const T v = lds[(cc >> 1) * a.LS + (cc & 1) * a.PO + P::pad(ODD ? row + 1 : row)];
     const long i = yb0 + (long)row * a.C + cc;
     if (a.mode == PM_RESID) {
       const double r = a.f[i] - (double)v;
@@ -379,7 +390,9 @@ struct C2CArgs {
 
 // PR: 0 full transform, 1 inputs >= M/2 zero (n_in <= M/2), 2 outputs below
 // M/2 only (n_out <= M/2).
-template <typename T, int M, int E, int DIR, int PR>
+// ODD (with PR 1 or 2): the lines are odd extensions (inputs at rows 1..n of
+// the lower half, outputs read from rows 1..n), as in k_first / k_last.
+template <typename T, int M, int E, int DIR, int PR, bool ODD>
 __global__ void __launch_bounds__(512) k_c2c(C2CArgs<T> a) {
   using P = Plan<M, E>;
   constexpr int TPL = P::TPL;
@@ -402,8 +415,9 @@ __global__ void __launch_bounds__(512) k_c2c(C2CArgs<T> a) {
     for (int j = 0; j < J; ++j) {
       const int e = threadIdx.x + j * nthr;
       const int row = e >> a.lw, l = e & (a.W - 1);
+      const int src = (ODD && PR == 1) ? row - 1 : row;   // odd extension of spatial rows
       x[j] = {0, 0};
-      if (row < a.n_in && l < ncol) x[j] = a.in[ib + (long)row * a.in_rs + l];
+      if (src >= 0 && src < a.n_in && l < ncol) x[j] = a.in[ib + (long)src * a.in_rs + l];
     }
 #pragma unroll
     for (int j = 0; j < J; ++j) {
@@ -418,7 +432,7 @@ __global__ void __launch_bounds__(512) k_c2c(C2CArgs<T> a) {
   {
     const int l = threadIdx.x / TPL, t = threadIdx.x % TPL;
     T* lre = lds + l * a.LS;
-    line_in_lds<T, M, E, DIR, PR == 1, PR == 2>(lre, lre + a.PO, t, a.tw);
+    line_in_lds<T, M, E, DIR, PR == 1 ? (ODD ? 2 : 1) : 0, PR == 2>(lre, lre + a.PO, t, a.tw);
   }
   __syncthreads();
   const long obase = o * a.out_os + col0;
@@ -430,7 +444,8 @@ __global__ void __launch_bounds__(512) k_c2c(C2CArgs<T> a) {
     const int row = e >> a.lw, l = e & (a.W - 1);
     if (e >= tot3 || l >= ncol) continue;
     const T* re = lds + l * a.LS;
-    a.out[obase + (long)row * a.out_rs + l] = {re[P::pad(row)], re[a.PO + P::pad(row)]};
+    const int src = (ODD && PR == 2) ? row + 1 : row;   // restriction to rows 1..n
+    a.out[obase + (long)row * a.out_rs + l] = {re[P::pad(src)], re[a.PO + P::pad(src)]};
   }
 }
 
@@ -453,7 +468,9 @@ struct MidArgs {
   const cx<T>* tw;
 };
 
-template <typename T, int M, int E>
+// ODD: each line is the odd extension of its n stored values (positions
+// 1..n and their negated reflections), outputs stored from positions 1..n.
+template <typename T, int M, int E, bool ODD>
 __global__ void __launch_bounds__(512) k_mid(MidArgs<T> a) {
   using P = Plan<M, E>;
   constexpr int TPL = P::TPL;
@@ -476,7 +493,15 @@ __global__ void __launch_bounds__(512) k_mid(MidArgs<T> a) {
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int i = t + j * TPL;   // n_in <= M/2: slots j >= E/2 are zero
-    v[j] = (j < E / 2 && h && i < a.n_in) ? base[i] : cx<T>{0, 0};
+    if (!ODD) {
+      v[j] = (j < E / 2 && h && i < a.n_in) ? base[i] : cx<T>{0, 0};
+    } else if (j < E / 2) {
+      v[j] = (h && i >= 1 && i - 1 < a.n_in) ? base[i - 1] : cx<T>{0, 0};
+    } else {
+      const int r = M - i - 1;
+      const cx<T> w = (h && i != M / 2 && r < a.n_in) ? base[r] : cx<T>{0, 0};
+      v[j] = {-w.x, -w.y};
+    }
   }
   fft_line<T, M, E, -1>(v, lre, lim, t, a.tw);
   // symbol row of this line
@@ -500,8 +525,8 @@ __global__ void __launch_bounds__(512) k_mid(MidArgs<T> a) {
   fft_line<T, M, E, +1>(v, lre, lim, t, a.tw);
 #pragma unroll
   for (int sl = 0; sl < E; ++sl) {
-    const int i = t + TPL * P::jslot(sl);   // n_out <= M/2
-    if (P::jslot(sl) < E / 2 && h && i < a.n_out) base[i] = v[sl];
+    const int i = t + TPL * P::jslot(sl) - (ODD ? 1 : 0);   // n_out <= M/2
+    if (P::jslot(sl) < E / 2 && h && i >= 0 && i < a.n_out) base[i] = v[sl];
   }
 }
 
@@ -552,7 +577,8 @@ struct Line1Args {
   const cx<T>* tw;
 };
 
-template <typename T, int M, int E>
+// ODD: the line is the odd extension of the n values (no PM_CG then).
+template <typename T, int M, int E, bool ODD>
 __global__ void __launch_bounds__(512) k_line1d(Line1Args<T> a) {
   using P = Plan<M, E>;
   constexpr int TPL = P::TPL;
@@ -577,7 +603,13 @@ __global__ void __launch_bounds__(512) k_line1d(Line1Args<T> a) {
   for (int j = 0; j < E; ++j) {
     const int i = t + j * TPL;   // n <= M/2: slots j >= E/2 are zero
     T re = 0;
-    if (j < E / 2 && i < n) {
+    if constexpr (ODD) {
+      if (j < E / 2) {
+        if (i >= 1 && i - 1 < n) re = a.u[base + i - 1];
+      } else if (i != M / 2 && M - i - 1 < n) {
+        re = -a.u[base + M - i - 1];
+      }
+    } else if (j < E / 2 && i < n) {
       if (a.mode == PM_CG) {
         re = a.r[base + i] + bt * a.p[base + i];
         a.p[base + i] = re;
@@ -598,8 +630,8 @@ __global__ void __launch_bounds__(512) k_line1d(Line1Args<T> a) {
   double acc = 0.0;
 #pragma unroll
   for (int sl = 0; sl < E; ++sl) {
-    const int i = t + TPL * P::jslot(sl);
-    if (P::jslot(sl) < E / 2 && i < n) {
+    const int i = t + TPL * P::jslot(sl) - (ODD ? 1 : 0);
+    if (P::jslot(sl) < E / 2 && i >= 0 && i < n) {
       if (a.mode == PM_RESID) {
         const double q = a.f[base + i] - (double)v[sl].x;
         a.y[base + i] = (T)q;
@@ -686,7 +718,7 @@ inline void lds_attr(K kernel, size_t bytes) {
 inline long pair_tiles(long C, int W) { return ((C + 1) / 2 + W - 1) / W; }
 
 template <typename T>
-void launch_first(int M, int E, FirstArgs<T> a, int nrhs, hipStream_t st) {
+void launch_first(int M, int E, FirstArgs<T> a, int nrhs, hipStream_t st, bool odd = false) {
   if (!pow2(a.W) || a.n_in > M / 2) throw Error(2, "first pass: bad tile width or rows");
   a.ntiles = pair_tiles(a.C, a.W);
   a.lw = ilog2i(a.W);
@@ -695,12 +727,17 @@ void launch_first(int M, int E, FirstArgs<T> a, int nrhs, hipStream_t st) {
   a.LS = tl.LS;
   dim3 grid((unsigned)(a.ntiles * nrhs));
   const int threads = a.W * (M / E);
-  FL_DISPATCH(M, E, FL_LAUNCH((k_first<T, M, E>), grid, dim3(threads), tl.bytes, st, a));
+  if (odd) {
+    if (a.mode == PM_CG) throw Error(2, "first pass: odd extension with a CG prologue");
+    FL_DISPATCH(M, E, FL_LAUNCH((k_first<T, M, E, true>), grid, dim3(threads), tl.bytes, st, a));
+  } else {
+    FL_DISPATCH(M, E, FL_LAUNCH((k_first<T, M, E, false>), grid, dim3(threads), tl.bytes, st, a));
+  }
   check_launch("first pass");
 }
 
 template <typename T>
-void launch_last(int M, int E, LastArgs<T> a, int nrhs, hipStream_t st) {
+void launch_last(int M, int E, LastArgs<T> a, int nrhs, hipStream_t st, bool odd = false) {
   if (!pow2(a.W) || a.n_out > M / 2) throw Error(2, "last pass: bad tile width or rows");
   a.ntiles = pair_tiles(a.C, a.W);
   if (a.mode != PM_PLAIN && a.ntiles > a.max_blocks)
@@ -711,12 +748,17 @@ void launch_last(int M, int E, LastArgs<T> a, int nrhs, hipStream_t st) {
   a.LS = tl.LS;
   dim3 grid((unsigned)(a.ntiles * nrhs));
   const int threads = a.W * (M / E);
-  FL_DISPATCH(M, E, FL_LAUNCH((k_last<T, M, E>), grid, dim3(threads), tl.bytes, st, a));
+  if (odd) {
+    FL_DISPATCH(M, E, FL_LAUNCH((k_last<T, M, E, true>), grid, dim3(threads), tl.bytes, st, a));
+  } else {
+    FL_DISPATCH(M, E, FL_LAUNCH((k_last<T, M, E, false>), grid, dim3(threads), tl.bytes, st, a));
+  }
   check_launch("last pass");
 }
 
 template <typename T>
-void launch_c2c(int M, int E, int dir, C2CArgs<T> a, long outer, hipStream_t st) {
+void launch_c2c(int M, int E, int dir, C2CArgs<T> a, long outer, hipStream_t st,
+                bool odd = false) {
   if (!pow2(a.W)) throw Error(2, "c2c pass: bad tile width");
   a.ntiles = (a.C + a.W - 1) / a.W;
   a.lw = ilog2i(a.W);
@@ -727,13 +769,21 @@ void launch_c2c(int M, int E, int dir, C2CArgs<T> a, long outer, hipStream_t st)
   const int threads = a.W * (M / E);
   const size_t sh = tl.bytes;
   if (dir < 0 && a.n_in <= M / 2 && a.n_out == M) {
-    FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, -1, 1>), grid, dim3(threads), sh, st, a));
+    if (odd) {
+      FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, -1, 1, true>), grid, dim3(threads), sh, st, a));
+    } else {
+      FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, -1, 1, false>), grid, dim3(threads), sh, st, a));
+    }
   } else if (dir > 0 && a.n_in == M && a.n_out <= M / 2) {
-    FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, 1, 2>), grid, dim3(threads), sh, st, a));
-  } else if (dir < 0 && a.n_in == M && a.n_out == M) {
-    FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, -1, 0>), grid, dim3(threads), sh, st, a));
-  } else if (dir > 0 && a.n_in == M && a.n_out == M) {
-    FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, 1, 0>), grid, dim3(threads), sh, st, a));
+    if (odd) {
+      FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, 1, 2, true>), grid, dim3(threads), sh, st, a));
+    } else {
+      FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, 1, 2, false>), grid, dim3(threads), sh, st, a));
+    }
+  } else if (!odd && dir < 0 && a.n_in == M && a.n_out == M) {
+    FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, -1, 0, false>), grid, dim3(threads), sh, st, a));
+  } else if (!odd && dir > 0 && a.n_in == M && a.n_out == M) {
+    FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, 1, 0, false>), grid, dim3(threads), sh, st, a));
   } else {
     throw Error(2, "c2c pass: unsupported row ranges");
   }
@@ -741,14 +791,18 @@ void launch_c2c(int M, int E, int dir, C2CArgs<T> a, long outer, hipStream_t st)
 }
 
 template <typename T>
-void launch_mid(int M, int E, const MidArgs<T>& a, int nrhs, hipStream_t st) {
+void launch_mid(int M, int E, const MidArgs<T>& a, int nrhs, hipStream_t st, bool odd = false) {
   if (a.n_in > M / 2 || a.n_out > M / 2) throw Error(2, "middle pass: rows beyond M/2");
   MidArgs<T> b = a;
   b.nrhs = nrhs;
   dim3 grid((unsigned)(((a.rows + a.LPB - 1) / a.LPB) * nrhs));
   const int threads = a.LPB * (M / E);
   const size_t sh = line_lds_bytes<T>(M, E) * a.LPB;
-  FL_DISPATCH(M, E, FL_LAUNCH((k_mid<T, M, E>), grid, dim3(threads), sh, st, b));
+  if (odd) {
+    FL_DISPATCH(M, E, FL_LAUNCH((k_mid<T, M, E, true>), grid, dim3(threads), sh, st, b));
+  } else {
+    FL_DISPATCH(M, E, FL_LAUNCH((k_mid<T, M, E, false>), grid, dim3(threads), sh, st, b));
+  }
   check_launch("middle pass");
 }
 
@@ -769,12 +823,17 @@ void launch_rows(int M, int E, int dir, cx<T>* data, long rows, int LPB, const c
 }
 
 template <typename T>
-void launch_line1d(int M, int E, const Line1Args<T>& a, hipStream_t st) {
+void launch_line1d(int M, int E, const Line1Args<T>& a, hipStream_t st, bool odd = false) {
   if (a.n > M / 2) throw Error(2, "1D line: rows beyond M/2");
   dim3 grid((unsigned)a.nrhs);
   const int threads = M / E;
   const size_t sh = line_lds_bytes<T>(M, E);
-  FL_DISPATCH(M, E, FL_LAUNCH((k_line1d<T, M, E>), grid, dim3(threads), sh, st, a));
+  if (odd) {
+    if (a.mode == PM_CG) throw Error(2, "1D line: odd extension with a CG prologue");
+    FL_DISPATCH(M, E, FL_LAUNCH((k_line1d<T, M, E, true>), grid, dim3(threads), sh, st, a));
+  } else {
+    FL_DISPATCH(M, E, FL_LAUNCH((k_line1d<T, M, E, false>), grid, dim3(threads), sh, st, a));
+  }
   check_launch("1D line");
 }
 

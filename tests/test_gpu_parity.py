@@ -158,7 +158,7 @@ def test_apply_ragged_and_edge_sizes():
         assert np.abs(y[0] - oracle.apply(G, u[0])).max() <= 1e-12 * abs_scale(G, u[0])
 
 
-@pytest.mark.parametrize("pc", [1, 0])
+@pytest.mark.parametrize("pc", [2, 1, 0])
 @pytest.mark.parametrize("d,alpha,p,N,mixed", [
     (1, 1.5, 1, 256, 0), (2, 1.5, 1, 16, 0), (2, 0.5, 2, 32, 0), (3, 1.0, 1, 8, 0),
     (2, 1.5, 1, 16, 1), (2, 1.0, 2, 32, 1), (3, 1.0, 1, 8, 1), (1, 1.5, 1, 256, 1),
@@ -306,6 +306,7 @@ def test_graph_replays_match_eager(mixed):
                                       (3, 8, False)])
 def test_precond_apply_parity(d, N, fp32):
     op = make_op(d, 1.5, 2 if N % 2 == 0 else 1, N)
+    op.set_preconditioner(1)
     u = inputs.uniform_rhs(d, N, 2, seed=41)
     ut = torch.from_numpy(u.astype(np.float32) if fp32 else u).cuda()
     y = op.apply_precond(ut).double().cpu().numpy()
@@ -333,6 +334,7 @@ def test_fp64_pcg_follows_oracle_pcg(d, alpha, p, N):
     iteration count (within one, for rounding at the threshold) and the same
     iterate to round-off growth."""
     op = make_op(d, alpha, p, N)
+    op.set_preconditioner(1)
     f = inputs.uniform_rhs(d, N, 1, seed=12)
     u, info = op.solve(torch.from_numpy(f).cuda(), tol=1e-10, mixed=0)
     G = orc_gen(d, alpha, p, N)
@@ -341,3 +343,59 @@ def test_fp64_pcg_follows_oracle_pcg(d, alpha, p, N):
     print(f"  gpu iters {info[0]['iters']}, oracle iters {it}")
     assert abs(info[0]["iters"] - it) <= 1
     assert np.abs(u[0].cpu().numpy() - ur).max() <= 1e-8 * np.abs(ur).max()
+
+
+@pytest.mark.parametrize("d,N,p,fp32", [(1, 64, 1, False), (1, 1024, 1, False), (2, 32, 2, False),
+                                        (2, 32, 2, True), (2, 16, 0, False), (3, 8, 1, False),
+                                        (3, 16, 2, True)])
+def test_tau_precond_apply_parity(d, N, p, fp32):
+    """fl_apply_precond with the tau preconditioner (odd-extended passes)
+    against the oracle's dense sine-transform form."""
+    op = make_op(d, 1.3, p, N)
+    op.set_preconditioner(2)
+    u = inputs.uniform_rhs(d, N, 3, seed=43)
+    ut = torch.from_numpy(u.astype(np.float32) if fp32 else u).cuda()
+    y = op.apply_precond(ut).double().cpu().numpy()
+    G = orc_gen(d, 1.3, p, N)
+    n = N - 1
+    k = np.arange(1, n + 1)
+    S = np.abs(np.sin(np.pi * np.outer(k, k) / N))
+    inv = 1.0 / np.abs(oracle.tau_symbol(G))
+    for r in range(3):
+        v = ut[r].double().cpu().numpy()
+        ref = oracle.tau_precond_apply(G, v)
+        # rounding acts on the magnitudes (2/N)^d |S|..(|1/lam| (|S|..|v|))
+        sc = np.abs(v)
+        for ax in range(d):
+            sc = np.moveaxis(np.tensordot(S, sc, axes=([1], [ax])), 0, ax)
+        sc = sc * inv
+        for ax in range(d):
+            sc = np.moveaxis(np.tensordot(S, sc, axes=([1], [ax])), 0, ax)
+        sc = sc.max() * (2.0 / N) ** d
+        tol = 1e-5 if fp32 else 1e-12
+        assert np.abs(y[r] - ref).max() <= tol * sc, (r, float(np.abs(y[r] - ref).max() / sc))
+
+
+@pytest.mark.parametrize("d,alpha,p,N", [(1, 1.5, 1, 256), (2, 1.0, 2, 64), (2, 1.9, 1, 32),
+                                         (3, 0.7, 1, 16)])
+def test_fp64_tau_pcg_follows_oracle(d, alpha, p, N):
+    op = make_op(d, alpha, p, N)
+    op.set_preconditioner(2)
+    f = inputs.uniform_rhs(d, N, 1, seed=12)
+    u, info = op.solve(torch.from_numpy(f).cuda(), tol=1e-10, mixed=0)
+    G = orc_gen(d, alpha, p, N)
+    ur, it, rel = oracle.solve_cg(G, f[0], tol=1e-10,
+                                  precond=lambda v: oracle.tau_precond_apply(G, v))
+    print(f"  gpu iters {info[0]['iters']}, oracle iters {it}")
+    assert abs(info[0]["iters"] - it) <= 1
+    assert np.abs(u[0].cpu().numpy() - ur).max() <= 1e-8 * np.abs(ur).max()
+
+
+def test_tau_cuts_iterations_at_high_alpha():
+    op = make_op(2, 1.9, 1, 128)
+    f = torch.from_numpy(inputs.uniform_rhs(2, 128, 1, seed=4)).cuda()
+    its = {}
+    for kind in (1, 2):
+        op.set_preconditioner(kind)
+        its[kind] = op.solve(f, tol=1e-10)[1][0]["iters"]
+    assert its[2] * 3 < its[1], its

@@ -430,3 +430,32 @@ def test_tau_pcg_matches_cholesky(d, N, alpha):
     _, it_emb, _ = oracle.solve_cg(G, f, tol=1e-12,
                                    precond=lambda v: oracle.precond_apply(G, v))
     assert it <= it_emb + 1
+
+
+@pytest.mark.parametrize("d,N", [(1, 24), (2, 12), (3, 6)])
+def test_tau_symbol_cosine_series_equals_sine_quotient(d, N):
+    """The cosine-series eigenvalues equal (S..S c) / prod sin(theta), c the
+    Hankel-corrected first column, evaluated with dense sine matrices."""
+    G = oracle.generator(d, 0.8, 1, N, lam=1.0)
+    n = N - 1
+    c = G[(slice(0, n),) * d].copy()
+    for ax in range(d):
+        a = [slice(None)] * d
+        b = [slice(None)] * d
+        a[ax] = slice(0, n - 2)
+        b[ax] = slice(2, n)
+        c2 = c.copy()
+        c2[tuple(a)] -= c[tuple(b)]
+        c = c2
+    k = np.arange(1, n + 1)
+    S = np.sin(np.pi * np.outer(k, k) / N)
+    y = c
+    for ax in range(d):
+        y = np.moveaxis(np.tensordot(S, y, axes=([1], [ax])), 0, ax)
+    den = np.ones((n,) * d)
+    for ax in range(d):
+        shp = [1] * d
+        shp[ax] = n
+        den = den * S[:, 0].reshape(shp)
+    lam = oracle.tau_symbol(G)
+    np.testing.assert_allclose(lam, y / den, rtol=1e-10, atol=1e-12 * np.abs(lam).max())
