@@ -43,7 +43,7 @@ def grid_points(N, d=1):
     return -1.0 + h * np.arange(1, N)
 
 
-def origin_rule(om, d, p):
+def origin_rule(om, d, p, gamma=2.0):
     """Redistribute omega_0 (the weight of Phi(x, 0), a limit) to the axis
     offsets.  gamma = 2: Phi(x, 0) = u''-type limit, replaced by the average
     over axes s of Phi(x, h e_s) (p <= 1; the paper's 1D rule
@@ -54,6 +54,9 @@ def origin_rule(om, d, p):
     zero = (0,) * d
     w0 = W[zero]
     W[zero] = 0.0
+    if gamma < 2.0:
+        # gamma < 2: Phi(x, 0) = 0 (eq. (gamma2)), the origin weight drops out
+        return W
     c1, c2 = (1.0, 0.0) if p <= 1 else (4.0 / 3.0, -1.0 / 3.0)
     for s in range(d):
         e1 = tuple(1 if j == s else 0 for j in range(d))
@@ -71,30 +74,32 @@ def _offset_tables(N, d):
     return k, z, norm
 
 
-def coefficients(W, d, h, T):
+def coefficients(W, d, h, T, gamma=GAMMA):
     """a_k for k in {0..N}^d from the origin-corrected weights W."""
     N = W.shape[0] - 1
     k, z, norm = _offset_tables(N, d)
     Wf = W.reshape(-1)
     a = np.zeros_like(Wf)
     nz = norm > 0
-    a[nz] = (2.0 ** z[nz]) * Wf[nz] / (h * norm[nz]) ** GAMMA
+    a[nz] = (2.0 ** z[nz]) * Wf[nz] / (h * norm[nz]) ** gamma
     # a_0: compensated sum over all neighbours, then the far field
     terms = list((2.0 ** (d - z[nz])) * a[nz])
     a[~nz] = -math.fsum(terms) - (2.0 ** d) * T
     return a.reshape(W.shape)
 
 
-def generator(d, alpha, p, N, lam=0.0, return_parts=False):
+def generator(d, alpha, p, N, lam=0.0, return_parts=False, gamma=2.0):
     """G_k = -c_{d,alpha} a_k on {0..N}^d (FP64).
 
     lam > 0 selects the tempered kernel exp(-lam r) (Remark 2.2, reading R6:
-    same normalisation constant c_{d,alpha})."""
+    same normalisation constant c_{d,alpha}).  gamma in (alpha, 2] is the
+    splitting parameter (Sec. 2.1: Phi = second difference / |xi|^gamma;
+    gamma < 2 has no origin term)."""
     h = 2.0 / N
-    om = _weights(d, alpha, p, N, h=h, lam=lam)
-    W = origin_rule(om, d, p)
+    om = _weights(d, alpha, p, N, h=h, lam=lam, gamma=gamma)
+    W = origin_rule(om, d, p, gamma=gamma)
     T = far_field_T(d, alpha, L=2.0, lam=lam)
-    a = coefficients(W, d, h, T)
+    a = coefficients(W, d, h, T, gamma=gamma)
     G = -c_dalpha(d, alpha) * a
     if return_parts:
         return G, dict(omega=om, W=W, T=T, a=a)

@@ -68,10 +68,10 @@ def _elements_1d(p, N):
     return out
 
 
-def _weights_1d(alpha, p, N, h, lam):
+def _weights_1d(alpha, p, N, h, lam, gamma=2.0):
     """Exact 1D weights in mpmath, returned as float64 (length N+1)."""
     with mpmath.workdps(50):
-        s0 = 2 - mpmath.mpf(alpha)          # sigma_0 = gamma - alpha
+        s0 = mpmath.mpf(gamma) - mpmath.mpf(alpha)   # sigma_0 = gamma - alpha
         lam_l = mpmath.mpf(lam) * mpmath.mpf(h)   # kernel rate in lattice units
 
         def moment(j, a, b):
@@ -84,9 +84,9 @@ def _weights_1d(alpha, p, N, h, lam):
 
         om = [mpmath.mpf(0)] * (N + 1)
         for lo, hi, basis in _elements_1d(p, N):
-            mom = [moment(j, lo, hi) for j in range(3)]
             for node, coef in basis:
-                om[node] += sum(mpmath.mpf(c) * mom[j] for j, c in enumerate(coef))
+                om[node] += sum(mpmath.mpf(c) * moment(j, lo, hi)
+                                for j, c in enumerate(coef) if c != 0)
         scale = mpmath.mpf(h) ** s0
         return np.array([float(w * scale) for w in om])
 
@@ -122,17 +122,17 @@ def _dim_tables(p, N, Q):
     return X, WB, first, els
 
 
-def _origin_element(d, alpha, p, h, lam, els, nr=24, nt=40):
+def _origin_element(d, alpha, p, h, lam, els, nr=24, nt=40, gamma=2.0):
     """Local integrals over the element touching xi = 0 (lattice units):
     I[a_1..a_d] = int_{[0,H]^d} prod_j phi_{a_j}(xi_j) g(xi) dxi,
-    g(xi) = K(h|xi|) |xi|^{2-d-alpha}, via d Duffy pyramids."""
+    g(xi) = K(h|xi|) |xi|^{gamma-d-alpha}, via d Duffy pyramids."""
     lo, H, basis = els[0]
     assert lo == 0.0
     nb = len(basis)
-    # Gauss-Jacobi on [0,H] with weight r^{1-alpha}: r = H(1+x)/2
-    xj, wj = roots_jacobi(nr, 0.0, 1.0 - alpha)
+    # Gauss-Jacobi on [0,H] with weight r^{gamma-alpha-1}: r = H(1+x)/2
+    xj, wj = roots_jacobi(nr, 0.0, gamma - alpha - 1.0)
     r = H * (1.0 + xj) / 2.0
-    wr = wj * (H / 2.0) ** (2.0 - alpha)
+    wr = wj * (H / 2.0) ** (gamma - alpha)
     xt, wt = _gl(nt)
     t = (xt + 1.0) / 2.0
     wt = wt / 2.0
@@ -157,7 +157,7 @@ def _origin_element(d, alpha, p, h, lam, els, nr=24, nt=40):
                 ti += 1
         R = np.outer(r, rho)
         kern = np.exp(-lam * h * R) if lam else 1.0
-        g = kern * rho[None, :] ** (2.0 - d - alpha)   # r^{1-alpha} in weight
+        g = kern * rho[None, :] ** (gamma - d - alpha)   # r^{gamma-alpha-1} in weight
         wgt = np.outer(wr, WT) * g
         vals = [[_poly_eval(coef, coords[j]) for (_, coef) in basis]
                 for j in range(d)]
@@ -169,13 +169,13 @@ def _origin_element(d, alpha, p, h, lam, els, nr=24, nt=40):
     return I
 
 
-def _weights_nd(d, alpha, p, N, h, lam, Q=None):
+def _weights_nd(d, alpha, p, N, h, lam, Q=None, gamma=2.0):
     if Q is None:
         Q = 20 if d == 2 else 14
     X, WB, first, els = _dim_tables(p, N, Q)
     E, nb = WB.shape[0], WB.shape[1]
     step = 2 if p == 2 else 1
-    ex = 2.0 - d - alpha
+    ex = gamma - d - alpha
 
     def g_of(r2):
         r = np.sqrt(r2)
@@ -212,13 +212,13 @@ def _weights_nd(d, alpha, p, N, h, lam, Q=None):
                                c: c + step * E: step] += I[:, a, b, c]
     else:
         raise ValueError("d must be 2 or 3 here")
-    I0 = _origin_element(d, alpha, p, h, lam, els)
+    I0 = _origin_element(d, alpha, p, h, lam, els, gamma=gamma)
     for idx in np.ndindex(*(nb,) * d):
         om[tuple(first[0] + i for i in idx)] += I0[idx]
-    return om * h ** (2.0 - alpha)
+    return om * h ** (gamma - alpha)
 
 
-def weights_at(d, alpha, p, N, nodes, h=None, lam=0.0, Q=None):
+def weights_at(d, alpha, p, N, nodes, h=None, lam=0.0, Q=None, gamma=2.0):
     """omega^p_k at selected multi-indices `nodes` (integer array (m, d)),
     d = 2 or 3, by the same element quadrature as weights(): the sum over
     the elements touching node k of int phi_k g.  For sampled checks at
@@ -229,8 +229,8 @@ def weights_at(d, alpha, p, N, nodes, h=None, lam=0.0, Q=None):
         Q = 20 if d == 2 else 14
     X, WB, first, els = _dim_tables(p, N, Q)
     E, nb = WB.shape[0], WB.shape[1]
-    ex = 2.0 - d - alpha
-    I0 = _origin_element(d, alpha, p, h, lam, els)
+    ex = gamma - d - alpha
+    I0 = _origin_element(d, alpha, p, h, lam, els, gamma=gamma)
     X2 = X ** 2
     out = np.zeros(len(nodes))
     for m, k in enumerate(np.asarray(nodes, dtype=np.int64)):
@@ -256,17 +256,20 @@ def weights_at(d, alpha, p, N, nodes, h=None, lam=0.0, Q=None):
             else:
                 total += np.einsum("qrs,q,r,s->", g, wb[0], wb[1], wb[2])
         out[m] = total
-    return out * h ** (2.0 - alpha)
+    return out * h ** (gamma - alpha)
 
 
-def weights(d, alpha, p, N, h=None, lam=0.0, Q=None):
-    """omega^p_k for k in {0..N}^d as an FP64 array of shape (N+1,)*d.
+def weights(d, alpha, p, N, h=None, lam=0.0, Q=None, gamma=2.0):
+    """omega^p_k for k in {0..N}^d as an FP64 array of shape (N+1,)*d, with
+    the splitting parameter gamma in (alpha, 2] (weight |xi|^{gamma-d-alpha}).
 
     h defaults to L/N with L = 2 (Omega = (-1,1)^d)."""
     if h is None:
         h = 2.0 / N
     if p == 2 and N % 2:
         raise ValueError("p = 2 needs an even N")
+    if not (alpha < gamma <= 2.0):
+        raise ValueError("gamma must lie in (alpha, 2]")
     if d == 1:
-        return _weights_1d(alpha, p, N, h, lam)
-    return _weights_nd(d, alpha, p, N, h, lam, Q=Q)
+        return _weights_1d(alpha, p, N, h, lam, gamma=gamma)
+    return _weights_nd(d, alpha, p, N, h, lam, Q=Q, gamma=gamma)

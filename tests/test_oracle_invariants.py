@@ -459,3 +459,100 @@ def test_tau_symbol_cosine_series_equals_sine_quotient(d, N):
         den = den * S[:, 0].reshape(shp)
     lam = oracle.tau_symbol(G)
     np.testing.assert_allclose(lam, y / den, rtol=1e-10, atol=1e-12 * np.abs(lam).max())
+
+
+def test_gamma_two_is_the_default_scheme():
+    for d, p, N in ((1, 2, 16), (2, 1, 8)):
+        assert np.array_equal(oracle.generator(d, 0.7, p, N),
+                              oracle.generator(d, 0.7, p, N, gamma=2.0))
+
+
+@pytest.mark.parametrize("d,N", [(1, 16), (2, 8)])
+@pytest.mark.parametrize("p", [0, 1, 2])
+def test_weight_moments_gamma(d, N, p):
+    """sum_k omega_k xi_k^j equals the moment of |xi|^{gamma-d-alpha} for
+    gamma = 1 + alpha/2 (omega_0 included)."""
+    alpha = 1.2
+    gamma = 1.0 + alpha / 2
+    L, h = 2.0, 2.0 / N
+    om = weights(d, alpha, p, N, h=h, gamma=gamma)
+    xi = h * np.arange(N + 1)
+    for js in itertools.product(range(p + 1), repeat=d):
+        J = sum(js)
+        if d == 1:
+            q = J + gamma - alpha
+            ref = L ** q / q
+        else:
+            # cone coordinates as in _moment_reference, radial power J + gamma - alpha
+            total = 0.0
+            for t in range(d):
+                def integrand(w):
+                    rho = math.sqrt(1.0 + w * w)
+                    e = [0.0, 0.0]
+                    e[t] = 1.0 / rho
+                    e[1 - t] = w / rho
+                    P = e[0] ** js[0] * e[1] ** js[1]
+                    qq = J + gamma - alpha
+                    return P * (L * rho) ** qq / qq * rho ** (-2)
+                total += integrate.quad(integrand, 0, 1, epsabs=0, epsrel=1e-13)[0]
+            ref = total
+        mono = np.ones_like(om)
+        for s in range(d):
+            shp = [1] * d
+            shp[s] = N + 1
+            mono = mono * (xi ** js[s]).reshape(shp)
+        got = math.fsum((om * mono).ravel())
+        assert math.isclose(got, ref, rel_tol=1e-10), (js, got, ref)
+
+
+@pytest.mark.parametrize("d,N", [(1, 8), (2, 4)])
+@pytest.mark.parametrize("p", [1, 2])
+def test_gamma_brute_force_sign_pattern_sum(d, N, p):
+    """gamma < 2: the scheme summed sign pattern by sign pattern with
+    Phi = second difference / |xi|^gamma and no origin term."""
+    alpha, gamma = 0.8, 1.5
+    G, parts = oracle.generator(d, alpha, p, N, return_parts=True, gamma=gamma)
+    om, T = parts["omega"], parts["T"]
+    h = 2.0 / N
+    c = c_dalpha(d, alpha)
+    rng = np.random.default_rng(8)
+    u = rng.uniform(-1, 1, (N - 1,) * d)
+    U = np.zeros((N + 1,) * d)
+    U[(slice(1, N),) * d] = u
+    ref = np.zeros((N - 1,) * d)
+    for i in itertools.product(range(1, N), repeat=d):
+        terms = []
+        for k in itertools.product(range(N + 1), repeat=d):
+            if not any(k):
+                continue
+            wk = om[k] / (h * math.sqrt(sum(kk * kk for kk in k))) ** gamma
+            for m in itertools.product((1, -1), repeat=d):
+                j = tuple(ii + mm * kk for ii, mm, kk in zip(i, m, k))
+                uj = U[j] if all(0 <= jj <= N for jj in j) else 0.0
+                terms.append(wk * (uj - U[i]))
+        terms.append(-(2 ** d) * T * U[i])
+        ref[tuple(ii - 1 for ii in i)] = -c * math.fsum(terms)
+    got = oracle.apply_dense(G, u)
+    scale = np.abs(oracle.dense_matrix(G)).sum(axis=1).max()
+    assert np.abs(got - ref).max() <= 1e-13 * scale
+
+
+@pytest.mark.parametrize("alpha", [0.6, 1.0, 1.5])
+@pytest.mark.parametrize("p", [0, 1, 2])
+def test_gamma_convergence_rate(alpha, p):
+    """gamma = 1 + alpha/2: the error of the product on u = (1-x^2)_+^{2.1+alpha}
+    decays like h^{2-alpha} for phi^0 and phi^1, as Sec. 3.1 states.  For
+    phi^2 the scheme as written (Phi(x, 0) = 0, no origin term) also gives
+    h^{2-alpha}: near xi = 0, Phi(x, xi) ~ u''(x) xi^{2-gamma} is not smooth,
+    and its interpolation error on the first element limits every degree."""
+    from oracle import exact
+    gamma = 1.0 + alpha / 2
+    s = 2.1 + alpha
+    errs = []
+    for N in (64, 128, 256):
+        G = oracle.generator(1, alpha, p, N, gamma=gamma)
+        x = oracle.grid_points(N)
+        y = oracle.apply(G, (1 - x * x) ** s)
+        errs.append(np.abs(y - exact.frac_lap_ball_power(x * x, s, alpha, 1)).max())
+    rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(abs(r - (2.0 - alpha)) <= 0.05 for r in rates), rates
