@@ -84,6 +84,17 @@ typedef struct {
 fl_status fl_weights(int d, double alpha, int degree, double h, int kernel, double lambda,
                      void *stream, fl_op *out);
 
+/*
+ * fl_weights_gamma -- as fl_weights with the splitting parameter gamma of
+ * the operator factorization (Sec. 2.1: Phi = second difference over
+ * |xi|^gamma, weights omega_k = int phi_k K(|xi|) |xi|^{gamma-d-alpha}),
+ * gamma in (alpha, 2].  gamma = 2 is fl_weights.  For gamma < 2 the origin
+ * value Phi(x, 0) is 0 (eq. (gamma2)): no origin term, a_k = 2^{z(k)}
+ * omega_k / |xi_k|^gamma.  FL_E_INVAL for gamma outside (alpha, 2].
+ */
+fl_status fl_weights_gamma(int d, double alpha, int degree, double h, int kernel, double lambda,
+                           double gamma, void *stream, fl_op *out);
+
 /* Copy the FP64 generator G_k, k in {0..N}^d (row-major, (N+1)^d values),
  * to host memory.  count must be >= (N+1)^d.  Test hook. */
 fl_status fl_generator(fl_op A, double *host_out, size_t count);

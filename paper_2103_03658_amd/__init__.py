@@ -28,12 +28,13 @@ def _stream_ptr(stream):
 class Operator:
     """The discrete operator A (g = 0 part of (-Delta)^{alpha/2}_h) on (-1,1)^d.
 
-    Built on the current CUDA/HIP device by fl_weights.  Vectors are torch
+    Built on the current CUDA/HIP device by fl_weights_gamma (splitting
+    parameter gamma in (alpha, 2], default 2).  Vectors are torch
     tensors on that device holding nrhs * n^d values (any shape with that
     many elements, contiguous)."""
 
     def __init__(self, d, alpha, degree, N=None, h=None, kernel="fractional", lam=0.0,
-                 stream=None):
+                 stream=None, gamma=2.0):
         if h is None:
             if N is None:
                 raise ValueError("give N or h")
@@ -41,12 +42,14 @@ class Operator:
         kind = {"fractional": FL_KERNEL_FRACTIONAL, "tempered": FL_KERNEL_TEMPERED}[kernel]
         self._h = ctypes.c_void_p()
         self._lib = lib()
-        check(self._lib.fl_weights(int(d), float(alpha), int(degree), float(h), kind,
-                                   float(lam), _stream_ptr(stream), ctypes.byref(self._h)))
+        check(self._lib.fl_weights_gamma(int(d), float(alpha), int(degree), float(h), kind,
+                                         float(lam), float(gamma), _stream_ptr(stream),
+                                         ctypes.byref(self._h)))
         q = [ctypes.c_int() for _ in range(4)]
         check(self._lib.fl_query(self._h, *[ctypes.byref(x) for x in q]))
         self.d, self.N, self.n, self.M = (x.value for x in q)
         self.alpha, self.degree, self.kernel, self.lam = float(alpha), int(degree), kernel, lam
+        self.gamma = float(gamma)
         self.nd = self.n ** self.d
 
     # -- host copies (test hooks) ------------------------------------------

@@ -45,6 +45,9 @@ _P = ctypes.c_void_p
 _SIGS = {
     "fl_weights": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                   ctypes.c_int, ctypes.c_double, _P, ctypes.POINTER(_P)]),
+    "fl_weights_gamma": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                        ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                        ctypes.c_double, _P, ctypes.POINTER(_P)]),
     "fl_generator": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t]),
     "fl_symbol": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t]),
     "fl_embedding": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t]),

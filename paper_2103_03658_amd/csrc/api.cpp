@@ -249,10 +249,16 @@ const char* fl_last_error(void) { return g_last_error.c_str(); }
 
 fl_status fl_weights(int d, double alpha, int degree, double h, int kernel, double lambda,
                      void* stream, fl_op* out) {
+  return fl_weights_gamma(d, alpha, degree, h, kernel, lambda, 2.0, stream, out);
+}
+
+fl_status fl_weights_gamma(int d, double alpha, int degree, double h, int kernel, double lambda,
+                           double gamma, void* stream, fl_op* out) {
   return guarded([&]() -> fl_status {
     if (!out) return fail(FL_E_INVAL, "out is NULL");
     if (d < 1 || d > 3) return fail(FL_E_INVAL, "d must be 1, 2 or 3");
     if (!(alpha > 0.0 && alpha < 2.0)) return fail(FL_E_INVAL, "alpha must lie in (0, 2)");
+    if (!(gamma > alpha && gamma <= 2.0)) return fail(FL_E_INVAL, "gamma must lie in (alpha, 2]");
     if (degree < 0 || degree > 2) return fail(FL_E_INVAL, "degree must be 0, 1 or 2");
     if (!(h > 0.0) || !std::isfinite(h)) return fail(FL_E_INVAL, "h must be positive");
     if (kernel != FL_KERNEL_FRACTIONAL && kernel != FL_KERNEL_TEMPERED)
@@ -295,7 +301,7 @@ fl_status fl_weights(int d, double alpha, int degree, double h, int kernel, doub
       A->lam32 = (float*)dmalloc((size_t)nf * sizeof(float));
       A->linv64 = (double*)dmalloc((size_t)nf * sizeof(double));
       A->linv32 = (float*)dmalloc((size_t)nf * sizeof(float));
-      fl::GenParams gp{d, degree, N, kernel, alpha, A->h, A->lambda, A->c};
+      fl::GenParams gp{d, degree, N, kernel, alpha, A->h, A->lambda, A->c, gamma};
       fl::build_generator(gp, A->G, st);
       fl::build_symbol(A->g, A->G, A->lam64, A->lam32, st);
       {

@@ -151,6 +151,7 @@ const void* twiddles(int M, bool fp32, hipStream_t st);
 struct GenParams {
   int d, p, N, kernel;
   double alpha, h, lambda, c;
+  double gamma;   // splitting parameter in (alpha, 2]
 };
 void build_generator(const GenParams& gp, double* G, hipStream_t st);
 void build_symbol(const Geometry& g, const double* G, double* lam64, float* lam32,

@@ -3,17 +3,18 @@
 //
 // Weight integrals (Sec. 2.1 eq. (wi-1D), Sec. 2.2 eq. (2D-scheme0),
 // Remark 2.2 for a kernel K):  omega_k = int_{[0,L]^d} phi_k K(|xi|)
-// |xi|^{gamma-d-alpha} dxi with gamma = 2, evaluated element by element:
+// |xi|^{gamma-d-alpha} dxi, gamma in (alpha, 2] the splitting parameter
+// (sigma = gamma - alpha below), evaluated element by element:
 //  * every element away from xi = 0 by tensor Gauss-Legendre (16 points per
 //    axis within four elements of the origin, 8 beyond, where the nearest
 //    singularity is far outside the element's Bernstein ellipse);
 //  * the element at the origin in cone coordinates xi = r e(w): the radial
-//    factor r^{1-alpha} times a polynomial (times exp(-lambda h rho r)) is
+//    factor r^{sigma-1} times a polynomial (times exp(-lambda h rho r)) is
 //    integrated exactly (power moments, or the all-positive series of the
 //    lower incomplete gamma function), the cone coordinates w by
 //    Gauss-Legendre.  No closed form with cancellation is used.
 // For K = 1 the integrals are taken on the unit lattice and scaled by
-// h^{2-alpha}.  Nodes gather their elements in a fixed order and a_0 is a
+// h^{sigma}.  Nodes gather their elements in a fixed order and a_0 is a
 // fixed-order tree sum, so the generator is deterministic.
 #include <cmath>
 #include <vector>
@@ -108,7 +109,7 @@ __device__ __forceinline__ double bsum(double v, double* sh) {
 // ---------------------------------------------------------------------------
 // origin element: out[a] for local multi-index a (nb^d values), lattice units
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_origin(int d, int p, double alpha, double lamh,
+__global__ void __launch_bounds__(256) k_origin(int d, int p, double sig, double lamh,
                                                 const GLTables* tb, double* out) {
   __shared__ double sh[8];
   const int nb = p + 1;
@@ -136,10 +137,10 @@ __global__ void __launch_bounds__(256) k_origin(int d, int p, double alpha, doub
     double rho2 = 0.0;
     for (int dd = 0; dd < d; ++dd) rho2 += e[dd] * e[dd];
     const double rho = sqrt(rho2);
-    const double ang = wang * pow(rho, 2.0 - d - alpha);
-    // radial moments r^{1-alpha+m}, m = 0 .. d*p
+    const double ang = wang * pow(rho, sig - d);
+    // radial moments r^{sigma-1+m}, m = 0 .. d*p
     double mom[7];
-    for (int m = 0; m <= d * p; ++m) mom[m] = radial_moment(2.0 - alpha + m, lamh * rho, H);
+    for (int m = 0; m <= d * p; ++m) mom[m] = radial_moment(sig + m, lamh * rho, H);
     for (int o = 0; o < nout; ++o) {
       // polynomial in r of prod_dd phi_{a_dd}(r e_dd)
       double poly[7] = {1, 0, 0, 0, 0, 0, 0};
@@ -195,7 +196,7 @@ __device__ __forceinline__ void elem_bounds(int p, int N, int e, double& lo, dou
 }
 
 template <int Q>
-__device__ void elem_quad(int d, int p, int N, const int* ev, double alpha, double lamh,
+__device__ void elem_quad(int d, int p, int N, const int* ev, double sig, double lamh,
                           const double* xq, const double* wq, double* acc) {
   const int nb = p + 1;
   double X[3][Q], Wt[3][Q], B[3][3][Q];
@@ -209,7 +210,7 @@ __device__ void elem_quad(int d, int p, int N, const int* ev, double alpha, doub
       for (int a = 0; a < nb; ++a) B[s][a][q] = basis_val(p, a, x - org);
     }
   }
-  const double ex = 0.5 * (2.0 - d - alpha);
+  const double ex = 0.5 * (sig - d);
   int nout = 1;
   for (int s = 0; s < d; ++s) nout *= nb;
   for (int o = 0; o < nout; ++o) acc[o] = 0.0;
@@ -253,7 +254,7 @@ __device__ void elem_quad(int d, int p, int N, const int* ev, double alpha, doub
 }
 
 __global__ void __launch_bounds__(128) k_elements(int d, int p, int N, int Eel, long total,
-                                                  double alpha, double lamh,
+                                                  double sig, double lamh,
                                                   const GLTables* tb, double* out) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
@@ -274,9 +275,9 @@ __global__ void __launch_bounds__(128) k_elements(int d, int p, int N, int Eel, 
     return;
   }
   if (emax < 4)
-    elem_quad<QN>(d, p, N, ev, alpha, lamh, tb->xn, tb->wn, acc);
+    elem_quad<QN>(d, p, N, ev, sig, lamh, tb->xn, tb->wn, acc);
   else
-    elem_quad<QF>(d, p, N, ev, alpha, lamh, tb->xf, tb->wf, acc);
+    elem_quad<QF>(d, p, N, ev, sig, lamh, tb->xf, tb->wf, acc);
   for (int o = 0; o < nout; ++o) out[e * nout + o] = acc[o];
 }
 
@@ -380,11 +381,12 @@ __global__ void __launch_bounds__(256) k_far(int d, double alpha, double lam, do
   if (threadIdx.x == 0) *T = t;
 }
 
-// a_k = 2^{z(k)} W_k / |xi_k|^2 (W: origin rule applied), G_k = -c a_k for
+// a_k = 2^{z(k)} W_k / |xi_k|^gamma (W: origin rule applied for gamma = 2;
+// for gamma < 2 Phi(x, 0) = 0 and omega_0 drops out), G_k = -c a_k for
 // k != 0; per-block partial of sum 2^{d-z(k)} a_k for the diagonal.
 __global__ void __launch_bounds__(256) k_coeff(int d, int p, int N, double h, double c,
-                                               long total, const double* omega, double* G,
-                                               double* part) {
+                                               double gamma, long total, const double* omega,
+                                               double* G, double* part) {
   __shared__ double sh[8];
   const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
   double term = 0.0;
@@ -403,7 +405,7 @@ __global__ void __launch_bounds__(256) k_coeff(int d, int p, int N, double h, do
       k2 += (long)kv[s] * kv[s];
     }
     double W = omega[k];
-    if (z == d - 1) {  // on an axis: origin rule
+    if (gamma == 2.0 && z == d - 1) {  // on an axis: origin rule
       const double w0 = omega[0];
       const int m = kv[nz];
       const double c1 = p <= 1 ? 1.0 : 4.0 / 3.0;
@@ -411,7 +413,8 @@ __global__ void __launch_bounds__(256) k_coeff(int d, int p, int N, double h, do
       if (m == 1) W += w0 * c1 / d;
       if (m == 2) W += w0 * c2 / d;
     }
-    const double a = (double)(1 << z) * W / (h * h * (double)k2);
+    const double r2 = h * h * (double)k2;
+    const double a = (double)(1 << z) * W / (gamma == 2.0 ? r2 : pow(r2, 0.5 * gamma));
     G[k] = -c * a;
     term = (double)(1 << (d - z)) * a;
   }
@@ -445,7 +448,8 @@ void build_generator(const GenParams& gp, double* G, hipStream_t st) {
   const bool tempered = gp.kernel == 1 && gp.lambda > 0.0;
   // lattice-unit kernel rate; for K = 1 integrate on the unit lattice and scale
   const double lamh = tempered ? gp.lambda * gp.h : 0.0;
-  const double scale = std::pow(gp.h, 2.0 - gp.alpha);
+  const double sig = gp.gamma - gp.alpha;
+  const double scale = std::pow(gp.h, sig);
   const int nb = p + 1;
   const int Eel = p == 0 ? N + 1 : (p == 1 ? N : N / 2);
   long nelem = 1, nnode = 1;
@@ -466,15 +470,15 @@ void build_generator(const GenParams& gp, double* G, hipStream_t st) {
   FL_HIP(hipMalloc(&part, (size_t)nblk * sizeof(double)));
   FL_HIP(hipMalloc(&T, sizeof(double)));
   FL_HIP(hipMemcpyAsync(dtb, &tb, sizeof(GLTables), hipMemcpyHostToDevice, st));
-  hipLaunchKernelGGL(k_origin, dim3(1), dim3(256), 0, st, d, p, gp.alpha, lamh, dtb, orig);
+  hipLaunchKernelGGL(k_origin, dim3(1), dim3(256), 0, st, d, p, sig, lamh, dtb, orig);
   hipLaunchKernelGGL(k_elements, dim3((unsigned)((nelem + 127) / 128)), dim3(128), 0, st, d, p,
-                     N, Eel, nelem, gp.alpha, lamh, dtb, elem);
+                     N, Eel, nelem, sig, lamh, dtb, elem);
   hipLaunchKernelGGL(k_gather, dim3((unsigned)nblk), dim3(thr), 0, st, d, p, N, Eel, nnode, elem,
                      orig, scale, omega);
   hipLaunchKernelGGL(k_far, dim3(1), dim3(256), 0, st, d, gp.alpha, tempered ? gp.lambda : 0.0,
                      2.0, dtb, T);
-  hipLaunchKernelGGL(k_coeff, dim3((unsigned)nblk), dim3(thr), 0, st, d, p, N, gp.h, gp.c, nnode,
-                     omega, G, part);
+  hipLaunchKernelGGL(k_coeff, dim3((unsigned)nblk), dim3(thr), 0, st, d, p, N, gp.h, gp.c,
+                     gp.gamma, nnode, omega, G, part);
   hipLaunchKernelGGL(k_diag, dim3(1), dim3(256), 0, st, d, gp.c, (int)nblk, part, T, G);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) throw Error(4, std::string("generator kernels: ") + hipGetErrorString(e));

@@ -115,3 +115,12 @@ def test_manufactured_rhs_matches_closed_form():
 def test_exterior_null_and_unsupported():
     lib = _lib.lib()
     assert lib.fl_exterior(None, None, None, None, 1, None) == _lib.FL_E_INVAL
+
+
+@pytest.mark.parametrize("gamma", [0.5, 1.0, 2.5, float("nan")])
+def test_fl_weights_gamma_validation(gamma):
+    lib = _lib.lib()
+    h = ctypes.c_void_p()
+    st = lib.fl_weights_gamma(2, 1.0, 1, 0.25, 0, 0.0, gamma, None, ctypes.byref(h))
+    assert st == _lib.FL_E_INVAL
+    assert h.value is None
