@@ -155,6 +155,29 @@ def pass_flops(d, N, nrhs):
     return [col * nrhs, mid * nrhs, col * nrhs]
 
 
+def precond_bytes(d, N, nrhs, sr):
+    """Algorithmic HBM bytes of each kernel of one batched tau preconditioner
+    application (2D: axis-0 sine pass, last-axis sine * multiplier * sine in
+    place, axis-0 sine pass): every intermediate is real, n^2 per RHS."""
+    n = N - 1
+    assert d == 2
+    vec = n * n * sr * nrhs
+    sym = (N + 1) ** 2 * sr
+    return [2 * vec, 2 * vec + sym, 2 * vec]
+
+
+def precond_flops(d, N, nrhs):
+    """Nominal flops of the tau passes: 5 M log2 M per length-M transform of
+    a packed pair of odd-extended lines, 2 per element for the multiplier."""
+    n, M = N - 1, 2 * N
+    assert d == 2
+    fft = 5.0 * M * math.log2(M)
+    pairs = (n + 1) // 2
+    col = pairs * fft
+    mid = pairs * (2.0 * fft + 2.0 * M)
+    return [col * nrhs, mid * nrhs, col * nrhs]
+
+
 def run_configs(dev, tol, quick=False):
     """The other workloads of the method at their full sizes (not the headline
     metric): per config, solves/s or latency, iterations, true residuals; and
@@ -351,9 +374,17 @@ def main():
             acc = m if acc is None else [x + y for x, y in zip(acc, m)]
         ms = [x / max(1, args.steps) for x in acc]
         by = pass_bytes(2, N, nrhs, 4 if fp32 else 8)
+        acc = None
+        for _ in range(max(1, args.steps)):
+            m = ops[1.5].profile_precond(u_, reps=args.profile_reps)
+            acc = m if acc is None else [x + y for x, y in zip(acc, m)]
+        mp = [x / max(1, args.steps) for x in acc]
+        bp = precond_bytes(2, N, nrhs, 4 if fp32 else 8)
         print(json.dumps({"roofline_only": True, "precision": "f32" if fp32 else "f64",
                           "ms_per_kernel": ms, "bytes_per_kernel": by,
                           "GBs": [b / (t * 1e-3) / 1e9 for b, t in zip(by, ms)],
+                          "precond_ms_per_kernel": mp, "precond_bytes_per_kernel": bp,
+                          "precond_GBs": [b / (t * 1e-3) / 1e9 for b, t in zip(bp, mp)],
                           "schedule": sched}))
         return
 
@@ -446,6 +477,20 @@ def main():
 
     pk64, pk32 = passes(False), passes(True)
 
+    # the tau preconditioner's kernels (same operator, schedule and batch)
+    pnames = ["tau_axis0_sine", "tau_last_axis_sine_mult_sine", "tau_axis0_sine_back"]
+
+    def ppasses(fp32):
+        u_ = rhs[a].to(torch.float32).contiguous() if fp32 else rhs[a]
+        ms_ = ops[a].profile_precond(u_, reps=args.profile_reps)
+        by_ = precond_bytes(2, N, nrhs, 4 if fp32 else 8)
+        fl_ = precond_flops(2, N, nrhs)
+        return [{"kernel": nm, "ms": t, "bytes": b, "GBs": b / (t * 1e-3) / 1e9,
+                 "flops": f, "TFLOPs": f / (t * 1e-3) / 1e12}
+                for nm, t, b, f in zip(pnames, ms_, by_, fl_)]
+
+    pp64, pp32 = ppasses(False), ppasses(True)
+
     # a plain device copy of 1 GiB (read + write), HIP events on torch's stream
     src = torch.ones((1 << 30) // 4, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
@@ -471,7 +516,10 @@ def main():
             "copy_GBs": copy_gbs, "frac_of_copy": kd["GBs"] / copy_gbs,
             "per_kernel_f64": pk64, "per_kernel_f32": pk32,
             "matvec_ms_f64": sum(k["ms"] for k in pk64),
-            "matvec_ms_f32": sum(k["ms"] for k in pk32)}
+            "matvec_ms_f32": sum(k["ms"] for k in pk32),
+            "precond_per_kernel_f64": pp64, "precond_per_kernel_f32": pp32,
+            "precond_ms_f64": sum(k["ms"] for k in pp64),
+            "precond_ms_f32": sum(k["ms"] for k in pp32)}
 
     configs = run_configs(dev, args.tol) if args.configs else None
 

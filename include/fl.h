@@ -220,6 +220,16 @@ fl_status fl_profile_apply(fl_op A, const void *u, void *y, int nrhs, int fp32, 
                            void *stream, double *ms_per_pass, int max_passes, int *n_passes);
 
 /*
+ * fl_profile_precond -- the same measurement for the preconditioner y = P u
+ * of fl_apply_precond (kind 2: the sine passes of the tau inverse, 1 kernel
+ * for d = 1, 3 for d = 2, 5 for d = 3; kind 1: the zero-padded passes of
+ * fl_profile_apply with the inverse multiplier).  Same arguments and errors
+ * as fl_profile_apply; FL_E_INVAL with preconditioner kind 0.
+ */
+fl_status fl_profile_precond(fl_op A, const void *u, void *y, int nrhs, int fp32, int reps,
+                             void *stream, double *ms_per_pass, int max_passes, int *n_passes);
+
+/*
  * Preconditioning of fl_solve (the paper names no solver; A is SPD, Sec. 2.2):
  *   kind 2 (default): P = tau(A)^{-1}, the inverse of the natural tau
  *     approximation of the multilevel Toeplitz matrix (A minus its Hankel

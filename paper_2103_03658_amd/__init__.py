@@ -145,16 +145,22 @@ class Operator:
     def profile_apply(self, u, out=None, reps=20, stream=None):
         """Mean milliseconds per kernel of y = A u (HIP events between the
         kernels, on the stream the kernels run on)."""
+        return self._profile(self._lib.fl_profile_apply, u, out, reps, stream)
+
+    def profile_precond(self, u, out=None, reps=20, stream=None):
+        """Mean milliseconds per kernel of the preconditioner y = P u."""
+        return self._profile(self._lib.fl_profile_precond, u, out, reps, stream)
+
+    def _profile(self, fn, u, out, reps, stream):
         import torch
         nrhs = self._nrhs(u)
         if out is None:
             out = torch.empty_like(u)
         ms = (ctypes.c_double * 8)()
         npass = ctypes.c_int()
-        check(self._lib.fl_profile_apply(self._h, ctypes.c_void_p(u.data_ptr()),
-                                         ctypes.c_void_p(out.data_ptr()), nrhs,
-                                         1 if u.dtype == torch.float32 else 0, int(reps),
-                                         _stream_ptr(stream), ms, 8, ctypes.byref(npass)))
+        check(fn(self._h, ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(out.data_ptr()), nrhs,
+                 1 if u.dtype == torch.float32 else 0, int(reps), _stream_ptr(stream), ms, 8,
+                 ctypes.byref(npass)))
         return [ms[i] for i in range(npass.value)]
 
     def set_refinement(self, delta=1e-3, inner_tol=1e-4, max_outer=40):
@@ -171,7 +177,8 @@ class Operator:
         check(self._lib.fl_set_preconditioner(self._h, int(kind)))
 
     def apply_precond(self, u, out=None, stream=None):
-        """y = P u (restricted inverse of the embedding circulant)."""
+        """y = P u with the selected preconditioner (2: tau inverse by sine
+        transforms, 1: restricted inverse of the embedding circulant)."""
         import torch
         nrhs = self._nrhs(u)
         if out is None:

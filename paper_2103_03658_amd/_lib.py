@@ -61,6 +61,9 @@ _SIGS = {
     "fl_profile_apply": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                         _P, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                                         ctypes.POINTER(ctypes.c_int)]),
+    "fl_profile_precond": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                          _P, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_int)]),
     "fl_set_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
     "fl_set_preconditioner": (ctypes.c_int, [_P, ctypes.c_int]),
     "fl_apply_precond": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, _P]),

@@ -509,32 +509,37 @@ fl_status fl_apply(fl_op A, const void* u, void* y, int nrhs, int fp32, void* st
   });
 }
 
-fl_status fl_profile_apply(fl_op A, const void* u, void* y, int nrhs, int fp32, int reps,
-                           void* stream, double* ms_per_pass, int max_passes, int* n_passes) {
+// Shared body of fl_profile_apply (pc false: y = A u) and fl_profile_precond
+// (pc true: y = P u).
+static fl_status profile_passes(fl_op A, const void* u, void* y, int nrhs, int fp32, int reps,
+                                void* stream, double* ms_per_pass, int max_passes,
+                                int* n_passes, bool pc) {
   return guarded([&]() -> fl_status {
     if (!A) return fail(FL_E_INVAL, "null handle");
     if (!u || !y || !ms_per_pass || !n_passes) return fail(FL_E_INVAL, "null argument");
     if (u == y) return fail(FL_E_INVAL, "u and y must be distinct");
     if (nrhs < 1 || reps < 1) return fail(FL_E_INVAL, "nrhs and reps must be >= 1");
+    if (pc && A->precond == 0) return fail(FL_E_INVAL, "no preconditioner selected");
     const int np = fl::apply_npasses(A->g.d);
     if (max_passes < np) return fail(FL_E_INVAL, "max_passes too small");
     set_device(A);
     hipStream_t st = (hipStream_t)stream;
     A->begin(st);
     void* ws = A->ws.get(fl::apply_workspace_bytes(A->g, nrhs, fp32 != 0));
+    const bool odd = pc && A->precond == 2;
     auto run = [&](int only) {
       if (fp32)
-        fl::apply_passes<float>(A->g, A->sc32, A->lam32, A->tw32, (const float*)u, (float*)y,
-                                nrhs, ws, st, fl::PM_PLAIN, nullptr, nullptr, nullptr, nullptr,
-                                nullptr, nullptr, only);
+        fl::apply_passes<float>(A->g, A->sc32, pc ? pc_symbol<float>(A) : A->lam32, A->tw32,
+                                (const float*)u, (float*)y, nrhs, ws, st, fl::PM_PLAIN, nullptr,
+                                nullptr, nullptr, nullptr, nullptr, nullptr, only, odd);
       else
-        fl::apply_passes<double>(A->g, A->sc64, A->lam64, A->tw64, (const double*)u,
-                                 (double*)y, nrhs, ws, st, fl::PM_PLAIN, nullptr, nullptr,
-                                 nullptr, nullptr, nullptr, nullptr, only);
+        fl::apply_passes<double>(A->g, A->sc64, pc ? pc_symbol<double>(A) : A->lam64, A->tw64,
+                                 (const double*)u, (double*)y, nrhs, ws, st, fl::PM_PLAIN,
+                                 nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, only, odd);
     };
-    // one whole product puts every pass's input in place; then each pass runs
-    // reps times back to back between two events; a last whole product
-    // leaves y = A u
+    // one whole application puts every pass's input in place; then each pass
+    // runs reps times back to back between two events; a last whole
+    // application leaves the result in y
     hipEvent_t ev[2];
     FL_HIP(hipEventCreate(&ev[0]));
     FL_HIP(hipEventCreate(&ev[1]));
@@ -556,6 +561,18 @@ fl_status fl_profile_apply(fl_op A, const void* u, void* y, int nrhs, int fp32, 
     A->end(st);
     return FL_OK;
   });
+}
+
+fl_status fl_profile_apply(fl_op A, const void* u, void* y, int nrhs, int fp32, int reps,
+                           void* stream, double* ms_per_pass, int max_passes, int* n_passes) {
+  return profile_passes(A, u, y, nrhs, fp32, reps, stream, ms_per_pass, max_passes, n_passes,
+                        false);
+}
+
+fl_status fl_profile_precond(fl_op A, const void* u, void* y, int nrhs, int fp32, int reps,
+                             void* stream, double* ms_per_pass, int max_passes, int* n_passes) {
+  return profile_passes(A, u, y, nrhs, fp32, reps, stream, ms_per_pass, max_passes, n_passes,
+                        true);
 }
 
 }  // extern "C"

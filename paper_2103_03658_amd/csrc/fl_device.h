@@ -235,6 +235,11 @@ struct Plan {
 
 // One Stockham stage s >= 1: exchange the previous stage's outputs through
 // LDS, then twiddle and DFT.  lre/lim: this line's LDS planes.
+// Twiddles: of the R - 1 factors w^j (w = e^{-2 pi i k / (Ls R)}) only
+// w^(2^b), b < log2 R, are read from the table (before the exchange, so that
+// the reads overlap it); the others are products of at most log2 R - 1 of
+// those, by the binary digits of j.  Reading all R - 1 per stage held more
+// registers than the transform itself and left each stage waiting on them.
 template <typename T, int M, int E, int DIR, int s>
 __device__ __forceinline__ void stockham_stage(cx<T> (&v)[E], T* lre, T* lim, int t,
                                                const cx<T>* __restrict__ tw) {
@@ -244,6 +249,15 @@ __device__ __forceinline__ void stockham_stage(cx<T> (&v)[E], T* lre, T* lim, in
   constexpr int Lp = P::ls(s - 1);
   constexpr int R = P::radix(s);
   constexpr int Ls = P::ls(s);
+  constexpr int LR = ilog2(R);
+  cx<T> pw[E / R][LR];
+#pragma unroll
+  for (int q = 0; q < E / R; ++q) {
+    const int k = (t + q * TPL) & (Ls - 1);
+    const int i1 = k * (M / (Ls * R));
+#pragma unroll
+    for (int bit = 0; bit < LR; ++bit) pw[q][bit] = tw[i1 << bit];
+  }
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < E / Rp; ++q) {
@@ -260,7 +274,6 @@ __device__ __forceinline__ void stockham_stage(cx<T> (&v)[E], T* lre, T* lim, in
 #pragma unroll
   for (int q = 0; q < E / R; ++q) {
     const int b = t + q * TPL;
-    const int k = b & (Ls - 1);
 #pragma unroll
     for (int j = 0; j < R; ++j) {
       const int i = P::pad(b + j * (M / R));
@@ -269,7 +282,15 @@ __device__ __forceinline__ void stockham_stage(cx<T> (&v)[E], T* lre, T* lim, in
     }
 #pragma unroll
     for (int j = 1; j < R; ++j) {
-      cx<T> w = tw[j * k * (M / (Ls * R))];
+      cx<T> w = {1, 0};
+      bool first = true;
+#pragma unroll
+      for (int bit = 0; bit < LR; ++bit) {
+        if (j & (1 << bit)) {
+          w = first ? pw[q][bit] : cmul(w, pw[q][bit]);
+          first = false;
+        }
+      }
       if constexpr (DIR > 0) w.y = -w.y;
       v[q * R + j] = cmul(v[q * R + j], w);
     }

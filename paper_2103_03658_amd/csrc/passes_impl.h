@@ -185,10 +185,7 @@ __device__ __forceinline__ void line_in_lds(T* lre, T* lim, int t, const cx<T>* 
   }
 }
 
-// ODD: the columns are odd-extended (row e holds input row e - 1 for
-// 1 <= e <= n, and -input row M - e - 1 above M/2), the embedding of the
-// sine transform used by the tau preconditioner.
-template <typename T, int M, int E, bool ODD>
+template <typename T, int M, int E>
 __global__ void __launch_bounds__(512) k_first(FirstArgs<T> a) {
   using P = Plan<M, E>;
   constexpr int TPL = P::TPL;
@@ -219,10 +216,9 @@ __global__ void __launch_bounds__(512) k_first(FirstArgs<T> a) {
     for (int j = 0; j < E; ++j) {
       const int e = threadIdx.x + j * nthr;
       const int row = e >> lw1, cc = e & (W2 - 1);
-      const int src = ODD ? row - 1 : row;
       x[j] = 0;
-      if (src >= 0 && src < a.n_in && cc < ncol) {
-        const long i = ib + (long)src * a.C + cc;
+      if (row < a.n_in && cc < ncol) {
+        const long i = ib + (long)row * a.C + cc;
         if (a.mode == PM_CG) {
           x[j] = a.r[i] + bt * a.p[i];
           a.p[i] = x[j];
@@ -242,7 +238,7 @@ __global__ void __launch_bounds__(512) k_first(FirstArgs<T> a) {
   {
     const int l = threadIdx.x / TPL, t = threadIdx.x % TPL;
     T* lre = lds + l * a.LS;
-    line_in_lds<T, M, E, -1, ODD ? 2 : 1, false>(lre, lre + a.PO, t, a.tw);
+    line_in_lds<T, M, E, -1, 1, false>(lre, lre + a.PO, t, a.tw);
   }
   __syncthreads();
   // Hermitian split of each packed pair, rows k = 0..M/2, row segments of
@@ -289,8 +285,7 @@ struct LastArgs {
   const cx<T>* tw;
 };
 
-// ODD: output rows are rows 1..n of the (odd) line.
-template <typename T, int M, int E, bool ODD>
+template <typename T, int M, int E>
 __global__ void __launch_bounds__(512) k_last(LastArgs<T> a) {
   using P = Plan<M, E>;
   constexpr int TPL = P::TPL;
@@ -353,7 +348,7 @@ __global__ void __launch_bounds__(512) k_last(LastArgs<T> a) {
     const int e = threadIdx.x + j * nthr;
     const int row = e >> lw1, cc = e & (W2 - 1);
     if (e >= tot3 || cc >= ncol) continue;
-    const T v = lds[(cc >> 1) * a.LS + (cc & 1) * a.PO + P::pad(ODD ? row + 1 : row)];
+    const T v = lds[(cc >> 1) * a.LS + (cc & 1) * a.PO + P::pad(row)];
     const long i = yb0 + (long)row * a.C + cc;
     if (a.mode == PM_RESID) {
       const double r = a.f[i] - (double)v;
@@ -390,9 +385,7 @@ struct C2CArgs {
 
 // PR: 0 full transform, 1 inputs >= M/2 zero (n_in <= M/2), 2 outputs below
 // M/2 only (n_out <= M/2).
-// ODD (with PR 1 or 2): the lines are odd extensions (inputs at rows 1..n of
-// the lower half, outputs read from rows 1..n), as in k_first / k_last.
-template <typename T, int M, int E, int DIR, int PR, bool ODD>
+template <typename T, int M, int E, int DIR, int PR>
 __global__ void __launch_bounds__(512) k_c2c(C2CArgs<T> a) {
   using P = Plan<M, E>;
   constexpr int TPL = P::TPL;
@@ -415,9 +408,8 @@ __global__ void __launch_bounds__(512) k_c2c(C2CArgs<T> a) {
     for (int j = 0; j < J; ++j) {
       const int e = threadIdx.x + j * nthr;
       const int row = e >> a.lw, l = e & (a.W - 1);
-      const int src = (ODD && PR == 1) ? row - 1 : row;   // odd extension of spatial rows
       x[j] = {0, 0};
-      if (src >= 0 && src < a.n_in && l < ncol) x[j] = a.in[ib + (long)src * a.in_rs + l];
+      if (row < a.n_in && l < ncol) x[j] = a.in[ib + (long)row * a.in_rs + l];
     }
 #pragma unroll
     for (int j = 0; j < J; ++j) {
@@ -432,7 +424,7 @@ __global__ void __launch_bounds__(512) k_c2c(C2CArgs<T> a) {
   {
     const int l = threadIdx.x / TPL, t = threadIdx.x % TPL;
     T* lre = lds + l * a.LS;
-    line_in_lds<T, M, E, DIR, PR == 1 ? (ODD ? 2 : 1) : 0, PR == 2>(lre, lre + a.PO, t, a.tw);
+    line_in_lds<T, M, E, DIR, PR == 1 ? 1 : 0, PR == 2>(lre, lre + a.PO, t, a.tw);
   }
   __syncthreads();
   const long obase = o * a.out_os + col0;
@@ -444,8 +436,7 @@ __global__ void __launch_bounds__(512) k_c2c(C2CArgs<T> a) {
     const int row = e >> a.lw, l = e & (a.W - 1);
     if (e >= tot3 || l >= ncol) continue;
     const T* re = lds + l * a.LS;
-    const int src = (ODD && PR == 2) ? row + 1 : row;   // restriction to rows 1..n
-    a.out[obase + (long)row * a.out_rs + l] = {re[P::pad(src)], re[a.PO + P::pad(src)]};
+    a.out[obase + (long)row * a.out_rs + l] = {re[P::pad(row)], re[a.PO + P::pad(row)]};
   }
 }
 
@@ -468,9 +459,7 @@ struct MidArgs {
   const cx<T>* tw;
 };
 
-// ODD: each line is the odd extension of its n stored values (positions
-// 1..n and their negated reflections), outputs stored from positions 1..n.
-template <typename T, int M, int E, bool ODD>
+template <typename T, int M, int E>
 __global__ void __launch_bounds__(512) k_mid(MidArgs<T> a) {
   using P = Plan<M, E>;
   constexpr int TPL = P::TPL;
@@ -493,15 +482,7 @@ __global__ void __launch_bounds__(512) k_mid(MidArgs<T> a) {
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int i = t + j * TPL;   // n_in <= M/2: slots j >= E/2 are zero
-    if (!ODD) {
-      v[j] = (j < E / 2 && h && i < a.n_in) ? base[i] : cx<T>{0, 0};
-    } else if (j < E / 2) {
-      v[j] = (h && i >= 1 && i - 1 < a.n_in) ? base[i - 1] : cx<T>{0, 0};
-    } else {
-      const int r = M - i - 1;
-      const cx<T> w = (h && i != M / 2 && r < a.n_in) ? base[r] : cx<T>{0, 0};
-      v[j] = {-w.x, -w.y};
-    }
+    v[j] = (j < E / 2 && h && i < a.n_in) ? base[i] : cx<T>{0, 0};
   }
   fft_line<T, M, E, -1>(v, lre, lim, t, a.tw);
   // symbol row of this line
@@ -525,8 +506,8 @@ __global__ void __launch_bounds__(512) k_mid(MidArgs<T> a) {
   fft_line<T, M, E, +1>(v, lre, lim, t, a.tw);
 #pragma unroll
   for (int sl = 0; sl < E; ++sl) {
-    const int i = t + TPL * P::jslot(sl) - (ODD ? 1 : 0);   // n_out <= M/2
-    if (P::jslot(sl) < E / 2 && h && i >= 0 && i < a.n_out) base[i] = v[sl];
+    const int i = t + TPL * P::jslot(sl);   // n_out <= M/2
+    if (P::jslot(sl) < E / 2 && h && i < a.n_out) base[i] = v[sl];
   }
 }
 
@@ -649,6 +630,184 @@ __global__ void __launch_bounds__(512) k_line1d(Line1Args<T> a) {
 }
 
 // ---------------------------------------------------------------------------
+// Real sine passes (the tau preconditioner of the CG solves: the natural
+// tau approximation of A is diagonalised by the sine transform of every
+// axis).  For a real line x_1..x_n (n = N - 1, M = 2N)
+// the length-M DFT of its odd extension (0, x_1..x_n, 0, -x_n..-x_1) is
+// -2i S x with (S x)_k = sum_j x_j sin(pi j k / N).  Two real lines a, b
+// packed as a + i b therefore give Z = 2 S b - 2i S a: sigma(a) := -2 S a =
+// Im Z and sigma(b) = -Re Z come out without a Hermitian split, and every
+// intermediate stays real, n values per line (half the bytes of a complex
+// half spectrum, whose real part would be zero).  The preconditioner is
+// sigma_0 .. sigma_{d-1} diag(m) sigma_{d-1} .. sigma_0 = 2^{2d} S diag(m) S.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct SineArgs {
+  const T* in;
+  T* out;                // may equal in: a block owns whole columns
+  const T* partner;      // dot != 0: partials of partner . out
+  const int* active;     // per RHS (outer index / outer_per_rhs), may be null
+  double* part;          // dot != 0: [nrhs][max_blocks]
+  int max_blocks;
+  long C;                // real columns per outer slice (= row stride)
+  long os;               // elements between outer slices
+  long ntiles;           // column-pair tiles per outer slice
+  int outer_per_rhs;
+  int n;                 // rows (= M/2 - 1)
+  int W, lw;             // column pairs per block, log2(W)
+  int PO, LS;
+  int dot;
+  const cx<T>* tw;
+};
+
+// Strided sine pass along the row axis of [outer][n][C]: each block owns 2W
+// columns (W packed pairs), loads all n rows into the LDS planes (row e
+// holds input row e - 1), transforms the odd-extended lines and writes
+// sigma of each column.
+template <typename T, int M, int E>
+__global__ void __launch_bounds__(512) k_sine_cols(SineArgs<T> a) {
+  using P = Plan<M, E>;
+  constexpr int TPL = P::TPL;
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ double red[16];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  long tile, o;
+  xcd_tile(a.ntiles, tile, o);
+  if (a.active && !a.active[o / a.outer_per_rhs]) return;
+  const int lw1 = a.lw + 1, W2 = 2 * a.W;
+  const int nthr = a.W * TPL;
+  const long col0 = tile * W2;
+  const long cl = a.C - col0;
+  const int ncol = cl < W2 ? (int)cl : W2;
+  const long base = o * a.os + col0;
+  // rows [0, M/2) of the tile: (M/2) * 2W elements, exactly E per thread
+  {
+    T x[E];
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int e = threadIdx.x + j * nthr;
+      const int row = e >> lw1, cc = e & (W2 - 1);
+      const int src = row - 1;
+      x[j] = (src >= 0 && src < a.n && cc < ncol) ? a.in[base + (long)src * a.C + cc] : (T)0;
+    }
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int e = threadIdx.x + j * nthr;
+      const int row = e >> lw1, cc = e & (W2 - 1);
+      lds[(cc >> 1) * a.LS + (cc & 1) * a.PO + P::pad(row)] = x[j];
+    }
+  }
+  __syncthreads();
+  {
+    const int l = threadIdx.x / TPL, t = threadIdx.x % TPL;
+    T* lre = lds + l * a.LS;
+    line_in_lds<T, M, E, -1, 2, true>(lre, lre + a.PO, t, a.tw);
+  }
+  __syncthreads();
+  // positions 1..n: first column of a pair from the imaginary plane, second
+  // from the negated real plane
+  double acc = 0.0;
+  const int tot = a.n * W2;
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int e = threadIdx.x + j * nthr;
+    const int row = e >> lw1, cc = e & (W2 - 1);
+    if (e >= tot || cc >= ncol) continue;
+    const T* ln = lds + (cc >> 1) * a.LS + P::pad(row + 1);
+    const T v = (cc & 1) ? -ln[0] : ln[a.PO];
+    const long i = base + (long)row * a.C + cc;
+    a.out[i] = v;
+    if (a.dot) acc += (double)a.partner[i] * (double)v;
+  }
+  if (!a.dot) return;
+  const double blk = block_sum(acc, red);
+  if (threadIdx.x == 0) a.part[(o / a.outer_per_rhs) * a.max_blocks + tile] = blk;
+}
+
+template <typename T>
+struct SineMidArgs {
+  T* data;               // [nrhs][rows][n], transformed in place
+  const T* m;            // folded multiplier, (N+1)^d
+  const int* active;
+  long rows;             // lines per RHS (n^(d-1))
+  long o_stride;         // elements between RHS
+  int n, N1, d;
+  int LPB;               // line pairs per block
+  int nrhs;
+  const cx<T>* tw;
+};
+
+// Multiplier row of line L of the last axis: the frequencies of the other
+// axes are k = (index along that axis) + 1.
+// (L < n^2 <= 2047^2: 32-bit arithmetic; a 64-bit division here costs
+// registers that the transforms need)
+__device__ __forceinline__ long sine_mrow(long L, int n, int N1, int d) {
+  const int l = (int)L;
+  if (d == 3) return (long)((l / n + 1) * N1 + (l % n + 1)) * N1;
+  return (long)(l + 1) * N1;
+}
+
+// Contiguous last-axis pass on pairs of lines: sigma, multiply each line by
+// its own multiplier row, sigma again.  After the first transform slot k
+// holds (-sigma(b)_k, sigma(a)_k); the second transform's packed input is
+// (m_a sigma(a), m_b sigma(b)) = (m_a Z.y, -m_b Z.x), odd in k because Z is
+// odd and the multiplier is even.
+template <typename T, int M, int E>
+__global__ void __launch_bounds__(512) k_sine_mid(SineMidArgs<T> a) {
+  using P = Plan<M, E>;
+  constexpr int TPL = P::TPL;
+  extern __shared__ unsigned char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  long ol, rb;
+  xcd_tile(a.nrhs, ol, rb);
+  const int o = (int)ol;
+  if (a.active && !a.active[o]) return;
+  const int l = threadIdx.x / TPL, t = threadIdx.x % TPL;
+  const long la = 2 * (rb * a.LPB + l);
+  const bool ha = la < a.rows, hb = la + 1 < a.rows;
+  T* lre = lds + (long)l * 2 * P::LDSN;
+  T* lim = lre + P::LDSN;
+  T* pa = a.data + (long)o * a.o_stride + (ha ? la : 0) * a.n;
+  T* pb = pa + a.n;   // dereferenced only if hb
+  const int n = a.n;
+  cx<T> v[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int i = t + j * TPL;
+    const int src = j < E / 2 ? i - 1 : M - i - 1;   // i = 0 and i = M/2 give -1 and n
+    const bool ok = src >= 0 && src < n;
+    T xa = (ha && ok) ? pa[src] : (T)0;
+    T xb = (hb && ok) ? pb[src] : (T)0;
+    if (j >= E / 2) {
+      xa = -xa;
+      xb = -xb;
+    }
+    v[j] = {xa, xb};
+  }
+  fft_line<T, M, E, -1>(v, lre, lim, t, a.tw);
+  const T* ma = a.m + (ha ? sine_mrow(la, n, a.N1, a.d) : 0);
+  const T* mb = a.m + (hb ? sine_mrow(la + 1, n, a.N1, a.d) : 0);
+#pragma unroll
+  for (int sl = 0; sl < E; ++sl) {
+    const int k = t + TPL * P::jslot(sl);
+    const int kk = k <= M / 2 ? k : M - k;
+    const T sa = ha ? ma[kk] : (T)0;
+    const T sb = hb ? mb[kk] : (T)0;
+    v[sl] = {sa * v[sl].y, -(sb * v[sl].x)};
+  }
+  to_natural<T, M, E>(v);
+  fft_line<T, M, E, -1>(v, lre, lim, t, a.tw);
+#pragma unroll
+  for (int sl = 0; sl < E; ++sl) {
+    const int pos = t + TPL * P::jslot(sl);
+    if (P::jslot(sl) < E / 2 && pos >= 1 && pos <= n) {
+      if (ha) pa[pos - 1] = v[sl].y;
+      if (hb) pb[pos - 1] = -v[sl].x;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 #define FL_CASE_ME(M_, E_, ...) \
@@ -718,7 +877,7 @@ inline void lds_attr(K kernel, size_t bytes) {
 inline long pair_tiles(long C, int W) { return ((C + 1) / 2 + W - 1) / W; }
 
 template <typename T>
-void launch_first(int M, int E, FirstArgs<T> a, int nrhs, hipStream_t st, bool odd = false) {
+void launch_first(int M, int E, FirstArgs<T> a, int nrhs, hipStream_t st) {
   if (!pow2(a.W) || a.n_in > M / 2) throw Error(2, "first pass: bad tile width or rows");
   a.ntiles = pair_tiles(a.C, a.W);
   a.lw = ilog2i(a.W);
@@ -727,17 +886,12 @@ void launch_first(int M, int E, FirstArgs<T> a, int nrhs, hipStream_t st, bool o
   a.LS = tl.LS;
   dim3 grid((unsigned)(a.ntiles * nrhs));
   const int threads = a.W * (M / E);
-  if (odd) {
-    if (a.mode == PM_CG) throw Error(2, "first pass: odd extension with a CG prologue");
-    FL_DISPATCH(M, E, FL_LAUNCH((k_first<T, M, E, true>), grid, dim3(threads), tl.bytes, st, a));
-  } else {
-    FL_DISPATCH(M, E, FL_LAUNCH((k_first<T, M, E, false>), grid, dim3(threads), tl.bytes, st, a));
-  }
+  FL_DISPATCH(M, E, FL_LAUNCH((k_first<T, M, E>), grid, dim3(threads), tl.bytes, st, a));
   check_launch("first pass");
 }
 
 template <typename T>
-void launch_last(int M, int E, LastArgs<T> a, int nrhs, hipStream_t st, bool odd = false) {
+void launch_last(int M, int E, LastArgs<T> a, int nrhs, hipStream_t st) {
   if (!pow2(a.W) || a.n_out > M / 2) throw Error(2, "last pass: bad tile width or rows");
   a.ntiles = pair_tiles(a.C, a.W);
   if (a.mode != PM_PLAIN && a.ntiles > a.max_blocks)
@@ -748,17 +902,12 @@ void launch_last(int M, int E, LastArgs<T> a, int nrhs, hipStream_t st, bool odd
   a.LS = tl.LS;
   dim3 grid((unsigned)(a.ntiles * nrhs));
   const int threads = a.W * (M / E);
-  if (odd) {
-    FL_DISPATCH(M, E, FL_LAUNCH((k_last<T, M, E, true>), grid, dim3(threads), tl.bytes, st, a));
-  } else {
-    FL_DISPATCH(M, E, FL_LAUNCH((k_last<T, M, E, false>), grid, dim3(threads), tl.bytes, st, a));
-  }
+  FL_DISPATCH(M, E, FL_LAUNCH((k_last<T, M, E>), grid, dim3(threads), tl.bytes, st, a));
   check_launch("last pass");
 }
 
 template <typename T>
-void launch_c2c(int M, int E, int dir, C2CArgs<T> a, long outer, hipStream_t st,
-                bool odd = false) {
+void launch_c2c(int M, int E, int dir, C2CArgs<T> a, long outer, hipStream_t st) {
   if (!pow2(a.W)) throw Error(2, "c2c pass: bad tile width");
   a.ntiles = (a.C + a.W - 1) / a.W;
   a.lw = ilog2i(a.W);
@@ -769,21 +918,13 @@ void launch_c2c(int M, int E, int dir, C2CArgs<T> a, long outer, hipStream_t st,
   const int threads = a.W * (M / E);
   const size_t sh = tl.bytes;
   if (dir < 0 && a.n_in <= M / 2 && a.n_out == M) {
-    if (odd) {
-      FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, -1, 1, true>), grid, dim3(threads), sh, st, a));
-    } else {
-      FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, -1, 1, false>), grid, dim3(threads), sh, st, a));
-    }
+    FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, -1, 1>), grid, dim3(threads), sh, st, a));
   } else if (dir > 0 && a.n_in == M && a.n_out <= M / 2) {
-    if (odd) {
-      FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, 1, 2, true>), grid, dim3(threads), sh, st, a));
-    } else {
-      FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, 1, 2, false>), grid, dim3(threads), sh, st, a));
-    }
-  } else if (!odd && dir < 0 && a.n_in == M && a.n_out == M) {
-    FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, -1, 0, false>), grid, dim3(threads), sh, st, a));
-  } else if (!odd && dir > 0 && a.n_in == M && a.n_out == M) {
-    FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, 1, 0, false>), grid, dim3(threads), sh, st, a));
+    FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, 1, 2>), grid, dim3(threads), sh, st, a));
+  } else if (dir < 0 && a.n_in == M && a.n_out == M) {
+    FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, -1, 0>), grid, dim3(threads), sh, st, a));
+  } else if (dir > 0 && a.n_in == M && a.n_out == M) {
+    FL_DISPATCH(M, E, FL_LAUNCH((k_c2c<T, M, E, 1, 0>), grid, dim3(threads), sh, st, a));
   } else {
     throw Error(2, "c2c pass: unsupported row ranges");
   }
@@ -791,18 +932,14 @@ void launch_c2c(int M, int E, int dir, C2CArgs<T> a, long outer, hipStream_t st,
 }
 
 template <typename T>
-void launch_mid(int M, int E, const MidArgs<T>& a, int nrhs, hipStream_t st, bool odd = false) {
+void launch_mid(int M, int E, const MidArgs<T>& a, int nrhs, hipStream_t st) {
   if (a.n_in > M / 2 || a.n_out > M / 2) throw Error(2, "middle pass: rows beyond M/2");
   MidArgs<T> b = a;
   b.nrhs = nrhs;
   dim3 grid((unsigned)(((a.rows + a.LPB - 1) / a.LPB) * nrhs));
   const int threads = a.LPB * (M / E);
   const size_t sh = line_lds_bytes<T>(M, E) * a.LPB;
-  if (odd) {
-    FL_DISPATCH(M, E, FL_LAUNCH((k_mid<T, M, E, true>), grid, dim3(threads), sh, st, b));
-  } else {
-    FL_DISPATCH(M, E, FL_LAUNCH((k_mid<T, M, E, false>), grid, dim3(threads), sh, st, b));
-  }
+  FL_DISPATCH(M, E, FL_LAUNCH((k_mid<T, M, E>), grid, dim3(threads), sh, st, b));
   check_launch("middle pass");
 }
 
@@ -820,6 +957,33 @@ void launch_rows(int M, int E, int dir, cx<T>* data, long rows, int LPB, const c
                                 LPB, tw));
   }
   check_launch("row transform");
+}
+
+template <typename T>
+void launch_sine_cols(int M, int E, SineArgs<T> a, long outer, hipStream_t st) {
+  if (!pow2(a.W) || a.n != M / 2 - 1) throw Error(2, "sine pass: bad tile width or rows");
+  a.ntiles = pair_tiles(a.C, a.W);
+  if (a.dot && (a.ntiles > a.max_blocks || a.outer_per_rhs != 1))
+    throw Error(2, "sine pass: bad reduction layout");
+  a.lw = ilog2i(a.W);
+  const TileLds tl = tile_lds(M, E, a.W, sizeof(T));
+  a.PO = tl.PO;
+  a.LS = tl.LS;
+  dim3 grid((unsigned)(a.ntiles * outer));
+  const int threads = a.W * (M / E);
+  FL_DISPATCH(M, E, FL_LAUNCH((k_sine_cols<T, M, E>), grid, dim3(threads), tl.bytes, st, a));
+  check_launch("sine pass");
+}
+
+template <typename T>
+void launch_sine_mid(int M, int E, const SineMidArgs<T>& a, hipStream_t st) {
+  if (a.n != M / 2 - 1 || a.LPB < 1) throw Error(2, "sine middle pass: bad rows");
+  const long pairs = (a.rows + 1) / 2;
+  dim3 grid((unsigned)(((pairs + a.LPB - 1) / a.LPB) * a.nrhs));
+  const int threads = a.LPB * (M / E);
+  const size_t sh = line_lds_bytes<T>(M, E) * a.LPB;
+  FL_DISPATCH(M, E, FL_LAUNCH((k_sine_mid<T, M, E>), grid, dim3(threads), sh, st, a));
+  check_launch("sine middle pass");
 }
 
 template <typename T>

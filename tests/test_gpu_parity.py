@@ -347,7 +347,8 @@ def test_fp64_pcg_follows_oracle_pcg(d, alpha, p, N):
 
 @pytest.mark.parametrize("d,N,p,fp32", [(1, 64, 1, False), (1, 1024, 1, False), (2, 32, 2, False),
                                         (2, 32, 2, True), (2, 16, 0, False), (3, 8, 1, False),
-                                        (3, 16, 2, True)])
+                                        (3, 16, 2, True), (2, 256, 1, False), (3, 32, 1, False),
+                                        (2, 4, 1, False)])
 def test_tau_precond_apply_parity(d, N, p, fp32):
     """fl_apply_precond with the tau preconditioner (odd-extended passes)
     against the oracle's dense sine-transform form."""
@@ -399,3 +400,22 @@ def test_tau_cuts_iterations_at_high_alpha():
         op.set_preconditioner(kind)
         its[kind] = op.solve(f, tol=1e-10)[1][0]["iters"]
     assert its[2] * 3 < its[1], its
+
+
+@pytest.mark.parametrize("d,N,npass", [(1, 64, 1), (2, 32, 3), (3, 16, 5)])
+@pytest.mark.parametrize("kind", [1, 2])
+def test_profile_precond_runs_the_preconditioner(d, N, npass, kind):
+    """fl_profile_precond times the preconditioner's own kernels (one per
+    sine or transform pass) and leaves y = P u, bit for bit as
+    fl_apply_precond; with kind 0 it is an error."""
+    import paper_2103_03658_amd as fl
+    op = make_op(d, 1.1, 1, N)
+    op.set_preconditioner(kind)
+    u = torch.from_numpy(inputs.uniform_rhs(d, N, 2, seed=8)).cuda()
+    y = torch.empty_like(u)
+    ms = op.profile_precond(u, out=y, reps=2)
+    assert len(ms) == npass and all(m > 0 for m in ms)
+    assert torch.equal(y, op.apply_precond(u))
+    op.set_preconditioner(0)
+    with pytest.raises(fl.FlError):
+        op.profile_precond(u, out=y, reps=1)
