@@ -37,11 +37,14 @@ VALU_PEAK_TFLOPS = 78.6
 # (kernel, precision, nrhs); valid only for the kernel sources they were
 # measured on (SHA-256 prefix of the transform-pass sources).
 TRAFFIC = {
-    ("axis0_fwd_r2c", "f64", 17): 109772645,
-    ("last_axis_fwd_symbol_inv", "f64", 17): 145085169,
-    ("axis0_inv_c2r", "f64", 17): 109423628,
+    ("axis0_fwd_r2c", "f64", 17): 108969572,
+    ("last_axis_fwd_symbol_inv", "f64", 17): 145081316,
+    ("axis0_inv_c2r", "f64", 17): 108995083,
+    ("tau_axis0_sine", "f64", 17): 72760979,
+    ("tau_last_axis_sine_mult_sine", "f64", 17): 73578463,
+    ("tau_axis0_sine_back", "f64", 17): 72760979,
 }
-TRAFFIC_SRC = "c87ceb5eca38b57a"
+TRAFFIC_SRC = "67d9d18c5b2c3bcc"
 
 
 def pass_sources_hash():
@@ -350,11 +353,15 @@ def main():
         t_tune = time.perf_counter()
         for fp32 in (True, False):
             best, _ = _tune.tune(ops[1.5], nrhs, fp32, use_cache=args.tune_cache)
+            bestp = ops[1.5].get_schedule(fp32, precond=True)
             for a in alphas:
                 ops[a].set_schedule(fp32, **best)
+                ops[a].set_schedule(fp32, precond=True, **bestp)
         sched["tune_s"] = time.perf_counter() - t_tune
     sched["f32"] = ops[1.5].get_schedule(True)
     sched["f64"] = ops[1.5].get_schedule(False)
+    sched["precond_f32"] = ops[1.5].get_schedule(True, precond=True)
+    sched["precond_f64"] = ops[1.5].get_schedule(False, precond=True)
 
     if args.roofline_only:
         if args.calib_copy_mib > 0:

@@ -193,13 +193,25 @@ fl_status fl_set_refinement(fl_op A, double delta, double inner_tol, int max_out
  * Launch schedule of the transform passes (elements per thread E and lines
  * per block) for FP64 (fp32 = 0) or FP32 transforms.  E in {8, 16, 32},
  * E <= M; lines per block >= 1 with (lines * M / E) <= 512 threads and
- * lines * 2 (M + M/E) * sizeof(real) <= 160 KiB of LDS.  Values <= 0 keep
+ * lines * 2 (M + M/E) * sizeof(real) <= 160 KiB of LDS (the contiguous
+ * middle pass uses half of that).  Values <= 0 keep
  * the current setting; FL_E_INVAL leaves it unchanged.  Used by the
  * schedule tuner; results do not depend on the schedule beyond rounding.
  */
 fl_status fl_set_schedule(fl_op A, int fp32, int e_first, int e_mid, int e_c2c, int w_first,
                           int w_c2c, int lpb_mid);
 fl_status fl_get_schedule(fl_op A, int fp32, int *sched6);
+
+/*
+ * The same for the preconditioner's passes (fl_apply_precond and the
+ * preconditioned solves), which have a schedule of their own: the tau
+ * preconditioner's sine passes move half the bytes of the product's
+ * complex passes and prefer other shapes.  Starts equal to the product's
+ * default schedule.  Same ranges and errors as fl_set_schedule.
+ */
+fl_status fl_set_precond_schedule(fl_op A, int fp32, int e_first, int e_mid, int e_c2c,
+                                  int w_first, int w_c2c, int lpb_mid);
+fl_status fl_get_precond_schedule(fl_op A, int fp32, int *sched6);
 
 /*
  * fl_profile_apply -- measurement hook: run fl_apply's kernel sequence once
@@ -234,7 +246,8 @@ fl_status fl_profile_precond(fl_op A, const void *u, void *y, int nrhs, int fp32
  *   kind 2 (default): P = tau(A)^{-1}, the inverse of the natural tau
  *     approximation of the multilevel Toeplitz matrix (A minus its Hankel
  *     part on every level), diagonalised by the sine transform of each axis
- *     and applied with the same transform passes on odd-extended lines;
+ *     and applied by real sine passes (DST-I of every axis through the
+ *     length-M transform of odd-extended line pairs);
  *   kind 1: P = R C^{-1} R^T, the restriction to the n^d interior of the
  *     inverse of the embedding circulant C (symbol 1 / max(lambda-hat,
  *     1e-12 max lambda-hat));

@@ -51,6 +51,7 @@ class Operator:
         self.alpha, self.degree, self.kernel, self.lam = float(alpha), int(degree), kernel, lam
         self.gamma = float(gamma)
         self.nd = self.n ** self.d
+        self.precond_kind = 2
 
     # -- host copies (test hooks) ------------------------------------------
     def _host(self, fn, count):
@@ -167,14 +168,18 @@ class Operator:
         check(self._lib.fl_set_refinement(self._h, float(delta), float(inner_tol),
                                           int(max_outer)))
 
-    def set_schedule(self, fp32, e_first=0, e_mid=0, e_c2c=0, w_first=0, w_c2c=0, lpb_mid=0):
-        check(self._lib.fl_set_schedule(self._h, int(bool(fp32)), e_first, e_mid, e_c2c,
-                                        w_first, w_c2c, lpb_mid))
+    def set_schedule(self, fp32, e_first=0, e_mid=0, e_c2c=0, w_first=0, w_c2c=0, lpb_mid=0,
+                     precond=False):
+        """Launch schedule of the product's passes, or with precond=True of
+        the preconditioner's passes (0 keeps a value)."""
+        fn = self._lib.fl_set_precond_schedule if precond else self._lib.fl_set_schedule
+        check(fn(self._h, int(bool(fp32)), e_first, e_mid, e_c2c, w_first, w_c2c, lpb_mid))
 
     def set_preconditioner(self, kind):
         """2: tau preconditioner (default), 1: restricted inverse of the
         embedding circulant, 0: plain CG."""
         check(self._lib.fl_set_preconditioner(self._h, int(kind)))
+        self.precond_kind = int(kind)
 
     def apply_precond(self, u, out=None, stream=None):
         """y = P u with the selected preconditioner (2: tau inverse by sine
@@ -192,9 +197,10 @@ class Operator:
     def set_graphs(self, enable):
         check(self._lib.fl_set_graphs(self._h, int(bool(enable))))
 
-    def get_schedule(self, fp32):
+    def get_schedule(self, fp32, precond=False):
         s = (ctypes.c_int * 6)()
-        check(self._lib.fl_get_schedule(self._h, int(bool(fp32)), s))
+        fn = self._lib.fl_get_precond_schedule if precond else self._lib.fl_get_schedule
+        check(fn(self._h, int(bool(fp32)), s))
         return dict(zip(["e_first", "e_mid", "e_c2c", "w_first", "w_c2c", "lpb_mid"], list(s)))
 
     def close(self):

@@ -58,6 +58,8 @@ _SIGS = {
     "fl_set_refinement": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double, ctypes.c_int]),
     "fl_set_schedule": (ctypes.c_int, [_P, ctypes.c_int] + [ctypes.c_int] * 6),
     "fl_get_schedule": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
+    "fl_set_precond_schedule": (ctypes.c_int, [_P, ctypes.c_int] + [ctypes.c_int] * 6),
+    "fl_get_precond_schedule": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
     "fl_profile_apply": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                         _P, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                                         ctypes.POINTER(ctypes.c_int)]),

@@ -135,7 +135,8 @@ struct fl_op_s {
   int precond = 2;            // 0 plain CG, 1 circulant, 2 tau preconditioner
   const void* tw64 = nullptr;
   const void* tw32 = nullptr;
-  fl::Schedule sc64{}, sc32{};
+  fl::Schedule sc64{}, sc32{};  // transform passes of the product A u
+  fl::Schedule sp64{}, sp32{};  // transform passes of the preconditioner
   double delta = 1e-3;      // reliable-update trigger (mixed = 1)
   double inner_tol = 1e-4;  // inner solve tolerance (mixed = 2)
   int max_outer = 40;
@@ -237,6 +238,12 @@ const float* pc_symbol<float>(fl_op A) {
   return A->linv32;
 }
 
+// schedule of the preconditioner's passes
+template <typename T>
+const fl::Schedule& pc_sched(fl_op A) {
+  return sizeof(T) == 4 ? A->sp32 : A->sp64;
+}
+
 void check_schedule(const fl::Geometry& g, const fl::Schedule& s, bool fp32) {
   if (!fl::schedule_ok(g, s, fp32)) throw Error(FL_E_INVAL, "schedule out of range");
 }
@@ -314,6 +321,8 @@ fl_status fl_weights_gamma(int d, double alpha, int degree, double h, int kernel
       A->tw32 = fl::twiddles(M, true, st);
       A->sc64 = fl::default_schedule(A->g, false);
       A->sc32 = fl::default_schedule(A->g, true);
+      A->sp64 = A->sc64;
+      A->sp32 = A->sc32;
       FL_HIP(hipEventCreateWithFlags(&A->done, hipEventDisableTiming));
       FL_HIP(hipStreamSynchronize(st));
     } catch (...) {
@@ -410,11 +419,12 @@ fl_status fl_embedding(fl_op A, double* host_out, size_t count) {
   });
 }
 
-fl_status fl_set_schedule(fl_op A, int fp32, int e_first, int e_mid, int e_c2c, int w_first,
-                          int w_c2c, int lpb_mid) {
+static fl_status set_sched(fl_op A, bool pc, int fp32, int e_first, int e_mid, int e_c2c,
+                           int w_first, int w_c2c, int lpb_mid) {
   return guarded([&]() -> fl_status {
     if (!A) return fail(FL_E_INVAL, "null handle");
-    fl::Schedule s = fp32 ? A->sc32 : A->sc64;
+    fl::Schedule& dst = pc ? (fp32 ? A->sp32 : A->sp64) : (fp32 ? A->sc32 : A->sc64);
+    fl::Schedule s = dst;
     if (e_first > 0) s.E_first = e_first;
     if (e_mid > 0) s.E_mid = e_mid;
     if (e_c2c > 0) s.E_c2c = e_c2c;
@@ -422,9 +432,19 @@ fl_status fl_set_schedule(fl_op A, int fp32, int e_first, int e_mid, int e_c2c, 
     if (w_c2c > 0) s.W_c2c = w_c2c;
     if (lpb_mid > 0) s.LPB_mid = lpb_mid;
     check_schedule(A->g, s, fp32 != 0);
-    (fp32 ? A->sc32 : A->sc64) = s;
+    dst = s;
     return FL_OK;
   });
+}
+
+fl_status fl_set_schedule(fl_op A, int fp32, int e_first, int e_mid, int e_c2c, int w_first,
+                          int w_c2c, int lpb_mid) {
+  return set_sched(A, false, fp32, e_first, e_mid, e_c2c, w_first, w_c2c, lpb_mid);
+}
+
+fl_status fl_set_precond_schedule(fl_op A, int fp32, int e_first, int e_mid, int e_c2c,
+                                  int w_first, int w_c2c, int lpb_mid) {
+  return set_sched(A, true, fp32, e_first, e_mid, e_c2c, w_first, w_c2c, lpb_mid);
 }
 
 fl_status fl_set_preconditioner(fl_op A, int kind) {
@@ -447,11 +467,11 @@ fl_status fl_apply_precond(fl_op A, const void* u, void* y, int nrhs, int fp32, 
     void* ws = A->ws.get(fl::apply_workspace_bytes(A->g, nrhs, fp32 != 0));
     const bool odd = A->precond == 2;
     if (fp32)
-      fl::apply_passes<float>(A->g, A->sc32, pc_symbol<float>(A), A->tw32, (const float*)u,
+      fl::apply_passes<float>(A->g, A->sp32, pc_symbol<float>(A), A->tw32, (const float*)u,
                               (float*)y, nrhs, ws, st, fl::PM_PLAIN, nullptr, nullptr, nullptr,
                               nullptr, nullptr, nullptr, -1, odd);
     else
-      fl::apply_passes<double>(A->g, A->sc64, pc_symbol<double>(A), A->tw64, (const double*)u,
+      fl::apply_passes<double>(A->g, A->sp64, pc_symbol<double>(A), A->tw64, (const double*)u,
                                (double*)y, nrhs, ws, st, fl::PM_PLAIN, nullptr, nullptr, nullptr,
                                nullptr, nullptr, nullptr, -1, odd);
     A->end(st);
@@ -465,9 +485,9 @@ fl_status fl_set_graphs(fl_op A, int enable) {
   return FL_OK;
 }
 
-fl_status fl_get_schedule(fl_op A, int fp32, int* s6) {
+static fl_status get_sched(fl_op A, bool pc, int fp32, int* s6) {
   if (!A || !s6) return fail(FL_E_INVAL, "null argument");
-  const fl::Schedule& s = fp32 ? A->sc32 : A->sc64;
+  const fl::Schedule& s = pc ? (fp32 ? A->sp32 : A->sp64) : (fp32 ? A->sc32 : A->sc64);
   s6[0] = s.E_first;
   s6[1] = s.E_mid;
   s6[2] = s.E_c2c;
@@ -475,6 +495,12 @@ fl_status fl_get_schedule(fl_op A, int fp32, int* s6) {
   s6[4] = s.W_c2c;
   s6[5] = s.LPB_mid;
   return FL_OK;
+}
+
+fl_status fl_get_schedule(fl_op A, int fp32, int* s6) { return get_sched(A, false, fp32, s6); }
+
+fl_status fl_get_precond_schedule(fl_op A, int fp32, int* s6) {
+  return get_sched(A, true, fp32, s6);
 }
 
 fl_status fl_set_refinement(fl_op A, double delta, double inner_tol, int max_outer) {
@@ -529,11 +555,11 @@ static fl_status profile_passes(fl_op A, const void* u, void* y, int nrhs, int f
     const bool odd = pc && A->precond == 2;
     auto run = [&](int only) {
       if (fp32)
-        fl::apply_passes<float>(A->g, A->sc32, pc ? pc_symbol<float>(A) : A->lam32, A->tw32,
+        fl::apply_passes<float>(A->g, pc ? A->sp32 : A->sc32, pc ? pc_symbol<float>(A) : A->lam32, A->tw32,
                                 (const float*)u, (float*)y, nrhs, ws, st, fl::PM_PLAIN, nullptr,
                                 nullptr, nullptr, nullptr, nullptr, nullptr, only, odd);
       else
-        fl::apply_passes<double>(A->g, A->sc64, pc ? pc_symbol<double>(A) : A->lam64, A->tw64,
+        fl::apply_passes<double>(A->g, pc ? A->sp64 : A->sc64, pc ? pc_symbol<double>(A) : A->lam64, A->tw64,
                                  (const double*)u, (double*)y, nrhs, ws, st, fl::PM_PLAIN,
                                  nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, only, odd);
     };
@@ -581,12 +607,13 @@ namespace {
 
 // Per-call view of the CG state: block counts, iteration cap, tolerance.
 fl::CgScalars cg_view(const fl::CgScalars& base, const fl::Geometry& g, const fl::Schedule& sc,
-                      int nrhs, int maxiter, double tol, int precond) {
+                      const fl::Schedule& scp, int nrhs, int maxiter, double tol, int precond) {
   fl::CgScalars c = base;
   c.nb_a = fl::last_pass_blocks(g, sc);
   c.nb_c = fl::vec_blocks(g.nd, nrhs);
-  c.nb_b = precond ? c.nb_a : c.nb_c;   // r.z from the preconditioner's last pass
-  if (c.nb_a > c.max_blocks || c.nb_c > c.max_blocks)
+  // r.z from the preconditioner's last pass (its own schedule)
+  c.nb_b = precond ? fl::last_pass_blocks(g, scp) : c.nb_c;
+  if (c.nb_a > c.max_blocks || c.nb_b > c.max_blocks || c.nb_c > c.max_blocks)
     throw Error(FL_E_UNSUPPORTED, "too many blocks for the reduction buffers");
   c.maxiter = maxiter;
   c.precond = precond;
@@ -732,11 +759,10 @@ inline std::vector<double> sched_key(const fl::Schedule& s) {
 // circulant (kind 1, zero-padded passes) or the inverse of the tau
 // approximation (kind 2, odd-extended passes); `linv` is its multiplier.
 template <typename T>
-void precond_apply(fl_op A, const fl::Schedule& sc, const T* linv, const void* tw, const T* r,
-                   T* z, int nrhs, void* ws, const fl::CgScalars& cg, const int* active,
-                   hipStream_t st) {
-  fl::apply_passes<T>(A->g, sc, linv, tw, r, z, nrhs, ws, st, fl::PM_DOT, nullptr, nullptr,
-                      nullptr, &cg, active, nullptr, -1, A->precond == 2);
+void precond_apply(fl_op A, const T* linv, const void* tw, const T* r, T* z, int nrhs, void* ws,
+                   const fl::CgScalars& cg, const int* active, hipStream_t st) {
+  fl::apply_passes<T>(A->g, pc_sched<T>(A), linv, tw, r, z, nrhs, ws, st, fl::PM_DOT, nullptr,
+                      nullptr, nullptr, &cg, active, nullptr, -1, A->precond == 2);
 }
 
 // CG start: x = 0, r = rhs, p = 0; preconditioned: z = P r.
@@ -746,7 +772,7 @@ void cg_start(fl_op A, const fl::Schedule& sc, const T* linv, const void* tw, co
               const int* outer_active, void* ws, hipStream_t st) {
   fl::fill_int(cg.n_active, 0, 1, st);
   fl::cg_init<T>(A->g, rhs, x, r, p, nrhs, cg, outer_active, st);
-  if (cg.precond) precond_apply<T>(A, sc, linv, tw, r, z, nrhs, ws, cg, cg.active, st);
+  if (cg.precond) precond_apply<T>(A, linv, tw, r, z, nrhs, ws, cg, cg.active, st);
 }
 
 // One CG (or preconditioned CG) iteration for all active right-hand sides.
@@ -757,7 +783,7 @@ void cg_iteration(fl_op A, const fl::Schedule& sc, const T* lam, const T* linv, 
   fl::apply_passes<T>(A->g, sc, lam, tw, nullptr, q, nrhs, ws, st, fl::PM_CG,
                       cg.precond ? z : r, p, nullptr, &cg, cg.active);
   fl::cg_update<T>(A->g, x, r, p, q, nrhs, cg, st);
-  if (cg.precond) precond_apply<T>(A, sc, linv, tw, r, z, nrhs, ws, cg, cg.active, st);
+  if (cg.precond) precond_apply<T>(A, linv, tw, r, z, nrhs, ws, cg, cg.active, st);
 }
 
 // CG from x0 = 0 on A x = rhs until no right-hand side is active.  The
@@ -873,7 +899,7 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
     sum_squares(A, f, nrhs, co, f2, st);
     const int pc = A->precond;
     if (!mixed) {
-      const fl::CgScalars cg = cg_view(A->cg.s, A->g, A->sc64, nrhs, maxiter, tol, pc);
+      const fl::CgScalars cg = cg_view(A->cg.s, A->g, A->sc64, A->sp64, nrhs, maxiter, tol, pc);
       char* vb = (char*)A->vecs.get(5 * a8);
       double* r = (double*)vb;
       double* p = (double*)(vb + a8);
@@ -885,6 +911,7 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
       std::vector<double> key = make_key(0, nrhs, chunk, maxiter, tol, pc);
       for (double v : {pkey(ws), pkey(vb), pkey(A->cg.mem.p), pkey(A->lam64)}) key.push_back(v);
       for (double v : sched_key(A->sc64)) key.push_back(v);
+      for (double v : sched_key(A->sp64)) key.push_back(v);
       predictive_loop(A, key, maxiter + 2, cg, nrhs, st, [&]() {
         cg_iteration<double>(A, A->sc64, A->lam64, pc_symbol<double>(A), A->tw64, x, r, p, q, z, nrhs, cg,
                              ws, st);
@@ -912,7 +939,7 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
       // tolerance) folds xlo into the FP64 iterate, recomputes r = f - A u
       // in FP64, stops if ||r|| <= tol ||f||, and otherwise continues from
       // r (rounded to FP32) with the same search direction.
-      fl::CgScalars cg = cg_view(A->cg.s, A->g, A->sc32, nrhs, maxiter, tol, pc);
+      fl::CgScalars cg = cg_view(A->cg.s, A->g, A->sc32, A->sp32, nrhs, maxiter, tol, pc);
       cg.tol2 = 0.0;  // the FP32 recursion never stops on its own residual
       const double delta2 = A->delta * A->delta;
       const int nb64 = fl::last_pass_blocks(A->g, A->sc64);
@@ -939,6 +966,7 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
                        pkey(A->outer_flags.p), pkey(A->lam32)})
         key.push_back(v);
       for (double v : sched_key(A->sc32)) key.push_back(v);
+      for (double v : sched_key(A->sp32)) key.push_back(v);
       for (double v : sched_key(A->sc64)) key.push_back(v);
       chunk_loop(A, A->graph[1], key, (maxiter + 2) / chunk + 2, cg, st, [&]() {
         for (int i = 0; i < chunk; ++i)
@@ -950,7 +978,7 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
                                  fl::PM_RESID, nullptr, nullptr, fc, &co, trig);
         fl::reliable_replace(A->g, r64, r32, nrhs, cg, co.part_a, nb64, co.max_blocks, rr_last,
                              f2, tol * tol, trig, nupd, st);
-        if (pc) precond_apply<float>(A, A->sc32, pc_symbol<float>(A), A->tw32, r32, z32, nrhs, ws, cg, trig,
+        if (pc) precond_apply<float>(A, pc_symbol<float>(A), A->tw32, r32, z32, nrhs, ws, cg, trig,
                                      st);
       });
       // fold what is left (RHS stopped by maxiter) and report true residuals
@@ -971,7 +999,7 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
       }
     } else {
       // FP64 residual and iterate; FP32 CG on A delta = r / ||r|| (inner_tol)
-      const fl::CgScalars cg = cg_view(A->cg.s, A->g, A->sc32, nrhs, maxiter, A->inner_tol, pc);
+      const fl::CgScalars cg = cg_view(A->cg.s, A->g, A->sc32, A->sp32, nrhs, maxiter, A->inner_tol, pc);
       char* vb = (char*)A->vecs.get(a8 + 6 * a4);
       double* r64 = (double*)vb;
       float* rhs32 = (float*)(vb + a8);

@@ -234,13 +234,15 @@ struct Plan {
 };
 
 // One Stockham stage s >= 1: exchange the previous stage's outputs through
-// LDS, then twiddle and DFT.  lre/lim: this line's LDS planes.
+// LDS, then twiddle and DFT.  lre/lim: this line's LDS planes; ONE: a single
+// plane (lre) carries the real and then the imaginary parts (half the LDS
+// of a line, so more lines fit a CU, for two more barriers per stage).
 // Twiddles: of the R - 1 factors w^j (w = e^{-2 pi i k / (Ls R)}) only
 // w^(2^b), b < log2 R, are read from the table (before the exchange, so that
 // the reads overlap it); the others are products of at most log2 R - 1 of
 // those, by the binary digits of j.  Reading all R - 1 per stage held more
 // registers than the transform itself and left each stage waiting on them.
-template <typename T, int M, int E, int DIR, int s>
+template <typename T, int M, int E, int DIR, int s, bool ONE>
 __device__ __forceinline__ void stockham_stage(cx<T> (&v)[E], T* lre, T* lim, int t,
                                                const cx<T>* __restrict__ tw) {
   using P = Plan<M, E>;
@@ -258,28 +260,46 @@ __device__ __forceinline__ void stockham_stage(cx<T> (&v)[E], T* lre, T* lim, in
 #pragma unroll
     for (int bit = 0; bit < LR; ++bit) pw[q][bit] = tw[i1 << bit];
   }
-  __syncthreads();
 #pragma unroll
-  for (int q = 0; q < E / Rp; ++q) {
-    const int b = t + q * TPL;
-    const int k = b & (Lp - 1);
+  for (int part = 0; part < (ONE ? 2 : 1); ++part) {
+    __syncthreads();
 #pragma unroll
-    for (int r = 0; r < Rp; ++r) {
-      const int o = P::pad((b - k) * Rp + k + r * Lp);
-      lre[o] = v[q * Rp + r].x;
-      lim[o] = v[q * Rp + r].y;
+    for (int q = 0; q < E / Rp; ++q) {
+      const int b = t + q * TPL;
+      const int k = b & (Lp - 1);
+#pragma unroll
+      for (int r = 0; r < Rp; ++r) {
+        const int o = P::pad((b - k) * Rp + k + r * Lp);
+        if (!ONE || part == 0) lre[o] = v[q * Rp + r].x;
+        if (!ONE) lim[o] = v[q * Rp + r].y;
+        if (ONE && part == 1) lre[o] = v[q * Rp + r].y;
+      }
+    }
+    __syncthreads();
+    T nx[E], ny[E];
+#pragma unroll
+    for (int q = 0; q < E / R; ++q) {
+      const int b = t + q * TPL;
+#pragma unroll
+      for (int j = 0; j < R; ++j) {
+        const int i = P::pad(b + j * (M / R));
+        nx[q * R + j] = lre[i];
+        if (!ONE) ny[q * R + j] = lim[i];
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (!ONE) {
+        v[e] = {nx[e], ny[e]};
+      } else if (part == 0) {
+        v[e].x = nx[e];
+      } else {
+        v[e].y = nx[e];
+      }
     }
   }
-  __syncthreads();
 #pragma unroll
   for (int q = 0; q < E / R; ++q) {
-    const int b = t + q * TPL;
-#pragma unroll
-    for (int j = 0; j < R; ++j) {
-      const int i = P::pad(b + j * (M / R));
-      v[q * R + j].x = lre[i];
-      v[q * R + j].y = lim[i];
-    }
 #pragma unroll
     for (int j = 1; j < R; ++j) {
       cx<T> w = {1, 0};
@@ -298,12 +318,12 @@ __device__ __forceinline__ void stockham_stage(cx<T> (&v)[E], T* lre, T* lim, in
   }
 }
 
-template <typename T, int M, int E, int DIR, int s>
+template <typename T, int M, int E, int DIR, int s, bool ONE>
 __device__ __forceinline__ void stockham_from(cx<T> (&v)[E], T* lre, T* lim, int t,
                                               const cx<T>* __restrict__ tw) {
   if constexpr (s < Plan<M, E>::S) {
-    stockham_stage<T, M, E, DIR, s>(v, lre, lim, t, tw);
-    stockham_from<T, M, E, DIR, s + 1>(v, lre, lim, t, tw);
+    stockham_stage<T, M, E, DIR, s, ONE>(v, lre, lim, t, tw);
+    stockham_from<T, M, E, DIR, s + 1, ONE>(v, lre, lim, t, tw);
   }
 }
 
@@ -314,7 +334,15 @@ template <typename T, int M, int E, int DIR>
 __device__ __forceinline__ void fft_line(cx<T> (&v)[E], T* lre, T* lim, int t,
                                          const cx<T>* __restrict__ tw) {
   dft<Plan<M, E>::radix(0), DIR>(v);
-  stockham_from<T, M, E, DIR, 1>(v, lre, lim, t, tw);
+  stockham_from<T, M, E, DIR, 1, false>(v, lre, lim, t, tw);
+}
+
+// The same with one LDS plane of Plan::LDSN elements for the exchanges.
+template <typename T, int M, int E, int DIR>
+__device__ __forceinline__ void fft_line_1p(cx<T> (&v)[E], T* l, int t,
+                                            const cx<T>* __restrict__ tw) {
+  dft<Plan<M, E>::radix(0), DIR>(v);
+  stockham_from<T, M, E, DIR, 1, true>(v, l, nullptr, t, tw);
 }
 
 // Reorder slots so that slot j holds element t + TPL*j (compile-time permutation).

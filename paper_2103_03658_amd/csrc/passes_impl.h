@@ -459,8 +459,10 @@ struct MidArgs {
   const cx<T>* tw;
 };
 
+// FP64 radix-16 lines fit 168 registers, which allows three waves per SIMD
+// (the compiler's own choice keeps two).
 template <typename T, int M, int E>
-__global__ void __launch_bounds__(512) k_mid(MidArgs<T> a) {
+__global__ void __launch_bounds__(512, (E == 16 && sizeof(T) == 8) ? 3 : 1) k_mid(MidArgs<T> a) {
   using P = Plan<M, E>;
   constexpr int TPL = P::TPL;
   extern __shared__ unsigned char smem_raw[];
@@ -475,8 +477,7 @@ __global__ void __launch_bounds__(512) k_mid(MidArgs<T> a) {
   const int l = threadIdx.x / TPL, t = threadIdx.x % TPL;
   const long line = rb * a.LPB + l;
   const bool h = line < a.rows;
-  T* lre = lds + (long)l * 2 * P::LDSN;
-  T* lim = lre + P::LDSN;
+  T* l1 = lds + (long)l * P::LDSN;
   cx<T>* base = a.data + (long)o * a.o_stride + (h ? line : 0) * a.row_stride;
   cx<T> v[E];
 #pragma unroll
@@ -484,7 +485,7 @@ __global__ void __launch_bounds__(512) k_mid(MidArgs<T> a) {
     const int i = t + j * TPL;   // n_in <= M/2: slots j >= E/2 are zero
     v[j] = (j < E / 2 && h && i < a.n_in) ? base[i] : cx<T>{0, 0};
   }
-  fft_line<T, M, E, -1>(v, lre, lim, t, a.tw);
+  fft_line_1p<T, M, E, -1>(v, l1, t, a.tw);
   // symbol row of this line
   long lrow = 0;
   if (h) {
@@ -503,7 +504,7 @@ __global__ void __launch_bounds__(512) k_mid(MidArgs<T> a) {
     v[sl] = cscale(v[sl], s);
   }
   to_natural<T, M, E>(v);
-  fft_line<T, M, E, +1>(v, lre, lim, t, a.tw);
+  fft_line_1p<T, M, E, +1>(v, l1, t, a.tw);
 #pragma unroll
   for (int sl = 0; sl < E; ++sl) {
     const int i = t + TPL * P::jslot(sl);   // n_out <= M/2
@@ -765,8 +766,7 @@ __global__ void __launch_bounds__(512) k_sine_mid(SineMidArgs<T> a) {
   const int l = threadIdx.x / TPL, t = threadIdx.x % TPL;
   const long la = 2 * (rb * a.LPB + l);
   const bool ha = la < a.rows, hb = la + 1 < a.rows;
-  T* lre = lds + (long)l * 2 * P::LDSN;
-  T* lim = lre + P::LDSN;
+  T* l1 = lds + (long)l * P::LDSN;
   T* pa = a.data + (long)o * a.o_stride + (ha ? la : 0) * a.n;
   T* pb = pa + a.n;   // dereferenced only if hb
   const int n = a.n;
@@ -784,7 +784,7 @@ __global__ void __launch_bounds__(512) k_sine_mid(SineMidArgs<T> a) {
     }
     v[j] = {xa, xb};
   }
-  fft_line<T, M, E, -1>(v, lre, lim, t, a.tw);
+  fft_line_1p<T, M, E, -1>(v, l1, t, a.tw);
   const T* ma = a.m + (ha ? sine_mrow(la, n, a.N1, a.d) : 0);
   const T* mb = a.m + (hb ? sine_mrow(la + 1, n, a.N1, a.d) : 0);
 #pragma unroll
@@ -796,7 +796,7 @@ __global__ void __launch_bounds__(512) k_sine_mid(SineMidArgs<T> a) {
     v[sl] = {sa * v[sl].y, -(sb * v[sl].x)};
   }
   to_natural<T, M, E>(v);
-  fft_line<T, M, E, -1>(v, lre, lim, t, a.tw);
+  fft_line_1p<T, M, E, -1>(v, l1, t, a.tw);
 #pragma unroll
   for (int sl = 0; sl < E; ++sl) {
     const int pos = t + TPL * P::jslot(sl);
@@ -842,6 +842,12 @@ __global__ void __launch_bounds__(512) k_sine_mid(SineMidArgs<T> a) {
 template <typename T>
 inline size_t line_lds_bytes(int M, int E) {
   return (size_t)2 * (M + M / E) * sizeof(T);
+}
+
+// one exchange plane per line (the contiguous passes)
+template <typename T>
+inline size_t plane_lds_bytes(int M, int E) {
+  return (size_t)(M + M / E) * sizeof(T);
 }
 
 inline void check_launch(const char* what) {
@@ -938,7 +944,7 @@ void launch_mid(int M, int E, const MidArgs<T>& a, int nrhs, hipStream_t st) {
   b.nrhs = nrhs;
   dim3 grid((unsigned)(((a.rows + a.LPB - 1) / a.LPB) * nrhs));
   const int threads = a.LPB * (M / E);
-  const size_t sh = line_lds_bytes<T>(M, E) * a.LPB;
+  const size_t sh = plane_lds_bytes<T>(M, E) * a.LPB;
   FL_DISPATCH(M, E, FL_LAUNCH((k_mid<T, M, E>), grid, dim3(threads), sh, st, b));
   check_launch("middle pass");
 }
@@ -981,7 +987,7 @@ void launch_sine_mid(int M, int E, const SineMidArgs<T>& a, hipStream_t st) {
   const long pairs = (a.rows + 1) / 2;
   dim3 grid((unsigned)(((pairs + a.LPB - 1) / a.LPB) * a.nrhs));
   const int threads = a.LPB * (M / E);
-  const size_t sh = line_lds_bytes<T>(M, E) * a.LPB;
+  const size_t sh = plane_lds_bytes<T>(M, E) * a.LPB;
   FL_DISPATCH(M, E, FL_LAUNCH((k_sine_mid<T, M, E>), grid, dim3(threads), sh, st, a));
   check_launch("sine middle pass");
 }

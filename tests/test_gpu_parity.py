@@ -358,23 +358,79 @@ def test_tau_precond_apply_parity(d, N, p, fp32):
     ut = torch.from_numpy(u.astype(np.float32) if fp32 else u).cuda()
     y = op.apply_precond(ut).double().cpu().numpy()
     G = orc_gen(d, 1.3, p, N)
+    for r in range(3):
+        v = ut[r].double().cpu().numpy()
+        ref = oracle.tau_precond_apply(G, v)
+        sc = tau_scale(G, v, N, d)
+        tol = 1e-5 if fp32 else 1e-12
+        assert np.abs(y[r] - ref).max() <= tol * sc, (r, float(np.abs(y[r] - ref).max() / sc))
+
+
+def tau_scale(G, v, N, d):
+    """Rounding of the tau product acts on the magnitudes
+    (2/N)^d |S|..(|1/lam| (|S|..|v|)); the largest of them."""
     n = N - 1
     k = np.arange(1, n + 1)
     S = np.abs(np.sin(np.pi * np.outer(k, k) / N))
     inv = 1.0 / np.abs(oracle.tau_symbol(G))
-    for r in range(3):
-        v = ut[r].double().cpu().numpy()
-        ref = oracle.tau_precond_apply(G, v)
-        # rounding acts on the magnitudes (2/N)^d |S|..(|1/lam| (|S|..|v|))
-        sc = np.abs(v)
-        for ax in range(d):
-            sc = np.moveaxis(np.tensordot(S, sc, axes=([1], [ax])), 0, ax)
-        sc = sc * inv
-        for ax in range(d):
-            sc = np.moveaxis(np.tensordot(S, sc, axes=([1], [ax])), 0, ax)
-        sc = sc.max() * (2.0 / N) ** d
-        tol = 1e-5 if fp32 else 1e-12
-        assert np.abs(y[r] - ref).max() <= tol * sc, (r, float(np.abs(y[r] - ref).max() / sc))
+    sc = np.abs(v)
+    for ax in range(d):
+        sc = np.moveaxis(np.tensordot(S, sc, axes=([1], [ax])), 0, ax)
+    sc = sc * inv
+    for ax in range(d):
+        sc = np.moveaxis(np.tensordot(S, sc, axes=([1], [ax])), 0, ax)
+    return sc.max() * (2.0 / N) ** d
+
+
+@pytest.mark.parametrize("d,N,fp32", [(2, 64, False), (2, 64, True), (3, 16, False)])
+def test_tau_every_precond_schedule(d, N, fp32):
+    """Every schedule the tuner may give the preconditioner's sine passes
+    (radix 8/16/32 stages, 1..16 column pairs or line pairs per block,
+    ragged last tiles) computes the same tau product, against the oracle."""
+    from paper_2103_03658_amd import tune
+    op = make_op(d, 1.2, 1, N)
+    u = inputs.uniform_rhs(d, N, 3, seed=47)
+    ut = torch.from_numpy(u.astype(np.float32) if fp32 else u).cuda()
+    G = orc_gen(d, 1.2, 1, N)
+    refs = [oracle.tau_precond_apply(G, ut[r].double().cpu().numpy()) for r in range(3)]
+    scs = [tau_scale(G, ut[r].double().cpu().numpy(), N, d) for r in range(3)]
+    tol = 1e-5 if fp32 else 1e-12
+    base = op.get_schedule(fp32, precond=True)
+    tried = 0
+    for E, W in tune.candidates(op.M, fp32):
+        for ek, wk in (("e_first", "w_first"), ("e_mid", "lpb_mid"), ("e_c2c", "w_c2c")):
+            s = dict(base)
+            s[ek], s[wk] = E, W
+            try:
+                op.set_schedule(fp32, precond=True, **s)
+            except Exception:
+                continue
+            y = op.apply_precond(ut).double().cpu().numpy()
+            for r in range(3):
+                assert np.abs(y[r] - refs[r]).max() <= tol * scs[r], (ek, E, wk, W)
+            tried += 1
+    assert tried >= 5
+
+
+@pytest.mark.parametrize("mixed", [0, 1])
+def test_precond_schedule_of_its_own_in_solves(mixed):
+    """Preconditioned solves whose preconditioner tiles differ from the
+    product's (so the r.z partials come in another count) agree with the
+    solve on equal schedules."""
+    N = 64
+    op = make_op(2, 1.3, 1, N)
+    f = torch.from_numpy(inputs.uniform_rhs(2, N, 3, seed=12)).cuda()
+    fp32 = bool(mixed)
+    op.set_schedule(fp32, e_first=8, w_first=4)
+    op.set_schedule(fp32, precond=True, e_first=8, w_first=4)
+    u0, i0 = op.solve(f, tol=1e-10, mixed=mixed)
+    op.set_schedule(fp32, precond=True, e_first=16, w_first=1, e_mid=8, lpb_mid=2)
+    u1, i1 = op.solve(f, tol=1e-10, mixed=mixed)
+    for a, b in zip(i0, i1):
+        assert a["converged"] == 1 and b["converged"] == 1
+        assert abs(a["iters"] - b["iters"]) <= 1
+    d = (u1 - u0).abs().max().item() / u0.abs().max().item()
+    assert d <= 1e-8, d
 
 
 @pytest.mark.parametrize("d,alpha,p,N", [(1, 1.5, 1, 256), (2, 1.0, 2, 64), (2, 1.9, 1, 32),
