@@ -161,6 +161,7 @@ struct fl_op_s {
   DBuf poll_dev;          // packed CG state for the host (device side)
   double* poll_host = nullptr;   // pinned copy
   size_t poll_cap = 0;
+  int iter_hint = 0;      // iterations of the last FP64 solve (first chunk length)
   bool use_graphs = true;
 
   // Order this call after the previous one if it ran on another stream
@@ -684,9 +685,12 @@ void chunk_loop(fl_op A, ChunkGraph& g, const std::vector<double>& key, int max_
 
 // Run CG iterations in chunks whose length is predicted from each active
 // right-hand side's observed contraction of r.r (iterations to reach its
-// threshold at the rate of the previous chunk, at most 16); the host reads
-// the state after every chunk, so no work is queued past convergence.
-// Chunks are composed of captured graphs of 16, 8, 4, 2 and 1 iterations.
+// threshold at the rate seen so far, from r_0 on, at most 16); the host
+// reads the state after every chunk, so no work is queued past convergence
+// beyond a misprediction.  The first chunk is the previous solve's
+// iteration count plus the one that detects convergence (8 on the first
+// solve).  Chunks are composed of captured graphs of 16, 8, 4, 2 and 1
+// iterations; iterations of stopped right-hand sides are masked no-ops.
 template <typename F>
 void predictive_loop(fl_op A, const std::vector<double>& key, int cap, const fl::CgScalars& cg,
                      int nrhs, hipStream_t st, F&& enqueue_one) {
@@ -702,7 +706,8 @@ void predictive_loop(fl_op A, const std::vector<double>& key, int cap, const fl:
   static const int lens[5] = {1, 2, 4, 8, 16};
   std::vector<double> rr_prev(nrhs, 0.0);
   std::vector<int> it_prev(nrhs, 0);
-  int done = 0, next = 8;
+  int done = 0, next = A->iter_hint > 0 ? std::min(A->iter_hint + 1, 16) : 8;
+  int max_it = 0;
   while (done < cap) {
     int k = std::min(next, cap - done);
     for (int b = 4; b >= 0; --b) {
@@ -720,6 +725,7 @@ void predictive_loop(fl_op A, const std::vector<double>& key, int cap, const fl:
     FL_HIP(hipMemcpyAsync(A->poll_host, dpoll, pb, hipMemcpyDeviceToHost, st));
     FL_HIP(hipStreamSynchronize(st));
     const double* h = A->poll_host;
+    for (int o = 0; o < nrhs; ++o) max_it = std::max(max_it, (int)h[1 + 4 * o + 3]);
     if (h[0] == 0.0) break;
     int need = 1;
     for (int o = 0; o < nrhs; ++o) {
@@ -727,12 +733,14 @@ void predictive_loop(fl_op A, const std::vector<double>& key, int cap, const fl:
       if (q[2] == 0.0) continue;
       const double rr = q[0], th = q[1];
       const int it = (int)q[3];
+      // before the first poll the reference is r_0: ||r_0||^2 = thresh2 / tol^2
+      if (rr_prev[o] == 0.0 && cg.tol2 > 0.0) rr_prev[o] = th / cg.tol2;
       int guess = 8;
       if (rr <= th) {
         guess = 1;
       } else if (rr_prev[o] > 0.0 && it > it_prev[o] && rr > 0.0 && th > 0.0) {
         const double rate = std::pow(rr / rr_prev[o], 1.0 / (it - it_prev[o]));
-        if (rate < 0.95) guess = (int)std::ceil(std::log(th / rr) / std::log(rate));
+        if (rate < 0.95) guess = (int)std::ceil(std::log(th / rr) / std::log(rate)) + 1;
       }
       need = std::max(need, guess);
       rr_prev[o] = rr;
@@ -741,6 +749,7 @@ void predictive_loop(fl_op A, const std::vector<double>& key, int cap, const fl:
     next = std::min(std::max(need, 1), 16);
   }
   FL_HIP(hipStreamSynchronize(st));
+  A->iter_hint = max_it;
 }
 
 template <typename... P>
