@@ -147,13 +147,12 @@ struct fl_op_s {
   hipEvent_t done = nullptr;
   hipStream_t last_stream = nullptr;
   bool used = false;
-  // solver stream (default priority), events and pinned flags for polling
+  // solver stream (default priority) and its input event
   hipStream_t solve_stream = nullptr;
   hipEvent_t ev_in = nullptr;
-  hipEvent_t ev_poll[2] = {nullptr, nullptr};
-  int* pinned = nullptr;
-  ChunkGraph graph[2];    // captured CG chunks: FP64 (0), FP32 reliable (1)
+  ChunkGraph grel;        // captured reliable-update step of mixed = 1
   ChunkGraph glen[5];     // FP64 CG chunks of 1, 2, 4, 8, 16 iterations
+  ChunkGraph glen32[5];   // FP32 CG chunks of 1, 2, 4, 8, 16 iterations (mixed = 1)
   DBuf ext_khat;          // transformed wrapped generator of the exterior term
   DBuf ext_work;          // exterior-term transform workspace
   bool ext_ready = false;
@@ -162,6 +161,7 @@ struct fl_op_s {
   double* poll_host = nullptr;   // pinned copy
   size_t poll_cap = 0;
   int iter_hint = 0;      // iterations of the last FP64 solve (first chunk length)
+  double mixed_rate = 0;  // slowest r.r contraction per FP32 iteration of the last mixed solve
   bool use_graphs = true;
 
   // Order this call after the previous one if it ran on another stream
@@ -352,17 +352,15 @@ void fl_destroy(fl_op A) {
   A->cg_out.mem.release();
   A->outer_flags.release();
   if (A->done) hipEventDestroy(A->done);
-  for (auto& gph : A->graph) gph.reset();
+  A->grel.reset();
   for (auto& gph : A->glen) gph.reset();
+  for (auto& gph : A->glen32) gph.reset();
   A->poll_dev.release();
   A->ext_khat.release();
   A->ext_work.release();
   A->ext_rhs.release();
   if (A->poll_host) hipHostFree(A->poll_host);
   if (A->ev_in) hipEventDestroy(A->ev_in);
-  for (auto& e : A->ev_poll)
-    if (e) hipEventDestroy(e);
-  if (A->pinned) hipHostFree(A->pinned);
   if (A->solve_stream) hipStreamDestroy(A->solve_stream);
   delete A;
 }
@@ -618,6 +616,10 @@ fl::CgScalars cg_view(const fl::CgScalars& base, const fl::Geometry& g, const fl
     throw Error(FL_E_UNSUPPORTED, "too many blocks for the reduction buffers");
   c.maxiter = maxiter;
   c.precond = precond;
+  c.rel_last = nullptr;
+  c.rel_f2 = nullptr;
+  c.rel_trig = nullptr;
+  c.rel_delta2 = c.rel_tol2 = 0.0;
   c.tol2 = tol * tol;
   return c;
 }
@@ -626,8 +628,6 @@ void ensure_solver_stream(fl_op A) {
   if (A->solve_stream) return;
   FL_HIP(hipStreamCreateWithFlags(&A->solve_stream, hipStreamNonBlocking));
   FL_HIP(hipEventCreateWithFlags(&A->ev_in, hipEventDisableTiming));
-  for (auto& e : A->ev_poll) FL_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  FL_HIP(hipHostMalloc((void**)&A->pinned, 2 * sizeof(int), hipHostMallocDefault));
 }
 
 // Replay the captured chunk if `key` matches; otherwise run `enqueue` once
@@ -664,23 +664,44 @@ void launch_chunk(ChunkGraph& g, const std::vector<double>& key, hipStream_t st,
   g.key = key;
 }
 
-// Run chunks until no right-hand side is active.  The active count of each
-// chunk is copied to pinned host memory and checked one chunk later, so the
-// GPU never waits for the host; the one extra chunk is fully masked.
+// Device and pinned host buffers of the poll record (fl::pack_poll).
+double* poll_buffers(fl_op A, int nrhs, double** dev, size_t* bytes) {
+  const size_t pb = (1 + fl::POLL_STRIDE * (size_t)nrhs) * sizeof(double);
+  *dev = (double*)A->poll_dev.get(pb);
+  if (A->poll_cap < pb) {
+    if (A->poll_host) FL_HIP(hipHostFree(A->poll_host));
+    A->poll_host = nullptr;
+    A->poll_cap = 0;
+    FL_HIP(hipHostMalloc((void**)&A->poll_host, pb, hipHostMallocDefault));
+    A->poll_cap = pb;
+  }
+  *bytes = pb;
+  return A->poll_host;
+}
+
+// n CG iterations as captured graphs of 16, 8, 4, 2 and 1 iterations.
 template <typename F>
-void chunk_loop(fl_op A, ChunkGraph& g, const std::vector<double>& key, int max_chunks,
-                const fl::CgScalars& cg, hipStream_t st, F&& enqueue) {
-  for (int c = 0; c < max_chunks; ++c) {
-    const int slot = c & 1;
-    launch_chunk(g, key, st, A->use_graphs, enqueue);
-    FL_HIP(hipMemcpyAsync(&A->pinned[slot], cg.n_active, sizeof(int), hipMemcpyDeviceToHost, st));
-    FL_HIP(hipEventRecord(A->ev_poll[slot], st));
-    if (c >= 1) {
-      FL_HIP(hipEventSynchronize(A->ev_poll[1 - slot]));
-      if (A->pinned[1 - slot] == 0) break;
+void launch_iterations(fl_op A, ChunkGraph* gl, const std::vector<double>& key, int n,
+                       hipStream_t st, F&& enqueue_one) {
+  static const int lens[5] = {1, 2, 4, 8, 16};
+  for (int b = 4; b >= 0; --b) {
+    while (n >= lens[b]) {
+      std::vector<double> kb = key;
+      kb.push_back(lens[b]);
+      launch_chunk(gl[b], kb, st, A->use_graphs, [&]() {
+        for (int i = 0; i < lens[b]; ++i) enqueue_one();
+      });
+      n -= lens[b];
     }
   }
-  FL_HIP(hipStreamSynchronize(st));
+}
+
+// Iterations for r.r to fall from rr to target at `rate` per iteration
+// (8 if the rate is unknown or too slow to extrapolate).
+inline int iterations_to(double rr, double target, double rate) {
+  if (!(rr > target)) return 0;
+  if (!(rate > 0.0 && rate < 0.95) || !(target > 0.0)) return 8;
+  return (int)std::ceil(std::log(target / rr) / std::log(rate));
 }
 
 // Run CG iterations in chunks whose length is predicted from each active
@@ -694,55 +715,36 @@ void chunk_loop(fl_op A, ChunkGraph& g, const std::vector<double>& key, int max_
 template <typename F>
 void predictive_loop(fl_op A, const std::vector<double>& key, int cap, const fl::CgScalars& cg,
                      int nrhs, hipStream_t st, F&& enqueue_one) {
-  const size_t pb = (1 + 4 * (size_t)nrhs) * sizeof(double);
-  double* dpoll = (double*)A->poll_dev.get(pb);
-  if (A->poll_cap < pb) {
-    if (A->poll_host) FL_HIP(hipHostFree(A->poll_host));
-    A->poll_host = nullptr;
-    A->poll_cap = 0;
-    FL_HIP(hipHostMalloc((void**)&A->poll_host, pb, hipHostMallocDefault));
-    A->poll_cap = pb;
-  }
-  static const int lens[5] = {1, 2, 4, 8, 16};
+  double* dpoll = nullptr;
+  size_t pb = 0;
+  const double* h = poll_buffers(A, nrhs, &dpoll, &pb);
   std::vector<double> rr_prev(nrhs, 0.0);
   std::vector<int> it_prev(nrhs, 0);
   int done = 0, next = A->iter_hint > 0 ? std::min(A->iter_hint + 1, 16) : 8;
   int max_it = 0;
   while (done < cap) {
-    int k = std::min(next, cap - done);
-    for (int b = 4; b >= 0; --b) {
-      while (k >= lens[b]) {
-        std::vector<double> kb = key;
-        kb.push_back(lens[b]);
-        launch_chunk(A->glen[b], kb, st, A->use_graphs, [&]() {
-          for (int i = 0; i < lens[b]; ++i) enqueue_one();
-        });
-        k -= lens[b];
-        done += lens[b];
-      }
-    }
-    fl::pack_poll(cg, nrhs, dpoll, st);
+    const int k = std::min(next, cap - done);
+    launch_iterations(A, A->glen, key, k, st, enqueue_one);
+    done += k;
+    fl::pack_poll(cg, nrhs, nullptr, nullptr, nullptr, dpoll, st);
     FL_HIP(hipMemcpyAsync(A->poll_host, dpoll, pb, hipMemcpyDeviceToHost, st));
     FL_HIP(hipStreamSynchronize(st));
-    const double* h = A->poll_host;
-    for (int o = 0; o < nrhs; ++o) max_it = std::max(max_it, (int)h[1 + 4 * o + 3]);
+    for (int o = 0; o < nrhs; ++o) max_it = std::max(max_it, (int)h[1 + fl::POLL_STRIDE * o + 3]);
     if (h[0] == 0.0) break;
     int need = 1;
     for (int o = 0; o < nrhs; ++o) {
-      const double* q = h + 1 + 4 * o;
+      const double* q = h + 1 + fl::POLL_STRIDE * o;
       if (q[2] == 0.0) continue;
-      const double rr = q[0], th = q[1];
+      // r.r after the last update (what the next iteration start tests)
+      const double rr = q[4], th = q[1];
       const int it = (int)q[3];
       // before the first poll the reference is r_0: ||r_0||^2 = thresh2 / tol^2
       if (rr_prev[o] == 0.0 && cg.tol2 > 0.0) rr_prev[o] = th / cg.tol2;
-      int guess = 8;
-      if (rr <= th) {
-        guess = 1;
-      } else if (rr_prev[o] > 0.0 && it > it_prev[o] && rr > 0.0 && th > 0.0) {
-        const double rate = std::pow(rr / rr_prev[o], 1.0 / (it - it_prev[o]));
-        if (rate < 0.95) guess = (int)std::ceil(std::log(th / rr) / std::log(rate)) + 1;
-      }
-      need = std::max(need, guess);
+      double rate = 0.0;
+      if (rr_prev[o] > 0.0 && it > it_prev[o] && rr > 0.0)
+        rate = std::pow(rr / rr_prev[o], 1.0 / (it - it_prev[o]));
+      // plus the iteration whose start detects convergence
+      need = std::max(need, iterations_to(rr, th, rate) + 1);
       rr_prev[o] = rr;
       it_prev[o] = it;
     }
@@ -750,6 +752,78 @@ void predictive_loop(fl_op A, const std::vector<double>& key, int cap, const fl:
   }
   FL_HIP(hipStreamSynchronize(st));
   A->iter_hint = max_it;
+}
+
+// Mixed precision (FP32 CG with FP64 reliable updates) in predicted chunks:
+// FP32 iterations as captured graphs, then the reliable step (fold the FP32
+// correction and replace the residual by the FP64 one for the right-hand
+// sides whose recursion stopped at its trigger, stop those that meet the
+// tolerance, resume the others), then a poll.  The trigger is tested at
+// every iteration start on the device, so chunk lengths change only when
+// the reliable step runs, never the arithmetic.  The next chunk lasts until
+// the slowest active right-hand side reaches its next trigger,
+// max(delta^2 rr_last, tol^2 ||f||^2), at the contraction of its FP32 r.r
+// observed between replacements.  The first chunk uses the previous mixed
+// solve's rate.
+template <typename F, typename G>
+void predictive_mixed_loop(fl_op A, const std::vector<double>& key, int maxiter,
+                           const fl::CgScalars& cg, int nrhs, const double* rr_last,
+                           const double* f2, const int* nupd, double delta2, double tol2,
+                           hipStream_t st, F&& enqueue_one, G&& enqueue_reliable) {
+  double* dpoll = nullptr;
+  size_t pb = 0;
+  const double* h = poll_buffers(A, nrhs, &dpoll, &pb);
+  std::vector<double> rr_ref(nrhs, 0.0), rate(nrhs, 0.0);
+  std::vector<int> it_ref(nrhs, 0), nu_ref(nrhs, 0);
+  int next = 8;
+  if (A->mixed_rate > 0.0 && A->mixed_rate < 0.95)
+    next = std::min(std::max(iterations_to(1.0, std::max(delta2, tol2), A->mixed_rate), 1), 16);
+  std::vector<double> krel = key;
+  krel.push_back(-1.0);
+  double slowest = 0.0;
+  // maxiter is enforced per RHS on the device; a right-hand side waiting for
+  // its reliable update skips the rest of the chunk, so launched iterations
+  // overcount.  Every chunk advances each active RHS by an iteration or a
+  // replacement, which bounds the number of chunks.
+  const int max_chunks = 2 * (maxiter + 2) + 8;
+  for (int c = 0; c < max_chunks; ++c) {
+    launch_iterations(A, A->glen32, key, next, st, enqueue_one);
+    launch_chunk(A->grel, krel, st, A->use_graphs, enqueue_reliable);
+    fl::pack_poll(cg, nrhs, rr_last, f2, nupd, dpoll, st);
+    FL_HIP(hipMemcpyAsync(A->poll_host, dpoll, pb, hipMemcpyDeviceToHost, st));
+    FL_HIP(hipStreamSynchronize(st));
+    if (h[0] == 0.0) break;
+    int need = 1;
+    for (int o = 0; o < nrhs; ++o) {
+      const double* q = h + 1 + fl::POLL_STRIDE * o;
+      if (q[2] == 0.0) continue;
+      const double res2 = q[0], rr = q[4], rl = q[5], ff = q[6];
+      const int it = (int)q[3], nu = (int)q[7];
+      if (rr_ref[o] == 0.0) rr_ref[o] = ff;   // x_0 = 0: r_0 = f
+      // contraction of the FP32 recursion since the reference: from r.r now
+      // if no replacement happened, else from r.r at the start of the last
+      // iteration (before the replacement)
+      double cur = rr;
+      int itc = it;
+      if (nu != nu_ref[o]) {
+        cur = res2;
+        itc = it - 1;
+      }
+      if (itc > it_ref[o] && cur > 0.0 && rr_ref[o] > 0.0) {
+        const double r = std::pow(cur / rr_ref[o], 1.0 / (itc - it_ref[o]));
+        if (r < 1.0) rate[o] = r;
+      }
+      slowest = std::max(slowest, rate[o]);
+      const double target = std::max(delta2 * rl, tol2 * ff);
+      need = std::max(need, iterations_to(rr, target, rate[o]));
+      rr_ref[o] = rr;
+      it_ref[o] = it;
+      nu_ref[o] = nu;
+    }
+    next = std::min(std::max(need, 1), 16);
+  }
+  FL_HIP(hipStreamSynchronize(st));
+  if (slowest > 0.0) A->mixed_rate = slowest;
 }
 
 template <typename... P>
@@ -943,14 +1017,22 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
       }
     } else if (mixed == 1) {
       // FP32 CG with FP64 reliable updates: the FP32 recursion runs on a
-      // correction xlo; every `chunk` iterations each RHS whose FP32 residual
-      // fell below delta^2 of its value at the last update (or below the
-      // tolerance) folds xlo into the FP64 iterate, recomputes r = f - A u
-      // in FP64, stops if ||r|| <= tol ||f||, and otherwise continues from
-      // r (rounded to FP32) with the same search direction.
+      // correction xlo; after every predicted chunk of iterations each RHS
+      // whose FP32 r.r fell below delta^2 of its value at the last update
+      // (or below the tolerance) folds xlo into the FP64 iterate, recomputes
+      // r = f - A u in FP64, stops if ||r|| <= tol ||f||, and otherwise
+      // continues from r (rounded to FP32); preconditioned, the search
+      // direction restarts there.
       fl::CgScalars cg = cg_view(A->cg.s, A->g, A->sc32, A->sp32, nrhs, maxiter, tol, pc);
       cg.tol2 = 0.0;  // the FP32 recursion never stops on its own residual
       const double delta2 = A->delta * A->delta;
+      // ... but waits for a reliable update at the iteration start where its
+      // r.r reaches the trigger (cg_begin)
+      cg.rel_last = rr_last;
+      cg.rel_f2 = f2;
+      cg.rel_trig = trig;
+      cg.rel_delta2 = delta2;
+      cg.rel_tol2 = tol * tol;
       const int nb64 = fl::last_pass_blocks(A->g, A->sc64);
       char* vb = (char*)A->vecs.get(3 * a8 + 6 * a4);
       double* r64 = (double*)vb;
@@ -967,6 +1049,7 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
       fl::to_float(f, rhs32, (long)nrhs * nd, st);
       FL_HIP(hipMemcpyAsync(rr_last, f2, nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
       fl::fill_int(nupd, 0, nrhs, st);
+      fl::fill_int(trig, 0, nrhs, st);
       cg_start<float>(A, A->sc32, pc_symbol<float>(A), A->tw32, rhs32, xlo, r32, p32, z32, nrhs, cg,
                       nullptr, ws, st);
       const int chunk = 8;
@@ -977,21 +1060,24 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
       for (double v : sched_key(A->sc32)) key.push_back(v);
       for (double v : sched_key(A->sp32)) key.push_back(v);
       for (double v : sched_key(A->sc64)) key.push_back(v);
-      chunk_loop(A, A->graph[1], key, (maxiter + 2) / chunk + 2, cg, st, [&]() {
-        for (int i = 0; i < chunk; ++i)
-          cg_iteration<float>(A, A->sc32, A->lam32, pc_symbol<float>(A), A->tw32, xlo, r32, p32, q32, z32,
-                              nrhs, cg, ws, st);
-        fl::reliable_accum(A->g, xhi, xlo, nrhs, cg, rr_last, f2, delta2, tol * tol, trig, false,
-                           st);
-        fl::apply_passes<double>(A->g, A->sc64, A->lam64, A->tw64, xhi, r64, nrhs, ws, st,
-                                 fl::PM_RESID, nullptr, nullptr, fc, &co, trig);
-        fl::reliable_replace(A->g, r64, r32, nrhs, cg, co.part_a, nb64, co.max_blocks, rr_last,
-                             f2, tol * tol, trig, nupd, st);
-        if (pc) precond_apply<float>(A, pc_symbol<float>(A), A->tw32, r32, z32, nrhs, ws, cg, trig,
-                                     st);
-      });
+      predictive_mixed_loop(
+          A, key, maxiter, cg, nrhs, rr_last, f2, nupd, delta2, tol * tol, st,
+          [&]() {
+            cg_iteration<float>(A, A->sc32, A->lam32, pc_symbol<float>(A), A->tw32, xlo, r32, p32,
+                                q32, z32, nrhs, cg, ws, st);
+          },
+          [&]() {
+            fl::reliable_accum(A->g, xhi, xlo, nrhs, cg, trig, false, st);
+            fl::apply_passes<double>(A->g, A->sc64, A->lam64, A->tw64, xhi, r64, nrhs, ws, st,
+                                     fl::PM_RESID, nullptr, nullptr, fc, &co, trig);
+            fl::reliable_replace(A->g, r64, r32, nrhs, cg, co.part_a, nb64, co.max_blocks,
+                                 rr_last, f2, tol * tol, trig, nupd, st);
+            if (pc)
+              precond_apply<float>(A, pc_symbol<float>(A), A->tw32, r32, z32, nrhs, ws, cg, trig,
+                                   st);
+          });
       // fold what is left (RHS stopped by maxiter) and report true residuals
-      fl::reliable_accum(A->g, xhi, xlo, nrhs, cg, rr_last, f2, delta2, tol * tol, trig, true, st);
+      fl::reliable_accum(A->g, xhi, xlo, nrhs, cg, trig, true, st);
       FL_HIP(hipMemcpyAsync(u, xhi, v8, hipMemcpyDeviceToDevice, st));
       fp64_residual(A, f, u, r64, nrhs, co, nullptr, rro, ws, st);
       FL_HIP(hipMemcpyAsync(iters.data(), cg.iters, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));

@@ -98,16 +98,27 @@ __global__ void k_fill_int(int* p, int v, int n) {
 }
 
 // Per-RHS CG state gathered for the host: [n_active, then per RHS
-// (r.r at the last iteration start, stopping threshold, active, iterations)].
-__global__ void k_pack_poll(CgScalars cg, int nrhs, double* out) {
+// POLL_STRIDE values: r.r at the last iteration start, stopping threshold,
+// active, iterations, r.r now (sum of the partials of the last update or
+// replacement), r.r at the last reliable update, ||f||^2, reliable updates].
+// The last three are 0 when their arrays are not given.
+__global__ void k_pack_poll(CgScalars cg, int nrhs, const double* rr_last, const double* f2,
+                            const int* nupd, double* out) {
   const int o = blockIdx.x * blockDim.x + threadIdx.x;
   if (o == 0) out[0] = (double)cg.n_active[0];
   if (o < nrhs) {
-    double* q = out + 1 + 4 * (long)o;
+    double* q = out + 1 + POLL_STRIDE * (long)o;
+    const double* part = (cg.precond ? cg.part_c : cg.part_b) + (long)o * cg.max_blocks;
+    double now = 0.0;
+    for (int i = 0; i < cg.nb_c; ++i) now += part[i];
     q[0] = cg.res2[o];
     q[1] = cg.thresh2[o];
     q[2] = (double)cg.active[o];
     q[3] = (double)cg.iters[o];
+    q[4] = now;
+    q[5] = rr_last ? rr_last[o] : 0.0;
+    q[6] = f2 ? f2[o] : 0.0;
+    q[7] = nupd ? (double)nupd[o] : 0.0;
   }
 }
 
@@ -166,29 +177,16 @@ __global__ void __launch_bounds__(VT) k_to_float(const double* src, float* dst, 
     dst[i] = (float)src[i];
 }
 
-// Reliable update, step 1: decide per RHS whether to replace the FP32
-// recursive residual by the true FP64 one (it fell below delta^2 times its
-// value at the last replacement, or below the final tolerance), and if so
-// fold the FP32 correction into the FP64 iterate: xhi += xlo, xlo = 0.
+// Reliable update, step 1: for each RHS whose FP32 recursion stopped at an
+// iteration start because its r.r fell below delta^2 times its value at the
+// last replacement, or below the final tolerance (trig[o] = 1, decided per
+// iteration, so the result does not depend on when this step runs), fold
+// the FP32 correction into the FP64 iterate: xhi += xlo, xlo = 0.
 // force: fold for every RHS (end of the solve).
 __global__ void __launch_bounds__(VT) k_reliable_accum(double* xhi, float* xlo, long nd,
-                                                       CgScalars cg, const double* rr_last,
-                                                       const double* f2, double delta2,
-                                                       double tol2, int* trig, int force) {
-  __shared__ double red[16];
+                                                       const int* trig, int force) {
   const int o = blockIdx.y;
-  bool t = true;
-  if (!force) {
-    if (!cg.active[o]) {
-      if (blockIdx.x == 0 && threadIdx.x == 0) trig[o] = 0;
-      return;
-    }
-    const double rr = sum_partials((cg.precond ? cg.part_c : cg.part_b) + (long)o * cg.max_blocks,
-                                   cg.nb_c, red);
-    t = !(rr >= delta2 * rr_last[o]) || rr <= tol2 * f2[o];
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) trig[o] = t ? 1 : 0;
-  if (!t) return;
+  if (!force && !trig[o]) return;
   const long base = (long)o * nd;
   for (long i = (long)blockIdx.x * VT + threadIdx.x; i < nd; i += (long)gridDim.x * VT) {
     xhi[base + i] += (double)xlo[base + i];
@@ -197,13 +195,14 @@ __global__ void __launch_bounds__(VT) k_reliable_accum(double* xhi, float* xlo, 
 }
 
 // Reliable update, step 2 (after r64 = f - A xhi in FP64 for the flagged
-// RHS): stop if ||r64|| meets the tolerance, else r32 = r64 and fresh
-// partials of r32.r32 for the next iteration's beta.
+// RHS): stop if ||r64|| meets the tolerance (and clear the flag, so the
+// preconditioner skips it), else resume the FP32 recursion from r32 = r64
+// with fresh partials of r32.r32.
 __global__ void __launch_bounds__(VT) k_reliable_replace(const double* r64, float* r32, long nd,
                                                          CgScalars cg, const double* part64,
                                                          int nb64, int mb64, double* rr_last,
                                                          const double* f2, double tol2,
-                                                         const int* trig, int* nupd) {
+                                                         int* trig, int* nupd) {
   __shared__ double red[16];
   const int o = blockIdx.y;
   if (!trig[o]) return;
@@ -213,13 +212,18 @@ __global__ void __launch_bounds__(VT) k_reliable_replace(const double* r64, floa
     rr_last[o] = rr64;
     nupd[o] = nupd[o] + 1;
   }
+  // the RHS is inactive since its recursion stopped; blocks other than the
+  // lead do nothing more on this branch, so clearing the flag cannot race
   if (rr64 <= tol2 * f2[o] || !isfinite(rr64)) {
     if (lead) {
-      cg.active[o] = 0;
       cg.status[o] = isfinite(rr64) ? 0 : 6;
-      atomicSub(cg.n_active, 1);
+      trig[o] = 0;
     }
     return;
+  }
+  if (lead) {
+    cg.active[o] = 1;
+    atomicAdd(cg.n_active, 1);
   }
   // Preconditioned: within one check interval the FP32 recursion reaches
   // FP32 accuracy, so the old search direction no longer matches the
@@ -248,17 +252,16 @@ void to_float(const double* src, float* dst, long n, hipStream_t st) {
 }
 
 void reliable_accum(const Geometry& g, double* xhi, float* xlo, int nrhs, const CgScalars& cg,
-                    const double* rr_last, const double* f2, double delta2, double tol2,
-                    int* trig, bool force, hipStream_t st) {
+                    const int* trig, bool force, hipStream_t st) {
   dim3 grid(cg.nb_c, nrhs);
-  hipLaunchKernelGGL(k_reliable_accum, grid, dim3(VT), 0, st, xhi, xlo, g.nd, cg, rr_last, f2,
-                     delta2, tol2, trig, force ? 1 : 0);
+  hipLaunchKernelGGL(k_reliable_accum, grid, dim3(VT), 0, st, xhi, xlo, g.nd, trig,
+                     force ? 1 : 0);
   check_launch("reliable accumulate");
 }
 
 void reliable_replace(const Geometry& g, const double* r64, float* r32, int nrhs,
                       const CgScalars& cg, const double* part64, int nb64, int mb64,
-                      double* rr_last, const double* f2, double tol2, const int* trig,
+                      double* rr_last, const double* f2, double tol2, int* trig,
                       int* nupd, hipStream_t st) {
   dim3 grid(cg.nb_c, nrhs);
   hipLaunchKernelGGL(k_reliable_replace, grid, dim3(VT), 0, st, r64, r32, g.nd, cg, part64, nb64,
@@ -307,8 +310,10 @@ void fill_int(int* p, int v, int n, hipStream_t st) {
   check_launch("fill");
 }
 
-void pack_poll(const CgScalars& cg, int nrhs, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_pack_poll, dim3((nrhs + 63) / 64), dim3(64), 0, st, cg, nrhs, out);
+void pack_poll(const CgScalars& cg, int nrhs, const double* rr_last, const double* f2,
+               const int* nupd, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_pack_poll, dim3((nrhs + 63) / 64), dim3(64), 0, st, cg, nrhs, rr_last, f2,
+                     nupd, out);
   check_launch("poll pack");
 }
 

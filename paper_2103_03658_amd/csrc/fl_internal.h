@@ -58,6 +58,13 @@ struct CgScalars {
   int maxiter;
   int precond;       // 1: z = P r (preconditioned CG), rho = r.z
   double tol2;
+  // FP32 recursion of the mixed path (null otherwise): at an iteration start
+  // whose r.r fell below rel_delta2 * rel_last[o] or rel_tol2 * rel_f2[o],
+  // RHS o stops and waits (rel_trig[o] = 1) for the reliable step
+  const double* rel_last;
+  const double* rel_f2;
+  int* rel_trig;
+  double rel_delta2, rel_tol2;
 };
 
 // Epilogue/prologue selection of the first and last FFT passes.
@@ -183,8 +190,11 @@ template <typename T>
 void cg_update(const Geometry& g, T* x, T* r, const T* p, const T* q, int nrhs,
                const CgScalars& cg, hipStream_t st);
 void fill_int(int* p, int v, int n, hipStream_t st);
-// out[0] = n_active; out[1 + 4 o ..] = res2, thresh2, active, iters of RHS o.
-void pack_poll(const CgScalars& cg, int nrhs, double* out, hipStream_t st);
+// out[0] = n_active; out[1 + POLL_STRIDE o ..] = res2, thresh2, active, iters,
+// r.r now, rr_last[o], f2[o], nupd[o] of RHS o (the last three 0 if null).
+constexpr int POLL_STRIDE = 8;   // doubles per RHS in the poll record
+void pack_poll(const CgScalars& cg, int nrhs, const double* rr_last, const double* f2,
+               const int* nupd, double* out, hipStream_t st);
 void fill_zero_bytes(void* p, size_t bytes, hipStream_t st);
 // out[o] = sum_{b < nb} part[o * max_blocks + b] (fixed order)
 void reduce_parts(const double* part, int nb, int max_blocks, int nrhs, double* out,
@@ -197,11 +207,10 @@ void refine_axpy(double* u, const float* d32, const double* scale, long nd, int 
 // FP32 CG with FP64 reliable updates (see cg unit)
 void to_float(const double* src, float* dst, long n, hipStream_t st);
 void reliable_accum(const Geometry& g, double* xhi, float* xlo, int nrhs, const CgScalars& cg,
-                    const double* rr_last, const double* f2, double delta2, double tol2,
-                    int* trig, bool force, hipStream_t st);
+                    const int* trig, bool force, hipStream_t st);
 void reliable_replace(const Geometry& g, const double* r64, float* r32, int nrhs,
                       const CgScalars& cg, const double* part64, int nb64, int mb64,
-                      double* rr_last, const double* f2, double tol2, const int* trig,
+                      double* rr_last, const double* f2, double tol2, int* trig,
                       int* nupd, hipStream_t st);
 // partials of sum v^2 per RHS into part (vec_blocks per RHS)
 void sum_squares_parts(const double* v, long nd, int nrhs, double* part, int max_blocks,

@@ -77,7 +77,7 @@ __device__ __forceinline__ bool cg_begin(const CgScalars& cg, int o, bool lead, 
   const double rr =
       cg.precond ? sum_partials(cg.part_c + (long)o * cg.max_blocks, cg.nb_c, sh) : rho;
   const int it = cg.iters[o];
-  bool stop = false;
+  bool stop = false, pending = false;
   int status = 0;
   double b = 0.0;
   if (!isfinite(rr) || !isfinite(rho)) {
@@ -85,6 +85,9 @@ __device__ __forceinline__ bool cg_begin(const CgScalars& cg, int o, bool lead, 
     status = 6;
   } else if (it == 0) {
     stop = rr == 0.0;
+  } else if (cg.rel_trig &&
+             (!(rr >= cg.rel_delta2 * cg.rel_last[o]) || rr <= cg.rel_tol2 * cg.rel_f2[o])) {
+    stop = pending = true;   // wait for the reliable update
   } else if (rr <= cg.thresh2[o]) {
     stop = true;
   } else if (it >= cg.maxiter) {
@@ -99,6 +102,7 @@ __device__ __forceinline__ bool cg_begin(const CgScalars& cg, int o, bool lead, 
   if (lead && threadIdx.x == 0) {
     cg.rr_cur[o] = rho;
     cg.res2[o] = rr;
+    if (cg.rel_trig) cg.rel_trig[o] = pending ? 1 : 0;
     if (it == 0) cg.thresh2[o] = cg.tol2 * rr;
     if (stop) {
       cg.active[o] = 0;
