@@ -343,7 +343,7 @@ def main():
     mixed = {"fp64": 0, "reliable": 1, "refine": 2}[args.path]
     if args.delta is not None or args.inner_tol is not None:
         for a in alphas:
-            ops[a].set_refinement(delta=args.delta if args.delta is not None else 1e-3,
+            ops[a].set_refinement(delta=args.delta if args.delta is not None else 1e-5,
                                   inner_tol=args.inner_tol if args.inner_tol is not None else 1e-4)
 
     # launch schedules: tuned once per precision on one operator (same M for all)

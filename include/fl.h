@@ -181,9 +181,10 @@ fl_status fl_solve(fl_op A, const double *f, const double *g, double tol, int ma
 fl_status fl_exterior(fl_op A, const double *g_lat, const double *tail, double *b, int nrhs,
                       void *stream);
 
-/* Mixed-precision settings.  delta (default 1e-3): a reliable update
- * (mixed = 1) happens once the FP32 residual norm has dropped below delta
- * times its value at the previous update.  inner_tol (default 1e-4):
+/* Mixed-precision settings.  delta (default 1e-5): a reliable update
+ * (mixed = 1) happens at the first FP32 iteration whose residual norm has
+ * dropped below delta times its value at the previous update (or below the
+ * tolerance); that right-hand side waits there for the FP64 residual.  inner_tol (default 1e-4):
  * relative tolerance of each FP32 inner solve of mixed = 2.  max_outer
  * (default 40): refinement step cap of mixed = 2.  delta, inner_tol in
  * (0, 1), max_outer >= 1, else FL_E_INVAL and nothing changes. */

@@ -164,7 +164,7 @@ class Operator:
                  ctypes.byref(npass)))
         return [ms[i] for i in range(npass.value)]
 
-    def set_refinement(self, delta=1e-3, inner_tol=1e-4, max_outer=40):
+    def set_refinement(self, delta=1e-5, inner_tol=1e-4, max_outer=40):
         check(self._lib.fl_set_refinement(self._h, float(delta), float(inner_tol),
                                           int(max_outer)))
 

@@ -137,7 +137,7 @@ struct fl_op_s {
   const void* tw32 = nullptr;
   fl::Schedule sc64{}, sc32{};  // transform passes of the product A u
   fl::Schedule sp64{}, sp32{};  // transform passes of the preconditioner
-  double delta = 1e-3;      // reliable-update trigger (mixed = 1)
+  double delta = 1e-5;      // reliable-update trigger (mixed = 1)
   double inner_tol = 1e-4;  // inner solve tolerance (mixed = 2)
   int max_outer = 40;
   DBuf ws;                // FFT intermediates
@@ -777,7 +777,7 @@ void predictive_mixed_loop(fl_op A, const std::vector<double>& key, int maxiter,
   std::vector<int> it_ref(nrhs, 0), nu_ref(nrhs, 0);
   int next = 8;
   if (A->mixed_rate > 0.0 && A->mixed_rate < 0.95)
-    next = std::min(std::max(iterations_to(1.0, std::max(delta2, tol2), A->mixed_rate), 1), 16);
+    next = std::min(std::max(iterations_to(1.0, std::max(delta2, tol2), A->mixed_rate) + 1, 1), 16);
   std::vector<double> krel = key;
   krel.push_back(-1.0);
   double slowest = 0.0;
@@ -815,7 +815,8 @@ void predictive_mixed_loop(fl_op A, const std::vector<double>& key, int maxiter,
       }
       slowest = std::max(slowest, rate[o]);
       const double target = std::max(delta2 * rl, tol2 * ff);
-      need = std::max(need, iterations_to(rr, target, rate[o]));
+      // plus the iteration whose start detects the trigger
+      need = std::max(need, iterations_to(rr, target, rate[o]) + 1);
       rr_ref[o] = rr;
       it_ref[o] = it;
       nu_ref[o] = nu;

@@ -101,16 +101,18 @@ __global__ void k_fill_int(int* p, int v, int n) {
 // POLL_STRIDE values: r.r at the last iteration start, stopping threshold,
 // active, iterations, r.r now (sum of the partials of the last update or
 // replacement), r.r at the last reliable update, ||f||^2, reliable updates].
-// The last three are 0 when their arrays are not given.
-__global__ void k_pack_poll(CgScalars cg, int nrhs, const double* rr_last, const double* f2,
-                            const int* nupd, double* out) {
-  const int o = blockIdx.x * blockDim.x + threadIdx.x;
-  if (o == 0) out[0] = (double)cg.n_active[0];
-  if (o < nrhs) {
+// The last three are 0 when their arrays are not given.  One wave per RHS.
+__global__ void __launch_bounds__(64) k_pack_poll(CgScalars cg, int nrhs, const double* rr_last,
+                                                  const double* f2, const int* nupd,
+                                                  double* out) {
+  const int o = blockIdx.x;
+  if (o == 0 && threadIdx.x == 0) out[0] = (double)cg.n_active[0];
+  const double* part = (cg.precond ? cg.part_c : cg.part_b) + (long)o * cg.max_blocks;
+  double now = 0.0;
+  for (int i = threadIdx.x; i < cg.nb_c; i += 64) now += part[i];
+  now = wave_sum(now);
+  if (threadIdx.x == 0) {
     double* q = out + 1 + POLL_STRIDE * (long)o;
-    const double* part = (cg.precond ? cg.part_c : cg.part_b) + (long)o * cg.max_blocks;
-    double now = 0.0;
-    for (int i = 0; i < cg.nb_c; ++i) now += part[i];
     q[0] = cg.res2[o];
     q[1] = cg.thresh2[o];
     q[2] = (double)cg.active[o];
@@ -312,8 +314,8 @@ void fill_int(int* p, int v, int n, hipStream_t st) {
 
 void pack_poll(const CgScalars& cg, int nrhs, const double* rr_last, const double* f2,
                const int* nupd, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_pack_poll, dim3((nrhs + 63) / 64), dim3(64), 0, st, cg, nrhs, rr_last, f2,
-                     nupd, out);
+  hipLaunchKernelGGL(k_pack_poll, dim3(nrhs), dim3(64), 0, st, cg, nrhs, rr_last, f2, nupd,
+                     out);
   check_launch("poll pack");
 }
 
