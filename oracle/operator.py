@@ -201,16 +201,21 @@ def apply_rows(G, u, rows):
 # circulant embedding (what a fast product computes)
 # ---------------------------------------------------------------------------
 
-def embed_generator(G):
-    """c on {0..M-1}^d, M = 2N: c[j] = G[m(j)], m(j_s) = min(j_s, M - j_s),
-    zero wherever some m(j_s) > N - 2 (reading R7)."""
+def embed_generator(G, M=None):
+    """c on {0..M-1}^d, M = 2N unless given: c[j] = G[m(j)], m(j_s) =
+    min(j_s, M - j_s), zero wherever some m(j_s) > N - 2 (reading R7).  The
+    interior product uses offsets -(N-2)..N-2 only, so any M >= 2N - 3 keeps
+    them apart (no wrap-around) and gives the same restricted product."""
     d = G.ndim
     N = G.shape[0] - 1
-    M = 2 * N
+    if M is None:
+        M = 2 * N
+    if M < 2 * N - 3:
+        raise ValueError("embedding length M must be >= 2N - 3")
     j = np.arange(M)
     m = np.minimum(j, M - j)
     keep = m <= N - 2
-    c = G[np.ix_(*([m] * d))].copy()
+    c = G[np.ix_(*([np.minimum(m, N)] * d))].copy()   # entries with m > N - 2 are zeroed below
     mask = keep
     for s in range(1, d):
         mask = np.multiply.outer(mask, keep)
@@ -218,22 +223,24 @@ def embed_generator(G):
     return c
 
 
-def symbol(G):
+def symbol(G, M=None):
     """lambda-hat = DFT_M(c) / M^d, real part (c is real and even)."""
-    c = embed_generator(G)
+    c = embed_generator(G, M)
     lam = np.fft.fftn(c)
     return lam.real / c.size, float(np.abs(lam.imag).max() / c.size)
 
 
-def precond_apply(G, v, floor_rel=1e-12):
+def precond_apply(G, v, floor_rel=1e-12, M=None):
     """y = R C^{-1} R^T v: the preconditioner the solver uses (not part of
     the paper, whose solver is unspecified).  C is the circulant embedding of
-    A (symbol lambda-hat), floored at floor_rel * max lambda-hat so that it
-    is positive definite; R restricts to the n^d interior."""
+    A (symbol lambda-hat) of length M per axis (2N unless given), floored at
+    floor_rel * max lambda-hat so that it is positive definite; R restricts
+    to the n^d interior."""
     d = G.ndim
     n = G.shape[0] - 2
-    M = 2 * (G.shape[0] - 1)
-    lam, _ = symbol(G)
+    if M is None:
+        M = 2 * (G.shape[0] - 1)
+    lam, _ = symbol(G, M)
     lam = np.maximum(lam, floor_rel * lam.max())
     z = np.zeros((M,) * d)
     z[(slice(0, n),) * d] = v
