@@ -9,8 +9,10 @@
  * (-Delta)^{alpha/2}_h u = A u + b, A the symmetric (multilevel) Toeplitz
  * matrix with generator G_k = -c_{d,alpha} a_k, k in {0..N}^d, h = 2/N,
  * splitting parameter gamma = 2, Lagrange basis of degree 0, 1 or 2 in xi.
- * The product A u is computed by circulant embedding of size M = 2N per axis
- * and FFT (Sec. 2.1: the Toeplitz structure admits FFT products).
+ * The product A u is computed by circulant embedding of size M per axis, the
+ * smallest power of two >= 2N (any M >= 2N - 3 holds the Toeplitz offsets
+ * -(N-2)..N-2 without wrap-around), and FFT (Sec. 2.1: the Toeplitz
+ * structure admits FFT products).
  *
  * Conventions for every entry point:
  *  - Vectors live in device memory owned by the caller, contiguous,
@@ -41,7 +43,7 @@ typedef struct fl_op_s *fl_op;
 typedef enum {
   FL_OK = 0,
   FL_E_INVAL = 1,       /* invalid argument */
-  FL_E_UNSUPPORTED = 2, /* valid but outside what is built (e.g. M not a power of two) */
+  FL_E_UNSUPPORTED = 2, /* valid but outside what is built (e.g. N > 1024) */
   FL_E_NOMEM = 3,       /* device allocation failed */
   FL_E_DEVICE = 4,      /* a HIP call failed */
   FL_E_NOCONV = 5,      /* maxiter reached before the tolerance */
@@ -73,7 +75,8 @@ typedef struct {
  *   alpha   in (0, 2)
  *   degree  Lagrange degree p in {0, 1, 2}; p = 2 needs N even
  *   h       mesh size; N = 2/h must be an integer (to 1e-12 relative),
- *           N >= 4, and M = 2N a power of two with 8 <= M <= 2048
+ *           4 <= N <= 1024 (embedding M = the smallest power of two
+ *           >= 2N, at most 2048)
  *   kernel  FL_KERNEL_FRACTIONAL (lambda ignored) or FL_KERNEL_TEMPERED
  *   lambda  tempering rate >= 0 (normalisation constant c_{d,alpha})
  *   stream  HIP stream for the setup kernels
@@ -99,8 +102,9 @@ fl_status fl_weights_gamma(int d, double alpha, int degree, double h, int kernel
  * to host memory.  count must be >= (N+1)^d.  Test hook. */
 fl_status fl_generator(fl_op A, double *host_out, size_t count);
 
-/* Copy the folded FP64 symbol lambda-hat_k, k in {0..N}^d (the full
- * symbol on {0..M-1}^d is even: lambda-hat_j = lambda-hat_{min(j, M-j)}). */
+/* Copy the folded FP64 symbol lambda-hat_k, k in {0..M/2}^d ((M/2+1)^d
+ * values; N + 1 per axis when M = 2N).  The full symbol on {0..M-1}^d is
+ * even: lambda-hat_j = lambda-hat_{min(j, M-j)}. */
 fl_status fl_symbol(fl_op A, double *host_out, size_t count);
 
 /* Copy the circulant embedding c_j, j in {0..M-1}^d, of the generator as
@@ -109,7 +113,8 @@ fl_status fl_symbol(fl_op A, double *host_out, size_t count);
 fl_status fl_embedding(fl_op A, double *host_out, size_t count);
 
 /* Geometry of A: dimension, intervals N, interior points per axis n = N-1,
- * embedding length M = 2N.  Any pointer may be NULL. */
+ * embedding length M (the smallest power of two >= 2N).  Any pointer may
+ * be NULL. */
 fl_status fl_query(fl_op A, int *d, int *N, int *n, int *M);
 
 /*
@@ -174,7 +179,7 @@ fl_status fl_solve(fl_op A, const double *f, const double *g, double tol, int ma
  *          interior nodes are ignored)
  *   tail   device, nrhs * n^d doubles (interior layout), or NULL (tail = 0)
  *   b      device, nrhs * n^d doubles, output
- * FL_E_UNSUPPORTED unless d = 1, or d = 2 with M = 2N <= 1024.  Same stream
+ * FL_E_UNSUPPORTED unless d = 1, or d = 2 with M <= 1024.  Same stream
  * rules as fl_apply; allocates its transform buffers (2 (4N)^2 complex
  * doubles for d = 2) on first use and keeps them with the operator.
  */
@@ -244,14 +249,15 @@ fl_status fl_profile_precond(fl_op A, const void *u, void *y, int nrhs, int fp32
 
 /*
  * Preconditioning of fl_solve (the paper names no solver; A is SPD, Sec. 2.2):
- *   kind 2 (default): P = tau(A)^{-1}, the inverse of the natural tau
- *     approximation of the multilevel Toeplitz matrix (A minus its Hankel
- *     part on every level), diagonalised by the sine transform of each axis
- *     and applied by real sine passes (DST-I of every axis through the
- *     length-M transform of odd-extended line pairs);
- *   kind 1: P = R C^{-1} R^T, the restriction to the n^d interior of the
- *     inverse of the embedding circulant C (symbol 1 / max(lambda-hat,
- *     1e-12 max lambda-hat));
+ *   kind 2 (default when 2N is a power of two): P = tau(A)^{-1}, the
+ *     inverse of the natural tau approximation of the multilevel Toeplitz
+ *     matrix (A minus its Hankel part on every level), diagonalised by the
+ *     sine transform of each axis and applied by real sine passes (DST-I of
+ *     every axis through the length-2N transform of odd-extended line
+ *     pairs); FL_E_UNSUPPORTED when 2N is not a power of two;
+ *   kind 1 (default otherwise): P = R C^{-1} R^T, the restriction to the
+ *     n^d interior of the inverse of the embedding circulant C (symbol
+ *     1 / max(lambda-hat, 1e-12 max lambda-hat));
  *   kind 0: plain CG.
  * Both preconditioners are symmetric positive definite (eigenvalues floored
  * at 1e-12 of the largest).  The stopping rule is the relative residual

@@ -51,7 +51,7 @@ class Operator:
         self.alpha, self.degree, self.kernel, self.lam = float(alpha), int(degree), kernel, lam
         self.gamma = float(gamma)
         self.nd = self.n ** self.d
-        self.precond_kind = 2
+        self.precond_kind = 2 if self.M == 2 * self.N else 1
 
     # -- host copies (test hooks) ------------------------------------------
     def _host(self, fn, count):
@@ -65,8 +65,9 @@ class Operator:
             (self.N + 1,) * self.d)
 
     def symbol(self):
-        return self._host(self._lib.fl_symbol, (self.N + 1) ** self.d).reshape(
-            (self.N + 1,) * self.d)
+        """Folded symbol lambda-hat on [0, M/2]^d (M/2 + 1 = N + 1 when M = 2N)."""
+        h = self.M // 2 + 1
+        return self._host(self._lib.fl_symbol, h ** self.d).reshape((h,) * self.d)
 
     def embedding(self):
         return self._host(self._lib.fl_embedding, self.M ** self.d).reshape((self.M,) * self.d)

@@ -281,9 +281,12 @@ fl_status fl_weights_gamma(int d, double alpha, int degree, double h, int kernel
     const int N = (int)Nr;
     if (N < 4) return fail(FL_E_INVAL, "N = 2/h must be >= 4");
     if (degree == 2 && N % 2) return fail(FL_E_INVAL, "degree 2 needs N even");
-    const int M = 2 * N;
-    if ((M & (M - 1)) || M < 8 || M > 2048)
-      return fail(FL_E_UNSUPPORTED, "M = 2N must be a power of two in [8, 2048]");
+    // embedding length: any M >= 2N - 3 makes the restricted circulant product
+    // exact; the transforms take powers of two up to 2048, and the tau
+    // preconditioner's sine transforms need M = 2N exactly
+    int M = 8;
+    while (M < 2 * N) M *= 2;
+    if (M > 2048) return fail(FL_E_UNSUPPORTED, "N must be at most 1024 (embedding M <= 2048)");
     hipStream_t st = (hipStream_t)stream;
     fl_op A = new fl_op_s();
     try {
@@ -292,6 +295,8 @@ fl_status fl_weights_gamma(int d, double alpha, int degree, double h, int kernel
       A->g.N = N;
       A->g.n = N - 1;
       A->g.M = M;
+      A->g.H = M / 2 + 1;
+      A->precond = M == 2 * N ? 2 : 1;
       A->g.nd = 1;
       for (int s = 0; s < d; ++s) A->g.nd *= (N - 1);
       A->degree = degree;
@@ -302,19 +307,22 @@ fl_status fl_weights_gamma(int d, double alpha, int degree, double h, int kernel
       // c_{d,alpha} = 2^{alpha-1} alpha Gamma((d+alpha)/2) / (pi^{d/2} Gamma(1-alpha/2))
       A->c = std::pow(2.0, alpha - 1.0) * alpha * std::tgamma((d + alpha) / 2.0) /
              (std::pow(M_PI, d / 2.0) * std::tgamma(1.0 - alpha / 2.0));
-      long nf = 1;
-      for (int s = 0; s < d; ++s) nf *= (N + 1);
+      long nf = 1, nh = 1;
+      for (int s = 0; s < d; ++s) {
+        nf *= (N + 1);
+        nh *= A->g.H;
+      }
       A->G = (double*)dmalloc((size_t)nf * sizeof(double));
-      A->lam64 = (double*)dmalloc((size_t)nf * sizeof(double));
-      A->lam32 = (float*)dmalloc((size_t)nf * sizeof(float));
-      A->linv64 = (double*)dmalloc((size_t)nf * sizeof(double));
-      A->linv32 = (float*)dmalloc((size_t)nf * sizeof(float));
+      A->lam64 = (double*)dmalloc((size_t)nh * sizeof(double));
+      A->lam32 = (float*)dmalloc((size_t)nh * sizeof(float));
+      A->linv64 = (double*)dmalloc((size_t)nh * sizeof(double));
+      A->linv32 = (float*)dmalloc((size_t)nh * sizeof(float));
       fl::GenParams gp{d, degree, N, kernel, alpha, A->h, A->lambda, A->c, gamma};
       fl::build_generator(gp, A->G, st);
       fl::build_symbol(A->g, A->G, A->lam64, A->lam32, st);
       {
         double* scr = (double*)dmalloc(256);
-        fl::build_inverse_symbol(A->g, A->lam64, nf, A->linv64, A->linv32, scr, st);
+        fl::build_inverse_symbol(A->g, A->lam64, nh, A->linv64, A->linv32, scr, st);
         FL_HIP(hipStreamSynchronize(st));
         hipFree(scr);
       }
@@ -397,7 +405,7 @@ fl_status fl_symbol(fl_op A, double* host_out, size_t count) {
   return guarded([&]() -> fl_status {
     if (!A) return fail(FL_E_INVAL, "null handle");
     size_t nf = 1;
-    for (int s = 0; s < A->g.d; ++s) nf *= (size_t)(A->g.N + 1);
+    for (int s = 0; s < A->g.d; ++s) nf *= (size_t)A->g.H;
     return copy_out(A, A->lam64, host_out, count, nf, sizeof(double));
   });
 }
@@ -449,6 +457,8 @@ fl_status fl_set_precond_schedule(fl_op A, int fp32, int e_first, int e_mid, int
 fl_status fl_set_preconditioner(fl_op A, int kind) {
   if (!A) return fail(FL_E_INVAL, "null handle");
   if (kind < 0 || kind > 2) return fail(FL_E_INVAL, "kind must be 0, 1 or 2");
+  if (kind == 2 && A->g.M != 2 * A->g.N)
+    return fail(FL_E_UNSUPPORTED, "the tau preconditioner needs 2N to be a power of two");
   A->precond = kind;
   return FL_OK;
 }

@@ -80,7 +80,8 @@ struct Geometry {
   int d;       // 1, 2, 3
   int N;       // intervals per axis
   int n;       // interior points per axis = N - 1
-  int M;       // embedding length per axis = 2N
+  int M;       // embedding length per axis: the smallest power of two >= 2N
+  int H;       // folded symbol length per axis = M/2 + 1 (N + 1 when M = 2N)
   long nd;     // n^d
 };
 

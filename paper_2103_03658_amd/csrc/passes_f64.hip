@@ -85,16 +85,17 @@ void embed_generator(const Geometry& g, const double* G, double* out, hipStream_
   check_launch("embed");
 }
 
-// lambda-hat folded to k in [0, N]^d: Re(c_hat[k]) / M^d, plus an FP32 copy.
-__global__ void k_fold(const cx<double>* chat, double* l64, float* l32, int d, int N, int M,
+// lambda-hat folded to k in [0, M/2]^d (H = M/2 + 1 per axis): Re(c_hat[k]) / M^d,
+// plus an FP32 copy.
+__global__ void k_fold(const cx<double>* chat, double* l64, float* l32, int d, int H, int M,
                        long total, double inv) {
   const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= total) return;
   long rem = k;
   int idx[3] = {0, 0, 0};
   for (int s = d - 1; s >= 0; --s) {
-    idx[s] = (int)(rem % (N + 1));
-    rem /= (N + 1);
+    idx[s] = (int)(rem % H);
+    rem /= H;
   }
   long ci = 0;
   for (int s = 0; s < d; ++s) ci = ci * M + idx[s];
@@ -189,9 +190,9 @@ void build_symbol(const Geometry& g, const double* G, double* lam64, float* lam3
   check_launch("embed");
   fft_full(M, d, c, -1, st);
   long nf = 1;
-  for (int s = 0; s < d; ++s) nf *= (g.N + 1);
+  for (int s = 0; s < d; ++s) nf *= g.H;
   hipLaunchKernelGGL(k_fold, dim3((unsigned)((nf + thr - 1) / thr)), dim3(thr), 0, st, c, lam64,
-                     lam32, d, g.N, M, nf, 1.0 / (double)total);
+                     lam32, d, g.H, M, nf, 1.0 / (double)total);
   check_launch("fold");
   FL_HIP(hipStreamSynchronize(st));
   FL_HIP(hipFree(c));

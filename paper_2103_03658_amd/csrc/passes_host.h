@@ -32,7 +32,7 @@ void apply_passes_t(const Geometry& g, const Schedule& sc, const T* lam, const v
     if (ev) FL_HIP(hipEventRecord(ev[pass], st));
   };
   const cx<T>* tw = reinterpret_cast<const cx<T>*>(twv);
-  const int M = g.M, n = g.n, N1 = g.N + 1;
+  const int M = g.M, n = g.n, N1 = g.H;   // folded symbol row length
   const long h = M / 2 + 1;
   CgScalars nocg{};
   const CgScalars& c = cg ? *cg : nocg;

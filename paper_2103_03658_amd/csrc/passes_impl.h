@@ -456,7 +456,7 @@ struct MidArgs {
   long o_stride;         // complex elements between RHS
   long row_stride;       // complex elements between lines
   int n_in, n_out;
-  int N1;                // N + 1
+  int N1;                // folded symbol row length M/2 + 1
   int d;
   int LPB;
   int nrhs;

@@ -47,7 +47,7 @@ def test_library_exports_header_symbols():
     ((2, 1.0, 1, -0.25), _lib.FL_E_INVAL),
     ((2, 1.0, 1, 1.0), _lib.FL_E_INVAL),         # N = 2 < 4
     ((2, 1.0, 2, 2.0 / 9), _lib.FL_E_INVAL),     # p = 2, N odd
-    ((2, 1.0, 1, 2.0 / 12), _lib.FL_E_UNSUPPORTED),  # M = 24
+    ((2, 1.0, 1, 2.0 / 1025), _lib.FL_E_UNSUPPORTED),  # M = 4096
     ((1, 1.0, 1, 2.0 / 2048), _lib.FL_E_UNSUPPORTED),  # M = 4096
 ])
 def test_fl_weights_validation(args, code):
