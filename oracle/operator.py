@@ -125,59 +125,80 @@ def generator_at(d, alpha, p, N, nodes, lam=0.0):
 # dense operator
 # ---------------------------------------------------------------------------
 
-def dense_matrix(G):
-    """Materialise A_{ij} = G_{|i-j|} on the interior (n = N-1 per axis)."""
+def grid_shape(G, shape=None):
+    """Interior points per axis: n = N-1 on every axis of the cube, or the
+    given box shape (Sec. 2.2: the weights live on Upsilon = [0, L]^d with L
+    the longest side, so a box with N_s <= N intervals on axis s uses the
+    cube's generator on its own n_s = N_s - 1 interior points)."""
     d = G.ndim
     n = G.shape[0] - 2
-    idx = np.indices((n,) * d).reshape(d, -1)
+    if shape is None:
+        return (n,) * d
+    shape = tuple(int(v) for v in shape)
+    if len(shape) != d or min(shape) < 1 or max(shape) > n:
+        raise ValueError("box shape must give 1 <= n_s <= N - 1 on each axis")
+    return shape
+
+
+def dense_matrix(G, shape=None):
+    """Materialise A_{ij} = G_{|i-j|} on the interior grid (n = N-1 per axis,
+    or the box `shape`)."""
+    d = G.ndim
+    shp = grid_shape(G, shape)
+    idx = np.indices(shp).reshape(d, -1)
     diff = [np.abs(idx[s][:, None] - idx[s][None, :]) for s in range(d)]
     return G[tuple(diff)]
 
 
 def apply_dense(G, u):
-    """y = A u with A materialised (small grids)."""
-    A = dense_matrix(G)
-    shp = u.shape
+    """y = A u with A materialised (small grids); the grid is u's first d
+    axes (the cube's or a box's), trailing axes are right-hand sides."""
     d = G.ndim
+    shp = u.shape
+    A = dense_matrix(G, shp[:d])
     ub = u.reshape((-1,) + shp[d:]) if u.ndim > d else u.reshape(-1)
     return (A @ ub).reshape(shp)
 
 
 def apply_bttb(G, u):
     """y = A u without an FFT: y[i0] = sum_{j0} A_{|i0-j0|} u[j0], each
-    block applied as a dense (d-1)-level Toeplitz product.  O(n^{2d})."""
+    block applied as a dense (d-1)-level Toeplitz product.  O(n^{2d}).  The
+    grid is u's shape (the cube's or a box's)."""
     d = G.ndim
-    n = G.shape[0] - 2
+    shp = grid_shape(G, u.shape)
+    n0 = shp[0]
     if d == 1:
-        T = toeplitz(G[:n])
+        T = toeplitz(G[:n0])
         return T @ u
     if d == 2:
         # y[i0] = sum_m ( Z_m[i0 - m] + Z_m[i0 + m] ), Z_m[j0] = T_m u[j0],
         # T_m[i1, j1] = G[m, |i1 - j1|] (symmetric Toeplitz block)
-        y = np.zeros((n, n))
-        for m in range(n):
-            Z = u @ toeplitz(G[m, :n])
-            y[m:] += Z[:n - m]
+        n1 = shp[1]
+        y = np.zeros(shp)
+        for m in range(n0):
+            Z = u @ toeplitz(G[m, :n1])
+            y[m:] += Z[:n0 - m]
             if m:
-                y[:n - m] += Z[m:]
+                y[:n0 - m] += Z[m:]
         return y
     if d == 3:
-        y = np.zeros((n, n, n))
+        y = np.zeros(shp)
+        rest = shp[1] * shp[2]
         # V[m, j0] = A2(G[m]) u[j0]
-        A2 = [dense_matrix(G[m]) for m in range(n)]
-        U = u.reshape(n, n * n)
-        V = np.stack([U @ A2[m].T for m in range(n)])   # (m, j0, n^2)
-        for i0 in range(n):
-            m = np.abs(i0 - np.arange(n))
-            y[i0] = V[m, np.arange(n)].sum(axis=0).reshape(n, n)
+        A2 = [dense_matrix(G[m], shp[1:]) for m in range(n0)]
+        U = u.reshape(n0, rest)
+        V = np.stack([U @ A2[m].T for m in range(n0)])   # (m, j0, n1 n2)
+        for i0 in range(n0):
+            m = np.abs(i0 - np.arange(n0))
+            y[i0] = V[m, np.arange(n0)].sum(axis=0).reshape(shp[1:])
         return y
     raise ValueError("d must be 1, 2 or 3")
 
 
 def apply(G, u):
-    """Dense product, materialised when small, block form otherwise."""
-    n = G.shape[0] - 2
-    if n ** G.ndim <= 4096:
+    """Dense product, materialised when small, block form otherwise (grid:
+    u's first d axes)."""
+    if int(np.prod(u.shape[:G.ndim])) <= 4096:
         return apply_dense(G, u)
     return apply_bttb(G, u)
 
@@ -187,8 +208,7 @@ def apply_rows(G, u, rows):
     `rows` (array (m, d)), each by a compensated sum.  For sampled parity at
     sizes where the full product is out of reach."""
     d = G.ndim
-    n = G.shape[0] - 2
-    idx = np.indices((n,) * d).reshape(d, -1)
+    idx = np.indices(grid_shape(G, u.shape)).reshape(d, -1)
     uf = u.reshape(-1)
     out = np.empty(len(rows))
     for r, i in enumerate(rows):
@@ -201,31 +221,43 @@ def apply_rows(G, u, rows):
 # circulant embedding (what a fast product computes)
 # ---------------------------------------------------------------------------
 
-def embed_generator(G, M=None):
-    """c on {0..M-1}^d, M = 2N unless given: c[j] = G[m(j)], m(j_s) =
-    min(j_s, M - j_s), zero wherever some m(j_s) > N - 2 (reading R7).  The
-    interior product uses offsets -(N-2)..N-2 only, so any M >= 2N - 3 keeps
-    them apart (no wrap-around) and gives the same restricted product."""
+def embed_generator(G, M=None, intervals=None):
+    """c on prod {0..M_s-1}: c[j] = G[m(j)], m(j_s) = min(j_s, M_s - j_s),
+    zero wherever some m(j_s) > N_s - 2 (reading R7).  N_s: intervals of
+    axis s (N for the cube; a box's axes, Sec. 2.2); M_s = 2 N_s unless
+    given (an int for every axis, or one per axis).  The interior product
+    uses offsets -(N_s-2)..N_s-2 only, so any M_s >= 2 N_s - 3 keeps them
+    apart (no wrap-around) and gives the same restricted product."""
     d = G.ndim
     N = G.shape[0] - 1
+    Ns = (N,) * d if intervals is None else tuple(int(v) for v in intervals)
+    if len(Ns) != d or max(Ns) > N or min(Ns) < 2:
+        raise ValueError("intervals must give 2 <= N_s <= N on each axis")
     if M is None:
-        M = 2 * N
-    if M < 2 * N - 3:
-        raise ValueError("embedding length M must be >= 2N - 3")
-    j = np.arange(M)
-    m = np.minimum(j, M - j)
-    keep = m <= N - 2
-    c = G[np.ix_(*([np.minimum(m, N)] * d))].copy()   # entries with m > N - 2 are zeroed below
-    mask = keep
+        Ms = tuple(2 * v for v in Ns)
+    elif np.ndim(M) == 0:
+        Ms = (int(M),) * d
+    else:
+        Ms = tuple(int(v) for v in M)
+    if any(Ms[s] < 2 * Ns[s] - 3 for s in range(d)):
+        raise ValueError("embedding length M_s must be >= 2 N_s - 3")
+    ms, keeps = [], []
+    for s in range(d):
+        j = np.arange(Ms[s])
+        m = np.minimum(j, Ms[s] - j)
+        ms.append(np.minimum(m, N))            # entries with m > N_s - 2 are zeroed below
+        keeps.append(m <= Ns[s] - 2)
+    c = G[np.ix_(*ms)].copy()
+    mask = keeps[0]
     for s in range(1, d):
-        mask = np.multiply.outer(mask, keep)
+        mask = np.multiply.outer(mask, keeps[s])
     c[~mask] = 0.0
     return c
 
 
-def symbol(G, M=None):
-    """lambda-hat = DFT_M(c) / M^d, real part (c is real and even)."""
-    c = embed_generator(G, M)
+def symbol(G, M=None, intervals=None):
+    """lambda-hat = DFT_M(c) / prod M_s, real part (c is real and even)."""
+    c = embed_generator(G, M, intervals)
     lam = np.fft.fftn(c)
     return lam.real / c.size, float(np.abs(lam.imag).max() / c.size)
 
@@ -233,26 +265,29 @@ def symbol(G, M=None):
 def precond_apply(G, v, floor_rel=1e-12, M=None):
     """y = R C^{-1} R^T v: the preconditioner the solver uses (not part of
     the paper, whose solver is unspecified).  C is the circulant embedding of
-    A (symbol lambda-hat) of length M per axis (2N unless given), floored at
-    floor_rel * max lambda-hat so that it is positive definite; R restricts
-    to the n^d interior."""
+    A (symbol lambda-hat) of length M per axis (an int or one per axis; 2 N_s
+    unless given, N_s = n_s + 1 for the grid of v), floored at floor_rel *
+    max lambda-hat so that it is positive definite; R restricts to the
+    interior grid of v."""
     d = G.ndim
-    n = G.shape[0] - 2
+    shp = grid_shape(G, v.shape)
+    intervals = tuple(n + 1 for n in shp)
     if M is None:
-        M = 2 * (G.shape[0] - 1)
-    lam, _ = symbol(G, M)
+        M = tuple(2 * i for i in intervals)
+    lam, _ = symbol(G, M, intervals)
+    Ms = lam.shape
     lam = np.maximum(lam, floor_rel * lam.max())
-    z = np.zeros((M,) * d)
-    z[(slice(0, n),) * d] = v
-    y = np.fft.ifftn(np.fft.fftn(z) / (lam * M ** d)).real
-    return y[(slice(0, n),) * d]
+    z = np.zeros(Ms)
+    z[tuple(slice(0, n) for n in shp)] = v
+    y = np.fft.ifftn(np.fft.fftn(z) / (lam * np.prod(Ms))).real
+    return y[tuple(slice(0, n) for n in shp)]
 
 
 # ---------------------------------------------------------------------------
 # exterior data g != 0 (the b term of the paper)
 # ---------------------------------------------------------------------------
 
-def tau_symbol(G):
+def tau_symbol(G, shape=None):
     """Eigenvalues of the natural tau approximation of the multilevel Toeplitz
     matrix A (entries G_{|i-j|}): tau(T) = T - H(T) on every level, H(T) the
     Hankel matrix with first row (t_2, ..., t_{n-1}, 0, 0) and last row its
@@ -265,35 +300,40 @@ def tau_symbol(G):
         lam(k) = sum_{j in [0, n-1]^d} t_j prod_s w(j_s) cos(j_s theta_{k_s}),
     w(0) = 1, w(j) = 2; summed in this form (dense cosine matrices), which
     keeps its accuracy near theta = 0 and pi where the sine quotient loses
-    digits.  Shape (n,)*d."""
+    digits.  Shape (n,)*d, or the box `shape` (n_s per axis, sine transform
+    of length n_s + 1 on axis s)."""
     d = G.ndim
-    n = G.shape[0] - 2
-    t = np.array(G[(slice(0, n),) * d], dtype=np.float64)
-    k = np.arange(1, n + 1)
-    j = np.arange(n)
-    C = np.cos(np.pi * np.outer(k, j) / (n + 1)) * np.where(j == 0, 1.0, 2.0)[None, :]
+    shp = grid_shape(G, shape)
+    t = np.array(G[tuple(slice(0, n) for n in shp)], dtype=np.float64)
     y = t
     for ax in range(d):
+        n = shp[ax]
+        k = np.arange(1, n + 1)
+        j = np.arange(n)
+        C = np.cos(np.pi * np.outer(k, j) / (n + 1)) * np.where(j == 0, 1.0, 2.0)[None, :]
         y = np.moveaxis(np.tensordot(C, y, axes=([1], [ax])), 0, ax)
     return y
 
 
 def tau_precond_apply(G, v, floor_rel=1e-12):
-    """tau(T)^{-1} v = (2/(n+1))^d S..S diag(1/lam) S..S v with the dense sine
-    matrices (S^2 = (n+1)/2 I); lam floored at floor_rel * max lam."""
+    """tau(T)^{-1} v = prod_s (2/(n_s+1)) S..S diag(1/lam) S..S v with the
+    dense sine matrices (S_s^2 = (n_s+1)/2 I) on v's grid (the cube's or a
+    box's); lam floored at floor_rel * max lam."""
     d = G.ndim
-    n = G.shape[0] - 2
-    lam = tau_symbol(G)
+    shp = grid_shape(G, v.shape)
+    lam = tau_symbol(G, shp)
     lam = np.maximum(lam, floor_rel * lam.max())
-    k = np.arange(1, n + 1)
-    S = np.sin(np.pi * np.outer(k, k) / (n + 1))
+    Ss = []
+    for n in shp:
+        k = np.arange(1, n + 1)
+        Ss.append(np.sin(np.pi * np.outer(k, k) / (n + 1)))
     y = np.array(v, dtype=np.float64)
     for ax in range(d):
-        y = np.moveaxis(np.tensordot(S, y, axes=([1], [ax])), 0, ax)
+        y = np.moveaxis(np.tensordot(Ss[ax], y, axes=([1], [ax])), 0, ax)
     y = y / lam
     for ax in range(d):
-        y = np.moveaxis(np.tensordot(S, y, axes=([1], [ax])), 0, ax)
-    return y * (2.0 / (n + 1)) ** d
+        y = np.moveaxis(np.tensordot(Ss[ax], y, axes=([1], [ax])), 0, ax)
+    return y * np.prod([2.0 / (n + 1) for n in shp])
 
 
 def exterior_lattice_1d(G, g):

@@ -18,8 +18,8 @@ def solve_cholesky(G, f):
     """u = A^{-1} f by Cholesky of the materialised A (f may carry RHS as
     trailing axes beyond the grid axes)."""
     d = G.ndim
-    A = dense_matrix(G)
     shp = f.shape
+    A = dense_matrix(G, shp[:d])   # the grid: f's first d axes (cube or box)
     fb = f.reshape((A.shape[0], -1)) if f.ndim > d else f.reshape(-1)
     u = cho_solve(cho_factor(A), fb)
     return u.reshape(shp)

@@ -571,3 +571,78 @@ def test_gamma_convergence_rate(alpha, p):
         errs.append(np.abs(y - exact.frac_lap_ball_power(x * x, s, alpha, 1)).max())
     rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
     assert all(abs(r - (2.0 - alpha)) <= 0.05 for r in rates), rates
+
+
+# ---------------------------------------------------------------------------
+# boxes (Sec. 2.2: Upsilon = [0, L]^d with L the longest side, N_s <= N
+# intervals on axis s): the cube's generator on the box's interior points
+# ---------------------------------------------------------------------------
+
+BOXES = [(2, 12, (11, 5)), (2, 8, (3, 7)), (3, 6, (5, 2, 4)), (1, 10, (6,))]
+
+
+@pytest.mark.parametrize("d,N,shape", BOXES)
+def test_box_matrix_is_cube_matrix_restricted(d, N, shape):
+    """The box occupies the first n_s interior points of each axis of the
+    cube's grid (axis s spans (-1, -1 + N_s h)), so its matrix is the cube's
+    restricted to those rows and columns."""
+    G = oracle.generator(d, 1.1, 1, N)
+    A = oracle.dense_matrix(G)
+    n = N - 1
+    sel = np.ravel_multi_index(np.indices(shape).reshape(d, -1), (n,) * d)
+    np.testing.assert_array_equal(oracle.dense_matrix(G, shape), A[np.ix_(sel, sel)])
+    assert np.linalg.eigvalsh(oracle.dense_matrix(G, shape)).min() > 0.0
+
+
+@pytest.mark.parametrize("d,N,shape", BOXES)
+def test_box_products_agree(d, N, shape):
+    """Box products: materialised, block form, sampled rows and the per-axis
+    padded circulant embedding all give the same y."""
+    G = oracle.generator(d, 0.7, 2, N)
+    rng = np.random.default_rng(4)
+    u = rng.uniform(-1, 1, shape)
+    y = oracle.apply_dense(G, u)
+    np.testing.assert_allclose(oracle.apply_bttb(G, u), y, atol=1e-13 * np.abs(y).max())
+    rows = np.array([[0] * d, [s - 1 for s in shape]])
+    np.testing.assert_allclose(oracle.apply_rows(G, u, rows), y[tuple(rows.T)],
+                               atol=1e-13 * np.abs(y).max())
+    intervals = tuple(s + 1 for s in shape)
+    for M in (None, tuple(max(8, 1 << (2 * i - 1).bit_length()) for i in intervals)):
+        lam, _ = oracle.symbol(G, M, intervals)
+        z = np.zeros(lam.shape)
+        z[tuple(slice(0, s) for s in shape)] = u
+        yf = np.fft.ifftn(lam * lam.size * np.fft.fftn(z)).real[tuple(slice(0, s) for s in shape)]
+        np.testing.assert_allclose(yf, y, atol=1e-13 * np.abs(G).sum() * np.abs(u).max())
+
+
+def test_box_tau_is_tensor_tau_2d():
+    """2-level tau on a box: sum_ab t_ab tau_{n0}(B_a) (x) tau_{n1}(B_b), built
+    densely; tau_precond_apply inverts it."""
+    N, shape = 10, (9, 5)
+    G = oracle.generator(2, 1.3, 1, N)
+    n0, n1 = shape
+
+    def basis(n):
+        out = []
+        for a in range(n):
+            e = np.zeros(n)
+            e[a] = 1.0
+            out.append(_hankel_tau_1d(e))
+        return out
+
+    t0, t1 = basis(n0), basis(n1)
+    tau = sum(G[a, b] * np.kron(t0[a], t1[b]) for a in range(n0) for b in range(n1))
+    v = np.random.default_rng(6).uniform(-1, 1, shape)
+    z = oracle.tau_precond_apply(G, v)
+    np.testing.assert_allclose(tau @ z.reshape(-1), v.reshape(-1), atol=1e-10)
+
+
+@pytest.mark.parametrize("d,N,shape", BOXES)
+def test_box_pcg_matches_cholesky(d, N, shape):
+    G = oracle.generator(d, 1.4, 1, N)
+    f = np.random.default_rng(11).uniform(-1, 1, shape)
+    uc = oracle.solve_cholesky(G, f)
+    for P in (lambda v: oracle.tau_precond_apply(G, v), lambda v: oracle.precond_apply(G, v)):
+        u, it, rel = oracle.solve_cg(G, f, tol=1e-12, precond=P)
+        assert rel <= 1e-12
+        assert np.abs(u - uc).max() <= 1e-9 * np.abs(uc).max()
