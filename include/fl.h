@@ -98,24 +98,49 @@ fl_status fl_weights(int d, double alpha, int degree, double h, int kernel, doub
 fl_status fl_weights_gamma(int d, double alpha, int degree, double h, int kernel, double lambda,
                            double gamma, void *stream, fl_op *out);
 
+/*
+ * fl_weights_box -- the operator on a box (Sec. 2.2: Omega a product of
+ * intervals, Upsilon = [0, L]^d with L the longest side; N_1 = N on the
+ * longest axis and N_s the smallest integer whose N_s h covers side s).
+ * The longest axis spans (-1, 1), h = 2/N with N = max_s intervals[s],
+ * axis s spans (-1, -1 + intervals[s] h) and has intervals[s] - 1 interior
+ * points.  The weights, generator and far-field constant are those of the
+ * cube of side 2 (they depend on Upsilon, not on Omega); the matrix is the
+ * cube's restricted to the box's interior points.
+ *   intervals  host array of d ints, each in [2, N]; N = max in [4, 1024]
+ *   gamma      splitting parameter in (alpha, 2] (2: fl_weights)
+ * Other arguments and errors as fl_weights_gamma.  Vectors are row-major
+ * over n_0 x .. x n_{d-1} (n_s = intervals[s] - 1, last index fastest).
+ * The tau preconditioner needs every 2 intervals[s] to be a power of two
+ * (otherwise the default is kind 1); fl_exterior supports the cube only.
+ */
+fl_status fl_weights_box(int d, double alpha, int degree, const int *intervals, int kernel,
+                         double lambda, double gamma, void *stream, fl_op *out);
+
 /* Copy the FP64 generator G_k, k in {0..N}^d (row-major, (N+1)^d values),
  * to host memory.  count must be >= (N+1)^d.  Test hook. */
 fl_status fl_generator(fl_op A, double *host_out, size_t count);
 
-/* Copy the folded FP64 symbol lambda-hat_k, k in {0..M/2}^d ((M/2+1)^d
- * values; N + 1 per axis when M = 2N).  The full symbol on {0..M-1}^d is
- * even: lambda-hat_j = lambda-hat_{min(j, M-j)}. */
+/* Copy the folded FP64 symbol lambda-hat_k, k_s in {0..M_s/2} (prod_s
+ * (M_s/2 + 1) values; N + 1 per axis when M = 2N).  The full symbol on
+ * prod {0..M_s-1} is even: lambda-hat_j = lambda-hat_{min(j_s, M_s-j_s)}. */
 fl_status fl_symbol(fl_op A, double *host_out, size_t count);
 
-/* Copy the circulant embedding c_j, j in {0..M-1}^d, of the generator as
- * laid out on the device: c_j = G_{m(j)}, m(j_s) = min(j_s, M - j_s), zero
- * where some m(j_s) > N-2.  count >= M^d.  Test hook for the index maps. */
+/* Copy the circulant embedding c_j, j_s in {0..M_s-1}, of the generator as
+ * laid out on the device: c_j = G_{m(j)}, m(j_s) = min(j_s, M_s - j_s),
+ * zero where some m(j_s) > N_s - 2.  count >= prod M_s.  Test hook for the
+ * index maps. */
 fl_status fl_embedding(fl_op A, double *host_out, size_t count);
 
 /* Geometry of A: dimension, intervals N, interior points per axis n = N-1,
  * embedding length M (the smallest power of two >= 2N).  Any pointer may
  * be NULL. */
 fl_status fl_query(fl_op A, int *d, int *N, int *n, int *M);
+
+/* Per-axis geometry of A (d entries each): intervals N_s, interior points
+ * n_s = N_s - 1, embedding lengths M_s (the smallest power of two >= 2 N_s).
+ * fl_query reports axis 0.  Any pointer may be NULL. */
+fl_status fl_query_axes(fl_op A, int *intervals, int *n, int *M);
 
 /*
  * fl_apply -- y = A u for nrhs right-hand sides (the g = 0 operator; the

@@ -26,32 +26,51 @@ def _stream_ptr(stream):
 
 
 class Operator:
-    """The discrete operator A (g = 0 part of (-Delta)^{alpha/2}_h) on (-1,1)^d.
+    """The discrete operator A (g = 0 part of (-Delta)^{alpha/2}_h) on (-1,1)^d,
+    or with box=(N_0, .., N_{d-1}) on the box whose longest axis spans (-1, 1)
+    with N = max N_s intervals and axis s has N_s.
 
-    Built on the current CUDA/HIP device by fl_weights_gamma (splitting
-    parameter gamma in (alpha, 2], default 2).  Vectors are torch
-    tensors on that device holding nrhs * n^d values (any shape with that
-    many elements, contiguous)."""
+    Built on the current CUDA/HIP device by fl_weights_gamma / fl_weights_box
+    (splitting parameter gamma in (alpha, 2], default 2).  Vectors are torch
+    tensors on that device holding nrhs * prod(n_s) values (any shape with
+    that many elements, contiguous; row-major over `shape`)."""
 
     def __init__(self, d, alpha, degree, N=None, h=None, kernel="fractional", lam=0.0,
-                 stream=None, gamma=2.0):
-        if h is None:
-            if N is None:
-                raise ValueError("give N or h")
-            h = 2.0 / N
+                 stream=None, gamma=2.0, box=None):
         kind = {"fractional": FL_KERNEL_FRACTIONAL, "tempered": FL_KERNEL_TEMPERED}[kernel]
         self._h = ctypes.c_void_p()
         self._lib = lib()
-        check(self._lib.fl_weights_gamma(int(d), float(alpha), int(degree), float(h), kind,
-                                         float(lam), float(gamma), _stream_ptr(stream),
-                                         ctypes.byref(self._h)))
+        if box is not None:
+            if len(box) != d:
+                raise ValueError("box needs d interval counts")
+            arr = (ctypes.c_int * 3)(*[int(b) for b in box])
+            check(self._lib.fl_weights_box(int(d), float(alpha), int(degree), arr, kind,
+                                           float(lam), float(gamma), _stream_ptr(stream),
+                                           ctypes.byref(self._h)))
+        else:
+            if h is None:
+                if N is None:
+                    raise ValueError("give N or h")
+                h = 2.0 / N
+            check(self._lib.fl_weights_gamma(int(d), float(alpha), int(degree), float(h), kind,
+                                             float(lam), float(gamma), _stream_ptr(stream),
+                                             ctypes.byref(self._h)))
         q = [ctypes.c_int() for _ in range(4)]
         check(self._lib.fl_query(self._h, *[ctypes.byref(x) for x in q]))
-        self.d, self.N, self.n, self.M = (x.value for x in q)
+        self.d, self.N = q[0].value, q[1].value
+        ax = [(ctypes.c_int * 3)() for _ in range(3)]
+        check(self._lib.fl_query_axes(self._h, *ax))
+        self.intervals = tuple(ax[0][s] for s in range(self.d))
+        self.shape = tuple(ax[1][s] for s in range(self.d))      # interior points per axis
+        self.Ms = tuple(ax[2][s] for s in range(self.d))         # embedding length per axis
+        self.M = max(self.Ms)
+        self.n = self.shape[0] if len(set(self.shape)) == 1 else None
         self.alpha, self.degree, self.kernel, self.lam = float(alpha), int(degree), kernel, lam
         self.gamma = float(gamma)
-        self.nd = self.n ** self.d
-        self.precond_kind = 2 if self.M == 2 * self.N else 1
+        self.nd = 1
+        for v in self.shape:
+            self.nd *= v
+        self.precond_kind = 2 if all(m == 2 * i for m, i in zip(self.Ms, self.intervals)) else 1
 
     # -- host copies (test hooks) ------------------------------------------
     def _host(self, fn, count):
@@ -65,12 +84,18 @@ class Operator:
             (self.N + 1,) * self.d)
 
     def symbol(self):
-        """Folded symbol lambda-hat on [0, M/2]^d (M/2 + 1 = N + 1 when M = 2N)."""
-        h = self.M // 2 + 1
-        return self._host(self._lib.fl_symbol, h ** self.d).reshape((h,) * self.d)
+        """Folded symbol lambda-hat on prod [0, M_s/2] (N + 1 per axis when M = 2N)."""
+        shp = tuple(m // 2 + 1 for m in self.Ms)
+        cnt = 1
+        for v in shp:
+            cnt *= v
+        return self._host(self._lib.fl_symbol, cnt).reshape(shp)
 
     def embedding(self):
-        return self._host(self._lib.fl_embedding, self.M ** self.d).reshape((self.M,) * self.d)
+        cnt = 1
+        for v in self.Ms:
+            cnt *= v
+        return self._host(self._lib.fl_embedding, cnt).reshape(self.Ms)
 
     # -- compute ----------------------------------------------------------------
     def _nrhs(self, t):

@@ -52,6 +52,11 @@ _SIGS = {
     "fl_symbol": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t]),
     "fl_embedding": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.c_size_t]),
     "fl_query": (ctypes.c_int, [_P] + [ctypes.POINTER(ctypes.c_int)] * 4),
+    "fl_query_axes": (ctypes.c_int, [_P] + [ctypes.POINTER(ctypes.c_int)] * 3),
+    "fl_weights_box": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                      ctypes.c_double, ctypes.c_double, _P,
+                                      ctypes.POINTER(_P)]),
     "fl_apply": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, _P]),
     "fl_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_int, ctypes.c_int, _P,
                                 ctypes.c_int, ctypes.POINTER(FlInfo), _P]),

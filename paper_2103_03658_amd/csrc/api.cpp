@@ -133,8 +133,7 @@ struct fl_op_s {
   double* linv64 = nullptr;   // preconditioner multiplier 1/lambda-hat (floored)
   float* linv32 = nullptr;
   int precond = 2;            // 0 plain CG, 1 circulant, 2 tau preconditioner
-  const void* tw64 = nullptr;
-  const void* tw32 = nullptr;
+  fl::Twiddles tw64{}, tw32{};   // per axis
   fl::Schedule sc64{}, sc32{};  // transform passes of the product A u
   fl::Schedule sp64{}, sp32{};  // transform passes of the preconditioner
   double delta = 1e-5;      // reliable-update trigger (mixed = 1)
@@ -182,17 +181,19 @@ static size_t line_bytes(int M, int E, bool fp32) {
   return (size_t)2 * (M + M / E) * (fp32 ? 4 : 8);
 }
 
+// E_first / W_first drive the axis-0 passes (length Ma[0]), E_c2c / W_c2c
+// the 3D axis-1 passes (Ma[1]), E_mid / LPB_mid the last axis (Ma[d-1]).
 bool schedule_ok(const Geometry& g, const Schedule& s, bool fp32) {
-  auto ok = [&](int E, int W, bool tiled) {
-    if (!(E == 8 || E == 16 || E == 32) || E > g.M) return false;
+  auto ok = [&](int M, int E, int W, bool tiled) {
+    if (!(E == 8 || E == 16 || E == 32) || E > M) return false;
     if (W < 1 || (tiled && !pow2(W))) return false;
-    if ((long)W * (g.M / E) > 512) return false;
-    const size_t b = tiled ? tile_lds(g.M, E, W, fp32 ? 4 : 8).bytes : line_bytes(g.M, E, fp32) * W;
+    if ((long)W * (M / E) > 512) return false;
+    const size_t b = tiled ? tile_lds(M, E, W, fp32 ? 4 : 8).bytes : line_bytes(M, E, fp32) * W;
     if (b > kMaxLds - 1024) return false;  // room for static LDS
     return true;
   };
-  return ok(s.E_first, s.W_first, true) && ok(s.E_mid, s.LPB_mid, false) &&
-         ok(s.E_c2c, s.W_c2c, true);
+  return ok(g.Ma[0], s.E_first, s.W_first, true) && ok(g.Ma[g.d - 1], s.E_mid, s.LPB_mid, false) &&
+         ok(g.d == 3 ? g.Ma[1] : g.Ma[0], s.E_c2c, s.W_c2c, true);
 }
 
 // Starting schedule before tuning: radix-16 register stages (radix 32 in the
@@ -200,23 +201,25 @@ bool schedule_ok(const Geometry& g, const Schedule& s, bool fp32) {
 // LDS, and as many lines per block as that allows (wider column tiles in the
 // strided passes).
 Schedule default_schedule(const Geometry& g, bool fp32) {
-  const int M = g.M;
-  auto pickE = [&](int want) { return std::min(want, M); };
-  Schedule s{};
-  const int e = fp32 && M >= 512 ? 32 : (M >= 256 ? 16 : 8);
-  s.E_first = pickE(e);
-  s.E_mid = pickE(std::min(e, 16));
-  s.E_c2c = pickE(e);
-  auto fitW = [&](int E, int want) {
+  auto pickE = [&](int M, int cap) {
+    const int e = fp32 && M >= 512 ? 32 : (M >= 256 ? 16 : 8);
+    return std::min(std::min(e, cap), M);
+  };
+  auto fitW = [&](int M, int E, int want) {
     const int tpl = M / E;
     int w = std::max(1, std::min(want, 256 / std::max(1, tpl)));
     w = 1 << ilog2i(w + 1) >> 1;   // largest power of two <= w
     while (w > 1 && tile_lds(M, E, w, fp32 ? 4 : 8).bytes > 96 * 1024) w /= 2;
     return w;
   };
-  s.W_first = fitW(s.E_first, 16);
-  s.W_c2c = fitW(s.E_c2c, 16);
-  s.LPB_mid = fitW(s.E_mid, 64);
+  const int M0 = g.Ma[0], Ml = g.Ma[g.d - 1], M1 = g.d == 3 ? g.Ma[1] : g.Ma[0];
+  Schedule s{};
+  s.E_first = pickE(M0, 32);
+  s.E_mid = pickE(Ml, 16);
+  s.E_c2c = pickE(M1, 32);
+  s.W_first = fitW(M0, s.E_first, 16);
+  s.W_c2c = fitW(M1, s.E_c2c, 16);
+  s.LPB_mid = fitW(Ml, s.E_mid, 64);
   return s;
 }
 
@@ -260,86 +263,123 @@ fl_status fl_weights(int d, double alpha, int degree, double h, int kernel, doub
   return fl_weights_gamma(d, alpha, degree, h, kernel, lambda, 2.0, stream, out);
 }
 
+// Operator setup shared by the cube (fl_weights_gamma) and the box
+// (fl_weights_box): generator on {0..N}^d with h = 2/N, grid of Nax[s]
+// intervals along axis s.
+static fl_status create_op(int d, double alpha, int degree, int N, const int* Nax, int kernel,
+                           double lambda, double gamma, void* stream, fl_op* out) {
+  if (!(gamma > alpha && gamma <= 2.0)) return fail(FL_E_INVAL, "gamma must lie in (alpha, 2]");
+  if (N < 4) return fail(FL_E_INVAL, "N = 2/h must be >= 4");
+  if (degree == 2 && N % 2) return fail(FL_E_INVAL, "degree 2 needs N even");
+  if (N > 1024) return fail(FL_E_UNSUPPORTED, "N must be at most 1024 (embedding M <= 2048)");
+  // embedding length per axis: any M >= 2 Na - 3 makes the restricted
+  // circulant product exact; the transforms take powers of two (8..2048),
+  // and the tau preconditioner's sine transforms need M = 2 Na exactly
+  int Ma[3] = {1, 1, 1};
+  for (int s = 0; s < d; ++s) {
+    if (Nax[s] < 2 || Nax[s] > N) return fail(FL_E_INVAL, "box intervals must lie in [2, N]");
+    Ma[s] = 8;
+    while (Ma[s] < 2 * Nax[s]) Ma[s] *= 2;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  fl_op A = new fl_op_s();
+  try {
+    FL_HIP(hipGetDevice(&A->device));
+    A->g.d = d;
+    A->g.N = N;
+    A->g.nd = 1;
+    for (int s = 0; s < 3; ++s) {
+      const bool on = s < d;
+      A->g.Na[s] = on ? Nax[s] : 2;
+      A->g.na[s] = on ? Nax[s] - 1 : 1;
+      A->g.Ma[s] = on ? Ma[s] : 1;
+      A->g.Ha[s] = on ? Ma[s] / 2 + 1 : 1;
+      A->g.nd *= A->g.na[s];
+    }
+    A->precond = A->g.sine_ok() ? 2 : 1;
+    A->degree = degree;
+    A->kernel = kernel;
+    A->alpha = alpha;
+    A->h = 2.0 / N;
+    A->lambda = kernel == FL_KERNEL_TEMPERED ? lambda : 0.0;
+    // c_{d,alpha} = 2^{alpha-1} alpha Gamma((d+alpha)/2) / (pi^{d/2} Gamma(1-alpha/2))
+    A->c = std::pow(2.0, alpha - 1.0) * alpha * std::tgamma((d + alpha) / 2.0) /
+           (std::pow(M_PI, d / 2.0) * std::tgamma(1.0 - alpha / 2.0));
+    long nf = 1;
+    for (int s = 0; s < d; ++s) nf *= (N + 1);
+    const long nh = A->g.nh();
+    A->G = (double*)dmalloc((size_t)nf * sizeof(double));
+    A->lam64 = (double*)dmalloc((size_t)nh * sizeof(double));
+    A->lam32 = (float*)dmalloc((size_t)nh * sizeof(float));
+    A->linv64 = (double*)dmalloc((size_t)nh * sizeof(double));
+    A->linv32 = (float*)dmalloc((size_t)nh * sizeof(float));
+    fl::GenParams gp{d, degree, N, kernel, alpha, A->h, A->lambda, A->c, gamma};
+    fl::build_generator(gp, A->G, st);
+    fl::build_symbol(A->g, A->G, A->lam64, A->lam32, st);
+    {
+      double* scr = (double*)dmalloc(256);
+      fl::build_inverse_symbol(A->g, A->lam64, nh, A->linv64, A->linv32, scr, st);
+      FL_HIP(hipStreamSynchronize(st));
+      hipFree(scr);
+    }
+    for (int s = 0; s < 3; ++s) {
+      const int M = A->g.Ma[s >= d ? 0 : s];
+      A->tw64.ax[s] = fl::twiddles(M, false, st);
+      A->tw32.ax[s] = fl::twiddles(M, true, st);
+    }
+    A->sc64 = fl::default_schedule(A->g, false);
+    A->sc32 = fl::default_schedule(A->g, true);
+    A->sp64 = A->sc64;
+    A->sp32 = A->sc32;
+    FL_HIP(hipEventCreateWithFlags(&A->done, hipEventDisableTiming));
+    FL_HIP(hipStreamSynchronize(st));
+  } catch (...) {
+    fl_destroy(A);
+    throw;
+  }
+  *out = A;
+  return FL_OK;
+}
+
+static fl_status check_common(int d, double alpha, int degree, int kernel, double lambda,
+                              fl_op* out) {
+  if (!out) return fail(FL_E_INVAL, "out is NULL");
+  if (d < 1 || d > 3) return fail(FL_E_INVAL, "d must be 1, 2 or 3");
+  if (!(alpha > 0.0 && alpha < 2.0)) return fail(FL_E_INVAL, "alpha must lie in (0, 2)");
+  if (degree < 0 || degree > 2) return fail(FL_E_INVAL, "degree must be 0, 1 or 2");
+  if (kernel != FL_KERNEL_FRACTIONAL && kernel != FL_KERNEL_TEMPERED)
+    return fail(FL_E_INVAL, "unknown kernel");
+  if (kernel == FL_KERNEL_TEMPERED && (!(lambda >= 0.0) || !std::isfinite(lambda)))
+    return fail(FL_E_INVAL, "lambda must be finite and >= 0");
+  return FL_OK;
+}
+
 fl_status fl_weights_gamma(int d, double alpha, int degree, double h, int kernel, double lambda,
                            double gamma, void* stream, fl_op* out) {
   return guarded([&]() -> fl_status {
-    if (!out) return fail(FL_E_INVAL, "out is NULL");
-    if (d < 1 || d > 3) return fail(FL_E_INVAL, "d must be 1, 2 or 3");
-    if (!(alpha > 0.0 && alpha < 2.0)) return fail(FL_E_INVAL, "alpha must lie in (0, 2)");
-    if (!(gamma > alpha && gamma <= 2.0)) return fail(FL_E_INVAL, "gamma must lie in (alpha, 2]");
-    if (degree < 0 || degree > 2) return fail(FL_E_INVAL, "degree must be 0, 1 or 2");
+    const fl_status e = check_common(d, alpha, degree, kernel, lambda, out);
+    if (e != FL_OK) return e;
     if (!(h > 0.0) || !std::isfinite(h)) return fail(FL_E_INVAL, "h must be positive");
-    if (kernel != FL_KERNEL_FRACTIONAL && kernel != FL_KERNEL_TEMPERED)
-      return fail(FL_E_INVAL, "unknown kernel");
-    if (kernel == FL_KERNEL_TEMPERED && (!(lambda >= 0.0) || !std::isfinite(lambda)))
-      return fail(FL_E_INVAL, "lambda must be finite and >= 0");
     const double Nf = 2.0 / h;
     const double Nr = std::round(Nf);
     if (!(Nr >= 1.0) || std::fabs(Nf - Nr) > 1e-12 * Nr)
       return fail(FL_E_INVAL, "2/h must be an integer");
     if (Nr > 1e6) return fail(FL_E_UNSUPPORTED, "N too large");
     const int N = (int)Nr;
-    if (N < 4) return fail(FL_E_INVAL, "N = 2/h must be >= 4");
-    if (degree == 2 && N % 2) return fail(FL_E_INVAL, "degree 2 needs N even");
-    // embedding length: any M >= 2N - 3 makes the restricted circulant product
-    // exact; the transforms take powers of two up to 2048, and the tau
-    // preconditioner's sine transforms need M = 2N exactly
-    int M = 8;
-    while (M < 2 * N) M *= 2;
-    if (M > 2048) return fail(FL_E_UNSUPPORTED, "N must be at most 1024 (embedding M <= 2048)");
-    hipStream_t st = (hipStream_t)stream;
-    fl_op A = new fl_op_s();
-    try {
-      FL_HIP(hipGetDevice(&A->device));
-      A->g.d = d;
-      A->g.N = N;
-      A->g.n = N - 1;
-      A->g.M = M;
-      A->g.H = M / 2 + 1;
-      A->precond = M == 2 * N ? 2 : 1;
-      A->g.nd = 1;
-      for (int s = 0; s < d; ++s) A->g.nd *= (N - 1);
-      A->degree = degree;
-      A->kernel = kernel;
-      A->alpha = alpha;
-      A->h = 2.0 / N;
-      A->lambda = kernel == FL_KERNEL_TEMPERED ? lambda : 0.0;
-      // c_{d,alpha} = 2^{alpha-1} alpha Gamma((d+alpha)/2) / (pi^{d/2} Gamma(1-alpha/2))
-      A->c = std::pow(2.0, alpha - 1.0) * alpha * std::tgamma((d + alpha) / 2.0) /
-             (std::pow(M_PI, d / 2.0) * std::tgamma(1.0 - alpha / 2.0));
-      long nf = 1, nh = 1;
-      for (int s = 0; s < d; ++s) {
-        nf *= (N + 1);
-        nh *= A->g.H;
-      }
-      A->G = (double*)dmalloc((size_t)nf * sizeof(double));
-      A->lam64 = (double*)dmalloc((size_t)nh * sizeof(double));
-      A->lam32 = (float*)dmalloc((size_t)nh * sizeof(float));
-      A->linv64 = (double*)dmalloc((size_t)nh * sizeof(double));
-      A->linv32 = (float*)dmalloc((size_t)nh * sizeof(float));
-      fl::GenParams gp{d, degree, N, kernel, alpha, A->h, A->lambda, A->c, gamma};
-      fl::build_generator(gp, A->G, st);
-      fl::build_symbol(A->g, A->G, A->lam64, A->lam32, st);
-      {
-        double* scr = (double*)dmalloc(256);
-        fl::build_inverse_symbol(A->g, A->lam64, nh, A->linv64, A->linv32, scr, st);
-        FL_HIP(hipStreamSynchronize(st));
-        hipFree(scr);
-      }
-      A->tw64 = fl::twiddles(M, false, st);
-      A->tw32 = fl::twiddles(M, true, st);
-      A->sc64 = fl::default_schedule(A->g, false);
-      A->sc32 = fl::default_schedule(A->g, true);
-      A->sp64 = A->sc64;
-      A->sp32 = A->sc32;
-      FL_HIP(hipEventCreateWithFlags(&A->done, hipEventDisableTiming));
-      FL_HIP(hipStreamSynchronize(st));
-    } catch (...) {
-      fl_destroy(A);
-      throw;
-    }
-    *out = A;
-    return FL_OK;
+    const int Nax[3] = {N, N, N};
+    return create_op(d, alpha, degree, N, Nax, kernel, lambda, gamma, stream, out);
+  });
+}
+
+fl_status fl_weights_box(int d, double alpha, int degree, const int* intervals, int kernel,
+                         double lambda, double gamma, void* stream, fl_op* out) {
+  return guarded([&]() -> fl_status {
+    const fl_status e = check_common(d, alpha, degree, kernel, lambda, out);
+    if (e != FL_OK) return e;
+    if (!intervals) return fail(FL_E_INVAL, "intervals is NULL");
+    int N = 0;
+    for (int s = 0; s < d; ++s) N = std::max(N, intervals[s]);
+    return create_op(d, alpha, degree, N, intervals, kernel, lambda, gamma, stream, out);
   });
 }
 
@@ -377,8 +417,18 @@ fl_status fl_query(fl_op A, int* d, int* N, int* n, int* M) {
   if (!A) return fail(FL_E_INVAL, "null handle");
   if (d) *d = A->g.d;
   if (N) *N = A->g.N;
-  if (n) *n = A->g.n;
-  if (M) *M = A->g.M;
+  if (n) *n = A->g.na[0];
+  if (M) *M = A->g.Ma[0];
+  return FL_OK;
+}
+
+fl_status fl_query_axes(fl_op A, int* intervals, int* n, int* M) {
+  if (!A) return fail(FL_E_INVAL, "null handle");
+  for (int s = 0; s < A->g.d; ++s) {
+    if (intervals) intervals[s] = A->g.Na[s];
+    if (n) n[s] = A->g.na[s];
+    if (M) M[s] = A->g.Ma[s];
+  }
   return FL_OK;
 }
 
@@ -404,8 +454,7 @@ fl_status fl_generator(fl_op A, double* host_out, size_t count) {
 fl_status fl_symbol(fl_op A, double* host_out, size_t count) {
   return guarded([&]() -> fl_status {
     if (!A) return fail(FL_E_INVAL, "null handle");
-    size_t nf = 1;
-    for (int s = 0; s < A->g.d; ++s) nf *= (size_t)A->g.H;
+    const size_t nf = (size_t)A->g.nh();
     return copy_out(A, A->lam64, host_out, count, nf, sizeof(double));
   });
 }
@@ -413,8 +462,7 @@ fl_status fl_symbol(fl_op A, double* host_out, size_t count) {
 fl_status fl_embedding(fl_op A, double* host_out, size_t count) {
   return guarded([&]() -> fl_status {
     if (!A || !host_out) return fail(FL_E_INVAL, "null argument");
-    size_t nm = 1;
-    for (int s = 0; s < A->g.d; ++s) nm *= (size_t)A->g.M;
+    const size_t nm = (size_t)A->g.nm();
     if (count < nm) return fail(FL_E_INVAL, "output buffer too small");
     set_device(A);
     double* tmp = (double*)dmalloc(nm * sizeof(double));
@@ -457,8 +505,9 @@ fl_status fl_set_precond_schedule(fl_op A, int fp32, int e_first, int e_mid, int
 fl_status fl_set_preconditioner(fl_op A, int kind) {
   if (!A) return fail(FL_E_INVAL, "null handle");
   if (kind < 0 || kind > 2) return fail(FL_E_INVAL, "kind must be 0, 1 or 2");
-  if (kind == 2 && A->g.M != 2 * A->g.N)
-    return fail(FL_E_UNSUPPORTED, "the tau preconditioner needs 2N to be a power of two");
+  if (kind == 2 && !A->g.sine_ok())
+    return fail(FL_E_UNSUPPORTED,
+                "the tau preconditioner needs 2 N_s to be a power of two on every axis");
   A->precond = kind;
   return FL_OK;
 }
@@ -853,7 +902,7 @@ inline std::vector<double> sched_key(const fl::Schedule& s) {
 // circulant (kind 1, zero-padded passes) or the inverse of the tau
 // approximation (kind 2, odd-extended passes); `linv` is its multiplier.
 template <typename T>
-void precond_apply(fl_op A, const T* linv, const void* tw, const T* r, T* z, int nrhs, void* ws,
+void precond_apply(fl_op A, const T* linv, const fl::Twiddles& tw, const T* r, T* z, int nrhs, void* ws,
                    const fl::CgScalars& cg, const int* active, hipStream_t st) {
   fl::apply_passes<T>(A->g, pc_sched<T>(A), linv, tw, r, z, nrhs, ws, st, fl::PM_DOT, nullptr,
                       nullptr, nullptr, &cg, active, nullptr, -1, A->precond == 2);
@@ -861,7 +910,7 @@ void precond_apply(fl_op A, const T* linv, const void* tw, const T* r, T* z, int
 
 // CG start: x = 0, r = rhs, p = 0; preconditioned: z = P r.
 template <typename T>
-void cg_start(fl_op A, const fl::Schedule& sc, const T* linv, const void* tw, const T* rhs,
+void cg_start(fl_op A, const fl::Schedule& sc, const T* linv, const fl::Twiddles& tw, const T* rhs,
               T* x, T* r, T* p, T* z, int nrhs, const fl::CgScalars& cg,
               const int* outer_active, void* ws, hipStream_t st) {
   fl::fill_int(cg.n_active, 0, 1, st);
@@ -871,7 +920,7 @@ void cg_start(fl_op A, const fl::Schedule& sc, const T* linv, const void* tw, co
 
 // One CG (or preconditioned CG) iteration for all active right-hand sides.
 template <typename T>
-void cg_iteration(fl_op A, const fl::Schedule& sc, const T* lam, const T* linv, const void* tw,
+void cg_iteration(fl_op A, const fl::Schedule& sc, const T* lam, const T* linv, const fl::Twiddles& tw,
                   T* x, T* r, T* p, T* q, T* z, int nrhs, const fl::CgScalars& cg, void* ws,
                   hipStream_t st) {
   fl::apply_passes<T>(A->g, sc, lam, tw, nullptr, q, nrhs, ws, st, fl::PM_CG,
@@ -884,7 +933,7 @@ void cg_iteration(fl_op A, const fl::Schedule& sc, const T* lam, const T* linv, 
 // number of active right-hand sides is read back every `chunk` iterations
 // (one 4-byte copy); masked launches past convergence cost only launch time.
 template <typename T>
-void cg_run(fl_op A, const fl::Schedule& sc, const T* lam, const T* linv, const void* tw,
+void cg_run(fl_op A, const fl::Schedule& sc, const T* lam, const T* linv, const fl::Twiddles& tw,
             const T* rhs, T* x, T* r, T* p, T* q, T* z, int nrhs, const fl::CgScalars& cg,
             const int* outer_active, void* ws, hipStream_t st) {
   cg_start<T>(A, sc, linv, tw, rhs, x, r, p, z, nrhs, cg, outer_active, ws, st);

@@ -109,12 +109,13 @@ void difference(const double* a, const double* b, double* out, long n, hipStream
 }
 
 bool exterior_supported(const Geometry& g) {
-  return g.d == 1 || (g.d == 2 && 2 * g.M <= 2048);
+  // the cube only (the exterior lattice of a box is not built)
+  return g.cube() && (g.d == 1 || (g.d == 2 && 2 * g.Ma[0] <= 2048));
 }
 
 size_t exterior_khat_bytes(const Geometry& g) {
   if (g.d != 2) return 0;
-  const long P = 2L * g.M;
+  const long P = 2L * g.Ma[0];
   return (size_t)P * P * sizeof(cx<double>);
 }
 
@@ -134,7 +135,8 @@ void exterior_term(const Geometry& g, const double* G, double c, const double* g
     return;
   }
   if (d != 2) throw Error(2, "exterior data: d = 3 is not supported");
-  const int P = 2 * g.M;
+  const int P = 2 * g.Ma[0];
+  const int Pd[3] = {P, P, P};
   const long total = (long)P * P;
   cx<double>* K = reinterpret_cast<cx<double>*>(khat);
   cx<double>* D = reinterpret_cast<cx<double>*>(work);
@@ -142,17 +144,17 @@ void exterior_term(const Geometry& g, const double* G, double c, const double* g
     hipLaunchKernelGGL(k_wrap_generator, dim3(blocks(total, thr)), dim3(thr), 0, st, G, d, N, P,
                        total, K);
     check_launch("wrap generator");
-    fft_full(P, d, K, -1, st);
+    fft_full(Pd, d, K, -1, st);
   }
   const double scale = 1.0 / (double)total;
   for (int o = 0; o < nrhs; ++o) {
     hipLaunchKernelGGL(k_place_exterior, dim3(blocks(total, thr)), dim3(thr), 0, st,
                        g_lat + (long)o * L * L, d, N, P, total, D);
     check_launch("place exterior data");
-    fft_full(P, d, D, -1, st);
+    fft_full(Pd, d, D, -1, st);
     hipLaunchKernelGGL(k_mul_spectra, dim3(blocks(total, thr)), dim3(thr), 0, st, D, K, total);
     check_launch("spectra product");
-    fft_full(P, d, D, 1, st);
+    fft_full(Pd, d, D, 1, st);
     hipLaunchKernelGGL(k_take_interior, dim3(blocks(nd, thr)), dim3(thr), 0, st, D, d, N, P, nd,
                        scale, tail ? tail + (long)o * nd : nullptr, c, b + (long)o * nd);
     check_launch("interior restriction");

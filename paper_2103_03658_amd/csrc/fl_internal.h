@@ -75,14 +75,38 @@ enum PassMode {
   PM_DOT = 3,       // y = A u and partials of u.y into `part` (preconditioner r.z)
 };
 
-// Geometry of one operator application.
+// Geometry of one operator application.  The generator lives on the cube
+// {0..N}^d (h = 2/N, the longest axis spans (-1, 1)); axis s of the grid has
+// Na[s] <= N intervals (a box; Na[s] = N for the cube) and n_s = Na[s] - 1
+// interior points.  Entries beyond d are 1 (na, Ma, Ha) so products over all
+// three axes hold.
 struct Geometry {
   int d;       // 1, 2, 3
-  int N;       // intervals per axis
-  int n;       // interior points per axis = N - 1
-  int M;       // embedding length per axis: the smallest power of two >= 2N
-  int H;       // folded symbol length per axis = M/2 + 1 (N + 1 when M = 2N)
-  long nd;     // n^d
+  int N;       // generator intervals per axis
+  int Na[3];   // intervals of axis s
+  int na[3];   // interior points of axis s = Na[s] - 1
+  int Ma[3];   // embedding length of axis s: the smallest power of two >= 2 Na[s]
+  int Ha[3];   // folded symbol length of axis s = Ma[s]/2 + 1
+  long nd;     // prod_s na[s]
+  bool cube() const {
+    for (int s = 1; s < d; ++s)
+      if (Na[s] != Na[0]) return false;
+    return true;
+  }
+  // the tau preconditioner's sine transforms need Ma[s] = 2 Na[s]
+  bool sine_ok() const {
+    for (int s = 0; s < d; ++s)
+      if (Ma[s] != 2 * Na[s]) return false;
+    return true;
+  }
+  long nh() const { return (long)Ha[0] * Ha[1] * Ha[2]; }
+  long nm() const { return (long)Ma[0] * Ma[1] * Ma[2]; }
+};
+
+// Twiddle tables of one precision, one per axis (the axes' embedding lengths
+// may differ).
+struct Twiddles {
+  const void* ax[3];
 };
 
 // Launch schedule (tunable).
@@ -143,7 +167,7 @@ int vec_blocks(long nd, int nrhs);
 // their negated reflections), which with a real even symbol applies
 // S diag(.) S with S the sine transform of each axis (not with PM_CG).
 template <typename T>
-void apply_passes(const Geometry& g, const Schedule& sc, const T* lam, const void* tw,
+void apply_passes(const Geometry& g, const Schedule& sc, const T* lam, const Twiddles& tw,
                   const T* u, T* y, int nrhs, void* ws, hipStream_t st, int mode,
                   const T* rvec, T* pvec, const double* fvec, const CgScalars* cg,
                   const int* active, hipEvent_t* ev = nullptr, int only = -1,
@@ -176,9 +200,10 @@ void exterior_term(const Geometry& g, const double* G, double c, const double* g
                    const double* tail, double* b, int nrhs, void* khat, bool khat_ready,
                    void* work, hipStream_t st);
 
-// In-place unnormalised DFT (dir -1) or inverse (dir +1) of a P^d complex FP64
-// array (interleaved re, im), P a supported power of two.
-void fft_full(int P, int d, void* c, int dir, hipStream_t st);
+// In-place unnormalised DFT (dir -1) or inverse (dir +1) of a complex FP64
+// array of P[0] x .. x P[d-1] points (interleaved re, im, last index
+// fastest), each P[s] a supported power of two.
+void fft_full(const int* P, int d, void* c, int dir, hipStream_t st);
 void build_inverse_symbol(const Geometry& g, const double* lam64, long nf, double* inv64,
                           float* inv32, double* scratch, hipStream_t st);
 

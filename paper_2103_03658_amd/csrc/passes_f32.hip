@@ -5,7 +5,7 @@ namespace fl {
 
 template <>
 void apply_passes<float>(const Geometry& g, const Schedule& sc, const float* lam,
-                         const void* tw, const float* u, float* y, int nrhs, void* ws,
+                         const Twiddles& tw, const float* u, float* y, int nrhs, void* ws,
                          hipStream_t st, int mode, const float* rvec, float* pvec,
                          const double* fvec, const CgScalars* cg, const int* active,
                           hipEvent_t* ev, int only, bool odd) {

@@ -9,7 +9,7 @@ namespace fl {
 
 template <>
 void apply_passes<double>(const Geometry& g, const Schedule& sc, const double* lam,
-                          const void* tw, const double* u, double* y, int nrhs, void* ws,
+                          const Twiddles& tw, const double* u, double* y, int nrhs, void* ws,
                           hipStream_t st, int mode, const double* rvec, double* pvec,
                           const double* fvec, const CgScalars* cg, const int* active,
                           hipEvent_t* ev, int only, bool odd) {
@@ -22,7 +22,7 @@ size_t apply_workspace_bytes(const Geometry& g, int nrhs, bool fp32) {
 
 int last_pass_blocks(const Geometry& g, const Schedule& sc) {
   if (g.d == 1) return 1;
-  const long C0 = g.d == 2 ? (long)g.n : (long)g.n * g.n;
+  const long C0 = (long)g.na[1] * g.na[2];   // columns of the axis-0 passes
   return (int)pair_tiles(C0, sc.W_first);
 }
 
@@ -49,56 +49,73 @@ const void* twiddles(int M, bool fp32, hipStream_t st) {
   return p;
 }
 
-// c[j] = G[m(j)] with m(j_s) = min(j_s, M - j_s); zero where some m(j_s) > N-2.
-__device__ __forceinline__ double embed_value(const double* G, int d, int N, int M, long j) {
+// Sizes of the embedding: per axis the length Ma and the largest kept
+// offset Na - 2; the generator is indexed on {0..N}^d.
+struct EmbedDims {
+  int d, N;
+  int Na[3], Ma[3];
+};
+
+// c[j] = G[m(j)] with m(j_s) = min(j_s, Ma_s - j_s); zero where some
+// m(j_s) > Na_s - 2 (the interior product never reads those offsets).
+__device__ __forceinline__ double embed_value(const double* G, const EmbedDims& e, long j) {
   long rem = j;
   long gi = 0;
   bool keep = true;
   int idx[3] = {0, 0, 0};
-  for (int s = d - 1; s >= 0; --s) {  // last index fastest
-    idx[s] = (int)(rem % M);
-    rem /= M;
+  for (int s = e.d - 1; s >= 0; --s) {  // last index fastest
+    idx[s] = (int)(rem % e.Ma[s]);
+    rem /= e.Ma[s];
   }
-  for (int s = 0; s < d; ++s) {
-    const int m = idx[s] <= M - idx[s] ? idx[s] : M - idx[s];
-    keep = keep && (m <= N - 2);
-    gi = gi * (N + 1) + m;
+  for (int s = 0; s < e.d; ++s) {
+    const int m = idx[s] <= e.Ma[s] - idx[s] ? idx[s] : e.Ma[s] - idx[s];
+    keep = keep && (m <= e.Na[s] - 2);
+    gi = gi * (e.N + 1) + (m <= e.N ? m : 0);
   }
   return keep ? G[gi] : 0.0;
 }
 
-__global__ void k_embed(cx<double>* c, const double* G, int d, int N, int M, long total) {
+__global__ void k_embed(cx<double>* c, const double* G, EmbedDims e, long total) {
   const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < total) c[j] = {embed_value(G, d, N, M, j), 0.0};
+  if (j < total) c[j] = {embed_value(G, e, j), 0.0};
 }
 
-__global__ void k_embed_real(double* c, const double* G, int d, int N, int M, long total) {
+__global__ void k_embed_real(double* c, const double* G, EmbedDims e, long total) {
   const long j = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j < total) c[j] = embed_value(G, d, N, M, j);
+  if (j < total) c[j] = embed_value(G, e, j);
+}
+
+inline EmbedDims embed_dims(const Geometry& g) {
+  EmbedDims e{g.d, g.N, {1, 1, 1}, {1, 1, 1}};
+  for (int s = 0; s < g.d; ++s) {
+    e.Na[s] = g.Na[s];
+    e.Ma[s] = g.Ma[s];
+  }
+  return e;
 }
 
 void embed_generator(const Geometry& g, const double* G, double* out, hipStream_t st) {
-  long total = 1;
-  for (int s = 0; s < g.d; ++s) total *= g.M;
+  const long total = g.nm();
   hipLaunchKernelGGL(k_embed_real, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, out,
-                     G, g.d, g.N, g.M, total);
+                     G, embed_dims(g), total);
   check_launch("embed");
 }
 
-// lambda-hat folded to k in [0, M/2]^d (H = M/2 + 1 per axis): Re(c_hat[k]) / M^d,
-// plus an FP32 copy.
-__global__ void k_fold(const cx<double>* chat, double* l64, float* l32, int d, int H, int M,
-                       long total, double inv) {
+// lambda-hat folded to k_s in [0, Ma_s/2] (Ha_s = Ma_s/2 + 1 per axis):
+// Re(c_hat[k]) / prod Ma, plus an FP32 copy.
+__global__ void k_fold(const cx<double>* chat, double* l64, float* l32, EmbedDims e, long total,
+                       double inv) {
   const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= total) return;
   long rem = k;
   int idx[3] = {0, 0, 0};
-  for (int s = d - 1; s >= 0; --s) {
+  for (int s = e.d - 1; s >= 0; --s) {
+    const int H = e.Ma[s] / 2 + 1;
     idx[s] = (int)(rem % H);
     rem /= H;
   }
   long ci = 0;
-  for (int s = 0; s < d; ++s) ci = ci * M + idx[s];
+  for (int s = 0; s < e.d; ++s) ci = ci * e.Ma[s] + idx[s];
   const double v = chat[ci].x * inv;
   l64[k] = v;
   l32[k] = (float)v;
@@ -140,7 +157,7 @@ __global__ void k_symbol_inv(const double* l, long n, const double* lmax, double
 void build_inverse_symbol(const Geometry& g, const double* lam64, long nf, double* inv64,
                           float* inv32, double* scratch, hipStream_t st) {
   double s = 1.0;
-  for (int k = 0; k < 2 * g.d; ++k) s /= (double)g.M;
+  for (int k = 0; k < g.d; ++k) s /= (double)g.Ma[k] * (double)g.Ma[k];
   hipLaunchKernelGGL(k_symbol_max, dim3(1), dim3(1024), 0, st, lam64, nf, scratch);
   check_launch("symbol max");
   hipLaunchKernelGGL(k_symbol_inv, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, st, lam64,
@@ -148,51 +165,53 @@ void build_inverse_symbol(const Geometry& g, const double* lam64, long nf, doubl
   check_launch("symbol inverse");
 }
 
-void fft_full(int P, int d, void* cv, int dir, hipStream_t st) {
-  cx<double>* c = reinterpret_cast<cx<double>*>(cv);
-  const cx<double>* tw = reinterpret_cast<const cx<double>*>(twiddles(P, false, st));
-  long total = 1;
-  for (int s = 0; s < d; ++s) total *= P;
-  const int E = P >= 16 ? 16 : 8;
-  const int TPL = P / E;
-  const size_t lb = line_lds_bytes<double>(P, E);
+// One axis transform of the in-place P[0] x .. x P[d-1] array.
+static void fft_axis(const int* P, int d, int axis, cx<double>* c, int dir, hipStream_t st) {
+  const int L = P[axis];
+  const cx<double>* tw = reinterpret_cast<const cx<double>*>(twiddles(L, false, st));
+  const int E = L >= 16 ? 16 : 8;
+  const int TPL = L / E;
+  long outer = 1, inner = 1;
+  for (int s = 0; s < axis; ++s) outer *= P[s];
+  for (int s = axis + 1; s < d; ++s) inner *= P[s];
+  if (axis == d - 1) {
+    // contiguous lines
+    const size_t lb = line_lds_bytes<double>(L, E);
+    int LPB = 256 / TPL;
+    if (LPB < 1) LPB = 1;
+    while (LPB > 1 && lb * LPB > 65536) LPB /= 2;
+    launch_rows<double>(L, E, dir, c, outer, LPB, tw, st);
+    return;
+  }
+  // strided: per outer slice, L rows of `inner` columns
   int W = 256 / TPL;
   if (W < 1) W = 1;
-  while (W > 1 && tile_lds(P, E, W, sizeof(double)).bytes > 65536) W /= 2;
-  const long Pd1 = total / P;  // lines per axis
-  if (d >= 2) {
-    // axis 0: columns = P^(d-1), row stride P^(d-1)
-    C2CArgs<double> a0{c, c, nullptr, Pd1, 0, Pd1, 0, Pd1, 0, 1, P, P, W, 0, 0, 0, tw};
-    launch_c2c<double>(P, E, dir, a0, 1, st);
-  }
-  if (d == 3) {
-    // axis 1: slices k0 (stride P*P), rows stride P, columns P
-    C2CArgs<double> a1{c, c, nullptr, P, (long)P * P, P, (long)P * P, P, 0, 1, P, P, W, 0, 0, 0,
-                       tw};
-    launch_c2c<double>(P, E, dir, a1, P, st);
-  }
-  int LPB = 256 / TPL;
-  if (LPB < 1) LPB = 1;
-  while (LPB > 1 && lb * LPB > 65536) LPB /= 2;
-  launch_rows<double>(P, E, dir, c, Pd1, LPB, tw, st);
+  while (W > 1 && tile_lds(L, E, W, sizeof(double)).bytes > 65536) W /= 2;
+  const long os = (long)L * inner;
+  C2CArgs<double> a{c, c, nullptr, inner, os, inner, os, inner, 0, 1, L, L, W, 0, 0, 0, tw};
+  launch_c2c<double>(L, E, dir, a, outer, st);
+}
+
+void fft_full(const int* P, int d, void* cv, int dir, hipStream_t st) {
+  cx<double>* c = reinterpret_cast<cx<double>*>(cv);
+  for (int axis = 0; axis < d; ++axis) fft_axis(P, d, axis, c, dir, st);
 }
 
 void build_symbol(const Geometry& g, const double* G, double* lam64, float* lam32,
                   hipStream_t st) {
-  const int M = g.M, d = g.d;
-  long total = 1;
-  for (int s = 0; s < d; ++s) total *= M;
+  const int d = g.d;
+  const long total = g.nm();
+  const EmbedDims e = embed_dims(g);
   cx<double>* c = nullptr;
   FL_HIP(hipMalloc(&c, (size_t)total * sizeof(cx<double>)));
   const int thr = 256;
   hipLaunchKernelGGL(k_embed, dim3((unsigned)((total + thr - 1) / thr)), dim3(thr), 0, st, c, G,
-                     d, g.N, M, total);
+                     e, total);
   check_launch("embed");
-  fft_full(M, d, c, -1, st);
-  long nf = 1;
-  for (int s = 0; s < d; ++s) nf *= g.H;
+  fft_full(g.Ma, d, c, -1, st);
+  const long nf = g.nh();
   hipLaunchKernelGGL(k_fold, dim3((unsigned)((nf + thr - 1) / thr)), dim3(thr), 0, st, c, lam64,
-                     lam32, d, g.H, M, nf, 1.0 / (double)total);
+                     lam32, e, nf, 1.0 / (double)total);
   check_launch("fold");
   FL_HIP(hipStreamSynchronize(st));
   FL_HIP(hipFree(c));

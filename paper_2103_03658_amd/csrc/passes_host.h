@@ -8,16 +8,16 @@ namespace fl {
 
 template <typename T>
 size_t ws_bytes_t(const Geometry& g, int nrhs) {
-  const size_t h = (size_t)(g.M / 2 + 1);
-  const size_t n = (size_t)g.n;
+  const size_t h0 = (size_t)g.Ha[0];
+  const size_t n1 = (size_t)g.na[1], n2 = (size_t)g.na[2];
   size_t cells = 0;
-  if (g.d == 2) cells = h * n;
-  if (g.d == 3) cells = h * n * n + h * (size_t)g.M * n;
+  if (g.d == 2) cells = h0 * n1;
+  if (g.d == 3) cells = h0 * n1 * n2 + h0 * (size_t)g.Ma[1] * n2;
   return cells * (size_t)nrhs * 2 * sizeof(T);
 }
 
 template <typename T>
-void apply_passes_t(const Geometry& g, const Schedule& sc, const T* lam, const void* twv,
+void apply_passes_t(const Geometry& g, const Schedule& sc, const T* lam, const Twiddles& twv,
                     const T* u, T* y, int nrhs, void* ws, hipStream_t st, int mode,
                     const T* rvec, T* pvec, const double* fvec, const CgScalars* cg,
                     const int* active, hipEvent_t* ev, int only, bool odd) {
@@ -31,69 +31,81 @@ void apply_passes_t(const Geometry& g, const Schedule& sc, const T* lam, const v
   auto done = [&]() {
     if (ev) FL_HIP(hipEventRecord(ev[pass], st));
   };
-  const cx<T>* tw = reinterpret_cast<const cx<T>*>(twv);
-  const int M = g.M, n = g.n, N1 = g.H;   // folded symbol row length
-  const long h = M / 2 + 1;
+  // per axis: interior points, embedding length, folded symbol length, twiddles
+  const int n0 = g.na[0], n1 = g.na[1], n2 = g.na[2];
+  const int M0 = g.Ma[0], M1 = g.Ma[1], M2 = g.Ma[2];
+  const cx<T>* tw0 = reinterpret_cast<const cx<T>*>(twv.ax[0]);
+  const cx<T>* tw1 = reinterpret_cast<const cx<T>*>(twv.ax[1]);
+  const cx<T>* tw2 = reinterpret_cast<const cx<T>*>(twv.ax[2]);
+  const long h0 = g.Ha[0];
   CgScalars nocg{};
   const CgScalars& c = cg ? *cg : nocg;
   if (mode != PM_PLAIN && !cg) throw Error(1, "missing reduction buffers");
   double* part = mode == PM_DOT ? c.part_b : c.part_a;
   if (g.d == 1) {
-    Line1Args<T> a{u, y, pvec, rvec, fvec, active, c, part, c.max_blocks, lam, n, nrhs,
-                   mode, tw};
-    if (go()) launch_line1d<T>(M, sc.E_mid, a, st, odd);
+    Line1Args<T> a{u, y, pvec, rvec, fvec, active, c, part, c.max_blocks, lam, n0, nrhs,
+                   mode, tw0};
+    if (go()) launch_line1d<T>(M0, sc.E_mid, a, st, odd);
     done();
     return;
   }
-  const long C0 = g.d == 2 ? (long)n : (long)n * n;   // columns of the axis-0 passes
+  const long C0 = (long)n1 * n2;   // columns of the axis-0 passes
   const long nd = g.nd;
   if (odd) {
     // real sine passes: axis 0 (r -> S1), 3D axis 1 (in place), last axis
     // with the multiplier (in place), 3D axis 1, axis 0 (S1 -> y, partials
     // of u.y in PM_DOT)
     if (mode != PM_PLAIN && mode != PM_DOT) throw Error(2, "odd passes: plain or dot mode only");
+    if (!g.sine_ok()) throw Error(2, "sine passes need the embedding length 2N on every axis");
     T* S1 = reinterpret_cast<T*>(ws);
-    SineArgs<T> a0{u, S1, nullptr, active, nullptr, 0, C0, nd, 0, 1, n,
-                   sc.W_first, 0, 0, 0, 0, tw};
-    SineArgs<T> a1{S1, S1, nullptr, active, nullptr, 0, n, (long)n * n, 0, n, n,
-                   sc.W_c2c, 0, 0, 0, 0, tw};
-    if (go()) launch_sine_cols<T>(M, sc.E_first, a0, nrhs, st);
-    if (g.d == 3 && go()) launch_sine_cols<T>(M, sc.E_c2c, a1, (long)nrhs * n, st);
-    SineMidArgs<T> m{S1, lam, active, nd / n, nd, n, N1, g.d, sc.LPB_mid, nrhs, tw};
-    if (go()) launch_sine_mid<T>(M, sc.E_mid, m, st);
-    if (g.d == 3 && go()) launch_sine_cols<T>(M, sc.E_c2c, a1, (long)nrhs * n, st);
+    SineArgs<T> a0{u, S1, nullptr, active, nullptr, 0, C0, nd, 0, 1, n0,
+                   sc.W_first, 0, 0, 0, 0, tw0};
+    SineArgs<T> a1{S1, S1, nullptr, active, nullptr, 0, n2, (long)n1 * n2, 0, n0, n1,
+                   sc.W_c2c, 0, 0, 0, 0, tw1};
+    if (go()) launch_sine_cols<T>(M0, sc.E_first, a0, nrhs, st);
+    if (g.d == 3 && go()) launch_sine_cols<T>(M1, sc.E_c2c, a1, (long)nrhs * n0, st);
+    const int nl = g.d == 2 ? n1 : n2;            // line length of the last axis
+    const int ml = g.d == 2 ? M1 : M2;
+    SineMidArgs<T> m{S1, lam, active, nd / nl, nd, nl, n1, g.Ha[g.d - 1], g.Ha[1], g.d,
+                     sc.LPB_mid, nrhs, g.d == 2 ? tw1 : tw2};
+    if (go()) launch_sine_mid<T>(ml, sc.E_mid, m, st);
+    if (g.d == 3 && go()) launch_sine_cols<T>(M1, sc.E_c2c, a1, (long)nrhs * n0, st);
     SineArgs<T> a2{S1, y, mode == PM_DOT ? u : nullptr, active, part, c.max_blocks, C0, nd, 0,
-                   1, n, sc.W_first, 0, 0, 0, mode == PM_DOT ? 1 : 0, tw};
-    if (go()) launch_sine_cols<T>(M, sc.E_first, a2, nrhs, st);
+                   1, n0, sc.W_first, 0, 0, 0, mode == PM_DOT ? 1 : 0, tw0};
+    if (go()) launch_sine_cols<T>(M0, sc.E_first, a2, nrhs, st);
     done();
     return;
   }
   cx<T>* T1 = reinterpret_cast<cx<T>*>(ws);
   // axis 0, forward (real pairs -> Hermitian half); CG: iteration start
   {
-    FirstArgs<T> a{u, pvec, rvec, active, c, T1, C0, nd, h * C0, 0, n,
-                   sc.W_first, 0, 0, 0, mode == PM_CG ? PM_CG : PM_PLAIN, tw};
-    if (go()) launch_first<T>(M, sc.E_first, a, nrhs, st);
+    FirstArgs<T> a{u, pvec, rvec, active, c, T1, C0, nd, h0 * C0, 0, n0,
+                   sc.W_first, 0, 0, 0, mode == PM_CG ? PM_CG : PM_PLAIN, tw0};
+    if (go()) launch_first<T>(M0, sc.E_first, a, nrhs, st);
   }
   if (g.d == 2) {
-    MidArgs<T> m{T1, lam, active, h, h * n, n, n, n, N1, 2, sc.LPB_mid, nrhs, tw};
-    if (go()) launch_mid<T>(M, sc.E_mid, m, nrhs, st);
+    // lines k0 < h0 of n1 values; symbol row k0 * Ha[1]
+    MidArgs<T> m{T1, lam, active, h0, h0 * n1, n1, n1, n1, g.Ha[1], 1, 1, 2, sc.LPB_mid, nrhs,
+                 tw1};
+    if (go()) launch_mid<T>(M1, sc.E_mid, m, nrhs, st);
   } else {
-    cx<T>* T2 = T1 + (long)nrhs * h * n * n;
-    // axis 1 forward: slices (rhs, k0), rows i1 < n -> k1 < M, columns i2
-    C2CArgs<T> f1{T1, T2, active, n, (long)n * n, n, (long)M * n, n, 0, (int)h, n, M,
-                  sc.W_c2c, 0, 0, 0, tw};
-    if (go()) launch_c2c<T>(M, sc.E_c2c, -1, f1, (long)nrhs * h, st);
-    MidArgs<T> m{T2, lam, active, h * M, h * M * n, n, n, n, N1, 3, sc.LPB_mid, nrhs, tw};
-    if (go()) launch_mid<T>(M, sc.E_mid, m, nrhs, st);
-    C2CArgs<T> i1{T2, T1, active, n, (long)M * n, n, (long)n * n, n, 0, (int)h, M, n,
-                  sc.W_c2c, 0, 0, 0, tw};
-    if (go()) launch_c2c<T>(M, sc.E_c2c, +1, i1, (long)nrhs * h, st);
+    cx<T>* T2 = T1 + (long)nrhs * h0 * n1 * n2;
+    // axis 1 forward: slices (rhs, k0), rows i1 < n1 -> k1 < M1, columns i2
+    C2CArgs<T> f1{T1, T2, active, n2, (long)n1 * n2, n2, (long)M1 * n2, n2, 0, (int)h0, n1, M1,
+                  sc.W_c2c, 0, 0, 0, tw1};
+    if (go()) launch_c2c<T>(M1, sc.E_c2c, -1, f1, (long)nrhs * h0, st);
+    // lines (k0, k1) of n2 values; symbol row (k0 Ha[1] + fold(k1)) Ha[2]
+    MidArgs<T> m{T2, lam, active, h0 * M1, h0 * M1 * n2, n2, n2, n2, g.Ha[2], g.Ha[1], M1, 3,
+                 sc.LPB_mid, nrhs, tw2};
+    if (go()) launch_mid<T>(M2, sc.E_mid, m, nrhs, st);
+    C2CArgs<T> i1{T2, T1, active, n2, (long)M1 * n2, n2, (long)n1 * n2, n2, 0, (int)h0, M1, n1,
+                  sc.W_c2c, 0, 0, 0, tw1};
+    if (go()) launch_c2c<T>(M1, sc.E_c2c, +1, i1, (long)nrhs * h0, st);
   }
   {
     LastArgs<T> a{T1, y, mode == PM_DOT ? u : pvec, fvec, active, part, c.max_blocks, C0,
-                  h * C0, nd, 0, n, sc.W_first, 0, 0, 0, mode, tw};
-    if (go()) launch_last<T>(M, sc.E_first, a, nrhs, st);
+                  h0 * C0, nd, 0, n0, sc.W_first, 0, 0, 0, mode, tw0};
+    if (go()) launch_last<T>(M0, sc.E_first, a, nrhs, st);
     done();
   }
 }

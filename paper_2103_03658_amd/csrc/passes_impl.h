@@ -450,13 +450,14 @@ __global__ void __launch_bounds__(512) k_c2c(C2CArgs<T> a) {
 template <typename T>
 struct MidArgs {
   cx<T>* data;
-  const T* lam;          // folded symbol, (N+1)^d
+  const T* lam;          // folded symbol, Ha[0] x .. x Ha[d-1]
   const int* active;
   long rows;             // lines per RHS
   long o_stride;         // complex elements between RHS
   long row_stride;       // complex elements between lines
   int n_in, n_out;
-  int N1;                // folded symbol row length M/2 + 1
+  int Hl;                // folded symbol length of the last axis (M/2 + 1)
+  int H1, M1;            // 3D: folded symbol length and embedding length of axis 1
   int d;
   int LPB;
   int nrhs;
@@ -494,10 +495,10 @@ __global__ void __launch_bounds__(512, (E == 16 && sizeof(T) == 8) ? 3 : 1) k_mi
   long lrow = 0;
   if (h) {
     if (a.d == 3) {
-      const long k0 = line / M, k1 = line % M;
-      lrow = (k0 * a.N1 + (k1 <= M / 2 ? k1 : M - k1)) * a.N1;
+      const long k0 = line / a.M1, k1 = line % a.M1;
+      lrow = (k0 * a.H1 + (k1 <= a.M1 / 2 ? k1 : a.M1 - k1)) * a.Hl;
     } else if (a.d == 2) {
-      lrow = line * a.N1;
+      lrow = line * a.Hl;
     }
   }
   const T* lr = a.lam + lrow;
@@ -732,11 +733,14 @@ __global__ void __launch_bounds__(512) k_sine_cols(SineArgs<T> a) {
 template <typename T>
 struct SineMidArgs {
   T* data;               // [nrhs][rows][n], transformed in place
-  const T* m;            // folded multiplier, (N+1)^d
+  const T* m;            // folded multiplier, Ha[0] x .. x Ha[d-1]
   const int* active;
-  long rows;             // lines per RHS (n^(d-1))
+  long rows;             // lines per RHS (product of the other axes' n)
   long o_stride;         // elements between RHS
-  int n, N1, d;
+  int n;                 // line length (last axis)
+  int n1;                // 3D: interior points of axis 1 (lines per axis-0 index)
+  int Hl, H1;            // folded multiplier lengths of the last axis and of axis 1
+  int d;
   int LPB;               // line pairs per block
   int nrhs;
   const cx<T>* tw;
@@ -744,12 +748,12 @@ struct SineMidArgs {
 
 // Multiplier row of line L of the last axis: the frequencies of the other
 // axes are k = (index along that axis) + 1.
-// (L < n^2 <= 2047^2: 32-bit arithmetic; a 64-bit division here costs
+// (L < n0 n1 <= 2047^2: 32-bit arithmetic; a 64-bit division here costs
 // registers that the transforms need)
-__device__ __forceinline__ long sine_mrow(long L, int n, int N1, int d) {
+__device__ __forceinline__ long sine_mrow(long L, int n1, int H1, int Hl, int d) {
   const int l = (int)L;
-  if (d == 3) return (long)((l / n + 1) * N1 + (l % n + 1)) * N1;
-  return (long)(l + 1) * N1;
+  if (d == 3) return (long)((l / n1 + 1) * H1 + (l % n1 + 1)) * Hl;
+  return (long)(l + 1) * Hl;
 }
 
 // Contiguous last-axis pass on pairs of lines: sigma, multiply each line by
@@ -789,8 +793,8 @@ __global__ void __launch_bounds__(512) k_sine_mid(SineMidArgs<T> a) {
     v[j] = {xa, xb};
   }
   fft_line_1p<T, M, E, -1>(v, l1, t, a.tw);
-  const T* ma = a.m + (ha ? sine_mrow(la, n, a.N1, a.d) : 0);
-  const T* mb = a.m + (hb ? sine_mrow(la + 1, n, a.N1, a.d) : 0);
+  const T* ma = a.m + (ha ? sine_mrow(la, a.n1, a.H1, a.Hl, a.d) : 0);
+  const T* mb = a.m + (hb ? sine_mrow(la + 1, a.n1, a.H1, a.Hl, a.d) : 0);
 #pragma unroll
   for (int sl = 0; sl < E; ++sl) {
     const int k = t + TPL * P::jslot(sl);

@@ -20,6 +20,13 @@ def uniform_rhs(d, N, nrhs=1, seed=0):
                      for j in range(nrhs)])
 
 
+def uniform_grid(shape, nrhs=1, seed=0):
+    """nrhs arrays of i.i.d. U[-1, 1] values on a grid of any shape (a box's
+    interior), shape (nrhs,) + shape."""
+    return np.stack([np.random.default_rng(seed + j).uniform(-1.0, 1.0, tuple(shape))
+                     for j in range(nrhs)])
+
+
 def normal_rhs(d, N, nrhs=1, seed=0):
     """nrhs arrays of i.i.d. N(0, 1) values, shape (nrhs, n, ..., n)."""
     shp = grid_shape(d, N)

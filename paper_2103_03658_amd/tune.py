@@ -44,7 +44,8 @@ def _store(db):
 
 def key(op, nrhs, fp32):
     pc = getattr(op, "precond_kind", 2)
-    return f"d{op.d}-M{op.M}-{'f32' if fp32 else 'f64'}-r{nrhs}-pc{pc}"
+    ms = "x".join(str(m) for m in getattr(op, "Ms", (op.M,) * op.d))
+    return f"d{op.d}-M{ms}-{'f32' if fp32 else 'f64'}-r{nrhs}-pc{pc}"
 
 
 def _lds_ok(M, E, W, fp32):

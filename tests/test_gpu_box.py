@@ -1,0 +1,137 @@
+"""Boxes (Sec. 2.2: the weights live on Upsilon = [0, L]^d with L the
+longest side; axis s has N_s <= N intervals): fl_weights_box builds the
+cube's generator and applies it on the box's n_0 x .. x n_{d-1} interior
+grid, with a circulant embedding and a transform length per axis.
+
+Parity against the oracle on the same box grid: the per-axis embedding
+index map bit-exact, the symbol, FP64/FP32 products (2D and 3D, power-of-two
+and other interval counts, ragged tiles), both preconditioners, and solves
+against Cholesky; a box with every axis N reproduces the cube bit for bit.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2103_03658_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+_ORC = {}
+
+
+def orc_gen(d, alpha, p, N):
+    key = (d, alpha, p, N)
+    if key not in _ORC:
+        _ORC[key] = oracle.generator(d, alpha, p, N)
+    return _ORC[key]
+
+
+def make_box(alpha, p, box):
+    import paper_2103_03658_amd as fl
+    return fl.Operator(len(box), alpha, p, box=box)
+
+
+def abs_scale(G, u):
+    return float(np.abs(oracle.apply(np.abs(G), np.abs(u))).max())
+
+
+BOXES = [(1.2, 1, (32, 12)), (0.7, 2, (16, 64)), (1.5, 1, (40, 7)), (1.0, 0, (5, 24)),
+         (1.3, 1, (8, 4, 6)), (0.9, 2, (16, 16, 8)), (1.6, 1, (10, 6, 12)), (1.1, 1, (4, 32, 3))]
+
+
+@pytest.mark.parametrize("alpha,p,box", BOXES[:3] + BOXES[4:6])
+def test_box_embedding_and_symbol(alpha, p, box):
+    op = make_box(alpha, p, box)
+    d = len(box)
+    assert op.intervals == tuple(box) and op.shape == tuple(b - 1 for b in box)
+    assert op.N == max(box)
+    Gg = op.generator()
+    assert np.array_equal(op.embedding(), oracle.embed_generator(Gg, op.Ms, op.intervals))
+    lo, _ = oracle.symbol(orc_gen(d, alpha, p, op.N), op.Ms, op.intervals)
+    lo = lo[tuple(slice(0, m // 2 + 1) for m in op.Ms)]
+    lg = op.symbol()
+    assert np.abs(lg - lo).max() <= 1e-12 * np.abs(lo).max()
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+@pytest.mark.parametrize("alpha,p,box", BOXES)
+def test_box_apply_parity(alpha, p, box, fp32):
+    print(f"[box apply] box={box} p={p} fp32={fp32}", flush=True)
+    op = make_box(alpha, p, box)
+    u = inputs.uniform_grid(op.shape, 3, seed=13)
+    ut = torch.from_numpy(u.astype(np.float32) if fp32 else u).cuda()
+    y = op.apply(ut).double().cpu().numpy()
+    G = orc_gen(len(box), alpha, p, op.N)
+    tol = 5e-6 if fp32 else 1e-12
+    for r in range(3):
+        ur = ut[r].double().cpu().numpy()
+        ref = oracle.apply(G, ur)
+        assert np.abs(y[r] - ref).max() <= tol * abs_scale(G, ur), r
+
+
+@pytest.mark.parametrize("d,N", [(2, 16), (3, 8)])
+def test_full_box_is_the_cube(d, N):
+    import paper_2103_03658_amd as fl
+    cube = fl.Operator(d, 1.2, 1, N=N)
+    box = make_box(1.2, 1, (N,) * d)
+    u = torch.from_numpy(inputs.uniform_rhs(d, N, 2, seed=1)).cuda()
+    assert torch.equal(cube.apply(u), box.apply(u))
+    assert np.array_equal(cube.symbol(), box.symbol())
+
+
+@pytest.mark.parametrize("box", [(32, 8), (8, 32), (16, 8, 4), (4, 8, 16)])
+def test_box_tau_precond_parity(box):
+    op = make_box(1.3, 1, box)
+    assert op.precond_kind == 2
+    v = inputs.uniform_grid(op.shape, 2, seed=17)
+    y = op.apply_precond(torch.from_numpy(v).cuda()).cpu().numpy()
+    G = orc_gen(len(box), 1.3, 1, op.N)
+    for r in range(2):
+        ref = oracle.tau_precond_apply(G, v[r])
+        assert np.abs(y[r] - ref).max() <= 1e-10 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("box", [(24, 10), (12, 5, 7)])
+def test_box_circulant_precond_parity(box):
+    op = make_box(1.3, 1, box)
+    assert op.precond_kind == 1
+    v = inputs.uniform_grid(op.shape, 2, seed=19)
+    y = op.apply_precond(torch.from_numpy(v).cuda()).cpu().numpy()
+    G = orc_gen(len(box), 1.3, 1, op.N)
+    for r in range(2):
+        ref = oracle.precond_apply(G, v[r], M=op.Ms)
+        assert np.abs(y[r] - ref).max() <= 1e-11 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("mixed", [0, 1])
+@pytest.mark.parametrize("alpha,p,box", [(1.5, 1, (32, 16)), (0.8, 2, (24, 10)),
+                                         (1.2, 1, (8, 4, 6)), (1.9, 1, (16, 8, 8))])
+def test_box_solve_matches_cholesky(alpha, p, box, mixed):
+    op = make_box(alpha, p, box)
+    f = inputs.uniform_grid(op.shape, 2, seed=23)
+    u, info = op.solve(torch.from_numpy(f).cuda(), tol=1e-10, mixed=mixed)
+    u = u.cpu().numpy()
+    G = orc_gen(len(box), alpha, p, op.N)
+    for r in range(2):
+        assert info[r]["converged"] == 1
+        assert info[r]["relres_true"] <= 2e-10
+        uc = oracle.solve_cholesky(G, f[r])
+        assert np.abs(u[r] - uc).max() <= 1e-8 * np.abs(uc).max()
+
+
+def test_box_validation_and_exterior():
+    import paper_2103_03658_amd as fl
+    with pytest.raises(fl.FlError):
+        make_box(1.0, 1, (16, 1))          # an axis needs >= 2 intervals
+    with pytest.raises(fl.FlError):
+        make_box(1.0, 2, (15, 8))          # degree 2 needs N even
+    with pytest.raises(fl.FlError):
+        make_box(1.0, 1, (2048, 8))        # N above 1024
+    op = make_box(1.0, 1, (16, 8))
+    with pytest.raises(fl.FlError):
+        op.exterior(torch.zeros((1, 49, 49), dtype=torch.float64).cuda())
+    with pytest.raises(fl.FlError):
+        make_box(1.0, 1, (24, 10)).set_preconditioner(2)
