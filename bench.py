@@ -37,14 +37,14 @@ VALU_PEAK_TFLOPS = 78.6
 # (kernel, precision, nrhs); valid only for the kernel sources they were
 # measured on (SHA-256 prefix of the transform-pass sources).
 TRAFFIC = {
-    ("axis0_fwd_r2c", "f64", 17): 108969572,
-    ("last_axis_fwd_symbol_inv", "f64", 17): 145081316,
-    ("axis0_inv_c2r", "f64", 17): 108995083,
-    ("tau_axis0_sine", "f64", 17): 72760979,
-    ("tau_last_axis_sine_mult_sine", "f64", 17): 73578463,
-    ("tau_axis0_sine_back", "f64", 17): 72760979,
+    ("axis0_fwd_r2c", "f64", 17): 109038071,
+    ("last_axis_fwd_symbol_inv", "f64", 17): 152627926,
+    ("axis0_inv_c2r", "f64", 17): 109007629,
+    ("tau_axis0_sine", "f64", 17): 72769768,
+    ("tau_last_axis_sine_mult_sine", "f64", 17): 73573119,
+    ("tau_axis0_sine_back", "f64", 17): 72769768,
 }
-TRAFFIC_SRC = "67d9d18c5b2c3bcc"
+TRAFFIC_SRC = "37429e61ff13821b"
 
 
 def pass_sources_hash():
