@@ -52,6 +52,9 @@ typedef enum {
 
 enum { FL_KERNEL_FRACTIONAL = 0, FL_KERNEL_TEMPERED = 1 };
 
+/* Most exponential terms a kernel of fl_weights_expsum may have. */
+#define FL_MAX_KERNEL_TERMS 16
+
 /* Per right-hand-side result of fl_solve. */
 typedef struct {
   int iters;          /* CG iterations (FP32 iterations for the mixed paths, summed) */
@@ -116,6 +119,32 @@ fl_status fl_weights_gamma(int d, double alpha, int degree, double h, int kernel
  */
 fl_status fl_weights_box(int d, double alpha, int degree, const int *intervals, int kernel,
                          double lambda, double gamma, void *stream, fl_op *out);
+
+/*
+ * fl_weights_expsum -- the operator of Remark 2.2 (kernel K(|x - y|) beside
+ * the hypersingular factor, normalisation c_{d,alpha}) for
+ *     K(r) = sum_{i < nterm} coef[i] exp(-rate[i] r).
+ * Only the weight integrals omega_k (K enters mu_gamma) and the far-field
+ * constant of a_0 depend on K, and both are linear in it: each term's are
+ * computed as for the tempered kernel, scaled by coef[i] and summed; the
+ * origin rule and a_k, a_0 then follow as for any kernel.  rate 0 is K = 1,
+ * so {coef 1, rate 0} is fl_weights_box with FL_KERNEL_FRACTIONAL and
+ * {coef 1, rate lambda} the tempered operator.  Non-negative sums of
+ * exponentials are dense in the completely monotone kernels (those are
+ * Laplace transforms of non-negative measures), e.g. quadratures of
+ * (1 + r)^{-beta} = int_0^inf t^{beta-1} e^{-t} e^{-t r} dt / Gamma(beta).
+ *   intervals  host array of d ints as in fl_weights_box (all equal: the cube)
+ *   nterm      1 .. FL_MAX_KERNEL_TERMS
+ *   coef       host array of nterm finite values >= 0, not all zero (K >= 0
+ *              keeps the matrix symmetric positive definite)
+ *   rate       host array of nterm finite rates >= 0
+ *   gamma      splitting parameter in (alpha, 2]
+ * Other arguments, layout and errors as fl_weights_box; FL_E_INVAL for a
+ * bad term.  Setup cost grows linearly with nterm.
+ */
+fl_status fl_weights_expsum(int d, double alpha, int degree, const int *intervals, int nterm,
+                            const double *coef, const double *rate, double gamma, void *stream,
+                            fl_op *out);
 
 /* Copy the FP64 generator G_k, k in {0..N}^d (row-major, (N+1)^d values),
  * to host memory.  count must be >= (N+1)^d.  Test hook. */

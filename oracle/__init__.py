@@ -20,7 +20,9 @@ definitions in its own order and notation:
               exterior-data term b (same equations), circulant embedding,
   solve       Cholesky and plain CG on the dense/BTTB product,
   exact       closed forms used as pins (eq. (fun0), Example 3.2.3, and
-              standard Fourier-transform identities).
+              standard Fourier-transform identities),
+  continuous  the 1D operator of Remark 2.2 for any kernel K by adaptive
+              quadrature (Example 3.2.2's right-hand side).
 
 Readings taken where the paper is silent, garbled or self-contradictory are
 listed in each function's docstring (and collected in the design notes):
@@ -32,15 +34,18 @@ listed in each function's docstring (and collected in the design notes):
   R4  3D and 2D p=2: the same axis-average rule, with the p=2 Richardson
       step of R2 on each axis.  Parity unpinned (no printed numbers).
   R5  gamma = 2 throughout (the paper's recommended and tabulated choice).
-  R6  Tempered kernel: normalisation c-bar = c_{d,alpha}; K enters the weight
-      integrals and the far-field constant.  Parity unpinned beyond the
-      lambda -> 0 reduction.
+  R6  Kernel K(r) of Remark 2.2 (tempered exp(-lambda r), sums of
+      exponentials): normalisation c-bar = c_{d,alpha}; K enters the weight
+      integrals and the far-field constant.  Pinned in 1D by consistency
+      with the continuous operator (continuous.py, itself pinned to the
+      Fourier side) and by Example 3.2.2's second-order solve rate.
   R7  Embedding slots whose folded offset exceeds N-2 are zero.
 """
 
 from .constants import c_dalpha, far_field_T, K_ball
 from .weights import weights, weights_at
-from .operator import (origin_rule, coefficients, generator, generator_at, dense_matrix,
+from .operator import (origin_rule, coefficients, generator, generator_expsum, generator_at,
+                       dense_matrix,
                        apply_dense, apply_bttb, apply, apply_rows,
                        embed_generator, symbol, precond_apply, tau_symbol,
                        tau_precond_apply,
@@ -48,12 +53,12 @@ from .operator import (origin_rule, coefficients, generator, generator_at, dense
                        exterior_lattice_2d, far_field_tail_1d, far_field_tail_2d,
                        grid_points)
 from .solve import solve_cholesky, solve_cg
-from . import exact
+from . import continuous, exact
 
 __all__ = [
     "c_dalpha", "far_field_T", "K_ball", "weights", "weights_at", "origin_rule",
-    "coefficients", "generator", "generator_at", "dense_matrix", "apply_dense", "apply_bttb",
+    "coefficients", "generator", "generator_expsum", "generator_at", "dense_matrix", "apply_dense", "apply_bttb",
     "apply", "apply_rows", "embed_generator", "symbol", "precond_apply", "tau_symbol", "tau_precond_apply", "exterior_b_1d", "exterior_b_2d",
     "exterior_lattice_1d", "exterior_lattice_2d", "far_field_tail_1d", "far_field_tail_2d",
-    "grid_points", "solve_cholesky", "solve_cg", "exact",
+    "grid_points", "solve_cholesky", "solve_cg", "continuous", "exact",
 ]

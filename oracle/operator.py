@@ -106,6 +106,22 @@ def generator(d, alpha, p, N, lam=0.0, return_parts=False, gamma=2.0):
     return G
 
 
+def generator_expsum(d, alpha, p, N, terms, gamma=2.0):
+    """G_k = -c_{d,alpha} a_k for K(r) = sum_i c_i exp(-lambda_i r), terms = [(c_i, lambda_i)].
+
+    Remark 2.2: K enters mu_gamma, hence only the weight integrals omega_k,
+    and the far-field constant T of a_0; both are integrals against K, so
+    they are the c_i-weighted sums of the one-exponential ones (lambda_i = 0
+    is K = 1).  The origin rule and a_k, a_0 are then formed once, as for
+    any kernel."""
+    h = 2.0 / N
+    om = sum(c * _weights(d, alpha, p, N, h=h, lam=lam, gamma=gamma) for c, lam in terms)
+    T = sum(c * far_field_T(d, alpha, L=2.0, lam=lam) for c, lam in terms)
+    W = origin_rule(om, d, p, gamma=gamma)
+    a = coefficients(W, d, h, T, gamma=gamma)
+    return -c_dalpha(d, alpha) * a
+
+
 def generator_at(d, alpha, p, N, nodes, lam=0.0):
     """G_k = -c_{d,alpha} 2^{z(k)} omega_k / |xi_k|^2 at selected offsets
     away from the origin correction (every node with |k|_1 > 2), d = 2, 3;

@@ -31,16 +31,36 @@ class Operator:
     with N = max N_s intervals and axis s has N_s.
 
     Built on the current CUDA/HIP device by fl_weights_gamma / fl_weights_box
-    (splitting parameter gamma in (alpha, 2], default 2).  Vectors are torch
+    (splitting parameter gamma in (alpha, 2], default 2).  kernel="expsum"
+    with terms=[(coef, rate), ...] takes K(r) = sum coef exp(-rate r)
+    (fl_weights_expsum; the cube, or the box given).  Vectors are torch
     tensors on that device holding nrhs * prod(n_s) values (any shape with
     that many elements, contiguous; row-major over `shape`)."""
 
     def __init__(self, d, alpha, degree, N=None, h=None, kernel="fractional", lam=0.0,
-                 stream=None, gamma=2.0, box=None):
-        kind = {"fractional": FL_KERNEL_FRACTIONAL, "tempered": FL_KERNEL_TEMPERED}[kernel]
+                 stream=None, gamma=2.0, box=None, terms=None):
         self._h = ctypes.c_void_p()
         self._lib = lib()
-        if box is not None:
+        if kernel == "expsum":
+            # K(r) = sum coef exp(-rate r) over terms = [(coef, rate), ...]
+            if not terms:
+                raise ValueError("kernel 'expsum' needs terms=[(coef, rate), ...]")
+            if box is None:
+                if N is None:
+                    if h is None:
+                        raise ValueError("give N, h or box")
+                    N = int(round(2.0 / h))
+                box = (N,) * d
+            if len(box) != d:
+                raise ValueError("box needs d interval counts")
+            arr = (ctypes.c_int * 3)(*[int(b) for b in box])
+            coef = (ctypes.c_double * len(terms))(*[float(t[0]) for t in terms])
+            rate = (ctypes.c_double * len(terms))(*[float(t[1]) for t in terms])
+            check(self._lib.fl_weights_expsum(int(d), float(alpha), int(degree), arr, len(terms),
+                                              coef, rate, float(gamma), _stream_ptr(stream),
+                                              ctypes.byref(self._h)))
+        elif box is not None:
+            kind = {"fractional": FL_KERNEL_FRACTIONAL, "tempered": FL_KERNEL_TEMPERED}[kernel]
             if len(box) != d:
                 raise ValueError("box needs d interval counts")
             arr = (ctypes.c_int * 3)(*[int(b) for b in box])
@@ -48,6 +68,7 @@ class Operator:
                                            float(lam), float(gamma), _stream_ptr(stream),
                                            ctypes.byref(self._h)))
         else:
+            kind = {"fractional": FL_KERNEL_FRACTIONAL, "tempered": FL_KERNEL_TEMPERED}[kernel]
             if h is None:
                 if N is None:
                     raise ValueError("give N or h")
@@ -66,6 +87,7 @@ class Operator:
         self.M = max(self.Ms)
         self.n = self.shape[0] if len(set(self.shape)) == 1 else None
         self.alpha, self.degree, self.kernel, self.lam = float(alpha), int(degree), kernel, lam
+        self.terms = [tuple(map(float, t)) for t in terms] if kernel == "expsum" else None
         self.gamma = float(gamma)
         self.nd = 1
         for v in self.shape:

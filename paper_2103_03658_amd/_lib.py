@@ -23,6 +23,7 @@ STATUS_NAMES = {0: "FL_OK", 1: "FL_E_INVAL", 2: "FL_E_UNSUPPORTED", 3: "FL_E_NOM
 
 FL_KERNEL_FRACTIONAL = 0
 FL_KERNEL_TEMPERED = 1
+FL_MAX_KERNEL_TERMS = 16
 
 
 class FlInfo(ctypes.Structure):
@@ -57,6 +58,11 @@ _SIGS = {
                                       ctypes.POINTER(ctypes.c_int), ctypes.c_int,
                                       ctypes.c_double, ctypes.c_double, _P,
                                       ctypes.POINTER(_P)]),
+    "fl_weights_expsum": (ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_int), ctypes.c_int,
+                                         ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_double), ctypes.c_double, _P,
+                                         ctypes.POINTER(_P)]),
     "fl_apply": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, _P]),
     "fl_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_int, ctypes.c_int, _P,
                                 ctypes.c_int, ctypes.POINTER(FlInfo), _P]),

@@ -125,8 +125,8 @@ struct ChunkGraph {
 
 struct fl_op_s {
   fl::Geometry g{};
-  int degree = 0, kernel = 0, device = 0;
-  double alpha = 0, h = 0, lambda = 0, c = 0;
+  int degree = 0, device = 0;
+  double alpha = 0, h = 0, c = 0;
   double* G = nullptr;
   double* lam64 = nullptr;
   float* lam32 = nullptr;
@@ -266,8 +266,23 @@ fl_status fl_weights(int d, double alpha, int degree, double h, int kernel, doub
 // Operator setup shared by the cube (fl_weights_gamma) and the box
 // (fl_weights_box): generator on {0..N}^d with h = 2/N, grid of Nax[s]
 // intervals along axis s.
-static fl_status create_op(int d, double alpha, int degree, int N, const int* Nax, int kernel,
-                           double lambda, double gamma, void* stream, fl_op* out) {
+static_assert(FL_MAX_KERNEL_TERMS == fl::kMaxKernelTerms, "kernel term limit");
+
+struct KernelTerms {
+  int n;
+  double coef[fl::kMaxKernelTerms], rate[fl::kMaxKernelTerms];
+};
+
+static KernelTerms single_term(int kernel, double lambda) {
+  KernelTerms kt{};
+  kt.n = 1;
+  kt.coef[0] = 1.0;
+  kt.rate[0] = kernel == FL_KERNEL_TEMPERED ? lambda : 0.0;
+  return kt;
+}
+
+static fl_status create_op(int d, double alpha, int degree, int N, const int* Nax,
+                           const KernelTerms& kt, double gamma, void* stream, fl_op* out) {
   if (!(gamma > alpha && gamma <= 2.0)) return fail(FL_E_INVAL, "gamma must lie in (alpha, 2]");
   if (N < 4) return fail(FL_E_INVAL, "N = 2/h must be >= 4");
   if (degree == 2 && N % 2) return fail(FL_E_INVAL, "degree 2 needs N even");
@@ -298,10 +313,8 @@ static fl_status create_op(int d, double alpha, int degree, int N, const int* Na
     }
     A->precond = A->g.sine_ok() ? 2 : 1;
     A->degree = degree;
-    A->kernel = kernel;
     A->alpha = alpha;
     A->h = 2.0 / N;
-    A->lambda = kernel == FL_KERNEL_TEMPERED ? lambda : 0.0;
     // c_{d,alpha} = 2^{alpha-1} alpha Gamma((d+alpha)/2) / (pi^{d/2} Gamma(1-alpha/2))
     A->c = std::pow(2.0, alpha - 1.0) * alpha * std::tgamma((d + alpha) / 2.0) /
            (std::pow(M_PI, d / 2.0) * std::tgamma(1.0 - alpha / 2.0));
@@ -313,7 +326,19 @@ static fl_status create_op(int d, double alpha, int degree, int N, const int* Na
     A->lam32 = (float*)dmalloc((size_t)nh * sizeof(float));
     A->linv64 = (double*)dmalloc((size_t)nh * sizeof(double));
     A->linv32 = (float*)dmalloc((size_t)nh * sizeof(float));
-    fl::GenParams gp{d, degree, N, kernel, alpha, A->h, A->lambda, A->c, gamma};
+    fl::GenParams gp{};
+    gp.d = d;
+    gp.p = degree;
+    gp.N = N;
+    gp.alpha = alpha;
+    gp.h = A->h;
+    gp.c = A->c;
+    gp.gamma = gamma;
+    gp.nterm = kt.n;
+    for (int i = 0; i < kt.n; ++i) {
+      gp.coef[i] = kt.coef[i];
+      gp.rate[i] = kt.rate[i];
+    }
     fl::build_generator(gp, A->G, st);
     fl::build_symbol(A->g, A->G, A->lam64, A->lam32, st);
     {
@@ -367,7 +392,7 @@ fl_status fl_weights_gamma(int d, double alpha, int degree, double h, int kernel
     if (Nr > 1e6) return fail(FL_E_UNSUPPORTED, "N too large");
     const int N = (int)Nr;
     const int Nax[3] = {N, N, N};
-    return create_op(d, alpha, degree, N, Nax, kernel, lambda, gamma, stream, out);
+    return create_op(d, alpha, degree, N, Nax, single_term(kernel, lambda), gamma, stream, out);
   });
 }
 
@@ -379,7 +404,36 @@ fl_status fl_weights_box(int d, double alpha, int degree, const int* intervals, 
     if (!intervals) return fail(FL_E_INVAL, "intervals is NULL");
     int N = 0;
     for (int s = 0; s < d; ++s) N = std::max(N, intervals[s]);
-    return create_op(d, alpha, degree, N, intervals, kernel, lambda, gamma, stream, out);
+    return create_op(d, alpha, degree, N, intervals, single_term(kernel, lambda), gamma, stream,
+                     out);
+  });
+}
+
+fl_status fl_weights_expsum(int d, double alpha, int degree, const int* intervals, int nterm,
+                            const double* coef, const double* rate, double gamma, void* stream,
+                            fl_op* out) {
+  return guarded([&]() -> fl_status {
+    const fl_status e = check_common(d, alpha, degree, FL_KERNEL_FRACTIONAL, 0.0, out);
+    if (e != FL_OK) return e;
+    if (!intervals || !coef || !rate) return fail(FL_E_INVAL, "intervals, coef or rate is NULL");
+    if (nterm < 1 || nterm > FL_MAX_KERNEL_TERMS)
+      return fail(FL_E_INVAL, "nterm must lie in [1, FL_MAX_KERNEL_TERMS]");
+    KernelTerms kt{};
+    kt.n = nterm;
+    double total = 0.0;
+    for (int i = 0; i < nterm; ++i) {
+      if (!(coef[i] >= 0.0) || !std::isfinite(coef[i]))
+        return fail(FL_E_INVAL, "kernel coefficients must be finite and >= 0");
+      if (!(rate[i] >= 0.0) || !std::isfinite(rate[i]))
+        return fail(FL_E_INVAL, "kernel rates must be finite and >= 0");
+      kt.coef[i] = coef[i];
+      kt.rate[i] = rate[i];
+      total += coef[i];
+    }
+    if (!(total > 0.0)) return fail(FL_E_INVAL, "kernel coefficients are all zero");
+    int N = 0;
+    for (int s = 0; s < d; ++s) N = std::max(N, intervals[s]);
+    return create_op(d, alpha, degree, N, intervals, kt, gamma, stream, out);
   });
 }
 

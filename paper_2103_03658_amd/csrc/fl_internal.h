@@ -180,10 +180,16 @@ inline int apply_npasses(int d) { return d == 1 ? 1 : (d == 2 ? 3 : 5); }
 const void* twiddles(int M, bool fp32, hipStream_t st);
 
 // Generator, symbol: see weights unit.
+// Kernel K(r) = sum_i coef[i] exp(-rate[i] r) (rate 0: K = 1).  The weight
+// integrals and the far-field constant are linear in K, so each term's are
+// built as for one exponential and summed with its coefficient.
+constexpr int kMaxKernelTerms = 16;
 struct GenParams {
-  int d, p, N, kernel;
-  double alpha, h, lambda, c;
+  int d, p, N;
+  double alpha, h, c;
   double gamma;   // splitting parameter in (alpha, 2]
+  int nterm;
+  double coef[kMaxKernelTerms], rate[kMaxKernelTerms];
 };
 void build_generator(const GenParams& gp, double* G, hipStream_t st);
 void build_symbol(const Geometry& g, const double* G, double* lam64, float* lam32,

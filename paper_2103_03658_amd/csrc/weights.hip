@@ -283,7 +283,7 @@ __global__ void __launch_bounds__(128) k_elements(int d, int p, int N, int Eel, 
 
 // node k gathers its elements in a fixed order; omega_k = scale * sum
 __global__ void k_gather(int d, int p, int N, int Eel, long total, const double* elem,
-                         const double* orig, double scale, double* omega) {
+                         const double* orig, double scale, int accumulate, double* omega) {
   const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= total) return;
   const int nb = p + 1;
@@ -331,7 +331,7 @@ __global__ void k_gather(int d, int p, int N, int Eel, long total, const double*
         }
         sum += origin ? orig[lidx] : elem[eidx * nout + lidx];
       }
-  omega[k] = scale * sum;
+  omega[k] = accumulate ? omega[k] + scale * sum : scale * sum;
 }
 
 // far-field constant T_d = int over R^d_+ minus [0,L]^d of K |xi|^{-d-alpha},
@@ -360,7 +360,8 @@ __device__ double far_F(double R, double alpha, double lam, const GLTables* tb) 
 }
 
 __global__ void __launch_bounds__(256) k_far(int d, double alpha, double lam, double L,
-                                             const GLTables* tb, double* T) {
+                                             double wt, int accumulate, const GLTables* tb,
+                                             double* T) {
   __shared__ double sh[8];
   const int npts = d == 1 ? 1 : (d == 2 ? NA : NA * NA);
   double acc = 0.0;
@@ -377,8 +378,8 @@ __global__ void __launch_bounds__(256) k_far(int d, double alpha, double lam, do
     const double rho = sqrt(rho2);
     acc += w * d * pow(rho, -(double)d) * far_F(L * rho, alpha, lam, tb);
   }
-  const double t = bsum(acc, sh);
-  if (threadIdx.x == 0) *T = t;
+  const double t = wt * bsum(acc, sh);
+  if (threadIdx.x == 0) *T = accumulate ? *T + t : t;
 }
 
 // a_k = 2^{z(k)} W_k / |xi_k|^gamma (W: origin rule applied for gamma = 2;
@@ -445,9 +446,6 @@ void build_generator(const GenParams& gp, double* G, hipStream_t st) {
   gauss_legendre(QN, tb.xn, tb.wn);
   gauss_legendre(QF, tb.xf, tb.wf);
   gauss_legendre(QP, tb.xp, tb.wp);
-  const bool tempered = gp.kernel == 1 && gp.lambda > 0.0;
-  // lattice-unit kernel rate; for K = 1 integrate on the unit lattice and scale
-  const double lamh = tempered ? gp.lambda * gp.h : 0.0;
   const double sig = gp.gamma - gp.alpha;
   const double scale = std::pow(gp.h, sig);
   const int nb = p + 1;
@@ -470,13 +468,18 @@ void build_generator(const GenParams& gp, double* G, hipStream_t st) {
   FL_HIP(hipMalloc(&part, (size_t)nblk * sizeof(double)));
   FL_HIP(hipMalloc(&T, sizeof(double)));
   FL_HIP(hipMemcpyAsync(dtb, &tb, sizeof(GLTables), hipMemcpyHostToDevice, st));
-  hipLaunchKernelGGL(k_origin, dim3(1), dim3(256), 0, st, d, p, sig, lamh, dtb, orig);
-  hipLaunchKernelGGL(k_elements, dim3((unsigned)((nelem + 127) / 128)), dim3(128), 0, st, d, p,
-                     N, Eel, nelem, sig, lamh, dtb, elem);
-  hipLaunchKernelGGL(k_gather, dim3((unsigned)nblk), dim3(thr), 0, st, d, p, N, Eel, nnode, elem,
-                     orig, scale, omega);
-  hipLaunchKernelGGL(k_far, dim3(1), dim3(256), 0, st, d, gp.alpha, tempered ? gp.lambda : 0.0,
-                     2.0, dtb, T);
+  // one pass per kernel term: omega and T accumulate coef * (that term's);
+  // the lattice-unit rate is rate * h (K = 1 integrates on the unit lattice)
+  for (int i = 0; i < gp.nterm; ++i) {
+    const double lamh = gp.rate[i] * gp.h;
+    hipLaunchKernelGGL(k_origin, dim3(1), dim3(256), 0, st, d, p, sig, lamh, dtb, orig);
+    hipLaunchKernelGGL(k_elements, dim3((unsigned)((nelem + 127) / 128)), dim3(128), 0, st, d, p,
+                       N, Eel, nelem, sig, lamh, dtb, elem);
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)nblk), dim3(thr), 0, st, d, p, N, Eel, nnode,
+                       elem, orig, scale * gp.coef[i], i > 0 ? 1 : 0, omega);
+    hipLaunchKernelGGL(k_far, dim3(1), dim3(256), 0, st, d, gp.alpha, gp.rate[i], 2.0,
+                       gp.coef[i], i > 0 ? 1 : 0, dtb, T);
+  }
   hipLaunchKernelGGL(k_coeff, dim3((unsigned)nblk), dim3(thr), 0, st, d, p, N, gp.h, gp.c,
                      gp.gamma, nnode, omega, G, part);
   hipLaunchKernelGGL(k_diag, dim3(1), dim3(256), 0, st, d, gp.c, (int)nblk, part, T, G);

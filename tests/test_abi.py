@@ -124,3 +124,26 @@ def test_fl_weights_gamma_validation(gamma):
     st = lib.fl_weights_gamma(2, 1.0, 1, 0.25, 0, 0.0, gamma, None, ctypes.byref(h))
     assert st == _lib.FL_E_INVAL
     assert h.value is None
+
+
+def test_fl_weights_expsum_validation():
+    """Bad kernel terms are rejected before any device work."""
+    lib = _lib.lib()
+    h = ctypes.c_void_p()
+    iv = (ctypes.c_int * 3)(8, 8, 8)
+
+    def call(coef, rate, nterm=None, intervals=iv):
+        n = len(coef) if nterm is None else nterm
+        c = (ctypes.c_double * max(len(coef), 1))(*coef)
+        r = (ctypes.c_double * max(len(rate), 1))(*rate)
+        return lib.fl_weights_expsum(2, 1.0, 1, intervals, n, c, r, 2.0, None, ctypes.byref(h))
+
+    assert call([1.0, -0.1], [0.0, 1.0]) == _lib.FL_E_INVAL          # negative coefficient
+    assert call([1.0], [-1.0]) == _lib.FL_E_INVAL                     # negative rate
+    assert call([0.0, 0.0], [1.0, 2.0]) == _lib.FL_E_INVAL            # K = 0
+    assert call([1.0], [float("inf")]) == _lib.FL_E_INVAL
+    assert call([float("nan")], [1.0]) == _lib.FL_E_INVAL
+    assert call([1.0] * 17, [0.0] * 17) == _lib.FL_E_INVAL            # too many terms
+    assert call([1.0], [0.0], nterm=0) == _lib.FL_E_INVAL
+    assert call([1.0], [0.0], intervals=None) == _lib.FL_E_INVAL
+    assert _lib.FL_MAX_KERNEL_TERMS == 16
