@@ -199,7 +199,9 @@ fl_status fl_apply(fl_op A, const void *u, void *y, int nrhs, int fp32, void *st
  *           delta (fl_set_refinement) since the last update, the
  *           correction is added to the FP64 iterate and the residual is
  *           recomputed as r = f - A u with an FP64 product; stops when that
- *           FP64 residual meets tol.  The test runs every 8 iterations.
+ *           FP64 residual meets tol.  The drop is tested at every iteration
+ *           start on the device (a right-hand side that reaches it waits);
+ *           the update runs after the current chunk of iterations.
  *           Preconditioned, the search direction restarts from the new
  *           residual at each update.
  *           2: iterative refinement with restarts: FP32 CG solves A d = r to
@@ -225,17 +227,18 @@ fl_status fl_solve(fl_op A, const double *f, const double *g, double tol, int ma
  *            field (xi >= 0 outside the box [0, L]^d, L = 2) of
  *            g(x_i + (-1)^m o xi) K(|xi|) |xi|^{-d-alpha} d xi.
  * The lattice sum runs on the GPU (a multilevel Toeplitz product of G with g
- * on the node lattice, by circulant embedding in 4N points per axis for
- * d = 2, directly for d = 1).  The far-field integrals need g beyond the
- * lattice, which the library cannot evaluate: the caller supplies them.
+ * on the node lattice, by circulant embedding in P = 2M >= 4N points per axis
+ * for d = 2, 3, directly for d = 1).  The far-field integrals need g beyond
+ * the lattice, which the library cannot evaluate: the caller supplies them.
  *   g_lat  device, nrhs * (3N+1)^d doubles: g(x_j), x_j = -1 + j h for
  *          j in [-N, 2N]^d, row-major, last index fastest (entries at
  *          interior nodes are ignored)
  *   tail   device, nrhs * n^d doubles (interior layout), or NULL (tail = 0)
  *   b      device, nrhs * n^d doubles, output
- * FL_E_UNSUPPORTED unless d = 1, or d = 2 with M <= 1024.  Same stream
- * rules as fl_apply; allocates its transform buffers (2 (4N)^2 complex
- * doubles for d = 2) on first use and keeps them with the operator.
+ * FL_E_UNSUPPORTED for a box, and unless d = 1, d = 2 with M <= 1024 or
+ * d = 3 with M <= 512.  Same stream rules as fl_apply; allocates its
+ * transform buffers (2 P^d complex doubles for d = 2, 3: 4.3 GB at d = 3,
+ * N = 128) on first use and keeps them with the operator.
  */
 fl_status fl_exterior(fl_op A, const double *g_lat, const double *tail, double *b, int nrhs,
                       void *stream);

@@ -408,6 +408,35 @@ def exterior_lattice_2d(G, g):
     return out
 
 
+def exterior_lattice_3d(G, g):
+    """Lattice part of the exterior-data term in 3D (the 2D definition of
+    bold-b_ij, eq. (2D-scheme), taken over three axes: reading R4): for every
+    interior node, the sum of G_{|k|} g(x_{i+k}) over the offsets k in
+    [-N, N]^3 whose node i + k is outside the interior.  g must accept numpy
+    arrays (x1, x2, x3)."""
+    N = G.shape[0] - 1
+    h = 2.0 / N
+    n = N - 1
+    k = np.arange(-N, N + 1)
+    ak = np.abs(k)
+    Gs = G[ak[:, None, None], ak[None, :, None], ak[None, None, :]]
+    out = np.zeros((n, n, n))
+    for i0 in range(1, N):
+        a0 = i0 + k
+        in0 = (a0 >= 1) & (a0 <= N - 1)
+        for i1 in range(1, N):
+            a1 = i1 + k
+            in1 = (a1 >= 1) & (a1 <= N - 1)
+            for i2 in range(1, N):
+                a2 = i2 + k
+                in2 = (a2 >= 1) & (a2 <= N - 1)
+                inside = in0[:, None, None] & in1[None, :, None] & in2[None, None, :]
+                vals = g((-1.0 + a0 * h)[:, None, None], (-1.0 + a1 * h)[None, :, None],
+                         (-1.0 + a2 * h)[None, None, :])
+                out[i0 - 1, i1 - 1, i2 - 1] = math.fsum((Gs * vals)[~inside].ravel())
+    return out
+
+
 def far_field_tail_2d(N, g, alpha, nq=160):
     """tail_ij = sum_m int_{Upsilon^c_+} g(x + (-1)^m o xi) |xi|^{-2-alpha} dxi
     (the far-field integrals of bold-b_ij).  The region is split into

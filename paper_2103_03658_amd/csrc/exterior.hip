@@ -4,8 +4,8 @@
 //   b_i = sum over exterior lattice nodes j, |j - i|_inf <= N, of G_{|j-i|} g(x_j)
 //         - c_{d,alpha} tail_i
 // The lattice sum is a multilevel Toeplitz product of G with g on the node
-// lattice [-N, 2N]^d (zero on the interior nodes).  In 2D it is done by
-// circulant embedding in P = 4N points per axis: with the data at offset
+// lattice [-N, 2N]^d (zero on the interior nodes).  In 2D and 3D it is done
+// by circulant embedding in P = 4N points per axis: with the data at offset
 // j + N in [0, 3N] and G wrapped to k mod P for |k| <= N, every offset i - j
 // of an interior i and a lattice j falls in [1 - 2N, 2N - 1], and those with
 // |i - j| > N land in the zero band (N, 3N) of the wrapped generator, so the
@@ -109,14 +109,20 @@ void difference(const double* a, const double* b, double* out, long n, hipStream
 }
 
 bool exterior_supported(const Geometry& g) {
-  // the cube only (the exterior lattice of a box is not built)
-  return g.cube() && (g.d == 1 || (g.d == 2 && 2 * g.Ma[0] <= 2048));
+  // the cube only (the exterior lattice of a box is not built); the
+  // transforms take P <= 2048 per axis, and in 3D P <= 1024 keeps the two
+  // P^3 complex buffers at 17 GB each
+  if (!g.cube()) return false;
+  const int P = 2 * g.Ma[0];
+  return g.d == 1 || (g.d == 2 && P <= 2048) || (g.d == 3 && P <= 1024);
 }
 
 size_t exterior_khat_bytes(const Geometry& g) {
-  if (g.d != 2) return 0;
+  if (g.d == 1) return 0;
   const long P = 2L * g.Ma[0];
-  return (size_t)P * P * sizeof(cx<double>);
+  long total = 1;
+  for (int s = 0; s < g.d; ++s) total *= P;
+  return (size_t)total * sizeof(cx<double>);
 }
 
 void exterior_term(const Geometry& g, const double* G, double c, const double* g_lat,
@@ -134,10 +140,13 @@ void exterior_term(const Geometry& g, const double* G, double c, const double* g
     }
     return;
   }
-  if (d != 2) throw Error(2, "exterior data: d = 3 is not supported");
   const int P = 2 * g.Ma[0];
   const int Pd[3] = {P, P, P};
-  const long total = (long)P * P;
+  long total = 1, Ld = 1;
+  for (int s = 0; s < d; ++s) {
+    total *= P;
+    Ld *= L;
+  }
   cx<double>* K = reinterpret_cast<cx<double>*>(khat);
   cx<double>* D = reinterpret_cast<cx<double>*>(work);
   if (!khat_ready) {
@@ -149,7 +158,7 @@ void exterior_term(const Geometry& g, const double* G, double c, const double* g
   const double scale = 1.0 / (double)total;
   for (int o = 0; o < nrhs; ++o) {
     hipLaunchKernelGGL(k_place_exterior, dim3(blocks(total, thr)), dim3(thr), 0, st,
-                       g_lat + (long)o * L * L, d, N, P, total, D);
+                       g_lat + (long)o * Ld, d, N, P, total, D);
     check_launch("place exterior data");
     fft_full(Pd, d, D, -1, st);
     hipLaunchKernelGGL(k_mul_spectra, dim3(blocks(total, thr)), dim3(thr), 0, st, D, K, total);

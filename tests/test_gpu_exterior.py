@@ -2,7 +2,9 @@
 exterior term).
 
 The lattice part of the term (the sum of G_{|j-i|} g(x_j) over exterior
-nodes) is computed by the library and compared with the oracle's direct sum.
+nodes) is computed by the library and compared with the oracle's direct sum
+(1D, 2D and 3D), and at the largest supported sizes (2D N = 512, 3D N = 128)
+through the identity b + A 1 = c_{d,alpha} 2^d T_d for g = 1.
 The far-field integrals need g beyond the node lattice, which the library
 cannot evaluate; they are caller data, supplied here from the oracle's
 quadrature, so the table pins below check the GPU lattice term, product and
@@ -105,11 +107,69 @@ def test_exterior_tail_and_solve_term():
     assert np.abs(u[0].cpu().numpy() - uc).max() <= 1e-9 * np.abs(uc).max()
 
 
-def test_exterior_rejects_3d():
+def g3(a, b, c):
+    return np.exp(-(a * a + b * b + c * c))
+
+
+def lattice_3d(N, g):
+    x = -1.0 + (2.0 / N) * np.arange(-N, 2 * N + 1)
+    return g(x[:, None, None], x[None, :, None], x[None, None, :])
+
+
+@pytest.mark.parametrize("alpha,p,N", [(1.0, 1, 8), (0.5, 2, 8), (1.7, 0, 6), (1.3, 1, 12),
+                                       (0.8, 1, 5)])
+def test_exterior_lattice_3d(alpha, p, N):
+    print(f"[exterior 3d] alpha={alpha} p={p} N={N}", flush=True)
+    op = make_op(3, alpha, p, N)
+    gl = lattice_3d(N, g3)
+    b = op.exterior(torch.from_numpy(np.stack([gl, -0.5 * gl])).cuda()).cpu().numpy()
+    G = orc_gen(3, alpha, p, N)
+    ref = oracle.exterior_lattice_3d(G, g3)
+    scale = oracle.exterior_lattice_3d(np.abs(G), lambda a, c, e: np.abs(g3(a, c, e)))
+    assert (np.abs(b[0] - ref) <= 1e-11 * scale).all(), float((np.abs(b[0] - ref) / scale).max())
+    assert (np.abs(b[1] + 0.5 * ref) <= 1e-11 * scale).all()
+
+
+@pytest.mark.parametrize("d,N", [(2, 512), (3, 128)])
+def test_exterior_unit_data_full_size(d, N):
+    """g = 1: b + A 1 is the whole offset-box sum of G, c_{d,alpha} 2^d T_d,
+    at the largest supported sizes (a property that holds at any N)."""
+    alpha = 1.4
+    print(f"[exterior unit data] d={d} N={N}", flush=True)
+    op = make_op(d, alpha, 1, N)
+    L = 3 * N + 1
+    b = op.exterior(torch.ones((1,) + (L,) * d, dtype=torch.float64).cuda())
+    a1 = op.apply(torch.ones((1,) + (N - 1,) * d, dtype=torch.float64).cuda())
+    tot = (a1 + b)[0].cpu().numpy()
+    full = oracle.c_dalpha(d, alpha) * 2 ** d * oracle.far_field_T(d, alpha)
+    Gg = op.generator()
+    # sum of |G| over the offset box: each k >= 0 with z zero entries stands for 2^(d-z) offsets
+    mult = np.ones((N + 1,) * d)
+    for s in range(d):
+        shape = [1] * d
+        shape[s] = N + 1
+        mult = mult * np.where(np.arange(N + 1) == 0, 1.0, 2.0).reshape(shape)
+    scale = float((mult * np.abs(Gg)).sum())
+    assert np.abs(tot - full).max() <= 1e-12 * scale, (np.abs(tot - full).max(), scale)
+
+
+def test_exterior_solve_3d():
+    """fl_solve with the 3D exterior term b solves A u = f - b."""
+    N, alpha = 8, 1.2
+    op = make_op(3, alpha, 1, N)
+    b = op.exterior(torch.from_numpy(lattice_3d(N, g3)[None].copy()).cuda())
+    f = torch.from_numpy(np.random.default_rng(5).uniform(-1, 1, (1, N - 1, N - 1, N - 1))).cuda()
+    u, info = op.solve(f, tol=1e-12, b=b)
+    G = orc_gen(3, alpha, 1, N)
+    uc = oracle.solve_cholesky(G, f[0].cpu().numpy() - oracle.exterior_lattice_3d(G, g3))
+    assert np.abs(u[0].cpu().numpy() - uc).max() <= 1e-9 * np.abs(uc).max()
+
+
+def test_exterior_rejects_box():
     import paper_2103_03658_amd as fl
-    op = make_op(3, 1.0, 1, 8)
+    op = fl.Operator(2, 1.0, 1, box=(8, 6))
     with pytest.raises(fl.FlError):
-        op.exterior(torch.zeros((1, 25, 25, 25), dtype=torch.float64).cuda())
+        op.exterior(torch.zeros((1, 25, 25), dtype=torch.float64).cuda())
 
 
 @pytest.mark.parametrize("row", [r for r in load("table_3_1_3") if int(r[1]) <= 1],
