@@ -228,17 +228,19 @@ fl_status fl_solve(fl_op A, const double *f, const double *g, double tol, int ma
  *            g(x_i + (-1)^m o xi) K(|xi|) |xi|^{-d-alpha} d xi.
  * The lattice sum runs on the GPU (a multilevel Toeplitz product of G with g
  * on the node lattice, by circulant embedding in P = 2M >= 4N points per axis
- * for d = 2, 3, directly for d = 1).  The far-field integrals need g beyond
- * the lattice, which the library cannot evaluate: the caller supplies them.
+ * for d = 2, 3, directly for d = 1; for d = 2 with M = 2048 the lattice is
+ * cut into 3 x 3 blocks whose circular products of length M are summed as
+ * spectra).  The far-field integrals need g beyond the lattice, which the
+ * library cannot evaluate: the caller supplies them.
  *   g_lat  device, nrhs * (3N+1)^d doubles: g(x_j), x_j = -1 + j h for
  *          j in [-N, 2N]^d, row-major, last index fastest (entries at
  *          interior nodes are ignored)
  *   tail   device, nrhs * n^d doubles (interior layout), or NULL (tail = 0)
  *   b      device, nrhs * n^d doubles, output
- * FL_E_UNSUPPORTED for a box, and unless d = 1, d = 2 with M <= 1024 or
- * d = 3 with M <= 512.  Same stream rules as fl_apply; allocates its
- * transform buffers (2 P^d complex doubles for d = 2, 3: 4.3 GB at d = 3,
- * N = 128) on first use and keeps them with the operator.
+ * FL_E_UNSUPPORTED for a box, and for d = 3 with M > 512.  Same stream
+ * rules as fl_apply; allocates its transform buffers on first use and keeps
+ * them with the operator: 2 P^d complex doubles (4.3 GB at d = 3, N = 128),
+ * 11 M^2 for the 2D block form (0.74 GB at M = 2048).
  */
 fl_status fl_exterior(fl_op A, const double *g_lat, const double *tail, double *b, int nrhs,
                       void *stream);

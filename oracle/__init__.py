@@ -50,7 +50,8 @@ from .operator import (origin_rule, coefficients, generator, generator_expsum, g
                        embed_generator, symbol, precond_apply, tau_symbol,
                        tau_precond_apply,
                        exterior_b_1d, exterior_b_2d, exterior_lattice_1d,
-                       exterior_lattice_2d, exterior_lattice_3d, far_field_tail_1d,
+                       exterior_lattice_2d, exterior_lattice_2d_at, exterior_lattice_3d,
+                       far_field_tail_1d,
                        far_field_tail_2d,
                        grid_points)
 from .solve import solve_cholesky, solve_cg
@@ -60,6 +61,6 @@ __all__ = [
     "c_dalpha", "far_field_T", "K_ball", "weights", "weights_at", "origin_rule",
     "coefficients", "generator", "generator_expsum", "generator_at", "dense_matrix", "apply_dense", "apply_bttb",
     "apply", "apply_rows", "embed_generator", "symbol", "precond_apply", "tau_symbol", "tau_precond_apply", "exterior_b_1d", "exterior_b_2d",
-    "exterior_lattice_1d", "exterior_lattice_2d", "exterior_lattice_3d", "far_field_tail_1d", "far_field_tail_2d",
+    "exterior_lattice_1d", "exterior_lattice_2d", "exterior_lattice_2d_at", "exterior_lattice_3d", "far_field_tail_1d", "far_field_tail_2d",
     "grid_points", "solve_cholesky", "solve_cg", "continuous", "exact",
 ]

@@ -393,18 +393,24 @@ def exterior_lattice_2d(G, g):
     the sum of G_{|k|} g(x_{i+k}) over the offsets k in [-N, N]^2 whose node
     i + k is outside the interior.  g must accept numpy arrays (x1, x2)."""
     N = G.shape[0] - 1
-    h = 2.0 / N
     n = N - 1
+    nodes = [(i, jj) for i in range(1, N) for jj in range(1, N)]
+    return exterior_lattice_2d_at(G, g, nodes).reshape(n, n)
+
+
+def exterior_lattice_2d_at(G, g, nodes):
+    """exterior_lattice_2d at the listed interior nodes (i, j), 1 <= i, j <= N - 1."""
+    N = G.shape[0] - 1
+    h = 2.0 / N
     k = np.arange(-N, N + 1)
     Gs = G[np.abs(k)[:, None], np.abs(k)[None, :]]        # symmetric stencil
-    out = np.zeros((n, n))
-    for i in range(1, N):
+    out = np.zeros(len(nodes))
+    for t, (i, jj) in enumerate(nodes):
         a0 = i + k
-        for jj in range(1, N):
-            a1 = jj + k
-            inside = ((a0 >= 1) & (a0 <= N - 1))[:, None] & ((a1 >= 1) & (a1 <= N - 1))[None, :]
-            vals = g((-1.0 + a0 * h)[:, None], (-1.0 + a1 * h)[None, :])
-            out[i - 1, jj - 1] = math.fsum((Gs * vals)[~inside].ravel())
+        a1 = jj + k
+        inside = ((a0 >= 1) & (a0 <= N - 1))[:, None] & ((a1 >= 1) & (a1 <= N - 1))[None, :]
+        vals = g((-1.0 + a0 * h)[:, None], (-1.0 + a1 * h)[None, :])
+        out[t] = math.fsum((Gs * vals)[~inside].ravel())
     return out
 
 

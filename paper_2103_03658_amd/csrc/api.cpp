@@ -1033,14 +1033,14 @@ extern "C" fl_status fl_exterior(fl_op A, const double* g_lat, const double* tai
     if (!g_lat || !b) return fail(FL_E_INVAL, "null argument");
     if (nrhs < 1) return fail(FL_E_INVAL, "nrhs must be >= 1");
     if (!fl::exterior_supported(A->g))
-      return fail(FL_E_UNSUPPORTED,
-                  "exterior data: the cube with d = 1, d = 2 with M <= 1024 or d = 3 with M <= 512");
+      return fail(FL_E_UNSUPPORTED, "exterior data: the cube with d = 1, 2, or d = 3 with M <= 512");
     set_device(A);
     hipStream_t st = (hipStream_t)stream;
     A->begin(st);
     const size_t kb = fl::exterior_khat_bytes(A->g);
     void* kh = kb ? A->ext_khat.get(kb) : nullptr;
-    void* wk = kb ? A->ext_work.get(kb) : nullptr;
+    const size_t wb = fl::exterior_work_bytes(A->g);
+    void* wk = wb ? A->ext_work.get(wb) : nullptr;
     fl::exterior_term(A->g, A->G, A->c, g_lat, tail, b, nrhs, kh, A->ext_ready, wk, st);
     A->ext_ready = kb != 0;
     A->end(st);

@@ -9,8 +9,14 @@
 // j + N in [0, 3N] and G wrapped to k mod P for |k| <= N, every offset i - j
 // of an interior i and a lattice j falls in [1 - 2N, 2N - 1], and those with
 // |i - j| > N land in the zero band (N, 3N) of the wrapped generator, so the
-// circular product restricted to the interior is the lattice sum.  In 1D the
-// sum over the 2N + 1 offsets is taken directly.
+// circular product restricted to the interior is the lattice sum.  When 4N
+// points exceed the longest transform (2D, N > 512) each axis of the lattice
+// is cut into the blocks [-N, -1], [0, N] and [N+1, 2N]: for an interior i
+// and a node j of a block from lo to hi the offset i - j spans fewer than
+// 2N <= M values, so with the block's data placed from position 0 and the
+// generator at (i - j + lo) mod M, a circular product of length M is exact at
+// positions i; the 3^d block products are summed as spectra and transformed
+// back once.  In 1D the sum over the 2N + 1 offsets is taken directly.
 
 #include <hip/hip_runtime.h>
 
@@ -67,9 +73,86 @@ __global__ void k_mul_spectra(cx<double>* D, const cx<double>* K, long total) {
   if (e < total) D[e] = cmul(D[e], K[e]);
 }
 
-// b_i = Re D[i + N] / P^d - c tail_i over the interior i in [1, N-1]^d.
-__global__ void k_take_interior(const cx<double>* D, int d, int N, int P, long nd, double scale,
-                                const double* tail, double c, double* b) {
+// Lattice blocks per axis: index a = 0, 1, 2 covers nodes [lo, hi].
+struct AxisBlocks {
+  int lo[3], hi[3];
+};
+
+__host__ __device__ inline AxisBlocks axis_blocks(int N) {
+  return {{-N, 0, N + 1}, {-1, N, 2 * N}};
+}
+
+// Generator of block (a_0, .., a_{d-1}) on P^d: position q_s holds the offset
+// k_s = v_s - lo_s, v_s = q_s (q_s <= N - 1) or q_s - P, for the offsets of
+// the block's range with |k_s| <= N; zero elsewhere.
+__global__ void k_block_generator(const double* G, int d, int N, int P, int blk, long total,
+                                  cx<double>* K) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const AxisBlocks ab = axis_blocks(N);
+  long rem = e, gi = 0;
+  bool ok = true;
+  int q[3] = {0, 0, 0}, a[3] = {0, 0, 0};
+  for (int s = d - 1; s >= 0; --s) {
+    q[s] = (int)(rem % P);
+    rem /= P;
+  }
+  for (int s = d - 1, b = blk; s >= 0; --s) {
+    a[s] = b % 3;
+    b /= 3;
+  }
+  for (int s = 0; s < d; ++s) {
+    const int lo = ab.lo[a[s]], hi = ab.hi[a[s]];
+    const int v = q[s] <= N - 1 ? q[s] : q[s] - P;
+    const int k = v - lo;
+    // offsets of interior i in [1, N-1] and j in [lo, hi]
+    if (k < 1 - hi || k > N - 1 - lo || k < -N || k > N) ok = false;
+    gi = gi * (N + 1) + (ok ? (k < 0 ? -k : k) : 0);
+  }
+  K[e] = {ok ? G[gi] : 0.0, 0.0};
+}
+
+// Exterior data of block blk on P^d: position q_s holds node lo_s + q_s for
+// q_s <= hi_s - lo_s; interior nodes are zero.
+__global__ void k_place_block(const double* g, int d, int N, int P, int blk, long total,
+                              cx<double>* D) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const AxisBlocks ab = axis_blocks(N);
+  const int L = 3 * N + 1;
+  long rem = e, gi = 0;
+  bool in = true, interior = true;
+  int q[3] = {0, 0, 0}, a[3] = {0, 0, 0};
+  for (int s = d - 1; s >= 0; --s) {
+    q[s] = (int)(rem % P);
+    rem /= P;
+  }
+  for (int s = d - 1, b = blk; s >= 0; --s) {
+    a[s] = b % 3;
+    b /= 3;
+  }
+  for (int s = 0; s < d; ++s) {
+    const int lo = ab.lo[a[s]], hi = ab.hi[a[s]];
+    const int j = lo + q[s];
+    if (j > hi) in = false;
+    if (j < 1 || j > N - 1) interior = false;
+    gi = gi * L + (j <= hi ? j + N : 0);
+  }
+  D[e] = {(in && !interior) ? g[gi] : 0.0, 0.0};
+}
+
+// acc (+)= D * K
+__global__ void k_mac_spectra(cx<double>* acc, const cx<double>* D, const cx<double>* K,
+                              long total, int first) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const cx<double> t = cmul(D[e], K[e]);
+  acc[e] = first ? t : cx<double>{acc[e].x + t.x, acc[e].y + t.y};
+}
+
+// b_i = Re D[i + shift] / P^d - c tail_i over the interior i in [1, N-1]^d.
+__global__ void k_take_interior(const cx<double>* D, int d, int N, int P, int shift, long nd,
+                                double scale, const double* tail, double c, double* b) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nd) return;
   const int n = N - 1;
@@ -79,7 +162,7 @@ __global__ void k_take_interior(const cx<double>* D, int d, int N, int P, long n
     i[s] = (int)(rem % n) + 1;
     rem /= n;
   }
-  for (int s = 0; s < d; ++s) pi = pi * P + (i[s] + N);
+  for (int s = 0; s < d; ++s) pi = pi * P + (i[s] + shift);
   b[e] = D[pi].x * scale - (tail ? c * tail[e] : 0.0);
 }
 
@@ -108,21 +191,34 @@ void difference(const double* a, const double* b, double* out, long n, hipStream
   check_launch("difference");
 }
 
+// 2D beyond 4N = 2048 points: the block form on M points per axis.
+static bool blocked(const Geometry& g) { return g.d == 2 && 2 * g.Ma[0] > 2048; }
+
 bool exterior_supported(const Geometry& g) {
   // the cube only (the exterior lattice of a box is not built); the
-  // transforms take P <= 2048 per axis, and in 3D P <= 1024 keeps the two
-  // P^3 complex buffers at 17 GB each
+  // transforms take at most 2048 points per axis, and in 3D P <= 1024 keeps
+  // the two P^3 complex buffers at 17 GB each
   if (!g.cube()) return false;
   const int P = 2 * g.Ma[0];
-  return g.d == 1 || (g.d == 2 && P <= 2048) || (g.d == 3 && P <= 1024);
+  return g.d == 1 || g.d == 2 || (g.d == 3 && P <= 1024);
+}
+
+static long exterior_points(const Geometry& g) {
+  const long P = blocked(g) ? g.Ma[0] : 2L * g.Ma[0];
+  long total = 1;
+  for (int s = 0; s < g.d; ++s) total *= P;
+  return total;
 }
 
 size_t exterior_khat_bytes(const Geometry& g) {
   if (g.d == 1) return 0;
-  const long P = 2L * g.Ma[0];
-  long total = 1;
-  for (int s = 0; s < g.d; ++s) total *= P;
-  return (size_t)total * sizeof(cx<double>);
+  const int nblk = blocked(g) ? 9 : 1;
+  return (size_t)nblk * exterior_points(g) * sizeof(cx<double>);
+}
+
+size_t exterior_work_bytes(const Geometry& g) {
+  if (g.d == 1) return 0;
+  return (size_t)(blocked(g) ? 2 : 1) * exterior_points(g) * sizeof(cx<double>);
 }
 
 void exterior_term(const Geometry& g, const double* G, double c, const double* g_lat,
@@ -140,7 +236,8 @@ void exterior_term(const Geometry& g, const double* G, double c, const double* g
     }
     return;
   }
-  const int P = 2 * g.Ma[0];
+  const bool blk = blocked(g);
+  const int P = blk ? g.Ma[0] : 2 * g.Ma[0];
   const int Pd[3] = {P, P, P};
   long total = 1, Ld = 1;
   for (int s = 0; s < d; ++s) {
@@ -149,13 +246,41 @@ void exterior_term(const Geometry& g, const double* G, double c, const double* g
   }
   cx<double>* K = reinterpret_cast<cx<double>*>(khat);
   cx<double>* D = reinterpret_cast<cx<double>*>(work);
+  const double scale = 1.0 / (double)total;
+  if (blk) {
+    const int nb = 9;
+    if (!khat_ready) {
+      for (int b = 0; b < nb; ++b) {
+        hipLaunchKernelGGL(k_block_generator, dim3(blocks(total, thr)), dim3(thr), 0, st, G, d,
+                           N, P, b, total, K + (long)b * total);
+        check_launch("block generator");
+        fft_full(Pd, d, K + (long)b * total, -1, st);
+      }
+    }
+    cx<double>* acc = D + total;
+    for (int o = 0; o < nrhs; ++o) {
+      for (int b = 0; b < nb; ++b) {
+        hipLaunchKernelGGL(k_place_block, dim3(blocks(total, thr)), dim3(thr), 0, st,
+                           g_lat + (long)o * Ld, d, N, P, b, total, D);
+        check_launch("place block");
+        fft_full(Pd, d, D, -1, st);
+        hipLaunchKernelGGL(k_mac_spectra, dim3(blocks(total, thr)), dim3(thr), 0, st, acc, D,
+                           K + (long)b * total, total, b == 0 ? 1 : 0);
+        check_launch("block spectra");
+      }
+      fft_full(Pd, d, acc, 1, st);
+      hipLaunchKernelGGL(k_take_interior, dim3(blocks(nd, thr)), dim3(thr), 0, st, acc, d, N, P,
+                         0, nd, scale, tail ? tail + (long)o * nd : nullptr, c, b + (long)o * nd);
+      check_launch("interior restriction");
+    }
+    return;
+  }
   if (!khat_ready) {
     hipLaunchKernelGGL(k_wrap_generator, dim3(blocks(total, thr)), dim3(thr), 0, st, G, d, N, P,
                        total, K);
     check_launch("wrap generator");
     fft_full(Pd, d, K, -1, st);
   }
-  const double scale = 1.0 / (double)total;
   for (int o = 0; o < nrhs; ++o) {
     hipLaunchKernelGGL(k_place_exterior, dim3(blocks(total, thr)), dim3(thr), 0, st,
                        g_lat + (long)o * Ld, d, N, P, total, D);
@@ -164,8 +289,8 @@ void exterior_term(const Geometry& g, const double* G, double c, const double* g
     hipLaunchKernelGGL(k_mul_spectra, dim3(blocks(total, thr)), dim3(thr), 0, st, D, K, total);
     check_launch("spectra product");
     fft_full(Pd, d, D, 1, st);
-    hipLaunchKernelGGL(k_take_interior, dim3(blocks(nd, thr)), dim3(thr), 0, st, D, d, N, P, nd,
-                       scale, tail ? tail + (long)o * nd : nullptr, c, b + (long)o * nd);
+    hipLaunchKernelGGL(k_take_interior, dim3(blocks(nd, thr)), dim3(thr), 0, st, D, d, N, P, N,
+                       nd, scale, tail ? tail + (long)o * nd : nullptr, c, b + (long)o * nd);
     check_launch("interior restriction");
   }
 }

@@ -197,11 +197,13 @@ void build_symbol(const Geometry& g, const double* G, double* lam64, float* lam3
 void embed_generator(const Geometry& g, const double* G, double* out, hipStream_t st);
 // Exterior-data term (exterior unit): b = lattice sum of G with g on
 // [-N, 2N]^d minus c * tail (tail may be null).  khat: the transformed
-// wrapped generator (exterior_khat_bytes), filled when !khat_ready; work:
-// the same size.  Supported for d = 1 and d = 2 with 2M <= 2048.
+// wrapped generator(s) (exterior_khat_bytes), filled when !khat_ready; work:
+// exterior_work_bytes.  Supported on the cube for d = 1, 2 and for d = 3
+// with 2M <= 1024.
 bool exterior_supported(const Geometry& g);
 void difference(const double* a, const double* b, double* out, long n, hipStream_t st);
 size_t exterior_khat_bytes(const Geometry& g);
+size_t exterior_work_bytes(const Geometry& g);
 void exterior_term(const Geometry& g, const double* G, double c, const double* g_lat,
                    const double* tail, double* b, int nrhs, void* khat, bool khat_ready,
                    void* work, hipStream_t st);

@@ -3,8 +3,9 @@ exterior term).
 
 The lattice part of the term (the sum of G_{|j-i|} g(x_j) over exterior
 nodes) is computed by the library and compared with the oracle's direct sum
-(1D, 2D and 3D), and at the largest supported sizes (2D N = 512, 3D N = 128)
-through the identity b + A 1 = c_{d,alpha} 2^d T_d for g = 1.
+(1D, 2D and 3D; sampled nodes for the 2D block form at N = 600 and 1024), and
+at the largest supported sizes (2D N = 512 and 1024, 3D N = 128) through the
+identity b + A 1 = c_{d,alpha} 2^d T_d for g = 1.
 The far-field integrals need g beyond the node lattice, which the library
 cannot evaluate; they are caller data, supplied here from the oracle's
 quadrature, so the table pins below check the GPU lattice term, product and
@@ -130,7 +131,28 @@ def test_exterior_lattice_3d(alpha, p, N):
     assert (np.abs(b[1] + 0.5 * ref) <= 1e-11 * scale).all()
 
 
-@pytest.mark.parametrize("d,N", [(2, 512), (3, 128)])
+@pytest.mark.parametrize("N", [600, 1024])
+def test_exterior_block_form_sampled(N):
+    """2D with 4N > 2048 points (the lattice cut into 3 x 3 blocks): sampled
+    interior nodes against the oracle's direct sum."""
+    print(f"[exterior 2d block form] N={N}", flush=True)
+    alpha = 1.3
+    op = make_op(2, alpha, 1, N)
+    gl = lattice_2d(N, g2)
+    b = op.exterior(torch.from_numpy(np.stack([gl, 3.0 * gl])).cuda()).cpu().numpy()
+    G = orc_gen(2, alpha, 1, N)
+    rng = np.random.default_rng(11)
+    nodes = [(1, 1), (N - 1, N - 1), (1, N - 1), (N // 2, 1), (N // 2, N // 2), (2, N - 2)]
+    nodes += [tuple(int(v) for v in rng.integers(1, N, size=2)) for _ in range(6)]
+    ref = oracle.exterior_lattice_2d_at(G, g2, nodes)
+    scale = oracle.exterior_lattice_2d_at(np.abs(G), lambda a, c: np.abs(g2(a, c)), nodes)
+    got = np.array([b[0][i - 1, j - 1] for i, j in nodes])
+    got3 = np.array([b[1][i - 1, j - 1] for i, j in nodes])
+    assert (np.abs(got - ref) <= 1e-11 * scale).all(), float((np.abs(got - ref) / scale).max())
+    assert (np.abs(got3 - 3.0 * ref) <= 3e-11 * scale).all()
+
+
+@pytest.mark.parametrize("d,N", [(2, 512), (2, 1024), (3, 128)])
 def test_exterior_unit_data_full_size(d, N):
     """g = 1: b + A 1 is the whole offset-box sum of G, c_{d,alpha} 2^d T_d,
     at the largest supported sizes (a property that holds at any N)."""
