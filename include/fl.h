@@ -115,7 +115,8 @@ fl_status fl_weights_gamma(int d, double alpha, int degree, double h, int kernel
  * Other arguments and errors as fl_weights_gamma.  Vectors are row-major
  * over n_0 x .. x n_{d-1} (n_s = intervals[s] - 1, last index fastest).
  * The tau preconditioner needs every 2 intervals[s] to be a power of two
- * (otherwise the default is kind 1); fl_exterior supports the cube only.
+ * (otherwise the default is kind 1).  fl_exterior takes the box's node
+ * lattice [-N, N_s + N] along axis s.
  */
 fl_status fl_weights_box(int d, double alpha, int degree, const int *intervals, int kernel,
                          double lambda, double gamma, void *stream, fl_op *out);
@@ -226,21 +227,24 @@ fl_status fl_solve(fl_op A, const double *f, const double *g, double tol, int ma
  *   tail_i = sum over the 2^d sign patterns m of the integral over the far
  *            field (xi >= 0 outside the box [0, L]^d, L = 2) of
  *            g(x_i + (-1)^m o xi) K(|xi|) |xi|^{-d-alpha} d xi.
- * The lattice sum runs on the GPU (a multilevel Toeplitz product of G with g
- * on the node lattice, by circulant embedding in P = 2M >= 4N points per axis
- * for d = 2, 3, directly for d = 1; for d = 2 with M = 2048 the lattice is
- * cut into 3 x 3 blocks whose circular products of length M are summed as
- * spectra).  The far-field integrals need g beyond the lattice, which the
- * library cannot evaluate: the caller supplies them.
- *   g_lat  device, nrhs * (3N+1)^d doubles: g(x_j), x_j = -1 + j h for
- *          j in [-N, 2N]^d, row-major, last index fastest (entries at
- *          interior nodes are ignored)
+ * On a box (fl_weights_box) axis s has the interior nodes 1 .. N_s - 1 and
+ * the node lattice [-N, N_s + N] (N_s = N on the cube).  The lattice sum runs
+ * on the GPU (a multilevel Toeplitz product of G with g on the node lattice:
+ * for d = 2, 3 by circulant embedding in P_s >= N_s + 2N + 1 points per axis,
+ * or for d = 2 beyond 2048 points by 3 x 3 lattice blocks whose circular
+ * products of length P_s >= max(2 N_s, N_s + N) are summed as spectra;
+ * directly for d = 1).  The far-field integrals need g beyond the lattice,
+ * which the library cannot evaluate: the caller supplies them.
+ *   g_lat  device, nrhs * prod_s (N_s + 2N + 1) doubles: g(x_j), x_j = -1 +
+ *          j h for j_s in [-N, N_s + N], row-major, last index fastest
+ *          (entries at interior nodes are ignored)
  *   tail   device, nrhs * n^d doubles (interior layout), or NULL (tail = 0)
  *   b      device, nrhs * n^d doubles, output
- * FL_E_UNSUPPORTED for a box, and for d = 3 with M > 512.  Same stream
- * rules as fl_apply; allocates its transform buffers on first use and keeps
- * them with the operator: 2 P^d complex doubles (4.3 GB at d = 3, N = 128),
- * 11 M^2 for the 2D block form (0.74 GB at M = 2048).
+ * FL_E_UNSUPPORTED for d = 3 beyond 1024^3 transform points (N <= 256 on
+ * the cube).  Same stream rules as fl_apply; allocates its transform
+ * buffers on first use and keeps them with the operator: 2 prod P_s complex
+ * doubles (4.3 GB at d = 3, N = 128), 11 prod P_s for the 2D block form
+ * (0.74 GB at N = 1024).
  */
 fl_status fl_exterior(fl_op A, const double *g_lat, const double *tail, double *b, int nrhs,
                       void *stream);

@@ -352,15 +352,17 @@ def tau_precond_apply(G, v, floor_rel=1e-12):
     return y * np.prod([2.0 / (n + 1) for n in shp])
 
 
-def exterior_lattice_1d(G, g):
-    """Lattice part of bold-b_i: sum over exterior nodes j (j <= 0 or j >= N,
-    |j - i| <= N) of G_{|j-i|} g(x_j), x_j = -1 + j h (eq. (1D-scheme))."""
+def exterior_lattice_1d(G, g, intervals=None):
+    """Lattice part of bold-b_i: sum over exterior nodes j (j <= 0 or j >= N_0,
+    |j - i| <= N) of G_{|j-i|} g(x_j), x_j = -1 + j h (eq. (1D-scheme)); N_0 =
+    intervals[0] intervals (N by default)."""
     N = G.shape[0] - 1
+    Na = N if intervals is None else intervals[0]
     h = 2.0 / N
-    out = np.zeros(N - 1)
-    for i in range(1, N):
+    out = np.zeros(Na - 1)
+    for i in range(1, Na):
         s = 0.0
-        for j in list(range(i - N, 1)) + list(range(N, i + N + 1)):
+        for j in list(range(i - N, 1)) + list(range(Na, i + N + 1)):
             s += G[abs(j - i)] * g(-1.0 + j * h)
         out[i - 1] = s
     return out
@@ -388,19 +390,22 @@ def exterior_b_1d(G, g, alpha, lam=0.0):
     return exterior_lattice_1d(G, g) - c_dalpha(1, alpha) * far_field_tail_1d(N, g, alpha, lam)
 
 
-def exterior_lattice_2d(G, g):
+def exterior_lattice_2d(G, g, intervals=None):
     """Lattice part of bold-b_ij (eq. (2D-scheme)): for every interior node,
     the sum of G_{|k|} g(x_{i+k}) over the offsets k in [-N, N]^2 whose node
-    i + k is outside the interior.  g must accept numpy arrays (x1, x2)."""
+    i + k is outside the interior.  g must accept numpy arrays (x1, x2).
+    intervals = (N_0, N_1) for a box (Sec. 2.2), the cube by default."""
     N = G.shape[0] - 1
-    n = N - 1
-    nodes = [(i, jj) for i in range(1, N) for jj in range(1, N)]
-    return exterior_lattice_2d_at(G, g, nodes).reshape(n, n)
+    Na = (N, N) if intervals is None else tuple(intervals)
+    nodes = [(i, jj) for i in range(1, Na[0]) for jj in range(1, Na[1])]
+    return exterior_lattice_2d_at(G, g, nodes, Na).reshape(Na[0] - 1, Na[1] - 1)
 
 
-def exterior_lattice_2d_at(G, g, nodes):
-    """exterior_lattice_2d at the listed interior nodes (i, j), 1 <= i, j <= N - 1."""
+def exterior_lattice_2d_at(G, g, nodes, intervals=None):
+    """exterior_lattice_2d at the listed interior nodes (i, j), 1 <= i < N_0,
+    1 <= j < N_1."""
     N = G.shape[0] - 1
+    Na = (N, N) if intervals is None else tuple(intervals)
     h = 2.0 / N
     k = np.arange(-N, N + 1)
     Gs = G[np.abs(k)[:, None], np.abs(k)[None, :]]        # symmetric stencil
@@ -408,34 +413,35 @@ def exterior_lattice_2d_at(G, g, nodes):
     for t, (i, jj) in enumerate(nodes):
         a0 = i + k
         a1 = jj + k
-        inside = ((a0 >= 1) & (a0 <= N - 1))[:, None] & ((a1 >= 1) & (a1 <= N - 1))[None, :]
+        inside = (((a0 >= 1) & (a0 <= Na[0] - 1))[:, None]
+                  & ((a1 >= 1) & (a1 <= Na[1] - 1))[None, :])
         vals = g((-1.0 + a0 * h)[:, None], (-1.0 + a1 * h)[None, :])
         out[t] = math.fsum((Gs * vals)[~inside].ravel())
     return out
 
 
-def exterior_lattice_3d(G, g):
+def exterior_lattice_3d(G, g, intervals=None):
     """Lattice part of the exterior-data term in 3D (the 2D definition of
     bold-b_ij, eq. (2D-scheme), taken over three axes: reading R4): for every
     interior node, the sum of G_{|k|} g(x_{i+k}) over the offsets k in
     [-N, N]^3 whose node i + k is outside the interior.  g must accept numpy
-    arrays (x1, x2, x3)."""
+    arrays (x1, x2, x3).  intervals = (N_0, N_1, N_2) for a box."""
     N = G.shape[0] - 1
+    Na = (N, N, N) if intervals is None else tuple(intervals)
     h = 2.0 / N
-    n = N - 1
     k = np.arange(-N, N + 1)
     ak = np.abs(k)
     Gs = G[ak[:, None, None], ak[None, :, None], ak[None, None, :]]
-    out = np.zeros((n, n, n))
-    for i0 in range(1, N):
+    out = np.zeros(tuple(v - 1 for v in Na))
+    for i0 in range(1, Na[0]):
         a0 = i0 + k
-        in0 = (a0 >= 1) & (a0 <= N - 1)
-        for i1 in range(1, N):
+        in0 = (a0 >= 1) & (a0 <= Na[0] - 1)
+        for i1 in range(1, Na[1]):
             a1 = i1 + k
-            in1 = (a1 >= 1) & (a1 <= N - 1)
-            for i2 in range(1, N):
+            in1 = (a1 >= 1) & (a1 <= Na[1] - 1)
+            for i2 in range(1, Na[2]):
                 a2 = i2 + k
-                in2 = (a2 >= 1) & (a2 <= N - 1)
+                in2 = (a2 >= 1) & (a2 <= Na[2] - 1)
                 inside = in0[:, None, None] & in1[None, :, None] & in2[None, None, :]
                 vals = g((-1.0 + a0 * h)[:, None, None], (-1.0 + a1 * h)[None, :, None],
                          (-1.0 + a2 * h)[None, None, :])

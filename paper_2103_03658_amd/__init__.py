@@ -144,21 +144,23 @@ class Operator:
 
     def exterior(self, g_lat, tail=None, out=None, stream=None):
         """Exterior-data term b (fl_exterior): g_lat holds g on the node
-        lattice [-N, 2N]^d, shape (nrhs, 3N+1, ...); tail the far-field
-        integrals per interior point (nrhs, n, ...) or None."""
+        lattice, [-N, N_s + N] along axis s (N_s = N on the cube), shape
+        (nrhs, N_0 + 2N + 1, ...); tail the far-field integrals per interior
+        point (nrhs, n_0, ...) or None."""
         import torch
         if g_lat.dtype != torch.float64 or not g_lat.is_contiguous():
             raise TypeError("g_lat must be a contiguous float64 tensor")
-        L = 3 * self.N + 1
-        if g_lat.numel() % (L ** self.d):
-            raise ValueError(f"g_lat must hold nrhs * {L}^{self.d} values")
-        nrhs = g_lat.numel() // L ** self.d
+        lat = 1
+        for v in self.intervals:
+            lat *= v + 2 * self.N + 1
+        if g_lat.numel() % lat:
+            raise ValueError(f"g_lat must hold nrhs * {lat} values")
+        nrhs = g_lat.numel() // lat
         if tail is not None and (tail.dtype != torch.float64 or tail.numel() != nrhs * self.nd
                                  or not tail.is_contiguous()):
             raise ValueError("tail must be a contiguous float64 tensor of nrhs * n^d values")
         if out is None:
-            out = torch.empty((nrhs,) + (self.N - 1,) * self.d, dtype=torch.float64,
-                              device=g_lat.device)
+            out = torch.empty((nrhs,) + self.shape, dtype=torch.float64, device=g_lat.device)
         check(self._lib.fl_exterior(self._h, ctypes.c_void_p(g_lat.data_ptr()),
                                     ctypes.c_void_p(tail.data_ptr()) if tail is not None
                                     else None, ctypes.c_void_p(out.data_ptr()), nrhs,

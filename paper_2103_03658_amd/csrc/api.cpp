@@ -1033,7 +1033,8 @@ extern "C" fl_status fl_exterior(fl_op A, const double* g_lat, const double* tai
     if (!g_lat || !b) return fail(FL_E_INVAL, "null argument");
     if (nrhs < 1) return fail(FL_E_INVAL, "nrhs must be >= 1");
     if (!fl::exterior_supported(A->g))
-      return fail(FL_E_UNSUPPORTED, "exterior data: the cube with d = 1, 2, or d = 3 with M <= 512");
+      return fail(FL_E_UNSUPPORTED,
+                  "exterior data: d = 3 needs at most 1024^3 transform points (N <= 256)");
     set_device(A);
     hipStream_t st = (hipStream_t)stream;
     A->begin(st);

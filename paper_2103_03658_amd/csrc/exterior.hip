@@ -3,20 +3,27 @@
 // of their matrix forms):
 //   b_i = sum over exterior lattice nodes j, |j - i|_inf <= N, of G_{|j-i|} g(x_j)
 //         - c_{d,alpha} tail_i
-// The lattice sum is a multilevel Toeplitz product of G with g on the node
-// lattice [-N, 2N]^d (zero on the interior nodes).  In 2D and 3D it is done
-// by circulant embedding in P = 4N points per axis: with the data at offset
-// j + N in [0, 3N] and G wrapped to k mod P for |k| <= N, every offset i - j
-// of an interior i and a lattice j falls in [1 - 2N, 2N - 1], and those with
-// |i - j| > N land in the zero band (N, 3N) of the wrapped generator, so the
-// circular product restricted to the interior is the lattice sum.  When 4N
-// points exceed the longest transform (2D, N > 512) each axis of the lattice
-// is cut into the blocks [-N, -1], [0, N] and [N+1, 2N]: for an interior i
-// and a node j of a block from lo to hi the offset i - j spans fewer than
-// 2N <= M values, so with the block's data placed from position 0 and the
-// generator at (i - j + lo) mod M, a circular product of length M is exact at
-// positions i; the 3^d block products are summed as spectra and transformed
-// back once.  In 1D the sum over the 2N + 1 offsets is taken directly.
+// Axis s of the grid has Na_s intervals (Na_s = N on the cube), interior
+// nodes 1..Na_s - 1 and the node lattice [-N, Na_s + N] (length L_s =
+// Na_s + 2N + 1); the lattice sum is a multilevel Toeplitz product of G with
+// g on that lattice (zero on the interior nodes).
+//
+// Direct form (2D, 3D): circular embedding in P_s >= L_s points per axis,
+// data at j + N, G wrapped to k mod P_s for |k| <= N.  Every offset i - j of
+// an interior i and a lattice j lies in [1 - Na_s - N, Na_s + N - 1], and
+// those with |i - j| > N land in the zero band (N, P_s - N) of the wrapped
+// generator, so the circular product restricted to the interior is the sum.
+//
+// Block form (2D, when some L_s would need more than 2048 points): each axis
+// of the lattice is cut into [-N, -1], [0, Na_s] and [Na_s + 1, Na_s + N].
+// For an interior i and the nodes j of a block from lo to hi, the offsets
+// i - j take fewer than P_s >= max(2 Na_s, Na_s + N) distinct values, so with
+// the block's data placed from position 0 and G at (i - j + lo) mod P_s (for
+// the block's offsets with |i - j| <= N, zero elsewhere) a circular product
+// of length P_s is exact at positions i; the 3^d block products are summed
+// as spectra and transformed back once.
+//
+// In 1D the sum over the 2N + 1 offsets is taken directly.
 
 #include <hip/hip_runtime.h>
 
@@ -25,19 +32,30 @@
 namespace fl {
 namespace {
 
-// Wrapped generator on P^d: K[q] = G_{|k|}, k = q or q - P, |k_s| <= N.
-__global__ void k_wrap_generator(const double* G, int d, int N, int P, long total,
-                                 cx<double>* K) {
+struct ExtGeom {
+  int d, N;
+  int Na[3];   // intervals per axis
+  int L[3];    // lattice length per axis, Na + 2N + 1
+  int P[3];    // transform length per axis
+};
+
+__device__ inline void split_index(long e, const ExtGeom& x, int* q) {
+  for (int s = x.d - 1; s >= 0; --s) {
+    q[s] = (int)(e % x.P[s]);
+    e /= x.P[s];
+  }
+}
+
+// Direct form: wrapped generator K[q] = G_{|k|}, k_s = q_s or q_s - P_s, |k_s| <= N.
+__global__ void k_wrap_generator(const double* G, ExtGeom x, long total, cx<double>* K) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
-  long rem = e, gi = 0;
-  bool inside = true;
   int q[3] = {0, 0, 0};
-  for (int s = d - 1; s >= 0; --s) {
-    q[s] = (int)(rem % P);
-    rem /= P;
-  }
-  for (int s = 0; s < d; ++s) {
+  split_index(e, x, q);
+  long gi = 0;
+  bool inside = true;
+  for (int s = 0; s < x.d; ++s) {
+    const int P = x.P[s], N = x.N;
     const int k = q[s] <= N ? q[s] : (q[s] >= P - N ? P - q[s] : -1);
     if (k < 0) inside = false;
     gi = gi * (N + 1) + (k < 0 ? 0 : k);
@@ -45,100 +63,86 @@ __global__ void k_wrap_generator(const double* G, int d, int N, int P, long tota
   K[e] = {inside ? G[gi] : 0.0, 0.0};
 }
 
-// Exterior lattice data on P^d: position j + N for j in [-N, 2N]^d, zero on
-// interior nodes (1 <= j_s <= N - 1 for every s) and beyond 3N.
-__global__ void k_place_exterior(const double* g, int d, int N, int P, long total,
-                                 cx<double>* D) {
+// Direct form: exterior lattice data at position j + N, zero on interior
+// nodes (1 <= j_s <= Na_s - 1 for every s) and beyond the lattice.
+__global__ void k_place_exterior(const double* g, ExtGeom x, long total, cx<double>* D) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
-  const int L = 3 * N + 1;
-  long rem = e, gi = 0;
-  bool inlat = true, interior = true;
   int q[3] = {0, 0, 0};
-  for (int s = d - 1; s >= 0; --s) {
-    q[s] = (int)(rem % P);
-    rem /= P;
-  }
-  for (int s = 0; s < d; ++s) {
-    if (q[s] >= L) inlat = false;
-    const int j = q[s] - N;
-    if (j < 1 || j > N - 1) interior = false;
-    gi = gi * L + (q[s] < L ? q[s] : 0);
+  split_index(e, x, q);
+  long gi = 0;
+  bool inlat = true, interior = true;
+  for (int s = 0; s < x.d; ++s) {
+    if (q[s] >= x.L[s]) inlat = false;
+    const int j = q[s] - x.N;
+    if (j < 1 || j > x.Na[s] - 1) interior = false;
+    gi = gi * x.L[s] + (q[s] < x.L[s] ? q[s] : 0);
   }
   D[e] = {(inlat && !interior) ? g[gi] : 0.0, 0.0};
 }
 
-__global__ void k_mul_spectra(cx<double>* D, const cx<double>* K, long total) {
-  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e < total) D[e] = cmul(D[e], K[e]);
+// Block form: block a_s of axis s covers nodes [lo, hi].
+__device__ inline void block_range(const ExtGeom& x, int s, int a, int& lo, int& hi) {
+  const int N = x.N, Na = x.Na[s];
+  lo = a == 0 ? -N : (a == 1 ? 0 : Na + 1);
+  hi = a == 0 ? -1 : (a == 1 ? Na : Na + N);
 }
 
-// Lattice blocks per axis: index a = 0, 1, 2 covers nodes [lo, hi].
-struct AxisBlocks {
-  int lo[3], hi[3];
-};
-
-__host__ __device__ inline AxisBlocks axis_blocks(int N) {
-  return {{-N, 0, N + 1}, {-1, N, 2 * N}};
+__device__ inline void block_axes(int blk, int d, int* a) {
+  for (int s = d - 1; s >= 0; --s) {
+    a[s] = blk % 3;
+    blk /= 3;
+  }
 }
 
-// Generator of block (a_0, .., a_{d-1}) on P^d: position q_s holds the offset
-// k_s = v_s - lo_s, v_s = q_s (q_s <= N - 1) or q_s - P, for the offsets of
-// the block's range with |k_s| <= N; zero elsewhere.
-__global__ void k_block_generator(const double* G, int d, int N, int P, int blk, long total,
+// Block form: generator of block blk; position q_s holds the offset
+// k_s = v_s - lo_s, v_s = q_s (q_s <= Na_s - 1) or q_s - P_s, for the offsets
+// of interior nodes and the block's nodes with |k_s| <= N; zero elsewhere.
+__global__ void k_block_generator(const double* G, ExtGeom x, int blk, long total,
                                   cx<double>* K) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
-  const AxisBlocks ab = axis_blocks(N);
-  long rem = e, gi = 0;
-  bool ok = true;
   int q[3] = {0, 0, 0}, a[3] = {0, 0, 0};
-  for (int s = d - 1; s >= 0; --s) {
-    q[s] = (int)(rem % P);
-    rem /= P;
-  }
-  for (int s = d - 1, b = blk; s >= 0; --s) {
-    a[s] = b % 3;
-    b /= 3;
-  }
-  for (int s = 0; s < d; ++s) {
-    const int lo = ab.lo[a[s]], hi = ab.hi[a[s]];
-    const int v = q[s] <= N - 1 ? q[s] : q[s] - P;
+  split_index(e, x, q);
+  block_axes(blk, x.d, a);
+  const int N = x.N;
+  long gi = 0;
+  bool ok = true;
+  for (int s = 0; s < x.d; ++s) {
+    int lo, hi;
+    block_range(x, s, a[s], lo, hi);
+    const int v = q[s] <= x.Na[s] - 1 ? q[s] : q[s] - x.P[s];
     const int k = v - lo;
-    // offsets of interior i in [1, N-1] and j in [lo, hi]
-    if (k < 1 - hi || k > N - 1 - lo || k < -N || k > N) ok = false;
+    if (k < 1 - hi || k > x.Na[s] - 1 - lo || k < -N || k > N) ok = false;
     gi = gi * (N + 1) + (ok ? (k < 0 ? -k : k) : 0);
   }
   K[e] = {ok ? G[gi] : 0.0, 0.0};
 }
 
-// Exterior data of block blk on P^d: position q_s holds node lo_s + q_s for
-// q_s <= hi_s - lo_s; interior nodes are zero.
-__global__ void k_place_block(const double* g, int d, int N, int P, int blk, long total,
-                              cx<double>* D) {
+// Block form: exterior data of block blk, position q_s holding node lo_s + q_s
+// for q_s <= hi_s - lo_s; interior nodes are zero.
+__global__ void k_place_block(const double* g, ExtGeom x, int blk, long total, cx<double>* D) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
-  const AxisBlocks ab = axis_blocks(N);
-  const int L = 3 * N + 1;
-  long rem = e, gi = 0;
-  bool in = true, interior = true;
   int q[3] = {0, 0, 0}, a[3] = {0, 0, 0};
-  for (int s = d - 1; s >= 0; --s) {
-    q[s] = (int)(rem % P);
-    rem /= P;
-  }
-  for (int s = d - 1, b = blk; s >= 0; --s) {
-    a[s] = b % 3;
-    b /= 3;
-  }
-  for (int s = 0; s < d; ++s) {
-    const int lo = ab.lo[a[s]], hi = ab.hi[a[s]];
+  split_index(e, x, q);
+  block_axes(blk, x.d, a);
+  long gi = 0;
+  bool in = true, interior = true;
+  for (int s = 0; s < x.d; ++s) {
+    int lo, hi;
+    block_range(x, s, a[s], lo, hi);
     const int j = lo + q[s];
     if (j > hi) in = false;
-    if (j < 1 || j > N - 1) interior = false;
-    gi = gi * L + (j <= hi ? j + N : 0);
+    if (j < 1 || j > x.Na[s] - 1) interior = false;
+    gi = gi * x.L[s] + (j <= hi ? j + x.N : 0);
   }
   D[e] = {(in && !interior) ? g[gi] : 0.0, 0.0};
+}
+
+__global__ void k_mul_spectra(cx<double>* D, const cx<double>* K, long total) {
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < total) D[e] = cmul(D[e], K[e]);
 }
 
 // acc (+)= D * K
@@ -150,30 +154,30 @@ __global__ void k_mac_spectra(cx<double>* acc, const cx<double>* D, const cx<dou
   acc[e] = first ? t : cx<double>{acc[e].x + t.x, acc[e].y + t.y};
 }
 
-// b_i = Re D[i + shift] / P^d - c tail_i over the interior i in [1, N-1]^d.
-__global__ void k_take_interior(const cx<double>* D, int d, int N, int P, int shift, long nd,
+// b_i = Re D[i + shift] / prod P - c tail_i over the interior nodes.
+__global__ void k_take_interior(const cx<double>* D, ExtGeom x, int shift, long nd,
                                 double scale, const double* tail, double c, double* b) {
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nd) return;
-  const int n = N - 1;
   long rem = e, pi = 0;
   int i[3] = {0, 0, 0};
-  for (int s = d - 1; s >= 0; --s) {
+  for (int s = x.d - 1; s >= 0; --s) {
+    const int n = x.Na[s] - 1;
     i[s] = (int)(rem % n) + 1;
     rem /= n;
   }
-  for (int s = 0; s < d; ++s) pi = pi * P + (i[s] + shift);
+  for (int s = 0; s < x.d; ++s) pi = pi * x.P[s] + (i[s] + shift);
   b[e] = D[pi].x * scale - (tail ? c * tail[e] : 0.0);
 }
 
-// 1D: b_i = sum_{j in [i-N, 0] u [N, i+N]} G_{|j-i|} g_j - c tail_i.
-__global__ void k_exterior_1d(const double* G, const double* g, int N, const double* tail,
-                              double c, double* b) {
+// 1D: b_i = sum_{j in [i-N, 0] u [Na, i+N]} G_{|j-i|} g_j - c tail_i.
+__global__ void k_exterior_1d(const double* G, const double* g, int N, int Na,
+                              const double* tail, double c, double* b) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x + 1;
-  if (i > N - 1) return;
+  if (i > Na - 1) return;
   double s = 0.0;
   for (int j = i - N; j <= 0; ++j) s += G[i - j] * g[j + N];
-  for (int j = N; j <= i + N; ++j) s += G[j - i] * g[j + N];
+  for (int j = Na; j <= i + N; ++j) s += G[j - i] * g[j + N];
   b[i - 1] = s - (tail ? c * tail[i - 1] : 0.0);
 }
 
@@ -184,6 +188,38 @@ __global__ void k_difference(const double* a, const double* b, double* out, long
 
 inline unsigned blocks(long n, int thr) { return (unsigned)((n + thr - 1) / thr); }
 
+inline int pow2_at_least(long v) {
+  int p = 8;
+  while (p < v) p *= 2;
+  return p;
+}
+
+// Transform lengths of the direct form, or of the block form when a direct
+// axis would need more than 2048 points (2D only).
+ExtGeom ext_geom(const Geometry& g, bool* blocked) {
+  ExtGeom x{};
+  x.d = g.d;
+  x.N = g.N;
+  bool blk = false;
+  for (int s = 0; s < 3; ++s) {
+    x.Na[s] = s < g.d ? g.Na[s] : 2;
+    x.L[s] = s < g.d ? g.Na[s] + 2 * g.N + 1 : 1;
+    x.P[s] = s < g.d ? pow2_at_least(x.L[s]) : 1;
+    if (s < g.d && x.P[s] > 2048) blk = true;
+  }
+  if (blk)
+    for (int s = 0; s < g.d; ++s)
+      x.P[s] = pow2_at_least(std::max(2L * g.Na[s], (long)g.Na[s] + g.N));
+  if (blocked) *blocked = blk;
+  return x;
+}
+
+long ext_points(const ExtGeom& x) {
+  long t = 1;
+  for (int s = 0; s < x.d; ++s) t *= x.P[s];
+  return t;
+}
+
 }  // namespace
 
 void difference(const double* a, const double* b, double* out, long n, hipStream_t st) {
@@ -191,34 +227,28 @@ void difference(const double* a, const double* b, double* out, long n, hipStream
   check_launch("difference");
 }
 
-// 2D beyond 4N = 2048 points: the block form on M points per axis.
-static bool blocked(const Geometry& g) { return g.d == 2 && 2 * g.Ma[0] > 2048; }
-
 bool exterior_supported(const Geometry& g) {
-  // the cube only (the exterior lattice of a box is not built); the
-  // transforms take at most 2048 points per axis, and in 3D P <= 1024 keeps
-  // the two P^3 complex buffers at 17 GB each
-  if (!g.cube()) return false;
-  const int P = 2 * g.Ma[0];
-  return g.d == 1 || g.d == 2 || (g.d == 3 && P <= 1024);
-}
-
-static long exterior_points(const Geometry& g) {
-  const long P = blocked(g) ? g.Ma[0] : 2L * g.Ma[0];
-  long total = 1;
-  for (int s = 0; s < g.d; ++s) total *= P;
-  return total;
+  if (g.d == 1) return true;
+  bool blk = false;
+  const ExtGeom x = ext_geom(g, &blk);
+  // the block form is built for 2D; in 3D the direct form with at most
+  // 1024^3 points keeps the two transform buffers at 17 GB each
+  if (g.d == 3) return !blk && ext_points(x) <= 1024L * 1024 * 1024;
+  return true;
 }
 
 size_t exterior_khat_bytes(const Geometry& g) {
   if (g.d == 1) return 0;
-  const int nblk = blocked(g) ? 9 : 1;
-  return (size_t)nblk * exterior_points(g) * sizeof(cx<double>);
+  bool blk = false;
+  const ExtGeom x = ext_geom(g, &blk);
+  return (size_t)(blk ? 9 : 1) * ext_points(x) * sizeof(cx<double>);
 }
 
 size_t exterior_work_bytes(const Geometry& g) {
   if (g.d == 1) return 0;
-  return (size_t)(blocked(g) ? 2 : 1) * exterior_points(g) * sizeof(cx<double>);
+  bool blk = false;
+  const ExtGeom x = ext_geom(g, &blk);
+  return (size_t)(blk ? 2 : 1) * ext_points(x) * sizeof(cx<double>);
 }
 
 void exterior_term(const Geometry& g, const double* G, double c, const double* g_lat,
@@ -226,71 +256,71 @@ void exterior_term(const Geometry& g, const double* G, double c, const double* g
                    void* work, hipStream_t st) {
   const int N = g.N, d = g.d, thr = 256;
   const long nd = g.nd;
-  const long L = 3L * N + 1;
   if (d == 1) {
+    const int Na = g.Na[0];
+    const long L = Na + 2L * N + 1;
     for (int o = 0; o < nrhs; ++o) {
-      hipLaunchKernelGGL(k_exterior_1d, dim3(blocks(N - 1, thr)), dim3(thr), 0, st, G,
-                         g_lat + (long)o * L, N, tail ? tail + (long)o * nd : nullptr, c,
+      hipLaunchKernelGGL(k_exterior_1d, dim3(blocks(Na - 1, thr)), dim3(thr), 0, st, G,
+                         g_lat + (long)o * L, N, Na, tail ? tail + (long)o * nd : nullptr, c,
                          b + (long)o * nd);
       check_launch("exterior 1D");
     }
     return;
   }
-  const bool blk = blocked(g);
-  const int P = blk ? g.Ma[0] : 2 * g.Ma[0];
-  const int Pd[3] = {P, P, P};
-  long total = 1, Ld = 1;
-  for (int s = 0; s < d; ++s) {
-    total *= P;
-    Ld *= L;
-  }
+  bool blk = false;
+  const ExtGeom x = ext_geom(g, &blk);
+  const int Pd[3] = {x.P[0], x.P[1], x.P[2]};
+  const long total = ext_points(x);
+  long Ld = 1;
+  for (int s = 0; s < d; ++s) Ld *= x.L[s];
   cx<double>* K = reinterpret_cast<cx<double>*>(khat);
   cx<double>* D = reinterpret_cast<cx<double>*>(work);
   const double scale = 1.0 / (double)total;
   if (blk) {
-    const int nb = 9;
+    int nb = 1;
+    for (int s = 0; s < d; ++s) nb *= 3;
     if (!khat_ready) {
-      for (int b = 0; b < nb; ++b) {
-        hipLaunchKernelGGL(k_block_generator, dim3(blocks(total, thr)), dim3(thr), 0, st, G, d,
-                           N, P, b, total, K + (long)b * total);
+      for (int bi = 0; bi < nb; ++bi) {
+        hipLaunchKernelGGL(k_block_generator, dim3(blocks(total, thr)), dim3(thr), 0, st, G, x,
+                           bi, total, K + (long)bi * total);
         check_launch("block generator");
-        fft_full(Pd, d, K + (long)b * total, -1, st);
+        fft_full(Pd, d, K + (long)bi * total, -1, st);
       }
     }
     cx<double>* acc = D + total;
     for (int o = 0; o < nrhs; ++o) {
-      for (int b = 0; b < nb; ++b) {
+      for (int bi = 0; bi < nb; ++bi) {
         hipLaunchKernelGGL(k_place_block, dim3(blocks(total, thr)), dim3(thr), 0, st,
-                           g_lat + (long)o * Ld, d, N, P, b, total, D);
+                           g_lat + (long)o * Ld, x, bi, total, D);
         check_launch("place block");
         fft_full(Pd, d, D, -1, st);
         hipLaunchKernelGGL(k_mac_spectra, dim3(blocks(total, thr)), dim3(thr), 0, st, acc, D,
-                           K + (long)b * total, total, b == 0 ? 1 : 0);
+                           K + (long)bi * total, total, bi == 0 ? 1 : 0);
         check_launch("block spectra");
       }
       fft_full(Pd, d, acc, 1, st);
-      hipLaunchKernelGGL(k_take_interior, dim3(blocks(nd, thr)), dim3(thr), 0, st, acc, d, N, P,
-                         0, nd, scale, tail ? tail + (long)o * nd : nullptr, c, b + (long)o * nd);
+      hipLaunchKernelGGL(k_take_interior, dim3(blocks(nd, thr)), dim3(thr), 0, st, acc, x, 0, nd,
+                         scale, tail ? tail + (long)o * nd : nullptr, c, b + (long)o * nd);
       check_launch("interior restriction");
     }
     return;
   }
   if (!khat_ready) {
-    hipLaunchKernelGGL(k_wrap_generator, dim3(blocks(total, thr)), dim3(thr), 0, st, G, d, N, P,
-                       total, K);
+    hipLaunchKernelGGL(k_wrap_generator, dim3(blocks(total, thr)), dim3(thr), 0, st, G, x, total,
+                       K);
     check_launch("wrap generator");
     fft_full(Pd, d, K, -1, st);
   }
   for (int o = 0; o < nrhs; ++o) {
     hipLaunchKernelGGL(k_place_exterior, dim3(blocks(total, thr)), dim3(thr), 0, st,
-                       g_lat + (long)o * Ld, d, N, P, total, D);
+                       g_lat + (long)o * Ld, x, total, D);
     check_launch("place exterior data");
     fft_full(Pd, d, D, -1, st);
     hipLaunchKernelGGL(k_mul_spectra, dim3(blocks(total, thr)), dim3(thr), 0, st, D, K, total);
     check_launch("spectra product");
     fft_full(Pd, d, D, 1, st);
-    hipLaunchKernelGGL(k_take_interior, dim3(blocks(nd, thr)), dim3(thr), 0, st, D, d, N, P, N,
-                       nd, scale, tail ? tail + (long)o * nd : nullptr, c, b + (long)o * nd);
+    hipLaunchKernelGGL(k_take_interior, dim3(blocks(nd, thr)), dim3(thr), 0, st, D, x, N, nd,
+                       scale, tail ? tail + (long)o * nd : nullptr, c, b + (long)o * nd);
     check_launch("interior restriction");
   }
 }

@@ -198,8 +198,8 @@ void embed_generator(const Geometry& g, const double* G, double* out, hipStream_
 // Exterior-data term (exterior unit): b = lattice sum of G with g on
 // [-N, 2N]^d minus c * tail (tail may be null).  khat: the transformed
 // wrapped generator(s) (exterior_khat_bytes), filled when !khat_ready; work:
-// exterior_work_bytes.  Supported on the cube for d = 1, 2 and for d = 3
-// with 2M <= 1024.
+// exterior_work_bytes.  Supported for d = 1, 2 and for d = 3 up to 1024^3
+// transform points (cubes and boxes).
 bool exterior_supported(const Geometry& g);
 void difference(const double* a, const double* b, double* out, long n, hipStream_t st);
 size_t exterior_khat_bytes(const Geometry& g);

@@ -122,7 +122,7 @@ def test_box_solve_matches_cholesky(alpha, p, box, mixed):
         assert np.abs(u[r] - uc).max() <= 1e-8 * np.abs(uc).max()
 
 
-def test_box_validation_and_exterior():
+def test_box_validation_and_exterior_shape():
     import paper_2103_03658_amd as fl
     with pytest.raises(fl.FlError):
         make_box(1.0, 1, (16, 1))          # an axis needs >= 2 intervals
@@ -131,7 +131,9 @@ def test_box_validation_and_exterior():
     with pytest.raises(fl.FlError):
         make_box(1.0, 1, (2048, 8))        # N above 1024
     op = make_box(1.0, 1, (16, 8))
-    with pytest.raises(fl.FlError):
+    # the exterior lattice of a box spans [-N, N_s + N] along axis s
+    with pytest.raises(ValueError):
         op.exterior(torch.zeros((1, 49, 49), dtype=torch.float64).cuda())
+    assert op.exterior(torch.zeros((2, 49, 41), dtype=torch.float64).cuda()).shape == (2, 15, 7)
     with pytest.raises(fl.FlError):
         make_box(1.0, 1, (24, 10)).set_preconditioner(2)

@@ -3,7 +3,8 @@ exterior term).
 
 The lattice part of the term (the sum of G_{|j-i|} g(x_j) over exterior
 nodes) is computed by the library and compared with the oracle's direct sum
-(1D, 2D and 3D; sampled nodes for the 2D block form at N = 600 and 1024), and
+(1D, 2D and 3D, cubes and boxes; sampled nodes at 2D N = 600, 700 and 1024
+and on a 1024 x 300 box, where the lattice is cut into blocks), and
 at the largest supported sizes (2D N = 512 and 1024, 3D N = 128) through the
 identity b + A 1 = c_{d,alpha} 2^d T_d for g = 1.
 The far-field integrals need g beyond the node lattice, which the library
@@ -131,10 +132,11 @@ def test_exterior_lattice_3d(alpha, p, N):
     assert (np.abs(b[1] + 0.5 * ref) <= 1e-11 * scale).all()
 
 
-@pytest.mark.parametrize("N", [600, 1024])
-def test_exterior_block_form_sampled(N):
-    """2D with 4N > 2048 points (the lattice cut into 3 x 3 blocks): sampled
-    interior nodes against the oracle's direct sum."""
+@pytest.mark.parametrize("N", [600, 700, 1024])
+def test_exterior_large_2d_sampled(N):
+    """2D at the longest transforms: N = 600 embeds its 3N + 1 lattice points
+    in 2048, N = 700 and 1024 need more and cut the lattice into 3 x 3
+    blocks.  Sampled interior nodes against the oracle's direct sum."""
     print(f"[exterior 2d block form] N={N}", flush=True)
     alpha = 1.3
     op = make_op(2, alpha, 1, N)
@@ -187,11 +189,68 @@ def test_exterior_solve_3d():
     assert np.abs(u[0].cpu().numpy() - uc).max() <= 1e-9 * np.abs(uc).max()
 
 
-def test_exterior_rejects_box():
+def make_box(alpha, p, box):
     import paper_2103_03658_amd as fl
-    op = fl.Operator(2, 1.0, 1, box=(8, 6))
-    with pytest.raises(fl.FlError):
-        op.exterior(torch.zeros((1, 25, 25), dtype=torch.float64).cuda())
+    return fl.Operator(len(box), alpha, p, box=box)
+
+
+def box_lattice(N, box, g):
+    h = 2.0 / N
+    axes = [-1.0 + h * np.arange(-N, v + N + 1) for v in box]
+    if len(box) == 2:
+        return g(axes[0][:, None], axes[1][None, :])
+    return g(axes[0][:, None, None], axes[1][None, :, None], axes[2][None, None, :])
+
+
+def g2s(a, c):
+    return np.exp(-(a * a + c * c)) + 0.25 * a
+
+
+def g3s(a, c, e):
+    return np.exp(-(a * a + c * c + e * e)) - 0.2 * e
+
+
+@pytest.mark.parametrize("alpha,p,box", [(1.2, 1, (16, 10)), (0.7, 2, (12, 6)), (1.5, 1, (9, 16)),
+                                         (1.0, 0, (5, 24)), (1.3, 1, (8, 5, 6)),
+                                         (0.9, 1, (4, 7, 3))])
+def test_exterior_box_parity(alpha, p, box):
+    print(f"[exterior box] box={box} p={p}", flush=True)
+    op = make_box(alpha, p, box)
+    N = op.N
+    gfun = g2s if len(box) == 2 else g3s
+    gl = box_lattice(N, box, gfun)
+    b = op.exterior(torch.from_numpy(gl[None].copy()).cuda()).cpu().numpy()[0]
+    G = orc_gen(len(box), alpha, p, N)
+    lat = oracle.exterior_lattice_2d if len(box) == 2 else oracle.exterior_lattice_3d
+    ref = lat(G, gfun, box)
+    scale = lat(np.abs(G), lambda *x: np.abs(gfun(*x)), box)
+    assert b.shape == ref.shape
+    assert (np.abs(b - ref) <= 1e-11 * scale).all(), float((np.abs(b - ref) / scale).max())
+
+
+def test_exterior_box_block_form_sampled():
+    """A 2D box whose lattice needs more than 2048 points along axis 0."""
+    box, alpha = (1024, 300), 1.1
+    op = make_box(alpha, 1, box)
+    gl = box_lattice(1024, box, g2s)
+    b = op.exterior(torch.from_numpy(gl[None].copy()).cuda()).cpu().numpy()[0]
+    G = orc_gen(2, alpha, 1, 1024)
+    nodes = [(1, 1), (1023, 299), (512, 1), (1, 299), (700, 150), (3, 17)]
+    ref = oracle.exterior_lattice_2d_at(G, g2s, nodes, box)
+    scale = oracle.exterior_lattice_2d_at(np.abs(G), lambda a, c: np.abs(g2s(a, c)), nodes, box)
+    got = np.array([b[i - 1, j - 1] for i, j in nodes])
+    assert (np.abs(got - ref) <= 1e-11 * scale).all(), float((np.abs(got - ref) / scale).max())
+
+
+def test_exterior_box_solve():
+    box, alpha = (16, 10), 1.4
+    op = make_box(alpha, 1, box)
+    b = op.exterior(torch.from_numpy(box_lattice(16, box, g2s)[None].copy()).cuda())
+    f = torch.from_numpy(np.random.default_rng(9).uniform(-1, 1, (1,) + op.shape)).cuda()
+    u, info = op.solve(f, tol=1e-12, b=b)
+    G = orc_gen(2, alpha, 1, 16)
+    uc = oracle.solve_cholesky(G, f[0].cpu().numpy() - oracle.exterior_lattice_2d(G, g2s, box))
+    assert np.abs(u[0].cpu().numpy() - uc).max() <= 1e-9 * np.abs(uc).max()
 
 
 @pytest.mark.parametrize("row", [r for r in load("table_3_1_3") if int(r[1]) <= 1],
