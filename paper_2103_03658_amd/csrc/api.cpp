@@ -1017,6 +1017,32 @@ void fp64_residual(fl_op A, const double* f, const double* u, double* r, int nrh
                    active, st);
 }
 
+// Per-RHS results of a finished solve: packed on the device and copied to
+// the pinned poll record in one transfer, then unpacked (synchronizes st).
+void read_results(fl_op A, int nrhs, const int* iters, const int* status, const int* nupd,
+                  const double* res2, const double* rro, const double* f2, hipStream_t st,
+                  std::vector<int>& h_iters, std::vector<int>& h_status, std::vector<int>& h_nupd,
+                  std::vector<double>& h_res2, std::vector<double>& h_rro,
+                  std::vector<double>& h_f2) {
+  double* dev = nullptr;
+  size_t pb = 0;
+  const double* h = poll_buffers(A, nrhs, &dev, &pb);
+  static_assert(fl::RESULT_STRIDE <= fl::POLL_STRIDE, "the result record fits the poll record");
+  fl::pack_results(nrhs, iters, status, nupd, res2, rro, f2, dev, st);
+  FL_HIP(hipMemcpyAsync(A->poll_host, dev, (size_t)fl::RESULT_STRIDE * nrhs * sizeof(double),
+                        hipMemcpyDeviceToHost, st));
+  FL_HIP(hipStreamSynchronize(st));
+  for (int o = 0; o < nrhs; ++o) {
+    const double* q = h + fl::RESULT_STRIDE * (size_t)o;
+    h_iters[o] = (int)q[0];
+    h_status[o] = (int)q[1];
+    h_nupd[o] = (int)q[2];
+    h_res2[o] = q[3];
+    h_rro[o] = q[4];
+    h_f2[o] = q[5];
+  }
+}
+
 void sum_squares(fl_op A, const double* v, int nrhs, const fl::CgScalars& co, double* out,
                  hipStream_t st) {
   fl::sum_squares_parts(v, A->g.nd, nrhs, co.part_b, co.max_blocks, st);
@@ -1116,15 +1142,12 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
                              ws, st);
       });
       FL_HIP(hipMemcpyAsync(u, x, v8, hipMemcpyDeviceToDevice, st));
-      std::vector<double> rr(nrhs);
-      FL_HIP(hipMemcpyAsync(iters.data(), cg.iters, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
-      FL_HIP(hipMemcpyAsync(status.data(), cg.status, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
-      FL_HIP(hipMemcpyAsync(rr.data(), cg.res2, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
-      // true residual with an FP64 product (into q)
+      // true residual with an FP64 product (into q); the results travel in
+      // one pinned record (copies into pageable memory would each wait)
       fp64_residual(A, f, u, q, nrhs, co, nullptr, rro, ws, st);
-      FL_HIP(hipMemcpyAsync(hrr.data(), rro, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
-      FL_HIP(hipMemcpyAsync(hf2.data(), f2, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
-      FL_HIP(hipStreamSynchronize(st));
+      std::vector<double> rr(nrhs);
+      read_results(A, nrhs, cg.iters, cg.status, nullptr, cg.res2, rro, f2, st, iters, status,
+                   outer, rr, hrr, hf2);
       for (int o = 0; o < nrhs; ++o) {
         const double fn = std::sqrt(hf2[o]);
         rec[o] = fn > 0 ? std::sqrt(rr[o]) / fn : 0.0;
@@ -1196,12 +1219,9 @@ extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double 
       fl::reliable_accum(A->g, xhi, xlo, nrhs, cg, trig, true, st);
       FL_HIP(hipMemcpyAsync(u, xhi, v8, hipMemcpyDeviceToDevice, st));
       fp64_residual(A, f, u, r64, nrhs, co, nullptr, rro, ws, st);
-      FL_HIP(hipMemcpyAsync(iters.data(), cg.iters, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
-      FL_HIP(hipMemcpyAsync(status.data(), cg.status, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
-      FL_HIP(hipMemcpyAsync(outer.data(), nupd, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
-      FL_HIP(hipMemcpyAsync(hrr.data(), rro, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
-      FL_HIP(hipMemcpyAsync(hf2.data(), f2, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
-      FL_HIP(hipStreamSynchronize(st));
+      std::vector<double> rr(nrhs);
+      read_results(A, nrhs, cg.iters, cg.status, nupd, nullptr, rro, f2, st, iters, status, outer,
+                   rr, hrr, hf2);
       for (int o = 0; o < nrhs; ++o) {
         const double rel = hf2[o] > 0 ? std::sqrt(hrr[o] / hf2[o]) : 0.0;
         rec[o] = rel;

@@ -124,6 +124,23 @@ __global__ void __launch_bounds__(64) k_pack_poll(CgScalars cg, int nrhs, const 
   }
 }
 
+// Per-RHS results of a finished solve in one record of RESULT_STRIDE doubles:
+// iterations, status, reliable updates (0 if nupd is null), r.r of the
+// recursion (0 if res2 is null), r.r of the FP64 residual, ||f||^2.
+__global__ void k_pack_results(int nrhs, const int* iters, const int* status, const int* nupd,
+                               const double* res2, const double* rro, const double* f2,
+                               double* out) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= nrhs) return;
+  double* q = out + RESULT_STRIDE * (long)o;
+  q[0] = (double)iters[o];
+  q[1] = (double)status[o];
+  q[2] = nupd ? (double)nupd[o] : 0.0;
+  q[3] = res2 ? res2[o] : 0.0;
+  q[4] = rro[o];
+  q[5] = f2[o];
+}
+
 __global__ void k_fill_zero(unsigned* p, size_t nwords) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < nwords) p[i] = 0u;
@@ -317,6 +334,14 @@ void pack_poll(const CgScalars& cg, int nrhs, const double* rr_last, const doubl
   hipLaunchKernelGGL(k_pack_poll, dim3(nrhs), dim3(64), 0, st, cg, nrhs, rr_last, f2, nupd,
                      out);
   check_launch("poll pack");
+}
+
+void pack_results(int nrhs, const int* iters, const int* status, const int* nupd,
+                  const double* res2, const double* rro, const double* f2, double* out,
+                  hipStream_t st) {
+  hipLaunchKernelGGL(k_pack_results, dim3((nrhs + 63) / 64), dim3(64), 0, st, nrhs, iters, status,
+                     nupd, res2, rro, f2, out);
+  check_launch("result pack");
 }
 
 void fill_zero_bytes(void* p, size_t bytes, hipStream_t st) {

@@ -229,6 +229,13 @@ void fill_int(int* p, int v, int n, hipStream_t st);
 constexpr int POLL_STRIDE = 8;   // doubles per RHS in the poll record
 void pack_poll(const CgScalars& cg, int nrhs, const double* rr_last, const double* f2,
                const int* nupd, double* out, hipStream_t st);
+// Results of a finished solve for the host, RESULT_STRIDE doubles per RHS:
+// iterations, status, reliable updates, recursive r.r, FP64 residual r.r,
+// ||f||^2 (nupd and res2 may be null: 0).
+constexpr int RESULT_STRIDE = 6;
+void pack_results(int nrhs, const int* iters, const int* status, const int* nupd,
+                  const double* res2, const double* rro, const double* f2, double* out,
+                  hipStream_t st);
 void fill_zero_bytes(void* p, size_t bytes, hipStream_t st);
 // out[o] = sum_{b < nb} part[o * max_blocks + b] (fixed order)
 void reduce_parts(const double* part, int nb, int max_blocks, int nrhs, double* out,
