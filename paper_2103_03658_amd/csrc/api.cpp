@@ -977,8 +977,16 @@ template <typename T>
 void cg_iteration(fl_op A, const fl::Schedule& sc, const T* lam, const T* linv, const fl::Twiddles& tw,
                   T* x, T* r, T* p, T* q, T* z, int nrhs, const fl::CgScalars& cg, void* ws,
                   hipStream_t st) {
-  fl::apply_passes<T>(A->g, sc, lam, tw, nullptr, q, nrhs, ws, st, fl::PM_CG,
-                      cg.precond ? z : r, p, nullptr, &cg, cg.active);
+  if (A->g.d >= 2) {
+    // iteration start and p = z + beta p streamed; the strided first pass
+    // then reads p alone
+    fl::cg_direction<T>(A->g, p, cg.precond ? z : r, nrhs, cg, st);
+    fl::apply_passes<T>(A->g, sc, lam, tw, p, q, nrhs, ws, st, fl::PM_PQ, nullptr, nullptr,
+                        nullptr, &cg, cg.active);
+  } else {
+    fl::apply_passes<T>(A->g, sc, lam, tw, nullptr, q, nrhs, ws, st, fl::PM_CG,
+                        cg.precond ? z : r, p, nullptr, &cg, cg.active);
+  }
   fl::cg_update<T>(A->g, x, r, p, q, nrhs, cg, st);
   if (cg.precond) precond_apply<T>(A, linv, tw, r, z, nrhs, ws, cg, cg.active, st);
 }

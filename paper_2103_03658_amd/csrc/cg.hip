@@ -92,6 +92,23 @@ __global__ void __launch_bounds__(VT) k_cg_update(T* x, T* r, const T* p, const 
   }
 }
 
+// Start of a CG iteration for d >= 2 as a streaming pass: the stopping test
+// and beta (cg_begin), then p = zr + beta p (zr = z preconditioned, else r).
+// A right-hand side that stops returns in every block: the lead block's
+// deactivation can only turn later blocks of it away, which is what they do.
+template <typename T>
+__global__ void __launch_bounds__(VT) k_cg_direction(T* p, const T* zr, long nd, CgScalars cg) {
+  __shared__ double red[16];
+  const int o = blockIdx.y;
+  if (!cg.active[o]) return;
+  double beta;
+  if (cg_begin(cg, o, blockIdx.x == 0, red, &beta)) return;
+  const T b = (T)beta;
+  const long base = (long)o * nd;
+  for (long i = (long)blockIdx.x * VT + threadIdx.x; i < nd; i += (long)gridDim.x * VT)
+    p[base + i] = zr[base + i] + b * p[base + i];
+}
+
 __global__ void k_fill_int(int* p, int v, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -315,6 +332,18 @@ void cg_update(const Geometry& g, T* x, T* r, const T* p, const T* q, int nrhs,
   check_launch("cg update");
 }
 
+template <typename T>
+void cg_direction(const Geometry& g, T* p, const T* zr, int nrhs, const CgScalars& cg,
+                  hipStream_t st) {
+  dim3 grid(cg.nb_c, nrhs);
+  hipLaunchKernelGGL((k_cg_direction<T>), grid, dim3(VT), 0, st, p, zr, g.nd, cg);
+  check_launch("cg direction");
+}
+
+template void cg_direction<double>(const Geometry&, double*, const double*, int,
+                                   const CgScalars&, hipStream_t);
+template void cg_direction<float>(const Geometry&, float*, const float*, int, const CgScalars&,
+                                  hipStream_t);
 template void cg_init<double>(const Geometry&, const double*, double*, double*, double*, int,
                               const CgScalars&, const int*, hipStream_t);
 template void cg_init<float>(const Geometry&, const float*, float*, float*, float*, int,

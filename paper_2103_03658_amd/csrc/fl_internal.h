@@ -73,6 +73,7 @@ enum PassMode {
   PM_CG = 1,        // first pass: beta, convergence, p = r + beta p; last pass: q = A p, p.q partials
   PM_RESID = 2,     // last pass: y = f - A u and partials of ||y||^2 (FP64 only)
   PM_DOT = 3,       // y = A u and partials of u.y into `part` (preconditioner r.z)
+  PM_PQ = 4,        // d >= 2: q = A p with p.q partials (after cg_direction)
 };
 
 // Geometry of one operator application.  The generator lives on the cube
@@ -220,6 +221,11 @@ void build_inverse_symbol(const Geometry& g, const double* lam64, long nf, doubl
 template <typename T>
 void cg_init(const Geometry& g, const T* rhs, T* x, T* r, T* p, int nrhs, const CgScalars& cg,
              const int* outer_active, hipStream_t st);
+// d >= 2: iteration start (stopping test, beta) and p = zr + beta p as a
+// streaming pass; the product then runs with PM_PQ.
+template <typename T>
+void cg_direction(const Geometry& g, T* p, const T* zr, int nrhs, const CgScalars& cg,
+                  hipStream_t st);
 template <typename T>
 void cg_update(const Geometry& g, T* x, T* r, const T* p, const T* q, int nrhs,
                const CgScalars& cg, hipStream_t st);

@@ -42,6 +42,7 @@ void apply_passes_t(const Geometry& g, const Schedule& sc, const T* lam, const T
   const CgScalars& c = cg ? *cg : nocg;
   if (mode != PM_PLAIN && !cg) throw Error(1, "missing reduction buffers");
   double* part = mode == PM_DOT ? c.part_b : c.part_a;
+  if (mode == PM_PQ && g.d == 1) throw Error(2, "PM_PQ: d >= 2 only");
   if (g.d == 1) {
     Line1Args<T> a{u, y, pvec, rvec, fvec, active, c, part, c.max_blocks, lam, n0, nrhs,
                    mode, tw0};
@@ -103,8 +104,10 @@ void apply_passes_t(const Geometry& g, const Schedule& sc, const T* lam, const T
     if (go()) launch_c2c<T>(M1, sc.E_c2c, +1, i1, (long)nrhs * h0, st);
   }
   {
-    LastArgs<T> a{T1, y, mode == PM_DOT ? u : pvec, fvec, active, part, c.max_blocks, C0,
-                  h0 * C0, nd, 0, n0, sc.W_first, 0, 0, 0, mode, tw0};
+    // PM_PQ: the CG last pass (q = A p, p.q partials) with p the input u
+    LastArgs<T> a{T1, y, (mode == PM_DOT || mode == PM_PQ) ? u : pvec, fvec, active, part,
+                  c.max_blocks, C0, h0 * C0, nd, 0, n0, sc.W_first, 0, 0, 0,
+                  mode == PM_PQ ? (int)PM_CG : mode, tw0};
     if (go()) launch_last<T>(M0, sc.E_first, a, nrhs, st);
     done();
   }
