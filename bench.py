@@ -37,14 +37,14 @@ VALU_PEAK_TFLOPS = 78.6
 # (kernel, precision, nrhs); valid only for the kernel sources they were
 # measured on (SHA-256 prefix of the transform-pass sources).
 TRAFFIC = {
-    ("axis0_fwd_r2c", "f64", 17): 109038071,
-    ("last_axis_fwd_symbol_inv", "f64", 17): 152627926,
-    ("axis0_inv_c2r", "f64", 17): 109007629,
-    ("tau_axis0_sine", "f64", 17): 72769768,
-    ("tau_last_axis_sine_mult_sine", "f64", 17): 73573119,
-    ("tau_axis0_sine_back", "f64", 17): 72769768,
+    ("axis0_fwd_r2c", "f64", 17): 109317046,
+    ("last_axis_fwd_symbol_inv", "f64", 17): 152572889,
+    ("axis0_inv_c2r", "f64", 17): 108978427,
+    ("tau_axis0_sine", "f64", 17): 72758712,
+    ("tau_last_axis_sine_mult_sine", "f64", 17): 73582995,
+    ("tau_axis0_sine_back", "f64", 17): 72758712,
 }
-TRAFFIC_SRC = "37429e61ff13821b"
+TRAFFIC_SRC = "6e9e6df7c3b97def"
 
 
 def pass_sources_hash():

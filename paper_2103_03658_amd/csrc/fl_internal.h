@@ -70,7 +70,7 @@ struct CgScalars {
 // Epilogue/prologue selection of the first and last FFT passes.
 enum PassMode {
   PM_PLAIN = 0,     // y = A u
-  PM_CG = 1,        // first pass: beta, convergence, p = r + beta p; last pass: q = A p, p.q partials
+  PM_CG = 1,        // d = 1: beta, convergence, p = r + beta p, q = A p, p.q partials
   PM_RESID = 2,     // last pass: y = f - A u and partials of ||y||^2 (FP64 only)
   PM_DOT = 3,       // y = A u and partials of u.y into `part` (preconditioner r.z)
   PM_PQ = 4,        // d >= 2: q = A p with p.q partials (after cg_direction)
@@ -160,9 +160,10 @@ int last_pass_blocks(const Geometry& g, const Schedule& sc);
 // Blocks per RHS of the vector kernels (update, init, sums).
 int vec_blocks(long nd, int nrhs);
 
-// y = A u (mode PM_PLAIN), CG step (PM_CG: p <- r + beta p from rvec/pvec,
-// q = A p into y), or FP64 residual (PM_RESID: y = f - A u).
-// PM_DOT writes its partials to cg->part_b.  ev (optional): npasses + 1
+// y = A u (mode PM_PLAIN), CG product (d = 1, PM_CG: iteration start,
+// p <- r + beta p from rvec/pvec, q = A p into y; d >= 2, PM_PQ: q = A u
+// with u = p, p.q partials into cg->part_a), or FP64 residual (PM_RESID:
+// y = f - A u).  PM_DOT writes its partials to cg->part_b.  ev (optional): npasses + 1
 // events recorded around the passes; only >= 0 launches that pass alone.
 // odd: every axis is odd-extended instead of zero-padded (positions 1..n and
 // their negated reflections), which with a real even symbol applies

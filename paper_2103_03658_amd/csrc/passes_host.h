@@ -78,10 +78,11 @@ void apply_passes_t(const Geometry& g, const Schedule& sc, const T* lam, const T
     return;
   }
   cx<T>* T1 = reinterpret_cast<cx<T>*>(ws);
-  // axis 0, forward (real pairs -> Hermitian half); CG: iteration start
+  // axis 0, forward (real pairs -> Hermitian half); the CG iteration start
+  // runs before it (cg_direction), so d >= 2 takes PM_PQ rather than PM_CG
+  if (mode == PM_CG) throw Error(2, "PM_CG: d = 1 only (d >= 2 uses PM_PQ)");
   {
-    FirstArgs<T> a{u, pvec, rvec, active, c, T1, C0, nd, h0 * C0, 0, n0,
-                   sc.W_first, 0, 0, 0, mode == PM_CG ? PM_CG : PM_PLAIN, tw0};
+    FirstArgs<T> a{u, active, T1, C0, nd, h0 * C0, 0, n0, sc.W_first, 0, 0, 0, tw0};
     if (go()) launch_first<T>(M0, sc.E_first, a, nrhs, st);
   }
   if (g.d == 2) {

@@ -137,20 +137,16 @@ __device__ __forceinline__ void xcd_tile(long ntiles, long& tile, long& outer) {
 // ---------------------------------------------------------------------------
 template <typename T>
 struct FirstArgs {
-  const T* u;            // PM_PLAIN input
-  T* p;                  // PM_CG: p <- r + beta p (in place)
-  const T* r;
+  const T* u;            // input
   const int* active;     // per RHS, may be null
-  CgScalars cg;
   cx<T>* out;
   long C;                // real columns per RHS (n^(d-1))
-  long in_os;            // elements between RHS in u/p/r
+  long in_os;            // elements between RHS in u
   long out_os;           // complex elements between RHS in out
   long ntiles;           // column-pair tiles per RHS
   int n_in;              // rows of input (n <= M/2)
   int W, lw;             // lines per block, log2(W)
   int PO, LS;            // LDS plane offset and line stride (elements)
-  int mode;
   const cx<T>* tw;
 };
 
@@ -194,18 +190,11 @@ __global__ void __launch_bounds__(512) k_first(FirstArgs<T> a) {
   using P = Plan<M, E>;
   constexpr int TPL = P::TPL;
   extern __shared__ unsigned char smem_raw[];
-  __shared__ double sh[16];
   T* lds = reinterpret_cast<T*>(smem_raw);
   long tile, ol;
   xcd_tile(a.ntiles, tile, ol);
   const int o = (int)ol;
   if (a.active && !a.active[o]) return;
-  T bt = 0;
-  if (a.mode == PM_CG) {
-    double beta;
-    if (cg_begin(a.cg, o, tile == 0, sh, &beta)) return;
-    bt = (T)beta;
-  }
   const int lw1 = a.lw + 1, W2 = 2 * a.W;
   const int nthr = a.W * TPL;
   const long col0 = tile * W2;
@@ -220,16 +209,7 @@ __global__ void __launch_bounds__(512) k_first(FirstArgs<T> a) {
     for (int j = 0; j < E; ++j) {
       const int e = threadIdx.x + j * nthr;
       const int row = e >> lw1, cc = e & (W2 - 1);
-      x[j] = 0;
-      if (row < a.n_in && cc < ncol) {
-        const long i = ib + (long)row * a.C + cc;
-        if (a.mode == PM_CG) {
-          x[j] = a.r[i] + bt * a.p[i];
-          a.p[i] = x[j];
-        } else {
-          x[j] = a.u[i];
-        }
-      }
+      x[j] = (row < a.n_in && cc < ncol) ? a.u[ib + (long)row * a.C + cc] : (T)0;
     }
 #pragma unroll
     for (int j = 0; j < E; ++j) {
