@@ -52,6 +52,10 @@ typedef enum {
 
 enum { FL_KERNEL_FRACTIONAL = 0, FL_KERNEL_TEMPERED = 1 };
 
+/* Caller-provided device allocator (fl_set_allocator). */
+typedef void *(*fl_alloc_fn)(size_t bytes, void *ctx);
+typedef void (*fl_release_fn)(void *ptr, void *ctx);
+
 /* Most exponential terms a kernel of fl_weights_expsum may have. */
 #define FL_MAX_KERNEL_TERMS 16
 
@@ -218,6 +222,33 @@ fl_status fl_solve(fl_op A, const double *f, const double *g, double tol, int ma
                    double *u, int nrhs, fl_info *info, void *stream);
 
 /*
+ * fl_solve_async -- fl_solve without blocking the calling thread, for
+ * serving loops that keep submitting while solves run.  The solve runs on a
+ * host thread of its own with the same arguments, semantics and results as
+ * fl_solve, after the work queued on `stream` so far; solves of one operator
+ * run one at a time (not necessarily in submission order), solves of
+ * different operators concurrently on their own streams.  f, g and u belong
+ * to the caller and must stay valid, f and g unchanged, until the request
+ * is finished, and the operator must not be destroyed before; `stream` does
+ * not wait for the result.
+ *   out  receives the request; every request must be finished with fl_wait
+ * Errors: argument errors as fl_solve, returned here (no request is made).
+ */
+typedef struct fl_request_s *fl_request;
+fl_status fl_solve_async(fl_op A, const double *f, const double *g, double tol, int maxiter,
+                         int mixed, double *u, int nrhs, void *stream, fl_request *out);
+
+/* fl_poll -- *done = 1 once the request's solve has finished (u and the
+ * results are then final), else 0.  Does not block. */
+fl_status fl_poll(fl_request r, int *done);
+
+/* fl_wait -- block until the request's solve has finished, copy its per-RHS
+ * results into info (nrhs entries, or NULL) and free the request.  Returns
+ * the solve's status (as fl_solve would have; fl_last_error then holds its
+ * text). */
+fl_status fl_wait(fl_request r, fl_info *info);
+
+/*
  * fl_exterior -- the exterior-data term b of the scheme with nonhomogeneous
  * data u = g outside Omega (Sec. 2.1 eq. (1D-scheme) and Sec. 2.2
  * eq. (2D-scheme), the terms of the discrete operator that involve values of
@@ -341,6 +372,24 @@ fl_status fl_apply_precond(fl_op A, const void *u, void *y, int nrhs, int fp32, 
 fl_status fl_set_graphs(fl_op A, int enable);
 
 /* Release the handle and its device memory.  NULL is accepted. */
+/*
+ * fl_set_allocator -- route the library's device allocations through the
+ * caller's allocator (a memory pool, a framework's caching allocator), for
+ * callers that manage device memory themselves.  Every buffer of an operator
+ * (generator, symbols, workspaces, CG state, exterior-data buffers) and every
+ * setup temporary allocated after this call comes from alloc(bytes, ctx) on
+ * the current device; the library returns it with release(ptr, ctx) once
+ * the device has finished with it (fl_destroy, or a workspace that grows).
+ * Blocks keep the allocator that made them: a later call changes only new
+ * allocations.  alloc must return memory aligned to 256 bytes, or NULL
+ * (FL_E_NOMEM from the call that needed it).  alloc = release = NULL
+ * restores hipMalloc / hipFree.  Twiddle tables, cached per device for the
+ * life of the process, always use hipMalloc.  Process-wide; do not call it
+ * while another thread is inside the library.
+ * FL_E_INVAL if exactly one of alloc and release is NULL.
+ */
+fl_status fl_set_allocator(fl_alloc_fn alloc, fl_release_fn release, void *ctx);
+
 void fl_destroy(fl_op A);
 
 /* Message for the last non-OK status returned on this thread ("" if none). */

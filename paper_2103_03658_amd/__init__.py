@@ -9,7 +9,32 @@ memory and streams only.
 
 import ctypes
 
-from ._lib import (FL_KERNEL_FRACTIONAL, FL_KERNEL_TEMPERED, FlError, FlInfo, check, lib)
+from ._lib import (ALLOC_FN, FL_KERNEL_FRACTIONAL, FL_KERNEL_TEMPERED, RELEASE_FN, FlError, FlInfo,
+                   check, lib)
+
+# Callbacks handed to fl_set_allocator.  Blocks keep the allocator that made
+# them until the library releases them, so no registered pair is ever freed.
+_allocator_refs = []
+
+
+def set_allocator(alloc, release):
+    """Route the library's device allocations through alloc(nbytes) -> int
+    device pointer (0 on failure) and release(ptr) (fl_set_allocator);
+    set_allocator(None, None) restores hipMalloc / hipFree."""
+    if alloc is None and release is None:
+        check(lib().fl_set_allocator(ALLOC_FN(), RELEASE_FN(), None))
+        return
+    a = ALLOC_FN(lambda nbytes, ctx: alloc(nbytes) or None)
+    r = RELEASE_FN(lambda ptr, ctx: release(ptr))
+    _allocator_refs.append((a, r))
+    check(lib().fl_set_allocator(a, r, None))
+
+
+def use_torch_allocator():
+    """Take operator memory from torch's caching allocator (current device)."""
+    import torch
+    set_allocator(lambda n: torch.cuda.caching_allocator_alloc(n),
+                  torch.cuda.caching_allocator_delete)
 
 __all__ = ["Operator", "FlError", "FlInfo", "lib"]
 
@@ -23,6 +48,30 @@ def _stream_ptr(stream):
             return ctypes.c_void_p(None)
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+class SolveRequest:
+    """A submitted solve (Operator.solve_async): done() polls, wait() blocks
+    and returns (u, per-RHS info dicts) like Operator.solve."""
+
+    def __init__(self, op, handle, nrhs, tensors):
+        self._op, self._h, self._nrhs, self._tensors = op, handle, nrhs, tensors
+
+    def done(self):
+        flag = ctypes.c_int()
+        check(self._op._lib.fl_poll(self._h, ctypes.byref(flag)))
+        return bool(flag.value)
+
+    def wait(self, raise_on_fail=True):
+        if self._h is None:
+            raise RuntimeError("request already waited for")
+        info = (FlInfo * self._nrhs)()
+        st = self._op._lib.fl_wait(self._h, info)
+        self._h = None
+        infos = [i.as_dict() for i in info]
+        if raise_on_fail:
+            check(st)
+        return self._tensors[2], infos
 
 
 class Operator:
@@ -192,6 +241,28 @@ class Operator:
         if raise_on_fail:
             check(st)
         return out, infos
+
+    def solve_async(self, f, tol=1e-10, maxiter=20000, mixed=False, out=None, stream=None,
+                    b=None):
+        """Submit the solve of solve() without waiting (fl_solve_async).  f, b
+        and out must stay alive and f, b unchanged until the returned
+        request's wait()."""
+        import torch
+        if f.dtype != torch.float64:
+            raise TypeError("f must be float64")
+        nrhs = self._nrhs(f)
+        if b is not None and (b.dtype != torch.float64 or b.shape != f.shape
+                              or not b.is_contiguous()):
+            raise ValueError("b must be a contiguous float64 tensor shaped like f")
+        if out is None:
+            out = torch.empty_like(f)
+        req = ctypes.c_void_p()
+        check(self._lib.fl_solve_async(self._h, ctypes.c_void_p(f.data_ptr()),
+                                       ctypes.c_void_p(b.data_ptr()) if b is not None else None,
+                                       float(tol), int(maxiter), int(mixed),
+                                       ctypes.c_void_p(out.data_ptr()), nrhs,
+                                       _stream_ptr(stream), ctypes.byref(req)))
+        return SolveRequest(self, req, nrhs, (f, b, out))
 
     def profile_apply(self, u, out=None, reps=20, stream=None):
         """Mean milliseconds per kernel of y = A u (HIP events between the

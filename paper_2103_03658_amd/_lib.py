@@ -41,6 +41,10 @@ class FlError(RuntimeError):
         self.status = status
 
 
+# fl_alloc_fn / fl_release_fn
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
 # name -> (restype, argtypes); mirrors include/fl.h
 _P = ctypes.c_void_p
 _SIGS = {
@@ -63,6 +67,11 @@ _SIGS = {
                                          ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_double), ctypes.c_double, _P,
                                          ctypes.POINTER(_P)]),
+    "fl_set_allocator": (ctypes.c_int, [ALLOC_FN, RELEASE_FN, _P]),
+    "fl_solve_async": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_int, ctypes.c_int, _P,
+                                      ctypes.c_int, _P, ctypes.POINTER(_P)]),
+    "fl_poll": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int)]),
+    "fl_wait": (ctypes.c_int, [_P, ctypes.POINTER(FlInfo)]),
     "fl_apply": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, _P]),
     "fl_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_int, ctypes.c_int, _P,
                                 ctypes.c_int, ctypes.POINTER(FlInfo), _P]),

@@ -5,13 +5,84 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "fl_internal.h"
+
+#include <unordered_map>
+
+namespace fl {
+namespace {
+
+struct Allocator {
+  fl_alloc_fn alloc = nullptr;
+  fl_release_fn release = nullptr;
+  void* ctx = nullptr;
+};
+
+std::mutex g_alloc_mu;
+Allocator g_alloc;                               // current (null: hipMalloc)
+std::unordered_map<void*, Allocator> g_owner;    // blocks from a registered allocator
+
+}  // namespace
+
+void* dev_alloc(size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  Allocator a;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    a = g_alloc;
+  }
+  void* p = nullptr;
+  if (!a.alloc) {
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(FL_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    return p;
+  }
+  p = a.alloc(bytes, a.ctx);
+  if (!p) throw Error(FL_E_NOMEM, "the registered allocator failed for " + std::to_string(bytes) +
+                                      " bytes");
+  if (reinterpret_cast<uintptr_t>(p) % 256) {
+    a.release(p, a.ctx);
+    throw Error(FL_E_NOMEM, "the registered allocator returned memory not aligned to 256 bytes");
+  }
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_owner[p] = a;
+  return p;
+}
+
+void dev_free(void* p) {
+  if (!p) return;
+  Allocator a;
+  bool registered = false;
+  {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    auto it = g_owner.find(p);
+    if (it != g_owner.end()) {
+      a = it->second;
+      g_owner.erase(it);
+      registered = true;
+    }
+  }
+  if (!registered) {
+    hipFree(p);
+    return;
+  }
+  // hipFree waits for the device; a caller's allocator may reuse the block at
+  // once, so wait here for every queued use of it to finish
+  (void)hipDeviceSynchronize();
+  a.release(p, a.ctx);
+}
+
+}  // namespace fl
 
 using fl::Error;
 
@@ -38,16 +109,7 @@ fl_status guarded(F&& f) {
   }
 }
 
-void* dmalloc(size_t bytes) {
-  void* p = nullptr;
-  if (bytes == 0) bytes = 256;
-  hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    throw Error(FL_E_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
-  }
-  return p;
-}
+void* dmalloc(size_t bytes) { return fl::dev_alloc(bytes); }
 
 // Grow-only device buffer.
 struct DBuf {
@@ -55,7 +117,7 @@ struct DBuf {
   size_t bytes = 0;
   void* get(size_t need) {
     if (need > bytes) {
-      if (p) hipFree(p);
+      if (p) fl::dev_free(p);
       p = nullptr;
       bytes = 0;
       p = dmalloc(need);
@@ -64,7 +126,7 @@ struct DBuf {
     return p;
   }
   void release() {
-    if (p) hipFree(p);
+    if (p) fl::dev_free(p);
     p = nullptr;
     bytes = 0;
   }
@@ -156,6 +218,7 @@ struct fl_op_s {
   DBuf ext_work;          // exterior-term transform workspace
   bool ext_ready = false;
   DBuf ext_rhs;           // f - b for solves with exterior data
+  std::mutex solve_mu;    // one solve at a time (fl_solve, fl_solve_async)
   DBuf poll_dev;          // packed CG state for the host (device side)
   double* poll_host = nullptr;   // pinned copy
   size_t poll_cap = 0;
@@ -345,7 +408,7 @@ static fl_status create_op(int d, double alpha, int degree, int N, const int* Na
       double* scr = (double*)dmalloc(256);
       fl::build_inverse_symbol(A->g, A->lam64, nh, A->linv64, A->linv32, scr, st);
       FL_HIP(hipStreamSynchronize(st));
-      hipFree(scr);
+      fl::dev_free(scr);
     }
     for (int s = 0; s < 3; ++s) {
       const int M = A->g.Ma[s >= d ? 0 : s];
@@ -437,17 +500,27 @@ fl_status fl_weights_expsum(int d, double alpha, int degree, const int* interval
   });
 }
 
+fl_status fl_set_allocator(fl_alloc_fn alloc, fl_release_fn release, void* ctx) {
+  if ((alloc == nullptr) != (release == nullptr))
+    return fail(FL_E_INVAL, "give both alloc and release, or neither");
+  std::lock_guard<std::mutex> lk(fl::g_alloc_mu);
+  fl::g_alloc.alloc = alloc;
+  fl::g_alloc.release = release;
+  fl::g_alloc.ctx = ctx;
+  return FL_OK;
+}
+
 void fl_destroy(fl_op A) {
   if (!A) return;
   hipSetDevice(A->device);
   // wait for this handle's own work only (other streams keep running)
   if (A->solve_stream) hipStreamSynchronize(A->solve_stream);
   if (A->used && A->done) hipEventSynchronize(A->done);
-  if (A->G) hipFree(A->G);
-  if (A->lam64) hipFree(A->lam64);
-  if (A->lam32) hipFree(A->lam32);
-  if (A->linv64) hipFree(A->linv64);
-  if (A->linv32) hipFree(A->linv32);
+  fl::dev_free(A->G);
+  fl::dev_free(A->lam64);
+  fl::dev_free(A->lam32);
+  fl::dev_free(A->linv64);
+  fl::dev_free(A->linv32);
   A->ws.release();
   A->vecs.release();
   A->cg.mem.release();
@@ -522,7 +595,7 @@ fl_status fl_embedding(fl_op A, double* host_out, size_t count) {
     double* tmp = (double*)dmalloc(nm * sizeof(double));
     fl::embed_generator(A->g, A->G, tmp, nullptr);
     hipError_t e = hipMemcpy(host_out, tmp, nm * sizeof(double), hipMemcpyDeviceToHost);
-    hipFree(tmp);
+    fl::dev_free(tmp);
     if (e != hipSuccess) return fail(FL_E_DEVICE, hipGetErrorString(e));
     return FL_OK;
   });
@@ -1083,230 +1156,307 @@ extern "C" fl_status fl_exterior(fl_op A, const double* g_lat, const double* tai
   });
 }
 
+// Argument checks of fl_solve and fl_solve_async (no device work).
+static fl_status check_solve(fl_op A, const double* f, const double* g, double tol, int maxiter,
+                             int mixed, const double* u, int nrhs) {
+  if (!A) return fail(FL_E_INVAL, "null handle");
+  if (!f || !u) return fail(FL_E_INVAL, "null vector");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(FL_E_INVAL, "tol must be positive");
+  if (maxiter < 1) return fail(FL_E_INVAL, "maxiter must be >= 1");
+  if (nrhs < 1) return fail(FL_E_INVAL, "nrhs must be >= 1");
+  if (mixed < 0 || mixed > 2) return fail(FL_E_INVAL, "mixed must be 0, 1 or 2");
+  if ((const void*)f == (const void*)u) return fail(FL_E_INVAL, "f and u must be distinct");
+  if (g && (const void*)g == (const void*)u) return fail(FL_E_INVAL, "g and u must be distinct");
+  return FL_OK;
+}
+
+// The solve, on the operator's own stream, one at a time per operator.  It
+// starts after `user`'s work so far, or, given `after`, after that event
+// (the asynchronous form, which also leaves `user` free of the result).
+static fl_status solve_body(fl_op A, const double* f, const double* g, double tol, int maxiter,
+                            int mixed, double* u, int nrhs, fl_info* info, hipStream_t user,
+                            hipEvent_t after) {
+  std::lock_guard<std::mutex> lock(A->solve_mu);
+  set_device(A);
+  ensure_solver_stream(A);
+  hipStream_t st = A->solve_stream;
+  if (after) {
+    FL_HIP(hipStreamWaitEvent(st, after, 0));
+  } else {
+    FL_HIP(hipEventRecord(A->ev_in, user));
+    FL_HIP(hipStreamWaitEvent(st, A->ev_in, 0));
+  }
+  A->begin(st);
+  const long nd = A->g.nd;
+  const size_t v8 = (size_t)nrhs * nd * sizeof(double);
+  if (g) {
+    // exterior term b: solve A u = f - b
+    double* fb = (double*)A->ext_rhs.get(v8);
+    fl::difference(f, g, fb, (long)nrhs * nd, st);
+    f = fb;
+  }
+  const size_t v4 = (size_t)nrhs * nd * sizeof(float);
+  const size_t a8 = ((v8 + 255) / 256) * 256, a4 = ((v4 + 255) / 256) * 256;
+  std::vector<int> iters(nrhs, 0), outer(nrhs, 0), status(nrhs, 0);
+  std::vector<double> rec(nrhs, 0.0), tru(nrhs, 0.0);
+  A->cg.ensure(nrhs, st);
+  A->cg_out.ensure(nrhs, st);
+  const fl::CgScalars& co = A->cg_out.s;
+  // per-RHS host-visible norms and flags: f2, rr (outer), scale, flags
+  char* fb = (char*)A->outer_flags.get(4 * (size_t)nrhs * sizeof(double) +
+                                       3 * (size_t)nrhs * sizeof(int) + 1024);
+  double* f2 = (double*)fb;
+  double* rro = f2 + nrhs;
+  double* scale = rro + nrhs;
+  double* rr_last = scale + nrhs;
+  int* oact = (int*)(rr_last + nrhs);
+  int* trig = oact + nrhs;
+  int* nupd = trig + nrhs;
+  void* ws = A->ws.get(fl::apply_workspace_bytes(A->g, nrhs, false));
+  std::vector<double> hf2(nrhs), hrr(nrhs);
+  sum_squares(A, f, nrhs, co, f2, st);
+  const int pc = A->precond;
+  if (!mixed) {
+    const fl::CgScalars cg = cg_view(A->cg.s, A->g, A->sc64, A->sp64, nrhs, maxiter, tol, pc);
+    char* vb = (char*)A->vecs.get(5 * a8);
+    double* r = (double*)vb;
+    double* p = (double*)(vb + a8);
+    double* q = (double*)(vb + 2 * a8);
+    double* x = (double*)(vb + 3 * a8);
+    double* z = (double*)(vb + 4 * a8);
+    cg_start<double>(A, A->sc64, pc_symbol<double>(A), A->tw64, f, x, r, p, z, nrhs, cg, nullptr, ws, st);
+    const int chunk = 8;
+    std::vector<double> key = make_key(0, nrhs, chunk, maxiter, tol, pc);
+    for (double v : {pkey(ws), pkey(vb), pkey(A->cg.mem.p), pkey(A->lam64)}) key.push_back(v);
+    for (double v : sched_key(A->sc64)) key.push_back(v);
+    for (double v : sched_key(A->sp64)) key.push_back(v);
+    predictive_loop(A, key, maxiter + 2, cg, nrhs, st, [&]() {
+      cg_iteration<double>(A, A->sc64, A->lam64, pc_symbol<double>(A), A->tw64, x, r, p, q, z, nrhs, cg,
+                           ws, st);
+    });
+    FL_HIP(hipMemcpyAsync(u, x, v8, hipMemcpyDeviceToDevice, st));
+    // true residual with an FP64 product (into q); the results travel in
+    // one pinned record (copies into pageable memory would each wait)
+    fp64_residual(A, f, u, q, nrhs, co, nullptr, rro, ws, st);
+    std::vector<double> rr(nrhs);
+    read_results(A, nrhs, cg.iters, cg.status, nullptr, cg.res2, rro, f2, st, iters, status,
+                 outer, rr, hrr, hf2);
+    for (int o = 0; o < nrhs; ++o) {
+      const double fn = std::sqrt(hf2[o]);
+      rec[o] = fn > 0 ? std::sqrt(rr[o]) / fn : 0.0;
+      tru[o] = fn > 0 ? std::sqrt(hrr[o]) / fn : 0.0;
+      if (status[o] == 0 && !(rec[o] <= tol) && fn > 0) status[o] = FL_E_NOCONV;
+    }
+  } else if (mixed == 1) {
+    // FP32 CG with FP64 reliable updates: the FP32 recursion runs on a
+    // correction xlo; after every predicted chunk of iterations each RHS
+    // whose FP32 r.r fell below delta^2 of its value at the last update
+    // (or below the tolerance) folds xlo into the FP64 iterate, recomputes
+    // r = f - A u in FP64, stops if ||r|| <= tol ||f||, and otherwise
+    // continues from r (rounded to FP32); preconditioned, the search
+    // direction restarts there.
+    fl::CgScalars cg = cg_view(A->cg.s, A->g, A->sc32, A->sp32, nrhs, maxiter, tol, pc);
+    cg.tol2 = 0.0;  // the FP32 recursion never stops on its own residual
+    const double delta2 = A->delta * A->delta;
+    // ... but waits for a reliable update at the iteration start where its
+    // r.r reaches the trigger (cg_begin)
+    cg.rel_last = rr_last;
+    cg.rel_f2 = f2;
+    cg.rel_trig = trig;
+    cg.rel_delta2 = delta2;
+    cg.rel_tol2 = tol * tol;
+    const int nb64 = fl::last_pass_blocks(A->g, A->sc64);
+    char* vb = (char*)A->vecs.get(3 * a8 + 6 * a4);
+    double* r64 = (double*)vb;
+    double* xhi = (double*)(vb + a8);
+    double* fc = (double*)(vb + 2 * a8);
+    float* rhs32 = (float*)(vb + 3 * a8);
+    float* xlo = (float*)(vb + 3 * a8 + a4);
+    float* r32 = (float*)(vb + 3 * a8 + 2 * a4);
+    float* p32 = (float*)(vb + 3 * a8 + 3 * a4);
+    float* q32 = (float*)(vb + 3 * a8 + 4 * a4);
+    float* z32 = (float*)(vb + 3 * a8 + 5 * a4);
+    fl::fill_zero_bytes(xhi, v8, st);
+    FL_HIP(hipMemcpyAsync(fc, f, v8, hipMemcpyDeviceToDevice, st));
+    fl::to_float(f, rhs32, (long)nrhs * nd, st);
+    FL_HIP(hipMemcpyAsync(rr_last, f2, nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
+    fl::fill_int(nupd, 0, nrhs, st);
+    fl::fill_int(trig, 0, nrhs, st);
+    cg_start<float>(A, A->sc32, pc_symbol<float>(A), A->tw32, rhs32, xlo, r32, p32, z32, nrhs, cg,
+                    nullptr, ws, st);
+    const int chunk = 8;
+    std::vector<double> key = make_key(1, nrhs, chunk, maxiter, tol, A->delta, pc);
+    for (double v : {pkey(ws), pkey(vb), pkey(A->cg.mem.p), pkey(A->cg_out.mem.p),
+                     pkey(A->outer_flags.p), pkey(A->lam32)})
+      key.push_back(v);
+    for (double v : sched_key(A->sc32)) key.push_back(v);
+    for (double v : sched_key(A->sp32)) key.push_back(v);
+    for (double v : sched_key(A->sc64)) key.push_back(v);
+    predictive_mixed_loop(
+        A, key, maxiter, cg, nrhs, rr_last, f2, nupd, delta2, tol * tol, st,
+        [&]() {
+          cg_iteration<float>(A, A->sc32, A->lam32, pc_symbol<float>(A), A->tw32, xlo, r32, p32,
+                              q32, z32, nrhs, cg, ws, st);
+        },
+        [&]() {
+          fl::reliable_accum(A->g, xhi, xlo, nrhs, cg, trig, false, st);
+          fl::apply_passes<double>(A->g, A->sc64, A->lam64, A->tw64, xhi, r64, nrhs, ws, st,
+                                   fl::PM_RESID, nullptr, nullptr, fc, &co, trig);
+          fl::reliable_replace(A->g, r64, r32, nrhs, cg, co.part_a, nb64, co.max_blocks,
+                               rr_last, f2, tol * tol, trig, nupd, st);
+          if (pc)
+            precond_apply<float>(A, pc_symbol<float>(A), A->tw32, r32, z32, nrhs, ws, cg, trig,
+                                 st);
+        });
+    // fold what is left (RHS stopped by maxiter) and report true residuals
+    fl::reliable_accum(A->g, xhi, xlo, nrhs, cg, trig, true, st);
+    FL_HIP(hipMemcpyAsync(u, xhi, v8, hipMemcpyDeviceToDevice, st));
+    fp64_residual(A, f, u, r64, nrhs, co, nullptr, rro, ws, st);
+    std::vector<double> rr(nrhs);
+    read_results(A, nrhs, cg.iters, cg.status, nupd, nullptr, rro, f2, st, iters, status, outer,
+                 rr, hrr, hf2);
+    for (int o = 0; o < nrhs; ++o) {
+      const double rel = hf2[o] > 0 ? std::sqrt(hrr[o] / hf2[o]) : 0.0;
+      rec[o] = rel;
+      tru[o] = rel;
+      if (status[o] == 0 && !(rel <= tol) && hf2[o] > 0) status[o] = FL_E_NOCONV;
+    }
+  } else {
+    // FP64 residual and iterate; FP32 CG on A delta = r / ||r|| (inner_tol)
+    const fl::CgScalars cg = cg_view(A->cg.s, A->g, A->sc32, A->sp32, nrhs, maxiter, A->inner_tol, pc);
+    char* vb = (char*)A->vecs.get(a8 + 6 * a4);
+    double* r64 = (double*)vb;
+    float* rhs32 = (float*)(vb + a8);
+    float* d32 = (float*)(vb + a8 + a4);
+    float* r32 = (float*)(vb + a8 + 2 * a4);
+    float* p32 = (float*)(vb + a8 + 3 * a4);
+    float* q32 = (float*)(vb + a8 + 4 * a4);
+    float* z32 = (float*)(vb + a8 + 5 * a4);
+    fl::fill_zero_bytes(u, v8, st);
+    FL_HIP(hipMemcpyAsync(r64, f, v8, hipMemcpyDeviceToDevice, st));
+    FL_HIP(hipMemcpyAsync(rro, f2, nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
+    std::vector<int> hact(nrhs), hit(nrhs), hst(nrhs);
+    FL_HIP(hipMemcpyAsync(hf2.data(), f2, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+    FL_HIP(hipStreamSynchronize(st));
+    hrr = hf2;
+    for (int step = 0;; ++step) {
+      int nact = 0;
+      for (int o = 0; o < nrhs; ++o) {
+        const double rel = hf2[o] > 0 ? std::sqrt(hrr[o] / hf2[o]) : 0.0;
+        const bool bad = !std::isfinite(rel);
+        hact[o] = (!bad && rel > tol && status[o] == 0) ? 1 : 0;
+        if (bad) status[o] = FL_E_BREAKDOWN;
+        nact += hact[o];
+      }
+      if (nact == 0) break;
+      if (step >= A->max_outer) {
+        for (int o = 0; o < nrhs; ++o)
+          if (hact[o]) status[o] = FL_E_NOCONV;
+        break;
+      }
+      FL_HIP(hipMemcpyAsync(oact, hact.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
+      fl::refine_scale(r64, rhs32, rro, scale, nd, nrhs, oact, st);
+      cg_run<float>(A, A->sc32, A->lam32, pc_symbol<float>(A), A->tw32, rhs32, d32, r32, p32, q32, z32,
+                    nrhs, cg, oact, ws, st);
+      fl::refine_axpy(u, d32, scale, nd, nrhs, oact, st);
+      fp64_residual(A, f, u, r64, nrhs, co, oact, rro, ws, st);
+      FL_HIP(hipMemcpyAsync(hit.data(), cg.iters, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
+      FL_HIP(hipMemcpyAsync(hst.data(), cg.status, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
+      FL_HIP(hipMemcpyAsync(hrr.data(), rro, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
+      FL_HIP(hipStreamSynchronize(st));
+      for (int o = 0; o < nrhs; ++o)
+        if (hact[o]) {
+          iters[o] += hit[o];
+          outer[o] += 1;
+          if (hst[o] == FL_E_BREAKDOWN && hit[o] == 0) status[o] = FL_E_BREAKDOWN;
+        }
+    }
+    for (int o = 0; o < nrhs; ++o) {
+      const double rel = hf2[o] > 0 ? std::sqrt(hrr[o] / hf2[o]) : 0.0;
+      rec[o] = rel;
+      tru[o] = rel;
+    }
+  }
+  A->end(st);
+  if (!after) FL_HIP(hipStreamWaitEvent(user, A->done, 0));
+  fl_status worst = FL_OK;
+  for (int o = 0; o < nrhs; ++o) {
+    if (info) {
+      info[o].iters = iters[o];
+      info[o].outer_iters = outer[o];
+      info[o].status = status[o];
+      info[o].converged = status[o] == 0;
+      info[o].relres_rec = rec[o];
+      info[o].relres_true = tru[o];
+    }
+    if (status[o] != 0 && worst == FL_OK) worst = (fl_status)status[o];
+  }
+  if (worst != FL_OK) g_last_error = "some right-hand sides did not converge";
+  return worst;
+}
+
 extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double tol, int maxiter,
                               int mixed, double* u, int nrhs, fl_info* info, void* stream) {
   return guarded([&]() -> fl_status {
-    if (!A) return fail(FL_E_INVAL, "null handle");
-    if (!f || !u) return fail(FL_E_INVAL, "null vector");
-    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(FL_E_INVAL, "tol must be positive");
-    if (maxiter < 1) return fail(FL_E_INVAL, "maxiter must be >= 1");
-    if (nrhs < 1) return fail(FL_E_INVAL, "nrhs must be >= 1");
-    if (mixed < 0 || mixed > 2) return fail(FL_E_INVAL, "mixed must be 0, 1 or 2");
-    if ((const void*)f == (const void*)u) return fail(FL_E_INVAL, "f and u must be distinct");
-    if (g && (const void*)g == (const void*)u) return fail(FL_E_INVAL, "g and u must be distinct");
-    set_device(A);
-    // work runs on the operator's own stream, ordered after `stream`
-    hipStream_t user = (hipStream_t)stream;
-    ensure_solver_stream(A);
-    hipStream_t st = A->solve_stream;
-    FL_HIP(hipEventRecord(A->ev_in, user));
-    FL_HIP(hipStreamWaitEvent(st, A->ev_in, 0));
-    A->begin(st);
-    const long nd = A->g.nd;
-    const size_t v8 = (size_t)nrhs * nd * sizeof(double);
-    if (g) {
-      // exterior term b: solve A u = f - b
-      double* fb = (double*)A->ext_rhs.get(v8);
-      fl::difference(f, g, fb, (long)nrhs * nd, st);
-      f = fb;
-    }
-    const size_t v4 = (size_t)nrhs * nd * sizeof(float);
-    const size_t a8 = ((v8 + 255) / 256) * 256, a4 = ((v4 + 255) / 256) * 256;
-    std::vector<int> iters(nrhs, 0), outer(nrhs, 0), status(nrhs, 0);
-    std::vector<double> rec(nrhs, 0.0), tru(nrhs, 0.0);
-    A->cg.ensure(nrhs, st);
-    A->cg_out.ensure(nrhs, st);
-    const fl::CgScalars& co = A->cg_out.s;
-    // per-RHS host-visible norms and flags: f2, rr (outer), scale, flags
-    char* fb = (char*)A->outer_flags.get(4 * (size_t)nrhs * sizeof(double) +
-                                         3 * (size_t)nrhs * sizeof(int) + 1024);
-    double* f2 = (double*)fb;
-    double* rro = f2 + nrhs;
-    double* scale = rro + nrhs;
-    double* rr_last = scale + nrhs;
-    int* oact = (int*)(rr_last + nrhs);
-    int* trig = oact + nrhs;
-    int* nupd = trig + nrhs;
-    void* ws = A->ws.get(fl::apply_workspace_bytes(A->g, nrhs, false));
-    std::vector<double> hf2(nrhs), hrr(nrhs);
-    sum_squares(A, f, nrhs, co, f2, st);
-    const int pc = A->precond;
-    if (!mixed) {
-      const fl::CgScalars cg = cg_view(A->cg.s, A->g, A->sc64, A->sp64, nrhs, maxiter, tol, pc);
-      char* vb = (char*)A->vecs.get(5 * a8);
-      double* r = (double*)vb;
-      double* p = (double*)(vb + a8);
-      double* q = (double*)(vb + 2 * a8);
-      double* x = (double*)(vb + 3 * a8);
-      double* z = (double*)(vb + 4 * a8);
-      cg_start<double>(A, A->sc64, pc_symbol<double>(A), A->tw64, f, x, r, p, z, nrhs, cg, nullptr, ws, st);
-      const int chunk = 8;
-      std::vector<double> key = make_key(0, nrhs, chunk, maxiter, tol, pc);
-      for (double v : {pkey(ws), pkey(vb), pkey(A->cg.mem.p), pkey(A->lam64)}) key.push_back(v);
-      for (double v : sched_key(A->sc64)) key.push_back(v);
-      for (double v : sched_key(A->sp64)) key.push_back(v);
-      predictive_loop(A, key, maxiter + 2, cg, nrhs, st, [&]() {
-        cg_iteration<double>(A, A->sc64, A->lam64, pc_symbol<double>(A), A->tw64, x, r, p, q, z, nrhs, cg,
-                             ws, st);
-      });
-      FL_HIP(hipMemcpyAsync(u, x, v8, hipMemcpyDeviceToDevice, st));
-      // true residual with an FP64 product (into q); the results travel in
-      // one pinned record (copies into pageable memory would each wait)
-      fp64_residual(A, f, u, q, nrhs, co, nullptr, rro, ws, st);
-      std::vector<double> rr(nrhs);
-      read_results(A, nrhs, cg.iters, cg.status, nullptr, cg.res2, rro, f2, st, iters, status,
-                   outer, rr, hrr, hf2);
-      for (int o = 0; o < nrhs; ++o) {
-        const double fn = std::sqrt(hf2[o]);
-        rec[o] = fn > 0 ? std::sqrt(rr[o]) / fn : 0.0;
-        tru[o] = fn > 0 ? std::sqrt(hrr[o]) / fn : 0.0;
-        if (status[o] == 0 && !(rec[o] <= tol) && fn > 0) status[o] = FL_E_NOCONV;
-      }
-    } else if (mixed == 1) {
-      // FP32 CG with FP64 reliable updates: the FP32 recursion runs on a
-      // correction xlo; after every predicted chunk of iterations each RHS
-      // whose FP32 r.r fell below delta^2 of its value at the last update
-      // (or below the tolerance) folds xlo into the FP64 iterate, recomputes
-      // r = f - A u in FP64, stops if ||r|| <= tol ||f||, and otherwise
-      // continues from r (rounded to FP32); preconditioned, the search
-      // direction restarts there.
-      fl::CgScalars cg = cg_view(A->cg.s, A->g, A->sc32, A->sp32, nrhs, maxiter, tol, pc);
-      cg.tol2 = 0.0;  // the FP32 recursion never stops on its own residual
-      const double delta2 = A->delta * A->delta;
-      // ... but waits for a reliable update at the iteration start where its
-      // r.r reaches the trigger (cg_begin)
-      cg.rel_last = rr_last;
-      cg.rel_f2 = f2;
-      cg.rel_trig = trig;
-      cg.rel_delta2 = delta2;
-      cg.rel_tol2 = tol * tol;
-      const int nb64 = fl::last_pass_blocks(A->g, A->sc64);
-      char* vb = (char*)A->vecs.get(3 * a8 + 6 * a4);
-      double* r64 = (double*)vb;
-      double* xhi = (double*)(vb + a8);
-      double* fc = (double*)(vb + 2 * a8);
-      float* rhs32 = (float*)(vb + 3 * a8);
-      float* xlo = (float*)(vb + 3 * a8 + a4);
-      float* r32 = (float*)(vb + 3 * a8 + 2 * a4);
-      float* p32 = (float*)(vb + 3 * a8 + 3 * a4);
-      float* q32 = (float*)(vb + 3 * a8 + 4 * a4);
-      float* z32 = (float*)(vb + 3 * a8 + 5 * a4);
-      fl::fill_zero_bytes(xhi, v8, st);
-      FL_HIP(hipMemcpyAsync(fc, f, v8, hipMemcpyDeviceToDevice, st));
-      fl::to_float(f, rhs32, (long)nrhs * nd, st);
-      FL_HIP(hipMemcpyAsync(rr_last, f2, nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
-      fl::fill_int(nupd, 0, nrhs, st);
-      fl::fill_int(trig, 0, nrhs, st);
-      cg_start<float>(A, A->sc32, pc_symbol<float>(A), A->tw32, rhs32, xlo, r32, p32, z32, nrhs, cg,
-                      nullptr, ws, st);
-      const int chunk = 8;
-      std::vector<double> key = make_key(1, nrhs, chunk, maxiter, tol, A->delta, pc);
-      for (double v : {pkey(ws), pkey(vb), pkey(A->cg.mem.p), pkey(A->cg_out.mem.p),
-                       pkey(A->outer_flags.p), pkey(A->lam32)})
-        key.push_back(v);
-      for (double v : sched_key(A->sc32)) key.push_back(v);
-      for (double v : sched_key(A->sp32)) key.push_back(v);
-      for (double v : sched_key(A->sc64)) key.push_back(v);
-      predictive_mixed_loop(
-          A, key, maxiter, cg, nrhs, rr_last, f2, nupd, delta2, tol * tol, st,
-          [&]() {
-            cg_iteration<float>(A, A->sc32, A->lam32, pc_symbol<float>(A), A->tw32, xlo, r32, p32,
-                                q32, z32, nrhs, cg, ws, st);
-          },
-          [&]() {
-            fl::reliable_accum(A->g, xhi, xlo, nrhs, cg, trig, false, st);
-            fl::apply_passes<double>(A->g, A->sc64, A->lam64, A->tw64, xhi, r64, nrhs, ws, st,
-                                     fl::PM_RESID, nullptr, nullptr, fc, &co, trig);
-            fl::reliable_replace(A->g, r64, r32, nrhs, cg, co.part_a, nb64, co.max_blocks,
-                                 rr_last, f2, tol * tol, trig, nupd, st);
-            if (pc)
-              precond_apply<float>(A, pc_symbol<float>(A), A->tw32, r32, z32, nrhs, ws, cg, trig,
-                                   st);
-          });
-      // fold what is left (RHS stopped by maxiter) and report true residuals
-      fl::reliable_accum(A->g, xhi, xlo, nrhs, cg, trig, true, st);
-      FL_HIP(hipMemcpyAsync(u, xhi, v8, hipMemcpyDeviceToDevice, st));
-      fp64_residual(A, f, u, r64, nrhs, co, nullptr, rro, ws, st);
-      std::vector<double> rr(nrhs);
-      read_results(A, nrhs, cg.iters, cg.status, nupd, nullptr, rro, f2, st, iters, status, outer,
-                   rr, hrr, hf2);
-      for (int o = 0; o < nrhs; ++o) {
-        const double rel = hf2[o] > 0 ? std::sqrt(hrr[o] / hf2[o]) : 0.0;
-        rec[o] = rel;
-        tru[o] = rel;
-        if (status[o] == 0 && !(rel <= tol) && hf2[o] > 0) status[o] = FL_E_NOCONV;
-      }
-    } else {
-      // FP64 residual and iterate; FP32 CG on A delta = r / ||r|| (inner_tol)
-      const fl::CgScalars cg = cg_view(A->cg.s, A->g, A->sc32, A->sp32, nrhs, maxiter, A->inner_tol, pc);
-      char* vb = (char*)A->vecs.get(a8 + 6 * a4);
-      double* r64 = (double*)vb;
-      float* rhs32 = (float*)(vb + a8);
-      float* d32 = (float*)(vb + a8 + a4);
-      float* r32 = (float*)(vb + a8 + 2 * a4);
-      float* p32 = (float*)(vb + a8 + 3 * a4);
-      float* q32 = (float*)(vb + a8 + 4 * a4);
-      float* z32 = (float*)(vb + a8 + 5 * a4);
-      fl::fill_zero_bytes(u, v8, st);
-      FL_HIP(hipMemcpyAsync(r64, f, v8, hipMemcpyDeviceToDevice, st));
-      FL_HIP(hipMemcpyAsync(rro, f2, nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
-      std::vector<int> hact(nrhs), hit(nrhs), hst(nrhs);
-      FL_HIP(hipMemcpyAsync(hf2.data(), f2, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
-      FL_HIP(hipStreamSynchronize(st));
-      hrr = hf2;
-      for (int step = 0;; ++step) {
-        int nact = 0;
-        for (int o = 0; o < nrhs; ++o) {
-          const double rel = hf2[o] > 0 ? std::sqrt(hrr[o] / hf2[o]) : 0.0;
-          const bool bad = !std::isfinite(rel);
-          hact[o] = (!bad && rel > tol && status[o] == 0) ? 1 : 0;
-          if (bad) status[o] = FL_E_BREAKDOWN;
-          nact += hact[o];
-        }
-        if (nact == 0) break;
-        if (step >= A->max_outer) {
-          for (int o = 0; o < nrhs; ++o)
-            if (hact[o]) status[o] = FL_E_NOCONV;
-          break;
-        }
-        FL_HIP(hipMemcpyAsync(oact, hact.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
-        fl::refine_scale(r64, rhs32, rro, scale, nd, nrhs, oact, st);
-        cg_run<float>(A, A->sc32, A->lam32, pc_symbol<float>(A), A->tw32, rhs32, d32, r32, p32, q32, z32,
-                      nrhs, cg, oact, ws, st);
-        fl::refine_axpy(u, d32, scale, nd, nrhs, oact, st);
-        fp64_residual(A, f, u, r64, nrhs, co, oact, rro, ws, st);
-        FL_HIP(hipMemcpyAsync(hit.data(), cg.iters, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
-        FL_HIP(hipMemcpyAsync(hst.data(), cg.status, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));
-        FL_HIP(hipMemcpyAsync(hrr.data(), rro, nrhs * sizeof(double), hipMemcpyDeviceToHost, st));
-        FL_HIP(hipStreamSynchronize(st));
-        for (int o = 0; o < nrhs; ++o)
-          if (hact[o]) {
-            iters[o] += hit[o];
-            outer[o] += 1;
-            if (hst[o] == FL_E_BREAKDOWN && hit[o] == 0) status[o] = FL_E_BREAKDOWN;
-          }
-      }
-      for (int o = 0; o < nrhs; ++o) {
-        const double rel = hf2[o] > 0 ? std::sqrt(hrr[o] / hf2[o]) : 0.0;
-        rec[o] = rel;
-        tru[o] = rel;
-      }
-    }
-    A->end(st);
-    FL_HIP(hipStreamWaitEvent(user, A->done, 0));
-    fl_status worst = FL_OK;
-    for (int o = 0; o < nrhs; ++o) {
-      if (info) {
-        info[o].iters = iters[o];
-        info[o].outer_iters = outer[o];
-        info[o].status = status[o];
-        info[o].converged = status[o] == 0;
-        info[o].relres_rec = rec[o];
-        info[o].relres_true = tru[o];
-      }
-      if (status[o] != 0 && worst == FL_OK) worst = (fl_status)status[o];
-    }
-    if (worst != FL_OK) g_last_error = "some right-hand sides did not converge";
-    return worst;
+    const fl_status e = check_solve(A, f, g, tol, maxiter, mixed, u, nrhs);
+    if (e != FL_OK) return e;
+    return solve_body(A, f, g, tol, maxiter, mixed, u, nrhs, info, (hipStream_t)stream, nullptr);
   });
+}
+
+// A solve running on its own host thread (fl_solve_async).
+struct fl_request_s {
+  std::thread worker;
+  std::atomic<int> done{0};
+  fl_status status = FL_OK;
+  std::string error;
+  std::vector<fl_info> info;
+};
+
+extern "C" fl_status fl_solve_async(fl_op A, const double* f, const double* g, double tol,
+                                    int maxiter, int mixed, double* u, int nrhs, void* stream,
+                                    fl_request* out) {
+  return guarded([&]() -> fl_status {
+    if (!out) return fail(FL_E_INVAL, "out is NULL");
+    const fl_status e = check_solve(A, f, g, tol, maxiter, mixed, u, nrhs);
+    if (e != FL_OK) return e;
+    // order the solve after the caller's work on `stream` submitted so far
+    set_device(A);
+    hipEvent_t after = nullptr;
+    FL_HIP(hipEventCreateWithFlags(&after, hipEventDisableTiming));
+    hipError_t he = hipEventRecord(after, (hipStream_t)stream);
+    if (he != hipSuccess) {
+      hipEventDestroy(after);
+      return fail(FL_E_DEVICE, hipGetErrorString(he));
+    }
+    fl_request R = new fl_request_s();
+    R->info.resize(nrhs);
+    R->worker = std::thread([=]() {
+      R->status = guarded([&]() -> fl_status {
+        return solve_body(A, f, g, tol, maxiter, mixed, u, nrhs, R->info.data(), nullptr, after);
+      });
+      if (R->status != FL_OK) R->error = fl_last_error();
+      hipEventDestroy(after);
+      R->done.store(1, std::memory_order_release);
+    });
+    *out = R;
+    return FL_OK;
+  });
+}
+
+extern "C" fl_status fl_poll(fl_request R, int* done) {
+  if (!R || !done) return fail(FL_E_INVAL, "null argument");
+  *done = R->done.load(std::memory_order_acquire);
+  return FL_OK;
+}
+
+extern "C" fl_status fl_wait(fl_request R, fl_info* info) {
+  if (!R) return fail(FL_E_INVAL, "null request");
+  if (R->worker.joinable()) R->worker.join();
+  if (info) std::copy(R->info.begin(), R->info.end(), info);
+  const fl_status st = R->status;
+  if (st != FL_OK) g_last_error = R->error;
+  else g_last_error.clear();
+  delete R;
+  return st;
 }

@@ -178,7 +178,14 @@ void apply_passes(const Geometry& g, const Schedule& sc, const T* lam, const Twi
 // Number of kernel launches (passes) of one application: 1, 3 or 5 for d = 1, 2, 3.
 inline int apply_npasses(int d) { return d == 1 ? 1 : (d == 2 ? 3 : 5); }
 
-// Twiddle table exp(-2 pi i j / M), j < M (cx<T> array), cached per device.
+// Device memory for operator buffers and setup temporaries: the allocator
+// registered with fl_set_allocator, else hipMalloc.  dev_free returns a block
+// to the allocator that made it (after the device has finished with it).
+void* dev_alloc(size_t bytes);
+void dev_free(void* p);
+
+// Twiddle table exp(-2 pi i j / M), j < M (cx<T> array), cached per device
+// for the life of the process (hipMalloc, not the registered allocator).
 const void* twiddles(int M, bool fp32, hipStream_t st);
 
 // Generator, symbol: see weights unit.

@@ -202,8 +202,7 @@ void build_symbol(const Geometry& g, const double* G, double* lam64, float* lam3
   const int d = g.d;
   const long total = g.nm();
   const EmbedDims e = embed_dims(g);
-  cx<double>* c = nullptr;
-  FL_HIP(hipMalloc(&c, (size_t)total * sizeof(cx<double>)));
+  cx<double>* c = (cx<double>*)dev_alloc((size_t)total * sizeof(cx<double>));
   const int thr = 256;
   hipLaunchKernelGGL(k_embed, dim3((unsigned)((total + thr - 1) / thr)), dim3(thr), 0, st, c, G,
                      e, total);
@@ -214,7 +213,7 @@ void build_symbol(const Geometry& g, const double* G, double* lam64, float* lam3
                      lam32, e, nf, 1.0 / (double)total);
   check_launch("fold");
   FL_HIP(hipStreamSynchronize(st));
-  FL_HIP(hipFree(c));
+  dev_free(c);
 }
 
 }  // namespace fl

@@ -461,12 +461,12 @@ void build_generator(const GenParams& gp, double* G, hipStream_t st) {
   const long nblk = (nnode + thr - 1) / thr;
   GLTables* dtb = nullptr;
   double *elem = nullptr, *orig = nullptr, *omega = nullptr, *part = nullptr, *T = nullptr;
-  FL_HIP(hipMalloc(&dtb, sizeof(GLTables)));
-  FL_HIP(hipMalloc(&elem, (size_t)nelem * nout * sizeof(double)));
-  FL_HIP(hipMalloc(&orig, 32 * sizeof(double)));
-  FL_HIP(hipMalloc(&omega, (size_t)nnode * sizeof(double)));
-  FL_HIP(hipMalloc(&part, (size_t)nblk * sizeof(double)));
-  FL_HIP(hipMalloc(&T, sizeof(double)));
+  dtb = (GLTables*)dev_alloc(sizeof(GLTables));
+  elem = (double*)dev_alloc((size_t)nelem * nout * sizeof(double));
+  orig = (double*)dev_alloc(32 * sizeof(double));
+  omega = (double*)dev_alloc((size_t)nnode * sizeof(double));
+  part = (double*)dev_alloc((size_t)nblk * sizeof(double));
+  T = (double*)dev_alloc(sizeof(double));
   FL_HIP(hipMemcpyAsync(dtb, &tb, sizeof(GLTables), hipMemcpyHostToDevice, st));
   // one pass per kernel term: omega and T accumulate coef * (that term's);
   // the lattice-unit rate is rate * h (K = 1 integrates on the unit lattice)
@@ -486,12 +486,12 @@ void build_generator(const GenParams& gp, double* G, hipStream_t st) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) throw Error(4, std::string("generator kernels: ") + hipGetErrorString(e));
   FL_HIP(hipStreamSynchronize(st));
-  hipFree(dtb);
-  hipFree(elem);
-  hipFree(orig);
-  hipFree(omega);
-  hipFree(part);
-  hipFree(T);
+  dev_free(dtb);
+  dev_free(elem);
+  dev_free(orig);
+  dev_free(omega);
+  dev_free(part);
+  dev_free(T);
 }
 
 }  // namespace fl

@@ -147,3 +147,20 @@ def test_fl_weights_expsum_validation():
     assert call([1.0], [0.0], nterm=0) == _lib.FL_E_INVAL
     assert call([1.0], [0.0], intervals=None) == _lib.FL_E_INVAL
     assert _lib.FL_MAX_KERNEL_TERMS == 16
+
+
+def test_allocator_and_async_argument_checks():
+    """fl_set_allocator needs both callbacks or neither; the request calls
+    reject null handles; fl_solve_async validates like fl_solve (no device
+    work happens in any of these)."""
+    lib = _lib.lib()
+    alloc = _lib.ALLOC_FN(lambda n, ctx: None)
+    assert lib.fl_set_allocator(alloc, _lib.RELEASE_FN(), None) == _lib.FL_E_INVAL
+    assert lib.fl_set_allocator(_lib.ALLOC_FN(), _lib.RELEASE_FN(), None) == _lib.FL_OK
+    flag = ctypes.c_int(7)
+    assert lib.fl_poll(None, ctypes.byref(flag)) == _lib.FL_E_INVAL
+    assert lib.fl_wait(None, None) == _lib.FL_E_INVAL
+    req = ctypes.c_void_p()
+    assert lib.fl_solve_async(None, None, None, 1e-10, 10, 0, None, 1, None,
+                              ctypes.byref(req)) == _lib.FL_E_INVAL
+    assert req.value is None

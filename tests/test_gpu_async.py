@@ -1,0 +1,114 @@
+"""The asynchronous solve (fl_solve_async / fl_poll / fl_wait) and the
+caller's device allocator (fl_set_allocator).
+
+An asynchronous solve gives the bits of the blocking one (same operator,
+same input, same graphs), while several run at once on different operators
+and queue on one; its failures come back through fl_wait.  With torch's
+caching allocator registered, the operator's memory comes from torch and
+goes back to it, and the results are the bits of a default operator.
+"""
+
+import time
+
+import numpy as np
+import pytest
+
+from paper_2103_03658_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def make_op(alpha, N=128, p=1):
+    import paper_2103_03658_amd as fl
+    return fl.Operator(2, alpha, p, N=N)
+
+
+def wait_all(reqs, limit_s=60.0):
+    t0 = time.time()
+    while not all(r.done() for r in reqs):
+        assert time.time() - t0 < limit_s, "asynchronous solves did not finish"
+        time.sleep(0.002)
+    return [r.wait() for r in reqs]
+
+
+@pytest.mark.parametrize("mixed", [0, 1])
+def test_async_matches_blocking(mixed):
+    print(f"[async] mixed={mixed}", flush=True)
+    ops = [make_op(a) for a in (0.5, 1.0, 1.5)]
+    fs = [torch.from_numpy(inputs.uniform_rhs(2, 128, 3, seed=40 + i)).cuda() for i in range(3)]
+    ref = [op.solve(f, tol=1e-10, mixed=mixed) for op, f in zip(ops, fs)]
+    # three operators at once, and a second request queued on the first one
+    f4 = torch.from_numpy(inputs.uniform_rhs(2, 128, 3, seed=77)).cuda()
+    ref4 = ops[0].solve(f4, tol=1e-10, mixed=mixed)
+    reqs = [op.solve_async(f, tol=1e-10, mixed=mixed) for op, f in zip(ops, fs)]
+    reqs.append(ops[0].solve_async(f4, tol=1e-10, mixed=mixed))
+    got = wait_all(reqs)
+    for (u, info), (ur, infor) in zip(got, ref + [ref4]):
+        assert torch.equal(u, ur)
+        assert [i["iters"] for i in info] == [i["iters"] for i in infor]
+        assert all(i["converged"] == 1 for i in info)
+
+
+def test_async_orders_after_the_callers_stream():
+    """The solve starts after the work queued on the given stream: a right-hand
+    side still being written there is the one solved."""
+    op = make_op(1.2)
+    s = torch.cuda.Stream()
+    f = torch.zeros((2, 127, 127), dtype=torch.float64, device="cuda")
+    src = torch.from_numpy(inputs.uniform_rhs(2, 128, 2, seed=5)).cuda()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        torch.cuda._sleep(2_000_000)          # keep the stream busy first
+        f.copy_(src)
+    req = op.solve_async(f, tol=1e-10, stream=s)
+    u, info = req.wait()
+    ur, _ = op.solve(src, tol=1e-10)
+    assert torch.equal(u, ur)
+
+
+def test_async_failure_comes_back_through_wait():
+    import paper_2103_03658_amd as fl
+    op = make_op(1.5)
+    f = torch.from_numpy(inputs.uniform_rhs(2, 128, 2, seed=9)).cuda()
+    req = op.solve_async(f, tol=1e-14, maxiter=2)
+    with pytest.raises(fl.FlError):
+        req.wait()
+    u, info = op.solve_async(f, tol=1e-14, maxiter=2).wait(raise_on_fail=False)
+    assert all(i["converged"] == 0 and i["iters"] <= 2 for i in info)
+
+
+def test_torch_allocator_holds_operator_memory():
+    import paper_2103_03658_amd as fl
+    made, returned = [], []
+
+    def alloc(n):
+        p = torch.cuda.caching_allocator_alloc(n)
+        made.append(p)
+        return p
+
+    def release(p):
+        returned.append(p)
+        torch.cuda.caching_allocator_delete(p)
+
+    f = torch.from_numpy(inputs.uniform_rhs(2, 128, 3, seed=2)).cuda()
+    torch.cuda.synchronize()
+    before = torch.cuda.memory_allocated()
+    fl.set_allocator(alloc, release)
+    try:
+        op = make_op(0.8)
+        u, info = op.solve(f, tol=1e-10)
+        y = op.apply(f)
+        held = torch.cuda.memory_allocated() - before
+    finally:
+        fl.set_allocator(None, None)
+    ref = make_op(0.8)
+    ur, _ = ref.solve(f, tol=1e-10)
+    assert torch.equal(u, ur) and torch.equal(y, ref.apply(f))
+    # the generator and symbols alone are (N+1)^2 + 4 (M/2+1)^2 values
+    assert held >= 129 * 129 * 8 and len(made) > 5
+    assert set(returned) <= set(made)
+    op.close()
+    torch.cuda.synchronize()
+    assert sorted(returned) == sorted(made)
