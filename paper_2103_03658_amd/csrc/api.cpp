@@ -1431,14 +1431,20 @@ extern "C" fl_status fl_solve_async(fl_op A, const double* f, const double* g, d
     }
     fl_request R = new fl_request_s();
     R->info.resize(nrhs);
-    R->worker = std::thread([=]() {
-      R->status = guarded([&]() -> fl_status {
-        return solve_body(A, f, g, tol, maxiter, mixed, u, nrhs, R->info.data(), nullptr, after);
+    try {
+      R->worker = std::thread([=]() {
+        R->status = guarded([&]() -> fl_status {
+          return solve_body(A, f, g, tol, maxiter, mixed, u, nrhs, R->info.data(), nullptr, after);
+        });
+        if (R->status != FL_OK) R->error = fl_last_error();
+        hipEventDestroy(after);
+        R->done.store(1, std::memory_order_release);
       });
-      if (R->status != FL_OK) R->error = fl_last_error();
+    } catch (...) {
+      delete R;
       hipEventDestroy(after);
-      R->done.store(1, std::memory_order_release);
-    });
+      throw;
+    }
     *out = R;
     return FL_OK;
   });
