@@ -796,8 +796,11 @@ fl::CgScalars cg_view(const fl::CgScalars& base, const fl::Geometry& g, const fl
   fl::CgScalars c = base;
   c.nb_a = fl::last_pass_blocks(g, sc);
   c.nb_c = fl::vec_blocks(g.nd, nrhs);
-  // r.z from the preconditioner's last pass (its own schedule)
-  c.nb_b = precond ? fl::last_pass_blocks(g, scp) : c.nb_c;
+  // r.z from the preconditioner (its own schedule): the tau middle pass or
+  // the last pass
+  c.nb_b = precond == 2   ? fl::tau_dot_blocks(g, scp, c.max_blocks)
+           : precond == 1 ? fl::last_pass_blocks(g, scp)
+                          : c.nb_c;
   if (c.nb_a > c.max_blocks || c.nb_b > c.max_blocks || c.nb_c > c.max_blocks)
     throw Error(FL_E_UNSUPPORTED, "too many blocks for the reduction buffers");
   c.maxiter = maxiter;

@@ -157,6 +157,12 @@ size_t apply_workspace_bytes(const Geometry& g, int nrhs, bool fp32);
 
 // Number of blocks per RHS of the last pass (= partials it writes).
 int last_pass_blocks(const Geometry& g, const Schedule& sc);
+// Blocks per RHS of the tau preconditioner's middle pass, and the number of
+// r.z partials its PM_DOT application writes: the middle pass's blocks when
+// they fit max_blocks (the dot is taken there, from the transformed values),
+// else the last pass's.
+long sine_mid_blocks(const Geometry& g, const Schedule& sc);
+int tau_dot_blocks(const Geometry& g, const Schedule& sc, int max_blocks);
 // Blocks per RHS of the vector kernels (update, init, sums).
 int vec_blocks(long nd, int nrhs);
 

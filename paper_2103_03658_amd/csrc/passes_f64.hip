@@ -26,6 +26,18 @@ int last_pass_blocks(const Geometry& g, const Schedule& sc) {
   return (int)pair_tiles(C0, sc.W_first);
 }
 
+long sine_mid_blocks(const Geometry& g, const Schedule& sc) {
+  const long rows = g.nd / g.na[g.d - 1];     // lines of the last axis
+  const long pairs = (rows + 1) / 2;
+  return (pairs + sc.LPB_mid - 1) / sc.LPB_mid;
+}
+
+int tau_dot_blocks(const Geometry& g, const Schedule& sc, int max_blocks) {
+  if (g.d == 1) return 1;
+  const long mb = sine_mid_blocks(g, sc);
+  return mb <= max_blocks ? (int)mb : last_pass_blocks(g, sc);
+}
+
 const void* twiddles(int M, bool fp32, hipStream_t st) {
   static std::mutex mu;
   static std::map<std::tuple<int, int, bool>, void*> cache;

@@ -67,12 +67,18 @@ void apply_passes_t(const Geometry& g, const Schedule& sc, const T* lam, const T
     if (g.d == 3 && go()) launch_sine_cols<T>(M1, sc.E_c2c, a1, (long)nrhs * n0, st);
     const int nl = g.d == 2 ? n1 : n2;            // line length of the last axis
     const int ml = g.d == 2 ? M1 : M2;
+    // PM_DOT: r.z = sum_k m_k sigma(r)_k^2 in the middle pass, from the
+    // transformed values, when its blocks fit the partials; else in the
+    // last pass against u
+    const bool dot = mode == PM_DOT;
+    const bool mid_dot = dot && sine_mid_blocks(g, sc) <= c.max_blocks;
     SineMidArgs<T> m{S1, lam, active, nd / nl, nd, nl, n1, g.Ha[g.d - 1], g.Ha[1], g.d,
-                     sc.LPB_mid, nrhs, g.d == 2 ? tw1 : tw2};
+                     sc.LPB_mid, nrhs, g.d == 2 ? tw1 : tw2, mid_dot ? 1 : 0, part, c.max_blocks};
     if (go()) launch_sine_mid<T>(ml, sc.E_mid, m, st);
     if (g.d == 3 && go()) launch_sine_cols<T>(M1, sc.E_c2c, a1, (long)nrhs * n0, st);
-    SineArgs<T> a2{S1, y, mode == PM_DOT ? u : nullptr, active, part, c.max_blocks, C0, nd, 0,
-                   1, n0, sc.W_first, 0, 0, 0, mode == PM_DOT ? 1 : 0, tw0};
+    const bool last_dot = dot && !mid_dot;
+    SineArgs<T> a2{S1, y, last_dot ? u : nullptr, active, part, c.max_blocks, C0, nd, 0,
+                   1, n0, sc.W_first, 0, 0, 0, last_dot ? 1 : 0, tw0};
     if (go()) launch_sine_cols<T>(M0, sc.E_first, a2, nrhs, st);
     done();
     return;

@@ -724,6 +724,11 @@ struct SineMidArgs {
   int LPB;               // line pairs per block
   int nrhs;
   const cx<T>* tw;
+  // dot != 0: partials of r.z = sum_k m_k sigma(r)_k^2 (z = sigma diag(m)
+  // sigma r, sigma symmetric), one per block, into part[rhs][block]
+  int dot;
+  double* part;
+  int max_blocks;
 };
 
 // Multiplier row of line L of the last axis: the frequencies of the other
@@ -775,12 +780,17 @@ __global__ void __launch_bounds__(512) k_sine_mid(SineMidArgs<T> a) {
   fft_line_1p<T, M, E, -1>(v, l1, t, a.tw);
   const T* ma = a.m + (ha ? sine_mrow(la, a.n1, a.H1, a.Hl, a.d) : 0);
   const T* mb = a.m + (hb ? sine_mrow(la + 1, a.n1, a.H1, a.Hl, a.d) : 0);
+  double acc = 0.0;
 #pragma unroll
   for (int sl = 0; sl < E; ++sl) {
     const int k = t + TPL * P::jslot(sl);
     const int kk = k <= M / 2 ? k : M - k;
     const T sa = ha ? ma[kk] : (T)0;
     const T sb = hb ? mb[kk] : (T)0;
+    // slots 1..n hold the sine coefficients (the others mirror them)
+    if (k >= 1 && k <= n)
+      acc += (double)sa * (double)v[sl].y * (double)v[sl].y +
+             (double)sb * (double)v[sl].x * (double)v[sl].x;
     v[sl] = {sa * v[sl].y, -(sb * v[sl].x)};
   }
   to_natural<T, M, E>(v);
@@ -793,6 +803,10 @@ __global__ void __launch_bounds__(512) k_sine_mid(SineMidArgs<T> a) {
       if (hb) pb[pos - 1] = -v[sl].x;
     }
   }
+  if (!a.dot) return;
+  __shared__ double red[16];
+  const double blk = block_sum(acc, red);
+  if (threadIdx.x == 0) a.part[(long)o * a.max_blocks + rb] = blk;
 }
 
 // ---------------------------------------------------------------------------
