@@ -73,7 +73,7 @@ void dev_free(void* p) {
     }
   }
   if (!registered) {
-    hipFree(p);
+    (void)hipFree(p);
     return;
   }
   // hipFree waits for the device; a caller's allocator may reuse the block at
@@ -177,7 +177,7 @@ struct ChunkGraph {
   hipGraphExec_t exec = nullptr;
   std::vector<double> key;
   void reset() {
-    if (exec) hipGraphExecDestroy(exec);
+    if (exec) (void)hipGraphExecDestroy(exec);
     exec = nullptr;
     key.clear();
   }
@@ -512,10 +512,10 @@ fl_status fl_set_allocator(fl_alloc_fn alloc, fl_release_fn release, void* ctx) 
 
 void fl_destroy(fl_op A) {
   if (!A) return;
-  hipSetDevice(A->device);
+  (void)hipSetDevice(A->device);
   // wait for this handle's own work only (other streams keep running)
-  if (A->solve_stream) hipStreamSynchronize(A->solve_stream);
-  if (A->used && A->done) hipEventSynchronize(A->done);
+  if (A->solve_stream) (void)hipStreamSynchronize(A->solve_stream);
+  if (A->used && A->done) (void)hipEventSynchronize(A->done);
   fl::dev_free(A->G);
   fl::dev_free(A->lam64);
   fl::dev_free(A->lam32);
@@ -526,7 +526,7 @@ void fl_destroy(fl_op A) {
   A->cg.mem.release();
   A->cg_out.mem.release();
   A->outer_flags.release();
-  if (A->done) hipEventDestroy(A->done);
+  if (A->done) (void)hipEventDestroy(A->done);
   A->grel.reset();
   for (auto& gph : A->glen) gph.reset();
   for (auto& gph : A->glen32) gph.reset();
@@ -534,9 +534,9 @@ void fl_destroy(fl_op A) {
   A->ext_khat.release();
   A->ext_work.release();
   A->ext_rhs.release();
-  if (A->poll_host) hipHostFree(A->poll_host);
-  if (A->ev_in) hipEventDestroy(A->ev_in);
-  if (A->solve_stream) hipStreamDestroy(A->solve_stream);
+  if (A->poll_host) (void)hipHostFree(A->poll_host);
+  if (A->ev_in) (void)hipEventDestroy(A->ev_in);
+  if (A->solve_stream) (void)hipStreamDestroy(A->solve_stream);
   delete A;
 }
 
@@ -767,8 +767,8 @@ static fl_status profile_passes(fl_op A, const void* u, void* y, int nrhs, int f
     run(-1);
     FL_HIP(hipStreamSynchronize(st));
     *n_passes = np;
-    hipEventDestroy(ev[0]);
-    hipEventDestroy(ev[1]);
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
     A->end(st);
     return FL_OK;
   });
@@ -1429,7 +1429,7 @@ extern "C" fl_status fl_solve_async(fl_op A, const double* f, const double* g, d
     FL_HIP(hipEventCreateWithFlags(&after, hipEventDisableTiming));
     hipError_t he = hipEventRecord(after, (hipStream_t)stream);
     if (he != hipSuccess) {
-      hipEventDestroy(after);
+      (void)hipEventDestroy(after);
       return fail(FL_E_DEVICE, hipGetErrorString(he));
     }
     fl_request R = new fl_request_s();
@@ -1440,12 +1440,12 @@ extern "C" fl_status fl_solve_async(fl_op A, const double* f, const double* g, d
           return solve_body(A, f, g, tol, maxiter, mixed, u, nrhs, R->info.data(), nullptr, after);
         });
         if (R->status != FL_OK) R->error = fl_last_error();
-        hipEventDestroy(after);
+        (void)hipEventDestroy(after);
         R->done.store(1, std::memory_order_release);
       });
     } catch (...) {
       delete R;
-      hipEventDestroy(after);
+      (void)hipEventDestroy(after);
       throw;
     }
     *out = R;
