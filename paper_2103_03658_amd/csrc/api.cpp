@@ -1227,16 +1227,24 @@ static fl_status solve_body(fl_op A, const double* f, const double* g, double to
     double* q = (double*)(vb + 2 * a8);
     double* x = (double*)(vb + 3 * a8);
     double* z = (double*)(vb + 4 * a8);
-    cg_start<double>(A, A->sc64, pc_symbol<double>(A), A->tw64, f, x, r, p, z, nrhs, cg, nullptr, ws, st);
-    const int chunk = 8;
-    std::vector<double> key = make_key(0, nrhs, chunk, maxiter, tol, pc);
-    for (double v : {pkey(ws), pkey(vb), pkey(A->cg.mem.p), pkey(A->lam64)}) key.push_back(v);
-    for (double v : sched_key(A->sc64)) key.push_back(v);
-    for (double v : sched_key(A->sp64)) key.push_back(v);
-    predictive_loop(A, key, maxiter + 2, cg, nrhs, st, [&]() {
-      cg_iteration<double>(A, A->sc64, A->lam64, pc_symbol<double>(A), A->tw64, x, r, p, q, z, nrhs, cg,
-                           ws, st);
-    });
+    if (A->g.d == 1) {
+      // the line fits a workgroup: the whole solve in one launch (radix 8:
+      // the most threads per line and no register spills)
+      fl::cg1d_solve(A->g, 8, f, x, A->lam64, pc ? pc_symbol<double>(A) : nullptr, pc == 2, cg,
+                     nrhs, maxiter, tol, A->tw64.ax[0], st);
+    } else {
+      cg_start<double>(A, A->sc64, pc_symbol<double>(A), A->tw64, f, x, r, p, z, nrhs, cg,
+                       nullptr, ws, st);
+      const int chunk = 8;
+      std::vector<double> key = make_key(0, nrhs, chunk, maxiter, tol, pc);
+      for (double v : {pkey(ws), pkey(vb), pkey(A->cg.mem.p), pkey(A->lam64)}) key.push_back(v);
+      for (double v : sched_key(A->sc64)) key.push_back(v);
+      for (double v : sched_key(A->sp64)) key.push_back(v);
+      predictive_loop(A, key, maxiter + 2, cg, nrhs, st, [&]() {
+        cg_iteration<double>(A, A->sc64, A->lam64, pc_symbol<double>(A), A->tw64, x, r, p, q, z,
+                             nrhs, cg, ws, st);
+      });
+    }
     FL_HIP(hipMemcpyAsync(u, x, v8, hipMemcpyDeviceToDevice, st));
     // true residual with an FP64 product (into q); the results travel in
     // one pinned record (copies into pageable memory would each wait)

@@ -157,6 +157,13 @@ size_t apply_workspace_bytes(const Geometry& g, int nrhs, bool fp32);
 
 // Number of blocks per RHS of the last pass (= partials it writes).
 int last_pass_blocks(const Geometry& g, const Schedule& sc);
+// d = 1, FP64: the whole PCG solve in one launch, one workgroup per RHS
+// (x, r, p, z in LDS).  pcs: preconditioner multiplier or null (plain CG);
+// pc_odd: the tau preconditioner.  Writes x and cg.iters / status / res2 /
+// active (0) per RHS; stops like the multi-kernel solve.
+void cg1d_solve(const Geometry& g, int E, const double* f, double* x, const double* lam,
+                const double* pcs, bool pc_odd, const CgScalars& cg, int nrhs, int maxiter,
+                double tol, const void* tw, hipStream_t st);
 // Blocks per RHS of the tau preconditioner's middle pass, and the number of
 // r.z partials its PM_DOT application writes: the middle pass's blocks when
 // they fit max_blocks (the dot is taken there, from the transformed values),

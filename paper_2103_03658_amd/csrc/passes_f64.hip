@@ -26,6 +26,15 @@ int last_pass_blocks(const Geometry& g, const Schedule& sc) {
   return (int)pair_tiles(C0, sc.W_first);
 }
 
+void cg1d_solve(const Geometry& g, int E, const double* f, double* x, const double* lam,
+                const double* pcs, bool pc_odd, const CgScalars& cg, int nrhs, int maxiter,
+                double tol, const void* tw, hipStream_t st) {
+  if (g.d != 1) throw Error(2, "one-launch solve: d = 1 only");
+  Cg1Args a{f, x, lam, pcs, pc_odd ? 1 : 0, cg, g.na[0], maxiter, tol * tol,
+            reinterpret_cast<const cx<double>*>(tw)};
+  launch_cg1d(g.Ma[0], E, a, nrhs, st);
+}
+
 long sine_mid_blocks(const Geometry& g, const Schedule& sc) {
   const long rows = g.nd / g.na[g.d - 1];     // lines of the last axis
   const long pairs = (rows + 1) / 2;

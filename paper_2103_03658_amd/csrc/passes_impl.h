@@ -616,6 +616,191 @@ __global__ void __launch_bounds__(512) k_line1d(Line1Args<T> a) {
 }
 
 // ---------------------------------------------------------------------------
+// 1D FP64 PCG in one workgroup per right-hand side: the line fits the block,
+// so the whole solve runs in one launch, with x, r, p, z in LDS.  The
+// iteration and its decisions are those of the multi-kernel solve (cg_begin
+// at every iteration start, breakdown when p.q <= 0, the same update).
+// ---------------------------------------------------------------------------
+struct Cg1Args {
+  const double* f;       // [nrhs][n]
+  double* x;             // [nrhs][n], the final iterate
+  const double* lam;     // folded symbol of A, M/2 + 1 values
+  const double* pcs;     // folded preconditioner multiplier, or null (plain CG)
+  int pc_odd;            // the tau preconditioner (odd extension), else zero padding
+  CgScalars cg;          // iters, status, res2, active per RHS
+  int n;
+  int maxiter;
+  double tol2;
+  const cx<double>* tw;
+};
+
+// Block sum returned to every thread (slot 15 of red carries the broadcast).
+__device__ __forceinline__ double block_sum_all(double v, double* red) {
+  const double s = block_sum(v, red);
+  if (threadIdx.x == 0) red[15] = s;
+  __syncthreads();
+  const double r = red[15];
+  __syncthreads();
+  return r;
+}
+
+// The transform y = F^-1 diag(sym) F of the n values `in` (LDS), zero-padded
+// or odd-extended to M, into the slots of v: y_i sits in slot sl with
+// i = t + TPL jslot(sl) - ODD, jslot(sl) < E/2, 0 <= i < n.
+template <int M, int E, bool ODD>
+__device__ __forceinline__ void line1_apply(const double* in, int n, const double* sym,
+                                            cx<double> (&v)[E], double* lre, double* lim, int t,
+                                            const cx<double>* tw) {
+  using P = Plan<M, E>;
+  constexpr int TPL = P::TPL;
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int i = t + j * TPL;
+    double re = 0.0;
+    if constexpr (ODD) {
+      if (j < E / 2) {
+        if (i >= 1 && i - 1 < n) re = in[i - 1];
+      } else if (i != M / 2 && M - i - 1 < n) {
+        re = -in[M - i - 1];
+      }
+    } else if (j < E / 2 && i < n) {
+      re = in[i];
+    }
+    v[j] = {re, 0.0};
+  }
+  fft_line<double, M, E, -1>(v, lre, lim, t, tw);
+#pragma unroll
+  for (int sl = 0; sl < E; ++sl) {
+    const int k = t + TPL * P::jslot(sl);
+    v[sl] = cscale(v[sl], sym[k <= M / 2 ? k : M - k]);
+  }
+  to_natural<double, M, E>(v);
+  fft_line<double, M, E, +1>(v, lre, lim, t, tw);
+}
+
+// z = P r into Z (LDS); returns r.z (every thread).
+template <int M, int E>
+__device__ __forceinline__ double line1_precond(const Cg1Args& a, const double* R, double* Z,
+                                                cx<double> (&v)[E], double* lre, double* lim,
+                                                int t, double* red) {
+  using P = Plan<M, E>;
+  constexpr int TPL = P::TPL;
+  const int n = a.n;
+  double acc = 0.0;
+  if (!a.pcs) {
+    for (int i = t; i < n; i += TPL) {
+      Z[i] = R[i];
+      acc += R[i] * R[i];
+    }
+    return block_sum_all(acc, red);
+  }
+  if (a.pc_odd) {
+    line1_apply<M, E, true>(R, n, a.pcs, v, lre, lim, t, a.tw);
+  } else {
+    line1_apply<M, E, false>(R, n, a.pcs, v, lre, lim, t, a.tw);
+  }
+  const int sh = a.pc_odd ? 1 : 0;
+#pragma unroll
+  for (int sl = 0; sl < E; ++sl) {
+    const int i = t + TPL * P::jslot(sl) - sh;
+    if (P::jslot(sl) < E / 2 && i >= 0 && i < n) {
+      Z[i] = v[sl].x;
+      acc += R[i] * v[sl].x;
+    }
+  }
+  return block_sum_all(acc, red);
+}
+
+template <int M, int E>
+__global__ void __launch_bounds__(512) k_cg1d(Cg1Args a) {
+  using P = Plan<M, E>;
+  constexpr int TPL = P::TPL;
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ double red[16];
+  double* lre = reinterpret_cast<double*>(smem_raw);
+  double* lim = lre + P::LDSN;
+  double* X = lim + P::LDSN;
+  double* R = X + M / 2;
+  double* Pv = R + M / 2;
+  double* Z = Pv + M / 2;
+  const int t = threadIdx.x, o = blockIdx.x, n = a.n;
+  const double* f = a.f + (long)o * n;
+  cx<double> v[E];
+  double acc = 0.0;
+  for (int i = t; i < n; i += TPL) {
+    const double fi = f[i];
+    R[i] = fi;
+    X[i] = 0.0;
+    Pv[i] = 0.0;
+    acc += fi * fi;
+  }
+  __syncthreads();
+  double rr = block_sum_all(acc, red);
+  double rz = line1_precond<M, E>(a, R, Z, v, lre, lim, t, red);
+  const double thresh2 = a.tol2 * rr;
+  double rz_prev = 0.0;
+  int it = 0, status = 0;
+  for (;;) {
+    // iteration start (the order of cg_begin's tests)
+    if (!isfinite(rr) || !isfinite(rz)) {
+      status = 6;
+      break;
+    }
+    if (it == 0) {
+      if (rr == 0.0) break;
+    } else if (rr <= thresh2) {
+      break;
+    } else if (it >= a.maxiter) {
+      status = 5;
+      break;
+    } else if (!(rz > 0.0)) {
+      status = 6;
+      break;
+    }
+    const double beta = it == 0 ? 0.0 : rz / rz_prev;
+    for (int i = t; i < n; i += TPL) Pv[i] = Z[i] + beta * Pv[i];
+    __syncthreads();
+    // q = A p in the slots; p.q
+    line1_apply<M, E, false>(Pv, n, a.lam, v, lre, lim, t, a.tw);
+    acc = 0.0;
+#pragma unroll
+    for (int sl = 0; sl < E; ++sl) {
+      const int i = t + TPL * P::jslot(sl);
+      if (P::jslot(sl) < E / 2 && i < n) acc += Pv[i] * v[sl].x;
+    }
+    const double pq = block_sum_all(acc, red);
+    const double alpha = rz / pq;
+    if (!(pq > 0.0) || !isfinite(alpha)) {
+      status = 6;
+      break;
+    }
+    acc = 0.0;
+#pragma unroll
+    for (int sl = 0; sl < E; ++sl) {
+      const int i = t + TPL * P::jslot(sl);
+      if (P::jslot(sl) < E / 2 && i < n) {
+        X[i] += alpha * Pv[i];
+        const double ri = R[i] - alpha * v[sl].x;
+        R[i] = ri;
+        acc += ri * ri;
+      }
+    }
+    rr = block_sum_all(acc, red);   // its barriers also publish X and R
+    ++it;
+    rz_prev = rz;
+    rz = line1_precond<M, E>(a, R, Z, v, lre, lim, t, red);
+  }
+  for (int i = t; i < n; i += TPL) a.x[(long)o * n + i] = X[i];
+  if (t == 0) {
+    a.cg.iters[o] = it;
+    a.cg.status[o] = status;
+    a.cg.res2[o] = rr;
+    a.cg.active[o] = 0;
+  }
+}
+
+
+// ---------------------------------------------------------------------------
 // Real sine passes (the tau preconditioner of the CG solves: the natural
 // tau approximation of A is diagonalised by the sine transform of every
 // axis).  For a real line x_1..x_n (n = N - 1, M = 2N)
@@ -1007,6 +1192,20 @@ void launch_line1d(int M, int E, const Line1Args<T>& a, hipStream_t st, bool odd
     FL_DISPATCH(M, E, FL_LAUNCH((k_line1d<T, M, E, false>), grid, dim3(threads), sh, st, a));
   }
   check_launch("1D line");
+}
+
+// LDS of k_cg1d: the two exchange planes and four vectors of M/2 values.
+inline size_t cg1d_lds_bytes(int M, int E) {
+  return line_lds_bytes<double>(M, E) + (size_t)4 * (M / 2) * sizeof(double);
+}
+
+inline void launch_cg1d(int M, int E, const Cg1Args& a, int nrhs, hipStream_t st) {
+  if (a.n > M / 2) throw Error(2, "1D solve: rows beyond M/2");
+  dim3 grid((unsigned)nrhs);
+  const int threads = M / E;
+  const size_t sh = cg1d_lds_bytes(M, E);
+  FL_DISPATCH(M, E, FL_LAUNCH((k_cg1d<M, E>), grid, dim3(threads), sh, st, a));
+  check_launch("1D solve");
 }
 
 }  // namespace fl
