@@ -37,14 +37,14 @@ VALU_PEAK_TFLOPS = 78.6
 # (kernel, precision, nrhs); valid only for the kernel sources they were
 # measured on (SHA-256 prefix of the transform-pass sources).
 TRAFFIC = {
-    ("axis0_fwd_r2c", "f64", 17): 109189261,
-    ("last_axis_fwd_symbol_inv", "f64", 17): 152592820,
-    ("axis0_inv_c2r", "f64", 17): 108993730,
-    ("tau_axis0_sine", "f64", 17): 72748611,
-    ("tau_last_axis_sine_mult_sine", "f64", 17): 73397373,
-    ("tau_axis0_sine_back", "f64", 17): 72748611,
+    ("axis0_fwd_r2c", "f64", 17): 109254053,
+    ("last_axis_fwd_symbol_inv", "f64", 17): 152542891,
+    ("axis0_inv_c2r", "f64", 17): 108950309,
+    ("tau_axis0_sine", "f64", 17): 72747797,
+    ("tau_last_axis_sine_mult_sine", "f64", 17): 73389098,
+    ("tau_axis0_sine_back", "f64", 17): 72747797,
 }
-TRAFFIC_SRC = "efbfd960d75eef98"
+TRAFFIC_SRC = "aea11e843e9e48a8"
 
 
 def pass_sources_hash():
