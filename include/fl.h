@@ -376,10 +376,14 @@ fl_status fl_set_graphs(fl_op A, int enable);
  * fl_set_allocator -- route the library's device allocations through the
  * caller's allocator (a memory pool, a framework's caching allocator), for
  * callers that manage device memory themselves.  Every buffer of an operator
- * (generator, symbols, workspaces, CG state, exterior-data buffers) and every
- * setup temporary allocated after this call comes from alloc(bytes, ctx) on
- * the current device; the library returns it with release(ptr, ctx) once
- * the device has finished with it (fl_destroy, or a workspace that grows).
+ * (generator, symbols, workspaces, CG state, exterior-data buffers) allocated
+ * after this call comes from alloc(bytes, ctx) on the current device; the
+ * library returns it with release(ptr, ctx) once the device has finished
+ * with it (fl_destroy, or a workspace that grows).  Setup temporaries (the
+ * weight integrals, the embedded generator being transformed) use a scratch
+ * area that each device keeps for the life of the process, grown with
+ * hipMalloc to the largest setup so far up to 256 MiB, so that setup frees
+ * nothing; a larger one comes from alloc and goes back through release.
  * Blocks keep the allocator that made them: a later call changes only new
  * allocations.  alloc must return memory aligned to 256 bytes, or NULL
  * (FL_E_NOMEM from the call that needed it).  alloc = release = NULL

@@ -82,6 +82,68 @@ void dev_free(void* p) {
   a.release(p, a.ctx);
 }
 
+struct SetupScratch::Area {
+  std::mutex mu;
+  char* p = nullptr;
+  size_t bytes = 0;
+};
+
+namespace {
+std::mutex g_area_mu;
+std::unordered_map<int, SetupScratch::Area*> g_areas;   // per device, never freed
+}  // namespace
+
+SetupScratch::SetupScratch(size_t bytes, hipStream_t st) : size_(scratch_round(bytes)), st_(st) {
+  if (size_ == 0) size_ = 256;
+  if (size_ > kSetupScratchCap) {
+    base_ = (char*)dev_alloc(size_);
+    return;
+  }
+  int dev = 0;
+  FL_HIP(hipGetDevice(&dev));
+  Area* a = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_area_mu);
+    auto it = g_areas.find(dev);
+    if (it == g_areas.end()) it = g_areas.emplace(dev, new Area).first;
+    a = it->second;
+  }
+  a->mu.lock();
+  if (a->bytes < size_) {
+    size_t grow = size_t(1) << 20;
+    while (grow < size_) grow <<= 1;
+    if (a->p) (void)hipFree(a->p);
+    a->p = nullptr;
+    a->bytes = 0;
+    if (hipMalloc(&a->p, grow) != hipSuccess) {
+      (void)hipGetLastError();
+      a->p = nullptr;
+      a->mu.unlock();
+      throw Error(FL_E_NOMEM, "hipMalloc of " + std::to_string(grow) +
+                                  " bytes of setup scratch failed");
+    }
+    a->bytes = grow;
+  }
+  area_ = a;
+  base_ = a->p;
+}
+
+SetupScratch::~SetupScratch() {
+  (void)hipStreamSynchronize(st_);
+  if (area_)
+    area_->mu.unlock();
+  else
+    dev_free(base_);
+}
+
+void* SetupScratch::take(size_t bytes) {
+  const size_t b = scratch_round(bytes == 0 ? 1 : bytes);
+  if (used_ + b > size_) throw Error(FL_E_DEVICE, "setup scratch lease exceeded");
+  void* p = base_ + used_;
+  used_ += b;
+  return p;
+}
+
 }  // namespace fl
 
 using fl::Error;
@@ -405,10 +467,10 @@ static fl_status create_op(int d, double alpha, int degree, int N, const int* Na
     fl::build_generator(gp, A->G, st);
     fl::build_symbol(A->g, A->G, A->lam64, A->lam32, st);
     {
-      double* scr = (double*)dmalloc(256);
-      fl::build_inverse_symbol(A->g, A->lam64, nh, A->linv64, A->linv32, scr, st);
+      fl::SetupScratch scr(256, st);
+      fl::build_inverse_symbol(A->g, A->lam64, nh, A->linv64, A->linv32,
+                               (double*)scr.take(256), st);
       FL_HIP(hipStreamSynchronize(st));
-      fl::dev_free(scr);
     }
     for (int s = 0; s < 3; ++s) {
       const int M = A->g.Ma[s >= d ? 0 : s];

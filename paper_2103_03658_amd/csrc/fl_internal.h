@@ -197,6 +197,32 @@ inline int apply_npasses(int d) { return d == 1 ? 1 : (d == 2 ? 3 : 5); }
 void* dev_alloc(size_t bytes);
 void dev_free(void* p);
 
+// Scratch memory of operator setup on the current device.  Each device keeps
+// one area (hipMalloc) for the life of the process; it grows to the largest
+// lease up to kSetupScratchCap, so that a setup after the first frees
+// nothing (hipFree waits for the whole device, stalling other streams' work).
+// A larger lease takes a block of its own from dev_alloc.  The lease holds
+// the device's area until it ends and synchronises `st` first, so every use
+// of the memory must be queued on `st`.
+constexpr size_t kSetupScratchCap = size_t(256) << 20;
+class SetupScratch {
+ public:
+  SetupScratch(size_t bytes, hipStream_t st);
+  ~SetupScratch();
+  SetupScratch(const SetupScratch&) = delete;
+  SetupScratch& operator=(const SetupScratch&) = delete;
+  // Next `bytes` of the lease, 256-byte aligned; throws past its size.
+  void* take(size_t bytes);
+  struct Area;
+
+ private:
+  Area* area_ = nullptr;      // the device's area (locked), or null for a block of its own
+  char* base_ = nullptr;
+  size_t size_ = 0, used_ = 0;
+  hipStream_t st_;
+};
+inline size_t scratch_round(size_t b) { return (b + 255) & ~size_t(255); }
+
 // Twiddle table exp(-2 pi i j / M), j < M (cx<T> array), cached per device
 // for the life of the process (hipMalloc, not the registered allocator).
 const void* twiddles(int M, bool fp32, hipStream_t st);

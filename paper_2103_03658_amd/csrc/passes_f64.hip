@@ -223,7 +223,8 @@ void build_symbol(const Geometry& g, const double* G, double* lam64, float* lam3
   const int d = g.d;
   const long total = g.nm();
   const EmbedDims e = embed_dims(g);
-  cx<double>* c = (cx<double>*)dev_alloc((size_t)total * sizeof(cx<double>));
+  SetupScratch scr((size_t)total * sizeof(cx<double>), st);
+  cx<double>* c = (cx<double>*)scr.take((size_t)total * sizeof(cx<double>));
   const int thr = 256;
   hipLaunchKernelGGL(k_embed, dim3((unsigned)((total + thr - 1) / thr)), dim3(thr), 0, st, c, G,
                      e, total);
@@ -234,7 +235,6 @@ void build_symbol(const Geometry& g, const double* G, double* lam64, float* lam3
                      lam32, e, nf, 1.0 / (double)total);
   check_launch("fold");
   FL_HIP(hipStreamSynchronize(st));
-  dev_free(c);
 }
 
 }  // namespace fl

@@ -459,14 +459,18 @@ void build_generator(const GenParams& gp, double* G, hipStream_t st) {
   }
   const int thr = 256;
   const long nblk = (nnode + thr - 1) / thr;
-  GLTables* dtb = nullptr;
-  double *elem = nullptr, *orig = nullptr, *omega = nullptr, *part = nullptr, *T = nullptr;
-  dtb = (GLTables*)dev_alloc(sizeof(GLTables));
-  elem = (double*)dev_alloc((size_t)nelem * nout * sizeof(double));
-  orig = (double*)dev_alloc(32 * sizeof(double));
-  omega = (double*)dev_alloc((size_t)nnode * sizeof(double));
-  part = (double*)dev_alloc((size_t)nblk * sizeof(double));
-  T = (double*)dev_alloc(sizeof(double));
+  const size_t b_elem = (size_t)nelem * nout * sizeof(double);
+  SetupScratch scr(scratch_round(sizeof(GLTables)) + scratch_round(b_elem) +
+                       scratch_round(32 * sizeof(double)) +
+                       scratch_round((size_t)nnode * sizeof(double)) +
+                       scratch_round((size_t)nblk * sizeof(double)) + scratch_round(sizeof(double)),
+                   st);
+  GLTables* dtb = (GLTables*)scr.take(sizeof(GLTables));
+  double* elem = (double*)scr.take(b_elem);
+  double* orig = (double*)scr.take(32 * sizeof(double));
+  double* omega = (double*)scr.take((size_t)nnode * sizeof(double));
+  double* part = (double*)scr.take((size_t)nblk * sizeof(double));
+  double* T = (double*)scr.take(sizeof(double));
   FL_HIP(hipMemcpyAsync(dtb, &tb, sizeof(GLTables), hipMemcpyHostToDevice, st));
   // one pass per kernel term: omega and T accumulate coef * (that term's);
   // the lattice-unit rate is rate * h (K = 1 integrates on the unit lattice)
@@ -485,13 +489,8 @@ void build_generator(const GenParams& gp, double* G, hipStream_t st) {
   hipLaunchKernelGGL(k_diag, dim3(1), dim3(256), 0, st, d, gp.c, (int)nblk, part, T, G);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) throw Error(4, std::string("generator kernels: ") + hipGetErrorString(e));
+  // the host tables are read by the copy above: wait before they go
   FL_HIP(hipStreamSynchronize(st));
-  dev_free(dtb);
-  dev_free(elem);
-  dev_free(orig);
-  dev_free(omega);
-  dev_free(part);
-  dev_free(T);
 }
 
 }  // namespace fl
