@@ -122,12 +122,14 @@ def run_serving(n_requests, workers, tol):
                     torch.from_numpy(inputs.request_rhs(r)).cuda(), t_arrive=r["t_arrive"])
             for r in spec]
     torch.cuda.synchronize()
-    srv = Server(workers=workers, tol=tol, mixed=1)
+    warm = sorted({(2, r["N"], r["degree"]) for r in spec})
+    srv = Server(workers=workers, tol=tol, mixed=1, warm=warm)
     st = srv.run(reqs, realtime=True)
     st["stream"] = (f"{n_requests} requests, Poisson arrivals at 200/s, d=2, "
                     "n in {63,127,255,511} (p=.4/.3/.2/.1), alpha~U(0.2,1.9) rounded to 0.01, "
                     "degree in {0,1,2}, 1-8 U[-1,1] RHS each, FP32 CG + FP64 reliable updates "
-                    f"to {tol:g}, {workers} worker streams")
+                    f"to {tol:g}, {workers} worker streams, each warmed first by one solve per "
+                    "(N, degree) of the stream (warmup_s)")
     return st
 
 

@@ -10,12 +10,18 @@ from several requests overlap on the device).
 
 * Operator cache: operators (weights, generator, symbol and their solver
   buffers) are kept by key (d, N, alpha, degree, kernel) and evicted least
-  recently used when the cache exceeds its byte budget.
+  recently used when the cache exceeds its byte budget (by default the free
+  device memory less the in-flight budget); evicted operators are closed
+  outside the server's lock.
 * Admission by HBM footprint: a request is dispatched only while the
   estimated device bytes of all in-flight batches plus its own fit in
   `hbm_budget`; a request that can never fit is rejected.
 * Per request: latency (arrival to completion), queueing time, batch size,
   iterations and final FP64 relative residual.
+* Warm-up: with `warm` shapes, each worker first solves one right-hand side
+  of each shape on its own stream (first kernel launches, its thread's and
+  stream's first library calls), and the server takes requests only once
+  every worker is done; `warmup_s` reports the time it took.
 
 The solver and every kernel are the library's (fl_solve through the C ABI);
 this module only schedules.  ctypes releases the GIL during library calls,
@@ -30,8 +36,10 @@ import numpy as np
 
 
 def op_bytes(d, N):
-    """Device bytes an operator holds without solver buffers."""
-    return (N + 1) ** d * (8 + 8 + 4)
+    """Device bytes an operator holds without solver buffers: the generator
+    (FP64) and the symbol and its inverse in FP64 and FP32, each (N + 1)^d
+    values on a cube."""
+    return (N + 1) ** d * (8 + 2 * (8 + 4))
 
 
 def batch_bytes(d, N, nrhs):
@@ -70,10 +78,14 @@ class Request:
 
 
 class Server:
-    def __init__(self, workers=4, hbm_budget=64 << 30, cache_bytes=16 << 30, max_batch_rhs=64,
-                 tol=1e-10, mixed=1, maxiter=20000, keep_solutions=False, device=0):
+    def __init__(self, workers=4, hbm_budget=64 << 30, cache_bytes=None, max_batch_rhs=64,
+                 tol=1e-10, mixed=1, maxiter=20000, keep_solutions=False, device=0, warm=()):
         self.workers = workers
+        self.warm = list(warm)                     # (d, N, degree) solved once per worker
+        self._warmed = threading.Barrier(workers + 1)
         self.hbm_budget = hbm_budget
+        if cache_bytes is None:
+            cache_bytes = self.default_cache_bytes(device, hbm_budget)
         self.cache_bytes = cache_bytes
         self.max_batch_rhs = max_batch_rhs
         self.tol, self.mixed, self.maxiter = tol, mixed, maxiter
@@ -93,6 +105,17 @@ class Server:
         self.errors = []
 
     # -- operator cache -------------------------------------------------------
+    @staticmethod
+    def default_cache_bytes(device, hbm_budget):
+        """Operator cache budget: three quarters of the device memory free at
+        start-up less the in-flight budget (about 150 GB on a 288 GB device),
+        at least 4 GiB.  Evicting an operator frees device memory, which waits
+        for every stream of the device, so a cache that holds the working set
+        keeps those waits out of the serving loop."""
+        import torch
+        free, _ = torch.cuda.mem_get_info(device)
+        return max(4 << 30, int(0.75 * free) - hbm_budget)
+
     def _get_op(self, req, nrhs):
         import paper_2103_03658_amd as fl
         k = req.key
@@ -110,10 +133,16 @@ class Server:
         with self._cv:
             self._ops[k] = (op, b)
             self._cached += b
-            self._evict_locked()
+            gone = self._evict_locked()
+        self._close(gone)
         return op, False
 
     def _evict_locked(self):
+        """Drop least recently used idle operators until the cache fits its
+        budget; returns them for _close, which runs outside the lock (freeing
+        device memory waits for the whole device, and other workers must not
+        wait for the lock meanwhile)."""
+        gone = []
         for k in list(self._ops):
             if self._cached <= self.cache_bytes:
                 break
@@ -121,6 +150,12 @@ class Server:
                 continue
             op, b = self._ops.pop(k)
             self._cached -= b
+            gone.append(op)
+        return gone
+
+    @staticmethod
+    def _close(ops):
+        for op in ops:
             op.close()
 
     # -- scheduling -----------------------------------------------------------
@@ -163,6 +198,12 @@ class Server:
         import torch
         torch.cuda.set_device(self.device)
         stream = torch.cuda.Stream()
+        try:
+            self._warm_up(stream)
+        except Exception as exc:
+            self.errors.append(f"warm-up: {exc!r}")
+        finally:
+            self._warmed.wait()
         while True:
             with self._cv:
                 item = None
@@ -184,8 +225,20 @@ class Server:
                     self._busy.discard(group[0].key)
                     self._inflight -= need
                     self.done.extend(group)
-                    self._evict_locked()
+                    gone = self._evict_locked()
                     self._cv.notify_all()
+                self._close(gone)
+
+    def _warm_up(self, stream):
+        import torch
+        import paper_2103_03658_amd as fl
+        for d, N, degree in self.warm:
+            op = fl.Operator(d, 1.0, degree, N=N)
+            f = torch.ones((1,) + (N - 1,) * d, dtype=torch.float64, device="cuda")
+            with torch.cuda.stream(stream):
+                op.solve(f, tol=self.tol, mixed=self.mixed, maxiter=self.maxiter,
+                         stream=stream, raise_on_fail=False)
+            op.close()
 
     def _run_batch(self, group, stream):
         import torch
@@ -217,9 +270,12 @@ class Server:
         arrive at once.  Returns a statistics dict."""
         threads = [threading.Thread(target=self._worker, daemon=True)
                    for _ in range(self.workers)]
+        t_warm = time.perf_counter()
         for t in threads:
             t.start()
+        self._warmed.wait()
         start = time.perf_counter()
+        self.warmup_s = start - t_warm
         for req in requests:
             if realtime:
                 delay = start + req.t_arrive - time.perf_counter()
@@ -247,6 +303,7 @@ class Server:
             "requests": len(self.done) + len(self.rejected),
             "served": len(self.done), "ok": len(ok), "rejected": len(self.rejected),
             "wall_s": end - start,
+            "warmup_s": getattr(self, "warmup_s", None),
             "rhs_solves_per_s": rhs / (end - start),
             "requests_per_s": len(self.done) / (end - start),
             "p50_ms": float(np.percentile(lat, 50)) if len(lat) else None,

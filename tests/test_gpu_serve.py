@@ -50,3 +50,24 @@ def test_hbm_budget_admission():
     tiny = Server(workers=2, hbm_budget=1024)
     st2 = tiny.run(_requests(SPECS[:3], seed=2), realtime=False)
     assert st2["rejected"] == 3 and st2["served"] == 0
+
+
+def test_cache_eviction_keeps_results_and_budget():
+    """A cache budget of about one operator: idle operators are closed as new
+    ones arrive (outside the server's lock), and every result is still the
+    one of a fresh operator.  The workers warm up first without errors."""
+    import paper_2103_03658_amd as fl
+    from paper_2103_03658_amd.serve import Server, batch_bytes, op_bytes
+    reqs = _requests(SPECS, seed=3)
+    budget = op_bytes(2, 64) + batch_bytes(2, 64, 4)
+    srv = Server(workers=3, cache_bytes=budget, keep_solutions=True, warm=[(2, 16, 0), (2, 32, 1)])
+    st = srv.run(reqs, realtime=False)
+    assert st["served"] == len(SPECS) and st["ok"] == len(SPECS), st
+    assert st["warmup_s"] > 0 and not st["errors"], st
+    assert srv._cached <= budget or len(srv._ops) == 1
+    assert len(srv._ops) < len({r.key for r in reqs})
+    for r in reqs:
+        op = fl.Operator(2, r.alpha, r.degree, N=r.N)
+        u, info = op.solve(r.f, tol=1e-10, mixed=1)
+        assert torch.equal(u, r.u), r.id
+        op.close()
