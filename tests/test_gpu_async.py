@@ -6,6 +6,8 @@ same input, same graphs), while several run at once on different operators
 and queue on one; its failures come back through fl_wait.  With torch's
 caching allocator registered, the operator's memory comes from torch and
 goes back to it, and the results are the bits of a default operator.
+Operators created concurrently from several threads (one shared setup
+scratch area per device) equal those created one at a time.
 """
 
 import time
@@ -112,3 +114,37 @@ def test_torch_allocator_holds_operator_memory():
     op.close()
     torch.cuda.synchronize()
     assert sorted(returned) == sorted(made)
+
+
+def test_concurrent_setup_matches_sequential():
+    """Operators created at once from several threads (sharing the device's
+    setup scratch area, which grows on the way: N = 32 ... 512, p = 0 ... 2)
+    hold the generator and symbol of operators created one at a time."""
+    import threading
+    import paper_2103_03658_amd as fl
+    shapes = [(2, 0.3 + 0.1 * i, i % 3, (32, 64, 128, 256, 512)[i % 5]) for i in range(12)]
+    shapes.append((3, 0.9, 1, 32))
+    ref = []
+    for d, a, p, N in shapes:
+        op = fl.Operator(d, a, p, N=N)
+        ref.append((op.generator(), op.symbol()))
+        op.close()
+    got = [None] * len(shapes)
+    errs = []
+
+    def make(i):
+        try:
+            d, a, p, N = shapes[i]
+            got[i] = fl.Operator(d, a, p, N=N)
+        except Exception as exc:   # surfaced by the assertion below
+            errs.append(repr(exc))
+
+    threads = [threading.Thread(target=make, args=(i,)) for i in range(len(shapes))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(120)
+    assert not errs and all(g is not None for g in got), errs
+    for (G, lam), op in zip(ref, got):
+        assert np.array_equal(op.generator(), G) and np.array_equal(op.symbol(), lam)
+        op.close()
