@@ -18,6 +18,10 @@ from several requests overlap on the device).
   `hbm_budget`; a request that can never fit is rejected.
 * Per request: latency (arrival to completion), queueing time, batch size,
   iterations and final FP64 relative residual.
+* Precision: FP64 PCG by default (`mixed=1` selects FP32 CG with FP64
+  reliable updates); on the serving stream (N = 64 ... 512) FP64 has the
+  lower latency, since the mixed path's extra iterations and reliable steps
+  outweigh its cheaper passes at these sizes.
 * Warm-up: with `warm` shapes, each worker first solves one right-hand side
   of each shape on its own stream (first kernel launches, its thread's and
   stream's first library calls), and the server takes requests only once
@@ -43,7 +47,7 @@ def op_bytes(d, N):
 
 
 def batch_bytes(d, N, nrhs):
-    """Device bytes of the solver buffers of a mixed-precision solve of nrhs
+    """Device bytes of the solver buffers of a solve (FP64 or mixed) of nrhs
     right-hand sides (transform workspace, vectors, reduction partials)."""
     n, M = N - 1, 2 * N
     nd = n ** d
@@ -79,7 +83,7 @@ class Request:
 
 class Server:
     def __init__(self, workers=4, hbm_budget=64 << 30, cache_bytes=None, max_batch_rhs=64,
-                 tol=1e-10, mixed=1, maxiter=20000, keep_solutions=False, device=0, warm=()):
+                 tol=1e-10, mixed=0, maxiter=20000, keep_solutions=False, device=0, warm=()):
         self.workers = workers
         self.warm = list(warm)                     # (d, N, degree) solved once per worker
         self._warmed = threading.Barrier(workers + 1)

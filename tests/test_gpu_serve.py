@@ -35,7 +35,7 @@ def test_results_same_alone_and_in_mix():
     assert st["mean_requests_per_batch"] > 1.0          # shared operators were merged
     for r in reqs:
         op = fl.Operator(2, r.alpha, r.degree, N=r.N)
-        u, info = op.solve(r.f, tol=1e-10, mixed=1)
+        u, info = op.solve(r.f, tol=1e-10, mixed=srv.mixed)
         assert torch.equal(u, r.u), r.id
         op.close()
 
@@ -68,6 +68,6 @@ def test_cache_eviction_keeps_results_and_budget():
     assert len(srv._ops) < len({r.key for r in reqs})
     for r in reqs:
         op = fl.Operator(2, r.alpha, r.degree, N=r.N)
-        u, info = op.solve(r.f, tol=1e-10, mixed=1)
+        u, info = op.solve(r.f, tol=1e-10, mixed=srv.mixed)
         assert torch.equal(u, r.u), r.id
         op.close()
