@@ -22,9 +22,14 @@ def make_op(alpha, p, N):
 @pytest.mark.parametrize("kind", [0, 1, 2])
 @pytest.mark.parametrize("alpha,p,N", [(1.5, 1, 1024), (0.6, 2, 64), (1.1, 0, 100), (1.9, 1, 8)])
 def test_one_launch_solve_matches_cholesky(alpha, p, N, kind):
+    import paper_2103_03658_amd as fl
     op = make_op(alpha, p, N)
     if kind == 2 and op.precond_kind != 2:
-        pytest.skip("the tau preconditioner needs 2N a power of two")
+        # the tau preconditioner's sine transforms need 2N a power of two
+        with pytest.raises(fl.FlError) as exc:
+            op.set_preconditioner(kind)
+        assert exc.value.status == 2              # FL_E_UNSUPPORTED
+        return
     op.set_preconditioner(kind)
     f = inputs.uniform_rhs(1, N, 3, seed=12)
     u, info = op.solve(torch.from_numpy(f).cuda(), tol=1e-12)
