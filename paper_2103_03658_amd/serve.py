@@ -198,10 +198,17 @@ class Server:
             self.admission_waits += 1
         return None
 
-    def _worker(self):
+    def _tensor_device(self):
+        return f"cuda:{self.device}"
+
+    def _open_stream(self):
+        """The worker's own stream on the server's device."""
         import torch
         torch.cuda.set_device(self.device)
-        stream = torch.cuda.Stream()
+        return torch.cuda.Stream()
+
+    def _worker(self):
+        stream = self._open_stream()
         try:
             self._warm_up(stream)
         except Exception as exc:
@@ -238,7 +245,8 @@ class Server:
         import paper_2103_03658_amd as fl
         for d, N, degree in self.warm:
             op = fl.Operator(d, 1.0, degree, N=N)
-            f = torch.ones((1,) + (N - 1,) * d, dtype=torch.float64, device="cuda")
+            f = torch.ones((1,) + (N - 1,) * d, dtype=torch.float64,
+                           device=self._tensor_device())
             with torch.cuda.stream(stream):
                 op.solve(f, tol=self.tol, mixed=self.mixed, maxiter=self.maxiter,
                          stream=stream, raise_on_fail=False)
