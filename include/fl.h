@@ -371,7 +371,6 @@ fl_status fl_apply_precond(fl_op A, const void *u, void *y, int nrhs, int fp32, 
  * on `stream` by events. */
 fl_status fl_set_graphs(fl_op A, int enable);
 
-/* Release the handle and its device memory.  NULL is accepted. */
 /*
  * fl_set_allocator -- route the library's device allocations through the
  * caller's allocator (a memory pool, a framework's caching allocator), for
@@ -394,6 +393,10 @@ fl_status fl_set_graphs(fl_op A, int enable);
  */
 fl_status fl_set_allocator(fl_alloc_fn alloc, fl_release_fn release, void *ctx);
 
+/* Release the handle and its device memory.  NULL is accepted.  Freeing
+ * device memory waits for all work on the device (hipFree, or an explicit
+ * device synchronisation before a registered allocator's release), so a
+ * server should destroy handles outside its latency-critical locks. */
 void fl_destroy(fl_op A);
 
 /* Message for the last non-OK status returned on this thread ("" if none). */
