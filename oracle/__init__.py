@@ -32,7 +32,12 @@ listed in each function's docstring (and collected in the design notes):
   R3  2D origin value: Phi(x,0) ~ (Phi(xi_10) + Phi(xi_01))/2, i.e. the
       average over axes (so a_11 carries no omega_00 term).
   R4  3D and 2D p=2: the same axis-average rule, with the p=2 Richardson
-      step of R2 on each axis.  Parity unpinned (no printed numbers).
+      step of R2 on each axis.  No printed numbers: pinned by the measured
+      convergence rate to the closed-form image of (1-|x|^2)_+^{4+alpha/2}
+      (4 - alpha for the 2D quadratic basis, 2 for the 3D linear basis;
+      dropped, one-sided or literally printed origin rules give 2 - alpha).
+      Which consistent rule (with or without the Richardson step in 2D and
+      3D) is meant stays a reading: both give the same rate.
   R5  gamma = 2 throughout (the paper's recommended and tabulated choice).
   R6  Kernel K(r) of Remark 2.2 (tempered exp(-lambda r), sums of
       exponentials): normalisation c-bar = c_{d,alpha}; K enters the weight

@@ -12,6 +12,7 @@ K(r) = exp(-lambda r) for the tempered operator (Remark 2.2).  It multiplies
 a_00).  In 1D with K = 1 it is the paper's 1/(alpha L^alpha).
 """
 
+import functools
 import math
 
 import mpmath
@@ -42,6 +43,7 @@ def _radial_tail(R, alpha, lam):
     return lam ** alpha * mpmath.gammainc(-alpha, lam * R)
 
 
+@functools.lru_cache(maxsize=None)   # pure function of its arguments; slow in 3D
 def far_field_T(d, alpha, L=2.0, lam=0.0, dps=30):
     """T_d = int over R^d_+ \\ [0,L]^d of K(|xi|) |xi|^{-d-alpha} d xi.
 

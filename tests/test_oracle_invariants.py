@@ -13,7 +13,7 @@ import math
 
 import numpy as np
 import pytest
-from scipy import integrate
+from scipy import integrate, special
 
 import oracle
 from oracle.constants import c_dalpha, far_field_T
@@ -78,8 +78,8 @@ def _moment_reference(d, alpha, js, L, lam):
             R = L * rho
             q = J + 2.0 - alpha            # r^{J} r^{2-d-alpha} r^{d-1}
             if lam:
-                rad = integrate.quad(lambda r: r ** (q - 1) * math.exp(-lam * r), 0, R,
-                                     epsabs=0, epsrel=1e-13)[0]
+                # int_0^R r^{q-1} e^{-lam r} dr = Gamma(q) P(q, lam R) / lam^q
+                rad = special.gamma(q) * special.gammainc(q, lam * R) / lam ** q
             else:
                 rad = R ** q / q
             return P * rad * rho ** (-d)       # dOmega = dw / rho^d
@@ -99,8 +99,6 @@ def test_weight_moments(d, N, p, alpha, lam):
     """sum_k omega_k prod_s xi_{k_s}^{j_s} equals the moment of the weight
     function for every j_s <= p (the basis reproduces such polynomials):
     partition of unity for all p, plus linear / quadratic reproduction."""
-    if d == 3 and lam:
-        pytest.skip("3D tempered moments: reference too slow; covered in 2D")
     L, h = 2.0, 2.0 / N
     om = weights(d, alpha, p, N, h=h, lam=lam)
     xi = h * np.arange(N + 1)
@@ -190,8 +188,6 @@ def test_2d_case_list():
 @pytest.mark.parametrize("p", [0, 1, 2])
 @pytest.mark.parametrize("alpha,lam", [(0.3, 0.0), (1.0, 0.0), (1.9, 0.0), (1.2, 3.0)])
 def test_symmetric_positive_definite(d, N, p, alpha, lam):
-    if d == 3 and lam and p != 1:
-        pytest.skip("3D tempered: one basis suffices (far-field constant is slow)")
     G = oracle.generator(d, alpha, p, N, lam=lam)
     A = oracle.dense_matrix(G)
     assert np.array_equal(A, A.T)
