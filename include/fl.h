@@ -26,8 +26,14 @@
  *    thread-local message readable with fl_last_error().  Argument checks
  *    happen before any device work.
  *  - An operator handle is immutable after creation apart from its
- *    schedule and solver settings; it owns its device buffers.  One handle
- *    must not be used by two host threads at once.
+ *    schedule and solver settings; it owns its device buffers (transform
+ *    workspaces, CG state) and reuses them across calls.  Calls on one
+ *    handle are serialised by a lock of the handle: a call that needs its
+ *    buffers or settings (fl_apply, fl_apply_precond, fl_exterior,
+ *    fl_profile_*, fl_set_*, fl_solve) waits while another call of the same
+ *    handle, including the solve of an fl_solve_async request, is inside
+ *    the library.  Handles do not share buffers; calls on different handles
+ *    run concurrently.
  */
 #ifndef FL_H
 #define FL_H
@@ -66,8 +72,9 @@ typedef struct {
                          (mixed = 2); 0 for mixed = 0 */
   int converged;      /* 1 if the stopping rule was met */
   int status;         /* fl_status of this right-hand side */
-  double relres_rec;  /* recursive ||r||_2 / ||f||_2 at exit (mixed: the FP64 residual) */
-  double relres_true; /* ||f - A u||_2 / ||f||_2 recomputed with an FP64 product at exit */
+  double relres_rec;  /* recursive ||r||_2 / ||f - b||_2 at exit (mixed: the FP64 residual) */
+  double relres_true; /* ||f - b - A u||_2 / ||f - b||_2 recomputed with an FP64 product at
+                         exit (b = 0 without exterior data) */
 } fl_info;
 
 /*
@@ -151,19 +158,28 @@ fl_status fl_weights_expsum(int d, double alpha, int degree, const int *interval
                             const double *coef, const double *rate, double gamma, void *stream,
                             fl_op *out);
 
-/* Copy the FP64 generator G_k, k in {0..N}^d (row-major, (N+1)^d values),
- * to host memory.  count must be >= (N+1)^d.  Test hook. */
+/* Copy the FP64 generator G_k = -c_{d,alpha} a_k, k in {0..N}^d (row-major,
+ * (N+1)^d values), to host memory: the entries of the symmetric (multilevel)
+ * Toeplitz matrix, A_{ij} = G_{|i-j|} (Sec. 2.1, the matrix A^(1) after
+ * eq. (1D-scheme); Sec. 2.2, the block matrix A^(2) after eq. (2D-scheme)).
+ * count must be >= (N+1)^d.  Synchronises the device.  Test hook. */
 fl_status fl_generator(fl_op A, double *host_out, size_t count);
 
 /* Copy the folded FP64 symbol lambda-hat_k, k_s in {0..M_s/2} (prod_s
- * (M_s/2 + 1) values; N + 1 per axis when M = 2N).  The full symbol on
- * prod {0..M_s-1} is even: lambda-hat_j = lambda-hat_{min(j_s, M_s-j_s)}. */
+ * (M_s/2 + 1) values; N + 1 per axis when M = 2N): the eigenvalues of the
+ * circulant that embeds A^(1) / A^(2) (Sec. 2.1 and 2.2: the Toeplitz
+ * structure admits products by FFT), lambda-hat = DFT(c) / prod M_s.  The
+ * full symbol on prod {0..M_s-1} is even: lambda-hat_j =
+ * lambda-hat_{min(j_s, M_s-j_s)}.  count >= prod (M_s/2 + 1).  Synchronises
+ * the device.  Test hook. */
 fl_status fl_symbol(fl_op A, double *host_out, size_t count);
 
-/* Copy the circulant embedding c_j, j_s in {0..M_s-1}, of the generator as
- * laid out on the device: c_j = G_{m(j)}, m(j_s) = min(j_s, M_s - j_s),
- * zero where some m(j_s) > N_s - 2.  count >= prod M_s.  Test hook for the
- * index maps. */
+/* Copy the circulant embedding c_j, j_s in {0..M_s-1}, of the generator
+ * (the first column of a circulant whose leading block is A^(1) / A^(2),
+ * Sec. 2.1 and 2.2) as laid out on the device: c_j = G_{m(j)},
+ * m(j_s) = min(j_s, M_s - j_s), zero where some m(j_s) > N_s - 2.
+ * count >= prod M_s.  Allocates a temporary of prod M_s doubles.  Test hook
+ * for the index maps. */
 fl_status fl_embedding(fl_op A, double *host_out, size_t count);
 
 /* Geometry of A: dimension, intervals N, interior points per axis n = N-1,
@@ -177,8 +193,11 @@ fl_status fl_query(fl_op A, int *d, int *N, int *n, int *M);
 fl_status fl_query_axes(fl_op A, int *intervals, int *n, int *M);
 
 /*
- * fl_apply -- y = A u for nrhs right-hand sides (the g = 0 operator; the
- * exterior-data term b is not added).
+ * fl_apply -- y = A u for nrhs right-hand sides: the differentiation matrix
+ * of the scheme, A^(1) of Sec. 2.1 (after eq. (1D-scheme)) and A^(2) of
+ * Sec. 2.2 (after eq. (2D-scheme)) and its 3-level analogue, applied by
+ * circulant embedding and FFT (the g = 0 operator; the exterior-data term b
+ * is not added).
  *   u, y    device arrays of nrhs * n^d doubles (fp32 = 0) or floats
  *           (fp32 = 1), distinct, caller-owned
  *   nrhs    >= 1
@@ -188,14 +207,18 @@ fl_status fl_query_axes(fl_op A, int *intervals, int *n, int *M);
 fl_status fl_apply(fl_op A, const void *u, void *y, int nrhs, int fp32, void *stream);
 
 /*
- * fl_solve -- solve A u = f for nrhs right-hand sides by conjugate gradients
- * (A is symmetric positive definite, Sec. 2.2), circulant-preconditioned by
- * default (fl_set_preconditioner).
+ * fl_solve -- solve A u = f - b for nrhs right-hand sides by conjugate
+ * gradients (the discrete equation A u + b = f of Sec. 2.1 eq. (1D-scheme)
+ * and Sec. 2.2 eq. (2D-scheme); A is symmetric positive definite, Sec. 2.2),
+ * preconditioned by default (fl_set_preconditioner).
  *   f       device, nrhs * n^d doubles
- *   g       device, nrhs * n^d doubles: the exterior-data term b of the scheme
- *           (fl_exterior); the solve is then A u = f - b.  NULL: g = 0
- *           outside Omega (b = 0).  Must not alias u.
- *   tol     stop when ||r||_2 <= tol ||f||_2 (per right-hand side), tol > 0
+ *   b       device, nrhs * n^d doubles: the exterior-data term of the scheme
+ *           (from fl_exterior, for data u = g outside Omega), or NULL for
+ *           g = 0 (b = 0).  Must not alias u.  With b given, the right-hand
+ *           side of the system is f - b, and the tolerance and the relres_*
+ *           results of fl_info are relative to ||f - b||_2.
+ *   tol     stop when ||r||_2 <= tol ||f - b||_2 (per right-hand side),
+ *           tol > 0
  *   maxiter CG iteration cap (mixed = 0, 1) / inner iteration cap per
  *           refinement step (mixed = 2), >= 1
  *   mixed   0: FP64 CG; stops on the recursive residual.
@@ -218,7 +241,7 @@ fl_status fl_apply(fl_op A, const void *u, void *y, int nrhs, int fp32, void *st
  * otherwise the first failing status (FL_E_NOCONV, FL_E_BREAKDOWN); u then
  * holds the last iterate.  A right-hand side f = 0 gives u = 0.
  */
-fl_status fl_solve(fl_op A, const double *f, const double *g, double tol, int maxiter, int mixed,
+fl_status fl_solve(fl_op A, const double *f, const double *b, double tol, int maxiter, int mixed,
                    double *u, int nrhs, fl_info *info, void *stream);
 
 /*
@@ -227,15 +250,17 @@ fl_status fl_solve(fl_op A, const double *f, const double *g, double tol, int ma
  * host thread of its own with the same arguments, semantics and results as
  * fl_solve, after the work queued on `stream` so far; solves of one operator
  * run one at a time (not necessarily in submission order), solves of
- * different operators concurrently on their own streams.  f, g and u belong
- * to the caller and must stay valid, f and g unchanged, until the request
+ * different operators concurrently on their own streams.  f, b and u belong
+ * to the caller and must stay valid, f and b unchanged, until the request
  * is finished, and the operator must not be destroyed before; `stream` does
- * not wait for the result.
+ * not wait for the result.  The solve holds the operator's lock while it
+ * runs: other calls on the same operator (fl_apply, fl_exterior, fl_set_*,
+ * ...) wait until it has finished, so they never share its workspaces.
  *   out  receives the request; every request must be finished with fl_wait
  * Errors: argument errors as fl_solve, returned here (no request is made).
  */
 typedef struct fl_request_s *fl_request;
-fl_status fl_solve_async(fl_op A, const double *f, const double *g, double tol, int maxiter,
+fl_status fl_solve_async(fl_op A, const double *f, const double *b, double tol, int maxiter,
                          int mixed, double *u, int nrhs, void *stream, fl_request *out);
 
 /* fl_poll -- *done = 1 once the request's solve has finished (u and the

@@ -280,7 +280,11 @@ struct fl_op_s {
   DBuf ext_work;          // exterior-term transform workspace
   bool ext_ready = false;
   DBuf ext_rhs;           // f - b for solves with exterior data
-  std::mutex solve_mu;    // one solve at a time (fl_solve, fl_solve_async)
+  // held by every call that uses the workspaces, CG state or settings
+  // (fl_apply, fl_apply_precond, fl_exterior, fl_profile_*, fl_set_*,
+  // fl_get_*schedule, fl_solve and the solves of fl_solve_async): one such
+  // call at a time per handle
+  std::mutex mu;
   DBuf poll_dev;          // packed CG state for the host (device side)
   double* poll_host = nullptr;   // pinned copy
   size_t poll_cap = 0;
@@ -667,6 +671,7 @@ static fl_status set_sched(fl_op A, bool pc, int fp32, int e_first, int e_mid, i
                            int w_first, int w_c2c, int lpb_mid) {
   return guarded([&]() -> fl_status {
     if (!A) return fail(FL_E_INVAL, "null handle");
+    std::lock_guard<std::mutex> lock(A->mu);
     fl::Schedule& dst = pc ? (fp32 ? A->sp32 : A->sp64) : (fp32 ? A->sc32 : A->sc64);
     fl::Schedule s = dst;
     if (e_first > 0) s.E_first = e_first;
@@ -697,6 +702,7 @@ fl_status fl_set_preconditioner(fl_op A, int kind) {
   if (kind == 2 && !A->g.sine_ok())
     return fail(FL_E_UNSUPPORTED,
                 "the tau preconditioner needs 2 N_s to be a power of two on every axis");
+  std::lock_guard<std::mutex> lock(A->mu);
   A->precond = kind;
   return FL_OK;
 }
@@ -707,6 +713,7 @@ fl_status fl_apply_precond(fl_op A, const void* u, void* y, int nrhs, int fp32, 
     if (!u || !y) return fail(FL_E_INVAL, "null vector");
     if (u == y) return fail(FL_E_INVAL, "u and y must be distinct");
     if (nrhs < 1) return fail(FL_E_INVAL, "nrhs must be >= 1");
+    std::lock_guard<std::mutex> lock(A->mu);
     if (A->precond == 0) return fail(FL_E_INVAL, "no preconditioner selected");
     set_device(A);
     hipStream_t st = (hipStream_t)stream;
@@ -728,12 +735,14 @@ fl_status fl_apply_precond(fl_op A, const void* u, void* y, int nrhs, int fp32, 
 
 fl_status fl_set_graphs(fl_op A, int enable) {
   if (!A) return fail(FL_E_INVAL, "null handle");
+  std::lock_guard<std::mutex> lock(A->mu);
   A->use_graphs = enable != 0;
   return FL_OK;
 }
 
 static fl_status get_sched(fl_op A, bool pc, int fp32, int* s6) {
   if (!A || !s6) return fail(FL_E_INVAL, "null argument");
+  std::lock_guard<std::mutex> lock(A->mu);
   const fl::Schedule& s = pc ? (fp32 ? A->sp32 : A->sp64) : (fp32 ? A->sc32 : A->sc64);
   s6[0] = s.E_first;
   s6[1] = s.E_mid;
@@ -754,6 +763,7 @@ fl_status fl_set_refinement(fl_op A, double delta, double inner_tol, int max_out
   if (!A) return fail(FL_E_INVAL, "null handle");
   if (!(delta > 0.0 && delta < 1.0) || !(inner_tol > 0.0 && inner_tol < 1.0) || max_outer < 1)
     return fail(FL_E_INVAL, "delta and inner_tol in (0,1) and max_outer >= 1 required");
+  std::lock_guard<std::mutex> lock(A->mu);
   A->delta = delta;
   A->inner_tol = inner_tol;
   A->max_outer = max_outer;
@@ -766,6 +776,7 @@ fl_status fl_apply(fl_op A, const void* u, void* y, int nrhs, int fp32, void* st
     if (!u || !y) return fail(FL_E_INVAL, "null vector");
     if (u == y) return fail(FL_E_INVAL, "u and y must be distinct");
     if (nrhs < 1) return fail(FL_E_INVAL, "nrhs must be >= 1");
+    std::lock_guard<std::mutex> lock(A->mu);
     set_device(A);
     hipStream_t st = (hipStream_t)stream;
     A->begin(st);
@@ -792,6 +803,7 @@ static fl_status profile_passes(fl_op A, const void* u, void* y, int nrhs, int f
     if (!u || !y || !ms_per_pass || !n_passes) return fail(FL_E_INVAL, "null argument");
     if (u == y) return fail(FL_E_INVAL, "u and y must be distinct");
     if (nrhs < 1 || reps < 1) return fail(FL_E_INVAL, "nrhs and reps must be >= 1");
+    std::lock_guard<std::mutex> lock(A->mu);
     if (pc && A->precond == 0) return fail(FL_E_INVAL, "no preconditioner selected");
     const int np = fl::apply_npasses(A->g.d);
     if (max_passes < np) return fail(FL_E_INVAL, "max_passes too small");
@@ -1207,6 +1219,7 @@ extern "C" fl_status fl_exterior(fl_op A, const double* g_lat, const double* tai
     if (!fl::exterior_supported(A->g))
       return fail(FL_E_UNSUPPORTED,
                   "exterior data: d = 3 needs at most 1024^3 transform points (N <= 256)");
+    std::lock_guard<std::mutex> lock(A->mu);
     set_device(A);
     hipStream_t st = (hipStream_t)stream;
     A->begin(st);
@@ -1222,7 +1235,7 @@ extern "C" fl_status fl_exterior(fl_op A, const double* g_lat, const double* tai
 }
 
 // Argument checks of fl_solve and fl_solve_async (no device work).
-static fl_status check_solve(fl_op A, const double* f, const double* g, double tol, int maxiter,
+static fl_status check_solve(fl_op A, const double* f, const double* b, double tol, int maxiter,
                              int mixed, const double* u, int nrhs) {
   if (!A) return fail(FL_E_INVAL, "null handle");
   if (!f || !u) return fail(FL_E_INVAL, "null vector");
@@ -1231,17 +1244,17 @@ static fl_status check_solve(fl_op A, const double* f, const double* g, double t
   if (nrhs < 1) return fail(FL_E_INVAL, "nrhs must be >= 1");
   if (mixed < 0 || mixed > 2) return fail(FL_E_INVAL, "mixed must be 0, 1 or 2");
   if ((const void*)f == (const void*)u) return fail(FL_E_INVAL, "f and u must be distinct");
-  if (g && (const void*)g == (const void*)u) return fail(FL_E_INVAL, "g and u must be distinct");
+  if (b && (const void*)b == (const void*)u) return fail(FL_E_INVAL, "b and u must be distinct");
   return FL_OK;
 }
 
 // The solve, on the operator's own stream, one at a time per operator.  It
 // starts after `user`'s work so far, or, given `after`, after that event
 // (the asynchronous form, which also leaves `user` free of the result).
-static fl_status solve_body(fl_op A, const double* f, const double* g, double tol, int maxiter,
+static fl_status solve_body(fl_op A, const double* f, const double* b, double tol, int maxiter,
                             int mixed, double* u, int nrhs, fl_info* info, hipStream_t user,
                             hipEvent_t after) {
-  std::lock_guard<std::mutex> lock(A->solve_mu);
+  std::lock_guard<std::mutex> lock(A->mu);
   set_device(A);
   ensure_solver_stream(A);
   hipStream_t st = A->solve_stream;
@@ -1254,10 +1267,10 @@ static fl_status solve_body(fl_op A, const double* f, const double* g, double to
   A->begin(st);
   const long nd = A->g.nd;
   const size_t v8 = (size_t)nrhs * nd * sizeof(double);
-  if (g) {
-    // exterior term b: solve A u = f - b
+  if (b) {
+    // exterior-data term b: solve A u = f - b (norms relative to ||f - b||)
     double* fb = (double*)A->ext_rhs.get(v8);
-    fl::difference(f, g, fb, (long)nrhs * nd, st);
+    fl::difference(f, b, fb, (long)nrhs * nd, st);
     f = fb;
   }
   const size_t v4 = (size_t)nrhs * nd * sizeof(float);
@@ -1468,12 +1481,12 @@ static fl_status solve_body(fl_op A, const double* f, const double* g, double to
   return worst;
 }
 
-extern "C" fl_status fl_solve(fl_op A, const double* f, const double* g, double tol, int maxiter,
+extern "C" fl_status fl_solve(fl_op A, const double* f, const double* b, double tol, int maxiter,
                               int mixed, double* u, int nrhs, fl_info* info, void* stream) {
   return guarded([&]() -> fl_status {
-    const fl_status e = check_solve(A, f, g, tol, maxiter, mixed, u, nrhs);
+    const fl_status e = check_solve(A, f, b, tol, maxiter, mixed, u, nrhs);
     if (e != FL_OK) return e;
-    return solve_body(A, f, g, tol, maxiter, mixed, u, nrhs, info, (hipStream_t)stream, nullptr);
+    return solve_body(A, f, b, tol, maxiter, mixed, u, nrhs, info, (hipStream_t)stream, nullptr);
   });
 }
 
@@ -1486,12 +1499,12 @@ struct fl_request_s {
   std::vector<fl_info> info;
 };
 
-extern "C" fl_status fl_solve_async(fl_op A, const double* f, const double* g, double tol,
+extern "C" fl_status fl_solve_async(fl_op A, const double* f, const double* b, double tol,
                                     int maxiter, int mixed, double* u, int nrhs, void* stream,
                                     fl_request* out) {
   return guarded([&]() -> fl_status {
     if (!out) return fail(FL_E_INVAL, "out is NULL");
-    const fl_status e = check_solve(A, f, g, tol, maxiter, mixed, u, nrhs);
+    const fl_status e = check_solve(A, f, b, tol, maxiter, mixed, u, nrhs);
     if (e != FL_OK) return e;
     // order the solve after the caller's work on `stream` submitted so far
     set_device(A);
@@ -1507,7 +1520,7 @@ extern "C" fl_status fl_solve_async(fl_op A, const double* f, const double* g, d
     try {
       R->worker = std::thread([=]() {
         R->status = guarded([&]() -> fl_status {
-          return solve_body(A, f, g, tol, maxiter, mixed, u, nrhs, R->info.data(), nullptr, after);
+          return solve_body(A, f, b, tol, maxiter, mixed, u, nrhs, R->info.data(), nullptr, after);
         });
         if (R->status != FL_OK) R->error = fl_last_error();
         (void)hipEventDestroy(after);

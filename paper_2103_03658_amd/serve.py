@@ -261,17 +261,26 @@ class Server:
             f = torch.cat([r.f for r in group]).contiguous() if len(group) > 1 else group[0].f
             u, info = op.solve(f, tol=self.tol, mixed=self.mixed, maxiter=self.maxiter,
                                stream=stream, raise_on_fail=False)
+            # copies on the worker stream, where u was allocated and written:
+            # the allocator may hand u's block to the next batch on this
+            # stream as soon as u is dropped
+            kept = []
+            if self.keep:
+                off = 0
+                for r in group:
+                    kept.append(u[off:off + r.nrhs].clone())
+                    off += r.nrhs
         t1 = time.perf_counter()
         self.batches.append((len(group), rhs, t1 - t0, group[0].N))
         off = 0
-        for r in group:
+        for k, r in enumerate(group):
             r.t_dispatch = t0
             r.t_done = t1
             r.cache_hit = hit
             r.batch_rhs = rhs
             r.info = info[off:off + r.nrhs]
             if self.keep:
-                r.u = u[off:off + r.nrhs].clone()
+                r.u = kept[k]
             r.status = "ok" if all(i["converged"] for i in r.info) else "noconv"
             off += r.nrhs
 

@@ -148,3 +148,30 @@ def test_concurrent_setup_matches_sequential():
     for (G, lam), op in zip(ref, got):
         assert np.array_equal(op.generator(), G) and np.array_equal(op.symbol(), lam)
         op.close()
+
+
+@pytest.mark.parametrize("mixed", [0, 1])
+def test_calls_during_async_solve_wait_for_it(mixed):
+    """Calls on a handle whose asynchronous solve is running wait for it (the
+    handle's lock): an apply with more right-hand sides than the solve (its
+    transform workspace must grow, which would free the solve's) and a
+    schedule change, issued right after the submission, leave the solve's
+    bits those of the blocking solve, and the apply's those of an apply on a
+    fresh operator."""
+    print(f"[async lock] mixed={mixed}", flush=True)
+    op = make_op(1.1)
+    ref_op = make_op(1.1)
+    f = torch.from_numpy(inputs.uniform_rhs(2, 128, 2, seed=31)).cuda()
+    big = torch.from_numpy(inputs.uniform_rhs(2, 128, 12, seed=32)).cuda()
+    ur, infor = ref_op.solve(f, tol=1e-10, mixed=mixed)
+    yr = ref_op.apply(big)
+    torch.cuda.synchronize()
+    req = op.solve_async(f, tol=1e-10, mixed=mixed)
+    y = op.apply(big)
+    sched = op.get_schedule(False)
+    op.set_schedule(False, **sched)          # same values: results unchanged
+    u, info = req.wait()
+    torch.cuda.synchronize()
+    assert torch.equal(u, ur)
+    assert [i["iters"] for i in info] == [i["iters"] for i in infor]
+    assert torch.equal(y, yr)
