@@ -206,6 +206,31 @@ fl_status fl_query_axes(fl_op A, int *intervals, int *n, int *M);
  */
 fl_status fl_apply(fl_op A, const void *u, void *y, int nrhs, int fp32, void *stream);
 
+/* Size of the fixed scratch area of fl_apply_noalloc, in MiB. */
+#define FL_NOALLOC_SCRATCH_MIB 128
+
+/*
+ * fl_apply_noalloc -- fl_apply for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the same product, kernels and launch schedule, so the
+ * same bits as fl_apply, with the transform intermediates in a fixed area of
+ * the library (FL_NOALLOC_SCRATCH_MIB, one copy per device, held from the
+ * library's first use on that device until the process ends) instead of the
+ * handle's workspace.  No call of it allocates device memory or calls
+ * hipMalloc / hipFree.
+ *   Intermediates needed, s = 8 (FP64) or 4 (FP32) bytes, h0 = M_0/2 + 1:
+ *     d = 1: none;  d = 2: nrhs * h0 * n_1 * 2s;
+ *     d = 3: nrhs * (h0 * n_1 * n_2 + h0 * M_1 * n_2) * 2s
+ *   (e.g. 2D N = 512 FP64: 4.19 MB per right-hand side, 32 fit).
+ * Every call on a device uses that device's one area: calls that overlap on
+ * one device (on different streams, from different threads or handles)
+ * race and give wrong results; the caller orders them.  The area keeps the
+ * last call's contents.  Arguments, layout and stream rules as fl_apply.
+ * Errors as fl_apply; FL_E_UNSUPPORTED (nothing launched) when the
+ * intermediates exceed the area.
+ */
+fl_status fl_apply_noalloc(fl_op A, const void *u, void *y, int nrhs, int fp32, void *stream);
+
 /*
  * fl_solve -- solve A u = f - b for nrhs right-hand sides by conjugate
  * gradients (the discrete equation A u + b = f of Sec. 2.1 eq. (1D-scheme)

@@ -191,6 +191,22 @@ class Operator:
                                  1 if u.dtype == torch.float32 else 0, _stream_ptr(stream)))
         return out
 
+    def apply_noalloc(self, u, out, stream=None):
+        """y = A u through fl_apply_noalloc: the product of apply() with the
+        transform intermediates in the library's fixed scratch area (no
+        device allocation; out must be given)."""
+        import torch
+        if u.dtype not in (torch.float32, torch.float64):
+            raise TypeError("u must be float32 or float64")
+        nrhs = self._nrhs(u)
+        if out.dtype != u.dtype or out.numel() != u.numel() or not out.is_contiguous():
+            raise ValueError("out must match u")
+        check(self._lib.fl_apply_noalloc(self._h, ctypes.c_void_p(u.data_ptr()),
+                                         ctypes.c_void_p(out.data_ptr()), nrhs,
+                                         1 if u.dtype == torch.float32 else 0,
+                                         _stream_ptr(stream)))
+        return out
+
     def exterior(self, g_lat, tail=None, out=None, stream=None):
         """Exterior-data term b (fl_exterior): g_lat holds g on the node
         lattice, [-N, N_s + N] along axis s (N_s = N on the cube), shape

@@ -24,6 +24,7 @@ STATUS_NAMES = {0: "FL_OK", 1: "FL_E_INVAL", 2: "FL_E_UNSUPPORTED", 3: "FL_E_NOM
 FL_KERNEL_FRACTIONAL = 0
 FL_KERNEL_TEMPERED = 1
 FL_MAX_KERNEL_TERMS = 16
+FL_NOALLOC_SCRATCH_MIB = 128
 
 
 class FlInfo(ctypes.Structure):
@@ -73,6 +74,7 @@ _SIGS = {
     "fl_poll": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int)]),
     "fl_wait": (ctypes.c_int, [_P, ctypes.POINTER(FlInfo)]),
     "fl_apply": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, _P]),
+    "fl_apply_noalloc": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, _P]),
     "fl_solve": (ctypes.c_int, [_P, _P, _P, ctypes.c_double, ctypes.c_int, ctypes.c_int, _P,
                                 ctypes.c_int, ctypes.POINTER(FlInfo), _P]),
     "fl_set_refinement": (ctypes.c_int, [_P, ctypes.c_double, ctypes.c_double, ctypes.c_int]),

@@ -19,7 +19,7 @@ OUT = os.path.join(HERE, "libfl.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["api.cpp", "weights.hip", "passes_f64.hip", "passes_f32.hip", "cg.hip",
-           "exterior.hip"]
+           "exterior.hip", "noalloc.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

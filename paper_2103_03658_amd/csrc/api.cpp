@@ -793,6 +793,41 @@ fl_status fl_apply(fl_op A, const void* u, void* y, int nrhs, int fp32, void* st
   });
 }
 
+}  // extern "C"
+
+int fl::apply_in_area(fl_op A, const void* u, void* y, int nrhs, int fp32, void* stream,
+                      void* (*area_of_device)(int dev), size_t area_bytes) {
+  return guarded([&]() -> fl_status {
+    if (!A) return fail(FL_E_INVAL, "null handle");
+    if (!u || !y) return fail(FL_E_INVAL, "null vector");
+    if (u == y) return fail(FL_E_INVAL, "u and y must be distinct");
+    if (nrhs < 1) return fail(FL_E_INVAL, "nrhs must be >= 1");
+    // the same checks, schedule and passes as fl_apply; the handle's
+    // buffers are not touched (only its generator-derived data is read), so
+    // no ordering against the handle's earlier calls is needed
+    std::lock_guard<std::mutex> lock(A->mu);
+    const size_t need = fl::apply_workspace_bytes(A->g, nrhs, fp32 != 0);
+    if (need > area_bytes)
+      return fail(FL_E_UNSUPPORTED,
+                  "fl_apply_noalloc: the product needs " + std::to_string(need) +
+                      " bytes of intermediates, the fixed scratch area holds " +
+                      std::to_string(area_bytes) + "; use fl_apply or fewer right-hand sides");
+    set_device(A);
+    void* ws = need ? area_of_device(A->device) : nullptr;
+    hipStream_t st = (hipStream_t)stream;
+    if (fp32)
+      fl::apply_passes<float>(A->g, A->sc32, A->lam32, A->tw32, (const float*)u, (float*)y, nrhs,
+                              ws, st, fl::PM_PLAIN, nullptr, nullptr, nullptr, nullptr, nullptr);
+    else
+      fl::apply_passes<double>(A->g, A->sc64, A->lam64, A->tw64, (const double*)u, (double*)y,
+                               nrhs, ws, st, fl::PM_PLAIN, nullptr, nullptr, nullptr, nullptr,
+                               nullptr);
+    return FL_OK;
+  });
+}
+
+extern "C" {
+
 // Shared body of fl_profile_apply (pc false: y = A u) and fl_profile_precond
 // (pc true: y = P u).
 static fl_status profile_passes(fl_op A, const void* u, void* y, int nrhs, int fp32, int reps,

@@ -8,6 +8,8 @@
 #include <stdexcept>
 #include <string>
 
+struct fl_op_s;   // the operator handle (include/fl.h)
+
 namespace fl {
 
 struct Error : std::runtime_error {
@@ -309,5 +311,15 @@ void reliable_replace(const Geometry& g, const double* r64, float* r32, int nrhs
 // partials of sum v^2 per RHS into part (vec_blocks per RHS)
 void sum_squares_parts(const double* v, long nd, int nrhs, double* part, int max_blocks,
                        hipStream_t st);
+
+// The body of fl_apply_noalloc: fl_apply's checks and passes, with the
+// transform intermediates in a fixed area of area_bytes instead of the
+// handle's workspace.  area_of_device(dev) returns the area's address on
+// device dev and is called with that device current (only when the product
+// needs intermediates, d >= 2).  Allocates nothing; FL_E_UNSUPPORTED when
+// the product needs more than area_bytes.  Returns an fl_status and sets the
+// thread's error text like every entry point.
+int apply_in_area(::fl_op_s* A, const void* u, void* y, int nrhs, int fp32, void* stream,
+                  void* (*area_of_device)(int dev), size_t area_bytes);
 
 }  // namespace fl
