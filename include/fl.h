@@ -368,7 +368,11 @@ fl_status fl_get_precond_schedule(fl_op A, int fp32, int *sched6);
  * on `stream` (so every kernel's input is in place), then each kernel alone
  * `reps` times back to back between two HIP events, and return the mean
  * duration per launch of each kernel in milliseconds; a last whole sequence
- * leaves y = A u.
+ * leaves y = A u.  If max_passes >= 2 * n_passes, each kernel is then also
+ * launched `reps` times with an event pair around every launch, and the mean
+ * of those single-dispatch durations (what a kernel trace reports per
+ * dispatch; it includes each dispatch's start-up and completion, which
+ * back-to-back launches overlap) goes to ms_per_pass[n_passes + k].
  * The kernels are the transform passes in launch order: 1 for d = 1 (the
  * whole product), 3 for d = 2 (axis 0 forward, last axis forward * symbol *
  * inverse, axis 0 inverse), 5 for d = 3 (axis 0, axis 1, last axis, axis 1

@@ -289,17 +289,30 @@ class Operator:
         """Mean milliseconds per kernel of the preconditioner y = P u."""
         return self._profile(self._lib.fl_profile_precond, u, out, reps, stream)
 
-    def _profile(self, fn, u, out, reps, stream):
+    def profile_apply_each(self, u, out=None, reps=20, stream=None):
+        """(back-to-back means, single-dispatch means) in milliseconds per
+        kernel of y = A u: every launch also timed between its own events."""
+        return self._profile(self._lib.fl_profile_apply, u, out, reps, stream, each=True)
+
+    def profile_precond_each(self, u, out=None, reps=20, stream=None):
+        return self._profile(self._lib.fl_profile_precond, u, out, reps, stream, each=True)
+
+    def _profile(self, fn, u, out, reps, stream, each=False):
         import torch
         nrhs = self._nrhs(u)
         if out is None:
             out = torch.empty_like(u)
-        ms = (ctypes.c_double * 8)()
+        npass_d = 1 if self.d == 1 else (3 if self.d == 2 else 5)   # kernels per product
+        cap = 2 * npass_d if each else npass_d
+        ms = (ctypes.c_double * cap)()
         npass = ctypes.c_int()
         check(fn(self._h, ctypes.c_void_p(u.data_ptr()), ctypes.c_void_p(out.data_ptr()), nrhs,
-                 1 if u.dtype == torch.float32 else 0, int(reps), _stream_ptr(stream), ms, 8,
+                 1 if u.dtype == torch.float32 else 0, int(reps), _stream_ptr(stream), ms, cap,
                  ctypes.byref(npass)))
-        return [ms[i] for i in range(npass.value)]
+        k = npass.value
+        if each:
+            return [ms[i] for i in range(k)], [ms[k + i] for i in range(k)]
+        return [ms[i] for i in range(k)]
 
     def set_refinement(self, delta=1e-5, inner_tol=1e-4, max_outer=40):
         check(self._lib.fl_set_refinement(self._h, float(delta), float(inner_tol),

@@ -264,6 +264,7 @@ struct fl_op_s {
   double inner_tol = 1e-4;  // inner solve tolerance (mixed = 2)
   int max_outer = 40;
   DBuf ws;                // FFT intermediates
+  DBuf tau_ws;            // the tau preconditioner's intermediate between its split halves
   DBuf vecs;              // solver vectors
   CgState cg, cg_out;     // CG state; partial sums of residual norms
   DBuf outer_flags;       // per-RHS flags and norms of the refinement loop
@@ -588,6 +589,7 @@ void fl_destroy(fl_op A) {
   fl::dev_free(A->linv64);
   fl::dev_free(A->linv32);
   A->ws.release();
+  A->tau_ws.release();
   A->vecs.release();
   A->cg.mem.release();
   A->cg_out.mem.release();
@@ -873,11 +875,39 @@ static fl_status profile_passes(fl_op A, const void* u, void* y, int nrhs, int f
       FL_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
       ms_per_pass[k] = (double)ms / reps;
     }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    if (max_passes >= 2 * np) {
+      // each launch between an event pair of its own (the duration of one
+      // dispatch, as a kernel trace reports it), averaged over reps
+      std::vector<hipEvent_t> evs(2 * (size_t)reps, nullptr);
+      try {
+        for (auto& e : evs) FL_HIP(hipEventCreate(&e));
+        for (int k = 0; k < np; ++k) {
+          for (int r = 0; r < reps; ++r) {
+            FL_HIP(hipEventRecord(evs[2 * r], st));
+            run(k);
+            FL_HIP(hipEventRecord(evs[2 * r + 1], st));
+          }
+          FL_HIP(hipEventSynchronize(evs[2 * reps - 1]));
+          double tot = 0.0;
+          for (int r = 0; r < reps; ++r) {
+            float ms = 0.f;
+            FL_HIP(hipEventElapsedTime(&ms, evs[2 * r], evs[2 * r + 1]));
+            tot += ms;
+          }
+          ms_per_pass[np + k] = tot / reps;
+        }
+      } catch (...) {
+        for (auto& e : evs)
+          if (e) (void)hipEventDestroy(e);
+        throw;
+      }
+      for (auto& e : evs) (void)hipEventDestroy(e);
+    }
     run(-1);
     FL_HIP(hipStreamSynchronize(st));
     *n_passes = np;
-    (void)hipEventDestroy(ev[0]);
-    (void)hipEventDestroy(ev[1]);
     A->end(st);
     return FL_OK;
   });
@@ -1147,21 +1177,44 @@ void precond_apply(fl_op A, const T* linv, const fl::Twiddles& tw, const T* r, T
                       nullptr, nullptr, &cg, active, nullptr, -1, A->precond == 2);
 }
 
-// CG start: x = 0, r = rhs, p = 0; preconditioned: z = P r.
+// Whether preconditioned CG runs the tau preconditioner split around the
+// iteration start (fl::tau_front / fl::tau_back_direction: z = P r is never
+// stored and the direction kernel is not launched): the tau preconditioner
+// with d >= 2 and the middle pass's r.z partials within the buffers.
+bool tau_split(fl_op A, const fl::Schedule& scp) {
+  return A->precond == 2 && A->g.d >= 2 && fl::sine_mid_blocks(A->g, scp) <= kMaxBlocks;
+}
+
+// CG start: x = 0, r = rhs, p = 0; preconditioned: z = P r (with the split
+// tau preconditioner, S1 != null: its first half, into S1).
 template <typename T>
 void cg_start(fl_op A, const fl::Schedule& sc, const T* linv, const fl::Twiddles& tw, const T* rhs,
               T* x, T* r, T* p, T* z, int nrhs, const fl::CgScalars& cg,
-              const int* outer_active, void* ws, hipStream_t st) {
+              const int* outer_active, void* ws, hipStream_t st, T* S1) {
   fl::fill_int(cg.n_active, 0, 1, st);
   fl::cg_init<T>(A->g, rhs, x, r, p, nrhs, cg, outer_active, st);
-  if (cg.precond) precond_apply<T>(A, linv, tw, r, z, nrhs, ws, cg, cg.active, st);
+  if (S1)
+    fl::tau_front<T>(A->g, pc_sched<T>(A), linv, tw, r, S1, nrhs, st, cg, cg.active);
+  else if (cg.precond)
+    precond_apply<T>(A, linv, tw, r, z, nrhs, ws, cg, cg.active, st);
 }
 
 // One CG (or preconditioned CG) iteration for all active right-hand sides.
+// With the split tau preconditioner (S1 != null) the iteration is: second
+// half of z = P r fused with the iteration start (p = z + beta p), the
+// product's passes, the update, first half of the next z = P r.
 template <typename T>
 void cg_iteration(fl_op A, const fl::Schedule& sc, const T* lam, const T* linv, const fl::Twiddles& tw,
                   T* x, T* r, T* p, T* q, T* z, int nrhs, const fl::CgScalars& cg, void* ws,
-                  hipStream_t st) {
+                  hipStream_t st, T* S1) {
+  if (S1) {
+    fl::tau_back_direction<T>(A->g, pc_sched<T>(A), tw, S1, p, nrhs, st, cg);
+    fl::apply_passes<T>(A->g, sc, lam, tw, p, q, nrhs, ws, st, fl::PM_PQ, nullptr, nullptr,
+                        nullptr, &cg, cg.active);
+    fl::cg_update<T>(A->g, x, r, p, q, nrhs, cg, st);
+    fl::tau_front<T>(A->g, pc_sched<T>(A), linv, tw, r, S1, nrhs, st, cg, cg.active);
+    return;
+  }
   if (A->g.d >= 2) {
     // iteration start and p = z + beta p streamed; the strided first pass
     // then reads p alone
@@ -1182,15 +1235,15 @@ void cg_iteration(fl_op A, const fl::Schedule& sc, const T* lam, const T* linv, 
 template <typename T>
 void cg_run(fl_op A, const fl::Schedule& sc, const T* lam, const T* linv, const fl::Twiddles& tw,
             const T* rhs, T* x, T* r, T* p, T* q, T* z, int nrhs, const fl::CgScalars& cg,
-            const int* outer_active, void* ws, hipStream_t st) {
-  cg_start<T>(A, sc, linv, tw, rhs, x, r, p, z, nrhs, cg, outer_active, ws, st);
+            const int* outer_active, void* ws, hipStream_t st, T* S1) {
+  cg_start<T>(A, sc, linv, tw, rhs, x, r, p, z, nrhs, cg, outer_active, ws, st, S1);
   int done = 0;
   int chunk = 8;
   const int cap = cg.maxiter + 2;
   while (done < cap) {
     const int k = std::min(chunk, cap - done);
     for (int i = 0; i < k; ++i)
-      cg_iteration<T>(A, sc, lam, linv, tw, x, r, p, q, z, nrhs, cg, ws, st);
+      cg_iteration<T>(A, sc, lam, linv, tw, x, r, p, q, z, nrhs, cg, ws, st, S1);
     done += k;
     int nact = 0;
     FL_HIP(hipMemcpyAsync(&nact, cg.n_active, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1343,16 +1396,20 @@ static fl_status solve_body(fl_op A, const double* f, const double* b, double to
       fl::cg1d_solve(A->g, 8, f, x, A->lam64, pc ? pc_symbol<double>(A) : nullptr, pc == 2, cg,
                      nrhs, maxiter, tol, A->tw64.ax[0], st);
     } else {
+      double* S1 = tau_split(A, A->sp64)
+                       ? (double*)A->tau_ws.get((size_t)nrhs * nd * sizeof(double))
+                       : nullptr;
       cg_start<double>(A, A->sc64, pc_symbol<double>(A), A->tw64, f, x, r, p, z, nrhs, cg,
-                       nullptr, ws, st);
+                       nullptr, ws, st, S1);
       const int chunk = 8;
       std::vector<double> key = make_key(0, nrhs, chunk, maxiter, tol, pc);
-      for (double v : {pkey(ws), pkey(vb), pkey(A->cg.mem.p), pkey(A->lam64)}) key.push_back(v);
+      for (double v : {pkey(ws), pkey(vb), pkey(A->cg.mem.p), pkey(A->lam64), pkey(S1)})
+        key.push_back(v);
       for (double v : sched_key(A->sc64)) key.push_back(v);
       for (double v : sched_key(A->sp64)) key.push_back(v);
       predictive_loop(A, key, maxiter + 2, cg, nrhs, st, [&]() {
         cg_iteration<double>(A, A->sc64, A->lam64, pc_symbol<double>(A), A->tw64, x, r, p, q, z,
-                             nrhs, cg, ws, st);
+                             nrhs, cg, ws, st, S1);
       });
     }
     FL_HIP(hipMemcpyAsync(u, x, v8, hipMemcpyDeviceToDevice, st));
@@ -1403,12 +1460,15 @@ static fl_status solve_body(fl_op A, const double* f, const double* b, double to
     FL_HIP(hipMemcpyAsync(rr_last, f2, nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
     fl::fill_int(nupd, 0, nrhs, st);
     fl::fill_int(trig, 0, nrhs, st);
+    float* S1 = tau_split(A, A->sp32)
+                    ? (float*)A->tau_ws.get((size_t)nrhs * nd * sizeof(float))
+                    : nullptr;
     cg_start<float>(A, A->sc32, pc_symbol<float>(A), A->tw32, rhs32, xlo, r32, p32, z32, nrhs, cg,
-                    nullptr, ws, st);
+                    nullptr, ws, st, S1);
     const int chunk = 8;
     std::vector<double> key = make_key(1, nrhs, chunk, maxiter, tol, A->delta, pc);
     for (double v : {pkey(ws), pkey(vb), pkey(A->cg.mem.p), pkey(A->cg_out.mem.p),
-                     pkey(A->outer_flags.p), pkey(A->lam32)})
+                     pkey(A->outer_flags.p), pkey(A->lam32), pkey(S1)})
       key.push_back(v);
     for (double v : sched_key(A->sc32)) key.push_back(v);
     for (double v : sched_key(A->sp32)) key.push_back(v);
@@ -1417,7 +1477,7 @@ static fl_status solve_body(fl_op A, const double* f, const double* b, double to
         A, key, maxiter, cg, nrhs, rr_last, f2, nupd, delta2, tol * tol, st,
         [&]() {
           cg_iteration<float>(A, A->sc32, A->lam32, pc_symbol<float>(A), A->tw32, xlo, r32, p32,
-                              q32, z32, nrhs, cg, ws, st);
+                              q32, z32, nrhs, cg, ws, st, S1);
         },
         [&]() {
           fl::reliable_accum(A->g, xhi, xlo, nrhs, cg, trig, false, st);
@@ -1425,7 +1485,12 @@ static fl_status solve_body(fl_op A, const double* f, const double* b, double to
                                    fl::PM_RESID, nullptr, nullptr, fc, &co, trig);
           fl::reliable_replace(A->g, r64, r32, nrhs, cg, co.part_a, nb64, co.max_blocks,
                                rr_last, f2, tol * tol, trig, nupd, st);
-          if (pc)
+          // the restarted right-hand sides' z = P r (or its first half,
+          // into S1, which the FP64 residual's passes above do not touch)
+          if (S1)
+            fl::tau_front<float>(A->g, A->sp32, pc_symbol<float>(A), A->tw32, r32, S1, nrhs, st,
+                                 cg, trig);
+          else if (pc)
             precond_apply<float>(A, pc_symbol<float>(A), A->tw32, r32, z32, nrhs, ws, cg, trig,
                                  st);
         });
@@ -1453,6 +1518,9 @@ static fl_status solve_body(fl_op A, const double* f, const double* b, double to
     float* p32 = (float*)(vb + a8 + 3 * a4);
     float* q32 = (float*)(vb + a8 + 4 * a4);
     float* z32 = (float*)(vb + a8 + 5 * a4);
+    float* S1 = tau_split(A, A->sp32)
+                    ? (float*)A->tau_ws.get((size_t)nrhs * nd * sizeof(float))
+                    : nullptr;
     fl::fill_zero_bytes(u, v8, st);
     FL_HIP(hipMemcpyAsync(r64, f, v8, hipMemcpyDeviceToDevice, st));
     FL_HIP(hipMemcpyAsync(rro, f2, nrhs * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -1478,7 +1546,7 @@ static fl_status solve_body(fl_op A, const double* f, const double* b, double to
       FL_HIP(hipMemcpyAsync(oact, hact.data(), nrhs * sizeof(int), hipMemcpyHostToDevice, st));
       fl::refine_scale(r64, rhs32, rro, scale, nd, nrhs, oact, st);
       cg_run<float>(A, A->sc32, A->lam32, pc_symbol<float>(A), A->tw32, rhs32, d32, r32, p32, q32, z32,
-                    nrhs, cg, oact, ws, st);
+                    nrhs, cg, oact, ws, st, S1);
       fl::refine_axpy(u, d32, scale, nd, nrhs, oact, st);
       fp64_residual(A, f, u, r64, nrhs, co, oact, rro, ws, st);
       FL_HIP(hipMemcpyAsync(hit.data(), cg.iters, nrhs * sizeof(int), hipMemcpyDeviceToHost, st));

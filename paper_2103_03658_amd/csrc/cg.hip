@@ -58,7 +58,7 @@ __global__ void __launch_bounds__(VT) k_cg_init(const T* rhs, T* x, T* r, T* p, 
 template <typename T>
 __global__ void __launch_bounds__(VT) k_cg_update(T* x, T* r, const T* p, const T* q, long nd,
                                                   CgScalars cg) {
-  __shared__ double red[16];
+  __shared__ double red[64];
   const int o = blockIdx.y;
   if (!cg.active[o]) return;
   const double pq = sum_partials(cg.part_a + (long)o * cg.max_blocks, cg.nb_a, red);
@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(VT) k_cg_update(T* x, T* r, const T* p, const 
 // deactivation can only turn later blocks of it away, which is what they do.
 template <typename T>
 __global__ void __launch_bounds__(VT) k_cg_direction(T* p, const T* zr, long nd, CgScalars cg) {
-  __shared__ double red[16];
+  __shared__ double red[64];
   const int o = blockIdx.y;
   if (!cg.active[o]) return;
   double beta;
@@ -165,7 +165,7 @@ __global__ void k_fill_zero(unsigned* p, size_t nwords) {
 
 __global__ void k_reduce_parts(const double* part, int nb, int max_blocks, double* out,
                                const int* active) {
-  __shared__ double red[16];
+  __shared__ double red[64];
   const int o = blockIdx.x;
   if (active && !active[o]) return;
   const double t = sum_partials(part + (long)o * max_blocks, nb, red);
@@ -239,7 +239,7 @@ __global__ void __launch_bounds__(VT) k_reliable_replace(const double* r64, floa
                                                          int nb64, int mb64, double* rr_last,
                                                          const double* f2, double tol2,
                                                          int* trig, int* nupd) {
-  __shared__ double red[16];
+  __shared__ double red[64];
   const int o = blockIdx.y;
   if (!trig[o]) return;
   const double rr64 = sum_partials(part64 + (long)o * mb64, nb64, red);

@@ -12,4 +12,17 @@ void apply_passes<float>(const Geometry& g, const Schedule& sc, const float* lam
   apply_passes_t<float>(g, sc, lam, tw, u, y, nrhs, ws, st, mode, rvec, pvec, fvec, cg, active, ev, only, odd);
 }
 
+template <>
+void tau_front<float>(const Geometry& g, const Schedule& sc, const float* m, const Twiddles& tw,
+                     const float* r, float* S1, int nrhs, hipStream_t st, const CgScalars& cg,
+                     const int* active) {
+  tau_front_t<float>(g, sc, m, tw, r, S1, nrhs, st, cg, active);
+}
+
+template <>
+void tau_back_direction<float>(const Geometry& g, const Schedule& sc, const Twiddles& tw, float* S1,
+                              float* p, int nrhs, hipStream_t st, const CgScalars& cg) {
+  tau_back_direction_t<float>(g, sc, tw, S1, p, nrhs, st, cg);
+}
+
 }  // namespace fl

@@ -16,6 +16,19 @@ void apply_passes<double>(const Geometry& g, const Schedule& sc, const double* l
   apply_passes_t<double>(g, sc, lam, tw, u, y, nrhs, ws, st, mode, rvec, pvec, fvec, cg, active, ev, only, odd);
 }
 
+template <>
+void tau_front<double>(const Geometry& g, const Schedule& sc, const double* m, const Twiddles& tw,
+                     const double* r, double* S1, int nrhs, hipStream_t st, const CgScalars& cg,
+                     const int* active) {
+  tau_front_t<double>(g, sc, m, tw, r, S1, nrhs, st, cg, active);
+}
+
+template <>
+void tau_back_direction<double>(const Geometry& g, const Schedule& sc, const Twiddles& tw, double* S1,
+                              double* p, int nrhs, hipStream_t st, const CgScalars& cg) {
+  tau_back_direction_t<double>(g, sc, tw, S1, p, nrhs, st, cg);
+}
+
 size_t apply_workspace_bytes(const Geometry& g, int nrhs, bool fp32) {
   return fp32 ? ws_bytes_t<float>(g, nrhs) : ws_bytes_t<double>(g, nrhs);
 }

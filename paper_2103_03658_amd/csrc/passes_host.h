@@ -120,6 +120,57 @@ void apply_passes_t(const Geometry& g, const Schedule& sc, const T* lam, const T
   }
 }
 
+// The tau preconditioner split around the CG iteration start (d >= 2, the
+// middle pass's blocks within the partial buffers).  tau_front: the sine
+// passes of r up to the middle pass, which writes S1 = sigma diag(m) sigma r
+// (all but the axis-0 back transform) and the r.z partials into part_b.
+// tau_back_direction: the rest; its axis-0 pass starts the next iteration
+// (k_sine_cols DIRF: stopping test, beta, p = z + beta p).  Between the two
+// S1 must stay untouched (it is not the product's workspace).
+template <typename T>
+void tau_front_t(const Geometry& g, const Schedule& sc, const T* m, const Twiddles& twv,
+                 const T* r, T* S1, int nrhs, hipStream_t st, const CgScalars& c,
+                 const int* active) {
+  if (g.d < 2 || !g.sine_ok() || sine_mid_blocks(g, sc) > c.max_blocks)
+    throw Error(2, "split tau preconditioner: d >= 2, 2N a power of two, mid-pass partials");
+  const int n0 = g.na[0], n1 = g.na[1], n2 = g.na[2];
+  const int M0 = g.Ma[0], M1 = g.Ma[1], M2 = g.Ma[2];
+  const cx<T>* tw0 = reinterpret_cast<const cx<T>*>(twv.ax[0]);
+  const cx<T>* tw1 = reinterpret_cast<const cx<T>*>(twv.ax[1]);
+  const cx<T>* tw2 = reinterpret_cast<const cx<T>*>(twv.ax[2]);
+  const long C0 = (long)n1 * n2, nd = g.nd;
+  SineArgs<T> a0{r, S1, nullptr, active, nullptr, 0, C0, nd, 0, 1, n0,
+                 sc.W_first, 0, 0, 0, 0, tw0};
+  launch_sine_cols<T>(M0, sc.E_first, a0, nrhs, st);
+  if (g.d == 3) {
+    SineArgs<T> a1{S1, S1, nullptr, active, nullptr, 0, n2, (long)n1 * n2, 0, n0, n1,
+                   sc.W_c2c, 0, 0, 0, 0, tw1};
+    launch_sine_cols<T>(M1, sc.E_c2c, a1, (long)nrhs * n0, st);
+  }
+  const int nl = g.d == 2 ? n1 : n2;
+  SineMidArgs<T> mid{S1, m, active, nd / nl, nd, nl, n1, g.Ha[g.d - 1], g.Ha[1], g.d,
+                     sc.LPB_mid, nrhs, g.d == 2 ? tw1 : tw2, 1, c.part_b, c.max_blocks};
+  launch_sine_mid<T>(g.d == 2 ? M1 : M2, sc.E_mid, mid, st);
+}
+
+template <typename T>
+void tau_back_direction_t(const Geometry& g, const Schedule& sc, const Twiddles& twv, T* S1,
+                          T* p, int nrhs, hipStream_t st, const CgScalars& c) {
+  const int n0 = g.na[0], n1 = g.na[1], n2 = g.na[2];
+  const int M0 = g.Ma[0], M1 = g.Ma[1];
+  const cx<T>* tw0 = reinterpret_cast<const cx<T>*>(twv.ax[0]);
+  const cx<T>* tw1 = reinterpret_cast<const cx<T>*>(twv.ax[1]);
+  const long C0 = (long)n1 * n2, nd = g.nd;
+  if (g.d == 3) {
+    SineArgs<T> a1{S1, S1, nullptr, c.active, nullptr, 0, n2, (long)n1 * n2, 0, n0, n1,
+                   sc.W_c2c, 0, 0, 0, 0, tw1};
+    launch_sine_cols<T>(M1, sc.E_c2c, a1, (long)nrhs * n0, st);
+  }
+  SineArgs<T> a2{S1, nullptr, nullptr, c.active, nullptr, 0, C0, nd, 0, 1, n0,
+                 sc.W_first, 0, 0, 0, 0, tw0, p, c};
+  launch_sine_cols<T>(M0, sc.E_first, a2, nrhs, st);
+}
+
 template <typename T>
 __global__ void k_twiddle(cx<T>* tw, int M) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;

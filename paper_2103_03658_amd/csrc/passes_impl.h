@@ -54,13 +54,28 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 }
 
 // Sum of nb per-block partials written by an earlier kernel, in a fixed
-// order, returned to every thread of the block.
+// order, returned to every thread of the block: 64 strided sums, then the
+// pairwise tree of wave_sum.  Blocks narrower than a wave (strided passes of
+// short lines) form the same 64 sums and the same tree in LDS, so the result
+// has the same bits for every block size.  sh holds 64 doubles.
 __device__ __forceinline__ double sum_partials(const double* part, int nb, double* sh) {
-  if (threadIdx.x < 64) {
-    double v = 0.0;
-    for (int i = threadIdx.x; i < nb; i += 64) v += part[i];
-    v = wave_sum(v);
-    if (threadIdx.x == 0) sh[0] = v;
+  if (blockDim.x >= 64) {
+    if (threadIdx.x < 64) {
+      double v = 0.0;
+      for (int i = threadIdx.x; i < nb; i += 64) v += part[i];
+      v = wave_sum(v);
+      if (threadIdx.x == 0) sh[0] = v;
+    }
+  } else {
+    for (int l = threadIdx.x; l < 64; l += blockDim.x) {
+      double v = 0.0;
+      for (int i = l; i < nb; i += 64) v += part[i];
+      sh[l] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int off = 32; off > 0; off >>= 1)
+        for (int l = 0; l < off; ++l) sh[l] += sh[l + off];
   }
   __syncthreads();
   const double t = sh[0];
@@ -274,7 +289,7 @@ __global__ void __launch_bounds__(512) k_last(LastArgs<T> a) {
   using P = Plan<M, E>;
   constexpr int TPL = P::TPL;
   extern __shared__ unsigned char smem_raw[];
-  __shared__ double red[16];
+  __shared__ double red[64];
   T* lds = reinterpret_cast<T*>(smem_raw);
   long tile, ol;
   xcd_tile(a.ntiles, tile, ol);
@@ -550,7 +565,7 @@ __global__ void __launch_bounds__(512) k_line1d(Line1Args<T> a) {
   using P = Plan<M, E>;
   constexpr int TPL = P::TPL;
   extern __shared__ unsigned char smem_raw[];
-  __shared__ double red[16];
+  __shared__ double red[64];
   T* lds = reinterpret_cast<T*>(smem_raw);
   T* lre = lds;
   T* lim = lds + P::LDSN;
@@ -716,7 +731,7 @@ __global__ void __launch_bounds__(512) k_cg1d(Cg1Args a) {
   using P = Plan<M, E>;
   constexpr int TPL = P::TPL;
   extern __shared__ unsigned char smem_raw[];
-  __shared__ double red[16];
+  __shared__ double red[64];
   double* lre = reinterpret_cast<double*>(smem_raw);
   double* lim = lre + P::LDSN;
   double* X = lim + P::LDSN;
@@ -829,18 +844,26 @@ struct SineArgs {
   int PO, LS;
   int dot;
   const cx<T>* tw;
+  // DIRF kernels (the last pass of the preconditioner fused with the next CG
+  // iteration start): the search direction, updated in place, and the CG
+  // state whose stopping test and beta every block evaluates first
+  T* pdir;
+  CgScalars cg;
 };
 
 // Strided sine pass along the row axis of [outer][n][C]: each block owns 2W
 // columns (W packed pairs), loads all n rows into the LDS planes (row e
 // holds input row e - 1), transforms the odd-extended lines and writes
-// sigma of each column.
-template <typename T, int M, int E>
+// sigma of each column.  DIRF: the pass that completes z = P r also starts
+// the next CG iteration (cg_begin: stopping test and beta, the same decision
+// in every block of the right-hand side) and writes p = z + beta p instead
+// of z, so z is never stored (the old p is loaded with the input tile).
+template <typename T, int M, int E, bool DIRF>
 __global__ void __launch_bounds__(512) k_sine_cols(SineArgs<T> a) {
   using P = Plan<M, E>;
   constexpr int TPL = P::TPL;
   extern __shared__ unsigned char smem_raw[];
-  __shared__ double red[16];
+  __shared__ double red[64];
   T* lds = reinterpret_cast<T*>(smem_raw);
   long tile, o;
   xcd_tile(a.ntiles, tile, o);
@@ -851,6 +874,22 @@ __global__ void __launch_bounds__(512) k_sine_cols(SineArgs<T> a) {
   const long cl = a.C - col0;
   const int ncol = cl < W2 ? (int)cl : W2;
   const long base = o * a.os + col0;
+  T bt = 0;
+  if constexpr (DIRF) {
+    double beta;
+    if (cg_begin(a.cg, (int)o, tile == 0, red, &beta)) return;
+    bt = (T)beta;
+  }
+  const int tot = a.n * W2;
+  T pold[DIRF ? E : 1];
+  if constexpr (DIRF) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int e = threadIdx.x + j * nthr;
+      const int row = e >> lw1, cc = e & (W2 - 1);
+      pold[j] = (e < tot && cc < ncol) ? a.pdir[base + (long)row * a.C + cc] : (T)0;
+    }
+  }
   // rows [0, M/2) of the tile: (M/2) * 2W elements, exactly E per thread
   {
     T x[E];
@@ -878,7 +917,6 @@ __global__ void __launch_bounds__(512) k_sine_cols(SineArgs<T> a) {
   // positions 1..n: first column of a pair from the imaginary plane, second
   // from the negated real plane
   double acc = 0.0;
-  const int tot = a.n * W2;
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int e = threadIdx.x + j * nthr;
@@ -887,10 +925,14 @@ __global__ void __launch_bounds__(512) k_sine_cols(SineArgs<T> a) {
     const T* ln = lds + (cc >> 1) * a.LS + P::pad(row + 1);
     const T v = (cc & 1) ? -ln[0] : ln[a.PO];
     const long i = base + (long)row * a.C + cc;
-    a.out[i] = v;
-    if (a.dot) acc += (double)a.partner[i] * (double)v;
+    if constexpr (DIRF) {
+      a.pdir[i] = v + bt * pold[j];
+    } else {
+      a.out[i] = v;
+      if (a.dot) acc += (double)a.partner[i] * (double)v;
+    }
   }
-  if (!a.dot) return;
+  if (DIRF || !a.dot) return;
   const double blk = block_sum(acc, red);
   if (threadIdx.x == 0) a.part[(o / a.outer_per_rhs) * a.max_blocks + tile] = blk;
 }
@@ -989,7 +1031,7 @@ __global__ void __launch_bounds__(512) k_sine_mid(SineMidArgs<T> a) {
     }
   }
   if (!a.dot) return;
-  __shared__ double red[16];
+  __shared__ double red[64];
   const double blk = block_sum(acc, red);
   if (threadIdx.x == 0) a.part[(long)o * a.max_blocks + rb] = blk;
 }
@@ -1158,13 +1200,21 @@ void launch_sine_cols(int M, int E, SineArgs<T> a, long outer, hipStream_t st) {
   a.ntiles = pair_tiles(a.C, a.W);
   if (a.dot && (a.ntiles > a.max_blocks || a.outer_per_rhs != 1))
     throw Error(2, "sine pass: bad reduction layout");
+  if (a.pdir && (a.dot || a.outer_per_rhs != 1))
+    throw Error(2, "sine pass: the fused iteration start needs one slice per RHS, no dot");
   a.lw = ilog2i(a.W);
   const TileLds tl = tile_lds(M, E, a.W, sizeof(T));
   a.PO = tl.PO;
   a.LS = tl.LS;
   dim3 grid((unsigned)(a.ntiles * outer));
   const int threads = a.W * (M / E);
-  FL_DISPATCH(M, E, FL_LAUNCH((k_sine_cols<T, M, E>), grid, dim3(threads), tl.bytes, st, a));
+  if (a.pdir) {
+    FL_DISPATCH(M, E, FL_LAUNCH((k_sine_cols<T, M, E, true>), grid, dim3(threads), tl.bytes, st,
+                                a));
+  } else {
+    FL_DISPATCH(M, E, FL_LAUNCH((k_sine_cols<T, M, E, false>), grid, dim3(threads), tl.bytes,
+                                st, a));
+  }
   check_launch("sine pass");
 }
 
