@@ -100,37 +100,75 @@ def parse():
                          "(the known-size kernel that scales the HBM byte counters)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only time the FFT-matvec kernels (for profiler runs)")
-    ap.add_argument("--serve-requests", type=int, default=512,
-                    help="requests of the serving stream (Poisson arrivals at 200/s; the full "
-                         "stream is 4096; 0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=4096,
+                    help="requests of the serving stream (Poisson arrivals at 200/s; 0: skip)")
     ap.add_argument("--serve-workers", type=int, default=4)
+    ap.add_argument("--serve-fp64", type=int, default=1,
+                    help="1: also serve the stream with FP64 PCG beside the mixed path")
+    ap.add_argument("--serve-burst", type=int, default=512,
+                    help="requests of the burst stream (six operators, arrivals at 4000/s; 0: skip)")
+    ap.add_argument("--serve-sample", type=int, default=32,
+                    help="requests of each stream re-solved alone and compared with the mix")
     ap.add_argument("--configs", type=int, default=1,
                     help="1: also measure the 1D, 2D 255^2, 3D 127^3 and tempered 1023^2 "
                          "workloads (a few seconds); 0: skip")
     ap.add_argument("--serve-only", action="store_true")
+    ap.add_argument("--d2-only", action="store_true",
+                    help="only time the product on the large working sets (default and tuned "
+                         "schedules; for profiler runs)")
+    ap.add_argument("--d2", type=int, default=1,
+                    help="1: report the large-working-set products in the bench line")
     return ap.parse_args()
 
 
-def run_serving(n_requests, workers, tol):
+def run_serving(n_requests, workers, tol, mixed=1, sample=32, burst=False):
     """Serving stream: d = 2, n in {63,127,255,511}, alpha ~ U(0.2, 1.9)
     rounded to 0.01, degree in {0,1,2}, 1-8 U[-1,1] right-hand sides,
-    Poisson arrivals at 200 requests/s, FP64 solves to tol."""
+    Poisson arrivals at 200 requests/s, solves to tol with the mixed path
+    (mixed = 1) or FP64 PCG (mixed = 0); burst: the six-operator stream at
+    4000 requests/s.  `sample` requests spread over the stream are solved
+    again alone on fresh operators and compared with their result in the mix."""
     import torch
+    import paper_2103_03658_amd as fl
     from paper_2103_03658_amd import inputs
     from paper_2103_03658_amd.serve import Request, Server
-    spec = inputs.request_stream(n_requests, rate=200.0, seed=0)
+    if burst:
+        spec = inputs.burst_stream(n_requests)
+    else:
+        spec = inputs.request_stream(n_requests, rate=200.0, seed=0)
     reqs = [Request(r["id"], 2, r["N"], r["alpha"], r["degree"],
                     torch.from_numpy(inputs.request_rhs(r)).cuda(), t_arrive=r["t_arrive"])
             for r in spec]
     torch.cuda.synchronize()
+    step = max(1, n_requests // max(1, sample))
+    keep = set(range(0, n_requests, step)[:sample])
     warm = sorted({(2, r["N"], r["degree"]) for r in spec})
-    srv = Server(workers=workers, tol=tol, mixed=0, warm=warm)
+    srv = Server(workers=workers, tol=tol, mixed=mixed, warm=warm, keep_solutions=keep)
     st = srv.run(reqs, realtime=True)
-    st["stream"] = (f"{n_requests} requests, Poisson arrivals at 200/s, d=2, "
-                    "n in {63,127,255,511} (p=.4/.3/.2/.1), alpha~U(0.2,1.9) rounded to 0.01, "
-                    "degree in {0,1,2}, 1-8 U[-1,1] RHS each, FP64 PCG "
-                    f"to {tol:g}, {workers} worker streams, each warmed first by one solve per "
-                    "(N, degree) of the stream (warmup_s)")
+    # alone against the mix: each sampled request on a fresh operator of its own
+    same, worst = 0, 0.0
+    for r in reqs:
+        if r.id not in keep or r.u is None:
+            continue
+        op = fl.Operator(2, r.alpha, r.degree, N=r.N)
+        u, _ = op.solve(r.f, tol=tol, mixed=mixed)
+        same += int(torch.equal(u, r.u))
+        worst = max(worst, float((u - r.u).abs().max() / u.abs().max()))
+        op.close()
+    st["alone_vs_mix"] = {"sampled": len(keep), "bitwise_equal": same,
+                          "max_rel_linf_diff": worst}
+    prec = "FP32 CG with FP64 reliable updates" if mixed else "FP64 PCG"
+    if burst:
+        st["stream"] = (f"{n_requests} requests, Poisson arrivals at 4000/s, d=2, n in "
+                        "{127,255}, alpha in {0.5,1,1.5}, degree 1 (six operators), 1-8 U[-1,1] "
+                        f"RHS each, {prec} to {tol:g}, {workers} worker streams")
+    else:
+        st["stream"] = (f"{n_requests} requests, Poisson arrivals at 200/s, d=2, "
+                        "n in {63,127,255,511} (p=.4/.3/.2/.1), alpha~U(0.2,1.9) rounded to 0.01, "
+                        f"degree in {{0,1,2}}, 1-8 U[-1,1] RHS each, {prec} "
+                        f"to {tol:g}, {workers} worker streams, each warmed first by one solve "
+                        "per (N, degree) of the stream (warmup_s)")
+    st["precision"] = prec
     return st
 
 
@@ -159,6 +197,58 @@ def pass_flops(d, N, nrhs):
     col = pairs * (fft + 6.0 * h)
     mid = h * (2.0 * fft + 2.0 * M)
     return [col * nrhs, mid * nrhs, col * nrhs]
+
+
+def pass_bytes_3d(N, nrhs, sr):
+    """Algorithmic HBM bytes of the five kernels of one batched 3D product:
+    axis-0 forward (n^3 real in, h n^2 complex out), axis-1 forward (h n^2
+    in, h M n out), last axis (h M n complex in and out, plus the folded
+    symbol), axis-1 inverse, axis-0 inverse (h = M/2 + 1, M = 2N)."""
+    n, M = N - 1, 2 * N
+    h = M // 2 + 1
+    vec = n ** 3 * sr * nrhs
+    t1 = h * n * n * 2 * sr * nrhs
+    t2 = h * M * n * 2 * sr * nrhs
+    sym = (N + 1) ** 3 * sr
+    return [vec + t1, t1 + t2, 2 * t2 + sym, t2 + t1, t1 + vec]
+
+
+def d2_shapes(dev, reps=20):
+    """The product on working sets far beyond the 256 MB Infinity Cache, with
+    the default launch schedule and the tuned one: tempered 2D 1023^2 FP32 x
+    64 right-hand sides, 3D 127^3 FP32 x 8 and FP64 x 4, and the headline 2D
+    511^2 FP64 x 17 (0.64 GB, partly cache-resident).  Per kernel: HIP-event
+    milliseconds (each kernel `reps` times back to back) and GB/s of the
+    algorithmic bytes."""
+    import torch
+    import paper_2103_03658_amd as fl
+    from paper_2103_03658_amd import inputs, tune
+    shapes = [("C5_2d_1023_tempered_fp32_x64", 2, 1024, 1, 1.2, 1.0, 64, True),
+              ("C3_3d_127_fp32_x8", 3, 128, 1, 1.0, 0.0, 8, True),
+              ("C3_3d_127_fp64_x4", 3, 128, 1, 1.0, 0.0, 4, False),
+              ("D1_2d_511_fp64_x17", 2, 512, 2, 1.5, 0.0, 17, False)]
+    out = {}
+    for name, d, N, p, a, lam, nrhs, fp32 in shapes:
+        op = (fl.Operator(d, a, p, N=N, kernel="tempered", lam=lam) if lam
+              else fl.Operator(d, a, p, N=N))
+        dt = torch.float32 if fp32 else torch.float64
+        u = torch.from_numpy(inputs.uniform_rhs(d, N, nrhs, seed=0)).to(dev).to(dt)
+        sr = 4 if fp32 else 8
+        by = pass_bytes_3d(N, nrhs, sr) if d == 3 else pass_bytes(2, N, nrhs, sr)
+        res = {"bytes_per_product": sum(by), "nrhs": nrhs, "precision": "f32" if fp32 else "f64"}
+        for label in ("default", "tuned"):
+            if label == "tuned":
+                tune.tune(op, nrhs, fp32, use_cache=False)
+            ms = op.profile_apply(u, reps=reps)
+            res[label] = {"schedule": op.get_schedule(fp32), "ms_per_kernel": ms,
+                          "GBs_per_kernel": [b / (t * 1e-3) / 1e9 for b, t in zip(by, ms)],
+                          "matvec_ms": sum(ms), "GBs": sum(by) / (sum(ms) * 1e-3) / 1e9,
+                          "frac_of_8TBs": sum(by) / (sum(ms) * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        out[name] = res
+        op.close()
+        del u
+        torch.cuda.empty_cache()
+    return out
 
 
 def precond_bytes(d, N, nrhs, sr):
@@ -224,6 +314,7 @@ def run_configs(dev, tol, quick=False):
                       "max_relres_true": max(i["relres_true"] for i in inf)}
         op.close()
     out["C2_2d_255_fp64_17rhs"] = c2
+    out["C2_h_sweep_p2"] = h_sweep(dev)
     # C3: 3D 127^3, alpha = 1, p = 1, N(0,1) seed 3, mixed precision; FP64 as reference
     op = fl.Operator(3, 1.0, 1, N=128)
     for fp32 in (True, False):
@@ -270,6 +361,42 @@ def run_configs(dev, tol, quick=False):
     return out
 
 
+def h_sweep(dev, Ns=(64, 128, 256, 512), alphas=(0.5, 1.0, 1.5)):
+    """h-refinement of the 2D quadratic-basis operator (63^2 -> 511^2): the
+    product on u = (1-|x|^2)_+^{4+alpha/2} (supported in the unit disk, so no
+    exterior data) against its closed-form image at the points
+    {-1/2, -1/4, 0, 1/4, 1/2}^2, where it is the terminating series
+    2^alpha Gamma(1+alpha/2) Gamma(s+1)/Gamma(s+1-alpha/2) 2F1(1+alpha/2, -4; 1; |x|^2),
+    s = 4 + alpha/2; the measured rate (the origin element caps the
+    quadratic basis at 4 - alpha)."""
+    import torch
+    from scipy.special import hyp2f1
+    import paper_2103_03658_amd as fl
+    pts = (-0.5, -0.25, 0.0, 0.25, 0.5)
+    out = {}
+    for a in alphas:
+        s_ = 4.0 + a / 2.0
+        errs = []
+        for N in Ns:
+            op = fl.Operator(2, a, 2, N=N)
+            x = -1.0 + (2.0 / N) * np.arange(1, N)
+            X0, X1 = np.meshgrid(x, x, indexing="ij")
+            u = np.maximum(1.0 - X0 * X0 - X1 * X1, 0.0) ** s_
+            y = op.apply(torch.from_numpy(u[None].copy()).to(dev)).cpu().numpy()[0]
+            idx = [int(round((v + 1.0) * N / 2.0)) - 1 for v in pts]
+            got = y[np.ix_(idx, idx)]
+            xs = np.array(pts)
+            r2 = xs[:, None] ** 2 + xs[None, :] ** 2
+            pref = (2.0 ** a * math.gamma(1.0 + a / 2.0) * math.gamma(s_ + 1.0)
+                    / math.gamma(s_ + 1.0 - a / 2.0))
+            ref = pref * hyp2f1(1.0 + a / 2.0, a / 2.0 - s_, 1.0, r2)
+            errs.append(float(np.abs(got - ref).max()))
+            op.close()
+        out[str(a)] = {"N": list(Ns), "max_err": errs,
+                       "rates": [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]}
+    return out
+
+
 def cpu_baseline(N, degree, alpha, tol, budget):
     """Time the oracle on this host: whole solves of one right-hand side by
     its preconditioned CG (dense block-Toeplitz product, no FFT, for A; the
@@ -279,6 +406,8 @@ def cpu_baseline(N, degree, alpha, tol, budget):
         from threadpoolctl import threadpool_limits
     except Exception:  # pragma: no cover
         threadpool_limits = None
+    # BLAS threads: the host cores this process may use, at most 16 (the CPU
+    # share of one GPU on the benchmark boxes, whatever the host shows)
     cores = len(os.sched_getaffinity(0))
     cores = min(cores, 16)
     ctx = threadpool_limits(limits=cores) if threadpool_limits else None
@@ -311,6 +440,23 @@ def cpu_baseline(N, degree, alpha, tol, budget):
                 solve_s=t_s, iterations=its[0], generator_s=t_gen)
 
 
+def serving_legs(args):
+    """The serving stream with the mixed path (as configured), beside it the
+    same stream with FP64 PCG, and the burst stream in which same-operator
+    requests queue and are merged."""
+    if args.serve_requests <= 0:
+        return None
+    out = run_serving(args.serve_requests, args.serve_workers, args.tol, mixed=1,
+                      sample=args.serve_sample)
+    if args.serve_fp64:
+        out["fp64"] = run_serving(args.serve_requests, args.serve_workers, args.tol, mixed=0,
+                                  sample=args.serve_sample)
+    if args.serve_burst > 0:
+        out["burst"] = run_serving(args.serve_burst, args.serve_workers, args.tol, mixed=1,
+                                   sample=args.serve_sample, burst=True)
+    return out
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -325,8 +471,10 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.serve_only:
-        print(json.dumps({"serving": run_serving(args.serve_requests, args.serve_workers,
-                                                 args.tol)}))
+        print(json.dumps({"serving": serving_legs(args)}))
+        return
+    if args.d2_only:
+        print(json.dumps({"d2": d2_shapes(dev, reps=args.profile_reps)}))
         return
     N, p = args.N, args.degree
     alphas = [0.5, 1.0, 1.5]
@@ -478,7 +626,10 @@ def main():
 
     def passes(fp32):
         u_ = rhs[a].to(torch.float32).contiguous() if fp32 else rhs[a]
-        ms_ = ops[a].profile_apply(u_, reps=args.profile_reps)
+        # mean over 5 measurements of `profile_reps` back-to-back launches (the
+        # mean per dispatch, as a kernel trace's average reports it)
+        runs = [ops[a].profile_apply(u_, reps=args.profile_reps) for _ in range(5)]
+        ms_ = [float(np.mean([r[i] for r in runs])) for i in range(len(runs[0]))]
         by_ = pass_bytes(2, N, nrhs, 4 if fp32 else 8)
         fl_ = pass_flops(2, N, nrhs)
         return [{"kernel": nm, "ms": t, "bytes": b, "GBs": b / (t * 1e-3) / 1e9,
@@ -492,7 +643,8 @@ def main():
 
     def ppasses(fp32):
         u_ = rhs[a].to(torch.float32).contiguous() if fp32 else rhs[a]
-        ms_ = ops[a].profile_precond(u_, reps=args.profile_reps)
+        runs = [ops[a].profile_precond(u_, reps=args.profile_reps) for _ in range(5)]
+        ms_ = [float(np.mean([r[i] for r in runs])) for i in range(len(runs[0]))]
         by_ = precond_bytes(2, N, nrhs, 4 if fp32 else 8)
         fl_ = precond_flops(2, N, nrhs)
         return [{"kernel": nm, "ms": t, "bytes": b, "GBs": b / (t * 1e-3) / 1e9,
@@ -532,10 +684,9 @@ def main():
             "precond_ms_f32": sum(k["ms"] for k in pp32)}
 
     configs = run_configs(dev, args.tol) if args.configs else None
+    d2 = d2_shapes(dev, reps=args.profile_reps) if args.d2 else None
 
-    serving = None
-    if args.serve_requests > 0:
-        serving = run_serving(args.serve_requests, args.serve_workers, args.tol)
+    serving = serving_legs(args)
 
     cpu = None
     if args.cpu_budget > 0:
@@ -558,7 +709,7 @@ def main():
         "latency_unit": "ms per batched solve (all RHS of the batch complete)",
         "max_relres_true": max_relres, "iters": iters, "outer_iters": outers,
         "setup_s": setup_s, "schedule": sched, "fp64_single": fp64, "mixed": mixed_res,
-        "serving": serving, "configs": configs,
+        "serving": serving, "configs": configs, "d2": d2,
         "roofline": roof, "cpu_baseline": cpu,
     }
     print(json.dumps(res))

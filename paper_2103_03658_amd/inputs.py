@@ -1,6 +1,8 @@
 """Seeded synthetic inputs (right-hand sides, request streams).
 
-Holds none of the method's arithmetic: only random draws and grid shapes.
+Holds none of the discretization's arithmetic: random draws, grid shapes and
+one closed form of the continuous operator (the benchmark's disk right-hand
+side, manufactured_rhs_disk).
 Seeds follow one convention everywhere: numpy's PCG64 via
 numpy.random.default_rng, FP64 draws in row-major order over the n^d
 interior points; right-hand side j of a batch seeded s uses seed s + j.
@@ -64,6 +66,20 @@ def request_stream(n_requests=4096, rate=200.0, seed=0, alpha_round=0.01):
     return reqs
 
 
+def burst_stream(n_requests=512, rate=4000.0, seed=1):
+    """Burst workload: requests for a few operators arriving faster than they
+    are served, so that requests for the same operator queue and are merged:
+    n in {127, 255}, alpha in {0.5, 1.0, 1.5}, degree 1 (six operators),
+    1..8 right-hand sides, Poisson arrivals at `rate` per second."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, n_requests))
+    ns = rng.choice([127, 255], size=n_requests)
+    alphas = rng.choice([0.5, 1.0, 1.5], size=n_requests)
+    nrhs = rng.integers(1, 9, n_requests)
+    return [dict(id=i, t_arrive=float(t[i]), d=2, N=int(ns[i]) + 1, alpha=float(alphas[i]),
+                 degree=1, nrhs=int(nrhs[i]), seed=[seed, i]) for i in range(n_requests)]
+
+
 def request_rhs(req):
     """Right-hand sides of one request, shape (nrhs, n, n)."""
     n = req["N"] - 1
@@ -72,12 +88,13 @@ def request_rhs(req):
 
 
 def manufactured_rhs_disk(N, alpha):
-    """Right-hand side for u = (1-|x|^2)_+^{1+alpha/2} on the 2D grid, taken
-    inside the unit disk from the closed form
-    2^alpha Gamma(1+alpha/2) Gamma(2+alpha/2) (1 - (1+alpha/2)|x|^2)
-    and set to zero in the corners |x| >= 1 of the square (there the
-    continuous value needs a singular quadrature; for throughput runs any
-    right-hand side serves).  Shape (n, n)."""
+    """The benchmark's structured right-hand side on the 2D grid: inside the
+    unit disk the closed-form image of u = (1-|x|^2)_+^{1+alpha/2},
+    2^alpha Gamma(1+alpha/2) Gamma(2+alpha/2) (1 - (1+alpha/2)|x|^2),
+    and zero in the corners |x| >= 1 of the square.  The image of u is
+    negative there (it needs a singular quadrature per point), so this f is
+    the image of no known solution on the square: a throughput input with the
+    manufactured solution's shape, not an accuracy test.  Shape (n, n)."""
     import math
     X0, X1 = interior_coords(2, N)
     r2 = X0 * X0 + X1 * X1

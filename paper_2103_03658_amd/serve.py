@@ -93,6 +93,7 @@ class Server:
         self.cache_bytes = cache_bytes
         self.max_batch_rhs = max_batch_rhs
         self.tol, self.mixed, self.maxiter = tol, mixed, maxiter
+        # True: keep every request's solution; a set of request ids: keep those
         self.keep = keep_solutions
         self.device = device
         self._cv = threading.Condition()
@@ -268,7 +269,7 @@ class Server:
             if self.keep:
                 off = 0
                 for r in group:
-                    kept.append(u[off:off + r.nrhs].clone())
+                    kept.append(u[off:off + r.nrhs].clone() if self._keeps(r) else None)
                     off += r.nrhs
         t1 = time.perf_counter()
         self.batches.append((len(group), rhs, t1 - t0, group[0].N))
@@ -279,10 +280,13 @@ class Server:
             r.cache_hit = hit
             r.batch_rhs = rhs
             r.info = info[off:off + r.nrhs]
-            if self.keep:
+            if self.keep and kept[k] is not None:
                 r.u = kept[k]
             r.status = "ok" if all(i["converged"] for i in r.info) else "noconv"
             off += r.nrhs
+
+    def _keeps(self, r):
+        return self.keep is True or (not isinstance(self.keep, bool) and r.id in self.keep)
 
     # -- driver ---------------------------------------------------------------
     def run(self, requests, realtime=True):
@@ -310,7 +314,14 @@ class Server:
         for t in threads:
             t.join()
         end = time.perf_counter()
+        self.device_bytes_in_use = self._device_bytes_in_use()
         return self.stats(start, end)
+
+    def _device_bytes_in_use(self):
+        """Device memory in use (operator cache included) at the end of a run."""
+        import torch
+        free, total = torch.cuda.mem_get_info(self.device)
+        return total - free
 
     def stats(self, start, end):
         ok = [r for r in self.done if r.status == "ok"]
@@ -335,6 +346,8 @@ class Server:
             "mean_requests_per_batch": float(np.mean([b[0] for b in self.batches]))
             if self.batches else None,
             "admission_waits": self.admission_waits,
+            "operators_cached": len(self._ops),
+            "device_gb_in_use_at_end": getattr(self, "device_bytes_in_use", 0) / 1e9,
             "max_relres_true": worst,
             "errors": self.errors[:5],
         }

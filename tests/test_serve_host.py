@@ -38,6 +38,9 @@ class HostServer(serve.Server):
     def _open_stream(self):
         return None
 
+    def _device_bytes_in_use(self):
+        return 0
+
     def _tensor_device(self):
         return "cpu"
 
