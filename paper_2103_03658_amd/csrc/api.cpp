@@ -1201,16 +1201,18 @@ void cg_start(fl_op A, const fl::Schedule& sc, const T* linv, const fl::Twiddles
 
 // One CG (or preconditioned CG) iteration for all active right-hand sides.
 // With the split tau preconditioner (S1 != null) the iteration is: second
-// half of z = P r fused with the iteration start (p = z + beta p), the
-// product's passes, the update, first half of the next z = P r.
+// half of z = P r fused with the iteration start (p = z + beta p) and the
+// product's first pass, the product's other passes, the update, first half
+// of the next z = P r.
 template <typename T>
 void cg_iteration(fl_op A, const fl::Schedule& sc, const T* lam, const T* linv, const fl::Twiddles& tw,
                   T* x, T* r, T* p, T* q, T* z, int nrhs, const fl::CgScalars& cg, void* ws,
                   hipStream_t st, T* S1) {
   if (S1) {
-    fl::tau_back_direction<T>(A->g, pc_sched<T>(A), tw, S1, p, nrhs, st, cg);
+    // z's last pass, p = z + beta p and the product's first pass in one kernel
+    fl::tau_back_direction<T>(A->g, sc, pc_sched<T>(A), tw, S1, p, ws, nrhs, st, cg);
     fl::apply_passes<T>(A->g, sc, lam, tw, p, q, nrhs, ws, st, fl::PM_PQ, nullptr, nullptr,
-                        nullptr, &cg, cg.active);
+                        nullptr, &cg, cg.active, nullptr, -1, false, true);
     fl::cg_update<T>(A->g, x, r, p, q, nrhs, cg, st);
     fl::tau_front<T>(A->g, pc_sched<T>(A), linv, tw, r, S1, nrhs, st, cg, cg.active);
     return;

@@ -188,20 +188,25 @@ void apply_passes(const Geometry& g, const Schedule& sc, const T* lam, const Twi
                   const T* u, T* y, int nrhs, void* ws, hipStream_t st, int mode,
                   const T* rvec, T* pvec, const double* fvec, const CgScalars* cg,
                   const int* active, hipEvent_t* ev = nullptr, int only = -1,
-                  bool odd = false);
+                  bool odd = false, bool first_done = false);
 
 // The tau preconditioner (d >= 2) split around the CG iteration start, for
 // preconditioned CG: tau_front applies the sine passes of r up to the middle
 // pass (into S1, nrhs * n^d values of T, with the r.z partials of the middle
 // pass in cg.part_b); tau_back_direction finishes z = P r from S1 and, in
 // the same pass, starts the next iteration: stopping test and beta
-// (cg_begin), then p = z + beta p.  Only when sine_mid_blocks <= max_blocks.
+// (cg_begin), then p = z + beta p; given T1 (the product's workspace) that
+// pass also runs the product's axis-0 forward pass of p on its tile (on the
+// product's schedule sc; sp is the preconditioner's), so the product follows
+// with apply_passes(..., first_done = true).  Only when sine_mid_blocks <=
+// max_blocks.
 template <typename T>
 void tau_front(const Geometry& g, const Schedule& sc, const T* m, const Twiddles& tw, const T* r,
                T* S1, int nrhs, hipStream_t st, const CgScalars& cg, const int* active);
 template <typename T>
-void tau_back_direction(const Geometry& g, const Schedule& sc, const Twiddles& tw, T* S1, T* p,
-                        int nrhs, hipStream_t st, const CgScalars& cg);
+void tau_back_direction(const Geometry& g, const Schedule& sc, const Schedule& sp,
+                        const Twiddles& tw, T* S1, T* p, void* T1, int nrhs, hipStream_t st,
+                        const CgScalars& cg);
 
 // Number of kernel launches (passes) of one application: 1, 3 or 5 for d = 1, 2, 3.
 inline int apply_npasses(int d) { return d == 1 ? 1 : (d == 2 ? 3 : 5); }

@@ -8,8 +8,9 @@ void apply_passes<float>(const Geometry& g, const Schedule& sc, const float* lam
                          const Twiddles& tw, const float* u, float* y, int nrhs, void* ws,
                          hipStream_t st, int mode, const float* rvec, float* pvec,
                          const double* fvec, const CgScalars* cg, const int* active,
-                          hipEvent_t* ev, int only, bool odd) {
-  apply_passes_t<float>(g, sc, lam, tw, u, y, nrhs, ws, st, mode, rvec, pvec, fvec, cg, active, ev, only, odd);
+                          hipEvent_t* ev, int only, bool odd, bool first_done) {
+  apply_passes_t<float>(g, sc, lam, tw, u, y, nrhs, ws, st, mode, rvec, pvec, fvec, cg, active, ev,
+                    only, odd, first_done);
 }
 
 template <>
@@ -20,9 +21,10 @@ void tau_front<float>(const Geometry& g, const Schedule& sc, const float* m, con
 }
 
 template <>
-void tau_back_direction<float>(const Geometry& g, const Schedule& sc, const Twiddles& tw, float* S1,
-                              float* p, int nrhs, hipStream_t st, const CgScalars& cg) {
-  tau_back_direction_t<float>(g, sc, tw, S1, p, nrhs, st, cg);
+void tau_back_direction<float>(const Geometry& g, const Schedule& sc, const Schedule& sp,
+                              const Twiddles& tw, float* S1, float* p, void* T1, int nrhs,
+                              hipStream_t st, const CgScalars& cg) {
+  tau_back_direction_t<float>(g, sc, sp, tw, S1, p, T1, nrhs, st, cg);
 }
 
 }  // namespace fl

@@ -12,8 +12,9 @@ void apply_passes<double>(const Geometry& g, const Schedule& sc, const double* l
                           const Twiddles& tw, const double* u, double* y, int nrhs, void* ws,
                           hipStream_t st, int mode, const double* rvec, double* pvec,
                           const double* fvec, const CgScalars* cg, const int* active,
-                          hipEvent_t* ev, int only, bool odd) {
-  apply_passes_t<double>(g, sc, lam, tw, u, y, nrhs, ws, st, mode, rvec, pvec, fvec, cg, active, ev, only, odd);
+                          hipEvent_t* ev, int only, bool odd, bool first_done) {
+  apply_passes_t<double>(g, sc, lam, tw, u, y, nrhs, ws, st, mode, rvec, pvec, fvec, cg, active, ev,
+                    only, odd, first_done);
 }
 
 template <>
@@ -24,9 +25,10 @@ void tau_front<double>(const Geometry& g, const Schedule& sc, const double* m, c
 }
 
 template <>
-void tau_back_direction<double>(const Geometry& g, const Schedule& sc, const Twiddles& tw, double* S1,
-                              double* p, int nrhs, hipStream_t st, const CgScalars& cg) {
-  tau_back_direction_t<double>(g, sc, tw, S1, p, nrhs, st, cg);
+void tau_back_direction<double>(const Geometry& g, const Schedule& sc, const Schedule& sp,
+                              const Twiddles& tw, double* S1, double* p, void* T1, int nrhs,
+                              hipStream_t st, const CgScalars& cg) {
+  tau_back_direction_t<double>(g, sc, sp, tw, S1, p, T1, nrhs, st, cg);
 }
 
 size_t apply_workspace_bytes(const Geometry& g, int nrhs, bool fp32) {

@@ -20,7 +20,7 @@ template <typename T>
 void apply_passes_t(const Geometry& g, const Schedule& sc, const T* lam, const Twiddles& twv,
                     const T* u, T* y, int nrhs, void* ws, hipStream_t st, int mode,
                     const T* rvec, T* pvec, const double* fvec, const CgScalars* cg,
-                    const int* active, hipEvent_t* ev, int only, bool odd) {
+                    const int* active, hipEvent_t* ev, int only, bool odd, bool first_done) {
   // optional timing: ev[k] recorded before pass k, ev[npasses] after the last;
   // only >= 0 launches that pass alone (its input must already be in place)
   int pass = 0;
@@ -87,7 +87,9 @@ void apply_passes_t(const Geometry& g, const Schedule& sc, const T* lam, const T
   // axis 0, forward (real pairs -> Hermitian half); the CG iteration start
   // runs before it (cg_direction), so d >= 2 takes PM_PQ rather than PM_CG
   if (mode == PM_CG) throw Error(2, "PM_CG: d = 1 only (d >= 2 uses PM_PQ)");
-  {
+  if (!first_done) {
+    // (first_done: the axis-0 forward pass has already written T1, fused
+    // into the preconditioner's last pass)
     FirstArgs<T> a{u, active, T1, C0, nd, h0 * C0, 0, n0, sc.W_first, 0, 0, 0, tw0};
     if (go()) launch_first<T>(M0, sc.E_first, a, nrhs, st);
   }
@@ -153,9 +155,13 @@ void tau_front_t(const Geometry& g, const Schedule& sc, const T* m, const Twiddl
   launch_sine_mid<T>(g.d == 2 ? M1 : M2, sc.E_mid, mid, st);
 }
 
+// T1 != null: the axis-0 pass also runs the product's first pass on the new
+// p (into T1, the product's workspace), on the product's tile schedule sc;
+// the 3D axis-1 sine pass keeps the preconditioner's schedule sp.
 template <typename T>
-void tau_back_direction_t(const Geometry& g, const Schedule& sc, const Twiddles& twv, T* S1,
-                          T* p, int nrhs, hipStream_t st, const CgScalars& c) {
+void tau_back_direction_t(const Geometry& g, const Schedule& sc, const Schedule& sp,
+                          const Twiddles& twv, T* S1, T* p, void* T1, int nrhs, hipStream_t st,
+                          const CgScalars& c) {
   const int n0 = g.na[0], n1 = g.na[1], n2 = g.na[2];
   const int M0 = g.Ma[0], M1 = g.Ma[1];
   const cx<T>* tw0 = reinterpret_cast<const cx<T>*>(twv.ax[0]);
@@ -163,12 +169,14 @@ void tau_back_direction_t(const Geometry& g, const Schedule& sc, const Twiddles&
   const long C0 = (long)n1 * n2, nd = g.nd;
   if (g.d == 3) {
     SineArgs<T> a1{S1, S1, nullptr, c.active, nullptr, 0, n2, (long)n1 * n2, 0, n0, n1,
-                   sc.W_c2c, 0, 0, 0, 0, tw1};
-    launch_sine_cols<T>(M1, sc.E_c2c, a1, (long)nrhs * n0, st);
+                   sp.W_c2c, 0, 0, 0, 0, tw1};
+    launch_sine_cols<T>(M1, sp.E_c2c, a1, (long)nrhs * n0, st);
   }
+  const Schedule& s0 = T1 ? sc : sp;
   SineArgs<T> a2{S1, nullptr, nullptr, c.active, nullptr, 0, C0, nd, 0, 1, n0,
-                 sc.W_first, 0, 0, 0, 0, tw0, p, c};
-  launch_sine_cols<T>(M0, sc.E_first, a2, nrhs, st);
+                 s0.W_first, 0, 0, 0, 0, tw0, p, c, reinterpret_cast<cx<T>*>(T1),
+                 (long)g.Ha[0] * C0};
+  launch_sine_cols<T>(M0, s0.E_first, a2, nrhs, st);
 }
 
 template <typename T>

@@ -200,6 +200,33 @@ __device__ __forceinline__ void line_in_lds(T* lre, T* lim, int t, const cx<T>* 
   }
 }
 
+// Hermitian split of the tile's W packed line pairs (transformed in the LDS
+// planes) into rows k = 0..M/2 of the axis-0 frequency, row segments of 2W
+// complex values: X_a = (Z_k + conj Z_{M-k})/2, X_b = (Z_k - conj Z_{M-k})/(2i).
+// out points at (rhs, row 0, first column of the tile); rows are C apart.
+template <typename T, int M, int E>
+__device__ __forceinline__ void hermitian_split_out(const T* lds, cx<T>* out, long C, int W,
+                                                    int lw, int PO, int LS, int ncol) {
+  using P = Plan<M, E>;
+  const int nthr = W * P::TPL;
+  const T half = (T)0.5;
+  const int tot3 = (M / 2 + 1) * W;   // E/2 full rounds and a partial one
+#pragma unroll
+  for (int j = 0; j <= E / 2; ++j) {
+    const int e = threadIdx.x + j * nthr;
+    const int k = e >> lw, l = e & (W - 1);
+    if (e >= tot3 || 2 * l >= ncol) continue;
+    const T* re = lds + l * LS;
+    const T* im = re + PO;
+    const int km = (M - k) & (M - 1);
+    const cx<T> z = {re[P::pad(k)], im[P::pad(k)]};
+    const cx<T> zm = {re[P::pad(km)], im[P::pad(km)]};
+    const long oi = (long)k * C + 2 * l;
+    out[oi] = {(z.x + zm.x) * half, (z.y - zm.y) * half};
+    if (2 * l + 1 < ncol) out[oi + 1] = {(z.y + zm.y) * half, (zm.x - z.x) * half};
+  }
+}
+
 template <typename T, int M, int E>
 __global__ void __launch_bounds__(512) k_first(FirstArgs<T> a) {
   using P = Plan<M, E>;
@@ -240,25 +267,8 @@ __global__ void __launch_bounds__(512) k_first(FirstArgs<T> a) {
     line_in_lds<T, M, E, -1, 1, false>(lre, lre + a.PO, t, a.tw);
   }
   __syncthreads();
-  // Hermitian split of each packed pair, rows k = 0..M/2, row segments of
-  // 2W complex values: X_a = (Z_k + conj Z_{M-k})/2, X_b = (Z_k - conj Z_{M-k})/(2i)
-  const long ob = (long)o * a.out_os + col0;
-  const T half = (T)0.5;
-  const int tot3 = (M / 2 + 1) * a.W;   // E/2 full rounds and a partial one
-#pragma unroll
-  for (int j = 0; j <= E / 2; ++j) {
-    const int e = threadIdx.x + j * nthr;
-    const int k = e >> a.lw, l = e & (a.W - 1);
-    if (e >= tot3 || 2 * l >= ncol) continue;
-    const T* re = lds + l * a.LS;
-    const T* im = re + a.PO;
-    const int km = (M - k) & (M - 1);
-    const cx<T> z = {re[P::pad(k)], im[P::pad(k)]};
-    const cx<T> zm = {re[P::pad(km)], im[P::pad(km)]};
-    const long oi = ob + (long)k * a.C + 2 * l;
-    a.out[oi] = {(z.x + zm.x) * half, (z.y - zm.y) * half};
-    if (2 * l + 1 < ncol) a.out[oi + 1] = {(z.y + zm.y) * half, (zm.x - z.x) * half};
-  }
+  hermitian_split_out<T, M, E>(lds, a.out + (long)o * a.out_os + col0, a.C, a.W, a.lw, a.PO,
+                               a.LS, ncol);
 }
 
 // ---------------------------------------------------------------------------
@@ -849,6 +859,10 @@ struct SineArgs {
   // state whose stopping test and beta every block evaluates first
   T* pdir;
   CgScalars cg;
+  // FIRST kernels (DIRF too): the product's axis-0 forward pass of the new p
+  // on the same tile, into T1 [nrhs][M/2+1][C] complex (t1_os per RHS)
+  cx<T>* t1;
+  long t1_os;
 };
 
 // Strided sine pass along the row axis of [outer][n][C]: each block owns 2W
@@ -858,8 +872,12 @@ struct SineArgs {
 // the next CG iteration (cg_begin: stopping test and beta, the same decision
 // in every block of the right-hand side) and writes p = z + beta p instead
 // of z, so z is never stored (the old p is loaded with the input tile).
-template <typename T, int M, int E, bool DIRF>
+// FIRST: the tile's new p then goes on through the product's first pass
+// (zero-padded forward transform along axis 0 and Hermitian split into T1),
+// so that pass does not read p back.
+template <typename T, int M, int E, bool DIRF, bool FIRST>
 __global__ void __launch_bounds__(512) k_sine_cols(SineArgs<T> a) {
+  static_assert(DIRF || !FIRST, "the fused first pass follows the direction update");
   using P = Plan<M, E>;
   constexpr int TPL = P::TPL;
   extern __shared__ unsigned char smem_raw[];
@@ -917,20 +935,44 @@ __global__ void __launch_bounds__(512) k_sine_cols(SineArgs<T> a) {
   // positions 1..n: first column of a pair from the imaginary plane, second
   // from the negated real plane
   double acc = 0.0;
+  T pnew[FIRST ? E : 1];
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int e = threadIdx.x + j * nthr;
     const int row = e >> lw1, cc = e & (W2 - 1);
+    if constexpr (FIRST) pnew[j] = 0;
     if (e >= tot || cc >= ncol) continue;
     const T* ln = lds + (cc >> 1) * a.LS + P::pad(row + 1);
     const T v = (cc & 1) ? -ln[0] : ln[a.PO];
     const long i = base + (long)row * a.C + cc;
     if constexpr (DIRF) {
-      a.pdir[i] = v + bt * pold[j];
+      const T pv = v + bt * pold[j];
+      a.pdir[i] = pv;
+      if constexpr (FIRST) pnew[j] = pv;
     } else {
       a.out[i] = v;
       if (a.dot) acc += (double)a.partner[i] * (double)v;
     }
+  }
+  if constexpr (FIRST) {
+    // the new p as the first pass's input tile: rows [0, M/2), zero from n on
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int e = threadIdx.x + j * nthr;
+      const int row = e >> lw1, cc = e & (W2 - 1);
+      lds[(cc >> 1) * a.LS + (cc & 1) * a.PO + P::pad(row)] = pnew[j];
+    }
+    __syncthreads();
+    {
+      const int l = threadIdx.x / TPL, t = threadIdx.x % TPL;
+      T* lre = lds + l * a.LS;
+      line_in_lds<T, M, E, -1, 1, false>(lre, lre + a.PO, t, a.tw);
+    }
+    __syncthreads();
+    hermitian_split_out<T, M, E>(lds, a.t1 + o * a.t1_os + col0, a.C, a.W, a.lw, a.PO, a.LS,
+                                 ncol);
+    return;
   }
   if (DIRF || !a.dot) return;
   const double blk = block_sum(acc, red);
@@ -1208,12 +1250,15 @@ void launch_sine_cols(int M, int E, SineArgs<T> a, long outer, hipStream_t st) {
   a.LS = tl.LS;
   dim3 grid((unsigned)(a.ntiles * outer));
   const int threads = a.W * (M / E);
-  if (a.pdir) {
-    FL_DISPATCH(M, E, FL_LAUNCH((k_sine_cols<T, M, E, true>), grid, dim3(threads), tl.bytes, st,
-                                a));
+  if (a.pdir && a.t1) {
+    FL_DISPATCH(M, E, FL_LAUNCH((k_sine_cols<T, M, E, true, true>), grid, dim3(threads),
+                                tl.bytes, st, a));
+  } else if (a.pdir) {
+    FL_DISPATCH(M, E, FL_LAUNCH((k_sine_cols<T, M, E, true, false>), grid, dim3(threads),
+                                tl.bytes, st, a));
   } else {
-    FL_DISPATCH(M, E, FL_LAUNCH((k_sine_cols<T, M, E, false>), grid, dim3(threads), tl.bytes,
-                                st, a));
+    FL_DISPATCH(M, E, FL_LAUNCH((k_sine_cols<T, M, E, false, false>), grid, dim3(threads),
+                                tl.bytes, st, a));
   }
   check_launch("sine pass");
 }
