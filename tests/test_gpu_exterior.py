@@ -76,8 +76,9 @@ def test_exterior_lattice_1d(alpha, p, N):
     G = orc_gen(1, alpha, p, N)
     ref = oracle.exterior_lattice_1d(G, g1)
     scale = oracle.exterior_lattice_1d(np.abs(G), lambda x: np.abs(g1(x)))
-    assert (np.abs(b[0] - ref) <= 1e-11 * scale).all()
-    assert (np.abs(b[1] - 2.0 * ref) <= 2e-11 * scale).all()
+    print(f"  max |b - ref| / scale = {float((np.abs(b[0] - ref) / scale).max()):.2e}")
+    assert (np.abs(b[0] - ref) <= 1e-12 * scale).all()
+    assert (np.abs(b[1] - 2.0 * ref) <= 2e-12 * scale).all()
 
 
 @pytest.mark.parametrize("alpha,p,N", [(0.2, 1, 8), (1.0, 1, 16), (1.9, 1, 16), (1.4, 2, 16),
@@ -90,7 +91,8 @@ def test_exterior_lattice_2d(alpha, p, N):
     G = orc_gen(2, alpha, p, N)
     ref = oracle.exterior_lattice_2d(G, g2)
     scale = oracle.exterior_lattice_2d(np.abs(G), lambda a, c: np.abs(g2(a, c)))
-    assert (np.abs(b - ref) <= 1e-11 * scale).all(), float((np.abs(b - ref) / scale).max())
+    print(f"  max |b - ref| / scale = {float((np.abs(b - ref) / scale).max()):.2e}")
+    assert (np.abs(b - ref) <= 1e-12 * scale).all(), float((np.abs(b - ref) / scale).max())
 
 
 def test_exterior_tail_and_solve_term():
@@ -101,8 +103,12 @@ def test_exterior_tail_and_solve_term():
     b = op.exterior(torch.from_numpy(lattice_2d(N, g2)[None].copy()).cuda(),
                     tail=torch.from_numpy(tail[None].copy()).cuda())
     G = orc_gen(2, alpha, 1, N)
-    ref = oracle.exterior_lattice_2d(G, g2) - oracle.c_dalpha(2, alpha) * tail
-    assert np.abs(b.cpu().numpy()[0] - ref).max() <= 1e-11 * np.abs(ref).max() * 1e2
+    c = oracle.c_dalpha(2, alpha)
+    ref = oracle.exterior_lattice_2d(G, g2) - c * tail
+    scale = oracle.exterior_lattice_2d(np.abs(G), lambda a, e: np.abs(g2(a, e))) + c * np.abs(tail)
+    err = np.abs(b.cpu().numpy()[0] - ref) / scale
+    print(f"  max |b - ref| / scale = {float(err.max()):.2e}")
+    assert (err <= 1e-12).all()
     f = torch.from_numpy(np.random.default_rng(3).uniform(-1, 1, (1, N - 1, N - 1))).cuda()
     u, info = op.solve(f, tol=1e-12, b=b)
     uc = oracle.solve_cholesky(G, f[0].cpu().numpy() - ref)
@@ -128,8 +134,9 @@ def test_exterior_lattice_3d(alpha, p, N):
     G = orc_gen(3, alpha, p, N)
     ref = oracle.exterior_lattice_3d(G, g3)
     scale = oracle.exterior_lattice_3d(np.abs(G), lambda a, c, e: np.abs(g3(a, c, e)))
-    assert (np.abs(b[0] - ref) <= 1e-11 * scale).all(), float((np.abs(b[0] - ref) / scale).max())
-    assert (np.abs(b[1] + 0.5 * ref) <= 1e-11 * scale).all()
+    print(f"  max |b - ref| / scale = {float((np.abs(b[0] - ref) / scale).max()):.2e}")
+    assert (np.abs(b[0] - ref) <= 1e-12 * scale).all(), float((np.abs(b[0] - ref) / scale).max())
+    assert (np.abs(b[1] + 0.5 * ref) <= 1e-12 * scale).all()
 
 
 @pytest.mark.parametrize("N", [600, 700, 1024])
@@ -150,8 +157,15 @@ def test_exterior_large_2d_sampled(N):
     scale = oracle.exterior_lattice_2d_at(np.abs(G), lambda a, c: np.abs(g2(a, c)), nodes)
     got = np.array([b[0][i - 1, j - 1] for i, j in nodes])
     got3 = np.array([b[1][i - 1, j - 1] for i, j in nodes])
-    assert (np.abs(got - ref) <= 1e-11 * scale).all(), float((np.abs(got - ref) / scale).max())
-    assert (np.abs(got3 - 3.0 * ref) <= 3e-11 * scale).all()
+    # the transform's rounding is spread over the whole lattice, so (as for
+    # the product) it is bounded relative to the largest summed magnitude,
+    # that of the nodes next to the boundary (among the samples), not each
+    # node's own: deep inside, the sum is small (N = 600: up to 2.8e-12 of a
+    # node's own magnitude)
+    top = scale.max()
+    print(f"  max |b - ref| / max scale = {float(np.abs(got - ref).max() / top):.2e}")
+    assert (np.abs(got - ref) <= 1e-12 * top).all(), float(np.abs(got - ref).max() / top)
+    assert (np.abs(got3 - 3.0 * ref) <= 3e-12 * top).all()
 
 
 @pytest.mark.parametrize("d,N", [(2, 512), (2, 1024), (3, 128)])
@@ -225,7 +239,8 @@ def test_exterior_box_parity(alpha, p, box):
     ref = lat(G, gfun, box)
     scale = lat(np.abs(G), lambda *x: np.abs(gfun(*x)), box)
     assert b.shape == ref.shape
-    assert (np.abs(b - ref) <= 1e-11 * scale).all(), float((np.abs(b - ref) / scale).max())
+    print(f"  max |b - ref| / scale = {float((np.abs(b - ref) / scale).max()):.2e}")
+    assert (np.abs(b - ref) <= 1e-12 * scale).all(), float((np.abs(b - ref) / scale).max())
 
 
 def test_exterior_box_block_form_sampled():
@@ -239,7 +254,8 @@ def test_exterior_box_block_form_sampled():
     ref = oracle.exterior_lattice_2d_at(G, g2s, nodes, box)
     scale = oracle.exterior_lattice_2d_at(np.abs(G), lambda a, c: np.abs(g2s(a, c)), nodes, box)
     got = np.array([b[i - 1, j - 1] for i, j in nodes])
-    assert (np.abs(got - ref) <= 1e-11 * scale).all(), float((np.abs(got - ref) / scale).max())
+    print(f"  max |b - ref| / scale = {float((np.abs(got - ref) / scale).max()):.2e}")
+    assert (np.abs(got - ref) <= 1e-12 * scale).all(), float((np.abs(got - ref) / scale).max())
 
 
 def test_exterior_box_solve():
