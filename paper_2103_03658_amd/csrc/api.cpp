@@ -1040,15 +1040,18 @@ inline int iterations_to(double rr, double target, double rate) {
 // iteration count plus the one that detects convergence (8 on the first
 // solve).  Chunks are composed of captured graphs of 16, 8, 4, 2 and 1
 // iterations; iterations of stopped right-hand sides are masked no-ops.
+// detect: iterations after the last useful one needed to detect
+// convergence (1 when the stopping test runs at the iteration start, 0 with
+// the split tau preconditioner, which tests at the end of the iteration).
 template <typename F>
 void predictive_loop(fl_op A, const std::vector<double>& key, int cap, const fl::CgScalars& cg,
-                     int nrhs, hipStream_t st, F&& enqueue_one) {
+                     int nrhs, hipStream_t st, int detect, F&& enqueue_one) {
   double* dpoll = nullptr;
   size_t pb = 0;
   const double* h = poll_buffers(A, nrhs, &dpoll, &pb);
   std::vector<double> rr_prev(nrhs, 0.0);
   std::vector<int> it_prev(nrhs, 0);
-  int done = 0, next = A->iter_hint > 0 ? std::min(A->iter_hint + 1, 16) : 8;
+  int done = 0, next = A->iter_hint > 0 ? std::min(A->iter_hint + detect, 16) : 8;
   int max_it = 0;
   while (done < cap) {
     const int k = std::min(next, cap - done);
@@ -1071,8 +1074,8 @@ void predictive_loop(fl_op A, const std::vector<double>& key, int cap, const fl:
       double rate = 0.0;
       if (rr_prev[o] > 0.0 && it > it_prev[o] && rr > 0.0)
         rate = std::pow(rr / rr_prev[o], 1.0 / (it - it_prev[o]));
-      // plus the iteration whose start detects convergence
-      need = std::max(need, iterations_to(rr, th, rate) + 1);
+      // plus the iteration whose start detects convergence (detect = 1)
+      need = std::max(need, iterations_to(rr, th, rate) + detect);
       rr_prev[o] = rr;
       it_prev[o] = it;
     }
@@ -1097,7 +1100,7 @@ template <typename F, typename G>
 void predictive_mixed_loop(fl_op A, const std::vector<double>& key, int maxiter,
                            const fl::CgScalars& cg, int nrhs, const double* rr_last,
                            const double* f2, const int* nupd, double delta2, double tol2,
-                           hipStream_t st, F&& enqueue_one, G&& enqueue_reliable) {
+                           hipStream_t st, int detect, F&& enqueue_one, G&& enqueue_reliable) {
   double* dpoll = nullptr;
   size_t pb = 0;
   const double* h = poll_buffers(A, nrhs, &dpoll, &pb);
@@ -1105,7 +1108,8 @@ void predictive_mixed_loop(fl_op A, const std::vector<double>& key, int maxiter,
   std::vector<int> it_ref(nrhs, 0), nu_ref(nrhs, 0);
   int next = 8;
   if (A->mixed_rate > 0.0 && A->mixed_rate < 0.95)
-    next = std::min(std::max(iterations_to(1.0, std::max(delta2, tol2), A->mixed_rate) + 1, 1), 16);
+    next = std::min(std::max(iterations_to(1.0, std::max(delta2, tol2), A->mixed_rate) + detect, 1),
+                    16);
   std::vector<double> krel = key;
   krel.push_back(-1.0);
   double slowest = 0.0;
@@ -1143,8 +1147,8 @@ void predictive_mixed_loop(fl_op A, const std::vector<double>& key, int maxiter,
       }
       slowest = std::max(slowest, rate[o]);
       const double target = std::max(delta2 * rl, tol2 * ff);
-      // plus the iteration whose start detects the trigger
-      need = std::max(need, iterations_to(rr, target, rate[o]) + 1);
+      // plus the iteration whose start detects the trigger (detect = 1)
+      need = std::max(need, iterations_to(rr, target, rate[o]) + detect);
       rr_ref[o] = rr;
       it_ref[o] = it;
       nu_ref[o] = nu;
@@ -1194,7 +1198,7 @@ void cg_start(fl_op A, const fl::Schedule& sc, const T* linv, const fl::Twiddles
   fl::fill_int(cg.n_active, 0, 1, st);
   fl::cg_init<T>(A->g, rhs, x, r, p, nrhs, cg, outer_active, st);
   if (S1)
-    fl::tau_front<T>(A->g, pc_sched<T>(A), linv, tw, r, S1, nrhs, st, cg, cg.active);
+    fl::tau_front<T>(A->g, pc_sched<T>(A), linv, tw, r, S1, nrhs, st, cg, cg.active, true);
   else if (cg.precond)
     precond_apply<T>(A, linv, tw, r, z, nrhs, ws, cg, cg.active, st);
 }
@@ -1214,7 +1218,7 @@ void cg_iteration(fl_op A, const fl::Schedule& sc, const T* lam, const T* linv, 
     fl::apply_passes<T>(A->g, sc, lam, tw, p, q, nrhs, ws, st, fl::PM_PQ, nullptr, nullptr,
                         nullptr, &cg, cg.active, nullptr, -1, false, true);
     fl::cg_update<T>(A->g, x, r, p, q, nrhs, cg, st);
-    fl::tau_front<T>(A->g, pc_sched<T>(A), linv, tw, r, S1, nrhs, st, cg, cg.active);
+    fl::tau_front<T>(A->g, pc_sched<T>(A), linv, tw, r, S1, nrhs, st, cg, cg.active, true);
     return;
   }
   if (A->g.d >= 2) {
@@ -1409,7 +1413,7 @@ static fl_status solve_body(fl_op A, const double* f, const double* b, double to
         key.push_back(v);
       for (double v : sched_key(A->sc64)) key.push_back(v);
       for (double v : sched_key(A->sp64)) key.push_back(v);
-      predictive_loop(A, key, maxiter + 2, cg, nrhs, st, [&]() {
+      predictive_loop(A, key, maxiter + 2, cg, nrhs, st, S1 ? 0 : 1, [&]() {
         cg_iteration<double>(A, A->sc64, A->lam64, pc_symbol<double>(A), A->tw64, x, r, p, q, z,
                              nrhs, cg, ws, st, S1);
       });
@@ -1476,7 +1480,7 @@ static fl_status solve_body(fl_op A, const double* f, const double* b, double to
     for (double v : sched_key(A->sp32)) key.push_back(v);
     for (double v : sched_key(A->sc64)) key.push_back(v);
     predictive_mixed_loop(
-        A, key, maxiter, cg, nrhs, rr_last, f2, nupd, delta2, tol * tol, st,
+        A, key, maxiter, cg, nrhs, rr_last, f2, nupd, delta2, tol * tol, st, S1 ? 0 : 1,
         [&]() {
           cg_iteration<float>(A, A->sc32, A->lam32, pc_symbol<float>(A), A->tw32, xlo, r32, p32,
                               q32, z32, nrhs, cg, ws, st, S1);
@@ -1491,7 +1495,7 @@ static fl_status solve_body(fl_op A, const double* f, const double* b, double to
           // into S1, which the FP64 residual's passes above do not touch)
           if (S1)
             fl::tau_front<float>(A->g, A->sp32, pc_symbol<float>(A), A->tw32, r32, S1, nrhs, st,
-                                 cg, trig);
+                                 cg, trig, false);
           else if (pc)
             precond_apply<float>(A, pc_symbol<float>(A), A->tw32, r32, z32, nrhs, ws, cg, trig,
                                  st);

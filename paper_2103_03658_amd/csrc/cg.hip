@@ -257,6 +257,15 @@ __global__ void __launch_bounds__(VT) k_reliable_replace(const double* r64, floa
     }
     return;
   }
+  // the iteration cap, which the recursion's own test would apply at its
+  // next check: the FP64 iterate and residual are final
+  if (cg.iters[o] >= cg.maxiter) {
+    if (lead) {
+      cg.status[o] = 5;
+      trig[o] = 0;
+    }
+    return;
+  }
   if (lead) {
     cg.active[o] = 1;
     atomicAdd(cg.n_active, 1);

@@ -200,9 +200,14 @@ void apply_passes(const Geometry& g, const Schedule& sc, const T* lam, const Twi
 // product's schedule sc; sp is the preconditioner's), so the product follows
 // with apply_passes(..., first_done = true).  Only when sine_mid_blocks <=
 // max_blocks.
+// stop_test: tau_front's first pass begins with the end-of-iteration tests
+// on r.r (tolerance, maxiter, non-finite, the reliable-update trigger), and
+// tau_back_direction then tests r.z and forms beta; without it (after a
+// reliable update) no test runs before the next iteration.
 template <typename T>
 void tau_front(const Geometry& g, const Schedule& sc, const T* m, const Twiddles& tw, const T* r,
-               T* S1, int nrhs, hipStream_t st, const CgScalars& cg, const int* active);
+               T* S1, int nrhs, hipStream_t st, const CgScalars& cg, const int* active,
+               bool stop_test);
 template <typename T>
 void tau_back_direction(const Geometry& g, const Schedule& sc, const Schedule& sp,
                         const Twiddles& tw, T* S1, T* p, void* T1, int nrhs, hipStream_t st,

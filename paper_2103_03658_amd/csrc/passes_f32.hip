@@ -16,8 +16,8 @@ void apply_passes<float>(const Geometry& g, const Schedule& sc, const float* lam
 template <>
 void tau_front<float>(const Geometry& g, const Schedule& sc, const float* m, const Twiddles& tw,
                      const float* r, float* S1, int nrhs, hipStream_t st, const CgScalars& cg,
-                     const int* active) {
-  tau_front_t<float>(g, sc, m, tw, r, S1, nrhs, st, cg, active);
+                     const int* active, bool stop_test) {
+  tau_front_t<float>(g, sc, m, tw, r, S1, nrhs, st, cg, active, stop_test);
 }
 
 template <>

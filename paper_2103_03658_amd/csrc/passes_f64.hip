@@ -20,8 +20,8 @@ void apply_passes<double>(const Geometry& g, const Schedule& sc, const double* l
 template <>
 void tau_front<double>(const Geometry& g, const Schedule& sc, const double* m, const Twiddles& tw,
                      const double* r, double* S1, int nrhs, hipStream_t st, const CgScalars& cg,
-                     const int* active) {
-  tau_front_t<double>(g, sc, m, tw, r, S1, nrhs, st, cg, active);
+                     const int* active, bool stop_test) {
+  tau_front_t<double>(g, sc, m, tw, r, S1, nrhs, st, cg, active, stop_test);
 }
 
 template <>

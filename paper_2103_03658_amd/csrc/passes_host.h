@@ -132,7 +132,7 @@ void apply_passes_t(const Geometry& g, const Schedule& sc, const T* lam, const T
 template <typename T>
 void tau_front_t(const Geometry& g, const Schedule& sc, const T* m, const Twiddles& twv,
                  const T* r, T* S1, int nrhs, hipStream_t st, const CgScalars& c,
-                 const int* active) {
+                 const int* active, bool stop_test) {
   if (g.d < 2 || !g.sine_ok() || sine_mid_blocks(g, sc) > c.max_blocks)
     throw Error(2, "split tau preconditioner: d >= 2, 2N a power of two, mid-pass partials");
   const int n0 = g.na[0], n1 = g.na[1], n2 = g.na[2];
@@ -141,9 +141,11 @@ void tau_front_t(const Geometry& g, const Schedule& sc, const T* m, const Twiddl
   const cx<T>* tw1 = reinterpret_cast<const cx<T>*>(twv.ax[1]);
   const cx<T>* tw2 = reinterpret_cast<const cx<T>*>(twv.ax[2]);
   const long C0 = (long)n1 * n2, nd = g.nd;
+  // stop_test: the first pass begins with the end-of-iteration tests on r.r
+  // (cg_stop_rr: a right-hand side that stops is not preconditioned again)
   SineArgs<T> a0{r, S1, nullptr, active, nullptr, 0, C0, nd, 0, 1, n0,
-                 sc.W_first, 0, 0, 0, 0, tw0};
-  launch_sine_cols<T>(M0, sc.E_first, a0, nrhs, st);
+                 sc.W_first, 0, 0, 0, 0, tw0, nullptr, c};
+  launch_sine_cols<T>(M0, sc.E_first, a0, nrhs, st, stop_test);
   if (g.d == 3) {
     SineArgs<T> a1{S1, S1, nullptr, active, nullptr, 0, n2, (long)n1 * n2, 0, n0, n1,
                    sc.W_c2c, 0, 0, 0, 0, tw1};

@@ -129,6 +129,69 @@ __device__ __forceinline__ bool cg_begin(const CgScalars& cg, int o, bool lead, 
   return stop;
 }
 
+// The iteration start split in two for the tau-preconditioned CG (the
+// decisions and state of cg_begin, in its order).  cg_stop_rr runs at the
+// end of an iteration, in the pass that starts z = P r: the tests on r.r
+// (non-finite, r_0 = 0, the reliable-update trigger, the tolerance,
+// maxiter), so that a right-hand side that stops is not preconditioned
+// again.  cg_beta_rho runs in the pass that finishes z: the tests on r.z
+// (non-finite, r.z <= 0 after the first iteration) and beta.
+__device__ __forceinline__ bool cg_stop_rr(const CgScalars& cg, int o, bool lead, double* sh) {
+  const double rr = sum_partials(cg.part_c + (long)o * cg.max_blocks, cg.nb_c, sh);
+  const int it = cg.iters[o];
+  bool stop = false, pending = false;
+  int status = 0;
+  if (!isfinite(rr)) {
+    stop = true;
+    status = 6;
+  } else if (it == 0) {
+    stop = rr == 0.0;
+  } else if (cg.rel_trig &&
+             (!(rr >= cg.rel_delta2 * cg.rel_last[o]) || rr <= cg.rel_tol2 * cg.rel_f2[o])) {
+    stop = pending = true;   // wait for the reliable update
+  } else if (rr <= cg.thresh2[o]) {
+    stop = true;
+  } else if (it >= cg.maxiter) {
+    stop = true;
+    status = 5;
+  }
+  if (lead && threadIdx.x == 0) {
+    cg.res2[o] = rr;
+    if (cg.rel_trig) cg.rel_trig[o] = pending ? 1 : 0;
+    if (it == 0) cg.thresh2[o] = cg.tol2 * rr;
+    if (stop) {
+      cg.active[o] = 0;
+      cg.status[o] = status;
+      atomicSub(cg.n_active, 1);
+    }
+  }
+  return stop;
+}
+
+__device__ __forceinline__ bool cg_beta_rho(const CgScalars& cg, int o, bool lead, double* sh,
+                                            double* beta) {
+  const double rho = sum_partials(cg.part_b + (long)o * cg.max_blocks, cg.nb_b, sh);
+  const int it = cg.iters[o];
+  bool stop = false;
+  double b = 0.0;
+  if (!isfinite(rho)) {
+    stop = true;
+  } else if (it > 0) {
+    if (!(rho > 0.0)) stop = true;   // r.z <= 0: the preconditioned iteration broke down
+    else b = rho / cg.rr_prev[o];
+  }
+  if (lead && threadIdx.x == 0) {
+    cg.rr_cur[o] = rho;
+    if (stop) {
+      cg.active[o] = 0;
+      cg.status[o] = 6;
+      atomicSub(cg.n_active, 1);
+    }
+  }
+  *beta = b;
+  return stop;
+}
+
 // Logical (tile, outer) of this block: hardware places block b on XCD b % 8;
 // XCD x is given the contiguous logical range starting at x*q + min(x, r).
 __device__ __forceinline__ void xcd_tile(long ntiles, long& tile, long& outer) {
@@ -874,10 +937,13 @@ struct SineArgs {
 // of z, so z is never stored (the old p is loaded with the input tile).
 // FIRST: the tile's new p then goes on through the product's first pass
 // (zero-padded forward transform along axis 0 and Hermitian split into T1),
-// so that pass does not read p back.
-template <typename T, int M, int E, bool DIRF, bool FIRST>
+// so that pass does not read p back.  STOP (the pass that starts z = P r):
+// the end-of-iteration tests on r.r first (cg_stop_rr); DIRF then takes only
+// the tests on r.z and beta (cg_beta_rho).
+template <typename T, int M, int E, bool DIRF, bool FIRST, bool STOP>
 __global__ void __launch_bounds__(512) k_sine_cols(SineArgs<T> a) {
   static_assert(DIRF || !FIRST, "the fused first pass follows the direction update");
+  static_assert(!(DIRF && STOP), "one test per pass");
   using P = Plan<M, E>;
   constexpr int TPL = P::TPL;
   extern __shared__ unsigned char smem_raw[];
@@ -895,8 +961,11 @@ __global__ void __launch_bounds__(512) k_sine_cols(SineArgs<T> a) {
   T bt = 0;
   if constexpr (DIRF) {
     double beta;
-    if (cg_begin(a.cg, (int)o, tile == 0, red, &beta)) return;
+    if (cg_beta_rho(a.cg, (int)o, tile == 0, red, &beta)) return;
     bt = (T)beta;
+  }
+  if constexpr (STOP) {
+    if (cg_stop_rr(a.cg, (int)o, tile == 0, red)) return;
   }
   const int tot = a.n * W2;
   T pold[DIRF ? E : 1];
@@ -1237,7 +1306,8 @@ void launch_rows(int M, int E, int dir, cx<T>* data, long rows, int LPB, const c
 }
 
 template <typename T>
-void launch_sine_cols(int M, int E, SineArgs<T> a, long outer, hipStream_t st) {
+void launch_sine_cols(int M, int E, SineArgs<T> a, long outer, hipStream_t st,
+                      bool stop_test = false) {
   if (!pow2(a.W) || a.n != M / 2 - 1) throw Error(2, "sine pass: bad tile width or rows");
   a.ntiles = pair_tiles(a.C, a.W);
   if (a.dot && (a.ntiles > a.max_blocks || a.outer_per_rhs != 1))
@@ -1251,13 +1321,17 @@ void launch_sine_cols(int M, int E, SineArgs<T> a, long outer, hipStream_t st) {
   dim3 grid((unsigned)(a.ntiles * outer));
   const int threads = a.W * (M / E);
   if (a.pdir && a.t1) {
-    FL_DISPATCH(M, E, FL_LAUNCH((k_sine_cols<T, M, E, true, true>), grid, dim3(threads),
+    FL_DISPATCH(M, E, FL_LAUNCH((k_sine_cols<T, M, E, true, true, false>), grid, dim3(threads),
                                 tl.bytes, st, a));
   } else if (a.pdir) {
-    FL_DISPATCH(M, E, FL_LAUNCH((k_sine_cols<T, M, E, true, false>), grid, dim3(threads),
+    FL_DISPATCH(M, E, FL_LAUNCH((k_sine_cols<T, M, E, true, false, false>), grid, dim3(threads),
+                                tl.bytes, st, a));
+  } else if (stop_test) {
+    if (a.dot || a.outer_per_rhs != 1) throw Error(2, "sine pass: the stop test needs one slice per RHS");
+    FL_DISPATCH(M, E, FL_LAUNCH((k_sine_cols<T, M, E, false, false, true>), grid, dim3(threads),
                                 tl.bytes, st, a));
   } else {
-    FL_DISPATCH(M, E, FL_LAUNCH((k_sine_cols<T, M, E, false, false>), grid, dim3(threads),
+    FL_DISPATCH(M, E, FL_LAUNCH((k_sine_cols<T, M, E, false, false, false>), grid, dim3(threads),
                                 tl.bytes, st, a));
   }
   check_launch("sine pass");
