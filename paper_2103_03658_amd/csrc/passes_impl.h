@@ -958,16 +958,9 @@ __global__ void __launch_bounds__(512) k_sine_cols(SineArgs<T> a) {
   const long cl = a.C - col0;
   const int ncol = cl < W2 ? (int)cl : W2;
   const long base = o * a.os + col0;
-  T bt = 0;
-  if constexpr (DIRF) {
-    double beta;
-    if (cg_beta_rho(a.cg, (int)o, tile == 0, red, &beta)) return;
-    bt = (T)beta;
-  }
-  if constexpr (STOP) {
-    if (cg_stop_rr(a.cg, (int)o, tile == 0, red)) return;
-  }
   const int tot = a.n * W2;
+  // the tile's loads are issued before the iteration tests, whose partial
+  // sums then wait on them together
   T pold[DIRF ? E : 1];
   if constexpr (DIRF) {
 #pragma unroll
@@ -978,15 +971,26 @@ __global__ void __launch_bounds__(512) k_sine_cols(SineArgs<T> a) {
     }
   }
   // rows [0, M/2) of the tile: (M/2) * 2W elements, exactly E per thread
-  {
-    T x[E];
+  T x[E];
 #pragma unroll
-    for (int j = 0; j < E; ++j) {
-      const int e = threadIdx.x + j * nthr;
-      const int row = e >> lw1, cc = e & (W2 - 1);
-      const int src = row - 1;
-      x[j] = (src >= 0 && src < a.n && cc < ncol) ? a.in[base + (long)src * a.C + cc] : (T)0;
-    }
+  for (int j = 0; j < E; ++j) {
+    const int e = threadIdx.x + j * nthr;
+    const int row = e >> lw1, cc = e & (W2 - 1);
+    const int src = row - 1;
+    x[j] = (src >= 0 && src < a.n && cc < ncol) ? a.in[base + (long)src * a.C + cc] : (T)0;
+  }
+  T bt = 0;
+  if constexpr (DIRF) {
+    double beta;
+    if (cg_beta_rho(a.cg, (int)o, tile == 0, red, &beta)) return;
+    bt = (T)beta;
+  }
+  if constexpr (STOP) {
+    // only the right-hand side's lead block takes the decision; the others
+    // transform their tiles anyway (nothing reads them if it stops)
+    if (tile == 0 && cg_stop_rr(a.cg, (int)o, true, red)) return;
+  }
+  {
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const int e = threadIdx.x + j * nthr;
