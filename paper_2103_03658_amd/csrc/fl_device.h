@@ -233,8 +233,78 @@ struct Plan {
   __device__ static __forceinline__ int pad(int i) { return i + (i >> LOGE); }
 };
 
+// Cross-lane exchanges of a wave's registers (gfx950 lane-swap instructions).
+// For a register pair (a, b) that differs in one register bit:
+//   permlane32_swap: lanes 32..63 of a <-> lanes 0..31 of b, which swaps lane
+//     bit 5 with that register bit;
+//   permlane16_swap: odd rows (16 lanes) of a <-> even rows of b, which swaps
+//     lane bit 4 with that register bit.
+// Each 32-bit word of a value goes through its own instruction.
+template <typename V>
+__device__ __forceinline__ void lane_swap32(V& a, V& b) {
+  constexpr int W = sizeof(V) / 4;
+  uint32_t wa[W], wb[W];
+  __builtin_memcpy(wa, &a, sizeof(V));
+  __builtin_memcpy(wb, &b, sizeof(V));
+#pragma unroll
+  for (int i = 0; i < W; ++i) {
+    const auto r = __builtin_amdgcn_permlane32_swap(wa[i], wb[i], false, false);
+    wa[i] = r[0];
+    wb[i] = r[1];
+  }
+  __builtin_memcpy(&a, wa, sizeof(V));
+  __builtin_memcpy(&b, wb, sizeof(V));
+}
+template <typename V>
+__device__ __forceinline__ void lane_swap16(V& a, V& b) {
+  constexpr int W = sizeof(V) / 4;
+  uint32_t wa[W], wb[W];
+  __builtin_memcpy(wa, &a, sizeof(V));
+  __builtin_memcpy(wb, &b, sizeof(V));
+#pragma unroll
+  for (int i = 0; i < W; ++i) {
+    const auto r = __builtin_amdgcn_permlane16_swap(wa[i], wb[i], false, false);
+    wa[i] = r[0];
+    wb[i] = r[1];
+  }
+  __builtin_memcpy(&a, wa, sizeof(V));
+  __builtin_memcpy(&b, wb, sizeof(V));
+}
+
+// The exchange before the last stage of a line held by exactly one wave
+// (TPL = 64), when the previous stages span Lp >= 16 elements.  With t =
+// Lp h + c, the previous stage leaves element h Lp E + r Lp + c in lane t,
+// register r; the last stage (radix R = 64/Lp) wants in lane t, slot q R + j
+// the element t + 64 q + j M/R, which lane Lp j + c holds in register q R + h.
+// So the lane bits above log2 Lp trade places with the low register bits:
+// lane bits 4, 5 with register bits 0, 1 (Lp = 16), or lane bit 5 with
+// register bit 0 (Lp = 32).  No LDS and no barrier.
+template <int M, int E, int s>
+struct LaneExchange {
+  using P = Plan<M, E>;
+  static constexpr bool ok = s == P::S - 1 && P::TPL == 64 && P::radix(s - 1) == E &&
+                             (P::ls(s - 1) == 16 || P::ls(s - 1) == 32);
+};
+
+template <typename T, int E, int LP>
+__device__ __forceinline__ void lane_exchange(cx<T> (&v)[E]) {
+  if constexpr (LP == 16) {
+#pragma unroll
+    for (int r = 0; r < E; ++r)
+      if ((r & 2) == 0) lane_swap32(v[r], v[r + 2]);
+#pragma unroll
+    for (int r = 0; r < E; ++r)
+      if ((r & 1) == 0) lane_swap16(v[r], v[r + 1]);
+  } else {
+#pragma unroll
+    for (int r = 0; r < E; ++r)
+      if ((r & 1) == 0) lane_swap32(v[r], v[r + 1]);
+  }
+}
+
 // One Stockham stage s >= 1: exchange the previous stage's outputs through
-// LDS, then twiddle and DFT.  lre/lim: this line's LDS planes; ONE: a single
+// LDS (or, before the last stage of a one-wave line, across lanes), then
+// twiddle and DFT.  lre/lim: this line's LDS planes; ONE: a single
 // plane (lre) carries the real and then the imaginary parts (half the LDS
 // of a line, so more lines fit a CU, for two more barriers per stage).
 // Twiddles: of the R - 1 factors w^j (w = e^{-2 pi i k / (Ls R)}) only
@@ -260,41 +330,45 @@ __device__ __forceinline__ void stockham_stage(cx<T> (&v)[E], T* lre, T* lim, in
 #pragma unroll
     for (int bit = 0; bit < LR; ++bit) pw[q][bit] = tw[i1 << bit];
   }
+  if constexpr (LaneExchange<M, E, s>::ok) {
+    lane_exchange<T, E, Lp>(v);
+  } else {
 #pragma unroll
-  for (int part = 0; part < (ONE ? 2 : 1); ++part) {
-    __syncthreads();
+    for (int part = 0; part < (ONE ? 2 : 1); ++part) {
+      __syncthreads();
 #pragma unroll
-    for (int q = 0; q < E / Rp; ++q) {
-      const int b = t + q * TPL;
-      const int k = b & (Lp - 1);
+      for (int q = 0; q < E / Rp; ++q) {
+        const int b = t + q * TPL;
+        const int k = b & (Lp - 1);
 #pragma unroll
-      for (int r = 0; r < Rp; ++r) {
-        const int o = P::pad((b - k) * Rp + k + r * Lp);
-        if (!ONE || part == 0) lre[o] = v[q * Rp + r].x;
-        if (!ONE) lim[o] = v[q * Rp + r].y;
-        if (ONE && part == 1) lre[o] = v[q * Rp + r].y;
+        for (int r = 0; r < Rp; ++r) {
+          const int o = P::pad((b - k) * Rp + k + r * Lp);
+          if (!ONE || part == 0) lre[o] = v[q * Rp + r].x;
+          if (!ONE) lim[o] = v[q * Rp + r].y;
+          if (ONE && part == 1) lre[o] = v[q * Rp + r].y;
+        }
       }
-    }
-    __syncthreads();
-    T nx[E], ny[E];
+      __syncthreads();
+      T nx[E], ny[E];
 #pragma unroll
-    for (int q = 0; q < E / R; ++q) {
-      const int b = t + q * TPL;
+      for (int q = 0; q < E / R; ++q) {
+        const int b = t + q * TPL;
 #pragma unroll
-      for (int j = 0; j < R; ++j) {
-        const int i = P::pad(b + j * (M / R));
-        nx[q * R + j] = lre[i];
-        if (!ONE) ny[q * R + j] = lim[i];
+        for (int j = 0; j < R; ++j) {
+          const int i = P::pad(b + j * (M / R));
+          nx[q * R + j] = lre[i];
+          if (!ONE) ny[q * R + j] = lim[i];
+        }
       }
-    }
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      if (!ONE) {
-        v[e] = {nx[e], ny[e]};
-      } else if (part == 0) {
-        v[e].x = nx[e];
-      } else {
-        v[e].y = nx[e];
+      for (int e = 0; e < E; ++e) {
+        if (!ONE) {
+          v[e] = {nx[e], ny[e]};
+        } else if (part == 0) {
+          v[e].x = nx[e];
+        } else {
+          v[e].y = nx[e];
+        }
       }
     }
   }
