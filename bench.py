@@ -67,6 +67,11 @@ METRIC = ("CG solves/s + p50/p99 latency (2D 511², tol 1e-10); "
           "FFT-matvec HBM GB/s")
 
 
+def progress(msg):
+    """One line per finished phase on stderr (the JSON line goes to stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -79,9 +84,9 @@ def parse():
     ap.add_argument("--path", choices=["reliable", "refine", "fp64"], default="fp64",
                     help="reliable: FP32 CG with FP64 reliable updates; refine: restarted FP32 "
                          "inner solves with FP64 refinement; fp64: FP64 CG")
-    ap.add_argument("--mixed-steps", type=int, default=3,
+    ap.add_argument("--mixed-steps", type=int, default=None,
                     help="timed batched solves of the mixed-precision path reported beside the "
-                         "headline path (0: skip)")
+                         "headline path, after the same warm-up (default: --steps; 0: skip)")
     ap.add_argument("--delta", type=float, default=None,
                     help="reliable path: residual reduction that triggers an FP64 update")
     ap.add_argument("--inner-tol", type=float, default=None,
@@ -448,6 +453,7 @@ def serving_legs(args):
         return None
     out = run_serving(args.serve_requests, args.serve_workers, args.tol, mixed=1,
                       sample=args.serve_sample)
+    progress("serving stream (mixed) done")
     if args.serve_fp64:
         out["fp64"] = run_serving(args.serve_requests, args.serve_workers, args.tol, mixed=0,
                                   sample=args.serve_sample)
@@ -563,6 +569,7 @@ def main():
         lat.append(time.perf_counter() - ts)
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
+    progress(f"headline: {args.steps * nrhs / total:.1f} solves/s")
     solves = args.steps * nrhs
     value = solves / total
     max_relres = max(i["relres_true"] for inf in infos for i in inf)
@@ -597,26 +604,34 @@ def main():
         fp64["mixed_vs_fp64_rel_linf"] = max(diffs)
 
     # the mixed-precision path (FP32 CG, FP64 reliable updates) on the same batches
+    # timed like the headline path: the same warm-up steps (every operator's
+    # first mixed solve captures its graphs), then the same number of steps
     mixed_res = None
-    if args.mixed_steps > 0 and mixed != 1:
+    msteps = args.steps if args.mixed_steps is None else args.mixed_steps
+    if msteps > 0 and mixed != 1:
         def mstep(k):
             a = alphas[k % len(alphas)]
             return ops[a].solve(rhs[a], tol=args.tol, mixed=1, out=out)[1]
-        mstep(0)
+        for k in range(max(args.warmup, len(alphas))):
+            mstep(k)
         torch.cuda.synchronize()
         mlat, minf = [], []
         t0m = time.perf_counter()
-        for k in range(args.mixed_steps):
+        for k in range(msteps):
             ts = time.perf_counter()
             minf.append(mstep(k))
             mlat.append(time.perf_counter() - ts)
         torch.cuda.synchronize()
         tm = time.perf_counter() - t0m
-        mixed_res = {"solves_per_s": args.mixed_steps * nrhs / tm,
+        mixed_res = {"solves_per_s": msteps * nrhs / tm, "steps": msteps,
                      "p50_ms": float(np.percentile(np.array(mlat) * 1e3, 50)),
+                     "p99_ms": float(np.percentile(np.array(mlat) * 1e3, 99)),
                      "max_relres_true": max(i["relres_true"] for inf in minf for i in inf),
-                     "iters": {alphas[k % 3]: max(i["iters"] for i in minf[k])
-                               for k in range(min(3, args.mixed_steps))},
+                     "iters": {alphas[k % 3]: [i["iters"] for i in minf[k]]
+                               for k in range(min(3, msteps))},
+                     "outer_iters": {alphas[k % 3]: [i["outer_iters"] for i in minf[k]]
+                                     for k in range(min(3, msteps))},
+                     "vs_fp64_batched": msteps * nrhs / tm / value,
                      "path": "FP32 CG with FP64 reliable updates"}
 
     # roofline of the dominant kernel of the timed path: per-pass durations
@@ -638,6 +653,7 @@ def main():
                 for nm, t, b, f in zip(names, ms_, by_, fl_)]
 
     pk64, pk32 = passes(False), passes(True)
+    progress("product passes timed")
 
     # the tau preconditioner's kernels (same operator, schedule and batch)
     pnames = ["tau_axis0_sine", "tau_last_axis_sine_mult_sine", "tau_axis0_sine_back"]
@@ -682,12 +698,18 @@ def main():
             "matvec_ms_f32": sum(k["ms"] for k in pk32),
             "precond_per_kernel_f64": pp64, "precond_per_kernel_f32": pp32,
             "precond_ms_f64": sum(k["ms"] for k in pp64),
-            "precond_ms_f32": sum(k["ms"] for k in pp32)}
+            "precond_ms_f32": sum(k["ms"] for k in pp32),
+            # time of each FP32 pass over its FP64 twin (0.5 = the byte ratio)
+            "f32_over_f64": {k64["kernel"]: k32["ms"] / k64["ms"]
+                             for k64, k32 in zip(pk64 + pp64, pk32 + pp32)}}
 
     configs = run_configs(dev, args.tol) if args.configs else None
+    progress("configs done")
     d2 = d2_shapes(dev, reps=args.profile_reps) if args.d2 else None
+    progress("large working sets done")
 
     serving = serving_legs(args)
+    progress("serving done")
 
     cpu = None
     if args.cpu_budget > 0:
