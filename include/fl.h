@@ -397,12 +397,16 @@ fl_status fl_profile_precond(fl_op A, const void *u, void *y, int nrhs, int fp32
 
 /*
  * Preconditioning of fl_solve (the paper names no solver; A is SPD, Sec. 2.2):
- *   kind 2 (default when 2N is a power of two): P = tau(A)^{-1}, the
- *     inverse of the natural tau approximation of the multilevel Toeplitz
- *     matrix (A minus its Hankel part on every level), diagonalised by the
- *     sine transform of each axis and applied by real sine passes (DST-I of
- *     every axis through the length-2N transform of odd-extended line
- *     pairs); FL_E_UNSUPPORTED when 2N is not a power of two;
+ *   kind 2 (the default where available): P = tau(A)^{-1}, the inverse of
+ *     the natural tau approximation of the multilevel Toeplitz matrix (A
+ *     minus its Hankel part on every level), diagonalised by the sine
+ *     transform of each axis and applied by real sine passes (DST-I of every
+ *     axis through the length-2 N_s transform of odd-extended line pairs).
+ *     Available when every 2 N_s is a power of two (radix-8/16/32 passes),
+ *     and for d >= 2 also when every 2 N_s has no prime factor above 7
+ *     (mixed-radix 8/4/2/3/5/7 passes, lines held in LDS, eigenvalues
+ *     summed as the cosine series of the generator); FL_E_UNSUPPORTED
+ *     otherwise;
  *   kind 1 (default otherwise): P = R C^{-1} R^T, the restriction to the
  *     n^d interior of the inverse of the embedding circulant C (symbol
  *     1 / max(lambda-hat, 1e-12 max lambda-hat));
@@ -412,6 +416,11 @@ fl_status fl_profile_precond(fl_op A, const void *u, void *y, int nrhs, int fp32
  * ||r||_2 <= tol ||f||_2 either way.  FL_E_INVAL for other kinds.
  */
 fl_status fl_set_preconditioner(fl_op A, int kind);
+
+/* The preconditioner kind fl_solve uses now (the default chosen at creation,
+ * or the last fl_set_preconditioner).  FL_E_INVAL for a null handle or
+ * pointer. */
+fl_status fl_get_preconditioner(fl_op A, int *kind);
 
 /* y = P u for nrhs right-hand sides with the selected preconditioner (same
  * layout, precision and stream rules as fl_apply).  FL_E_INVAL with kind 0.

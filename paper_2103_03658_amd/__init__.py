@@ -141,7 +141,9 @@ class Operator:
         self.nd = 1
         for v in self.shape:
             self.nd *= v
-        self.precond_kind = 2 if all(m == 2 * i for m, i in zip(self.Ms, self.intervals)) else 1
+        kind = ctypes.c_int(0)
+        check(self._lib.fl_get_preconditioner(self._h, ctypes.byref(kind)))
+        self.precond_kind = kind.value   # the library's default (tau where available)
 
     # -- host copies (test hooks) ------------------------------------------
     def _host(self, fn, count):

@@ -90,6 +90,7 @@ _SIGS = {
                                           ctypes.POINTER(ctypes.c_int)]),
     "fl_set_graphs": (ctypes.c_int, [_P, ctypes.c_int]),
     "fl_set_preconditioner": (ctypes.c_int, [_P, ctypes.c_int]),
+    "fl_get_preconditioner": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int)]),
     "fl_apply_precond": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.c_int, _P]),
     "fl_exterior": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int, _P]),
     "fl_destroy": (None, [_P]),

@@ -256,6 +256,10 @@ struct fl_op_s {
   float* lam32 = nullptr;
   double* linv64 = nullptr;   // preconditioner multiplier 1/lambda-hat (floored)
   float* linv32 = nullptr;
+  // the tau preconditioner's multiplier for the mixed-radix sine passes (some
+  // 2 N_s not a power of two; null otherwise)
+  double* tinv64 = nullptr;
+  float* tinv32 = nullptr;
   int precond = 2;            // 0 plain CG, 1 circulant, 2 tau preconditioner
   fl::Twiddles tw64{}, tw32{};   // per axis
   fl::Schedule sc64{}, sc32{};  // transform passes of the product A u
@@ -365,11 +369,11 @@ template <typename T>
 const T* pc_symbol(fl_op A);
 template <>
 const double* pc_symbol<double>(fl_op A) {
-  return A->linv64;
+  return A->precond == 2 && A->tinv64 ? A->tinv64 : A->linv64;
 }
 template <>
 const float* pc_symbol<float>(fl_op A) {
-  return A->linv32;
+  return A->precond == 2 && A->tinv32 ? A->tinv32 : A->linv32;
 }
 
 // schedule of the preconditioner's passes
@@ -418,8 +422,9 @@ static fl_status create_op(int d, double alpha, int degree, int N, const int* Na
   if (degree == 2 && N % 2) return fail(FL_E_INVAL, "degree 2 needs N even");
   if (N > 1024) return fail(FL_E_UNSUPPORTED, "N must be at most 1024 (embedding M <= 2048)");
   // embedding length per axis: any M >= 2 Na - 3 makes the restricted
-  // circulant product exact; the transforms take powers of two (8..2048),
-  // and the tau preconditioner's sine transforms need M = 2 Na exactly
+  // circulant product exact; the transforms take powers of two (8..2048).
+  // The tau preconditioner's sine transforms have length 2 Na: the
+  // power-of-two passes when that is M, else (d >= 2) mixed-radix passes
   int Ma[3] = {1, 1, 1};
   for (int s = 0; s < d; ++s) {
     if (Nax[s] < 2 || Nax[s] > N) return fail(FL_E_INVAL, "box intervals must lie in [2, N]");
@@ -439,9 +444,10 @@ static fl_status create_op(int d, double alpha, int degree, int N, const int* Na
       A->g.na[s] = on ? Nax[s] - 1 : 1;
       A->g.Ma[s] = on ? Ma[s] : 1;
       A->g.Ha[s] = on ? Ma[s] / 2 + 1 : 1;
+      A->g.La[s] = on ? 2 * Nax[s] : 1;
       A->g.nd *= A->g.na[s];
     }
-    A->precond = A->g.sine_ok() ? 2 : 1;
+    A->precond = A->g.tau_ok() ? 2 : 1;
     A->degree = degree;
     A->alpha = alpha;
     A->h = 2.0 / N;
@@ -481,6 +487,19 @@ static fl_status create_op(int d, double alpha, int degree, int N, const int* Na
       const int M = A->g.Ma[s >= d ? 0 : s];
       A->tw64.ax[s] = fl::twiddles(M, false, st);
       A->tw32.ax[s] = fl::twiddles(M, true, st);
+      A->tw64.sx[s] = A->tw64.ax[s];
+      A->tw32.sx[s] = A->tw32.ax[s];
+    }
+    if (!A->g.sine_ok() && A->g.sine_any_ok()) {
+      // the tau preconditioner on mixed-radix sine passes of length 2 N_s
+      const long nt = fl::tau_any_entries(A->g);
+      A->tinv64 = (double*)dmalloc((size_t)nt * sizeof(double));
+      A->tinv32 = (float*)dmalloc((size_t)nt * sizeof(float));
+      fl::build_tau_multiplier(A->g, A->G, A->tinv64, A->tinv32, st);
+      for (int s = 0; s < d; ++s) {
+        A->tw64.sx[s] = fl::twiddles(A->g.La[s], false, st);
+        A->tw32.sx[s] = fl::twiddles(A->g.La[s], true, st);
+      }
     }
     A->sc64 = fl::default_schedule(A->g, false);
     A->sc32 = fl::default_schedule(A->g, true);
@@ -588,6 +607,8 @@ void fl_destroy(fl_op A) {
   fl::dev_free(A->lam32);
   fl::dev_free(A->linv64);
   fl::dev_free(A->linv32);
+  fl::dev_free(A->tinv64);
+  fl::dev_free(A->tinv32);
   A->ws.release();
   A->tau_ws.release();
   A->vecs.release();
@@ -701,11 +722,19 @@ fl_status fl_set_precond_schedule(fl_op A, int fp32, int e_first, int e_mid, int
 fl_status fl_set_preconditioner(fl_op A, int kind) {
   if (!A) return fail(FL_E_INVAL, "null handle");
   if (kind < 0 || kind > 2) return fail(FL_E_INVAL, "kind must be 0, 1 or 2");
-  if (kind == 2 && !A->g.sine_ok())
+  if (kind == 2 && !A->g.tau_ok())
     return fail(FL_E_UNSUPPORTED,
-                "the tau preconditioner needs 2 N_s to be a power of two on every axis");
+                "the tau preconditioner needs 2 N_s to be a power of two on every axis, or, "
+                "for d >= 2, to have no prime factor above 7");
   std::lock_guard<std::mutex> lock(A->mu);
   A->precond = kind;
+  return FL_OK;
+}
+
+fl_status fl_get_preconditioner(fl_op A, int* kind) {
+  if (!A || !kind) return fail(FL_E_INVAL, "null argument");
+  std::lock_guard<std::mutex> lock(A->mu);
+  *kind = A->precond;
   return FL_OK;
 }
 
@@ -1184,9 +1213,11 @@ void precond_apply(fl_op A, const T* linv, const fl::Twiddles& tw, const T* r, T
 // Whether preconditioned CG runs the tau preconditioner split around the
 // iteration start (fl::tau_front / fl::tau_back_direction: z = P r is never
 // stored and the direction kernel is not launched): the tau preconditioner
-// with d >= 2 and the middle pass's r.z partials within the buffers.
+// on the power-of-two sine passes with d >= 2 and the middle pass's r.z
+// partials within the buffers.
 bool tau_split(fl_op A, const fl::Schedule& scp) {
-  return A->precond == 2 && A->g.d >= 2 && fl::sine_mid_blocks(A->g, scp) <= kMaxBlocks;
+  return A->precond == 2 && A->g.d >= 2 && A->g.sine_ok() &&
+         fl::sine_mid_blocks(A->g, scp) <= kMaxBlocks;
 }
 
 // CG start: x = 0, r = rhs, p = 0; preconditioned: z = P r (with the split

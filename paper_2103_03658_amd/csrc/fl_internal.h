@@ -90,18 +90,23 @@ struct Geometry {
   int na[3];   // interior points of axis s = Na[s] - 1
   int Ma[3];   // embedding length of axis s: the smallest power of two >= 2 Na[s]
   int Ha[3];   // folded symbol length of axis s = Ma[s]/2 + 1
+  int La[3];   // sine transform length of axis s (tau preconditioner) = 2 Na[s]
   long nd;     // prod_s na[s]
   bool cube() const {
     for (int s = 1; s < d; ++s)
       if (Na[s] != Na[0]) return false;
     return true;
   }
-  // the tau preconditioner's sine transforms need Ma[s] = 2 Na[s]
+  // the power-of-two sine passes of the tau preconditioner need Ma[s] = 2 Na[s]
   bool sine_ok() const {
     for (int s = 0; s < d; ++s)
       if (Ma[s] != 2 * Na[s]) return false;
     return true;
   }
+  // otherwise (d >= 2) the mixed-radix sine passes take every La[s] whose
+  // prime factors are 2, 3, 5 and 7
+  bool sine_any_ok() const;
+  bool tau_ok() const { return sine_ok() || sine_any_ok(); }
   long nh() const { return (long)Ha[0] * Ha[1] * Ha[2]; }
   long nm() const { return (long)Ma[0] * Ma[1] * Ma[2]; }
 };
@@ -109,7 +114,8 @@ struct Geometry {
 // Twiddle tables of one precision, one per axis (the axes' embedding lengths
 // may differ).
 struct Twiddles {
-  const void* ax[3];
+  const void* ax[3];   // exp(-2 pi i j / Ma[s]), j < Ma[s]
+  const void* sx[3];   // exp(-2 pi i j / La[s]): the mixed-radix sine passes
 };
 
 // Launch schedule (tunable).
@@ -172,6 +178,14 @@ void cg1d_solve(const Geometry& g, int E, const double* f, double* x, const doub
 // else the last pass's.
 long sine_mid_blocks(const Geometry& g, const Schedule& sc);
 int tau_dot_blocks(const Geometry& g, const Schedule& sc, int max_blocks);
+// The same for the mixed-radix sine passes (some 2 N_s not a power of two).
+int tau_dot_blocks_any(const Geometry& g, int max_blocks);
+// Multiplier of the tau preconditioner for the mixed-radix sine passes:
+// tau_any_entries() = prod_s (N_s + 1) values (folded frequencies k_s in
+// [0, N_s]), FP64 and FP32, from the generator G on {0..N}^d.
+long tau_any_entries(const Geometry& g);
+void build_tau_multiplier(const Geometry& g, const double* G, double* m64, float* m32,
+                          hipStream_t st);
 // Blocks per RHS of the vector kernels (update, init, sums).
 int vec_blocks(long nd, int nrhs);
 

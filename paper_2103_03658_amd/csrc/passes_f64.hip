@@ -58,6 +58,7 @@ long sine_mid_blocks(const Geometry& g, const Schedule& sc) {
 
 int tau_dot_blocks(const Geometry& g, const Schedule& sc, int max_blocks) {
   if (g.d == 1) return 1;
+  if (!g.sine_ok()) return tau_dot_blocks_any(g, max_blocks);
   const long mb = sine_mid_blocks(g, sc);
   return mb <= max_blocks ? (int)mb : last_pass_blocks(g, sc);
 }
@@ -249,6 +250,146 @@ void build_symbol(const Geometry& g, const double* G, double* lam64, float* lam3
   hipLaunchKernelGGL(k_fold, dim3((unsigned)((nf + thr - 1) / thr)), dim3(thr), 0, st, c, lam64,
                      lam32, e, nf, 1.0 / (double)total);
   check_launch("fold");
+  FL_HIP(hipStreamSynchronize(st));
+}
+
+}  // namespace fl
+
+namespace fl {
+
+// ---------------------------------------------------------------------------
+// The tau preconditioner where some 2 N_s is not a power of two.  The
+// embedding symbol then samples other frequencies, so the eigenvalues of the
+// tau approximation are summed directly as the truncated cosine series
+//   lam(k) = sum_{j_s <= N_s - 2} G_j prod_s w(j_s) cos(pi j_s k_s / N_s),
+// w(0) = 1, w(j) = 2 (the first column of tau(T) on each level), one axis at
+// a time, on k in [0, N_s]^d.  The multiplier is then the one the
+// power-of-two path stores, 1 / (prod_s 2 N_s  max(lam, 1e-12 max lam)),
+// with the maximum over the interior frequencies k_s in [1, N_s - 1], and
+// zero elsewhere (those slots multiply zeros).
+// ---------------------------------------------------------------------------
+bool Geometry::sine_any_ok() const {
+  if (d < 2) return false;
+  for (int s = 0; s < d; ++s) {
+    RadixPlan p;
+    if (!radix_plan(La[s], p)) return false;
+  }
+  return true;
+}
+
+int tau_dot_blocks_any(const Geometry& g, int max_blocks) {
+  const long mb = sine_any_mid_blocks(g);
+  return mb <= max_blocks ? (int)mb : (int)sine_any_last_blocks(g);
+}
+
+namespace {
+
+// cos(pi m / Ns), m < 2 Ns
+__global__ void k_cos_table(double* t, int Ns) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < 2 * Ns) t[m] = cospi((double)m / (double)Ns);
+}
+
+// out[.., k, ..] = sum_{j = 0}^{Ns - 2} w(j) cos(pi j k / Ns) in[.., j, ..]
+// along `axis` of the row-major arrays in (dims I) and out (dims O, O[axis] =
+// Ns + 1, the others equal to I's).
+__global__ void k_tau_axis(const double* in, double* out, int I0, int I1, int I2, int O0,
+                           int O1, int O2, int axis, int Ns, const double* ctab) {
+  const long total = (long)O0 * O1 * O2;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int o2 = (int)(e % O2), o1 = (int)((e / O2) % O1), o0 = (int)(e / ((long)O1 * O2));
+  const int k = axis == 0 ? o0 : axis == 1 ? o1 : o2;
+  const long sin0 = (long)I1 * I2, sin1 = I2;
+  const long stride = axis == 0 ? sin0 : axis == 1 ? sin1 : 1;
+  long base = (axis == 0 ? 0 : (long)o0 * sin0) + (axis == 1 ? 0 : (long)o1 * sin1) +
+              (axis == 2 ? 0 : o2);
+  double acc = 0.0;
+  int m = 0;   // (j k) mod 2 Ns
+  for (int j = 0; j <= Ns - 2; ++j) {
+    const double w = j == 0 ? 1.0 : 2.0;
+    acc += w * ctab[m] * in[base + (long)j * stride];
+    m += k;
+    if (m >= 2 * Ns) m -= 2 * Ns;
+  }
+  out[e] = acc;
+}
+
+// zero lam outside the interior frequencies k_s in [1, Ns - 1] (in place)
+__global__ void k_tau_interior(double* lam, int H0, int H1, int H2, int d) {
+  const long total = (long)H0 * H1 * H2;
+  const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int k2 = (int)(e % H2), k1 = (int)((e / H2) % H1), k0 = (int)(e / ((long)H1 * H2));
+  bool in = k0 >= 1 && k0 <= H0 - 2;
+  if (d >= 2) in = in && k1 >= 1 && k1 <= H1 - 2;
+  if (d >= 3) in = in && k2 >= 1 && k2 <= H2 - 2;
+  if (!in) lam[e] = 0.0;
+}
+
+__global__ void k_tau_mult(const double* lam, long n, const double* lmax, double s, double* m64,
+                           float* m32) {
+  const long k = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  const double l = lam[k];
+  const double v = l == 0.0 ? 0.0 : s / fmax(l, 1e-12 * lmax[0]);
+  m64[k] = v;
+  m32[k] = (float)v;
+}
+
+}  // namespace
+
+long tau_any_entries(const Geometry& g) {
+  long n = 1;
+  for (int s = 0; s < g.d; ++s) n *= g.Na[s] + 1;
+  return n;
+}
+
+void build_tau_multiplier(const Geometry& g, const double* G, double* m64, float* m32,
+                          hipStream_t st) {
+  if (g.d < 2) throw Error(2, "tau multiplier of the mixed-radix passes: d >= 2");
+  int I[3] = {1, 1, 1};
+  for (int s = 0; s < g.d; ++s) I[s] = g.N + 1;
+  long cap = 1;
+  for (int s = 0; s < g.d; ++s) cap *= g.N + 1;
+  int maxN = 0;
+  for (int s = 0; s < g.d; ++s) maxN = g.Na[s] > maxN ? g.Na[s] : maxN;
+  SetupScratch scr(2 * scratch_round((size_t)cap * sizeof(double)) +
+                       scratch_round((size_t)2 * maxN * sizeof(double)) + 256,
+                   st);
+  double* a = (double*)scr.take((size_t)cap * sizeof(double));
+  double* b = (double*)scr.take((size_t)cap * sizeof(double));
+  double* ctab = (double*)scr.take((size_t)2 * maxN * sizeof(double));
+  double* lmax = (double*)scr.take(sizeof(double));
+  const double* src = G;
+  double* dst = a;
+  for (int ax = 0; ax < g.d; ++ax) {
+    const int Ns = g.Na[ax];
+    hipLaunchKernelGGL(k_cos_table, dim3((2 * Ns + 255) / 256), dim3(256), 0, st, ctab, Ns);
+    check_launch("cosine table");
+    int O[3] = {I[0], I[1], I[2]};
+    O[ax] = Ns + 1;
+    // dims as three axes (trailing ones for d = 2)
+    const long tot = (long)O[0] * O[1] * O[2];
+    hipLaunchKernelGGL(k_tau_axis, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, src,
+                       dst, I[0], I[1], I[2], O[0], O[1], O[2], ax, Ns, ctab);
+    check_launch("tau eigenvalues");
+    I[ax] = O[ax];
+    src = dst;
+    dst = dst == a ? b : a;
+  }
+  double* lam = const_cast<double*>(src);
+  const long n = (long)I[0] * I[1] * I[2];
+  hipLaunchKernelGGL(k_tau_interior, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, lam,
+                     I[0], I[1], I[2], g.d);
+  check_launch("tau interior");
+  hipLaunchKernelGGL(k_symbol_max, dim3(1), dim3(1024), 0, st, lam, n, lmax);
+  check_launch("tau max");
+  double s = 1.0;
+  for (int ax = 0; ax < g.d; ++ax) s /= 2.0 * (double)g.Na[ax];
+  hipLaunchKernelGGL(k_tau_mult, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, lam, n, lmax,
+                     s, m64, m32);
+  check_launch("tau multiplier");
   FL_HIP(hipStreamSynchronize(st));
 }
 

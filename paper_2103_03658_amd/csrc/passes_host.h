@@ -3,6 +3,7 @@
 #pragma once
 
 #include "passes_impl.h"
+#include "sine_any.h"
 
 namespace fl {
 
@@ -57,8 +58,38 @@ void apply_passes_t(const Geometry& g, const Schedule& sc, const T* lam, const T
     // with the multiplier (in place), 3D axis 1, axis 0 (S1 -> y, partials
     // of u.y in PM_DOT)
     if (mode != PM_PLAIN && mode != PM_DOT) throw Error(2, "odd passes: plain or dot mode only");
-    if (!g.sine_ok()) throw Error(2, "sine passes need the embedding length 2N on every axis");
     T* S1 = reinterpret_cast<T*>(ws);
+    if (!g.sine_ok()) {
+      // mixed-radix sine passes (2 N_s not a power of two on some axis); the
+      // same sequence, r.z in the middle pass when its blocks fit
+      if (!g.sine_any_ok())
+        throw Error(2, "sine passes: d >= 2 and 2 N_s with prime factors 2, 3, 5, 7 only");
+      const cx<T>* sw0 = reinterpret_cast<const cx<T>*>(twv.sx[0]);
+      const cx<T>* sw1 = reinterpret_cast<const cx<T>*>(twv.sx[1]);
+      const cx<T>* sw2 = reinterpret_cast<const cx<T>*>(twv.sx[2]);
+      const RadixPlan p0 = radix_plan_or_throw(g.La[0]);
+      const RadixPlan p1 = radix_plan_or_throw(g.La[1]);
+      SineAnyArgs<T> b0{u, S1, nullptr, active, nullptr, 0, C0, nd, 0, 1, n0, 0, 0, sw0, p0};
+      SineAnyArgs<T> b1{S1, S1, nullptr, active, nullptr, 0, n2, (long)n1 * n2, 0, n0, n1,
+                        0, 0, sw1, p1};
+      if (go()) launch_sine_any_cols<T>(b0, nrhs, st);
+      if (g.d == 3 && go()) launch_sine_any_cols<T>(b1, (long)nrhs * n0, st);
+      const int nl = g.d == 2 ? n1 : n2;
+      const RadixPlan pl = radix_plan_or_throw(g.La[g.d - 1]);
+      const bool dot = mode == PM_DOT;
+      const bool mid_dot = dot && sine_any_mid_blocks(g) <= c.max_blocks;
+      SineAnyMidArgs<T> m{S1, lam, active, nd / nl, nd, nl, n1, g.Na[g.d - 1] + 1, g.Na[1] + 1,
+                          g.d, 0, 0, mid_dot ? 1 : 0, part, c.max_blocks,
+                          g.d == 2 ? sw1 : sw2, pl};
+      if (go()) launch_sine_any_mid<T>(m, nrhs, st);
+      if (g.d == 3 && go()) launch_sine_any_cols<T>(b1, (long)nrhs * n0, st);
+      const bool last_dot = dot && !mid_dot;
+      SineAnyArgs<T> b2{S1, y, last_dot ? u : nullptr, active, part, c.max_blocks, C0, nd, 0,
+                        1, n0, 0, last_dot ? 1 : 0, sw0, p0};
+      if (go()) launch_sine_any_cols<T>(b2, nrhs, st);
+      done();
+      return;
+    }
     SineArgs<T> a0{u, S1, nullptr, active, nullptr, 0, C0, nd, 0, 1, n0,
                    sc.W_first, 0, 0, 0, 0, tw0};
     SineArgs<T> a1{S1, S1, nullptr, active, nullptr, 0, n2, (long)n1 * n2, 0, n0, n1,

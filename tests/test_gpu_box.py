@@ -82,7 +82,8 @@ def test_full_box_is_the_cube(d, N):
     assert np.array_equal(cube.symbol(), box.symbol())
 
 
-@pytest.mark.parametrize("box", [(32, 8), (8, 32), (16, 8, 4), (4, 8, 16)])
+@pytest.mark.parametrize("box", [(32, 8), (8, 32), (16, 8, 4), (4, 8, 16), (24, 10), (12, 5, 7),
+                                 (30, 9), (64, 6)])
 def test_box_tau_precond_parity(box):
     op = make_box(1.3, 1, box)
     assert op.precond_kind == 2
@@ -97,7 +98,8 @@ def test_box_tau_precond_parity(box):
 @pytest.mark.parametrize("box", [(24, 10), (12, 5, 7)])
 def test_box_circulant_precond_parity(box):
     op = make_box(1.3, 1, box)
-    assert op.precond_kind == 1
+    assert op.precond_kind == 2   # tau on mixed-radix sine passes (2 N_s = 48, 20 / 24, 10, 14)
+    op.set_preconditioner(1)
     v = inputs.uniform_grid(op.shape, 2, seed=19)
     y = op.apply_precond(torch.from_numpy(v).cuda()).cpu().numpy()
     G = orc_gen(len(box), 1.3, 1, op.N)
@@ -136,4 +138,4 @@ def test_box_validation_and_exterior_shape():
         op.exterior(torch.zeros((1, 49, 49), dtype=torch.float64).cuda())
     assert op.exterior(torch.zeros((2, 49, 41), dtype=torch.float64).cuda()).shape == (2, 15, 7)
     with pytest.raises(fl.FlError):
-        make_box(1.0, 1, (24, 10)).set_preconditioner(2)
+        make_box(1.0, 1, (22, 10)).set_preconditioner(2)   # 2 N_0 = 44 = 4 x 11

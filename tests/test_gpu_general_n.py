@@ -1,12 +1,15 @@
 """Grids whose 2N is not a power of two: the library embeds the Toeplitz
 matrix into the next power-of-two circulant (any M >= 2N - 3 keeps the
-offsets -(N-2)..N-2 apart) and preconditions with the restricted inverse of
-that circulant (the tau preconditioner's sine transforms need M = 2N).
+offsets -(N-2)..N-2 apart).  The tau preconditioner's sine transforms have
+length 2N: for d >= 2 and 2N without a prime factor above 7 they run as
+mixed-radix passes (radix 8, 4, 2, 3, 5, 7) and tau is the default; otherwise
+the default is the restricted inverse of the embedding circulant.
 
 Parity against the oracle: the embedding index map bit-exact, the symbol of
 the same padded embedding, products (FP64 and FP32) against the dense
-Toeplitz product, the circulant preconditioner, solves against Cholesky,
-and the exterior-data term of the 2D scheme.
+Toeplitz product, both preconditioners against their dense forms, the tau
+PCG against the oracle's PCG step for step, solves against Cholesky, and
+the exterior-data term of the 2D scheme.
 """
 
 import numpy as np
@@ -100,7 +103,9 @@ def test_apply_parity_general_n(d, alpha, p, N, nrhs, fp32):
 @pytest.mark.parametrize("d,N", [(1, 12), (2, 12), (3, 6)])
 def test_circulant_precond_parity_general_n(d, N):
     op = make_op(d, 1.3, 1, N)
-    assert op.precond_kind == 1
+    # default: tau where its mixed-radix passes run (d >= 2), else circulant
+    assert op.precond_kind == (1 if d == 1 else 2)
+    op.set_preconditioner(1)
     v = inputs.uniform_rhs(d, N, 2, seed=9)
     y = op.apply_precond(torch.from_numpy(v).cuda()).cpu().numpy()
     G = orc_gen(d, 1.3, 1, N)
@@ -109,13 +114,102 @@ def test_circulant_precond_parity_general_n(d, N):
         assert np.abs(y[r] - ref).max() <= 1e-11 * np.abs(ref).max()
 
 
-def test_tau_needs_power_of_two_2n():
+def test_tau_availability_general_n():
+    """tau needs every 2 N_s free of prime factors above 7 (and d >= 2 when
+    2N is not a power of two); elsewhere FL_E_UNSUPPORTED and the circulant
+    preconditioner is the default."""
     import paper_2103_03658_amd as fl
-    op = make_op(2, 1.0, 1, 12)
-    with pytest.raises(fl.FlError):
+    for d, N in [(1, 12), (2, 47), (3, 11), (2, 777)]:
+        op = make_op(d, 1.0, 1, N)
+        assert op.precond_kind == 1, (d, N)
+        with pytest.raises(fl.FlError):
+            op.set_preconditioner(2)
+        op.set_preconditioner(0)
+        op.set_preconditioner(1)
+    for d, N in [(2, 5), (2, 12), (2, 700), (3, 6), (3, 10)]:
+        op = make_op(d, 1.0, 1, N)
+        assert op.precond_kind == 2, (d, N)
+        op.set_preconditioner(1)
         op.set_preconditioner(2)
-    op.set_preconditioner(0)
-    op.set_preconditioner(1)
+
+
+def tau_scale_axes(G, v):
+    """Magnitude chain prod_s (2/N_s) |S|..(|1/lam| (|S|..|v|)) of the tau
+    product on v's grid (N_s = n_s + 1 per axis); its largest entry."""
+    shp = v.shape
+    inv = 1.0 / np.abs(oracle.tau_symbol(G, shp))
+    Ss = []
+    for n in shp:
+        k = np.arange(1, n + 1)
+        Ss.append(np.abs(np.sin(np.pi * np.outer(k, k) / (n + 1))))
+    sc = np.abs(v)
+    for ax in range(len(shp)):
+        sc = np.moveaxis(np.tensordot(Ss[ax], sc, axes=([1], [ax])), 0, ax)
+    sc = sc * inv
+    for ax in range(len(shp)):
+        sc = np.moveaxis(np.tensordot(Ss[ax], sc, axes=([1], [ax])), 0, ax)
+    return sc.max() * np.prod([2.0 / (n + 1) for n in shp])
+
+
+# 2N = 10, 12, 24, 40, 48, 200, 1200, 1400, 2000: every radix (8, 4, 2, 3, 5, 7)
+TAU_ANY = [(2, 5, 1), (2, 6, 2), (2, 12, 1), (2, 20, 0), (2, 24, 1), (2, 100, 2), (2, 600, 1),
+           (2, 700, 1), (2, 1000, 1), (3, 5, 1), (3, 6, 2), (3, 12, 1), (3, 20, 1)]
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+@pytest.mark.parametrize("d,N,p", TAU_ANY)
+def test_tau_any_precond_parity(d, N, p, fp32):
+    """fl_apply_precond with the tau preconditioner on mixed-radix sine
+    passes against the oracle's dense sine-transform form (1e-12 / 1e-5 of
+    the magnitude chain, as on the power-of-two passes)."""
+    print(f"[tau any] d={d} N={N} p={p} fp32={fp32}", flush=True)
+    op = make_op(d, 1.3, p, N)
+    assert op.precond_kind == 2
+    u = inputs.uniform_rhs(d, N, 3, seed=43)
+    ut = torch.from_numpy(u.astype(np.float32) if fp32 else u).cuda()
+    y = op.apply_precond(ut).double().cpu().numpy()
+    G = orc_gen(d, 1.3, p, N)
+    for r in range(3):
+        v = ut[r].double().cpu().numpy()
+        ref = oracle.tau_precond_apply(G, v)
+        sc = tau_scale_axes(G, v)
+        tol = 1e-5 if fp32 else 1e-12
+        err = float(np.abs(y[r] - ref).max() / sc)
+        assert err <= tol, (r, err)
+
+
+@pytest.mark.parametrize("d,alpha,p,N", [(2, 1.9, 1, 24), (2, 1.0, 2, 40), (2, 0.6, 1, 48),
+                                         (3, 1.2, 1, 10)])
+def test_tau_any_pcg_follows_oracle(d, alpha, p, N):
+    op = make_op(d, alpha, p, N)
+    assert op.precond_kind == 2
+    f = inputs.uniform_rhs(d, N, 1, seed=12)
+    u, info = op.solve(torch.from_numpy(f).cuda(), tol=1e-10, mixed=0)
+    G = orc_gen(d, alpha, p, N)
+    ur, it, rel = oracle.solve_cg(G, f[0], tol=1e-10,
+                                  precond=lambda v: oracle.tau_precond_apply(G, v))
+    print(f"  gpu iters {info[0]['iters']}, oracle iters {it}")
+    assert abs(info[0]["iters"] - it) <= 1
+    assert np.abs(u[0].cpu().numpy() - ur).max() <= 1e-8 * np.abs(ur).max()
+
+
+@pytest.mark.parametrize("N", [600, 700])
+def test_tau_any_cuts_iterations(N):
+    """On grids of 2N = 1200 and 1400 points the tau preconditioner takes
+    far fewer iterations than the circulant one it replaces as the default,
+    FP64 and mixed, to the same tolerance."""
+    op = make_op(2, 1.5, 1, N)
+    f = torch.from_numpy(inputs.uniform_rhs(2, N, 2, seed=4)).cuda()
+    its = {}
+    for kind in (1, 2):
+        op.set_preconditioner(kind)
+        for mixed in (0, 1):
+            _, info = op.solve(f, tol=1e-10, mixed=mixed)
+            assert all(i["converged"] == 1 and i["relres_true"] <= 2e-10 for i in info)
+            its[(kind, mixed)] = max(i["iters"] for i in info)
+    print(f"  N={N} iterations {its}")
+    assert its[(2, 0)] * 2 <= its[(1, 0)], its
+    assert its[(2, 1)] * 2 <= its[(1, 1)], its
 
 
 @pytest.mark.parametrize("mixed", [0, 1])
