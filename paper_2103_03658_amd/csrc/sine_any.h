@@ -151,7 +151,7 @@ __device__ cx<T>* any_fft(cx<T>* b0, cx<T>* b1, const RadixPlan& p, int nlines,
 // values per line within 128 KB in FP64 (the same count in FP32, so that the
 // number of partial sums a pass writes does not depend on the precision).
 constexpr size_t kSineAnyLds = size_t(128) << 10;
-constexpr int kSineAnyThreads = 256;
+constexpr int kSineAnyThreads = 1024;
 inline int sine_any_lines(int L) {
   int w = (int)(kSineAnyLds / (2 * (size_t)L * sizeof(cx<double>)));
   if (w > 8) w = 8;
