@@ -373,9 +373,11 @@ def _hankel_tau_1d(t):
     return T - H
 
 
-@pytest.mark.parametrize("alpha,p", [(0.5, 1), (1.5, 2), (1.9, 0)])
-def test_tau_symbol_1d_is_spectrum_of_t_minus_hankel(alpha, p):
-    N = 16
+@pytest.mark.parametrize("alpha,p,N", [(0.5, 1, 16), (1.5, 2, 16), (1.9, 0, 16), (1.2, 1, 12),
+                                       (0.7, 2, 10), (1.6, 1, 21)])
+def test_tau_symbol_1d_is_spectrum_of_t_minus_hankel(alpha, p, N):
+    """Any N, also where 2N is not a power of two (the GPU's mixed-radix
+    sine passes are checked against this oracle form there)."""
     G = oracle.generator(1, alpha, p, N)
     n = N - 1
     tau = _hankel_tau_1d(G[:n])
@@ -387,23 +389,33 @@ def test_tau_symbol_1d_is_spectrum_of_t_minus_hankel(alpha, p):
                                rtol=1e-11, atol=1e-12 * lam.max())
 
 
-def test_tau_symbol_2d_is_spectrum_of_tensor_tau():
+@pytest.mark.parametrize("N,shape", [(8, None), (6, None), (10, (9, 4)), (12, (5, 11))])
+def test_tau_symbol_2d_is_spectrum_of_tensor_tau(N, shape):
     """2-level: tau(T) = sum_ab t_ab tau(B_a) (x) tau(B_b), B_a the Toeplitz
-    basis matrix of offset a, built densely; its eigen-decomposition in the
-    2D sine basis has the oracle's eigenvalues."""
-    N, alpha = 8, 1.2
+    basis matrix of offset a (size n_s of its axis), built densely; its
+    eigen-decomposition in the 2D sine basis has the oracle's eigenvalues.
+    Cubes and boxes, 2N a power of two or not."""
+    alpha = 1.2
     G = oracle.generator(2, alpha, 1, N)
-    n = N - 1
-    taus = []
-    for a in range(n):
-        e = np.zeros(n)
-        e[a] = 1.0
-        taus.append(_hankel_tau_1d(e))
-    tau = sum(G[a, b] * np.kron(taus[a], taus[b]) for a in range(n) for b in range(n))
-    k = np.arange(1, n + 1)
-    S = np.sin(np.pi * np.outer(k, k) / N) * np.sqrt(2.0 / N)
-    S2 = np.kron(S, S)
-    lam = oracle.tau_symbol(G).reshape(-1)
+    n0, n1 = shape if shape else (N - 1, N - 1)
+
+    def basis(n):
+        out = []
+        for a in range(n):
+            e = np.zeros(n)
+            e[a] = 1.0
+            out.append(_hankel_tau_1d(e))
+        return out
+
+    t0, t1 = basis(n0), basis(n1)
+    tau = sum(G[a, b] * np.kron(t0[a], t1[b]) for a in range(n0) for b in range(n1))
+
+    def sine(n):
+        k = np.arange(1, n + 1)
+        return np.sin(np.pi * np.outer(k, k) / (n + 1)) * np.sqrt(2.0 / (n + 1))
+
+    S2 = np.kron(sine(n0), sine(n1))
+    lam = oracle.tau_symbol(G, (n0, n1)).reshape(-1)
     np.testing.assert_allclose(S2 @ np.diag(lam) @ S2, tau, atol=1e-12 * np.abs(tau).max())
 
 
