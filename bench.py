@@ -411,8 +411,8 @@ def cpu_baseline(N, degree, alpha, tol, budget):
         from threadpoolctl import threadpool_limits
     except Exception:  # pragma: no cover
         threadpool_limits = None
-    # BLAS threads: the host cores this process may use, at most 16 (the CPU
-    # share of one GPU on the benchmark boxes, whatever the host shows)
+    # BLAS threads: the host cores this process may use, capped at 16 (one
+    # GPU's share of a multi-GPU host's cores); `cores` reports the count used
     cores = len(os.sched_getaffinity(0))
     cores = min(cores, 16)
     ctx = threadpool_limits(limits=cores) if threadpool_limits else None
