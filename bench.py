@@ -75,7 +75,8 @@ def progress(msg):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=6)
+    ap.add_argument("--steps", type=int, default=21,
+                    help="timed batched solves (7 per alpha: p50/p99 over >= 20)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--N", type=int, default=512)
     ap.add_argument("--degree", type=int, default=2)
@@ -96,6 +97,8 @@ def parse():
     ap.add_argument("--cpu-budget", type=float, default=20.0,
                     help="seconds of oracle work for the CPU baseline (0: skip)")
     ap.add_argument("--profile-reps", type=int, default=20)
+    ap.add_argument("--d2-reps", type=int, default=100,
+                    help="back-to-back launches per pass in the large-working-set products")
     ap.add_argument("--no-tune", action="store_true", help="keep the default launch schedule")
     ap.add_argument("--tune-cache", action="store_true",
                     help="reuse / store tuned schedules in the tuner's JSON cache "
@@ -460,6 +463,11 @@ def serving_legs(args):
     if args.serve_burst > 0:
         out["burst"] = run_serving(args.serve_burst, args.serve_workers, args.tol, mixed=1,
                                    sample=args.serve_sample, burst=True)
+        if args.serve_fp64:
+            # the same saturated stream in FP64 PCG: the batched serving path's
+            # throughput in each precision when requests queue
+            out["burst_fp64"] = run_serving(args.serve_burst, args.serve_workers, args.tol,
+                                            mixed=0, sample=args.serve_sample, burst=True)
     return out
 
 
@@ -480,7 +488,7 @@ def main():
         print(json.dumps({"serving": serving_legs(args)}))
         return
     if args.d2_only:
-        print(json.dumps({"d2": d2_shapes(dev, reps=args.profile_reps,
+        print(json.dumps({"d2": d2_shapes(dev, reps=args.d2_reps,
                                           use_cache=args.tune_cache)}))
         return
     N, p = args.N, args.degree
@@ -670,8 +678,8 @@ def main():
 
     pp64, pp32 = ppasses(False), ppasses(True)
 
-    # a plain device copy of 1 GiB (read + write), HIP events on torch's stream
-    src = torch.ones((1 << 30) // 4, dtype=torch.float32, device=dev)
+    # a plain device copy of 4 GiB (read + write), HIP events on torch's stream
+    src = torch.ones((4 << 30) // 4, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
     dst.copy_(src)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -680,7 +688,7 @@ def main():
         dst.copy_(src)
     e1.record()
     e1.synchronize()
-    copy_gbs = 5 * 2 * (1 << 30) / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    copy_gbs = 5 * 2 * (4 << 30) / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del src, dst
 
     pk = pk32 if mixed else pk64
@@ -705,7 +713,7 @@ def main():
 
     configs = run_configs(dev, args.tol) if args.configs else None
     progress("configs done")
-    d2 = d2_shapes(dev, reps=args.profile_reps) if args.d2 else None
+    d2 = d2_shapes(dev, reps=args.d2_reps) if args.d2 else None
     progress("large working sets done")
 
     serving = serving_legs(args)
