@@ -71,6 +71,10 @@ def test_null_handle_errors():
     assert lib.fl_apply(None, None, None, 1, 0, None) == _lib.FL_E_INVAL
     assert lib.fl_solve(None, None, None, 1e-10, 10, 0, None, 1, None, None) == _lib.FL_E_INVAL
     assert lib.fl_set_refinement(None, 0.1, 1e-3, 3) == _lib.FL_E_INVAL
+    kind = ctypes.c_int(-1)
+    assert lib.fl_get_preconditioner(None, ctypes.byref(kind)) == _lib.FL_E_INVAL
+    assert kind.value == -1
+    assert lib.fl_set_preconditioner(None, 2) == _lib.FL_E_INVAL
     lib.fl_destroy(None)  # accepted
 
 
