@@ -111,6 +111,9 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=4096,
                     help="requests of the serving stream (Poisson arrivals at 200/s; 0: skip)")
     ap.add_argument("--serve-workers", type=int, default=4)
+    ap.add_argument("--serve-graphs", type=int, default=1,
+                    help="fl_set_graphs mode of the served operators (2: capture a CG chunk "
+                         "when it runs a second time; 1: at its first run; 0: never)")
     ap.add_argument("--serve-fp64", type=int, default=1,
                     help="1: also serve the stream with FP64 PCG beside the mixed path")
     ap.add_argument("--serve-burst", type=int, default=512,
@@ -129,7 +132,7 @@ def parse():
     return ap.parse_args()
 
 
-def run_serving(n_requests, workers, tol, mixed=1, sample=32, burst=False):
+def run_serving(n_requests, workers, tol, mixed=1, sample=32, burst=False, graphs=1):
     """Serving stream: d = 2, n in {63,127,255,511}, alpha ~ U(0.2, 1.9)
     rounded to 0.01, degree in {0,1,2}, 1-8 U[-1,1] right-hand sides,
     Poisson arrivals at 200 requests/s, solves to tol with the mixed path
@@ -151,7 +154,8 @@ def run_serving(n_requests, workers, tol, mixed=1, sample=32, burst=False):
     step = max(1, n_requests // max(1, sample))
     keep = set(range(0, n_requests, step)[:sample])
     warm = sorted({(2, r["N"], r["degree"]) for r in spec})
-    srv = Server(workers=workers, tol=tol, mixed=mixed, warm=warm, keep_solutions=keep)
+    srv = Server(workers=workers, tol=tol, mixed=mixed, warm=warm, keep_solutions=keep,
+                 graphs=graphs)
     st = srv.run(reqs, realtime=True)
     # alone against the mix: each sampled request on a fresh operator of its own
     same, worst = 0, 0.0
@@ -454,20 +458,20 @@ def serving_legs(args):
     requests queue and are merged."""
     if args.serve_requests <= 0:
         return None
-    out = run_serving(args.serve_requests, args.serve_workers, args.tol, mixed=1,
-                      sample=args.serve_sample)
+    kw = dict(sample=args.serve_sample, graphs=args.serve_graphs)
+    out = run_serving(args.serve_requests, args.serve_workers, args.tol, mixed=1, **kw)
     progress("serving stream (mixed) done")
     if args.serve_fp64:
         out["fp64"] = run_serving(args.serve_requests, args.serve_workers, args.tol, mixed=0,
-                                  sample=args.serve_sample)
+                                  **kw)
     if args.serve_burst > 0:
         out["burst"] = run_serving(args.serve_burst, args.serve_workers, args.tol, mixed=1,
-                                   sample=args.serve_sample, burst=True)
+                                   burst=True, **kw)
         if args.serve_fp64:
             # the same saturated stream in FP64 PCG: the batched serving path's
             # throughput in each precision when requests queue
             out["burst_fp64"] = run_serving(args.serve_burst, args.serve_workers, args.tol,
-                                            mixed=0, sample=args.serve_sample, burst=True)
+                                            mixed=0, burst=True, **kw)
     return out
 
 

@@ -427,11 +427,15 @@ fl_status fl_get_preconditioner(fl_op A, int *kind);
  * Test hook for the preconditioners. */
 fl_status fl_apply_precond(fl_op A, const void *u, void *y, int nrhs, int fp32, void *stream);
 
-/* Replay CG iteration chunks from captured HIP graphs (enable = 1, the
- * default) or launch every kernel directly (enable = 0).  Results are the
- * same either way; graphs cut host launch cost.  fl_solve runs its work on
- * a stream owned by the handle, ordered after `stream` and before later work
- * on `stream` by events. */
+/* Replay CG iteration chunks from captured HIP graphs or launch every
+ * kernel directly: enable = 1 (the default) captures a chunk the first time
+ * it runs; enable = 2 runs it directly the first time and captures it when
+ * the same launch sequence comes again (for operators that are solved once
+ * or twice, e.g. in a serving stream: no capture and instantiation cost on
+ * their first solve); enable = 0 never captures.  Results are the same every
+ * way; graphs cut host launch cost.  FL_E_INVAL for other values.  fl_solve
+ * runs its work on a stream owned by the handle, ordered after `stream` and
+ * before later work on `stream` by events. */
 fl_status fl_set_graphs(fl_op A, int enable);
 
 /*

@@ -347,7 +347,10 @@ class Operator:
         return out
 
     def set_graphs(self, enable):
-        check(self._lib.fl_set_graphs(self._h, int(bool(enable))))
+        """1 / True: capture CG chunks as HIP graphs at their first launch
+        (default); 2: capture them when they come a second time (operators
+        solved once pay nothing for capture); 0 / False: direct launches."""
+        check(self._lib.fl_set_graphs(self._h, int(enable)))
 
     def get_schedule(self, fp32, precond=False):
         s = (ctypes.c_int * 6)()

@@ -238,10 +238,12 @@ struct CgState {
 struct ChunkGraph {
   hipGraphExec_t exec = nullptr;
   std::vector<double> key;
+  std::vector<double> seen;   // key of the last eager launch (captured on its next use)
   void reset() {
     if (exec) (void)hipGraphExecDestroy(exec);
     exec = nullptr;
     key.clear();
+    seen.clear();
   }
 };
 
@@ -295,7 +297,7 @@ struct fl_op_s {
   size_t poll_cap = 0;
   int iter_hint = 0;      // iterations of the last FP64 solve (first chunk length)
   double mixed_rate = 0;  // slowest r.r contraction per FP32 iteration of the last mixed solve
-  bool use_graphs = true;
+  int graph_mode = 1;     // 0 direct launches, 1 capture at first use, 2 at the second
 
   // Order this call after the previous one if it ran on another stream
   // (the workspace is shared).
@@ -767,7 +769,8 @@ fl_status fl_apply_precond(fl_op A, const void* u, void* y, int nrhs, int fp32, 
 fl_status fl_set_graphs(fl_op A, int enable) {
   if (!A) return fail(FL_E_INVAL, "null handle");
   std::lock_guard<std::mutex> lock(A->mu);
-  A->use_graphs = enable != 0;
+  if (enable < 0 || enable > 2) return fail(FL_E_INVAL, "enable must be 0, 1 or 2");
+  A->graph_mode = enable;
   return FL_OK;
 }
 
@@ -988,16 +991,24 @@ void ensure_solver_stream(fl_op A) {
 }
 
 // Replay the captured chunk if `key` matches; otherwise run `enqueue` once
-// directly and capture it into a new graph for the next calls.
+// directly and capture it into a new graph for the next calls (mode 1), or
+// (mode 2) capture it only when the same sequence comes a second time, so
+// that an operator solved once, as most are in a serving stream, never pays
+// for capture and instantiation.  Mode 0: direct launches only.
 template <typename F>
-void launch_chunk(ChunkGraph& g, const std::vector<double>& key, hipStream_t st, bool graphs,
+void launch_chunk(ChunkGraph& g, const std::vector<double>& key, hipStream_t st, int mode,
                   F&& enqueue) {
-  if (!graphs) {
+  if (mode == 0) {
     enqueue();
     return;
   }
   if (g.exec && g.key == key) {
     FL_HIP(hipGraphLaunch(g.exec, st));
+    return;
+  }
+  if (mode == 2 && g.seen != key) {
+    g.seen = key;
+    enqueue();
     return;
   }
   g.reset();
@@ -1045,7 +1056,7 @@ void launch_iterations(fl_op A, ChunkGraph* gl, const std::vector<double>& key, 
     while (n >= lens[b]) {
       std::vector<double> kb = key;
       kb.push_back(lens[b]);
-      launch_chunk(gl[b], kb, st, A->use_graphs, [&]() {
+      launch_chunk(gl[b], kb, st, A->graph_mode, [&]() {
         for (int i = 0; i < lens[b]; ++i) enqueue_one();
       });
       n -= lens[b];
@@ -1149,7 +1160,7 @@ void predictive_mixed_loop(fl_op A, const std::vector<double>& key, int maxiter,
   const int max_chunks = 2 * (maxiter + 2) + 8;
   for (int c = 0; c < max_chunks; ++c) {
     launch_iterations(A, A->glen32, key, next, st, enqueue_one);
-    launch_chunk(A->grel, krel, st, A->use_graphs, enqueue_reliable);
+    launch_chunk(A->grel, krel, st, A->graph_mode, enqueue_reliable);
     fl::pack_poll(cg, nrhs, rr_last, f2, nupd, dpoll, st);
     FL_HIP(hipMemcpyAsync(A->poll_host, dpoll, pb, hipMemcpyDeviceToHost, st));
     FL_HIP(hipStreamSynchronize(st));

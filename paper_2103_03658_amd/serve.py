@@ -83,8 +83,14 @@ class Request:
 
 class Server:
     def __init__(self, workers=4, hbm_budget=64 << 30, cache_bytes=None, max_batch_rhs=64,
-                 tol=1e-10, mixed=0, maxiter=20000, keep_solutions=False, device=0, warm=()):
+                 tol=1e-10, mixed=0, maxiter=20000, keep_solutions=False, device=0, warm=(),
+                 graphs=1):
         self.workers = workers
+        # HIP graphs of the operators' CG chunks (fl_set_graphs mode): 1
+        # captures a chunk at its first run; 2 at its second, so that an
+        # operator solved once never pays for capture (on the 4096-request
+        # stream the two measured the same within run-to-run spread)
+        self.graphs = graphs
         self.warm = list(warm)                     # (d, N, degree) solved once per worker
         self._warmed = threading.Barrier(workers + 1)
         self.hbm_budget = hbm_budget
@@ -134,6 +140,8 @@ class Server:
                     self._ops[k] = (op, need)
                 return op, True
         op = fl.Operator(req.d, req.alpha, req.degree, N=req.N, kernel=req.kernel, lam=req.lam)
+        if self.graphs != 1:     # 1 is the library's default
+            op.set_graphs(self.graphs)
         b = op_bytes(req.d, req.N) + batch_bytes(req.d, req.N, nrhs)
         with self._cv:
             self._ops[k] = (op, b)

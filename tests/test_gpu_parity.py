@@ -321,6 +321,25 @@ def test_graph_replays_match_eager(mixed):
         op.set_graphs(True)
 
 
+@pytest.mark.parametrize("mixed", [0, 1])
+def test_graph_capture_at_second_use_matches_eager(mixed):
+    """fl_set_graphs(2): the first solve launches directly, the second
+    captures, the later ones replay; every one gives the eager bits."""
+    import paper_2103_03658_amd as fl
+    op = make_op(2, 1.1, 1, 32)
+    f = torch.from_numpy(inputs.uniform_rhs(2, 32, 3, seed=33)).cuda()
+    op.set_graphs(0)
+    ue, ie = op.solve(f, tol=1e-10, mixed=mixed)
+    op.set_graphs(2)
+    for rep in range(4):
+        ug, ig = op.solve(f, tol=1e-10, mixed=mixed)
+        torch.cuda.synchronize()
+        assert torch.equal(ug, ue), rep
+        assert [i["iters"] for i in ig] == [i["iters"] for i in ie]
+    with pytest.raises(fl.FlError):
+        op.set_graphs(3)
+
+
 @pytest.mark.parametrize("d,N,fp32", [(1, 64, False), (2, 32, False), (2, 32, True),
                                       (3, 8, False)])
 def test_precond_apply_parity(d, N, fp32):

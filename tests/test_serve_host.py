@@ -33,6 +33,9 @@ class FakeOperator:
         with FakeOperator.lock:
             FakeOperator.closed.append(self.key)
 
+    def set_graphs(self, mode):
+        self.graphs = mode
+
 
 class HostServer(serve.Server):
     def _open_stream(self):
