@@ -403,10 +403,9 @@ fl_status fl_profile_precond(fl_op A, const void *u, void *y, int nrhs, int fp32
  *     transform of each axis and applied by real sine passes (DST-I of every
  *     axis through the length-2 N_s transform of odd-extended line pairs).
  *     Available when every 2 N_s is a power of two (radix-8/16/32 passes),
- *     and for d >= 2 also when every 2 N_s has no prime factor above 7
- *     (mixed-radix 8/4/2/3/5/7 passes, lines held in LDS, eigenvalues
- *     summed as the cosine series of the generator); FL_E_UNSUPPORTED
- *     otherwise;
+ *     and also when every 2 N_s has no prime factor above 7 (mixed-radix
+ *     8/4/2/3/5/7 passes, lines held in LDS, eigenvalues summed as the
+ *     cosine series of the generator); FL_E_UNSUPPORTED otherwise;
  *   kind 1 (default otherwise): P = R C^{-1} R^T, the restriction to the
  *     n^d interior of the inverse of the embedding circulant C (symbol
  *     1 / max(lambda-hat, 1e-12 max lambda-hat));

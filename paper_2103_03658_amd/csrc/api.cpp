@@ -426,7 +426,7 @@ static fl_status create_op(int d, double alpha, int degree, int N, const int* Na
   // embedding length per axis: any M >= 2 Na - 3 makes the restricted
   // circulant product exact; the transforms take powers of two (8..2048).
   // The tau preconditioner's sine transforms have length 2 Na: the
-  // power-of-two passes when that is M, else (d >= 2) mixed-radix passes
+  // power-of-two passes when that is M, else mixed-radix passes
   int Ma[3] = {1, 1, 1};
   for (int s = 0; s < d; ++s) {
     if (Nax[s] < 2 || Nax[s] > N) return fail(FL_E_INVAL, "box intervals must lie in [2, N]");
@@ -726,8 +726,8 @@ fl_status fl_set_preconditioner(fl_op A, int kind) {
   if (kind < 0 || kind > 2) return fail(FL_E_INVAL, "kind must be 0, 1 or 2");
   if (kind == 2 && !A->g.tau_ok())
     return fail(FL_E_UNSUPPORTED,
-                "the tau preconditioner needs 2 N_s to be a power of two on every axis, or, "
-                "for d >= 2, to have no prime factor above 7");
+                "the tau preconditioner needs every 2 N_s to be a power of two or to have no "
+                "prime factor above 7");
   std::lock_guard<std::mutex> lock(A->mu);
   A->precond = kind;
   return FL_OK;
@@ -1438,9 +1438,11 @@ static fl_status solve_body(fl_op A, const double* f, const double* b, double to
     double* q = (double*)(vb + 2 * a8);
     double* x = (double*)(vb + 3 * a8);
     double* z = (double*)(vb + 4 * a8);
-    if (A->g.d == 1) {
+    if (A->g.d == 1 && !(pc == 2 && !A->g.sine_ok())) {
       // the line fits a workgroup: the whole solve in one launch (radix 8:
-      // the most threads per line and no register spills)
+      // the most threads per line and no register spills); the tau
+      // preconditioner of a 2N that is not a power of two runs the
+      // multi-kernel iteration with the mixed-radix sine pass
       fl::cg1d_solve(A->g, 8, f, x, A->lam64, pc ? pc_symbol<double>(A) : nullptr, pc == 2, cg,
                      nrhs, maxiter, tol, A->tw64.ax[0], st);
     } else {

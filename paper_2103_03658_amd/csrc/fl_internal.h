@@ -103,8 +103,8 @@ struct Geometry {
       if (Ma[s] != 2 * Na[s]) return false;
     return true;
   }
-  // otherwise (d >= 2) the mixed-radix sine passes take every La[s] whose
-  // prime factors are 2, 3, 5 and 7
+  // otherwise the mixed-radix sine passes take every La[s] whose prime
+  // factors are 2, 3, 5 and 7
   bool sine_any_ok() const;
   bool tau_ok() const { return sine_ok() || sine_any_ok(); }
   long nh() const { return (long)Ha[0] * Ha[1] * Ha[2]; }

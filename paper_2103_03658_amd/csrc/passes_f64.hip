@@ -269,7 +269,6 @@ namespace fl {
 // zero elsewhere (those slots multiply zeros).
 // ---------------------------------------------------------------------------
 bool Geometry::sine_any_ok() const {
-  if (d < 2) return false;
   for (int s = 0; s < d; ++s) {
     RadixPlan p;
     if (!radix_plan(La[s], p)) return false;
@@ -347,7 +346,6 @@ long tau_any_entries(const Geometry& g) {
 
 void build_tau_multiplier(const Geometry& g, const double* G, double* m64, float* m32,
                           hipStream_t st) {
-  if (g.d < 2) throw Error(2, "tau multiplier of the mixed-radix passes: d >= 2");
   int I[3] = {1, 1, 1};
   for (int s = 0; s < g.d; ++s) I[s] = g.N + 1;
   long cap = 1;

@@ -259,6 +259,15 @@ struct SineAnyMidArgs {
   RadixPlan plan;
 };
 
+// Multiplier row of line L of the last axis (the other axes' frequencies are
+// their indices + 1); d = 1: the one line.
+__device__ __forceinline__ long any_mrow(long L, int n1, int H1, int Hl, int d) {
+  if (d == 1) return 0;
+  const int l = (int)L;
+  if (d == 3) return (long)((l / n1 + 1) * H1 + (l % n1 + 1)) * Hl;
+  return (long)(l + 1) * Hl;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kSineAnyThreads) k_sine_any_mid(SineAnyMidArgs<T> a) {
   extern __shared__ unsigned char smem_raw[];
@@ -296,8 +305,8 @@ __global__ void __launch_bounds__(kSineAnyThreads) k_sine_any_mid(SineAnyMidArgs
     const int kk = k <= N ? k : L - k;
     const long la = la0 + 2 * pr;
     const bool ha = la < a.rows, hb = la + 1 < a.rows;
-    const T sa = ha ? a.m[sine_mrow(la, a.n1, a.H1, a.Hl, a.d) + kk] : (T)0;
-    const T sb = hb ? a.m[sine_mrow(la + 1, a.n1, a.H1, a.Hl, a.d) + kk] : (T)0;
+    const T sa = ha ? a.m[any_mrow(la, a.n1, a.H1, a.Hl, a.d) + kk] : (T)0;
+    const T sb = hb ? a.m[any_mrow(la + 1, a.n1, a.H1, a.Hl, a.d) + kk] : (T)0;
     const cx<T> z = res[f];
     if (a.dot && k >= 1 && k <= n)
       acc += (double)sa * (double)z.y * (double)z.y + (double)sb * (double)z.x * (double)z.x;

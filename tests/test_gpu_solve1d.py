@@ -25,7 +25,8 @@ def test_one_launch_solve_matches_cholesky(alpha, p, N, kind):
     import paper_2103_03658_amd as fl
     op = make_op(alpha, p, N)
     if kind == 2 and op.precond_kind != 2:
-        # the tau preconditioner's sine transforms need 2N a power of two
+        # the tau preconditioner needs 2N without prime factors above 7 (with
+        # 2N not a power of two it runs the multi-kernel iteration)
         with pytest.raises(fl.FlError) as exc:
             op.set_preconditioner(kind)
         assert exc.value.status == 2              # FL_E_UNSUPPORTED
