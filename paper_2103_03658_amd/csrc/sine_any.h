@@ -157,11 +157,17 @@ inline int sine_any_lines(int L) {
   if (w > 8) w = 8;
   return w < 1 ? 1 : w;
 }
+// The contiguous middle pass runs one line pair per block (its loads are
+// whole lines, so the lines per block do not matter for coalescing): two LDS
+// buffers of at most 32 KB (FP64, L <= 2048), so that several blocks share
+// a CU and hide each other's stage barriers and twiddle loads; 256 threads
+// up to L = 1600, 512 above (measured: L = 1200 and 1400 faster with 256,
+// L = 2000 with 512).
+constexpr int kSineAnyMidThreads = 512;
+inline int sine_any_mid_threads(int L) { return L <= 1600 ? 256 : 512; }
 inline long sine_any_mid_blocks(const Geometry& g) {
   const long rows = g.nd / g.na[g.d - 1];
-  const long pairs = (rows + 1) / 2;
-  const int lpb = sine_any_lines(g.La[g.d - 1]);
-  return (pairs + lpb - 1) / lpb;
+  return (rows + 1) / 2;
 }
 inline long sine_any_last_blocks(const Geometry& g) {
   return pair_tiles((long)g.na[1] * g.na[2], sine_any_lines(g.La[0]));
@@ -269,7 +275,7 @@ __device__ __forceinline__ long any_mrow(long L, int n1, int H1, int Hl, int d) 
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kSineAnyThreads) k_sine_any_mid(SineAnyMidArgs<T> a) {
+__global__ void __launch_bounds__(kSineAnyMidThreads) k_sine_any_mid(SineAnyMidArgs<T> a) {
   extern __shared__ unsigned char smem_raw[];
   __shared__ double red[64];
   const int L = a.plan.L, N = L / 2, n = a.n;
@@ -344,12 +350,11 @@ void launch_sine_any_cols(SineAnyArgs<T> a, long outer, hipStream_t st) {
 
 template <typename T>
 void launch_sine_any_mid(SineAnyMidArgs<T> a, int nrhs, hipStream_t st) {
-  a.LPB = sine_any_lines(a.plan.L);
-  const long pairs = (a.rows + 1) / 2;
-  a.nblk = (pairs + a.LPB - 1) / a.LPB;
+  a.LPB = 1;
+  a.nblk = (a.rows + 1) / 2;
   const size_t sh = 2 * (size_t)a.LPB * a.plan.L * sizeof(cx<T>);
   dim3 grid((unsigned)(a.nblk * nrhs));
-  FL_LAUNCH((k_sine_any_mid<T>), grid, dim3(kSineAnyThreads), sh, st, a);
+  FL_LAUNCH((k_sine_any_mid<T>), grid, dim3(sine_any_mid_threads(a.plan.L)), sh, st, a);
   check_launch("mixed-radix sine middle pass");
 }
 
