@@ -243,3 +243,19 @@ def test_exterior_term_general_n():
     scale = oracle.exterior_lattice_2d(np.abs(G), lambda a, c: np.abs(g(a, c)))
     print(f"  max |b - ref| / scale = {float((np.abs(b - ref) / scale).max()):.2e}")
     assert (np.abs(b - ref) <= 1e-12 * scale).all()
+
+
+@pytest.mark.parametrize("mixed", [0, 1])
+@pytest.mark.parametrize("d,N", [(1, 100), (2, 24), (3, 10)])
+def test_tau_any_solve_batch_invariance_bitwise(d, N, mixed):
+    """With the mixed-radix tau passes a right-hand side gives the same bits
+    alone and inside a batch (every block works on one right-hand side's
+    lines and the partial sums are re-added in a fixed order)."""
+    op = make_op(d, 1.3, 1, N)
+    assert op.precond_kind == 2
+    f = torch.from_numpy(inputs.uniform_rhs(d, N, 3, seed=29)).cuda()
+    ub, ib = op.solve(f, tol=1e-10, mixed=mixed)
+    for r in range(3):
+        ua, ia = op.solve(f[r].contiguous(), tol=1e-10, mixed=mixed)
+        assert torch.equal(ua, ub[r]), r
+        assert ia[0]["iters"] == ib[r]["iters"]
