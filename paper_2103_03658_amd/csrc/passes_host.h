@@ -45,18 +45,16 @@ void apply_passes_t(const Geometry& g, const Schedule& sc, const T* lam, const T
   double* part = mode == PM_DOT ? c.part_b : c.part_a;
   if (mode == PM_PQ && g.d == 1) throw Error(2, "PM_PQ: d >= 2 only");
   if (g.d == 1 && odd && !g.sine_ok()) {
-    // mixed-radix sine passes of length 2N (not a power of two): y = u,
-    // then the middle pass in place on the one line (with the u.y = sum_k
-    // m_k sigma(u)_k^2 partials in PM_DOT, one block per RHS)
+    // mixed-radix sine passes of length 2N (not a power of two): the middle
+    // pass on the one line, u -> y (with the u.y = sum_k m_k sigma(u)_k^2
+    // partials in PM_DOT, one block per RHS)
     if (mode != PM_PLAIN && mode != PM_DOT) throw Error(2, "odd passes: plain or dot mode only");
     if (!g.sine_any_ok()) throw Error(2, "sine passes: 2N with prime factors 2, 3, 5, 7 only");
-    if (go()) {
-      FL_HIP(hipMemcpyAsync(y, u, (size_t)nrhs * n0 * sizeof(T), hipMemcpyDeviceToDevice, st));
-      SineAnyMidArgs<T> m{y, lam, active, 1, n0, n0, 1, g.Na[0] + 1, 1, 1, 0, 0,
-                          mode == PM_DOT ? 1 : 0, part, c.max_blocks,
-                          reinterpret_cast<const cx<T>*>(twv.sx[0]), radix_plan_or_throw(g.La[0])};
-      launch_sine_any_mid<T>(m, nrhs, st);
-    }
+    SineAnyMidArgs<T> m{y, lam, active, 1, n0, n0, 1, g.Na[0] + 1, 1, 1, 0, 0,
+                        mode == PM_DOT ? 1 : 0, part, c.max_blocks,
+                        reinterpret_cast<const cx<T>*>(twv.sx[0]), radix_plan_or_throw(g.La[0]),
+                        u};
+    if (go()) launch_sine_any_mid<T>(m, nrhs, st);
     done();
     return;
   }

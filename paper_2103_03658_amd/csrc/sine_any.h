@@ -247,7 +247,7 @@ __global__ void __launch_bounds__(kSineAnyThreads) k_sine_any_cols(SineAnyArgs<T
 // with the partials of r.z = sum_k m_k sigma(r)_k^2 when dot.
 template <typename T>
 struct SineAnyMidArgs {
-  T* data;
+  T* data;             // output (may equal `in`: a block reads all its lines first)
   const T* m;          // folded multiplier, (N_0 + 1) x .. x (N_{d-1} + 1)
   const int* active;
   long rows;           // lines per RHS
@@ -263,6 +263,7 @@ struct SineAnyMidArgs {
   int max_blocks;
   const cx<T>* tw;
   RadixPlan plan;
+  const T* in;         // input lines (null: data)
 };
 
 // Multiplier row of line L of the last axis (the other axes' frequencies are
@@ -287,6 +288,7 @@ __global__ void __launch_bounds__(kSineAnyMidThreads) k_sine_any_mid(SineAnyMidA
   const int o = (int)ol;
   if (a.active && !a.active[o]) return;
   T* base = a.data + (long)o * a.o_stride;
+  const T* src = (a.in ? a.in : a.data) + (long)o * a.o_stride;
   const long la0 = 2 * rb * a.LPB;
   for (int l = threadIdx.x; l < a.LPB; l += blockDim.x) {
     b0[(long)l * L] = {0, 0};
@@ -296,7 +298,7 @@ __global__ void __launch_bounds__(kSineAnyMidThreads) k_sine_any_mid(SineAnyMidA
   for (int e = threadIdx.x; e < tot; e += blockDim.x) {
     const int lp = e / n, pos = e - lp * n;   // lp = 2 * pair + comp
     const long line = la0 + lp;
-    const T x = line < a.rows ? base[line * n + pos] : (T)0;
+    const T x = line < a.rows ? src[line * n + pos] : (T)0;
     const long pr = lp >> 1;
     const int comp = lp & 1;
     bt[2 * (pr * L + pos + 1) + comp] = x;
