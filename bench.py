@@ -124,6 +124,9 @@ def parse():
                     help="1: also measure the 1D, 2D 255^2, 3D 127^3 and tempered 1023^2 "
                          "workloads (a few seconds); 0: skip")
     ap.add_argument("--serve-only", action="store_true")
+    ap.add_argument("--general-n-only", action="store_true",
+                    help="only the tau-vs-circulant comparison on grids whose 2N is not a "
+                         "power of two (for profiler runs)")
     ap.add_argument("--d2-only", action="store_true",
                     help="only time the product on the large working sets (default and tuned "
                          "schedules; for profiler runs)")
@@ -370,6 +373,42 @@ def run_configs(dev, tol, quick=False):
                         "per_pass_GBs": [b / (m * 1e-3) / 1e9 for b, m in zip(by5, ms5)]}
         op.close()
     out["C5_tempered_1023_64rhs"] = c5
+    out["general_n_tau"] = general_n_tau(dev, tol)
+    return out
+
+
+def general_n_tau(dev, tol, reps=3):
+    """Grids whose 2N is not a power of two (2D, p = 1, 4 U[-1,1] RHS):
+    the tau preconditioner on mixed-radix sine passes (2N = 1200, 1400, 2000)
+    against the restricted circulant inverse on the power-of-two embedding:
+    iterations and ms per batched solve (FP64 and mixed), and the
+    preconditioner's passes (HIP events, 10 back-to-back launches each)."""
+    import torch
+    import paper_2103_03658_amd as fl
+    from paper_2103_03658_amd import inputs
+    out = {}
+    for N in (600, 700, 1000):
+        for a in (0.5, 1.5):
+            op = fl.Operator(2, a, 1, N=N)
+            f = torch.from_numpy(inputs.uniform_rhs(2, N, 4, seed=1)).to(dev)
+            res = {}
+            for kind in (1, 2):
+                op.set_preconditioner(kind)
+                res[f"precond{kind}_us_per_pass"] = [1e3 * x for x in
+                                                     op.profile_precond(f, reps=10)]
+                for mixed in (0, 1):
+                    op.solve(f, tol=tol, mixed=mixed)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for _ in range(reps):
+                        _, info = op.solve(f, tol=tol, mixed=mixed)
+                    torch.cuda.synchronize()
+                    res[f"kind{kind}_{'mixed' if mixed else 'fp64'}"] = {
+                        "ms_per_batched_solve": 1e3 * (time.perf_counter() - t0) / reps,
+                        "iters": max(i["iters"] for i in info),
+                        "max_relres_true": max(i["relres_true"] for i in info)}
+            out[f"N{N}_alpha{a}"] = res
+            op.close()
     return out
 
 
@@ -490,6 +529,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.serve_only:
         print(json.dumps({"serving": serving_legs(args)}))
+        return
+    if args.general_n_only:
+        print(json.dumps({"general_n_tau": general_n_tau(dev, args.tol)}))
         return
     if args.d2_only:
         print(json.dumps({"d2": d2_shapes(dev, reps=args.d2_reps,
