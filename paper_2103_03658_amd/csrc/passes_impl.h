@@ -940,8 +940,11 @@ struct SineArgs {
 // so that pass does not read p back.  STOP (the pass that starts z = P r):
 // the end-of-iteration tests on r.r first (cg_stop_rr); DIRF then takes only
 // the tests on r.z and beta (cg_beta_rho).
+// The FP64 radix-8 fused pass (DIRF + FIRST) is built for three waves per
+// SIMD (168 registers; the compiler's own choice, 178, keeps two).
 template <typename T, int M, int E, bool DIRF, bool FIRST, bool STOP>
-__global__ void __launch_bounds__(512) k_sine_cols(SineArgs<T> a) {
+__global__ void __launch_bounds__(512, (FIRST && E == 8 && sizeof(T) == 8) ? 3 : 1)
+    k_sine_cols(SineArgs<T> a) {
   static_assert(DIRF || !FIRST, "the fused first pass follows the direction update");
   static_assert(!(DIRF && STOP), "one test per pass");
   using P = Plan<M, E>;
@@ -960,16 +963,9 @@ __global__ void __launch_bounds__(512) k_sine_cols(SineArgs<T> a) {
   const long base = o * a.os + col0;
   const int tot = a.n * W2;
   // the tile's loads are issued before the iteration tests, whose partial
-  // sums then wait on them together
+  // sums then wait on them together; the old p is loaded after the
+  // transform, so that it is not held in registers across it
   T pold[DIRF ? E : 1];
-  if constexpr (DIRF) {
-#pragma unroll
-    for (int j = 0; j < E; ++j) {
-      const int e = threadIdx.x + j * nthr;
-      const int row = e >> lw1, cc = e & (W2 - 1);
-      pold[j] = (e < tot && cc < ncol) ? a.pdir[base + (long)row * a.C + cc] : (T)0;
-    }
-  }
   // rows [0, M/2) of the tile: (M/2) * 2W elements, exactly E per thread
   T x[E];
 #pragma unroll
@@ -1003,6 +999,14 @@ __global__ void __launch_bounds__(512) k_sine_cols(SineArgs<T> a) {
     const int l = threadIdx.x / TPL, t = threadIdx.x % TPL;
     T* lre = lds + l * a.LS;
     line_in_lds<T, M, E, -1, 2, true>(lre, lre + a.PO, t, a.tw);
+  }
+  if constexpr (DIRF) {
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int e = threadIdx.x + j * nthr;
+      const int row = e >> lw1, cc = e & (W2 - 1);
+      pold[j] = (e < tot && cc < ncol) ? a.pdir[base + (long)row * a.C + cc] : (T)0;
+    }
   }
   __syncthreads();
   // positions 1..n: first column of a pair from the imaginary plane, second
