@@ -1139,6 +1139,10 @@ __global__ void __launch_bounds__(512) k_sine_mid(SineMidArgs<T> a) {
              (double)sb * (double)v[sl].x * (double)v[sl].x;
     v[sl] = {sa * v[sl].y, -(sb * v[sl].x)};
   }
+  // the r.z sum is formed here: left to the compiler it is sunk to its use
+  // after the second transform, which then holds the transformed values
+  // across that transform (28-40 more registers, spills at E = 16)
+  asm volatile("" : "+v"(acc));
   to_natural<T, M, E>(v);
   fft_line_1p<T, M, E, -1>(v, l1, t, a.tw);
 #pragma unroll
