@@ -1000,10 +1000,15 @@ __global__ void __launch_bounds__(512, (FIRST && E == 8 && sizeof(T) == 8) ? 3 :
     T* lre = lds + l * a.LS;
     line_in_lds<T, M, E, -1, 2, true>(lre, lre + a.PO, t, a.tw);
   }
+  // the thread index of the tile's stores, opaque to the compiler: it then
+  // forms their addresses here instead of keeping those of the loads in
+  // registers across the transform
+  int tx = threadIdx.x;
+  asm volatile("" : "+v"(tx));
   if constexpr (DIRF) {
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-      const int e = threadIdx.x + j * nthr;
+      const int e = tx + j * nthr;
       const int row = e >> lw1, cc = e & (W2 - 1);
       pold[j] = (e < tot && cc < ncol) ? a.pdir[base + (long)row * a.C + cc] : (T)0;
     }
@@ -1015,7 +1020,7 @@ __global__ void __launch_bounds__(512, (FIRST && E == 8 && sizeof(T) == 8) ? 3 :
   T pnew[FIRST ? E : 1];
 #pragma unroll
   for (int j = 0; j < E; ++j) {
-    const int e = threadIdx.x + j * nthr;
+    const int e = tx + j * nthr;
     const int row = e >> lw1, cc = e & (W2 - 1);
     if constexpr (FIRST) pnew[j] = 0;
     if (e >= tot || cc >= ncol) continue;
@@ -1036,7 +1041,7 @@ __global__ void __launch_bounds__(512, (FIRST && E == 8 && sizeof(T) == 8) ? 3 :
     __syncthreads();
 #pragma unroll
     for (int j = 0; j < E; ++j) {
-      const int e = threadIdx.x + j * nthr;
+      const int e = tx + j * nthr;
       const int row = e >> lw1, cc = e & (W2 - 1);
       lds[(cc >> 1) * a.LS + (cc & 1) * a.PO + P::pad(row)] = pnew[j];
     }
