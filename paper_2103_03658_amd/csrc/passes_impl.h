@@ -533,9 +533,12 @@ struct MidArgs {
 };
 
 // FP64 radix-16 lines fit 168 registers, which allows three waves per SIMD
-// (the compiler's own choice keeps two).
+// (the compiler's own choice keeps two at some lengths).  At 1024 points
+// they fit 128 (four waves), but measured slower: 39.1 -> 40.9 us on the
+// 511^2 batch.
 template <typename T, int M, int E>
-__global__ void __launch_bounds__(512, (E == 16 && sizeof(T) == 8) ? 3 : 1) k_mid(MidArgs<T> a) {
+__global__ void __launch_bounds__(512, (E == 16 && sizeof(T) == 8) ? 3 : 1)
+    k_mid(MidArgs<T> a) {
   using P = Plan<M, E>;
   constexpr int TPL = P::TPL;
   extern __shared__ unsigned char smem_raw[];
@@ -577,7 +580,13 @@ __global__ void __launch_bounds__(512, (E == 16 && sizeof(T) == 8) ? 3 : 1) k_mi
     v[sl] = cscale(v[sl], s);
   }
   to_natural<T, M, E>(v);
-  fft_line_1p<T, M, E, +1>(v, l1, t, a.tw);
+  // The second transform takes the lane index through an empty asm: with
+  // the same index the compiler shares the two transforms' LDS and twiddle
+  // index arithmetic and keeps it in registers across the symbol multiply
+  // (FP64 E = 16: 166 -> 134 registers, FP32: 120 -> 92, five waves).
+  int t2 = t;
+  asm volatile("" : "+v"(t2));
+  fft_line_1p<T, M, E, +1>(v, l1, t2, a.tw);
 #pragma unroll
   for (int sl = 0; sl < E; ++sl) {
     const int i = t + TPL * P::jslot(sl);   // n_out <= M/2
@@ -940,11 +949,8 @@ struct SineArgs {
 // so that pass does not read p back.  STOP (the pass that starts z = P r):
 // the end-of-iteration tests on r.r first (cg_stop_rr); DIRF then takes only
 // the tests on r.z and beta (cg_beta_rho).
-// The FP64 radix-8 fused pass (DIRF + FIRST) is built for three waves per
-// SIMD (168 registers; the compiler's own choice, 178, keeps two).
 template <typename T, int M, int E, bool DIRF, bool FIRST, bool STOP>
-__global__ void __launch_bounds__(512, (FIRST && E == 8 && sizeof(T) == 8) ? 3 : 1)
-    k_sine_cols(SineArgs<T> a) {
+__global__ void __launch_bounds__(512) k_sine_cols(SineArgs<T> a) {
   static_assert(DIRF || !FIRST, "the fused first pass follows the direction update");
   static_assert(!(DIRF && STOP), "one test per pass");
   using P = Plan<M, E>;
@@ -1047,7 +1053,11 @@ __global__ void __launch_bounds__(512, (FIRST && E == 8 && sizeof(T) == 8) ? 3 :
     }
     __syncthreads();
     {
-      const int l = threadIdx.x / TPL, t = threadIdx.x % TPL;
+      // opaque lane index: the index arithmetic of the sine transform above
+      // is not kept for this one (FP64: 137 -> 116 registers, four waves)
+      int tx3 = threadIdx.x;
+      asm volatile("" : "+v"(tx3));
+      const int l = tx3 / TPL, t = tx3 % TPL;
       T* lre = lds + l * a.LS;
       line_in_lds<T, M, E, -1, 1, false>(lre, lre + a.PO, t, a.tw);
     }
@@ -1149,7 +1159,11 @@ __global__ void __launch_bounds__(512) k_sine_mid(SineMidArgs<T> a) {
   // across that transform (28-40 more registers, spills at E = 16)
   asm volatile("" : "+v"(acc));
   to_natural<T, M, E>(v);
-  fft_line_1p<T, M, E, -1>(v, l1, t, a.tw);
+  // opaque lane index for the second transform, as in k_mid (FP64 E = 8:
+  // 148 -> 104 registers, four waves per SIMD)
+  int t2 = t;
+  asm volatile("" : "+v"(t2));
+  fft_line_1p<T, M, E, -1>(v, l1, t2, a.tw);
 #pragma unroll
   for (int sl = 0; sl < E; ++sl) {
     const int pos = t + TPL * P::jslot(sl);
