@@ -1141,26 +1141,32 @@ __global__ void __launch_bounds__(512) k_sine_mid(SineMidArgs<T> a) {
   fft_line_1p<T, M, E, -1>(v, l1, t, a.tw);
   const T* ma = a.m + (ha ? sine_mrow(la, a.n1, a.H1, a.Hl, a.d) : 0);
   const T* mb = a.m + (hb ? sine_mrow(la + 1, a.n1, a.H1, a.Hl, a.d) : 0);
+  // The r.z sum is pinned after each quarter of the slots (an empty asm with
+  // the sum as an in/out register): left to the compiler it is sunk to its
+  // use after the second transform, which then holds the transformed values
+  // across that transform, and the multiplier loads of all slots are issued
+  // at once (FP64 E = 16: 256 registers with spills -> 150 with the opaque
+  // lane index below, three waves).  The sum keeps its order.
   double acc = 0.0;
 #pragma unroll
-  for (int sl = 0; sl < E; ++sl) {
-    const int k = t + TPL * P::jslot(sl);
-    const int kk = k <= M / 2 ? k : M - k;
-    const T sa = ha ? ma[kk] : (T)0;
-    const T sb = hb ? mb[kk] : (T)0;
-    // slots 1..n hold the sine coefficients (the others mirror them)
-    if (k >= 1 && k <= n)
-      acc += (double)sa * (double)v[sl].y * (double)v[sl].y +
-             (double)sb * (double)v[sl].x * (double)v[sl].x;
-    v[sl] = {sa * v[sl].y, -(sb * v[sl].x)};
+  for (int qq = 0; qq < 4; ++qq) {
+#pragma unroll
+    for (int sl = qq * (E / 4); sl < (qq + 1) * (E / 4); ++sl) {
+      const int k = t + TPL * P::jslot(sl);
+      const int kk = k <= M / 2 ? k : M - k;
+      const T sa = ha ? ma[kk] : (T)0;
+      const T sb = hb ? mb[kk] : (T)0;
+      // slots 1..n hold the sine coefficients (the others mirror them)
+      if (k >= 1 && k <= n)
+        acc += (double)sa * (double)v[sl].y * (double)v[sl].y +
+               (double)sb * (double)v[sl].x * (double)v[sl].x;
+      v[sl] = {sa * v[sl].y, -(sb * v[sl].x)};
+    }
+    asm volatile("" : "+v"(acc));
   }
-  // the r.z sum is formed here: left to the compiler it is sunk to its use
-  // after the second transform, which then holds the transformed values
-  // across that transform (28-40 more registers, spills at E = 16)
-  asm volatile("" : "+v"(acc));
   to_natural<T, M, E>(v);
   // opaque lane index for the second transform, as in k_mid (FP64 E = 8:
-  // 148 -> 104 registers, four waves per SIMD)
+  // 148 -> 94 registers with the quarters above, five waves per SIMD)
   int t2 = t;
   asm volatile("" : "+v"(t2));
   fft_line_1p<T, M, E, -1>(v, l1, t2, a.tw);
