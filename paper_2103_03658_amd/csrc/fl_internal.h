@@ -150,6 +150,22 @@ inline TileLds tile_lds(int M, int E, int W, size_t elem) {
   const int LS = up(PO + ldsn, (2 * R) % banks);
   return {PO, LS, (size_t)W * LS * elem};
 }
+// The sine passes that keep only the lower half of each line (the odd
+// extension's mirror is formed in registers, and only outputs below M/2 are
+// read) hold a line's real and imaginary lower halves in one plane of
+// M + M/E (the real half at 0, the imaginary half at PO), which is also the
+// transform's exchange plane: half the LDS of tile_lds.
+inline TileLds tile_lds_half(int M, int E, int W, size_t elem) {
+  const int ldsn = M + M / E;
+  const int half = M / 2 + M / (2 * E);   // padded index of row M/2
+  const int banks = elem == 8 ? 16 : 32;
+  int R = banks / (2 * W);
+  if (R < 1) R = 1;
+  auto up = [&](int x, int res) { return x + (((res - x) % banks) + banks) % banks; };
+  const int PO = up(half, R % banks);
+  const int LS = up(PO + half > ldsn ? PO + half : ldsn, (2 * R) % banks);
+  return {PO, LS, (size_t)W * LS * elem};
+}
 inline bool pow2(int w) { return w >= 1 && (w & (w - 1)) == 0; }
 inline int ilog2i(int w) {
   int l = 0;

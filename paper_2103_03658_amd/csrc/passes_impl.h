@@ -263,6 +263,41 @@ __device__ __forceinline__ void line_in_lds(T* lre, T* lim, int t, const cx<T>* 
   }
 }
 
+// The same with one exchange plane, lre[0, M + M/E): the line's lower halves
+// at lre (real) and lim (imaginary) lie inside it (tile_lds_half), and the
+// transform overwrites them after every lane has read its inputs (the
+// exchange begins with a barrier).  Only the lower half of the outputs.
+template <typename T, int M, int E, int DIR, int IN>
+__device__ __forceinline__ void line_in_lds_half(T* lre, T* lim, int t, const cx<T>* tw) {
+  static_assert(IN == 1 || IN == 2, "the inputs' upper half is zero or mirrored");
+  using P = Plan<M, E>;
+  constexpr int TPL = P::TPL;
+  cx<T> v[E];
+#pragma unroll
+  for (int j = 0; j < E; ++j) {
+    const int e = t + j * TPL;
+    if (j < E / 2) {
+      const int i = P::pad(e);
+      v[j] = {lre[i], lim[i]};
+    } else if (IN == 1) {
+      v[j] = {0, 0};
+    } else {
+      const int i = P::pad(M - e);
+      v[j] = e == M / 2 ? cx<T>{0, 0} : cx<T>{-lre[i], -lim[i]};
+    }
+  }
+  fft_line_1p<T, M, E, DIR>(v, lre, t, tw);
+  __syncthreads();
+#pragma unroll
+  for (int sl = 0; sl < E; ++sl) {
+    if (P::jslot(sl) < E / 2) {
+      const int i = P::pad(t + TPL * P::jslot(sl));
+      lre[i] = v[sl].x;
+      lim[i] = v[sl].y;
+    }
+  }
+}
+
 // Hermitian split of the tile's W packed line pairs (transformed in the LDS
 // planes) into rows k = 0..M/2 of the axis-0 frequency, row segments of 2W
 // complex values: X_a = (Z_k + conj Z_{M-k})/2, X_b = (Z_k - conj Z_{M-k})/(2i).
@@ -968,10 +1003,17 @@ __global__ void __launch_bounds__(512) k_sine_cols(SineArgs<T> a) {
   const int ncol = cl < W2 ? (int)cl : W2;
   const long base = o * a.os + col0;
   const int tot = a.n * W2;
-  // the tile's loads are issued before the iteration tests, whose partial
-  // sums then wait on them together; the old p is loaded after the
+  // DIRF: the tile's loads are issued before the iteration tests, whose
+  // partial sums then wait on them together; the old p is loaded after the
   // transform, so that it is not held in registers across it
   T pold[DIRF ? E : 1];
+  if constexpr (STOP) {
+    // only the right-hand side's lead block takes the decision; the others
+    // transform their tiles anyway (nothing reads them if it stops).  The
+    // test comes before the tile's loads: held across it, they cost every
+    // block some 25 registers (a wave per SIMD)
+    if (tile == 0 && cg_stop_rr(a.cg, (int)o, true, red)) return;
+  }
   // rows [0, M/2) of the tile: (M/2) * 2W elements, exactly E per thread
   T x[E];
 #pragma unroll
@@ -987,11 +1029,6 @@ __global__ void __launch_bounds__(512) k_sine_cols(SineArgs<T> a) {
     if (cg_beta_rho(a.cg, (int)o, tile == 0, red, &beta)) return;
     bt = (T)beta;
   }
-  if constexpr (STOP) {
-    // only the right-hand side's lead block takes the decision; the others
-    // transform their tiles anyway (nothing reads them if it stops)
-    if (tile == 0 && cg_stop_rr(a.cg, (int)o, true, red)) return;
-  }
   {
 #pragma unroll
     for (int j = 0; j < E; ++j) {
@@ -1004,7 +1041,10 @@ __global__ void __launch_bounds__(512) k_sine_cols(SineArgs<T> a) {
   {
     const int l = threadIdx.x / TPL, t = threadIdx.x % TPL;
     T* lre = lds + l * a.LS;
-    line_in_lds<T, M, E, -1, 2, true>(lre, lre + a.PO, t, a.tw);
+    if constexpr (DIRF)
+      line_in_lds<T, M, E, -1, 2, true>(lre, lre + a.PO, t, a.tw);
+    else
+      line_in_lds_half<T, M, E, -1, 2>(lre, lre + a.PO, t, a.tw);
   }
   // the thread index of the tile's stores, opaque to the compiler: it then
   // forms their addresses here instead of keeping those of the loads in
@@ -1352,7 +1392,9 @@ void launch_sine_cols(int M, int E, SineArgs<T> a, long outer, hipStream_t st,
   if (a.pdir && (a.dot || a.outer_per_rhs != 1))
     throw Error(2, "sine pass: the fused iteration start needs one slice per RHS, no dot");
   a.lw = ilog2i(a.W);
-  const TileLds tl = tile_lds(M, E, a.W, sizeof(T));
+  // the fused passes keep both planes (the product's first pass needs whole
+  // lines); the others one (line_in_lds_half)
+  const TileLds tl = a.pdir ? tile_lds(M, E, a.W, sizeof(T)) : tile_lds_half(M, E, a.W, sizeof(T));
   a.PO = tl.PO;
   a.LS = tl.LS;
   dim3 grid((unsigned)(a.ntiles * outer));
