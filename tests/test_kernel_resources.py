@@ -27,8 +27,8 @@ EXPECT_F64 = {
     "fl::k_first<double, 1024, 8>": 4,
     "fl::k_last<double, 1024, 8>": 4,
     "fl::k_sine_cols<double, 1024, 8, true, true, false>": 4,
-    "fl::k_sine_cols<double, 1024, 8, false, false, true>": 4,
-    "fl::k_sine_cols<double, 1024, 8, false, false, false>": 4,
+    "fl::k_sine_cols<double, 1024, 8, false, false, true>": 5,
+    "fl::k_sine_cols<double, 1024, 8, false, false, false>": 5,
     "fl::k_sine_mid<double, 1024, 16>": 3,
     "fl::k_sine_mid<double, 1024, 8>": 4,
     "fl::k_mid<double, 2048, 16>": 3,
@@ -38,6 +38,7 @@ EXPECT_F32 = {
     "fl::k_sine_mid<float, 1024, 16>": 5,
     "fl::k_sine_cols<float, 1024, 8, true, true, false>": 4,
     "fl::k_sine_cols<float, 1024, 16, true, true, false>": 4,
+    "fl::k_sine_cols<float, 1024, 16, false, false, true>": 5,
     "fl::k_first<float, 2048, 16>": 4,
     "fl::k_mid<float, 2048, 16>": 4,
     "fl::k_last<float, 2048, 16>": 4,
