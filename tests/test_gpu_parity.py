@@ -244,10 +244,12 @@ def test_solve_zero_rhs_and_maxiter():
 
 
 @pytest.mark.parametrize("d,N,fp32", [(2, 64, False), (2, 64, True), (3, 16, False),
-                                      (3, 16, True), (1, 256, True)])
+                                      (3, 16, True), (1, 256, True), (2, 512, False),
+                                      (2, 512, True)])
 def test_schedules_give_same_product(d, N, fp32):
     """Every launch schedule the tuner may pick computes the same product
-    (radix 8/16/32 register stages, 1..16 lines per block)."""
+    (radix 8/16/32 register stages, 1..16 lines per block; the bench's
+    1024-point lines at N = 512)."""
     from paper_2103_03658_amd import tune
     op = make_op(d, 1.1, 1, N)
     u = inputs.uniform_rhs(d, N, 3, seed=21)
@@ -420,11 +422,13 @@ def tau_scale(G, v, N, d):
     return sc.max() * (2.0 / N) ** d
 
 
-@pytest.mark.parametrize("d,N,fp32", [(2, 64, False), (2, 64, True), (3, 16, False)])
+@pytest.mark.parametrize("d,N,fp32", [(2, 64, False), (2, 64, True), (3, 16, False),
+                                      (2, 512, False), (2, 512, True)])
 def test_tau_every_precond_schedule(d, N, fp32):
     """Every schedule the tuner may give the preconditioner's sine passes
     (radix 8/16/32 stages, 1..16 column pairs or line pairs per block,
-    ragged last tiles) computes the same tau product, against the oracle."""
+    ragged last tiles; the bench's 1024-point lines at N = 512) computes the
+    same tau product, against the oracle."""
     from paper_2103_03658_amd import tune
     op = make_op(d, 1.2, 1, N)
     u = inputs.uniform_rhs(d, N, 3, seed=47)
