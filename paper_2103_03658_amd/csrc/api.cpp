@@ -1544,10 +1544,13 @@ static fl_status solve_body(fl_op A, const double* f, const double* b, double to
             precond_apply<float>(A, pc_symbol<float>(A), A->tw32, r32, z32, nrhs, ws, cg, trig,
                                  st);
         });
-    // fold what is left (RHS stopped by maxiter) and report true residuals
+    // fold what is left (RHS stopped by maxiter) and report true residuals:
+    // a converged RHS has its final iterate's FP64 residual from its last
+    // replacement; the others get a fresh FP64 product
     fl::reliable_accum(A->g, xhi, xlo, nrhs, cg, trig, true, st);
     FL_HIP(hipMemcpyAsync(u, xhi, v8, hipMemcpyDeviceToDevice, st));
-    fp64_residual(A, f, u, r64, nrhs, co, nullptr, rro, ws, st);
+    fl::reliable_final(cg.status, rr_last, trig, rro, nrhs, st);
+    fp64_residual(A, f, u, r64, nrhs, co, trig, rro, ws, st);
     std::vector<double> rr(nrhs);
     read_results(A, nrhs, cg.iters, cg.status, nupd, nullptr, rro, f2, st, iters, status, outer,
                  rr, hrr, hf2);

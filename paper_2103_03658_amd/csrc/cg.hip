@@ -230,6 +230,22 @@ __global__ void __launch_bounds__(VT) k_reliable_accum(double* xhi, float* xlo, 
   }
 }
 
+// End of a reliable-update solve.  A right-hand side that converged did so
+// at a replacement (the recursion's tolerance test only flags one), after
+// which its FP32 correction was folded and nothing was added: the FP64
+// residual of that replacement, rr_last = ||f - A x||^2, belongs to the
+// final iterate.  The others (iteration cap or breakdown inside the FP32
+// recursion, with a correction folded only now) get mask = 1 for a fresh
+// FP64 residual.
+__global__ void k_reliable_final(const int* status, const double* rr_last, int* mask,
+                                 double* rr_true, int nrhs) {
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= nrhs) return;
+  const bool done = status[o] == 0;
+  mask[o] = done ? 0 : 1;
+  if (done) rr_true[o] = rr_last[o];
+}
+
 // Reliable update, step 2 (after r64 = f - A xhi in FP64 for the flagged
 // RHS): stop if ||r64|| meets the tolerance (and clear the flag, so the
 // preconditioner skips it), else resume the FP32 recursion from r32 = r64
@@ -302,6 +318,13 @@ void reliable_accum(const Geometry& g, double* xhi, float* xlo, int nrhs, const 
   hipLaunchKernelGGL(k_reliable_accum, grid, dim3(VT), 0, st, xhi, xlo, g.nd, trig,
                      force ? 1 : 0);
   check_launch("reliable accumulate");
+}
+
+void reliable_final(const int* status, const double* rr_last, int* mask, double* rr_true,
+                    int nrhs, hipStream_t st) {
+  hipLaunchKernelGGL(k_reliable_final, dim3((nrhs + 63) / 64), dim3(64), 0, st, status, rr_last,
+                     mask, rr_true, nrhs);
+  check_launch("reliable final");
 }
 
 void reliable_replace(const Geometry& g, const double* r64, float* r32, int nrhs,

@@ -357,6 +357,8 @@ void refine_axpy(double* u, const float* d32, const double* scale, long nd, int 
 void to_float(const double* src, float* dst, long n, hipStream_t st);
 void reliable_accum(const Geometry& g, double* xhi, float* xlo, int nrhs, const CgScalars& cg,
                     const int* trig, bool force, hipStream_t st);
+void reliable_final(const int* status, const double* rr_last, int* mask, double* rr_true,
+                    int nrhs, hipStream_t st);
 void reliable_replace(const Geometry& g, const double* r64, float* r32, int nrhs,
                       const CgScalars& cg, const double* part64, int nb64, int mb64,
                       double* rr_last, const double* f2, double tol2, int* trig,
